@@ -1,0 +1,104 @@
+"""Restarted GMRES with right preconditioning (oracle; test infrastructure only).
+
+The paper pairs its preconditioner with "standard GMRES" at relative
+tolerance 1e-6 (Sec. 2.5). Reading G11: right preconditioning in the flexible
+form (the preconditioned directions z_j = P v_j are stored and the iterate is
+x = x0 + Z y), x0 = 0, tolerance relative to ||g||_2, modified Gram-Schmidt
+Arnoldi, complex Givens rotations in the LAPACK zlartg convention. A cycle
+ends when the residual estimate meets the tolerance, on breakdown, or after
+``restart`` steps; the true residual g - A x then decides whether to stop or
+restart from it. The iteration count is the number of Arnoldi steps over all
+cycles.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class GmresResult:
+    x: np.ndarray
+    iterations: int
+    converged: bool
+    rel_residual: float                 # true ||g - A x|| / ||g||
+    estimates: list                     # residual estimate after every step, relative
+
+
+def givens(f: complex, g: complex):
+    """(c, s, r) with [c s; -conj(s) c] [f; g] = [r; 0] (zlartg convention)."""
+    if g == 0:
+        return 1.0, 0.0 + 0.0j, f
+    if f == 0:
+        return 0.0, np.conj(g) / abs(g), abs(g)
+    af, ag = abs(f), abs(g)
+    rho = np.hypot(af, ag)
+    c = af / rho
+    s = (f / af) * np.conj(g) / rho
+    return c, s, (f / af) * rho
+
+
+def fgmres(apply_A: Callable, apply_P: Callable, g: np.ndarray, tol: float,
+           restart: int = 30, max_iters: int = 1000) -> GmresResult:
+    shape = g.shape
+    g = g.reshape(-1)
+    beta0 = float(np.linalg.norm(g))
+    x = np.zeros_like(g)
+    if beta0 == 0.0:
+        return GmresResult(x.reshape(shape), 0, True, 0.0, [])
+    iters = 0
+    estimates = []
+    r = g.copy()
+    while True:
+        beta = float(np.linalg.norm(r))
+        V = [r / beta]
+        Z = []
+        H = np.zeros((restart + 1, restart), dtype=np.complex128)
+        cs = np.zeros(restart)
+        sn = np.zeros(restart, dtype=np.complex128)
+        s = np.zeros(restart + 1, dtype=np.complex128)
+        s[0] = beta
+        j_end = 0
+        for j in range(restart):
+            z = apply_P(V[j].reshape(shape)).reshape(-1)
+            Z.append(z)
+            w = apply_A(z.reshape(shape)).reshape(-1)
+            for k in range(j + 1):                       # modified Gram-Schmidt
+                H[k, j] = np.vdot(V[k], w)
+                w = w - H[k, j] * V[k]
+            H[j + 1, j] = np.linalg.norm(w)
+            for k in range(j):                           # previous rotations
+                a, bb = H[k, j], H[k + 1, j]
+                H[k, j] = cs[k] * a + sn[k] * bb
+                H[k + 1, j] = -np.conj(sn[k]) * a + cs[k] * bb
+            c, sgn, rr = givens(H[j, j], H[j + 1, j])
+            cs[j], sn[j] = c, sgn
+            H[j, j] = rr
+            hnext = H[j + 1, j]
+            H[j + 1, j] = 0.0
+            s[j + 1] = -np.conj(sgn) * s[j]
+            s[j] = c * s[j]
+            iters += 1
+            j_end = j + 1
+            estimates.append(abs(s[j + 1]) / beta0)
+            if abs(s[j + 1]) <= tol * beta0 or iters >= max_iters:
+                break
+            # breakdown: w is (numerically) zero, the Krylov space is invariant
+            wn = float(np.linalg.norm(w))
+            if wn == 0.0:
+                break
+            V.append(w / wn)
+            del hnext
+        y = np.zeros(j_end, dtype=np.complex128)
+        for i in range(j_end - 1, -1, -1):               # back substitution
+            y[i] = (s[i] - H[i, i + 1:j_end] @ y[i + 1:j_end]) / H[i, i]
+        for i in range(j_end):
+            x = x + y[i] * Z[i]
+        r = g - apply_A(x.reshape(shape)).reshape(-1)
+        rel = float(np.linalg.norm(r)) / beta0
+        if rel <= tol:
+            return GmresResult(x.reshape(shape), iters, True, rel, estimates)
+        if iters >= max_iters:
+            return GmresResult(x.reshape(shape), iters, False, rel, estimates)
