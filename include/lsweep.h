@@ -1,0 +1,206 @@
+/*
+ * lsweep: sparsify-and-sweep preconditioned GMRES for the discretized
+ * Lippmann-Schwinger equation on AMD MI355X (gfx950).
+ *
+ * Method: F. Liu and L. Ying, "Sparsify and sweep: an efficient
+ * preconditioner for the Lippmann-Schwinger equation".
+ *
+ * Problem (Sec. 1, eq. LS; Sec. 2.1, eqs. LS_d and LS_d_c): on the unit square
+ * with n interior points per axis (h = 1/(n+1)), find u on the interior grid I
+ * with
+ *     u_i + omega^2 sum_{j in I} k_{i-j} m_j u_j = g_i,
+ *     g_i = -omega^2 sum_{j in I} k_{i-j} m_j [u_I]_j,
+ * where k_delta = G(|delta| h) h^2 for delta != 0 (G the free-space Green's
+ * function) and k_0 is the integral of G over the disk of area h^2.
+ * The solver is right-preconditioned restarted GMRES; the preconditioner is
+ * the sparsified system H (Sec. 2.2) inverted approximately by the
+ * moving-PML sweep (Sec. 2.3, Algorithms 1 and 2).
+ *
+ * Conventions shared by every entry point
+ *  - All array arguments are DEVICE pointers on the handle's device unless a
+ *    parameter name ends in _host.
+ *  - Arrays are C-ordered; a grid array is [i1][i2] with i2 fastest; i1 is the
+ *    sweep axis. Interior arrays are [n][n], extended-grid arrays are [L][L]
+ *    with L = n + 2 + 2b and extended index e = i + b (i in [-b, n+1+b]).
+ *  - A batch is [nrhs][grid]. Complex values are interleaved (re, im):
+ *    complex128 (double2) when a precision argument is LS_FP64, complex64
+ *    (float2) when it is LS_MIXED.
+ *  - The caller owns every array it passes; the library copies what it keeps.
+ *  - Every call returns an ls_status; ls_last_error() gives a message for the
+ *    last failure on the calling thread. No C++ exception crosses this ABI.
+ *  - Work is enqueued on opts.hip_stream (NULL: the default stream); every
+ *    entry point returns with its work complete (host-synchronised).
+ *  - Calls on one handle must not overlap.
+ *  - Only dim = 2 is implemented; other values return LS_E_INVALID.
+ */
+#ifndef LSWEEP_H
+#define LSWEEP_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ls_handle ls_handle;
+
+typedef enum {
+  LS_OK = 0,
+  LS_E_INVALID = 1,   /* bad argument (dim, n, omega, b, w, m not finite or m >= 1, ...) */
+  LS_E_NOMEM = 2,     /* a device or host allocation failed */
+  LS_E_DEVICE = 3,    /* a HIP runtime call failed */
+  LS_E_SINGULAR = 4,  /* zero pivot in a slice factorization */
+  LS_E_NOCONV = 5,    /* max_iters reached; the best iterate and info are still written */
+  LS_E_NUMERIC = 6,   /* NaN or Inf met in a norm */
+  LS_E_STATE = 7      /* call out of order (ls_adjoint without a matching ls_solve) */
+} ls_status;
+
+typedef enum { LS_FP64 = 0, LS_MIXED = 1 } ls_precision;
+typedef enum { LS_RHS_SOURCE = 0, LS_RHS_INCIDENT = 1 } ls_rhs_kind;
+
+typedef struct {
+  int dim;  /* 2 */
+  int n;    /* interior points per axis, h = 1/(n+1) */
+} ls_grid;
+
+typedef struct {
+  int precision;     /* ls_precision. LS_FP64: every apply in complex128.
+                        LS_MIXED: FFT, stencil, slice factors and sweep in
+                        complex64 inside a complex128 flexible GMRES loop. */
+  int restart;       /* GMRES restart length (default 30) */
+  int max_iters;     /* total Arnoldi steps per right-hand side (default 1000) */
+  double pml_C;      /* PML strength C of Sec. 2.2.2 (default 10) */
+  int freq_samples;  /* local-frequency samples for the auxiliary PML (0: n, Sec. 2.3) */
+  int autotune;      /* reserved, 0 */
+  void* hip_stream;  /* hipStream_t to enqueue on (NULL: default stream) */
+} ls_options;
+
+typedef struct {
+  int iterations;       /* Arnoldi steps over all restart cycles */
+  double rel_residual;  /* true ||g - A u||_2 / ||g||_2, in float64 */
+  int converged;        /* 1 if rel_residual <= tol */
+} ls_rhs_info;
+
+/* Fill *opts with the defaults listed above. */
+void ls_default_options(ls_options* opts);
+
+/*
+ * Algorithm 1 (setup). Builds the Green's-function table and its FFT, the
+ * type-1 stencils alpha and beta (eqs. alpha, beta), the PML stencils gamma
+ * (eq. gamma) for the global PML and for the auxiliary PML at the sampled
+ * local frequencies, slices the extended grid along i1 into floor((n+2)/w)
+ * slices, and factors every moving-PML slice subproblem (eq. Hwv_approx).
+ *   grid             dim and n
+ *   omega            angular frequency, > 0
+ *   m_dev            float64 [n][n] perturbation m = 1 - 1/c^2 on the interior grid;
+ *                    every value finite and < 1
+ *   pml_width        b >= 1, PML width in cells (global and auxiliary)
+ *   layer_thickness  w >= 1, interior lines per slice (the last slice takes the remainder)
+ *   opts             NULL for defaults
+ *   out              receives the handle (NULL on failure)
+ */
+ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int pml_width,
+                   int layer_thickness, const ls_options* opts, ls_handle** out);
+
+/*
+ * Solve (I + omega^2 K M) u = g for a batch of right-hand sides with
+ * right-preconditioned restarted GMRES (flexible form), stopping each
+ * right-hand side when its true relative residual is <= tol (Sec. 2.5).
+ *   rhs_dev    complex128 [nrhs][n][n]: g itself (LS_RHS_SOURCE) or the incident
+ *              wave u_I on the interior grid (LS_RHS_INCIDENT, g = -omega^2 K (m u_I))
+ *   u_dev      complex128 [nrhs][n][n] output, the scattered field
+ *   info_host  host array of nrhs entries (may be NULL)
+ * A zero right-hand side gives u = 0 after 0 iterations. Returns LS_E_NOCONV
+ * if any right-hand side hit max_iters (u and info are still written).
+ * Keeps the total fields needed by ls_adjoint.
+ */
+ls_status ls_solve(ls_handle* h, const void* rhs_dev, int nrhs, int rhs_kind, double tol,
+                   void* u_dev, ls_rhs_info* info_host);
+
+/*
+ * Gradient of J = sum_j 1/2 |R u_j - d_j|^2 with respect to the grid vector m,
+ * for the fields of the last ls_solve (same nrhs):
+ *   dJ/dm = -omega^2 Re sum_j psi_j * nu_j,   A nu_j = K conj(r_j),
+ * psi_j = u_j + u_I,j (incident kind) or u_j (source kind), r_j = R^T (R u_j - d_j).
+ *   resid_dev  complex128 [nrhs][n][n], the residuals r_j on the grid
+ *   grad_dev   float64 [n][n] output
+ *   info_host  host array of nrhs entries for the adjoint solves (may be NULL)
+ */
+ls_status ls_adjoint(ls_handle* h, const void* resid_dev, int nrhs, double tol, double* grad_dev,
+                     ls_rhs_info* info_host);
+
+/* Release every resource of the handle; NULL is a no-op. */
+void ls_destroy(ls_handle* h);
+
+/* Message of the last failure on the calling thread ("" if none). */
+const char* ls_last_error(void);
+
+/* ---- Per-operator entry points (parity tests and benchmarks) ---- */
+
+/* y = (I + omega^2 K M) x on the interior grid (eq. LS_d_c). x, y: [nrhs][n][n]. */
+ls_status ls_apply_A(ls_handle* h, const void* x_dev, int nrhs, void* y_dev, int precision);
+
+/* y = K x (the convolution with k alone). x, y: [nrhs][n][n]. */
+ls_status ls_apply_K(ls_handle* h, const void* x_dev, int nrhs, void* y_dev, int precision);
+
+/* f = Q r: f_i = alpha^* r_{mu_i} on I^h = [0, n+1]^2, 0 on the PML (eq. Huf).
+ * r: [nrhs][n][n] interior, f: [nrhs][L][L] extended. */
+ls_status ls_apply_Q(ls_handle* h, const void* r_dev, int nrhs, void* f_dev, int precision);
+
+/* y = H u on the extended grid (eqs. sp_stc, Huf), u = 0 on the Dirichlet ring.
+ * u, y: [nrhs][L][L]. */
+ls_status ls_apply_H(ls_handle* h, const void* u_dev, int nrhs, void* y_dev, int precision);
+
+/* z = P r, Algorithm 2: f = Q r, forward and backward sweep, restrict to I.
+ * r, z: [nrhs][n][n]. precision must equal the handle's. */
+ls_status ls_apply_precond(ls_handle* h, const void* r_dev, int nrhs, void* z_dev, int precision);
+
+/* w = T~_k v for slice k (0-based): the D_k part of the subproblem solution with
+ * right-hand side 0 on the auxiliary PML and v on D_k (eq. Hwv_approx).
+ * v, w: [nrhs][lines of D_k][L]. precision must equal the handle's. */
+ls_status ls_slice_solve(ls_handle* h, int slice, const void* v_dev, int nrhs, void* w_dev,
+                         int precision);
+
+typedef struct {
+  int dim, n, pml_width, layer_thickness, L, nslices, freq_samples, precision;
+  double omega, h, pml_C, freq_lo, freq_delta;
+} ls_setup_info;
+
+/* Sizes of the setup. */
+ls_status ls_get_info(const ls_handle* h, ls_setup_info* info_host);
+
+/* First and last grid line i1 of slice k, and its number of auxiliary lines. */
+ls_status ls_get_slice(const ls_handle* h, int slice, int* first_line, int* last_line, int* aux_lines);
+
+/* Copies of the setup tables, float64 interleaved complex, on the host:
+ *   alpha_host, beta_host  9 complex each (neighbourhood offsets (d1, d2) in
+ *                          {-1,0,1}^2, d1 slowest)
+ *   gamma_host             (2b+1)^2 x 9 complex, global PML stencils by per-axis
+ *                          class (c1, c2), c = 0 interior, 1..b for i = -b..-1,
+ *                          b+1..2b for i = n+2..n+1+b; entry (0,0) unused
+ *   aux_host               b x (2b+1) x freq_samples x 9 complex, auxiliary PML
+ *                          stencils by (depth q, class c2, sample k)
+ * Any pointer may be NULL. */
+ls_status ls_get_stencils(const ls_handle* h, double* alpha_host, double* beta_host,
+                          double* gamma_host, double* aux_host);
+
+/* Sample index k* for every extended-grid point, int32 [L][L] on the host. */
+ls_status ls_get_sample_map(const ls_handle* h, int* kmap_host);
+
+/*
+ * Host-only (no device needed): the float64 setup tables of Algorithm 1,
+ * steps 1-2, for a medium given on the host. Same tables and layouts as
+ * ls_get_stencils / ls_get_sample_map, plus
+ *   green_host  (n+2) x (n+2) complex, k_delta for delta in [0, n+1]^2
+ *               (k is even in each axis), float64 interleaved
+ * Any output pointer may be NULL. aux_host needs b x (2b+1) x ns x 9
+ * complex entries with ns = freq_samples (or n if freq_samples is 0, or 1
+ * when m is constant); entries no auxiliary point uses are zero.
+ */
+ls_status ls_host_tables(int n, double omega, const double* m_host, int pml_width, int layer_thickness,
+                         double pml_C, int freq_samples, double* alpha_host, double* beta_host,
+                         double* gamma_host, double* aux_host, int* kmap_host, double* green_host);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LSWEEP_H */

@@ -1,0 +1,1049 @@
+// C ABI of the solver: setup (Algorithm 1), the right-preconditioned
+// flexible GMRES loop in float64 around the applies (Sec. 2.5), the adjoint
+// gradient, and the per-operator entry points.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/lsweep.h"
+#include "kernels.hpp"
+#include "setup_host.hpp"
+
+namespace lsw {
+
+namespace {
+thread_local std::string g_error;
+}
+void set_error(const std::string& msg) { g_error = msg; }
+const char* get_error() { return g_error.c_str(); }
+
+namespace {
+
+// Device buffer owned by the handle.
+struct DBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DBuf() = default;
+  DBuf(const DBuf&) = delete;
+  DBuf& operator=(const DBuf&) = delete;
+  ~DBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  hipError_t alloc(size_t nbytes) {
+    if (nbytes <= bytes && p) return hipSuccess;
+    release();
+    if (nbytes == 0) nbytes = 16;
+    hipError_t e = hipMalloc(&p, nbytes);
+    if (e == hipSuccess) bytes = nbytes;
+    else p = nullptr;
+    return e;
+  }
+  template <typename X>
+  X* as() const { return static_cast<X*>(p); }
+};
+
+#define LSW_ALLOC(buf, nbytes)                                                      \
+  do {                                                                              \
+    if ((buf).alloc(nbytes) != hipSuccess) {                                        \
+      (void)hipGetLastError();                                                      \
+      lsw::set_error("device allocation of " + std::to_string((size_t)(nbytes)) +   \
+                     " bytes failed");                                              \
+      return LS_E_NOMEM;                                                            \
+    }                                                                               \
+  } while (0)
+
+}  // namespace
+}  // namespace lsw
+
+using namespace lsw;
+
+struct ls_handle {
+  int device = 0;
+  hipStream_t st = nullptr;
+  ls_options opt{};
+  HostSetup H;
+  int n = 0, b = 0, w = 0, L = 0, P = 0, ns = 0, nslices = 0, prec = LS_FP64;
+  double omega = 0;
+  size_t N = 0, E = 0;
+  // tables
+  DBuf m, m32, khat, khat32, tw, tw32, alpha, beta, gglob, gaux, kmap;
+  DBuf s_lo, s_hi, s_first, s_t, fs_off, fg_off, FS, FG, Hm, Hp, status;
+  // workspaces
+  int cap = 0;  // right-hand sides the workspaces hold
+  DBuf fftw64, fftw32, fext, uext, yscr, vin, zout, aout;
+  DBuf V, Z, W, X, G, R, T1, T2;
+  DBuf pairs, partials, coefs, outs, terms64, terms32, ptrs_a, ptrs_b;
+  // adjoint state
+  int last_nrhs = 0;
+  DBuf psi;
+
+  StencilTables stencils() const {
+    StencilTables s;
+    s.alpha = alpha.as<double2>();
+    s.beta = beta.as<double2>();
+    s.gglob = gglob.as<double2>();
+    s.gaux = gaux.as<double2>();
+    s.kmap = kmap.as<int>();
+    s.m = m.as<double>();
+    s.n = n;
+    s.b = b;
+    s.L = L;
+    s.ns = ns;
+    s.omega2 = omega * omega;
+    return s;
+  }
+  SliceTables slices() const {
+    SliceTables t;
+    t.lo = s_lo.as<int>();
+    t.hi = s_hi.as<int>();
+    t.first = s_first.as<int>();
+    t.t = s_t.as<int>();
+    t.fs_off = fs_off.as<size_t>();
+    t.fg_off = fg_off.as<size_t>();
+    t.nslices = nslices;
+    return t;
+  }
+};
+
+namespace {
+
+template <typename T>
+struct Prec;
+template <>
+struct Prec<double> {
+  static const double2* khat(const ls_handle* h) { return h->khat.as<double2>(); }
+  static const double2* tw(const ls_handle* h) { return h->tw.as<double2>(); }
+  static const double* m(const ls_handle* h) { return h->m.as<double>(); }
+  static double2* fftw(ls_handle* h) { return h->fftw64.as<double2>(); }
+};
+template <>
+struct Prec<float> {
+  static const float2* khat(const ls_handle* h) { return h->khat32.as<float2>(); }
+  static const float2* tw(const ls_handle* h) { return h->tw32.as<float2>(); }
+  static const float* m(const ls_handle* h) { return h->m32.as<float>(); }
+  static float2* fftw(ls_handle* h) { return h->fftw32.as<float2>(); }
+};
+
+ls_status check_handle(const ls_handle* h) {
+  if (!h) {
+    set_error("null handle");
+    return LS_E_INVALID;
+  }
+  return LS_OK;
+}
+
+// Workspaces sized for nrhs right-hand sides.
+ls_status ensure_workspace(ls_handle* h, int nrhs) {
+  if (nrhs <= h->cap) return LS_OK;
+  const size_t N = h->N, E = h->E;
+  const int rs = h->opt.restart;
+  const size_t cs = h->prec == LS_FP64 ? sizeof(double2) : sizeof(float2);
+  LSW_ALLOC(h->fftw64, fft_work_elems<double>(h->n, nrhs) * sizeof(double2));
+  LSW_ALLOC(h->fftw32, fft_work_elems<float>(h->n, nrhs) * sizeof(float2));
+  LSW_ALLOC(h->fext, (size_t)nrhs * E * cs);
+  LSW_ALLOC(h->uext, (size_t)nrhs * E * cs);
+  LSW_ALLOC(h->yscr, (size_t)nrhs * h->L * 32 * cs);
+  LSW_ALLOC(h->vin, (size_t)nrhs * N * cs);
+  LSW_ALLOC(h->zout, (size_t)nrhs * N * cs);
+  LSW_ALLOC(h->aout, (size_t)nrhs * N * cs);
+  LSW_ALLOC(h->V, (size_t)nrhs * (rs + 1) * N * sizeof(double2));
+  LSW_ALLOC(h->Z, (size_t)nrhs * rs * N * cs);
+  LSW_ALLOC(h->W, (size_t)nrhs * N * sizeof(double2));
+  LSW_ALLOC(h->X, (size_t)nrhs * N * sizeof(double2));
+  LSW_ALLOC(h->G, (size_t)nrhs * N * sizeof(double2));
+  LSW_ALLOC(h->R, (size_t)nrhs * N * sizeof(double2));
+  LSW_ALLOC(h->T1, (size_t)nrhs * N * sizeof(double2));
+  LSW_ALLOC(h->T2, (size_t)nrhs * N * sizeof(double2));
+  const size_t maxpairs = (size_t)nrhs * (rs + 2);
+  LSW_ALLOC(h->pairs, maxpairs * sizeof(DotPair));
+  LSW_ALLOC(h->partials, maxpairs * kDotBlocks * sizeof(double2));
+  LSW_ALLOC(h->coefs, (4 * maxpairs + 16) * sizeof(double2));
+  LSW_ALLOC(h->outs, (size_t)nrhs * 2 * sizeof(AxpyOut));
+  // two Gram-Schmidt passes of up to nrhs * restart terms each
+  LSW_ALLOC(h->terms64, (2 * maxpairs + 2 * nrhs) * sizeof(AxpyTerm<double>));
+  LSW_ALLOC(h->terms32, (2 * maxpairs + 2 * nrhs) * sizeof(AxpyTerm<float>));
+  LSW_ALLOC(h->ptrs_a, (size_t)nrhs * sizeof(void*));
+  LSW_ALLOC(h->ptrs_b, (size_t)nrhs * sizeof(void*));
+  h->cap = nrhs;
+  return LS_OK;
+}
+
+// Host -> device copy of a small descriptor table. Synchronous, so the host
+// vector may be reused as soon as this returns.
+template <typename X>
+ls_status upload(const ls_handle* h, DBuf& dst, const std::vector<X>& src) {
+  if (src.empty()) return LS_OK;
+  if (src.size() * sizeof(X) > dst.bytes) {
+    set_error("internal: descriptor table larger than its device buffer");
+    return LS_E_INVALID;
+  }
+  LSW_HIP_TRY(hipMemcpyAsync(dst.p, src.data(), src.size() * sizeof(X), hipMemcpyHostToDevice, h->st));
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  return LS_OK;
+}
+
+// ---- the applies, on contiguous batches ------------------------------------
+template <typename T>
+ls_status apply_A(ls_handle* h, const C<T>* x, int nb, C<T>* y) {
+  LSW_HIP_TRY(launch_convolve<T>(x, Prec<T>::m(h), h->n, nb, Prec<T>::khat(h), Prec<T>::tw(h), (T)1,
+                                 (T)(h->omega * h->omega), Prec<T>::fftw(h), y, h->st));
+  return LS_OK;
+}
+
+template <typename T>
+ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
+  const StencilTables S = h->stencils();
+  LSW_HIP_TRY(launch_apply_Q<T>(S, r, nb, h->fext.as<C<T>>(), h->st));
+  LSW_HIP_TRY(launch_sweep<T>(h->slices(), h->L, h->b, h->FS.as<C<T>>(), h->FG.as<C<T>>(), h->Hm.as<C<T>>(),
+                              h->Hp.as<C<T>>(), h->fext.as<C<T>>(), h->uext.as<C<T>>(), h->yscr.as<C<T>>(), nb,
+                              kSweepFull, 0, h->st));
+  LSW_HIP_TRY(launch_extract<T>(h->n, h->b, h->uext.as<C<T>>(), nb, z, h->st));
+  return LS_OK;
+}
+
+// ---- flexible GMRES, float64 outer loop (Sec. 2.5, reading G11) -----------
+struct RhsState {
+  int j = 0;          // Arnoldi steps in the current cycle
+  int iters = 0;      // over all cycles
+  int done = 0;       // 1 converged, 2 gave up
+  double beta0 = 0;   // ||g||
+  double relres = 0;
+  std::vector<std::complex<double>> Hm;  // (restart+1) x restart, column-major
+  std::vector<double> cs;
+  std::vector<std::complex<double>> sn, s;
+};
+
+void givens(std::complex<double> f, std::complex<double> g, double& c, std::complex<double>& s,
+            std::complex<double>& r) {
+  if (g == 0.0) {
+    c = 1.0;
+    s = 0.0;
+    r = f;
+    return;
+  }
+  if (f == 0.0) {
+    c = 0.0;
+    s = std::conj(g) / std::abs(g);
+    r = std::abs(g);
+    return;
+  }
+  const double af = std::abs(f), ag = std::abs(g);
+  const double rho = std::hypot(af, ag);
+  c = af / rho;
+  s = (f / af) * std::conj(g) / rho;
+  r = (f / af) * rho;
+}
+
+template <typename T>
+ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& info) {
+  // G holds g, X receives the solution.
+  const size_t N = h->N;
+  const int rs = h->opt.restart;
+  hipStream_t st = h->st;
+  double2* Vb = h->V.as<double2>();
+  C<T>* Zb = h->Z.as<C<T>>();
+  double2* Wb = h->W.as<double2>();
+  double2* Xb = h->X.as<double2>();
+  double2* Gb = h->G.as<double2>();
+  double2* Rb = h->R.as<double2>();
+  double2* coefs = h->coefs.as<double2>();
+  auto Vp = [&](int r, int k) { return Vb + ((size_t)r * (rs + 1) + k) * N; };
+  auto Zp = [&](int r, int k) { return Zb + ((size_t)r * rs + k) * N; };
+
+  std::vector<RhsState> S(nrhs);
+  for (auto& s : S) {
+    s.Hm.assign((size_t)(rs + 1) * rs, 0.0);
+    s.cs.assign(rs, 0.0);
+    s.sn.assign(rs, 0.0);
+    s.s.assign(rs + 1, 0.0);
+  }
+  LSW_HIP_TRY(hipMemsetAsync(Xb, 0, (size_t)nrhs * N * sizeof(double2), st));
+
+  std::vector<DotPair> hp;
+  std::vector<AxpyOut> ho;
+  std::vector<AxpyTerm<double>> ht64;
+  std::vector<AxpyTerm<T>> htT;
+  std::vector<double2> hc;
+  std::vector<void*> pa, pb;
+  const double2 one = make_double2(1.0, 0.0);
+
+  // norms of a set of vectors -> host
+  auto norms = [&](const std::vector<const double2*>& vecs, std::vector<double>& out) -> ls_status {
+    hp.clear();
+    for (auto v : vecs) hp.push_back({v, v});
+    if (upload(h, h->pairs, hp) != LS_OK) return LS_E_DEVICE;
+    LSW_HIP_TRY(launch_dots(h->pairs.as<DotPair>(), (int)hp.size(), N, h->partials.as<double2>(), coefs, st));
+    hc.resize(hp.size());
+    LSW_HIP_TRY(hipMemcpyAsync(hc.data(), coefs, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+    LSW_HIP_TRY(hipStreamSynchronize(st));
+    out.resize(vecs.size());
+    for (size_t i = 0; i < vecs.size(); ++i) out[i] = std::sqrt(std::max(hc[i].x, 0.0));
+    return LS_OK;
+  };
+  // y_i = src_i / nrm_i (host scalars) for a set of (y, src)
+  auto scaled_copies = [&](const std::vector<std::pair<double2*, const double2*>>& ys,
+                           const std::vector<double>& scal) -> ls_status {
+    ho.clear();
+    ht64.clear();
+    hc.assign(ys.size() + 1, one);
+    for (size_t i = 0; i < ys.size(); ++i) {
+      hc[i + 1] = make_double2(1.0 / scal[i], 0.0);
+      ht64.push_back({ys[i].second, (int)i + 1, 0});
+      ho.push_back({ys[i].first, (int)i, (int)i + 1, 1, -1, 0});
+    }
+    if (upload(h, h->coefs, hc) != LS_OK || upload(h, h->outs, ho) != LS_OK || upload(h, h->terms64, ht64) != LS_OK)
+      return LS_E_DEVICE;
+    LSW_HIP_TRY(launch_axpys<double>(h->outs.as<AxpyOut>(), (int)ho.size(), h->terms64.as<AxpyTerm<double>>(),
+                                     coefs, N, st));
+    return LS_OK;
+  };
+
+  // initial residual r = g (x0 = 0)
+  {
+    std::vector<const double2*> v;
+    for (int r = 0; r < nrhs; ++r) v.push_back(Gb + (size_t)r * N);
+    std::vector<double> nr;
+    ls_status e = norms(v, nr);
+    if (e != LS_OK) return e;
+    std::vector<std::pair<double2*, const double2*>> ys;
+    std::vector<double> sc;
+    for (int r = 0; r < nrhs; ++r) {
+      S[r].beta0 = nr[r];
+      if (!std::isfinite(nr[r])) {
+        set_error("right-hand side has a non-finite norm");
+        return LS_E_NUMERIC;
+      }
+      if (nr[r] == 0.0) {
+        S[r].done = 1;
+        continue;
+      }
+      S[r].s[0] = nr[r];
+      ys.push_back({Vp(r, 0), Gb + (size_t)r * N});
+      sc.push_back(nr[r]);
+    }
+    if (!ys.empty() && (e = scaled_copies(ys, sc)) != LS_OK) return e;
+  }
+
+  const int max_iters = h->opt.max_iters;
+  while (true) {
+    std::vector<int> act;
+    for (int r = 0; r < nrhs; ++r)
+      if (!S[r].done) act.push_back(r);
+    if (act.empty()) break;
+    const int na = (int)act.size();
+    C<T>* vin = h->vin.as<C<T>>();
+    C<T>* zout = h->zout.as<C<T>>();
+    C<T>* aout = h->aout.as<C<T>>();
+    // z = P v_j (precision T), kept in Z
+    pa.clear();
+    pb.clear();
+    for (int p = 0; p < na; ++p) {
+      pa.push_back(vin + (size_t)p * N);
+      pb.push_back(Vp(act[p], S[act[p]].j));
+    }
+    if (upload(h, h->ptrs_a, pa) != LS_OK || upload(h, h->ptrs_b, pb) != LS_OK) return LS_E_DEVICE;
+    LSW_HIP_TRY((launch_copy_cast<T, double>(h->ptrs_a.as<C<T>*>(), h->ptrs_b.as<const double2*>(), na, N, st)));
+    ls_status e = apply_P<T>(h, vin, na, zout);
+    if (e != LS_OK) return e;
+    pa.clear();
+    pb.clear();
+    for (int p = 0; p < na; ++p) {
+      pa.push_back(Zp(act[p], S[act[p]].j));
+      pb.push_back(zout + (size_t)p * N);
+    }
+    if (upload(h, h->ptrs_a, pa) != LS_OK || upload(h, h->ptrs_b, pb) != LS_OK) return LS_E_DEVICE;
+    LSW_HIP_TRY((launch_copy_cast<T, T>(h->ptrs_a.as<C<T>*>(), h->ptrs_b.as<const C<T>*>(), na, N, st)));
+    // w = A z (precision T) -> float64 work vector W[r]
+    if ((e = apply_A<T>(h, zout, na, aout)) != LS_OK) return e;
+    pa.clear();
+    pb.clear();
+    for (int p = 0; p < na; ++p) {
+      pa.push_back(Wb + (size_t)act[p] * N);
+      pb.push_back(aout + (size_t)p * N);
+    }
+    if (upload(h, h->ptrs_a, pa) != LS_OK || upload(h, h->ptrs_b, pb) != LS_OK) return LS_E_DEVICE;
+    LSW_HIP_TRY((launch_copy_cast<double, T>(h->ptrs_a.as<double2*>(), h->ptrs_b.as<const C<T>*>(), na, N, st)));
+    // classical Gram-Schmidt, twice, then the norm
+    hp.clear();
+    std::vector<int> off(na + 1, 0);
+    for (int p = 0; p < na; ++p) {
+      const int r = act[p];
+      for (int k = 0; k <= S[r].j; ++k) hp.push_back({Vp(r, k), Wb + (size_t)r * N});
+      off[p + 1] = (int)hp.size();
+    }
+    const int np = (int)hp.size();
+    for (int p = 0; p < na; ++p) hp.push_back({Wb + (size_t)act[p] * N, Wb + (size_t)act[p] * N});
+    if (upload(h, h->pairs, hp) != LS_OK) return LS_E_DEVICE;
+    const int base1 = 1, base2 = 1 + np, base3 = 1 + 2 * np;
+    ho.clear();
+    ht64.clear();
+    for (int p = 0; p < na; ++p) {
+      const int r = act[p];
+      AxpyOut o{Wb + (size_t)r * N, (int)ht64.size(), 0, 0, -1, 0};
+      for (int k = 0; k <= S[r].j; ++k) ht64.push_back({Vp(r, k), base1 + off[p] + k, 1});
+      o.tend = (int)ht64.size();
+      ho.push_back(o);
+    }
+    // second-pass terms use the base2 coefficients
+    const int nterm = (int)ht64.size();
+    for (int i = 0; i < nterm; ++i) ht64.push_back({ht64[i].x, ht64[i].coef + np, 1});
+    for (int p = 0; p < na; ++p) {
+      AxpyOut o = ho[p];
+      o.tbeg += nterm;
+      o.tend += nterm;
+      ho.push_back(o);
+    }
+    hc.assign(1, one);
+    if (upload(h, h->coefs, hc) != LS_OK || upload(h, h->outs, ho) != LS_OK || upload(h, h->terms64, ht64) != LS_OK)
+      return LS_E_DEVICE;
+    LSW_HIP_TRY(launch_dots(h->pairs.as<DotPair>(), np, N, h->partials.as<double2>(), coefs + base1, st));
+    LSW_HIP_TRY(launch_axpys<double>(h->outs.as<AxpyOut>(), na, h->terms64.as<AxpyTerm<double>>(), coefs, N, st));
+    LSW_HIP_TRY(launch_dots(h->pairs.as<DotPair>(), np, N, h->partials.as<double2>(), coefs + base2, st));
+    LSW_HIP_TRY(launch_axpys<double>(h->outs.as<AxpyOut>() + na, na, h->terms64.as<AxpyTerm<double>>(), coefs, N, st));
+    LSW_HIP_TRY(launch_dots(h->pairs.as<DotPair>() + np, na, N, h->partials.as<double2>(), coefs + base3, st));
+    hc.resize(base3 + na);
+    LSW_HIP_TRY(hipMemcpyAsync(hc.data(), coefs, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+    LSW_HIP_TRY(hipStreamSynchronize(st));
+    // next basis vectors v_{j+1} = w / ||w|| (scale read on the device)
+    ho.clear();
+    ht64.clear();
+    std::vector<int> ending;
+    for (int p = 0; p < na; ++p) {
+      const int r = act[p];
+      RhsState& s = S[r];
+      const int j = s.j;
+      std::complex<double>* col = &s.Hm[(size_t)j * (rs + 1)];
+      for (int k = 0; k <= j; ++k) {
+        const double2 a = hc[base1 + off[p] + k], c2 = hc[base2 + off[p] + k];
+        col[k] = std::complex<double>(a.x + c2.x, a.y + c2.y);
+      }
+      const double w2 = hc[base3 + p].x;
+      const double hn = std::sqrt(std::max(w2, 0.0));
+      if (!std::isfinite(hn)) {
+        set_error("non-finite norm in the Arnoldi process");
+        return LS_E_NUMERIC;
+      }
+      col[j + 1] = hn;
+      for (int k = 0; k < j; ++k) {
+        const std::complex<double> a = col[k], c = col[k + 1];
+        col[k] = s.cs[k] * a + s.sn[k] * c;
+        col[k + 1] = -std::conj(s.sn[k]) * a + s.cs[k] * c;
+      }
+      double c;
+      std::complex<double> sg, rr;
+      givens(col[j], col[j + 1], c, sg, rr);
+      s.cs[j] = c;
+      s.sn[j] = sg;
+      col[j] = rr;
+      col[j + 1] = 0.0;
+      s.s[j + 1] = -std::conj(sg) * s.s[j];
+      s.s[j] = c * s.s[j];
+      s.iters += 1;
+      s.j += 1;
+      const bool conv = std::abs(s.s[j + 1]) <= tol * s.beta0;
+      if (conv || s.j == rs || s.iters >= max_iters || hn == 0.0) {
+        ending.push_back(r);
+      } else {
+        ht64.push_back({Wb + (size_t)r * N, 0, 0});
+        ho.push_back({Vp(r, s.j), (int)ht64.size() - 1, (int)ht64.size(), 1, base3 + p, 1});
+      }
+    }
+    if (!ho.empty()) {
+      if (upload(h, h->outs, ho) != LS_OK || upload(h, h->terms64, ht64) != LS_OK) return LS_E_DEVICE;
+      LSW_HIP_TRY(launch_axpys<double>(h->outs.as<AxpyOut>(), (int)ho.size(), h->terms64.as<AxpyTerm<double>>(),
+                                       coefs, N, st));
+      LSW_HIP_TRY(hipStreamSynchronize(st));
+    }
+    if (ending.empty()) continue;
+    // cycle end: x += Z y, true residual in float64
+    ho.clear();
+    htT.clear();
+    hc.assign(1, one);
+    for (int r : ending) {
+      RhsState& s = S[r];
+      const int j = s.j;
+      std::vector<std::complex<double>> y(j);
+      for (int i = j - 1; i >= 0; --i) {
+        std::complex<double> acc = s.s[i];
+        for (int k = i + 1; k < j; ++k) acc -= s.Hm[(size_t)k * (rs + 1) + i] * y[k];
+        y[i] = acc / s.Hm[(size_t)i * (rs + 1) + i];
+      }
+      AxpyOut o{Xb + (size_t)r * N, (int)htT.size(), 0, 0, -1, 0};
+      for (int i = 0; i < j; ++i) {
+        hc.push_back(make_double2(y[i].real(), y[i].imag()));
+        htT.push_back({Zp(r, i), (int)hc.size() - 1, 0});
+      }
+      o.tend = (int)htT.size();
+      ho.push_back(o);
+    }
+    if (upload(h, h->coefs, hc) != LS_OK || upload(h, h->outs, ho) != LS_OK) return LS_E_DEVICE;
+    DBuf& tb = std::is_same<T, double>::value ? h->terms64 : h->terms32;
+    if (upload(h, tb, htT) != LS_OK) return LS_E_DEVICE;
+    LSW_HIP_TRY(launch_axpys<T>(h->outs.as<AxpyOut>(), (int)ho.size(), tb.as<AxpyTerm<T>>(), coefs, N, st));
+    // pack x of the ending set, A x in float64, r = g - A x
+    const int ne = (int)ending.size();
+    double2* T1 = h->T1.as<double2>();
+    double2* T2 = h->T2.as<double2>();
+    pa.clear();
+    pb.clear();
+    for (int p = 0; p < ne; ++p) {
+      pa.push_back(T1 + (size_t)p * N);
+      pb.push_back(Xb + (size_t)ending[p] * N);
+    }
+    if (upload(h, h->ptrs_a, pa) != LS_OK || upload(h, h->ptrs_b, pb) != LS_OK) return LS_E_DEVICE;
+    LSW_HIP_TRY((launch_copy_cast<double, double>(h->ptrs_a.as<double2*>(), h->ptrs_b.as<const double2*>(), ne, N, st)));
+    if ((e = apply_A<double>(h, T1, ne, T2)) != LS_OK) return e;
+    ho.clear();
+    ht64.clear();
+    for (int p = 0; p < ne; ++p) {
+      const int r = ending[p];
+      ht64.push_back({Gb + (size_t)r * N, 0, 0});
+      ht64.push_back({T2 + (size_t)p * N, 0, 1});
+      ho.push_back({Rb + (size_t)r * N, 2 * p, 2 * p + 2, 1, -1, 0});
+    }
+    hc.assign(1, one);
+    if (upload(h, h->coefs, hc) != LS_OK || upload(h, h->outs, ho) != LS_OK || upload(h, h->terms64, ht64) != LS_OK)
+      return LS_E_DEVICE;
+    LSW_HIP_TRY(launch_axpys<double>(h->outs.as<AxpyOut>(), ne, h->terms64.as<AxpyTerm<double>>(), coefs, N, st));
+    std::vector<const double2*> rv;
+    for (int r : ending) rv.push_back(Rb + (size_t)r * N);
+    std::vector<double> rn;
+    if ((e = norms(rv, rn)) != LS_OK) return e;
+    std::vector<std::pair<double2*, const double2*>> ys;
+    std::vector<double> sc;
+    for (int p = 0; p < ne; ++p) {
+      const int r = ending[p];
+      RhsState& s = S[r];
+      if (!std::isfinite(rn[p])) {
+        set_error("non-finite true residual");
+        return LS_E_NUMERIC;
+      }
+      s.relres = rn[p] / s.beta0;
+      if (s.relres <= tol) {
+        s.done = 1;
+      } else if (s.iters >= max_iters) {
+        s.done = 2;
+      } else if (rn[p] == 0.0) {
+        s.done = 1;
+      } else {
+        // restart from the true residual
+        s.j = 0;
+        std::fill(s.s.begin(), s.s.end(), 0.0);
+        s.s[0] = rn[p];
+        ys.push_back({Vp(r, 0), Rb + (size_t)r * N});
+        sc.push_back(rn[p]);
+      }
+    }
+    if (!ys.empty() && (e = scaled_copies(ys, sc)) != LS_OK) return e;
+    LSW_HIP_TRY(hipStreamSynchronize(st));
+  }
+  info.resize(nrhs);
+  bool all = true;
+  for (int r = 0; r < nrhs; ++r) {
+    info[r].iterations = S[r].iters;
+    info[r].rel_residual = S[r].beta0 == 0.0 ? 0.0 : S[r].relres;
+    info[r].converged = S[r].done == 1;
+    all = all && S[r].done == 1;
+  }
+  if (!all) {
+    set_error("GMRES reached max_iters before the tolerance for some right-hand side");
+    return LS_E_NOCONV;
+  }
+  return LS_OK;
+}
+
+ls_status run_gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& info) {
+  return h->prec == LS_FP64 ? gmres<double>(h, nrhs, tol, info) : gmres<float>(h, nrhs, tol, info);
+}
+
+ls_status device_setup(ls_handle* h, const double* m_dev) {
+  HostSetup& Hs = h->H;
+  const int n = h->n, L = h->L, P = h->P;
+  hipStream_t st = h->st;
+  // tables to the device
+  LSW_ALLOC(h->m, (size_t)n * n * sizeof(double));
+  LSW_HIP_TRY(hipMemcpyAsync(h->m.p, m_dev, (size_t)n * n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  std::vector<float> m32((size_t)n * n);
+  {
+    std::vector<double> mh((size_t)n * n);
+    LSW_HIP_TRY(hipMemcpy(mh.data(), m_dev, mh.size() * sizeof(double), hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < mh.size(); ++i) m32[i] = (float)mh[i];
+  }
+  LSW_ALLOC(h->m32, m32.size() * sizeof(float));
+  LSW_HIP_TRY(hipMemcpyAsync(h->m32.p, m32.data(), m32.size() * sizeof(float), hipMemcpyHostToDevice, st));
+  std::vector<double2> tw(P);
+  std::vector<float2> tw32(P);
+  for (int k = 0; k < P; ++k) {
+    const double a = -2.0 * M_PI * (double)k / (double)P;
+    tw[k] = make_double2(std::cos(a), std::sin(a));
+    tw32[k] = make_float2((float)tw[k].x, (float)tw[k].y);
+  }
+  LSW_ALLOC(h->tw, P * sizeof(double2));
+  LSW_ALLOC(h->tw32, P * sizeof(float2));
+  LSW_HIP_TRY(hipMemcpyAsync(h->tw.p, tw.data(), P * sizeof(double2), hipMemcpyHostToDevice, st));
+  LSW_HIP_TRY(hipMemcpyAsync(h->tw32.p, tw32.data(), P * sizeof(float2), hipMemcpyHostToDevice, st));
+  auto to_d2 = [](const std::vector<cd>& v) {
+    std::vector<double2> o(v.size());
+    for (size_t i = 0; i < v.size(); ++i) o[i] = make_double2(v[i].real(), v[i].imag());
+    return o;
+  };
+  // Green's table quadrant -> khat
+  {
+    DBuf kq, scratch;
+    const std::vector<double2> kq_h = to_d2(Hs.kq);
+    LSW_ALLOC(kq, kq_h.size() * sizeof(double2));
+    LSW_ALLOC(scratch, (size_t)P * P * sizeof(double2));
+    const size_t half = (size_t)(P / 2 + 1) * (P / 2 + 1);
+    LSW_ALLOC(h->khat, half * sizeof(double2));
+    LSW_ALLOC(h->khat32, half * sizeof(float2));
+    LSW_HIP_TRY(hipMemcpyAsync(kq.p, kq_h.data(), kq_h.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+    LSW_HIP_TRY(launch_green_spectrum(kq.as<double2>(), n, h->tw.as<double2>(), scratch.as<double2>(),
+                                      h->khat.as<double2>(), h->khat32.as<float2>(), st));
+    LSW_HIP_TRY(hipStreamSynchronize(st));
+  }
+  std::vector<double2> ab(9), bb(9);
+  for (int i = 0; i < 9; ++i) {
+    ab[i] = make_double2(Hs.alpha[i].real(), Hs.alpha[i].imag());
+    bb[i] = make_double2(Hs.beta[i].real(), Hs.beta[i].imag());
+  }
+  LSW_ALLOC(h->alpha, 9 * sizeof(double2));
+  LSW_ALLOC(h->beta, 9 * sizeof(double2));
+  if (upload(h, h->alpha, ab) != LS_OK || upload(h, h->beta, bb) != LS_OK) return LS_E_DEVICE;
+  const std::vector<double2> gg = to_d2(Hs.gamma_glob), ga = to_d2(Hs.gamma_aux);
+  LSW_ALLOC(h->gglob, gg.size() * sizeof(double2));
+  LSW_ALLOC(h->gaux, std::max<size_t>(ga.size(), 1) * sizeof(double2));
+  LSW_ALLOC(h->kmap, Hs.kmap.size() * sizeof(int));
+  if (upload(h, h->gglob, gg) != LS_OK || upload(h, h->gaux, ga) != LS_OK || upload(h, h->kmap, Hs.kmap) != LS_OK)
+    return LS_E_DEVICE;
+  // slice plan and factor storage
+  const int nl = h->nslices;
+  std::vector<int> lo(nl), hi(nl), first(nl), t(nl);
+  std::vector<size_t> fso(nl), fgo(nl);
+  size_t fs_tot = 0, fg_tot = 0;
+  for (int k = 0; k < nl; ++k) {
+    const SlicePlan& p = Hs.slices[k];
+    lo[k] = p.lo;
+    hi[k] = p.hi;
+    first[k] = p.first;
+    t[k] = p.t;
+    fso[k] = fs_tot;
+    fgo[k] = fg_tot;
+    fs_tot += (size_t)L * (p.t * p.t + 3 * p.t);
+    fg_tot += (size_t)L * p.t * p.t;
+  }
+  LSW_ALLOC(h->s_lo, nl * sizeof(int));
+  LSW_ALLOC(h->s_hi, nl * sizeof(int));
+  LSW_ALLOC(h->s_first, nl * sizeof(int));
+  LSW_ALLOC(h->s_t, nl * sizeof(int));
+  LSW_ALLOC(h->fs_off, nl * sizeof(size_t));
+  LSW_ALLOC(h->fg_off, nl * sizeof(size_t));
+  if (upload(h, h->s_lo, lo) != LS_OK || upload(h, h->s_hi, hi) != LS_OK || upload(h, h->s_first, first) != LS_OK ||
+      upload(h, h->s_t, t) != LS_OK || upload(h, h->fs_off, fso) != LS_OK || upload(h, h->fg_off, fgo) != LS_OK)
+    return LS_E_DEVICE;
+  const size_t cs = h->prec == LS_FP64 ? sizeof(double2) : sizeof(float2);
+  LSW_ALLOC(h->FS, fs_tot * cs);
+  LSW_ALLOC(h->FG, fg_tot * cs);
+  LSW_ALLOC(h->Hm, (size_t)nl * L * 3 * cs);
+  LSW_ALLOC(h->Hp, (size_t)nl * L * 3 * cs);
+  LSW_ALLOC(h->status, sizeof(int));
+  LSW_HIP_TRY(hipMemsetAsync(h->status.p, 0, sizeof(int), st));
+  const StencilTables S = h->stencils();
+  if (h->prec == LS_FP64) {
+    LSW_HIP_TRY(launch_factor_slices<double>(S, h->slices(), h->FS.as<double2>(), h->FG.as<double2>(),
+                                             h->Hm.as<double2>(), h->Hp.as<double2>(), h->status.as<int>(), st));
+  } else {
+    LSW_HIP_TRY(launch_factor_slices<float>(S, h->slices(), h->FS.as<float2>(), h->FG.as<float2>(),
+                                            h->Hm.as<float2>(), h->Hp.as<float2>(), h->status.as<int>(), st));
+  }
+  int status = 0;
+  LSW_HIP_TRY(hipMemcpyAsync(&status, h->status.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  LSW_HIP_TRY(hipStreamSynchronize(st));
+  if (status != 0) {
+    set_error("zero pivot in the factorization of slice " + std::to_string(status - 1));
+    return LS_E_SINGULAR;
+  }
+  return LS_OK;
+}
+
+ls_status check_precision(const ls_handle* h, int precision, bool factors) {
+  if (precision != LS_FP64 && precision != LS_MIXED) {
+    set_error("precision must be LS_FP64 or LS_MIXED");
+    return LS_E_INVALID;
+  }
+  if (factors && precision != h->prec) {
+    set_error("this entry point needs the handle's own precision");
+    return LS_E_INVALID;
+  }
+  return LS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void ls_default_options(ls_options* o) {
+  if (!o) return;
+  o->precision = LS_FP64;
+  o->restart = 30;
+  o->max_iters = 1000;
+  o->pml_C = 10.0;
+  o->freq_samples = 0;
+  o->autotune = 0;
+  o->hip_stream = nullptr;
+}
+
+const char* ls_last_error(void) { return lsw::get_error(); }
+
+ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int pml_width, int layer_thickness,
+                   const ls_options* opts, ls_handle** out) {
+  try {
+    set_error("");
+    if (!out) {
+      set_error("out must not be NULL");
+      return LS_E_INVALID;
+    }
+    *out = nullptr;
+    if (!grid || !m_dev) {
+      set_error("grid and m_dev must not be NULL");
+      return LS_E_INVALID;
+    }
+    if (grid->dim != 2) {
+      set_error("only dim = 2 is implemented");
+      return LS_E_INVALID;
+    }
+    ls_options o;
+    ls_default_options(&o);
+    if (opts) o = *opts;
+    if (o.precision != LS_FP64 && o.precision != LS_MIXED) {
+      set_error("precision must be LS_FP64 or LS_MIXED");
+      return LS_E_INVALID;
+    }
+    if (o.restart < 1 || o.restart > 200 || o.max_iters < 1) {
+      set_error("restart must be in [1, 200] and max_iters >= 1");
+      return LS_E_INVALID;
+    }
+    std::unique_ptr<ls_handle> h(new ls_handle());
+    h->opt = o;
+    h->st = static_cast<hipStream_t>(o.hip_stream);
+    LSW_HIP_TRY(hipGetDevice(&h->device));
+    const int n = grid->n;
+    if (n < 1 || n > 16383) {
+      set_error("n must be in [1, 16383]");
+      return LS_E_INVALID;
+    }
+    std::vector<double> mh((size_t)n * n);
+    LSW_HIP_TRY(hipMemcpy(mh.data(), m_dev, mh.size() * sizeof(double), hipMemcpyDeviceToHost));
+    const std::string err = build_host_setup(mh.data(), n, omega, pml_width, layer_thickness, o.pml_C,
+                                             o.freq_samples, h->H);
+    if (!err.empty()) {
+      set_error(err);
+      return LS_E_INVALID;
+    }
+    h->n = n;
+    h->b = pml_width;
+    h->w = layer_thickness;
+    h->L = h->H.L;
+    h->P = fft_len(n);
+    h->ns = h->H.ns;
+    h->nslices = h->H.nslices;
+    h->omega = omega;
+    h->prec = o.precision;
+    h->N = (size_t)n * n;
+    h->E = (size_t)h->L * h->L;
+    ls_status e = device_setup(h.get(), m_dev);
+    if (e != LS_OK) return e;
+    *out = h.release();
+    return LS_OK;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return LS_E_NOMEM;
+  } catch (const std::exception& ex) {
+    set_error(ex.what());
+    return LS_E_INVALID;
+  }
+}
+
+void ls_destroy(ls_handle* h) { delete h; }
+
+ls_status ls_solve(ls_handle* h, const void* rhs_dev, int nrhs, int rhs_kind, double tol, void* u_dev,
+                   ls_rhs_info* info_host) {
+  try {
+    if (check_handle(h) != LS_OK) return LS_E_INVALID;
+    if (nrhs < 1 || !rhs_dev || !u_dev || !(tol > 0.0) || !std::isfinite(tol) ||
+        (rhs_kind != LS_RHS_SOURCE && rhs_kind != LS_RHS_INCIDENT)) {
+      set_error("ls_solve: bad argument (nrhs >= 1, non-null arrays, tol > 0, rhs_kind)");
+      return LS_E_INVALID;
+    }
+    ls_status e = ensure_workspace(h, nrhs);
+    if (e != LS_OK) return e;
+    const size_t N = h->N;
+    double2* G = h->G.as<double2>();
+    if (rhs_kind == LS_RHS_INCIDENT) {
+      // g = -omega^2 K (m u_I)
+      LSW_HIP_TRY(launch_convolve<double>(static_cast<const double2*>(rhs_dev), h->m.as<double>(), h->n, nrhs,
+                                          h->khat.as<double2>(), h->tw.as<double2>(), 0.0, -h->omega * h->omega,
+                                          h->fftw64.as<double2>(), G, h->st));
+    } else {
+      LSW_HIP_TRY(hipMemcpyAsync(G, rhs_dev, (size_t)nrhs * N * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
+    }
+    std::vector<ls_rhs_info> info;
+    h->last_nrhs = 0;
+    const ls_status gs = run_gmres(h, nrhs, tol, info);
+    if (gs != LS_OK && gs != LS_E_NOCONV) return gs;
+    LSW_HIP_TRY(hipMemcpyAsync(u_dev, h->X.p, (size_t)nrhs * N * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
+    // total field psi = u + u_I (incident) or u (source), kept for ls_adjoint
+    LSW_ALLOC(h->psi, (size_t)nrhs * N * sizeof(double2));
+    LSW_HIP_TRY(hipMemcpyAsync(h->psi.p, h->X.p, (size_t)nrhs * N * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
+    if (rhs_kind == LS_RHS_INCIDENT)
+      LSW_HIP_TRY(launch_add_scaled(h->psi.as<double2>(), static_cast<const double2*>(rhs_dev), 1.0, (size_t)nrhs * N,
+                                    h->st));
+    LSW_HIP_TRY(hipStreamSynchronize(h->st));
+    h->last_nrhs = nrhs;
+    if (info_host)
+      for (int r = 0; r < nrhs; ++r) info_host[r] = info[r];
+    return gs;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return LS_E_NOMEM;
+  } catch (const std::exception& ex) {
+    set_error(ex.what());
+    return LS_E_INVALID;
+  }
+}
+
+ls_status ls_adjoint(ls_handle* h, const void* resid_dev, int nrhs, double tol, double* grad_dev,
+                     ls_rhs_info* info_host) {
+  try {
+    if (check_handle(h) != LS_OK) return LS_E_INVALID;
+    if (h->last_nrhs == 0 || nrhs != h->last_nrhs) {
+      set_error("ls_adjoint needs a preceding ls_solve with the same nrhs");
+      return LS_E_STATE;
+    }
+    if (!resid_dev || !grad_dev || !(tol > 0.0)) {
+      set_error("ls_adjoint: bad argument");
+      return LS_E_INVALID;
+    }
+    const size_t N = h->N;
+    // b_j = K conj(r_j)
+    double2* T1 = h->T1.as<double2>();
+    LSW_HIP_TRY(launch_conj(T1, static_cast<const double2*>(resid_dev), (size_t)nrhs * N, h->st));
+    LSW_HIP_TRY(launch_convolve<double>(T1, nullptr, h->n, nrhs, h->khat.as<double2>(), h->tw.as<double2>(), 0.0, 1.0,
+                                        h->fftw64.as<double2>(), h->G.as<double2>(), h->st));
+    std::vector<ls_rhs_info> info;
+    const ls_status gs = run_gmres(h, nrhs, tol, info);
+    if (gs != LS_OK && gs != LS_E_NOCONV) return gs;
+    LSW_HIP_TRY(launch_adjoint_product(h->psi.as<double2>(), h->X.as<double2>(), nrhs, N, h->omega * h->omega,
+                                       grad_dev, h->st));
+    LSW_HIP_TRY(hipStreamSynchronize(h->st));
+    if (info_host)
+      for (int r = 0; r < nrhs; ++r) info_host[r] = info[r];
+    return gs;
+  } catch (const std::exception& ex) {
+    set_error(ex.what());
+    return LS_E_INVALID;
+  }
+}
+
+ls_status ls_apply_A(ls_handle* h, const void* x, int nrhs, void* y, int precision) {
+  if (check_handle(h) != LS_OK || check_precision(h, precision, false) != LS_OK) return LS_E_INVALID;
+  if (nrhs < 1 || !x || !y) {
+    set_error("ls_apply_A: bad argument");
+    return LS_E_INVALID;
+  }
+  ls_status e = ensure_workspace(h, nrhs);
+  if (e != LS_OK) return e;
+  e = precision == LS_FP64
+          ? apply_A<double>(h, static_cast<const double2*>(x), nrhs, static_cast<double2*>(y))
+          : apply_A<float>(h, static_cast<const float2*>(x), nrhs, static_cast<float2*>(y));
+  if (e != LS_OK) return e;
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  return LS_OK;
+}
+
+ls_status ls_apply_K(ls_handle* h, const void* x, int nrhs, void* y, int precision) {
+  if (check_handle(h) != LS_OK || check_precision(h, precision, false) != LS_OK) return LS_E_INVALID;
+  if (nrhs < 1 || !x || !y) {
+    set_error("ls_apply_K: bad argument");
+    return LS_E_INVALID;
+  }
+  ls_status e = ensure_workspace(h, nrhs);
+  if (e != LS_OK) return e;
+  if (precision == LS_FP64)
+    LSW_HIP_TRY(launch_convolve<double>(static_cast<const double2*>(x), nullptr, h->n, nrhs, h->khat.as<double2>(),
+                                        h->tw.as<double2>(), 0.0, 1.0, h->fftw64.as<double2>(),
+                                        static_cast<double2*>(y), h->st));
+  else
+    LSW_HIP_TRY(launch_convolve<float>(static_cast<const float2*>(x), nullptr, h->n, nrhs, h->khat32.as<float2>(),
+                                       h->tw32.as<float2>(), 0.0f, 1.0f, h->fftw32.as<float2>(),
+                                       static_cast<float2*>(y), h->st));
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  return LS_OK;
+}
+
+ls_status ls_apply_Q(ls_handle* h, const void* r, int nrhs, void* f, int precision) {
+  if (check_handle(h) != LS_OK || check_precision(h, precision, false) != LS_OK) return LS_E_INVALID;
+  if (nrhs < 1 || !r || !f) {
+    set_error("ls_apply_Q: bad argument");
+    return LS_E_INVALID;
+  }
+  const StencilTables S = h->stencils();
+  if (precision == LS_FP64)
+    LSW_HIP_TRY(launch_apply_Q<double>(S, static_cast<const double2*>(r), nrhs, static_cast<double2*>(f), h->st));
+  else
+    LSW_HIP_TRY(launch_apply_Q<float>(S, static_cast<const float2*>(r), nrhs, static_cast<float2*>(f), h->st));
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  return LS_OK;
+}
+
+ls_status ls_apply_H(ls_handle* h, const void* u, int nrhs, void* y, int precision) {
+  if (check_handle(h) != LS_OK || check_precision(h, precision, false) != LS_OK) return LS_E_INVALID;
+  if (nrhs < 1 || !u || !y) {
+    set_error("ls_apply_H: bad argument");
+    return LS_E_INVALID;
+  }
+  const StencilTables S = h->stencils();
+  if (precision == LS_FP64)
+    LSW_HIP_TRY(launch_apply_H<double>(S, static_cast<const double2*>(u), nrhs, static_cast<double2*>(y), h->st));
+  else
+    LSW_HIP_TRY(launch_apply_H<float>(S, static_cast<const float2*>(u), nrhs, static_cast<float2*>(y), h->st));
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  return LS_OK;
+}
+
+ls_status ls_apply_precond(ls_handle* h, const void* r, int nrhs, void* z, int precision) {
+  if (check_handle(h) != LS_OK || check_precision(h, precision, true) != LS_OK) return LS_E_INVALID;
+  if (nrhs < 1 || !r || !z) {
+    set_error("ls_apply_precond: bad argument");
+    return LS_E_INVALID;
+  }
+  ls_status e = ensure_workspace(h, nrhs);
+  if (e != LS_OK) return e;
+  e = precision == LS_FP64 ? apply_P<double>(h, static_cast<const double2*>(r), nrhs, static_cast<double2*>(z))
+                           : apply_P<float>(h, static_cast<const float2*>(r), nrhs, static_cast<float2*>(z));
+  if (e != LS_OK) return e;
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  return LS_OK;
+}
+
+ls_status ls_slice_solve(ls_handle* h, int slice, const void* v, int nrhs, void* w, int precision) {
+  if (check_handle(h) != LS_OK || check_precision(h, precision, true) != LS_OK) return LS_E_INVALID;
+  if (nrhs < 1 || !v || !w || slice < 0 || slice >= h->nslices) {
+    set_error("ls_slice_solve: bad argument");
+    return LS_E_INVALID;
+  }
+  ls_status e = ensure_workspace(h, nrhs);
+  if (e != LS_OK) return e;
+  if (precision == LS_FP64)
+    LSW_HIP_TRY(launch_sweep<double>(h->slices(), h->L, h->b, h->FS.as<double2>(), h->FG.as<double2>(),
+                                     h->Hm.as<double2>(), h->Hp.as<double2>(), static_cast<const double2*>(v),
+                                     static_cast<double2*>(w), h->yscr.as<double2>(), nrhs, kSliceOnly, slice, h->st));
+  else
+    LSW_HIP_TRY(launch_sweep<float>(h->slices(), h->L, h->b, h->FS.as<float2>(), h->FG.as<float2>(),
+                                    h->Hm.as<float2>(), h->Hp.as<float2>(), static_cast<const float2*>(v),
+                                    static_cast<float2*>(w), h->yscr.as<float2>(), nrhs, kSliceOnly, slice, h->st));
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  return LS_OK;
+}
+
+ls_status ls_get_info(const ls_handle* h, ls_setup_info* o) {
+  if (check_handle(h) != LS_OK) return LS_E_INVALID;
+  if (!o) {
+    set_error("info must not be NULL");
+    return LS_E_INVALID;
+  }
+  o->dim = 2;
+  o->n = h->n;
+  o->pml_width = h->b;
+  o->layer_thickness = h->w;
+  o->L = h->L;
+  o->nslices = h->nslices;
+  o->freq_samples = h->ns;
+  o->precision = h->prec;
+  o->omega = h->omega;
+  o->h = h->H.h;
+  o->pml_C = h->H.C;
+  o->freq_lo = h->H.freq_lo;
+  o->freq_delta = h->H.freq_delta;
+  return LS_OK;
+}
+
+ls_status ls_get_slice(const ls_handle* h, int slice, int* first_line, int* last_line, int* aux_lines) {
+  if (check_handle(h) != LS_OK) return LS_E_INVALID;
+  if (slice < 0 || slice >= h->nslices) {
+    set_error("slice out of range");
+    return LS_E_INVALID;
+  }
+  const SlicePlan& p = h->H.slices[slice];
+  if (first_line) *first_line = p.lo;
+  if (last_line) *last_line = p.hi;
+  if (aux_lines) *aux_lines = p.naux;
+  return LS_OK;
+}
+
+ls_status ls_get_stencils(const ls_handle* h, double* alpha, double* beta, double* gamma, double* aux) {
+  if (check_handle(h) != LS_OK) return LS_E_INVALID;
+  auto put = [](double* dst, const cd* src, size_t count) {
+    for (size_t i = 0; i < count; ++i) {
+      dst[2 * i] = src[i].real();
+      dst[2 * i + 1] = src[i].imag();
+    }
+  };
+  if (alpha) put(alpha, h->H.alpha, 9);
+  if (beta) put(beta, h->H.beta, 9);
+  if (gamma) put(gamma, h->H.gamma_glob.data(), h->H.gamma_glob.size());
+  if (aux) put(aux, h->H.gamma_aux.data(), h->H.gamma_aux.size());
+  return LS_OK;
+}
+
+ls_status ls_get_sample_map(const ls_handle* h, int* kmap) {
+  if (check_handle(h) != LS_OK) return LS_E_INVALID;
+  if (!kmap) {
+    set_error("kmap must not be NULL");
+    return LS_E_INVALID;
+  }
+  std::copy(h->H.kmap.begin(), h->H.kmap.end(), kmap);
+  return LS_OK;
+}
+
+ls_status ls_host_tables(int n, double omega, const double* m_host, int pml_width, int layer_thickness,
+                         double pml_C, int freq_samples, double* alpha, double* beta, double* gamma, double* aux,
+                         int* kmap, double* green) {
+  try {
+    set_error("");
+    if (!m_host) {
+      set_error("m_host must not be NULL");
+      return LS_E_INVALID;
+    }
+    HostSetup Hs;
+    const std::string err = build_host_setup(m_host, n, omega, pml_width, layer_thickness, pml_C, freq_samples, Hs);
+    if (!err.empty()) {
+      set_error(err);
+      return LS_E_INVALID;
+    }
+    auto put = [](double* dst, const cd* src, size_t count) {
+      for (size_t i = 0; i < count; ++i) {
+        dst[2 * i] = src[i].real();
+        dst[2 * i + 1] = src[i].imag();
+      }
+    };
+    if (alpha) put(alpha, Hs.alpha, 9);
+    if (beta) put(beta, Hs.beta, 9);
+    if (gamma) put(gamma, Hs.gamma_glob.data(), Hs.gamma_glob.size());
+    if (aux) put(aux, Hs.gamma_aux.data(), Hs.gamma_aux.size());
+    if (kmap) std::copy(Hs.kmap.begin(), Hs.kmap.end(), kmap);
+    if (green) put(green, Hs.kq.data(), Hs.kq.size());
+    return LS_OK;
+  } catch (const std::exception& ex) {
+    set_error(ex.what());
+    return LS_E_NOMEM;
+  }
+}
+
+}  // extern "C"

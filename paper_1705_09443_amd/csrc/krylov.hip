@@ -1,0 +1,187 @@
+// Krylov-loop helpers for the float64 (flexible) GMRES: batched dot products
+// with fixed-order reductions (bitwise reproducible, no float atomics),
+// multi-term axpy updates, precision casts and the adjoint's pointwise
+// product.
+#include "kernels.hpp"
+
+namespace lsw {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+__device__ inline double2 wave_sum(double2 v) {
+  for (int off = 32; off > 0; off >>= 1) {
+    v.x += __shfl_xor(v.x, off);
+    v.y += __shfl_xor(v.y, off);
+  }
+  return v;
+}
+
+// partials[p][blk] = sum over the blk-th chunk of conj(x_p) y_p
+__global__ __launch_bounds__(kThreads) void k_dot_partials(const DotPair* __restrict__ pairs, size_t N,
+                                                           double2* __restrict__ partials) {
+  const int p = blockIdx.y, blk = blockIdx.x;
+  const DotPair pr = pairs[p];
+  const size_t chunk = (N + kDotBlocks - 1) / kDotBlocks;
+  const size_t beg = blk * chunk;
+  const size_t end = beg + chunk < N ? beg + chunk : N;
+  double2 acc = make_double2(0.0, 0.0);
+  for (size_t i = beg + threadIdx.x; i < end; i += kThreads) {
+    const double2 a = pr.x[i], c = pr.y[i];
+    acc.x += a.x * c.x + a.y * c.y;
+    acc.y += a.x * c.y - a.y * c.x;
+  }
+  acc = wave_sum(acc);
+  __shared__ double2 ws[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double2 s = ws[0];
+    for (int w = 1; w < kThreads / 64; ++w) {
+      s.x += ws[w].x;
+      s.y += ws[w].y;
+    }
+    partials[(size_t)p * kDotBlocks + blk] = s;
+  }
+}
+
+__global__ void k_dot_reduce(const double2* __restrict__ partials, int npairs, double2* __restrict__ out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= npairs) return;
+  double2 s = make_double2(0.0, 0.0);
+  for (int b = 0; b < kDotBlocks; ++b) {
+    s.x += partials[(size_t)p * kDotBlocks + b].x;
+    s.y += partials[(size_t)p * kDotBlocks + b].y;
+  }
+  out[p] = s;
+}
+
+template <typename TX>
+__global__ __launch_bounds__(kThreads) void k_axpys(const AxpyOut* __restrict__ outs,
+                                                    const AxpyTerm<TX>* __restrict__ terms,
+                                                    const double2* __restrict__ coefs, size_t N) {
+  const AxpyOut o = outs[blockIdx.y];
+  double sc = 1.0;
+  if (o.scale_coef >= 0) {
+    const double v = coefs[o.scale_coef].x;
+    sc = 1.0 / (o.sqrt_scale ? sqrt(v) : v);
+  }
+  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < N; i += (size_t)gridDim.x * kThreads) {
+    double2 acc = make_double2(0.0, 0.0);
+    for (int t = o.tbeg; t < o.tend; ++t) {
+      const AxpyTerm<TX> tm = terms[t];
+      double2 c = coefs[tm.coef];
+      if (tm.negate) {
+        c.x = -c.x;
+        c.y = -c.y;
+      }
+      const C<TX> xv = tm.x[i];
+      acc.x += c.x * (double)xv.x - c.y * (double)xv.y;
+      acc.y += c.x * (double)xv.y + c.y * (double)xv.x;
+    }
+    double2 y = o.zero_first ? make_double2(0.0, 0.0) : o.y[i];
+    y.x = (y.x + acc.x) * sc;
+    y.y = (y.y + acc.y) * sc;
+    o.y[i] = y;
+  }
+}
+
+template <typename TD, typename TS>
+__global__ void k_copy_cast(C<TD>* const* __restrict__ dst, const C<TS>* const* __restrict__ src, size_t N) {
+  const int p = blockIdx.y;
+  C<TD>* d = dst[p];
+  const C<TS>* s = src[p];
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x)
+    d[i] = ccast<TD, TS>(s[i]);
+}
+
+__global__ void k_adjoint_product(const double2* __restrict__ psi, const double2* __restrict__ nu, int nrhs,
+                                  size_t N, double omega2, double* __restrict__ grad) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int j = 0; j < nrhs; ++j) {
+      const double2 a = psi[(size_t)j * N + i], c = nu[(size_t)j * N + i];
+      s += a.x * c.x - a.y * c.y;
+    }
+    grad[i] = -omega2 * s;
+  }
+}
+
+__global__ void k_add_scaled(double2* __restrict__ x, const double2* __restrict__ y, double s, size_t N) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
+    x[i].x += s * y[i].x;
+    x[i].y += s * y[i].y;
+  }
+}
+
+__global__ void k_conj(double2* __restrict__ d, const double2* __restrict__ s, size_t N) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x)
+    d[i] = make_double2(s[i].x, -s[i].y);
+}
+
+unsigned grid_for(size_t N) {
+  size_t g = (N + kThreads - 1) / kThreads;
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  return (unsigned)g;
+}
+
+}  // namespace
+
+hipError_t launch_dots(const DotPair* pairs, int npairs, size_t N, double2* partials, double2* out,
+                       hipStream_t st) {
+  if (npairs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_dot_partials, dim3(kDotBlocks, npairs), dim3(kThreads), 0, st, pairs, N, partials);
+  hipLaunchKernelGGL(k_dot_reduce, dim3((npairs + 127) / 128), dim3(128), 0, st, partials, npairs, out);
+  return hipGetLastError();
+}
+
+template <typename TX>
+hipError_t launch_axpys(const AxpyOut* outs, int nout, const AxpyTerm<TX>* terms, const double2* coefs,
+                        size_t N, hipStream_t st) {
+  if (nout <= 0) return hipSuccess;
+  unsigned g = grid_for(N);
+  if (g > 512) g = 512;
+  hipLaunchKernelGGL(k_axpys<TX>, dim3(g, nout), dim3(kThreads), 0, st, outs, terms, coefs, N);
+  return hipGetLastError();
+}
+template hipError_t launch_axpys<double>(const AxpyOut*, int, const AxpyTerm<double>*, const double2*,
+                                         size_t, hipStream_t);
+template hipError_t launch_axpys<float>(const AxpyOut*, int, const AxpyTerm<float>*, const double2*,
+                                        size_t, hipStream_t);
+
+template <typename TD, typename TS>
+hipError_t launch_copy_cast(C<TD>* const* dst, const C<TS>* const* src, int npairs, size_t N, hipStream_t st) {
+  if (npairs <= 0) return hipSuccess;
+  unsigned g = grid_for(N);
+  if (g > 512) g = 512;
+  hipLaunchKernelGGL((k_copy_cast<TD, TS>), dim3(g, npairs), dim3(kThreads), 0, st, dst, src, N);
+  return hipGetLastError();
+}
+template hipError_t launch_copy_cast<double, double>(double2* const*, const double2* const*, int, size_t,
+                                                     hipStream_t);
+template hipError_t launch_copy_cast<float, double>(float2* const*, const double2* const*, int, size_t,
+                                                    hipStream_t);
+template hipError_t launch_copy_cast<double, float>(double2* const*, const float2* const*, int, size_t,
+                                                    hipStream_t);
+template hipError_t launch_copy_cast<float, float>(float2* const*, const float2* const*, int, size_t,
+                                                   hipStream_t);
+
+hipError_t launch_adjoint_product(const double2* psi, const double2* nu, int nrhs, size_t N, double omega2,
+                                  double* grad, hipStream_t st) {
+  hipLaunchKernelGGL(k_adjoint_product, dim3(grid_for(N)), dim3(kThreads), 0, st, psi, nu, nrhs, N, omega2, grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_conj(double2* dst, const double2* src, size_t N, hipStream_t st) {
+  hipLaunchKernelGGL(k_conj, dim3(grid_for(N)), dim3(kThreads), 0, st, dst, src, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_add_scaled(double2* x, const double2* y, double s, size_t N, hipStream_t st) {
+  hipLaunchKernelGGL(k_add_scaled, dim3(grid_for(N)), dim3(kThreads), 0, st, x, y, s, N);
+  return hipGetLastError();
+}
+
+}  // namespace lsw

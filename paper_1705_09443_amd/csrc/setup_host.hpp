@@ -1,0 +1,49 @@
+// Host-side float64 setup of the sparsify-and-sweep preconditioner
+// (Algorithm 1, steps 1-3): Green's-function table, type-1 stencils alpha and
+// beta (eqs. alpha, beta), PML stencils gamma (eq. gamma) for the global PML
+// and for the auxiliary PML at sampled local frequencies (Sec. 2.3), and the
+// slice plan along x1.
+#pragma once
+
+#include <complex>
+#include <string>
+#include <vector>
+
+namespace lsw {
+
+using cd = std::complex<double>;
+
+struct SlicePlan {
+  int lo;     // first grid line i1 of D_k
+  int hi;     // last grid line of D_k
+  int first;  // first line of the subproblem (lo - b for k > 0, lo for k = 0)
+  int t;      // lines in the subproblem, hi - first + 1
+  int naux;   // auxiliary lines, lo - first
+};
+
+struct HostSetup {
+  int n = 0, b = 0, w = 0, L = 0, P = 0, nslices = 0, ns = 0;
+  double omega = 0, h = 0, C = 0;
+  double freq_lo = 0, freq_delta = 0;
+  std::vector<cd> kq;          // k_delta for delta in [0, n+1]^2, [(n+2)][(n+2)]
+  cd alpha[9], beta[9];        // neighbourhood order (d1, d2), d1 slowest
+  double alpha_sv[9];          // singular values of K_{mu,mu^c}, descending
+  std::vector<cd> gamma_glob;  // [(2b+1)^2][9] by per-axis class (c1, c2)
+  std::vector<cd> gamma_aux;   // [b][2b+1][ns][9] by (depth q, class c2, sample k)
+  std::vector<int> kmap;       // [L][L] sample index of every extended point
+  std::vector<SlicePlan> slices;
+};
+
+// Own float64 Bessel functions (series, Miller recurrence with the Neumann
+// series for Y0, Hankel's asymptotic expansion for large arguments).
+void bessel_j0y0(double x, double* j0, double* y0);
+void bessel_j1y1_small(double x, double* j1, double* y1);
+
+// Per-axis stretch class of grid index i (0 interior, 1..b low, b+1..2b high).
+int axis_class(int i, int n, int b);
+
+// Build everything from m on the host. Returns "" on success, else a message.
+std::string build_host_setup(const double* m_host, int n, double omega, int b, int w, double C,
+                             int freq_samples, HostSetup& out);
+
+}  // namespace lsw

@@ -1,0 +1,453 @@
+// Sparsified system and moving-PML sweep on the GPU.
+//
+// Stencils (Sec. 2.2): rows of H at grid points of I^h = [0, n+1]^2 use
+// conj(alpha_o) + omega^2 conj(beta_o) m_{i+o} (eq. local_c_approx); rows in
+// the PML use conj(gamma_i,o) (eq. PML_stencil); u = 0 on the Dirichlet ring.
+//
+// Slices (Sec. 2.3): D_k is a range of lines i1; the subproblem of slice k
+// (eq. Hwv_approx) lives on t lines [first_k, hi_k] x L transverse points:
+// b auxiliary PML lines (k > 0, gamma rows at the sampled local frequency)
+// followed by the lines of D_k (rows of H, coupling to D_{k+1} dropped).
+// Ordered by the transverse index j, the subproblem is block tridiagonal with
+// t x t blocks
+//     B_j x_{j-1} + A_j x_j + C_j x_{j+1} = r_j,
+// each block itself tridiagonal (9-point stencil). Block elimination
+//     S_0 = A_0,  S_j = A_j - B_j G_{j-1},  G_j = S_j^{-1} C_j
+// is done in float64 with partial pivoting inside each S_j; the factors kept
+// per block are S_j^{-1} (dense), G_j (dense) and the three diagonals of B_j.
+// A solve is then
+//     y_j = S_j^{-1} (r_j - B_j y_{j-1}),   x_{L-1} = y_{L-1},  x_j = y_j - G_j x_{j+1}.
+//
+// Sweep (Algorithm 2): forward u_1 = T_1 f_1, u_k = T_k (f_k - H_[k,k-1] u_{k-1});
+// backward u_k -= T_k (H_[k,k+1] u_{k+1}). Only the first line of D_k couples
+// to the last line of D_{k-1} (and the last to the first of D_{k+1}), three
+// coefficients per transverse point, kept in Hm and Hp.
+#include "kernels.hpp"
+
+namespace lsw {
+
+namespace {
+
+__device__ inline int d_axis_class(int i, int n, int b) {
+  if (i < 0) return i + b + 1;
+  if (i > n + 1) return i - (n + 2) + b + 1;
+  return 0;
+}
+
+// Coefficient of H in the row of grid point (i1, i2) for neighbour (d1, d2).
+__device__ double2 h_coef(const StencilTables& S, int i1, int i2, int d1, int d2) {
+  const int o = (d1 + 1) * 3 + (d2 + 1);
+  const int n = S.n;
+  if (i1 >= 0 && i1 <= n + 1 && i2 >= 0 && i2 <= n + 1) {
+    const int j1 = i1 + d1, j2 = i2 + d2;
+    double mm = 0.0;
+    if (j1 >= 1 && j1 <= n && j2 >= 1 && j2 <= n) mm = S.m[(size_t)(j1 - 1) * n + (j2 - 1)];
+    const double2 al = S.alpha[o], be = S.beta[o];
+    return make_double2(al.x + S.omega2 * be.x * mm, -al.y - S.omega2 * be.y * mm);
+  }
+  const int NC = 2 * S.b + 1;
+  const int c1 = d_axis_class(i1, n, S.b), c2 = d_axis_class(i2, n, S.b);
+  const double2 g = S.gglob[((size_t)c1 * NC + c2) * 9 + o];
+  return make_double2(g.x, -g.y);
+}
+
+// Coefficient of an auxiliary-PML row at depth q, transverse grid index i2,
+// sample ks, neighbour (d1, d2).
+__device__ double2 aux_coef(const StencilTables& S, int q, int i2, int ks, int d1, int d2) {
+  const int o = (d1 + 1) * 3 + (d2 + 1);
+  const int NC = 2 * S.b + 1;
+  const int c2 = d_axis_class(i2, S.n, S.b);
+  const double2 g = S.gaux[(((size_t)q * NC + c2) * S.ns + ks) * 9 + o];
+  return make_double2(g.x, -g.y);
+}
+
+template <typename T>
+__device__ inline C<T> shfl_xor_c(C<T> v, int mask) {
+  return mk<T>(__shfl_xor(v.x, mask), __shfl_xor(v.y, mask));
+}
+
+// ---- Q and H applies ---------------------------------------------------
+template <typename T>
+__global__ void k_apply_Q(StencilTables S, const C<T>* __restrict__ r, int nrhs, C<T>* __restrict__ f) {
+  const int L = S.L, n = S.n, b = S.b;
+  const size_t plane = (size_t)L * L;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= plane * nrhs) return;
+  const int rhs = (int)(idx / plane);
+  const int e = (int)(idx % plane);
+  const int i1 = e / L - b, i2 = e % L - b;
+  C<T> acc = mk<T>(0, 0);
+  if (i1 >= 0 && i1 <= n + 1 && i2 >= 0 && i2 <= n + 1) {
+    const C<T>* rr = r + (size_t)rhs * n * n;
+    for (int o = 0; o < 9; ++o) {
+      const int j1 = i1 + o / 3 - 1, j2 = i2 + o % 3 - 1;
+      if (j1 < 1 || j1 > n || j2 < 1 || j2 > n) continue;
+      const double2 al = S.alpha[o];
+      acc = cfma<T>(acc, mk<T>((T)al.x, (T)-al.y), rr[(size_t)(j1 - 1) * n + (j2 - 1)]);
+    }
+  }
+  f[idx] = acc;
+}
+
+template <typename T>
+__global__ void k_apply_H(StencilTables S, const C<T>* __restrict__ u, int nrhs, C<T>* __restrict__ y) {
+  const int L = S.L, b = S.b;
+  const size_t plane = (size_t)L * L;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= plane * nrhs) return;
+  const int rhs = (int)(idx / plane);
+  const int e = (int)(idx % plane);
+  const int e1 = e / L, e2 = e % L;
+  const C<T>* ur = u + (size_t)rhs * plane;
+  C<T> acc = mk<T>(0, 0);
+  for (int o = 0; o < 9; ++o) {
+    const int d1 = o / 3 - 1, d2 = o % 3 - 1;
+    const int f1 = e1 + d1, f2 = e2 + d2;
+    if (f1 < 0 || f1 >= L || f2 < 0 || f2 >= L) continue;
+    const double2 c = h_coef(S, e1 - b, e2 - b, d1, d2);
+    acc = cfma<T>(acc, mk<T>((T)c.x, (T)c.y), ur[(size_t)f1 * L + f2]);
+  }
+  y[idx] = acc;
+}
+
+template <typename T>
+__global__ void k_extract(int n, int b, const C<T>* __restrict__ uext, int nrhs, C<T>* __restrict__ z) {
+  const size_t nn = (size_t)n * n;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nn * nrhs) return;
+  const int rhs = (int)(idx / nn);
+  const int a = (int)(idx % nn);
+  const int a1 = a / n, a2 = a % n;
+  const int L = n + 2 + 2 * b;
+  z[idx] = uext[(size_t)rhs * L * L + (size_t)(a1 + 1 + b) * L + (a2 + 1 + b)];
+}
+
+// ---- slice assembly and block elimination (one workgroup per slice) ------
+constexpr int kTMax = 32;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_factor(StencilTables S, SliceTables P, C<T>* __restrict__ FS,
+                                                C<T>* __restrict__ FG, C<T>* __restrict__ Hm,
+                                                C<T>* __restrict__ Hp, int* __restrict__ status) {
+  const int k = blockIdx.x;
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int lo = P.lo[k], hi = P.hi[k], first = P.first[k], t = P.t[k];
+  const int naux = lo - first;
+  const int L = S.L, b = S.b;
+  const int W = 2 * t;
+  const int tt = t * t, fstride = tt + 3 * t;
+  __shared__ double2 Gp[kTMax * kTMax];
+  __shared__ double2 M[kTMax * 2 * kTMax];
+  __shared__ double2 At[kTMax * 3], Bt[kTMax * 3], Ct[kTMax * 3];
+  __shared__ double2 fcol[kTMax];
+  __shared__ int piv_s;
+  __shared__ double2 ipiv_s;
+  C<T>* fs = FS + P.fs_off[k];
+  C<T>* fg = FG + P.fg_off[k];
+  for (int j = 0; j < L; ++j) {
+    // 1. the three tridiagonal blocks of block row j
+    for (int idx = tid; idx < t * 9; idx += nt) {
+      const int a = idx / 9, o = idx % 9, d1 = o / 3 - 1, d2 = o % 3 - 1;
+      const int line = first + a, i2 = j - b;
+      double2 c = make_double2(0.0, 0.0);
+      if (a + d1 >= 0 && a + d1 < t && j + d2 >= 0 && j + d2 < L) {
+        if (a < naux) {
+          const int q = lo - 1 - line;
+          const int ks = S.kmap[(size_t)(line + b) * L + j];
+          c = aux_coef(S, q, i2, ks, d1, d2);
+        } else {
+          c = h_coef(S, line, i2, d1, d2);
+        }
+      }
+      double2* dst = d2 < 0 ? Bt : (d2 == 0 ? At : Ct);
+      dst[a * 3 + d1 + 1] = c;
+    }
+    __syncthreads();
+    // 2. S_j = A_j - B_j G_{j-1}, augmented with the identity
+    for (int idx = tid; idx < t * W; idx += nt) {
+      const int a = idx / W, c = idx % W;
+      double2 v = make_double2(0.0, 0.0);
+      if (c < t) {
+        if (c - a >= -1 && c - a <= 1) v = At[a * 3 + (c - a) + 1];
+        if (j > 0) {
+          for (int d = -1; d <= 1; ++d) {
+            const int a2 = a + d;
+            if (a2 < 0 || a2 >= t) continue;
+            const double2 bb = Bt[a * 3 + d + 1], g = Gp[a2 * kTMax + c];
+            v.x -= bb.x * g.x - bb.y * g.y;
+            v.y -= bb.x * g.y + bb.y * g.x;
+          }
+        }
+      } else if (c - t == a) {
+        v.x = 1.0;
+      }
+      M[a * (2 * kTMax) + c] = v;
+    }
+    for (int idx = tid; idx < 3 * t; idx += nt) fs[(size_t)j * fstride + tt + idx] = ccast<T, double>(Bt[idx]);
+    __syncthreads();
+    // 3. Gauss-Jordan with partial pivoting: [S | I] -> [I | S^{-1}]
+    for (int p = 0; p < t; ++p) {
+      if (tid < 64) {
+        double best = -1.0;
+        int br = p;
+        for (int r = p + tid; r < t; r += 64) {
+          const double2 v = M[r * (2 * kTMax) + p];
+          const double a2 = v.x * v.x + v.y * v.y;
+          if (a2 > best) {
+            best = a2;
+            br = r;
+          }
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+          const double ob = __shfl_xor(best, off);
+          const int orr = __shfl_xor(br, off);
+          if (ob > best || (ob == best && orr < br)) {
+            best = ob;
+            br = orr;
+          }
+        }
+        if (tid < t) {
+          const int src = tid == p ? br : (tid == br ? p : tid);
+          fcol[tid] = M[src * (2 * kTMax) + p];
+        }
+        if (tid == 0) {
+          piv_s = br;
+          const double2 pv = M[br * (2 * kTMax) + p];
+          const double d = pv.x * pv.x + pv.y * pv.y;
+          if (!(d > 0.0) || !(d < INFINITY)) {
+            atomicMax(status, k + 1);
+            ipiv_s = make_double2(0.0, 0.0);
+          } else {
+            ipiv_s = make_double2(pv.x / d, -pv.y / d);
+          }
+        }
+      }
+      __syncthreads();
+      const int pr = piv_s;
+      const double2 ip = ipiv_s;
+      for (int c = tid; c < W; c += nt) {  // swap rows p, pr and scale the pivot row
+        const double2 vp = M[p * (2 * kTMax) + c], vr = M[pr * (2 * kTMax) + c];
+        M[p * (2 * kTMax) + c] = make_double2(vr.x * ip.x - vr.y * ip.y, vr.x * ip.y + vr.y * ip.x);
+        if (pr != p) M[pr * (2 * kTMax) + c] = vp;
+      }
+      __syncthreads();
+      for (int idx = tid; idx < t * W; idx += nt) {
+        const int r = idx / W, c = idx % W;
+        if (r == p) continue;
+        const double2 fr = fcol[r], pc = M[p * (2 * kTMax) + c];
+        double2 v = M[r * (2 * kTMax) + c];
+        v.x -= fr.x * pc.x - fr.y * pc.y;
+        v.y -= fr.x * pc.y + fr.y * pc.x;
+        M[r * (2 * kTMax) + c] = v;
+      }
+      __syncthreads();
+    }
+    // 4. store S_j^{-1}; G_j = S_j^{-1} C_j (C_j tridiagonal)
+    for (int idx = tid; idx < tt; idx += nt) {
+      const int a = idx / t, c = idx % t;
+      fs[(size_t)j * fstride + idx] = ccast<T, double>(M[a * (2 * kTMax) + t + c]);
+      double2 g = make_double2(0.0, 0.0);
+      for (int d = -1; d <= 1; ++d) {
+        const int c2 = c - d;  // row c2 of C_j has its entry at column c2 + d = c
+        if (c2 < 0 || c2 >= t) continue;
+        const double2 s = M[a * (2 * kTMax) + t + c2], cc = Ct[c2 * 3 + d + 1];
+        g.x += s.x * cc.x - s.y * cc.y;
+        g.y += s.x * cc.y + s.y * cc.x;
+      }
+      Gp[a * kTMax + c] = g;
+      fg[(size_t)j * tt + idx] = ccast<T, double>(g);
+    }
+    __syncthreads();
+  }
+  // couplings H_[k,k-1] (first line of D_k) and H_[k,k+1] (last line of D_k)
+  for (int idx = tid; idx < 3 * L; idx += nt) {
+    const int j = idx / 3, d2 = idx % 3 - 1;
+    const bool ok = j + d2 >= 0 && j + d2 < L;
+    double2 cm = make_double2(0.0, 0.0), cp = make_double2(0.0, 0.0);
+    if (ok && k > 0) cm = h_coef(S, lo, j - b, -1, d2);
+    if (ok && k < P.nslices - 1) cp = h_coef(S, hi, j - b, +1, d2);
+    Hm[(size_t)k * L * 3 + idx] = ccast<T, double>(cm);
+    Hp[(size_t)k * L * 3 + idx] = ccast<T, double>(cp);
+  }
+}
+
+// ---- slice solves and the sweep (one workgroup per right-hand side) -------
+enum SolveKind { kFwd = 0, kBwd = 1, kTest = 2 };
+
+template <typename T>
+__device__ void slice_solve(int kind, int k, const SliceTables& P, int L, int b,
+                            const C<T>* __restrict__ FS, const C<T>* __restrict__ FG,
+                            const C<T>* __restrict__ Hm, const C<T>* __restrict__ Hp,
+                            const C<T>* __restrict__ in, C<T>* __restrict__ out, C<T>* __restrict__ yg,
+                            C<T> (*ybuf)[kTMax], C<T>* zbuf) {
+  const int lo = P.lo[k], hi = P.hi[k], first = P.first[k], t = P.t[k];
+  const int naux = lo - first;
+  const int a = threadIdx.x >> 3, cb = threadIdx.x & 7;
+  const int tt = t * t, fstride = tt + 3 * t;
+  const C<T>* fs = FS + P.fs_off[k];
+  const C<T>* fg = FG + P.fg_off[k];
+  const bool own = (cb == 0) && (a < t);
+  // forward elimination
+  for (int j = 0; j < L; ++j) {
+    const int cur = j & 1;
+    if (own) {
+      C<T> z = mk<T>(0, 0);
+      if (kind == kFwd) {
+        if (a >= naux) {
+          z = in[(size_t)(first + a + b) * L + j];
+          if (a == naux && k > 0) {
+            const C<T>* hm = Hm + ((size_t)k * L + j) * 3;
+            const C<T>* prev = out + (size_t)(lo - 1 + b) * L;
+            for (int d = -1; d <= 1; ++d)
+              if (j + d >= 0 && j + d < L) z = csub<T>(z, cmul<T>(hm[d + 1], prev[j + d]));
+          }
+        }
+      } else if (kind == kBwd) {
+        if (a == t - 1) {
+          const C<T>* hp = Hp + ((size_t)k * L + j) * 3;
+          const C<T>* next = out + (size_t)(hi + 1 + b) * L;
+          for (int d = -1; d <= 1; ++d)
+            if (j + d >= 0 && j + d < L) z = cfma<T>(z, hp[d + 1], next[j + d]);
+        }
+      } else {
+        if (a >= naux) z = in[(size_t)(a - naux) * L + j];
+      }
+      if (j > 0) {
+        const C<T>* Bd = fs + (size_t)j * fstride + tt + a * 3;
+        for (int d = -1; d <= 1; ++d) {
+          const int a2 = a + d;
+          if (a2 >= 0 && a2 < t) z = csub<T>(z, cmul<T>(Bd[d + 1], ybuf[cur ^ 1][a2]));
+        }
+      }
+      zbuf[a] = z;
+    }
+    __syncthreads();
+    C<T> acc = mk<T>(0, 0);
+    if (a < t) {
+      const C<T>* Sj = fs + (size_t)j * fstride + a * t;
+      for (int c = cb; c < t; c += 8) acc = cfma<T>(acc, Sj[c], zbuf[c]);
+    }
+    acc = cadd<T>(acc, shfl_xor_c<T>(acc, 1));
+    acc = cadd<T>(acc, shfl_xor_c<T>(acc, 2));
+    acc = cadd<T>(acc, shfl_xor_c<T>(acc, 4));
+    if (own) {
+      ybuf[cur][a] = acc;
+      yg[(size_t)j * kTMax + a] = acc;
+    }
+    __syncthreads();
+  }
+  // back substitution
+  int cur = (L - 1) & 1;
+  auto emit = [&](int j, C<T> x) {
+    if (a < naux) return;
+    if (kind == kFwd) {
+      out[(size_t)(first + a + b) * L + j] = x;
+    } else if (kind == kBwd) {
+      C<T>* o = out + (size_t)(first + a + b) * L + j;
+      *o = csub<T>(*o, x);
+    } else {
+      out[(size_t)(a - naux) * L + j] = x;
+    }
+  };
+  if (own) emit(L - 1, ybuf[cur][a]);
+  for (int j = L - 2; j >= 0; --j) {
+    C<T> acc = mk<T>(0, 0);
+    if (a < t) {
+      const C<T>* Gj = fg + (size_t)j * tt + a * t;
+      for (int c = cb; c < t; c += 8) acc = cfma<T>(acc, Gj[c], ybuf[cur][c]);
+    }
+    acc = cadd<T>(acc, shfl_xor_c<T>(acc, 1));
+    acc = cadd<T>(acc, shfl_xor_c<T>(acc, 2));
+    acc = cadd<T>(acc, shfl_xor_c<T>(acc, 4));
+    if (own) {
+      const C<T> x = csub<T>(yg[(size_t)j * kTMax + a], acc);
+      ybuf[cur ^ 1][a] = x;
+      emit(j, x);
+    }
+    __syncthreads();
+    cur ^= 1;
+  }
+  __threadfence();
+  __syncthreads();
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_sweep(SliceTables P, int L, int b, const C<T>* __restrict__ FS,
+                                               const C<T>* __restrict__ FG, const C<T>* __restrict__ Hm,
+                                               const C<T>* __restrict__ Hp, const C<T>* __restrict__ f,
+                                               C<T>* __restrict__ u, C<T>* __restrict__ yscr, int mode,
+                                               int slice) {
+  __shared__ C<T> ybuf[2][kTMax];
+  __shared__ C<T> zbuf[kTMax];
+  const int rhs = blockIdx.x;
+  C<T>* yg = yscr + (size_t)rhs * L * kTMax;
+  if (mode == kSweepFull) {
+    const size_t plane = (size_t)L * L;
+    const C<T>* fr = f + rhs * plane;
+    C<T>* ur = u + rhs * plane;
+    for (int k = 0; k < P.nslices; ++k)
+      slice_solve<T>(kFwd, k, P, L, b, FS, FG, Hm, Hp, fr, ur, yg, ybuf, zbuf);
+    for (int k = P.nslices - 2; k >= 0; --k)
+      slice_solve<T>(kBwd, k, P, L, b, FS, FG, Hm, Hp, fr, ur, yg, ybuf, zbuf);
+  } else {
+    const int lines = P.hi[slice] - P.lo[slice] + 1;
+    const size_t sz = (size_t)lines * L;
+    slice_solve<T>(kTest, slice, P, L, b, FS, FG, Hm, Hp, f + rhs * sz, u + rhs * sz, yg, ybuf, zbuf);
+  }
+}
+
+inline unsigned blocks_for(size_t total, int nt) { return (unsigned)((total + nt - 1) / nt); }
+
+}  // namespace
+
+template <typename T>
+hipError_t launch_apply_Q(const StencilTables& S, const C<T>* r, int nrhs, C<T>* f, hipStream_t st) {
+  const size_t tot = (size_t)S.L * S.L * nrhs;
+  hipLaunchKernelGGL(k_apply_Q<T>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, S, r, nrhs, f);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_apply_H(const StencilTables& S, const C<T>* u, int nrhs, C<T>* y, hipStream_t st) {
+  const size_t tot = (size_t)S.L * S.L * nrhs;
+  hipLaunchKernelGGL(k_apply_H<T>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, S, u, nrhs, y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_extract(int n, int b, const C<T>* uext, int nrhs, C<T>* z, hipStream_t st) {
+  const size_t tot = (size_t)n * n * nrhs;
+  hipLaunchKernelGGL(k_extract<T>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, n, b, uext, nrhs, z);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_factor_slices(const StencilTables& S, const SliceTables& P, C<T>* FS, C<T>* FG,
+                                C<T>* Hm, C<T>* Hp, int* status, hipStream_t st) {
+  hipLaunchKernelGGL(k_factor<T>, dim3(P.nslices), dim3(256), 0, st, S, P, FS, FG, Hm, Hp, status);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_sweep(const SliceTables& P, int L, int b, const C<T>* FS, const C<T>* FG,
+                        const C<T>* Hm, const C<T>* Hp, const C<T>* f, C<T>* u, C<T>* yscratch,
+                        int nrhs, int mode, int slice, hipStream_t st) {
+  hipLaunchKernelGGL(k_sweep<T>, dim3(nrhs), dim3(256), 0, st, P, L, b, FS, FG, Hm, Hp, f, u, yscratch,
+                     mode, slice);
+  return hipGetLastError();
+}
+
+#define LSW_INST(T)                                                                                  \
+  template hipError_t launch_apply_Q<T>(const StencilTables&, const C<T>*, int, C<T>*, hipStream_t); \
+  template hipError_t launch_apply_H<T>(const StencilTables&, const C<T>*, int, C<T>*, hipStream_t); \
+  template hipError_t launch_extract<T>(int, int, const C<T>*, int, C<T>*, hipStream_t);             \
+  template hipError_t launch_factor_slices<T>(const StencilTables&, const SliceTables&, C<T>*,       \
+                                              C<T>*, C<T>*, C<T>*, int*, hipStream_t);               \
+  template hipError_t launch_sweep<T>(const SliceTables&, int, int, const C<T>*, const C<T>*,        \
+                                      const C<T>*, const C<T>*, const C<T>*, C<T>*, C<T>*, int, int, \
+                                      int, hipStream_t);
+LSW_INST(double)
+LSW_INST(float)
+#undef LSW_INST
+
+}  // namespace lsw

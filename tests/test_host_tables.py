@@ -1,0 +1,98 @@
+"""Parity of the library's float64 host setup (own Bessel functions, streamed
+QR + one-sided Jacobi SVD for alpha, Householder null vectors for gamma)
+against the oracle (scipy AMOS Hankel, numpy QR + LAPACK SVD): the stencil
+tables agree to 1e-12 after the phase normalisation (reading G5), the sample
+map is bit-exact (an integer decided in float64 by the same expression)."""
+import math
+
+import numpy as np
+import pytest
+
+import workloads
+import oracle
+from oracle.sparse import class_index
+from oracle.stencils import sigma_global, FrequencySamples
+from paper_1705_09443_amd import host_tables
+
+
+def _oracle_setup(wl, m, b, w, C=10.0):
+    return oracle.OracleSolver(2, wl.n, wl.omega, m, b, w, pml_C=C)
+
+
+@pytest.fixture(scope="module")
+def c0():
+    wl = workloads.workload("C0")
+    m = wl.medium_array()
+    ref = _oracle_setup(wl, m, 12, 4)
+    got = host_tables(m, wl.omega, 12, 4)
+    return wl, m, ref, got
+
+
+def test_green_quadrant(c0):
+    wl, m, ref, got = c0
+    n = wl.n
+    t = ref.op.table[n + 1:, n + 1:]
+    env = np.abs(t).max()
+    assert np.abs(got["green"] - t).max() <= 1e-14 * env
+    # away from the centre, relative to the local size of G h^2
+    h = 1.0 / (n + 1)
+    r = np.hypot(*np.meshgrid(np.arange(n + 2), np.arange(n + 2), indexing="ij")) * h
+    r[0, 0] = 1
+    scale = 0.25 * np.sqrt(2 / (math.pi * wl.omega * r)) * h * h
+    assert (np.abs(got["green"] - t) / scale)[1:, 1:].max() < 1e-13
+
+
+def test_alpha_beta(c0):
+    wl, m, ref, got = c0
+    assert np.abs(got["alpha"] - ref.alpha).max() <= 1e-12
+    assert np.abs(got["beta"] - ref.beta).max() <= 1e-12 * np.abs(ref.beta).max()
+
+
+def test_global_gamma(c0):
+    wl, m, ref, got = c0
+    b = 12
+    for key, g in ref.system.gamma_by_class.items():
+        assert np.abs(got["gamma"][key] - g).max() <= 1e-12, key
+
+
+def test_sample_map_bit_exact(c0):
+    wl, m, ref, got = c0
+    s = ref.system
+    km = ref.sweep.samples.index(s.m_ext).reshape(s.L, s.L)
+    np.testing.assert_array_equal(got["kmap"], km)
+
+
+def test_aux_gamma(c0):
+    wl, m, ref, got = c0
+    assert len(ref.sweep.aux_gamma) > 100
+    for (q, c2, ks), g in ref.sweep.aux_gamma.items():
+        assert np.abs(got["aux"][q, c2, ks] - g).max() <= 1e-12, (q, c2, ks)
+    # every table entry the library filled is one some auxiliary point uses
+    used = set(ref.sweep.aux_gamma)
+    filled = set(map(tuple, np.argwhere(np.abs(got["aux"]).sum(-1) > 0)))
+    assert filled == used
+
+
+@pytest.mark.parametrize("n,ppw", [(255, 16.0), (31, 2.0)])
+def test_alpha_other_sizes(n, ppw):
+    omega = 2 * math.pi * ppw
+    t = oracle.green_table(2, n, omega)
+    alpha, beta, sv = oracle.alpha_beta(t, n, 2)
+    m = np.zeros((n, n))
+    got = host_tables(m, omega, 8, 4)
+    assert np.abs(got["alpha"] - alpha).max() <= 1e-12
+    assert np.abs(got["beta"] - beta).max() <= 1e-12 * np.abs(beta).max()
+    # constant medium: one frequency sample, index 0 everywhere
+    assert got["aux"].shape[2] == 1 and got["kmap"].max() == 0
+
+
+def test_invalid_inputs_raise():
+    from paper_1705_09443_amd import LsError
+    with pytest.raises(LsError):
+        host_tables(np.full((7, 7), 1.0), 10.0, 4, 2)        # m >= 1
+    with pytest.raises(LsError):
+        host_tables(np.zeros((7, 7)), 1000.0, 4, 2)          # < 2 points per wavelength
+    bad = np.zeros((7, 7))
+    bad[3, 3] = np.nan
+    with pytest.raises(LsError):
+        host_tables(bad, 10.0, 4, 2)
