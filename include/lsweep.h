@@ -71,7 +71,12 @@ typedef struct {
   int freq_samples;  /* local-frequency samples for the auxiliary PML (0: n, Sec. 2.3) */
   int autotune;      /* reserved, 0 */
   void* hip_stream;  /* hipStream_t to enqueue on (NULL: default stream) */
+  int sweep_schedule;  /* LS_SWEEP_INTERFACE (default): all slice solves at once plus the
+                          interface recurrences; LS_SWEEP_SEQUENTIAL: Algorithm 2 slice by slice.
+                          Both compute the same preconditioner up to rounding. */
 } ls_options;
+
+typedef enum { LS_SWEEP_INTERFACE = 0, LS_SWEEP_SEQUENTIAL = 1 } ls_sweep_schedule;
 
 typedef struct {
   int iterations;       /* Arnoldi steps over all restart cycles */
@@ -184,6 +189,22 @@ ls_status ls_get_stencils(const ls_handle* h, double* alpha_host, double* beta_h
 
 /* Sample index k* for every extended-grid point, int32 [L][L] on the host. */
 ls_status ls_get_sample_map(const ls_handle* h, int* kmap_host);
+
+/* ---- Kernel timing (HIP events recorded on the handle's stream) ---- */
+
+typedef struct {
+  char name[32];     /* "sweep", "fft_convolve", "stencil_Q", "extract", "factor" */
+  int launches;      /* launches recorded since profiling was enabled */
+  double total_ms;   /* summed event-to-event durations */
+} ls_kernel_time;
+
+/* enable = 1: clear and start recording events around every kernel launch of
+ * the handle; enable = 0: stop recording (the records stay readable). */
+ls_status ls_profile(ls_handle* h, int enable);
+
+/* Per-kind totals of the recorded launches; waits for them to finish.
+ * out: host array of max entries; *count receives the number of kinds. */
+ls_status ls_profile_read(ls_handle* h, ls_kernel_time* out_host, int max, int* count);
 
 /*
  * Host-only (no device needed): the float64 setup tables of Algorithm 1,

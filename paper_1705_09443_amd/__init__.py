@@ -56,7 +56,7 @@ class LSSolver:
 
     def __init__(self, m: torch.Tensor, omega: float, pml_width: int = 12, layer_thickness: int = 4,
                  precision: str = "fp64", restart: int = 30, max_iters: int = 1000, pml_C: float = 10.0,
-                 freq_samples: int = 0):
+                 freq_samples: int = 0, schedule: str = "interface"):
         self._lib = _lib.load()
         if m.dim() != 2 or m.shape[0] != m.shape[1]:
             raise ValueError("m must be [n, n]")
@@ -71,6 +71,7 @@ class LSSolver:
         opts.max_iters = max_iters
         opts.pml_C = pml_C
         opts.freq_samples = freq_samples
+        opts.sweep_schedule = {"interface": 0, "sequential": 1}[schedule]
         opts.hip_stream = _stream_ptr()
         self._opts = opts
         grid = LsGrid(2, self.n)
@@ -171,6 +172,18 @@ class LSSolver:
         w = torch.empty_like(v)
         _lib.check(self._lib.ls_slice_solve(self._h, k, v.data_ptr(), nb, w.data_ptr(), code), "ls_slice_solve")
         return w
+
+    # -- kernel timing ------------------------------------------------------
+    def profile(self, enable: bool = True):
+        """Start (clear) or stop recording HIP events around the library's launches."""
+        _lib.check(self._lib.ls_profile(self._h, 1 if enable else 0), "ls_profile")
+
+    def profile_read(self):
+        """{kind: (launches, total_ms)} of the recorded launches."""
+        out = (_lib.LsKernelTime * 16)()
+        cnt = _lib.c_int()
+        _lib.check(self._lib.ls_profile_read(self._h, out, 16, ctypes_byref(cnt)), "ls_profile_read")
+        return {out[i].name.decode(): (out[i].launches, out[i].total_ms) for i in range(cnt.value)}
 
     # -- setup tables -------------------------------------------------------
     def stencils(self):

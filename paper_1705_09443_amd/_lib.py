@@ -19,6 +19,7 @@ STATUS_NAMES = ["LS_OK", "LS_E_INVALID", "LS_E_NOMEM", "LS_E_DEVICE", "LS_E_SING
                 "LS_E_NUMERIC", "LS_E_STATE"]
 LS_FP64, LS_MIXED = 0, 1
 LS_RHS_SOURCE, LS_RHS_INCIDENT = 0, 1
+LS_SWEEP_INTERFACE, LS_SWEEP_SEQUENTIAL = 0, 1
 
 c_int, c_double, c_void_p = ctypes.c_int, ctypes.c_double, ctypes.c_void_p
 P_int = ctypes.POINTER(ctypes.c_int)
@@ -31,7 +32,8 @@ class LsGrid(ctypes.Structure):
 
 class LsOptions(ctypes.Structure):
     _fields_ = [("precision", c_int), ("restart", c_int), ("max_iters", c_int), ("pml_C", c_double),
-                ("freq_samples", c_int), ("autotune", c_int), ("hip_stream", c_void_p)]
+                ("freq_samples", c_int), ("autotune", c_int), ("hip_stream", c_void_p),
+                ("sweep_schedule", c_int)]
 
 
 class LsRhsInfo(ctypes.Structure):
@@ -43,6 +45,10 @@ class LsSetupInfo(ctypes.Structure):
                 ("L", c_int), ("nslices", c_int), ("freq_samples", c_int), ("precision", c_int),
                 ("omega", c_double), ("h", c_double), ("pml_C", c_double), ("freq_lo", c_double),
                 ("freq_delta", c_double)]
+
+
+class LsKernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int), ("total_ms", c_double)]
 
 
 class LsError(RuntimeError):
@@ -70,6 +76,8 @@ _SIGNATURES = {
     "ls_get_slice": (c_int, [c_void_p, c_int, P_int, P_int, P_int]),
     "ls_get_stencils": (c_int, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "ls_get_sample_map": (c_int, [c_void_p, c_void_p]),
+    "ls_profile": (c_int, [c_void_p, c_int]),
+    "ls_profile_read": (c_int, [c_void_p, ctypes.POINTER(LsKernelTime), c_int, P_int]),
     "ls_host_tables": (c_int, [c_int, c_double, c_void_p, c_int, c_int, c_double, c_int, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p, c_void_p]),
 }

@@ -2,8 +2,10 @@
 // flexible GMRES loop in float64 around the applies (Sec. 2.5), the adjoint
 // gradient, and the per-operator entry points.
 #include <algorithm>
+#include <cstdio>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
 #include <string>
 #include <type_traits>
@@ -75,14 +77,44 @@ struct ls_handle {
   // tables
   DBuf m, m32, khat, khat32, tw, tw32, alpha, beta, gglob, gaux, kmap;
   DBuf s_lo, s_hi, s_first, s_t, fs_off, fg_off, FS, FG, Hm, Hp, status;
+  // interface maps M_k, P_k, N_k ([nslices][L][L]) and runs of slices with equal t class
+  DBuf IM, IP, IN;
+  struct Run {
+    int k0, count, tmax, fstride;  // slices [k0, k0+count): line-count class and factor stride
+  };
+  std::vector<Run> runs;
   // workspaces
   int cap = 0;  // right-hand sides the workspaces hold
-  DBuf fftw64, fftw32, fext, uext, yscr, vin, zout, aout;
+  DBuf fftw64, fftw32, fext, uext, yscr, vin, zout, aout, lam, mu, sscr;
   DBuf V, Z, W, X, G, R, T1, T2;
   DBuf pairs, partials, coefs, outs, terms64, terms32, ptrs_a, ptrs_b;
   // adjoint state
   int last_nrhs = 0;
   DBuf psi;
+  // captured interface recurrences, one graph per (batch size, precision)
+  hipStream_t cst = nullptr;
+  std::map<std::pair<int, int>, hipGraphExec_t> graphs;
+  void drop_graphs() {
+    for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
+    graphs.clear();
+  }
+  // kernel timing
+  bool profiling = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  ~ls_handle() {
+    drop_graphs();
+    if (cst) (void)hipStreamDestroy(cst);
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    for (auto e : pool) (void)hipEventDestroy(e);
+  }
 
   StencilTables stencils() const {
     StencilTables s;
@@ -114,6 +146,41 @@ struct ls_handle {
 
 namespace {
 
+enum KernelKind { kKSweep = 0, kKFft, kKQ, kKExtract, kKFactor, kKSlices, kKIface, kKNumKinds };
+const char* kKindNames[kKNumKinds] = {"sweep", "fft_convolve", "stencil_Q", "extract", "factor",
+                                      "slice_solves", "interface"};
+
+hipEvent_t take_event(ls_handle* h) {
+  if (!h->pool.empty()) {
+    hipEvent_t e = h->pool.back();
+    h->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  (void)hipEventCreate(&e);
+  return e;
+}
+
+// Brackets one launch with events on the handle's stream when profiling.
+struct Timed {
+  ls_handle* h;
+  int kind;
+  hipEvent_t a = nullptr;
+  Timed(ls_handle* hh, int k) : h(hh), kind(k) {
+    if (h->profiling) {
+      a = take_event(h);
+      (void)hipEventRecord(a, h->st);
+    }
+  }
+  ~Timed() {
+    if (a) {
+      hipEvent_t b = take_event(h);
+      (void)hipEventRecord(b, h->st);
+      h->recs.push_back({kind, a, b});
+    }
+  }
+};
+
 template <typename T>
 struct Prec;
 template <>
@@ -139,9 +206,13 @@ ls_status check_handle(const ls_handle* h) {
   return LS_OK;
 }
 
+// Right-hand sides per workgroup of the slice solves.
+int rhs_group(int nrhs) { return nrhs == 1 ? 1 : (nrhs <= 4 ? 4 : 8); }
+
 // Workspaces sized for nrhs right-hand sides.
 ls_status ensure_workspace(ls_handle* h, int nrhs) {
   if (nrhs <= h->cap) return LS_OK;
+  h->drop_graphs();  // captured launches refer to the old buffers
   const size_t N = h->N, E = h->E;
   const int rs = h->opt.restart;
   const size_t cs = h->prec == LS_FP64 ? sizeof(double2) : sizeof(float2);
@@ -150,6 +221,10 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   LSW_ALLOC(h->fext, (size_t)nrhs * E * cs);
   LSW_ALLOC(h->uext, (size_t)nrhs * E * cs);
   LSW_ALLOC(h->yscr, (size_t)nrhs * h->L * 32 * cs);
+  LSW_ALLOC(h->lam, (size_t)h->nslices * nrhs * h->L * cs);
+  LSW_ALLOC(h->mu, (size_t)h->nslices * nrhs * h->L * cs);
+  // slice-solve scratch: groups of up to 8 waves, one per right-hand side
+  LSW_ALLOC(h->sscr, (size_t)h->nslices * std::max(4, nrhs + 7) * slice_scratch_elems<double>(h->L, 1) * cs);
   LSW_ALLOC(h->vin, (size_t)nrhs * N * cs);
   LSW_ALLOC(h->zout, (size_t)nrhs * N * cs);
   LSW_ALLOC(h->aout, (size_t)nrhs * N * cs);
@@ -192,19 +267,174 @@ ls_status upload(const ls_handle* h, DBuf& dst, const std::vector<X>& src) {
 // ---- the applies, on contiguous batches ------------------------------------
 template <typename T>
 ls_status apply_A(ls_handle* h, const C<T>* x, int nb, C<T>* y) {
+  Timed tm(h, kKFft);
   LSW_HIP_TRY(launch_convolve<T>(x, Prec<T>::m(h), h->n, nb, Prec<T>::khat(h), Prec<T>::tw(h), (T)1,
                                  (T)(h->omega * h->omega), Prec<T>::fftw(h), y, h->st));
   return LS_OK;
 }
 
 template <typename T>
+SliceSolveArgs<T> slice_args(ls_handle* h) {
+  SliceSolveArgs<T> a{};
+  a.P = h->slices();
+  a.L = h->L;
+  a.b = h->b;
+  a.FS = h->FS.as<C<T>>();
+  a.FG = h->FG.as<C<T>>();
+  a.Hm = h->Hm.as<C<T>>();
+  a.Hp = h->Hp.as<C<T>>();
+  return a;
+}
+
+// All slices of [k0, k1) solved at once, run by run (one launch per run of
+// slices with equal line-count class and factor stride), Wmax right-hand
+// sides (waves) per workgroup at most, fewer if the LDS would not fit.
+template <typename T>
+ls_status solve_slices(ls_handle* h, SliceSolveArgs<T> a, int k0, int k1, int Wmax) {
+  for (const auto& run : h->runs) {
+    const int b0 = std::max(k0, run.k0), b1 = std::min(k1, run.k0 + run.count);
+    if (b0 >= b1) continue;
+    a.slice0 = b0;
+    a.stage = slice_stage_elems<T>(run.tmax, run.fstride);
+    int W = Wmax;
+    while (W > 1 && slice_lds<T>(run.tmax, a.stage, W) > 163840) W = W == 8 ? 4 : 1;
+    if (slice_lds<T>(run.tmax, a.stage, W) > 163840) {
+      set_error("slice subproblem too large for the LDS of one workgroup");
+      return LS_E_INVALID;
+    }
+    LSW_HIP_TRY(launch_slice_solves<T>(a, b1 - b0, run.tmax, W, (a.nrhs + W - 1) / W, h->st));
+  }
+  return LS_OK;
+}
+
+// z = P r (Algorithm 2), interface schedule or slice by slice.
+template <typename T>
 ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
   const StencilTables S = h->stencils();
-  LSW_HIP_TRY(launch_apply_Q<T>(S, r, nb, h->fext.as<C<T>>(), h->st));
-  LSW_HIP_TRY(launch_sweep<T>(h->slices(), h->L, h->b, h->FS.as<C<T>>(), h->FG.as<C<T>>(), h->Hm.as<C<T>>(),
-                              h->Hp.as<C<T>>(), h->fext.as<C<T>>(), h->uext.as<C<T>>(), h->yscr.as<C<T>>(), nb,
-                              kSweepFull, 0, h->st));
-  LSW_HIP_TRY(launch_extract<T>(h->n, h->b, h->uext.as<C<T>>(), nb, z, h->st));
+  C<T>* f = h->fext.as<C<T>>();
+  C<T>* u = h->uext.as<C<T>>();
+  {
+    Timed tm(h, kKQ);
+    LSW_HIP_TRY(launch_apply_Q<T>(S, r, nb, f, h->st));
+  }
+  if (h->opt.sweep_schedule == LS_SWEEP_SEQUENTIAL) {
+    Timed tm(h, kKSweep);
+    LSW_HIP_TRY(launch_sweep<T>(h->slices(), h->L, h->b, h->FS.as<C<T>>(), h->FG.as<C<T>>(), h->Hm.as<C<T>>(),
+                                h->Hp.as<C<T>>(), f, u, h->yscr.as<C<T>>(), nb, kSweepFull, 0, h->st));
+  } else {
+    const int nl = h->nslices, L = h->L, R = rhs_group(nb);
+    C<T>* lam = h->lam.as<C<T>>();
+    C<T>* mu = h->mu.as<C<T>>();
+    const size_t LL = (size_t)L * L, vs = (size_t)nb * L;
+    SliceSolveArgs<T> a = slice_args<T>(h);
+    a.nrhs = nb;
+    a.yscr = h->sscr.as<C<T>>();
+    if (nl > 1) {
+      // phase A: boundary lines of T_k f_k for every slice
+      Timed tm(h, kKSlices);
+      a.src_kind = kSrcGrid;
+      a.src = f;
+      a.dst_kind = kDstLines;
+      a.dstE = lam;
+      a.dstF = mu;
+      a.sk = vs;
+      a.sr = L;
+      a.sj = 1;
+      ls_status e = solve_slices<T>(h, a, 0, nl, R);
+      if (e != LS_OK) return e;
+    }
+    if (nl > 1) {
+      // interface recurrences: 2(l-2)+2 dependent launches, captured once per batch size
+      Timed tm(h, kKIface);
+      const std::pair<int, int> key(nb, (int)sizeof(T));
+      auto it = h->graphs.find(key);
+      if (it == h->graphs.end()) {
+        if (!h->cst) LSW_HIP_TRY(hipStreamCreateWithFlags(&h->cst, hipStreamNonBlocking));
+        const C<T>* IM = h->IM.as<C<T>>();
+        const C<T>* IP = h->IP.as<C<T>>();
+        const C<T>* IN = h->IN.as<C<T>>();
+        hipGraph_t graph = nullptr;
+        LSW_HIP_TRY(hipStreamBeginCapture(h->cst, hipStreamCaptureModeThreadLocal));
+        hipError_t ce = hipSuccess;
+        for (int k = 1; k <= nl - 2 && ce == hipSuccess; ++k)
+          ce = launch_iface_step<T>(IM, lam, lam, lam, L, nb, k, 1, LL, vs, -1, h->cst);
+        if (ce == hipSuccess) ce = launch_iface_step<T>(IP, mu, lam, mu, L, nb, 1, nl - 1, LL, vs, -1, h->cst);
+        for (int k = nl - 2; k >= 1 && ce == hipSuccess; --k)
+          ce = launch_iface_step<T>(IN, mu, mu, mu, L, nb, k, 1, LL, vs, +1, h->cst);
+        if (ce == hipSuccess)
+          ce = launch_couple<T>(h->slices(), L, h->b, h->Hm.as<C<T>>(), h->Hp.as<C<T>>(), lam, mu, nb, f, h->cst);
+        const hipError_t ee = hipStreamEndCapture(h->cst, &graph);
+        LSW_HIP_TRY(ce);
+        LSW_HIP_TRY(ee);
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        LSW_HIP_TRY(ie);
+        it = h->graphs.emplace(key, exec).first;
+      }
+      LSW_HIP_TRY(hipGraphLaunch(it->second, h->st));
+    }
+    {
+      // phase C: every slice's field from its coupled right-hand side
+      Timed tm(h, kKSlices);
+      a.src_kind = kSrcGrid;
+      a.src = f;
+      a.dst_kind = kDstGrid;
+      a.dst = u;
+      a.dstE = a.dstF = nullptr;
+      ls_status e = solve_slices<T>(h, a, 0, nl, R);
+      if (e != LS_OK) return e;
+    }
+  }
+  {
+    Timed tm(h, kKExtract);
+    LSW_HIP_TRY(launch_extract<T>(h->n, h->b, u, nb, z, h->st));
+  }
+  return LS_OK;
+}
+
+// Interface maps M_k = E T_k J_F Hm_k, P_k = F T_k J_F Hm_k (k >= 1) and
+// N_k = F T_k J_E Hp_k (1 <= k <= l-2): slice solves whose right-hand sides
+// are the L columns of J_F Hm_k or J_E Hp_k, 32 columns per workgroup.
+template <typename T>
+ls_status build_interface(ls_handle* h) {
+  const int nl = h->nslices, L = h->L;
+  if (nl < 2) return LS_OK;
+  const size_t cs = sizeof(C<T>);
+  const size_t LL = (size_t)L * L;
+  LSW_ALLOC(h->IM, (size_t)nl * LL * cs);
+  LSW_ALLOC(h->IP, (size_t)nl * LL * cs);
+  LSW_ALLOC(h->IN, (size_t)nl * LL * cs);
+  constexpr int W = 8;  // columns per workgroup (one wave each)
+  // columns per launch: as many groups as a ~2 GB scratch allows
+  const size_t per_group = (size_t)nl * slice_scratch_elems<double>(L, W) * cs;
+  const int groups = (int)std::max<size_t>(1, std::min<size_t>((L + W - 1) / W, (size_t)2e9 / per_group));
+  const int cols = groups * W;
+  DBuf scr;
+  LSW_ALLOC(scr, per_group * groups);
+  SliceSolveArgs<T> a = slice_args<T>(h);
+  a.yscr = scr.as<C<T>>();
+  a.dst_kind = kDstLines;
+  a.sk = LL;
+  a.sr = 1;
+  a.sj = L;
+  for (int col0 = 0; col0 < L; col0 += cols) {
+    a.col0 = col0;
+    a.nrhs = std::min(cols, L - col0);
+    a.src_kind = kSrcUnitF;
+    a.dstE = h->IM.as<C<T>>();
+    a.dstF = h->IP.as<C<T>>();
+    ls_status e = solve_slices<T>(h, a, 1, nl, W);
+    if (e != LS_OK) return e;
+    if (nl > 2) {
+      a.src_kind = kSrcUnitE;
+      a.dstE = nullptr;
+      a.dstF = h->IN.as<C<T>>();
+      e = solve_slices<T>(h, a, 1, nl - 1, W);
+      if (e != LS_OK) return e;
+    }
+  }
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
   return LS_OK;
 }
 
@@ -635,8 +865,18 @@ ls_status device_setup(ls_handle* h, const double* m_dev) {
     t[k] = p.t;
     fso[k] = fs_tot;
     fgo[k] = fg_tot;
-    fs_tot += (size_t)L * (p.t * p.t + 3 * p.t);
-    fg_tot += (size_t)L * p.t * p.t;
+    fs_tot += (size_t)L * factor_stride(p.t, p.hi - p.lo + 1);
+    fg_tot += (size_t)L * factor_stride(p.t, 0);
+  }
+  h->runs.clear();
+  for (int k = 0; k < nl; ++k) {
+    const int cls = t[k] > 16 ? 32 : 16;
+    const int fstride = factor_stride(t[k], hi[k] - lo[k] + 1);
+    auto& R = h->runs;
+    if (!R.empty() && R.back().tmax == cls && R.back().fstride == fstride && R.back().k0 + R.back().count == k)
+      R.back().count += 1;
+    else
+      R.push_back({k, 1, cls, fstride});
   }
   LSW_ALLOC(h->s_lo, nl * sizeof(int));
   LSW_ALLOC(h->s_hi, nl * sizeof(int));
@@ -648,8 +888,9 @@ ls_status device_setup(ls_handle* h, const double* m_dev) {
       upload(h, h->s_t, t) != LS_OK || upload(h, h->fs_off, fso) != LS_OK || upload(h, h->fg_off, fgo) != LS_OK)
     return LS_E_DEVICE;
   const size_t cs = h->prec == LS_FP64 ? sizeof(double2) : sizeof(float2);
-  LSW_ALLOC(h->FS, fs_tot * cs);
-  LSW_ALLOC(h->FG, fg_tot * cs);
+  // padding: the last 16-byte copy of a chunk may read one value past the end
+  LSW_ALLOC(h->FS, (fs_tot + 128) * cs);
+  LSW_ALLOC(h->FG, (fg_tot + 128) * cs);
   LSW_ALLOC(h->Hm, (size_t)nl * L * 3 * cs);
   LSW_ALLOC(h->Hp, (size_t)nl * L * 3 * cs);
   LSW_ALLOC(h->status, sizeof(int));
@@ -668,6 +909,10 @@ ls_status device_setup(ls_handle* h, const double* m_dev) {
   if (status != 0) {
     set_error("zero pivot in the factorization of slice " + std::to_string(status - 1));
     return LS_E_SINGULAR;
+  }
+  if (h->opt.sweep_schedule == LS_SWEEP_INTERFACE) {
+    ls_status e = h->prec == LS_FP64 ? build_interface<double>(h) : build_interface<float>(h);
+    if (e != LS_OK) return e;
   }
   return LS_OK;
 }
@@ -697,6 +942,7 @@ void ls_default_options(ls_options* o) {
   o->freq_samples = 0;
   o->autotune = 0;
   o->hip_stream = nullptr;
+  o->sweep_schedule = LS_SWEEP_INTERFACE;
 }
 
 const char* ls_last_error(void) { return lsw::get_error(); }
@@ -723,6 +969,10 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
     if (opts) o = *opts;
     if (o.precision != LS_FP64 && o.precision != LS_MIXED) {
       set_error("precision must be LS_FP64 or LS_MIXED");
+      return LS_E_INVALID;
+    }
+    if (o.sweep_schedule != LS_SWEEP_INTERFACE && o.sweep_schedule != LS_SWEEP_SEQUENTIAL) {
+      set_error("sweep_schedule must be LS_SWEEP_INTERFACE or LS_SWEEP_SEQUENTIAL");
       return LS_E_INVALID;
     }
     if (o.restart < 1 || o.restart > 200 || o.max_iters < 1) {
@@ -940,14 +1190,19 @@ ls_status ls_slice_solve(ls_handle* h, int slice, const void* v, int nrhs, void*
   }
   ls_status e = ensure_workspace(h, nrhs);
   if (e != LS_OK) return e;
-  if (precision == LS_FP64)
-    LSW_HIP_TRY(launch_sweep<double>(h->slices(), h->L, h->b, h->FS.as<double2>(), h->FG.as<double2>(),
-                                     h->Hm.as<double2>(), h->Hp.as<double2>(), static_cast<const double2*>(v),
-                                     static_cast<double2*>(w), h->yscr.as<double2>(), nrhs, kSliceOnly, slice, h->st));
-  else
-    LSW_HIP_TRY(launch_sweep<float>(h->slices(), h->L, h->b, h->FS.as<float2>(), h->FG.as<float2>(),
-                                    h->Hm.as<float2>(), h->Hp.as<float2>(), static_cast<const float2*>(v),
-                                    static_cast<float2*>(w), h->yscr.as<float2>(), nrhs, kSliceOnly, slice, h->st));
+  auto run = [&](auto tag) -> ls_status {
+    using T = decltype(tag);
+    SliceSolveArgs<T> a = slice_args<T>(h);
+    a.nrhs = nrhs;
+    a.yscr = h->sscr.as<C<T>>();
+    a.src_kind = kSrcSlice;
+    a.src = static_cast<const C<T>*>(v);
+    a.dst_kind = kDstSlice;
+    a.dst = static_cast<C<T>*>(w);
+    return solve_slices<T>(h, a, slice, slice + 1, rhs_group(nrhs));
+  };
+  e = precision == LS_FP64 ? run(double{}) : run(float{});
+  if (e != LS_OK) return e;
   LSW_HIP_TRY(hipStreamSynchronize(h->st));
   return LS_OK;
 }
@@ -1009,6 +1264,47 @@ ls_status ls_get_sample_map(const ls_handle* h, int* kmap) {
     return LS_E_INVALID;
   }
   std::copy(h->H.kmap.begin(), h->H.kmap.end(), kmap);
+  return LS_OK;
+}
+
+ls_status ls_profile(ls_handle* h, int enable) {
+  if (check_handle(h) != LS_OK) return LS_E_INVALID;
+  if (enable) {
+    LSW_HIP_TRY(hipStreamSynchronize(h->st));
+    for (auto& r : h->recs) {
+      h->pool.push_back(r.a);
+      h->pool.push_back(r.b);
+    }
+    h->recs.clear();
+  }
+  h->profiling = enable != 0;
+  return LS_OK;
+}
+
+ls_status ls_profile_read(ls_handle* h, ls_kernel_time* out, int max, int* count) {
+  if (check_handle(h) != LS_OK) return LS_E_INVALID;
+  if (!out || !count) {
+    set_error("out and count must not be NULL");
+    return LS_E_INVALID;
+  }
+  int launches[kKNumKinds] = {};
+  double ms[kKNumKinds] = {};
+  for (auto& r : h->recs) {
+    LSW_HIP_TRY(hipEventSynchronize(r.b));
+    float t = 0.f;
+    LSW_HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
+    launches[r.kind] += 1;
+    ms[r.kind] += t;
+  }
+  int c = 0;
+  for (int k = 0; k < kKNumKinds && c < max; ++k) {
+    if (!launches[k]) continue;
+    std::snprintf(out[c].name, sizeof out[c].name, "%s", kKindNames[k]);
+    out[c].launches = launches[k];
+    out[c].total_ms = ms[k];
+    ++c;
+  }
+  *count = c;
   return LS_OK;
 }
 

@@ -60,6 +60,14 @@ __host__ __device__ inline T cabs2(C<T> a) { return a.x * a.x + a.y * a.y; }
 template <typename TO, typename TI>
 __host__ __device__ inline C<TO> ccast(C<TI> a) { return mk<TO>((TO)a.x, (TO)a.y); }
 
+// Workgroup barrier that orders LDS accesses only: outstanding global loads
+// and stores stay in flight across it (a plain __syncthreads waits for them).
+__device__ inline void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // thread-local message of the last failure of the C ABI
 void set_error(const std::string& msg);
 const char* get_error();

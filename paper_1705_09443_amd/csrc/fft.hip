@@ -21,68 +21,81 @@ namespace lsw {
 
 namespace {
 
-constexpr int kMaxButterflies = 8;
+// In-place Stockham FFT (radix 4, a final radix 2 when log2 P is odd) of nseq
+// interleaved sequences: element k of sequence s lives at buf[k * nseq + s].
+// tw[k] = exp(-2 pi i k / P); the inverse uses the conjugate (unnormalised).
+// complex values a thread holds per pass (16: no register spills at 512 threads)
+template <typename T>
+constexpr int kVals = 16;
+constexpr int kFftMaxThreads = 512;
+
+template <typename T, int R>
+__device__ inline void lds_fft_pass(C<T>* buf, int P, int nseq, int Ns, const C<T>* __restrict__ tw, bool inv) {
+  constexpr int NB = kVals<T> / R;  // butterflies per thread
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nbf = P / R;
+  const int total = nbf * nseq;
+  C<T> v[NB][R];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int bidx = tid + q * nt;
+    if (bidx < total) {
+      const int s = bidx % nseq, j = bidx / nseq;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * nbf) * nseq + s];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int bidx = tid + q * nt;
+    if (bidx >= total) continue;
+    const int s = bidx % nseq, j = bidx / nseq;
+    const int k = j % Ns;
+    const int step = k * (P / (Ns * R));
+    C<T>* x = v[q];
+#pragma unroll
+    for (int r = 1; r < R; ++r) {
+      C<T> w = tw[r * step];
+      if (inv) w.y = -w.y;
+      x[r] = cmul<T>(x[r], w);
+    }
+    if (R == 4) {
+      const C<T> a0 = cadd<T>(x[0], x[2]), a1 = csub<T>(x[0], x[2]);
+      const C<T> a2 = cadd<T>(x[1], x[3]);
+      const C<T> d = csub<T>(x[1], x[3]);
+      // times -i (forward) or +i (inverse)
+      const C<T> a3 = inv ? mk<T>(-d.y, d.x) : mk<T>(d.y, -d.x);
+      x[0] = cadd<T>(a0, a2);
+      x[2] = csub<T>(a0, a2);
+      x[1] = cadd<T>(a1, a3);
+      x[3] = csub<T>(a1, a3);
+    } else {
+      const C<T> a0 = cadd<T>(x[0], x[1]), a1 = csub<T>(x[0], x[1]);
+      x[0] = a0;
+      x[1] = a1;
+    }
+    const int idxD = (j / Ns) * Ns * R + k;
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[(idxD + r * Ns) * nseq + s] = x[r];
+  }
+  __syncthreads();
+}
 
 // In-place Stockham FFT (radix 4, a final radix 2 when log2 P is odd) of nseq
 // interleaved sequences: element k of sequence s lives at buf[k * nseq + s].
 // tw[k] = exp(-2 pi i k / P); the inverse uses the conjugate (unnormalised).
+// Needs blockDim.x >= nseq * P / kVals<T>.
 template <typename T>
 __device__ void lds_fft(C<T>* buf, int P, int nseq, const C<T>* __restrict__ tw, bool inv) {
-  const int tid = threadIdx.x, nt = blockDim.x;
-  for (int Ns = 1; Ns < P;) {
-    const int R = (P / Ns >= 4) ? 4 : 2;
-    const int nbf = P / R;
-    const int total = nbf * nseq;
-    C<T> v[kMaxButterflies][4];
-    int cnt = 0;
-    for (int bidx = tid; bidx < total; bidx += nt, ++cnt) {
-      const int s = bidx % nseq, j = bidx / nseq;
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (r < R) v[cnt][r] = buf[(j + r * nbf) * nseq + s];
-    }
-    __syncthreads();
-    cnt = 0;
-    for (int bidx = tid; bidx < total; bidx += nt, ++cnt) {
-      const int s = bidx % nseq, j = bidx / nseq;
-      const int k = j % Ns;
-      const int step = k * (P / (Ns * R));
-      C<T>* x = v[cnt];
-#pragma unroll
-      for (int r = 1; r < 4; ++r)
-        if (r < R) {
-          C<T> w = tw[r * step];
-          if (inv) w.y = -w.y;
-          x[r] = cmul<T>(x[r], w);
-        }
-      if (R == 4) {
-        const C<T> a0 = cadd<T>(x[0], x[2]), a1 = csub<T>(x[0], x[2]);
-        const C<T> a2 = cadd<T>(x[1], x[3]);
-        C<T> d = csub<T>(x[1], x[3]);
-        // times -i (forward) or +i (inverse)
-        const C<T> a3 = inv ? mk<T>(-d.y, d.x) : mk<T>(d.y, -d.x);
-        x[0] = cadd<T>(a0, a2);
-        x[2] = csub<T>(a0, a2);
-        x[1] = cadd<T>(a1, a3);
-        x[3] = csub<T>(a1, a3);
-      } else {
-        const C<T> a0 = cadd<T>(x[0], x[1]), a1 = csub<T>(x[0], x[1]);
-        x[0] = a0;
-        x[1] = a1;
-      }
-      const int idxD = (j / Ns) * Ns * R + k;
-#pragma unroll
-      for (int r = 0; r < 4; ++r)
-        if (r < R) buf[(idxD + r * Ns) * nseq + s] = x[r];
-    }
-    __syncthreads();
-    Ns *= R;
-  }
+  int Ns = 1;
+  for (; P / Ns >= 4; Ns *= 4) lds_fft_pass<T, 4>(buf, P, nseq, Ns, tw, inv);
+  if (Ns < P) lds_fft_pass<T, 2>(buf, P, nseq, Ns, tw, inv);
 }
 
 // ---- pass 1: rows of (s .* x), zero-padded to P -----------------------------
 template <typename T>
-__global__ void k_row_forward(const C<T>* __restrict__ x, const T* __restrict__ m, int n, int P,
+__global__ __launch_bounds__(kFftMaxThreads) void k_row_forward(const C<T>* __restrict__ x, const T* __restrict__ m, int n, int P,
                               int S, const C<T>* __restrict__ tw, C<T>* __restrict__ X) {
   extern __shared__ unsigned char smem_raw[];
   C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
@@ -114,7 +127,7 @@ __global__ void k_row_forward(const C<T>* __restrict__ x, const T* __restrict__ 
 
 // ---- pass 2: columns, times khat, inverse columns ------------------------
 template <typename T>
-__global__ void k_col_convolve(C<T>* __restrict__ X, const C<T>* __restrict__ khat, int n, int P,
+__global__ __launch_bounds__(kFftMaxThreads) void k_col_convolve(C<T>* __restrict__ X, const C<T>* __restrict__ khat, int n, int P,
                                int S, const C<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
@@ -142,7 +155,7 @@ __global__ void k_col_convolve(C<T>* __restrict__ X, const C<T>* __restrict__ kh
 
 // ---- pass 3: inverse rows and epilogue y = a x + coef * conv --------------
 template <typename T>
-__global__ void k_row_inverse(const C<T>* __restrict__ X, const C<T>* __restrict__ x, int n, int P,
+__global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __restrict__ X, const C<T>* __restrict__ x, int n, int P,
                               int S, const C<T>* __restrict__ tw, T a, T coef,
                               C<T>* __restrict__ y) {
   extern __shared__ unsigned char smem_raw[];
@@ -183,7 +196,7 @@ __global__ void k_wrap_table(const double2* __restrict__ kq, int n, int P, doubl
 }
 
 // In-place FFT of S full rows (stride P) of a P x P array.
-__global__ void k_fft_rows_full(double2* __restrict__ W, int P, int S, const double2* __restrict__ tw) {
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_rows_full(double2* __restrict__ W, int P, int S, const double2* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   double2* buf = reinterpret_cast<double2*>(smem_raw);
   const int r0 = blockIdx.x * S;
@@ -200,7 +213,7 @@ __global__ void k_fft_rows_full(double2* __restrict__ W, int P, int S, const dou
 }
 
 // In-place FFT of S full columns of a P x P array; quadrant written to khat.
-__global__ void k_fft_cols_full(double2* __restrict__ W, int P, int S, const double2* __restrict__ tw,
+__global__ __launch_bounds__(kFftMaxThreads) void k_fft_cols_full(double2* __restrict__ W, int P, int S, const double2* __restrict__ tw,
                                 double2* __restrict__ khat, float2* __restrict__ khat32) {
   extern __shared__ unsigned char smem_raw[];
   double2* buf = reinterpret_cast<double2*>(smem_raw);
@@ -226,15 +239,17 @@ template <typename T>
 int seq_per_block(int P) {
   int S = 131072 / (P * (int)sizeof(C<T>));
   if (S > 8) S = 8;
+  if (S * P > kVals<T> * kFftMaxThreads) S = kVals<T> * kFftMaxThreads / P;
   if (S > P) S = P;
   if (S < 1) S = 1;
   return S;
 }
 
+template <typename T>
 int threads_for(int S, int P) {
-  int nt = S * P / 16;
+  int nt = S * P / kVals<T>;
   if (nt < 64) nt = 64;
-  if (nt > 1024) nt = 1024;
+  if (nt > kFftMaxThreads) nt = kFftMaxThreads;
   return nt;
 }
 
@@ -260,7 +275,7 @@ hipError_t launch_convolve(const C<T>* x, const T* m, int n, int nrhs, const C<T
                            const C<T>* tw, T a, T c, C<T>* work, C<T>* y, hipStream_t st) {
   const int P = fft_len(n);
   const int S = seq_per_block<T>(P);
-  const int nt = threads_for(S, P);
+  const int nt = threads_for<T>(S, P);
   const size_t lds = (size_t)S * P * sizeof(C<T>);
   hipError_t e;
   if ((e = allow_lds(k_row_forward<T>, lds)) != hipSuccess) return e;
@@ -283,7 +298,7 @@ hipError_t launch_green_spectrum(const double2* kq, int n, const double2* tw, do
                                  double2* khat, float2* khat32, hipStream_t st) {
   const int P = fft_len(n);
   const int S = seq_per_block<double>(P);
-  const int nt = threads_for(S, P);
+  const int nt = threads_for<double>(S, P);
   const size_t lds = (size_t)S * P * sizeof(double2);
   hipError_t e;
   if ((e = allow_lds(k_fft_rows_full, lds)) != hipSuccess) return e;

@@ -1,0 +1,563 @@
+// Interface form of the moving-PML sweep (Algorithm 2) for the GPU.
+//
+// The sweep couples slice k to its neighbours only through one line each:
+// H_[k,k-1] reads the last line of D_{k-1}, H_[k,k+1] the first line of
+// D_{k+1}. Write E (F) for the restriction to the last (first) line of D_k,
+// J_E (J_F) for the injection into the right-hand side rows of that line and
+// Hm_k, Hp_k for the three-coefficient coupling rows. With
+//     lambda_k = E u_k(forward pass),   mu_k = F u_k(final),
+// Algorithm 2 is equivalent to
+//     lambda_0 = E T_0 f_0,   lambda_k = E T_k f_k - M_k lambda_{k-1},
+//     mu_{l-1} = F T_{l-1} f_{l-1} - P_{l-1} lambda_{l-2},
+//     mu_k     = F T_k f_k - P_k lambda_{k-1} - N_k mu_{k+1},
+//     u_k      = T_k (f_k - J_F Hm_k lambda_{k-1} - J_E Hp_k mu_{k+1}),
+// with the L x L interface maps M_k = E T_k J_F Hm_k, P_k = F T_k J_F Hm_k,
+// N_k = F T_k J_E Hp_k built once at setup (slice solves with the L
+// columns of J_F Hm_k or J_E Hp_k as right-hand sides). Every slice solve
+// is then independent: all slices run at once (phase A: the boundary lines
+// of T_k f_k; phase C: the final fields), and only the two short recurrences
+// for lambda and mu remain sequential, each step a dense L x L product.
+// The result is that of the sequential sweep up to rounding.
+//
+// Slice solves: block elimination along the transverse index j with the
+// factors of k_factor (W_j = S_j^{-1} B_j, the columns of S_j^{-1} on the
+// lines of D_k, G_j = S_j^{-1} C_j). A workgroup solves one slice, one wave
+// per right-hand side; factor blocks stream into LDS D steps ahead by direct
+// global-to-LDS copies, so the dependent chain of 2L block steps reads LDS
+// only and needs no workgroup barrier per step.
+#include "kernels.hpp"
+
+namespace lsw {
+
+namespace {
+
+constexpr int kNT = 256;
+
+template <typename T>
+__device__ inline C<T> shfl_xor_c(C<T> v, int mask) {
+  return mk<T>(__shfl_xor(v.x, mask), __shfl_xor(v.y, mask));
+}
+
+// complex values per 16-byte direct-to-LDS copy
+template <typename T>
+constexpr int kCpl = 16 / (int)sizeof(C<T>);
+// block steps staged per chunk (16-line or 32-line subproblems)
+template <int TP>
+constexpr int kDepth = TP == 16 ? 8 : 2;
+
+// exchanges within lane quads: quad_perm(1,0,3,2) = 0xB1, quad_perm(2,3,0,1) = 0x4E
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline double dpp_d(double v) {
+  const int lo = __double2loint(v), hi = __double2hiint(v);
+  return __hiloint2double(__builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false),
+                          __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ inline float dpp(float v) { return dpp_f<CTRL>(v); }
+template <int CTRL>
+__device__ inline double dpp(double v) { return dpp_d<CTRL>(v); }
+
+// threads of a slice-solve workgroup: W computing waves, at least 4 (float)
+// or 8 (double) waves so that staging a chunk takes few registers per thread
+template <typename T, int W>
+constexpr int slice_threads() {
+  constexpr int hw = sizeof(T) == 8 ? 8 : 4;
+  return 64 * (W > hw ? W : hw);
+}
+
+// Dynamic LDS of k_slice_solve for SB stage elements per buffer.
+template <typename T, int TP, int W>
+constexpr size_t slice_lds_bytes(size_t SB) {
+  return (2 * SB + (size_t)W * (4 * kDepth<TP> * TP + 2 * TP)) * sizeof(C<T>);
+}
+
+// Chunk staging through registers: load count values (this thread's share)
+// while the previous chunk is in use, store them to LDS when it is done.
+template <typename T, int NREG>
+struct Stager {
+  T re[NREG], im[NREG];
+  __device__ __attribute__((always_inline)) inline void load(const C<T>* g, int count, int tid, int nt) {
+#pragma unroll
+    for (int q = 0; q < NREG; ++q) {
+      const int e = tid + q * nt;
+      const C<T> v = e < count ? g[e] : mk<T>(0, 0);
+      re[q] = v.x;
+      im[q] = v.y;
+    }
+  }
+  __device__ __attribute__((always_inline)) inline void store(C<T>* l, int count, int tid, int nt) {
+#pragma unroll
+    for (int q = 0; q < NREG; ++q) {
+      const int e = tid + q * nt;
+      if (e < count) l[e] = mk<T>(re[q], im[q]);
+    }
+  }
+};
+
+// One slice subproblem per workgroup, one right-hand side per wave. Lanes:
+// S = 4 (16-line) or 2 (32-line) lanes per row, each lane a stride-S set of
+// columns, reductions within lane quads by DPP. The dependent chain
+//   y_j = S_j^{-1} r_j - W_j y_{j-1}   (forward),   x_j = y_j - G_j x_{j+1}   (backward)
+// passes the t-vector through the wave's own LDS row (LDS operations of a
+// wave complete in order, so no barrier per step).
+template <typename T, int TP, int W>
+__global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSolveArgs<T> A) {
+  constexpr int NT = slice_threads<T, W>();
+  constexpr int CB = 4;  // columns per lane loaded and used together
+  constexpr int S = TP == 16 ? 4 : 2;
+  constexpr int D = kDepth<TP>;
+  constexpr int NR = (D * TP + 63) / 64;
+  // largest chunk: D blocks of the forward factors (t^2 + t tw <= 2 TP^2)
+  constexpr int NSTAGE = (D * 2 * TP * TP + NT - 1) / NT;
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* lds = reinterpret_cast<C<T>*>(smem_raw);
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const bool computes = wv < W;  // waves beyond W only help staging
+  const int a = lane / S, cq = lane % S;
+  const int k = A.slice0 + blockIdx.x;
+  const int rr = blockIdx.y * W + wv;
+  const bool rvalid = computes && rr < A.nrhs;
+  const int L = A.L, b = A.b;
+  const int lo = A.P.lo[k], hi = A.P.hi[k], first = A.P.first[k], t = A.P.t[k];
+  const int naux = lo - first, tw = hi - lo + 1;
+  const int tt = t * t, fstride = factor_stride(t, tw), gstride = factor_stride(t, 0);
+  const C<T>* fs = A.FS + A.P.fs_off[k];
+  const C<T>* fg = A.FG + A.P.fg_off[k];
+  const bool unit_src = A.src_kind >= kSrcUnitF;
+  const C<T>* hrow = A.src_kind == kSrcUnitF ? A.Hm : A.Hp;
+  const int unit_c = A.src_kind == kSrcUnitF ? 0 : tw - 1;  // right-hand side line within D_k
+  const int col = A.col0 + rr;                               // column of the unit sources
+  const bool arow = a < t;
+
+  const size_t SB = A.stage;
+  C<T>* stage = lds;                                     // [2][SB] factor chunks (shared)
+  C<T>* wreg = lds + 2 * SB + (size_t)(computes ? wv : 0) * (4 * D * TP + 2 * TP);
+  C<T>* rst = wreg;                                      // [2][D][TP] right-hand sides
+  C<T>* yst = wreg + 2 * D * TP;                         // [2][D][TP] forward results
+  C<T>* yb = wreg + 4 * D * TP;                          // [TP] exchange row
+  C<T>* yg = A.yscr + (((size_t)blockIdx.x * gridDim.y + blockIdx.y) * W + (computes ? wv : 0)) * (size_t)L * TP;
+  const int tid = threadIdx.x;
+  Stager<T, NSTAGE> stg;
+  Stager<T, NR> ystg;
+
+  const int nchunks = (L + D - 1) / D;
+  C<T> rreg[NR];
+  auto load_rhs = [&](int c) {  // element e = line * D + jj (consecutive j in memory)
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int e = lane + q * 64;
+      const int jj = e % D, cl = e / D;
+      const int j = c * D + jj;
+      C<T> v = mk<T>(0, 0);
+      if (rvalid && cl < tw && j < L) {
+        if (A.src_kind == kSrcGrid) {
+          v = A.src[((size_t)rr * L + lo + cl + b) * L + j];
+        } else if (A.src_kind == kSrcSlice) {
+          v = A.src[((size_t)rr * tw + cl) * L + j];
+        } else if (cl == unit_c) {
+          const int dj = col - j;
+          if (dj >= -1 && dj <= 1) v = hrow[((size_t)k * L + j) * 3 + dj + 1];
+        }
+      }
+      rreg[q] = v;
+    }
+  };
+  auto store_rhs = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int e = lane + q * 64;
+      if (e < D * TP) rst[buf * D * TP + (e % D) * TP + e / D] = rreg[q];
+    }
+  };
+  auto reduce = [&](C<T> v) {
+    v.x += dpp<0xB1>(v.x);
+    v.y += dpp<0xB1>(v.y);
+    if (S == 4) {
+      v.x += dpp<0x4E>(v.x);
+      v.y += dpp<0x4E>(v.y);
+    }
+    return v;
+  };
+
+  // ---------------- forward elimination ----------------
+  if (computes && lane < TP) yb[lane] = mk<T>(0, 0);
+  {
+    const int cnt = (L < D ? L : D) * fstride;
+    stg.load(fs, cnt, tid, NT);
+    if (computes) load_rhs(0);
+    stg.store(stage, cnt, tid, NT);
+    if (computes) store_rhs(0);
+    lds_barrier();
+  }
+  C<T> ylast = mk<T>(0, 0);
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    const int j1 = (c + 1) * D;
+    const int cnt1 = c + 1 < nchunks ? (L - j1 < D ? L - j1 : D) * fstride : 0;
+    if (c + 1 < nchunks) {
+      stg.load(fs + (size_t)j1 * fstride, cnt1, tid, NT);
+      if (computes) load_rhs(c + 1);
+    }
+    const C<T>* F = stage + buf * SB;
+    const C<T>* RB = rst + buf * D * TP;
+    const int jend = (L - c * D < D) ? L - c * D : D;
+    for (int jj = 0; jj < jend && computes; ++jj) {
+      const int j = c * D + jj;
+      // rows a >= t and columns >= t read in-range LDS garbage that the masks drop
+      const C<T>* Wj = F + jj * fstride + a * t;
+      const C<T>* Sd = F + jj * fstride + tt + a * tw;
+      C<T> acc = mk<T>(0, 0);
+      const bool chain = j > 0;
+#pragma unroll
+      for (int blk = 0; blk < TP / S / CB; ++blk) {
+        C<T> wv[CB], yv[CB], sv[CB], rv[CB];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+          const int cc = cq + (blk * CB + i) * S;
+          const int cw = cc < t ? cc : 0, cs = cc < tw ? cc : 0;
+          wv[i] = Wj[cw];
+          yv[i] = yb[cw];
+          sv[i] = Sd[cs];
+          rv[i] = RB[jj * TP + cs];
+        }
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+          // selects, not multiplications by 0: masked operands may hold any bits
+          const int cc = cq + (blk * CB + i) * S;
+          C<T> pw = cmul<T>(wv[i], yv[i]), ps = cmul<T>(sv[i], rv[i]);
+          if (!(cc < t && chain)) pw = mk<T>(0, 0);
+          if (!(cc < tw)) ps = mk<T>(0, 0);
+          acc.x += ps.x - pw.x;
+          acc.y += ps.y - pw.y;
+        }
+      }
+      if (!arow) acc = mk<T>(0, 0);
+      acc = reduce(acc);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (cq == 0 && arow) {
+        yb[a] = acc;
+        yg[(size_t)j * TP + a] = acc;
+      }
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      ylast = acc;
+    }
+    if (c + 1 < nchunks) {
+      lds_barrier();  // every wave is done with buffer buf ^ 1's previous contents
+      stg.store(stage + (buf ^ 1) * SB, cnt1, tid, NT);
+      if (computes) store_rhs(buf ^ 1);
+      lds_barrier();
+    }
+  }
+  // the forward results in yg are read back below
+  __threadfence_block();
+  __syncthreads();
+
+  // ---------------- back substitution ----------------
+  auto emit = [&](int j, C<T> x) {
+    if (!rvalid || !arow || cq != 0) return;
+    if (A.dst_kind == kDstGrid) {
+      if (a >= naux) A.dst[((size_t)rr * L + first + a + b) * L + j] = x;
+    } else if (A.dst_kind == kDstSlice) {
+      if (a >= naux) A.dst[((size_t)rr * tw + a - naux) * L + j] = x;
+    } else {
+      const size_t ci = unit_src ? (size_t)col : (size_t)rr;
+      if (a == t - 1 && A.dstE) A.dstE[k * A.sk + ci * A.sr + (size_t)j * A.sj] = x;
+      if (a == naux && A.dstF) A.dstF[k * A.sk + ci * A.sr + (size_t)j * A.sj] = x;
+    }
+  };
+  emit(L - 1, ylast);  // x_{L-1} = y_{L-1}; it is also what yb holds
+  const int nbch = (L - 1 + D - 1) / D;  // chunks of j in [c D, c D + D) cover 0..L-2
+  auto load_bwd = [&](int c) {
+    const int j0 = c * D;
+    const int n = (L - 1 - j0 < D ? L - 1 - j0 : D);
+    stg.load(fg + (size_t)j0 * gstride, n * gstride, tid, NT);
+    if (computes) ystg.load(yg + (size_t)j0 * TP, n * TP, lane, 64);  // this wave's own rows
+  };
+  auto store_bwd = [&](int c, int buf) {
+    const int j0 = c * D;
+    const int n = (L - 1 - j0 < D ? L - 1 - j0 : D);
+    stg.store(stage + buf * SB, n * gstride, tid, NT);
+    if (computes) ystg.store(yst + buf * D * TP, n * TP, lane, 64);
+  };
+  if (nbch > 0) {
+    load_bwd(nbch - 1);
+    store_bwd(nbch - 1, 0);
+    lds_barrier();
+  }
+  for (int ci = 0; ci < nbch; ++ci) {
+    const int c = nbch - 1 - ci;
+    const int buf = ci & 1;
+    if (ci + 1 < nbch) load_bwd(c - 1);
+    const C<T>* G = stage + buf * SB;
+    const C<T>* Y = yst + buf * D * TP;
+    for (int jj = D - 1; jj >= 0 && computes; --jj) {
+      const int j = c * D + jj;
+      if (j > L - 2) continue;
+      const C<T>* Gj = G + jj * gstride + a * t;
+      C<T> acc = mk<T>(0, 0);
+#pragma unroll
+      for (int blk = 0; blk < TP / S / CB; ++blk) {
+        C<T> gv[CB], xv[CB];
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+          const int cc = cq + (blk * CB + i) * S;
+          const int cw = cc < t ? cc : 0;
+          gv[i] = Gj[cw];
+          xv[i] = yb[cw];
+        }
+#pragma unroll
+        for (int i = 0; i < CB; ++i) {
+          C<T> p = cmul<T>(gv[i], xv[i]);
+          if (!(cq + (blk * CB + i) * S < t)) p = mk<T>(0, 0);
+          acc.x += p.x;
+          acc.y += p.y;
+        }
+      }
+      if (!arow) acc = mk<T>(0, 0);
+      acc = reduce(acc);
+      C<T> x = mk<T>(0, 0);
+      if (arow) x = csub<T>(Y[jj * TP + a], acc);
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      if (cq == 0 && arow) yb[a] = x;
+      __atomic_signal_fence(__ATOMIC_SEQ_CST);
+      emit(j, x);
+    }
+    if (ci + 1 < nbch) {
+      lds_barrier();
+      store_bwd(c - 1, buf ^ 1);
+      lds_barrier();
+    }
+  }
+}
+
+// ---- interface recurrences: y = add - M x for a batch of right-hand sides --
+// M: [L][L] row-major per slice (stride mstride); add, x, y: [nrhs][L] per slice.
+// blockIdx.z selects the slice k = kbeg + z.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_iface_gemv(const C<T>* __restrict__ M, const C<T>* add, const C<T>* x,
+                                                    C<T>* y, int L, int nrhs, int kbeg, size_t mstride,
+                                                    size_t vstride, int xoff) {
+  // nrhs <= 4: one wave per output row, lanes over columns, 8 loads in flight per lane
+  constexpr int U = 8;
+  const int k = kbeg + blockIdx.z;
+  const C<T>* Mk = M + (size_t)k * mstride;
+  const C<T>* xk = x + (size_t)(k + xoff) * vstride;
+  const C<T>* ak = add + (size_t)k * vstride;
+  C<T>* yk = y + (size_t)k * vstride;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int row = blockIdx.x * (kNT / 64) + wave;
+  if (row >= L) return;
+  C<T> acc[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) acc[q] = mk<T>(0, 0);
+  const C<T>* Mr = Mk + (size_t)row * L;
+  for (int c0 = 0; c0 < L; c0 += 64 * U) {
+    C<T> mv[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int c = c0 + u * 64 + lane;
+      mv[u] = c < L ? Mr[c] : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      if (q >= nrhs) break;
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int c = c0 + u * 64 + lane;
+        if (c < L) acc[q] = cfma<T>(acc[q], mv[u], xk[(size_t)q * L + c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    for (int m = 32; m > 0; m >>= 1) acc[q] = cadd<T>(acc[q], shfl_xor_c<T>(acc[q], m));
+    if (lane == 0 && q < nrhs) yk[(size_t)q * L + row] = csub<T>(ak[(size_t)q * L + row], acc[q]);
+  }
+}
+
+// nrhs > 4: tiles of 16 rows x 16 right-hand sides, columns staged by CT with
+// the next chunk's loads in flight while the current one is used.
+template <typename T>
+__global__ __launch_bounds__(kNT) void k_iface_gemm(const C<T>* __restrict__ M, const C<T>* add, const C<T>* x,
+                                                    C<T>* y, int L, int nrhs, int kbeg, size_t mstride,
+                                                    size_t vstride, int xoff) {
+  constexpr int RT = 16, QT = 16, CT = 64;
+  constexpr int PER = RT * CT / kNT;  // loads per thread per chunk and operand
+  __shared__ C<T> Ms[2][RT][CT + 1];
+  __shared__ C<T> Xs[2][QT][CT + 1];
+  const int k = kbeg + blockIdx.z;
+  const C<T>* Mk = M + (size_t)k * mstride;
+  const C<T>* xk = x + (size_t)(k + xoff) * vstride;
+  const C<T>* ak = add + (size_t)k * vstride;
+  C<T>* yk = y + (size_t)k * vstride;
+  const int r0 = blockIdx.x * RT, q0 = blockIdx.y * QT;
+  const int ri = threadIdx.x / QT, qi = threadIdx.x % QT;
+  C<T> mreg[PER], xreg[PER];
+  auto load = [&](int c0) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int idx = threadIdx.x + p * kNT;
+      const int rr = idx / CT, cc = idx % CT;
+      mreg[p] = (r0 + rr < L && c0 + cc < L) ? Mk[(size_t)(r0 + rr) * L + c0 + cc] : mk<T>(0, 0);
+      xreg[p] = (q0 + rr < nrhs && c0 + cc < L) ? xk[(size_t)(q0 + rr) * L + c0 + cc] : mk<T>(0, 0);
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int p = 0; p < PER; ++p) {
+      const int idx = threadIdx.x + p * kNT;
+      Ms[buf][idx / CT][idx % CT] = mreg[p];
+      Xs[buf][idx / CT][idx % CT] = xreg[p];
+    }
+  };
+  C<T> acc = mk<T>(0, 0);
+  load(0);
+  store(0);
+  __syncthreads();
+  int buf = 0;
+  for (int c0 = 0; c0 < L; c0 += CT) {
+    const bool more = c0 + CT < L;
+    if (more) load(c0 + CT);
+#pragma unroll 8
+    for (int cc = 0; cc < CT; ++cc) acc = cfma<T>(acc, Ms[buf][ri][cc], Xs[buf][qi][cc]);
+    if (more) {
+      store(buf ^ 1);
+      __syncthreads();
+      buf ^= 1;
+    }
+  }
+  const int row = r0 + ri, q = q0 + qi;
+  if (row < L && q < nrhs) yk[(size_t)q * L + row] = csub<T>(ak[(size_t)q * L + row], acc);
+}
+
+// f on the first line of D_k -= Hm_k lambda_{k-1}; on its last line -= Hp_k mu_{k+1}.
+template <typename T>
+__global__ void k_couple(SliceTables P, int L, int b, const C<T>* __restrict__ Hm, const C<T>* __restrict__ Hp,
+                         const C<T>* __restrict__ lam, const C<T>* __restrict__ mu, int nrhs, C<T>* f) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t tot = (size_t)P.nslices * nrhs * L;
+  if (idx >= tot) return;
+  const int j = (int)(idx % L);
+  const int r = (int)((idx / L) % nrhs);
+  const int k = (int)(idx / ((size_t)L * nrhs));
+  C<T>* fr = f + (size_t)r * L * L;
+  if (k > 0) {
+    const C<T>* lv = lam + ((size_t)(k - 1) * nrhs + r) * L;
+    const C<T>* hm = Hm + ((size_t)k * L + j) * 3;
+    C<T> acc = mk<T>(0, 0);
+    for (int d = -1; d <= 1; ++d)
+      if (j + d >= 0 && j + d < L) acc = cfma<T>(acc, hm[d + 1], lv[j + d]);
+    C<T>* o = fr + (size_t)(P.lo[k] + b) * L + j;
+    *o = csub<T>(*o, acc);
+  }
+  if (k < P.nslices - 1) {
+    const C<T>* mv = mu + ((size_t)(k + 1) * nrhs + r) * L;
+    const C<T>* hp = Hp + ((size_t)k * L + j) * 3;
+    C<T> acc = mk<T>(0, 0);
+    for (int d = -1; d <= 1; ++d)
+      if (j + d >= 0 && j + d < L) acc = cfma<T>(acc, hp[d + 1], mv[j + d]);
+    C<T>* o = fr + (size_t)(P.hi[k] + b) * L + j;
+    *o = csub<T>(*o, acc);
+  }
+}
+
+template <typename K>
+hipError_t allow_lds(K kernel, size_t bytes) {
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                             (int)bytes);
+}
+
+template <typename T, int TP, int W>
+hipError_t launch_one(const SliceSolveArgs<T>& a, int nslices, int ngroups, hipStream_t st) {
+  const size_t bytes = slice_lds_bytes<T, TP, W>(a.stage);
+  hipError_t e = allow_lds(k_slice_solve<T, TP, W>, bytes);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_slice_solve<T, TP, W>), dim3(nslices, ngroups), dim3(slice_threads<T, W>()), bytes, st, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+template <typename T>
+size_t slice_scratch_elems(int L, int W) {
+  return (size_t)L * 32 * W;
+}
+template size_t slice_scratch_elems<double>(int, int);
+template size_t slice_scratch_elems<float>(int, int);
+
+template <typename T>
+size_t slice_stage_elems(int tmax, int fstride_max) {
+  const int TP = tmax > 16 ? 32 : 16;
+  const int D = TP == 16 ? kDepth<16> : kDepth<32>;
+  const int gmax = factor_stride(TP, 0);
+  const size_t sb = (size_t)D * (fstride_max > gmax ? fstride_max : gmax);
+  const size_t q = 64 * kCpl<T>;  // whole 64-lane copies stay inside the buffer
+  return (sb + q - 1) / q * q;
+}
+template size_t slice_stage_elems<double>(int, int);
+template size_t slice_stage_elems<float>(int, int);
+
+template <typename T>
+size_t slice_lds(int tmax, size_t stage, int W) {
+  const bool big = tmax > 16;
+  switch (W) {
+    case 1: return big ? slice_lds_bytes<T, 32, 1>(stage) : slice_lds_bytes<T, 16, 1>(stage);
+    case 4: return big ? slice_lds_bytes<T, 32, 4>(stage) : slice_lds_bytes<T, 16, 4>(stage);
+    case 8: return big ? slice_lds_bytes<T, 32, 8>(stage) : slice_lds_bytes<T, 16, 8>(stage);
+    default: return 0;
+  }
+}
+template size_t slice_lds<double>(int, size_t, int);
+template size_t slice_lds<float>(int, size_t, int);
+
+template <typename T>
+hipError_t launch_slice_solves(const SliceSolveArgs<T>& a, int nslices, int tmax, int W, int ngroups,
+                               hipStream_t st) {
+  const bool big = tmax > 16;
+  switch (W) {
+    case 1: return big ? launch_one<T, 32, 1>(a, nslices, ngroups, st) : launch_one<T, 16, 1>(a, nslices, ngroups, st);
+    case 4: return big ? launch_one<T, 32, 4>(a, nslices, ngroups, st) : launch_one<T, 16, 4>(a, nslices, ngroups, st);
+    case 8: return big ? launch_one<T, 32, 8>(a, nslices, ngroups, st) : launch_one<T, 16, 8>(a, nslices, ngroups, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+template hipError_t launch_slice_solves<double>(const SliceSolveArgs<double>&, int, int, int, int, hipStream_t);
+template hipError_t launch_slice_solves<float>(const SliceSolveArgs<float>&, int, int, int, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
+                             int kcount, size_t mstride, size_t vstride, int xoff, hipStream_t st) {
+  if (kcount <= 0) return hipSuccess;
+  if (nrhs <= 4) {
+    hipLaunchKernelGGL(k_iface_gemv<T>, dim3((L + 3) / 4, 1, kcount), dim3(kNT), 0, st, M, add, x, y, L, nrhs, kbeg,
+                       mstride, vstride, xoff);
+  } else {
+    hipLaunchKernelGGL(k_iface_gemm<T>, dim3((L + 15) / 16, (nrhs + 15) / 16, kcount), dim3(kNT), 0, st, M, add, x,
+                       y, L, nrhs, kbeg, mstride, vstride, xoff);
+  }
+  return hipGetLastError();
+}
+template hipError_t launch_iface_step<double>(const double2*, const double2*, const double2*, double2*, int, int,
+                                              int, int, size_t, size_t, int, hipStream_t);
+template hipError_t launch_iface_step<float>(const float2*, const float2*, const float2*, float2*, int, int, int,
+                                             int, size_t, size_t, int, hipStream_t);
+
+template <typename T>
+hipError_t launch_couple(const SliceTables& P, int L, int b, const C<T>* Hm, const C<T>* Hp, const C<T>* lam,
+                         const C<T>* mu, int nrhs, C<T>* f, hipStream_t st) {
+  const size_t tot = (size_t)P.nslices * nrhs * L;
+  hipLaunchKernelGGL(k_couple<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, P, L, b, Hm, Hp, lam, mu,
+                     nrhs, f);
+  return hipGetLastError();
+}
+template hipError_t launch_couple<double>(const SliceTables&, int, int, const double2*, const double2*,
+                                          const double2*, const double2*, int, double2*, hipStream_t);
+template hipError_t launch_couple<float>(const SliceTables&, int, int, const float2*, const float2*, const float2*,
+                                         const float2*, int, float2*, hipStream_t);
+
+}  // namespace lsw

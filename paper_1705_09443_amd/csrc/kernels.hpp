@@ -34,13 +34,18 @@ struct StencilTables {
   double omega2;
 };
 
+// Complex values per block step of a slice factor: t^2 (+ t * tw for the
+// forward factors), rounded up to an even count so every block starts on a
+// 16-byte boundary.
+__host__ __device__ inline int factor_stride(int t, int tw) { return (t * t + t * tw + 1) & ~1; }
+
 struct SliceTables {
   const int* lo;     // per slice: first grid line of D_k
   const int* hi;     // last grid line of D_k
   const int* first;  // first line of the subproblem
   const int* t;      // lines of the subproblem
-  const size_t* fs_off;  // offset (complex elements) of slice k in FS: L x (t^2 + 3t)
-  const size_t* fg_off;  // offset of slice k in FG: L x t^2
+  const size_t* fs_off;  // offset (complex elements) of slice k in FS: L x factor_stride(t, tw)
+  const size_t* fg_off;  // offset of slice k in FG: L x factor_stride(t, 0)
   int nslices;
 };
 
@@ -64,6 +69,53 @@ template <typename T>
 hipError_t launch_sweep(const SliceTables& P, int L, int b, const C<T>* FS, const C<T>* FG,
                         const C<T>* Hm, const C<T>* Hp, const C<T>* f, C<T>* u, C<T>* yscratch,
                         int nrhs, int mode, int slice, hipStream_t st);
+
+// ---- interface form of the sweep (interface.hip) ----
+enum SliceSrc { kSrcGrid = 0, kSrcSlice = 1, kSrcUnitF = 2, kSrcUnitE = 3 };
+enum SliceDst { kDstGrid = 0, kDstSlice = 1, kDstLines = 2 };
+template <typename T>
+struct SliceSolveArgs {
+  SliceTables P;
+  int L, b;
+  const C<T>* FS;
+  const C<T>* FG;
+  const C<T>* Hm;
+  const C<T>* Hp;
+  int slice0;      // slice of blockIdx.x = 0
+  int nrhs;        // right-hand sides (columns) of this launch
+  int src_kind;    // SliceSrc
+  const C<T>* src; // [nrhs][L][L] (grid) or [nrhs][lines][L] (slice)
+  int col0;        // first column for the unit sources (columns of J_F Hm or J_E Hp)
+  int dst_kind;    // SliceDst
+  C<T>* dst;       // grid or slice array
+  C<T>* dstE;      // lines: last line of D_k  at dstE[k sk + col sr + j sj]
+  C<T>* dstF;      // lines: first line of D_k at dstF[k sk + col sr + j sj]
+  size_t sk, sr, sj;
+  C<T>* yscr;      // nslices * ngroups * slice_scratch_elems(L, W)
+  size_t stage;    // LDS stage buffer length (slice_stage_elems)
+};
+// Scratch (complex elements) of one workgroup of W waves.
+template <typename T>
+size_t slice_scratch_elems(int L, int W);
+// LDS stage buffer length for slices with at most tmax lines and factor stride fstride_max.
+template <typename T>
+size_t slice_stage_elems(int tmax, int fstride_max);
+// Dynamic LDS bytes of one workgroup (0 for an unsupported W).
+template <typename T>
+size_t slice_lds(int tmax, size_t stage, int W);
+// One workgroup per (slice, group of W right-hand sides), one wave per
+// right-hand side; W in {1, 4, 8}; tmax = largest line count (<= 32).
+template <typename T>
+hipError_t launch_slice_solves(const SliceSolveArgs<T>& a, int nslices, int tmax, int W, int ngroups,
+                               hipStream_t st);
+// y_k = add_k - M_k x_{k+xoff} for k = kbeg .. kbeg+kcount-1 (in place allowed, y == add)
+template <typename T>
+hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
+                             int kcount, size_t mstride, size_t vstride, int xoff, hipStream_t st);
+// f -= J_F Hm_k lambda_{k-1} + J_E Hp_k mu_{k+1} on every slice
+template <typename T>
+hipError_t launch_couple(const SliceTables& P, int L, int b, const C<T>* Hm, const C<T>* Hp, const C<T>* lam,
+                         const C<T>* mu, int nrhs, C<T>* f, hipStream_t st);
 
 // ---- Krylov helpers (krylov.hip) ----
 struct DotPair {

@@ -135,7 +135,8 @@ __global__ __launch_bounds__(256) void k_factor(StencilTables S, SliceTables P, 
   const int naux = lo - first;
   const int L = S.L, b = S.b;
   const int W = 2 * t;
-  const int tt = t * t, fstride = tt + 3 * t;
+  const int tw = t - naux;  // lines of D_k
+  const int tt = t * t, fstride = factor_stride(t, tw), gstride = factor_stride(t, 0);
   __shared__ double2 Gp[kTMax * kTMax];
   __shared__ double2 M[kTMax * 2 * kTMax];
   __shared__ double2 At[kTMax * 3], Bt[kTMax * 3], Ct[kTMax * 3];
@@ -162,7 +163,7 @@ __global__ __launch_bounds__(256) void k_factor(StencilTables S, SliceTables P, 
       double2* dst = d2 < 0 ? Bt : (d2 == 0 ? At : Ct);
       dst[a * 3 + d1 + 1] = c;
     }
-    __syncthreads();
+    lds_barrier();
     // 2. S_j = A_j - B_j G_{j-1}, augmented with the identity
     for (int idx = tid; idx < t * W; idx += nt) {
       const int a = idx / W, c = idx % W;
@@ -183,8 +184,7 @@ __global__ __launch_bounds__(256) void k_factor(StencilTables S, SliceTables P, 
       }
       M[a * (2 * kTMax) + c] = v;
     }
-    for (int idx = tid; idx < 3 * t; idx += nt) fs[(size_t)j * fstride + tt + idx] = ccast<T, double>(Bt[idx]);
-    __syncthreads();
+    lds_barrier();
     // 3. Gauss-Jordan with partial pivoting: [S | I] -> [I | S^{-1}]
     for (int p = 0; p < t; ++p) {
       if (tid < 64) {
@@ -222,7 +222,7 @@ __global__ __launch_bounds__(256) void k_factor(StencilTables S, SliceTables P, 
           }
         }
       }
-      __syncthreads();
+      lds_barrier();
       const int pr = piv_s;
       const double2 ip = ipiv_s;
       for (int c = tid; c < W; c += nt) {  // swap rows p, pr and scale the pivot row
@@ -230,7 +230,7 @@ __global__ __launch_bounds__(256) void k_factor(StencilTables S, SliceTables P, 
         M[p * (2 * kTMax) + c] = make_double2(vr.x * ip.x - vr.y * ip.y, vr.x * ip.y + vr.y * ip.x);
         if (pr != p) M[pr * (2 * kTMax) + c] = vp;
       }
-      __syncthreads();
+      lds_barrier();
       for (int idx = tid; idx < t * W; idx += nt) {
         const int r = idx / W, c = idx % W;
         if (r == p) continue;
@@ -240,24 +240,31 @@ __global__ __launch_bounds__(256) void k_factor(StencilTables S, SliceTables P, 
         v.y -= fr.x * pc.y + fr.y * pc.x;
         M[r * (2 * kTMax) + c] = v;
       }
-      __syncthreads();
+      lds_barrier();
     }
-    // 4. store S_j^{-1}; G_j = S_j^{-1} C_j (C_j tridiagonal)
+    // 4. W_j = S_j^{-1} B_j and G_j = S_j^{-1} C_j (B_j, C_j tridiagonal); the
+    //    columns of S_j^{-1} on the lines of D_k (the only nonzero right-hand side rows)
     for (int idx = tid; idx < tt; idx += nt) {
       const int a = idx / t, c = idx % t;
-      fs[(size_t)j * fstride + idx] = ccast<T, double>(M[a * (2 * kTMax) + t + c]);
-      double2 g = make_double2(0.0, 0.0);
+      double2 g = make_double2(0.0, 0.0), wv = make_double2(0.0, 0.0);
       for (int d = -1; d <= 1; ++d) {
-        const int c2 = c - d;  // row c2 of C_j has its entry at column c2 + d = c
+        const int c2 = c - d;  // rows c2 of B_j, C_j have their entry at column c2 + d = c
         if (c2 < 0 || c2 >= t) continue;
-        const double2 s = M[a * (2 * kTMax) + t + c2], cc = Ct[c2 * 3 + d + 1];
+        const double2 s = M[a * (2 * kTMax) + t + c2], cc = Ct[c2 * 3 + d + 1], bb = Bt[c2 * 3 + d + 1];
         g.x += s.x * cc.x - s.y * cc.y;
         g.y += s.x * cc.y + s.y * cc.x;
+        wv.x += s.x * bb.x - s.y * bb.y;
+        wv.y += s.x * bb.y + s.y * bb.x;
       }
       Gp[a * kTMax + c] = g;
-      fg[(size_t)j * tt + idx] = ccast<T, double>(g);
+      fg[(size_t)j * gstride + idx] = ccast<T, double>(g);
+      fs[(size_t)j * fstride + idx] = ccast<T, double>(wv);
     }
-    __syncthreads();
+    for (int idx = tid; idx < t * tw; idx += nt) {
+      const int a = idx / tw, c = idx % tw;
+      fs[(size_t)j * fstride + tt + idx] = ccast<T, double>(M[a * (2 * kTMax) + t + naux + c]);
+    }
+    lds_barrier();
   }
   // couplings H_[k,k-1] (first line of D_k) and H_[k,k+1] (last line of D_k)
   for (int idx = tid; idx < 3 * L; idx += nt) {
@@ -283,11 +290,12 @@ __device__ void slice_solve(int kind, int k, const SliceTables& P, int L, int b,
   const int lo = P.lo[k], hi = P.hi[k], first = P.first[k], t = P.t[k];
   const int naux = lo - first;
   const int a = threadIdx.x >> 3, cb = threadIdx.x & 7;
-  const int tt = t * t, fstride = tt + 3 * t;
+  const int tt = t * t, fstride = factor_stride(t, t - naux), gstride = factor_stride(t, 0);
   const C<T>* fs = FS + P.fs_off[k];
   const C<T>* fg = FG + P.fg_off[k];
   const bool own = (cb == 0) && (a < t);
-  // forward elimination
+  const int tw = t - naux;
+  // forward elimination: y_j = S_j^{-1} r_j - W_j y_{j-1} (r_j nonzero on the lines of D_k only)
   for (int j = 0; j < L; ++j) {
     const int cur = j & 1;
     if (own) {
@@ -312,20 +320,16 @@ __device__ void slice_solve(int kind, int k, const SliceTables& P, int L, int b,
       } else {
         if (a >= naux) z = in[(size_t)(a - naux) * L + j];
       }
-      if (j > 0) {
-        const C<T>* Bd = fs + (size_t)j * fstride + tt + a * 3;
-        for (int d = -1; d <= 1; ++d) {
-          const int a2 = a + d;
-          if (a2 >= 0 && a2 < t) z = csub<T>(z, cmul<T>(Bd[d + 1], ybuf[cur ^ 1][a2]));
-        }
-      }
       zbuf[a] = z;
     }
     __syncthreads();
     C<T> acc = mk<T>(0, 0);
     if (a < t) {
-      const C<T>* Sj = fs + (size_t)j * fstride + a * t;
-      for (int c = cb; c < t; c += 8) acc = cfma<T>(acc, Sj[c], zbuf[c]);
+      const C<T>* Wj = fs + (size_t)j * fstride + a * t;
+      const C<T>* Sd = fs + (size_t)j * fstride + tt + a * tw;
+      for (int c = cb; c < tw; c += 8) acc = cfma<T>(acc, Sd[c], zbuf[naux + c]);
+      if (j > 0)
+        for (int c = cb; c < t; c += 8) acc = csub<T>(acc, cmul<T>(Wj[c], ybuf[cur ^ 1][c]));
     }
     acc = cadd<T>(acc, shfl_xor_c<T>(acc, 1));
     acc = cadd<T>(acc, shfl_xor_c<T>(acc, 2));
@@ -353,7 +357,7 @@ __device__ void slice_solve(int kind, int k, const SliceTables& P, int L, int b,
   for (int j = L - 2; j >= 0; --j) {
     C<T> acc = mk<T>(0, 0);
     if (a < t) {
-      const C<T>* Gj = fg + (size_t)j * tt + a * t;
+      const C<T>* Gj = fg + (size_t)j * gstride + a * t;
       for (int c = cb; c < t; c += 8) acc = cfma<T>(acc, Gj[c], ybuf[cur][c]);
     }
     acc = cadd<T>(acc, shfl_xor_c<T>(acc, 1));

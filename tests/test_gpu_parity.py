@@ -67,6 +67,29 @@ def case(request):
     g32.close()
 
 
+def test_sequential_schedule_matches(case):
+    # Algorithm 2 slice by slice versus the interface schedule (all slices at
+    # once plus the boundary-line recurrences): the same operator up to rounding
+    from paper_1705_09443_amd import LSSolver
+    name, wl, m, ref, g64, g32 = case
+    n = wl.n
+    b, w = CASES[name][2], CASES[name][3]
+    say(f"[{name}] sequential schedule fp64 / mixed")
+    rng = np.random.default_rng(9)
+    r = crand(rng, (2, n, n))
+    md = torch.as_tensor(m).cuda()
+    with LSSolver(md, wl.omega, b, w, precision="fp64", schedule="sequential") as s64, \
+            LSSolver(md, wl.omega, b, w, precision="mixed", schedule="sequential") as s32:
+        zs = s64.apply_precond(to_dev(r)).cpu().numpy()
+        zi = g64.apply_precond(to_dev(r)).cpu().numpy()
+        zs32 = s32.apply_precond(to_dev(r, torch.complex64)).cpu().numpy()
+    for j in range(2):
+        zr = ref.precondition(r[j])
+        assert rel(zs[j], zr) <= 1e-12
+        assert rel(zi[j], zs[j]) <= 1e-12
+        assert rel(zs32[j], zr) <= 1e-4
+
+
 def test_apply_A_and_K(case):
     name, wl, m, ref, g64, g32 = case
     n = wl.n
@@ -201,3 +224,25 @@ def test_zero_rhs_and_source_kind(case):
         n, 2, wl.omega, workloads.angle_directions(1, 2))[0])
     u, info = g64.solve(to_dev(g[None]), "source", 1e-8)
     assert rel(ref.op.apply_A(u.cpu().numpy()[0]), g) <= 1.01e-8
+
+
+def test_graph_replays_agree(case):
+    # the interface recurrences run as a captured graph; replay it several
+    # times with other (eager) work and synchronisations in between, and
+    # check every replay against the eager sequential schedule's result
+    from paper_1705_09443_amd import LSSolver
+    name, wl, m, ref, g64, g32 = case
+    n = wl.n
+    b, w = CASES[name][2], CASES[name][3]
+    rng = np.random.default_rng(10)
+    r = to_dev(crand(rng, (3, n, n)))
+    say(f"[{name}] graph replays")
+    with LSSolver(torch.as_tensor(m).cuda(), wl.omega, b, w, precision="fp64", schedule="sequential") as seq:
+        zref = seq.apply_precond(r).cpu().numpy()
+    outs = []
+    for it in range(4):
+        outs.append(g64.apply_precond(r).cpu().numpy())
+        g64.apply_A(r)                     # eager work between replays
+        torch.cuda.synchronize()
+    for z in outs:
+        assert rel(z, zref) <= 1e-12
