@@ -4,22 +4,23 @@ beside the plain float64 form with one incident wave.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W]
 
-One step = one ls_solve of the whole batch: every GMRES iteration applies the
-sweeping preconditioner (Q stencil, forward and backward moving-PML sweep)
-and the FFT operator to all right-hand sides still running, until every
-right-hand side meets the tolerance. Inputs are resident in HBM before the
-timed region; setup (Algorithm 1) is timed separately and excluded.
+One step = one ls_solve of the whole batch: every FGMRES iteration applies
+the preconditioner (Q stencil, slice solves, interface recurrences, slice
+solves, extraction) and the FFT operator to every right-hand side still
+running, until every right-hand side meets the tolerance. Inputs are resident
+in HBM before the timed region; setup (Algorithm 1) is timed separately and
+excluded.
 
 Prints one JSON line. Besides the contract fields it carries the float64
-reference (same medium, one wave), the roofline of the dominant kernel timed
-with HIP events inside the timed region, and the CPU oracle timed on a
-bounded sample of the same workload.
+form (same medium, one wave), per-kind kernel times from HIP events recorded
+on the library's stream inside the timed region, the roofline of the
+dominant kind, and the CPU oracle timed on a bounded sample of the same
+workload (one of the 64 right-hand sides, solved in full).
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -29,52 +30,101 @@ sys.path.insert(0, ROOT)
 
 METRIC = "unknowns*RHS solved/s to 1e-6 residual, mixed+batched vs plain FP64 on 1 GPU"
 HBM_PEAK_GBS = 8000.0
+# published MI355X vector peaks (TFLOP/s): fp32 157.3, fp64 78.6
+ALU_PEAK = {8: 157.3, 16: 78.6}
 
 
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
-    p.add_argument("--steps", type=int, default=2)
+    p.add_argument("--steps", type=int, default=3)
     p.add_argument("--warmup", type=int, default=1)
-    p.add_argument("--fp64-steps", type=int, default=1)
+    p.add_argument("--fp64-steps", type=int, default=2)
     p.add_argument("--n", type=int, default=None, help="grid override (default: the workload's)")
     p.add_argument("--nrhs", type=int, default=None)
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
-    p.add_argument("--cpu-iters", type=int, default=1, help="oracle Arnoldi steps timed")
     return p.parse_args()
 
 
-def sweep_bytes(solver, nrhs: int, cbytes: int) -> float:
-    """Algorithmic HBM bytes of one sweep launch: every slice factor read once
-    per slice solve (2l-1 solves: S_j^{-1}, B_j diagonals, G_j per block), and
-    per right-hand side the slice right-hand sides read, the solutions written
-    and the float-accumulated scratch y written and read back."""
-    b, L = solver.pml_width, solver.L
-    total = 0.0
-    per_rhs = 0.0
-    for k in range(solver.nslices):
-        lo, hi, naux = solver.slice_bounds(k)
-        t = hi - lo + 1 + naux
-        solves = 2 if k < solver.nslices - 1 else 1
-        total += solves * L * (2 * t * t + 3 * t) * cbytes
-        per_rhs += solves * L * (2 * (hi - lo + 1) + 2 * t) * cbytes
-    return total + nrhs * per_rhs
+def fstride(t: int, tw: int) -> int:
+    return (t * t + t * tw + 1) & ~1
 
 
-def fft_bytes(n: int, P: int, cbytes: int, nrhs: int) -> float:
-    """Algorithmic bytes of one FFT operator apply on nrhs inputs: read x and m,
-    write and read the n x P row transforms twice (row pass, column pass,
-    inverse row pass), read x again for y = x + omega^2 (.), write y, and the
-    (P/2+1)^2 spectrum once."""
-    per = 2 * n * n * cbytes + n * n * cbytes / 2 + 4 * n * P * cbytes + n * n * cbytes
-    return nrhs * per + (P // 2 + 1) ** 2 * cbytes
+def work_per_column(solver, kind: str, cbytes: int, n: int):
+    """(flops, shared_bytes, column_bytes) of one launch of a kind, per
+    right-hand-side column: flops and the bytes every column moves, plus the
+    bytes the launch reads once whatever its batch (factors, maps, spectrum).
+
+    slice_solves: forward y_j = S_j^-1 r_j - W_j y_{j-1} (t^2 + t tw complex
+      multiply-adds per transverse step) and backward x_j = y_j - G_j x_{j+1}
+      (t^2), all slices; reads the factors once; per column reads the slice
+      right-hand sides, writes and reads back the forward results and writes
+      the solution.
+    interface: 3l-5 dense L x L products (lambda chain, P term, mu chain).
+    fft_convolve: read x and m, three passes over the n x P row transforms
+      (written and read), write y; the (P/2+1)^2 spectrum once.
+    stencil_Q: read n^2, write L^2.
+    """
+    L, nl = solver.L, solver.nslices
+    if kind == "slice_solves":
+        fl = sh = col = 0.0
+        for k in range(nl):
+            lo, hi, naux = solver.slice_bounds(k)
+            tw = hi - lo + 1
+            t = tw + naux
+            fl += 8.0 * L * (2 * t * t + t * tw)
+            sh += cbytes * L * (fstride(t, tw) + fstride(t, 0))
+            col += cbytes * L * (2 * tw + 2 * t)
+        return fl, sh, col
+    if kind == "interface":
+        steps = max(0, 3 * nl - 5)
+        return 8.0 * steps * L * L, float(cbytes * steps * L * L), float(cbytes * 3 * nl * L)
+    if kind == "fft_convolve":
+        P = 1
+        while P < 2 * (n + 1):
+            P <<= 1
+        col = 2 * n * n * cbytes + n * n * 4 + 4 * n * P * cbytes + n * n * cbytes
+        return 10.0 * P * P * (2 * P.bit_length() - 2), float((P // 2 + 1) ** 2 * cbytes), float(col)
+    if kind == "stencil_Q":
+        return 8.0 * 9 * n * n, 0.0, float(cbytes * (n * n + L * L))
+    if kind == "extract":
+        return 0.0, 0.0, float(cbytes * 2 * n * n)
+    return 0.0, 0.0, 0.0
 
 
-def cpu_baseline(wl, m, uinc, iters_mean, n_steps):
-    """The float64 oracle on the machine's host cores: setup (not timed, like the
-    GPU's), then n_steps Arnoldi steps (sweep + FFT operator + MGS) timed on
-    one right-hand side at the full grid, scaled by the mean iteration count."""
+def roofline(solver, prof, cbytes: int, n: int):
+    """Roofline entry of the kind with the largest total time: algorithmic
+    work per launch (mean columns per launch x per-column work + shared work)
+    over the mean event-timed launch duration, against the HBM or the vector
+    ALU peak, whichever bounds the work at that intensity."""
+    dominant = max(prof, key=lambda k: prof[k][1])
+    launches, total_ms, columns = prof[dominant]
+    avg_ms = total_ms / launches
+    cols = columns / launches
+    fl, sh, colb = work_per_column(solver, dominant, cbytes, n)
+    flops = fl * cols
+    nbytes = sh + colb * cols
+    ridge = ALU_PEAK[cbytes] * 1e12 / (HBM_PEAK_GBS * 1e9)
+    intensity = flops / nbytes if nbytes else float("inf")
+    if intensity > ridge:
+        achieved = flops / (avg_ms * 1e-3) / 1e12
+        out = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK[cbytes], "unit": "TFLOP/s"}
+    else:
+        achieved = nbytes / (avg_ms * 1e-3) / 1e9
+        out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+    out["frac"] = out["achieved"] / out["peak"]
+    out["traffic"] = None
+    out.update({"kernel": dominant, "avg_launch_ms": avg_ms, "mean_columns_per_launch": cols,
+                "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
+                "flop_per_byte": intensity})
+    return out
+
+
+def cpu_baseline(wl, m, uinc):
+    """The float64 oracle on the machine's host cores: its setup (not timed into
+    the value, like the GPU's), then one full FGMRES solve of the first
+    incident wave of the batch at the full grid."""
     cores = len(os.sched_getaffinity(0))
     os.environ.setdefault("OMP_NUM_THREADS", str(cores))
     try:
@@ -82,44 +132,33 @@ def cpu_baseline(wl, m, uinc, iters_mean, n_steps):
         threadpoolctl.threadpool_limits(cores)
     except Exception:
         pass
-    import numpy as np
     import oracle
     t0 = time.perf_counter()
     s = oracle.OracleSolver(2, wl.n, wl.omega, m, wl.pml_width, wl.layer_thickness, workers=cores)
     t_setup = time.perf_counter() - t0
-    g = s.op.rhs_incident(uinc[0])
-    v = g / np.linalg.norm(g)
     t0 = time.perf_counter()
-    V = [v]
-    for j in range(n_steps):
-        z = s.precondition(V[-1])
-        w = s.op.apply_A(z)
-        for vk in V:
-            w = w - np.vdot(vk, w) * vk
-        V.append(w / np.linalg.norm(w))
-    t_step = (time.perf_counter() - t0) / n_steps
-    t_solve = iters_mean * t_step
+    res = s.solve_incident(uinc[:1], tol=wl.tol)[0]
+    t_solve = time.perf_counter() - t0
+    iters = res.iterations
     return {
         "value": wl.n ** 2 / t_solve,
         "unit": "unknowns*RHS/s",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"{n_steps} Arnoldi step(s) of the float64 oracle (Algorithm-2 sweep with SuperLU slice "
-                   f"factors, scipy FFT operator, MGS) at {wl.n}^2 on 1 right-hand side, "
-                   f"{t_step:.2f} s each, scaled by the mean iteration count {iters_mean:.2f}; "
-                   f"oracle setup {t_setup:.1f} s excluded like the GPU setup; SuperLU single-threaded, "
-                   f"FFT and BLAS on {cores} threads"),
+        "sample": (f"1 of the {wl.nrhs} right-hand sides (theta=0), full {wl.n}^2 grid, solved to {wl.tol} by the "
+                   f"float64 oracle (FGMRES, Algorithm-2 sweep with SuperLU slice factors, scipy FFT operator) in "
+                   f"{t_solve:.1f} s, {iters} iterations; oracle setup {t_setup:.1f} s excluded like the GPU "
+                   f"setup; SuperLU single-threaded, FFT and BLAS on {cores} threads"),
     }
 
 
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the natural shard, "
-              "incident directions across GPUs, is described in DESIGN.md). Run with --gpus 1.",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path (its natural shard "
+              "would be the incident directions across GPUs). Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
-    import numpy as np
+    import dataclasses
     import torch
     import workloads
     from paper_1705_09443_amd import LSSolver
@@ -132,7 +171,6 @@ def main():
         wl2 = wl2.scaled(args.n)
         wl1 = wl1.scaled(args.n)
     if args.nrhs:
-        import dataclasses
         wl2 = dataclasses.replace(wl2, nrhs=args.nrhs)
     m = wl2.medium_array()
     md = torch.as_tensor(m, device=dev)
@@ -149,7 +187,8 @@ def main():
     print(f"[bench] mixed setup {setup_mixed:.2f} s (n={n}, slices={mixed.nslices})", file=sys.stderr, flush=True)
     for i in range(args.warmup):
         u, info = mixed.solve(uinc2, "incident", wl2.tol)
-        print(f"[bench] warmup {i}: iterations {[x.iterations for x in info][:8]}...", file=sys.stderr, flush=True)
+        print(f"[bench] warmup {i}: iterations {sorted(set(x.iterations for x in info))}", file=sys.stderr,
+              flush=True)
     torch.cuda.synchronize()
     mixed.profile(True)
     t0 = time.perf_counter()
@@ -163,29 +202,9 @@ def main():
     iters = [x.iterations for x in info]
     assert all(x.converged and x.rel_residual <= wl2.tol for x in info), "a right-hand side did not converge"
     value = wl2.nrhs * N / t_mixed
-
-    # roofline of the dominant kernel
-    dominant = max(prof, key=lambda k: prof[k][1])
-    launches, total_ms = prof[dominant]
-    avg_ms = total_ms / launches
-    applies = sum(iters) / args.steps if False else None
-    # batch size per sweep launch varies as right-hand sides finish; use the mean
-    P = 1
-    while P < 2 * (n + 1):
-        P <<= 1
-    n_apply_rhs = sum(iters)  # right-hand-side applies per solve
-    if dominant == "sweep":
-        mean_batch = n_apply_rhs / (launches / args.steps)
-        traffic_alg = sweep_bytes(mixed, mean_batch, 8)
-    elif dominant == "fft_convolve":
-        mean_batch = (n_apply_rhs + wl2.nrhs) / (launches / args.steps)
-        traffic_alg = fft_bytes(n, P, 8, mean_batch)
-    else:
-        mean_batch = n_apply_rhs / (launches / args.steps)
-        traffic_alg = 2 * mean_batch * (mixed.L ** 2) * 8
-    achieved = traffic_alg / (avg_ms * 1e-3) / 1e9
-    kernels = {k: {"launches": v[0], "avg_ms": v[1] / v[0], "share": v[1] / (t_mixed * 1e3 * args.steps)}
-               for k, v in prof.items()}
+    roof = roofline(mixed, prof, 8, n)
+    kernels = {k: {"launches": v[0], "avg_ms": v[1] / v[0], "columns_per_launch": v[2] / v[0],
+                   "share_of_step": v[1] / (t_mixed * 1e3 * args.steps)} for k, v in prof.items()}
 
     out = {
         "metric": METRIC,
@@ -198,19 +217,18 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "c64 applies in a c128 (f64) Krylov loop",
+        "dtype": "c64 applies (f32) in a c128 (f64) FGMRES loop",
         "data": "synthetic: seeded Gaussian-bump medium and plane waves",
-        "config": {"workload": (f"2D {n}^2, 32 Gaussian bumps (seed 0), {wl2.nrhs} plane waves, mixed precision, "
-                                f"b={wl2.pml_width}, w={wl2.layer_thickness}, restart {wl2.restart}, tol {wl2.tol}"),
+        "config": {"workload": (f"2D {n}^2, omega=2pi*{wl2.ppw_omega:g}, 32 Gaussian bumps (seed 0), {wl2.nrhs} "
+                                f"plane waves theta_j=2pi j/{wl2.nrhs}, mixed precision, b={wl2.pml_width}, "
+                                f"w={wl2.layer_thickness}, restart {wl2.restart}, tol {wl2.tol}"),
                    "n": n, "nrhs": wl2.nrhs, "omega": wl2.omega, "precision": "mixed"},
         "iterations": {"min": min(iters), "max": max(iters), "mean": sum(iters) / len(iters)},
         "setup_s": {"mixed": setup_mixed},
         "kernels": kernels,
-        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": achieved, "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "algorithmic_bytes_per_launch": traffic_alg, "avg_launch_ms": avg_ms,
-                     "mean_rhs_per_launch": mean_batch},
+        "roofline": roof,
     }
+    mixed.close()
     del mixed
 
     # ---- plain float64, one wave ----
@@ -221,22 +239,25 @@ def main():
         torch.cuda.synchronize()
         setup_f64 = time.perf_counter() - t0
         print(f"[bench] fp64 setup {setup_f64:.2f} s", file=sys.stderr, flush=True)
+        u1, info1 = f64.solve(uinc1, "incident", wl1.tol)  # warm-up (graph capture)
+        torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i in range(args.fp64_steps):
             u1, info1 = f64.solve(uinc1, "incident", wl1.tol)
-            print(f"[bench] fp64 step {i} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t_f64 = (time.perf_counter() - t0) / args.fp64_steps
+        print(f"[bench] fp64 solve {t_f64 * 1e3:.1f} ms", file=sys.stderr, flush=True)
         v64 = wl1.nrhs * N / t_f64
         out["fp64"] = {"value": v64, "ms_per_step": t_f64 * 1e3, "iterations": info1[0].iterations,
-                       "setup_s": setup_f64, "nrhs": wl1.nrhs}
+                       "rel_residual": info1[0].rel_residual, "setup_s": setup_f64, "nrhs": wl1.nrhs}
         out["ratio_vs_fp64"] = value / v64
+        f64.close()
         del f64
 
     # ---- CPU oracle on a bounded sample ----
     if not args.no_cpu:
         print("[bench] cpu oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl2, m, wl2.incident(), sum(iters) / len(iters), args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(wl2, m, wl2.incident())
     print(json.dumps(out), flush=True)
 
 

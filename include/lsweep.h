@@ -193,9 +193,11 @@ ls_status ls_get_sample_map(const ls_handle* h, int* kmap_host);
 /* ---- Kernel timing (HIP events recorded on the handle's stream) ---- */
 
 typedef struct {
-  char name[32];     /* "sweep", "fft_convolve", "stencil_Q", "extract", "factor" */
-  int launches;      /* launches recorded since profiling was enabled */
-  double total_ms;   /* summed event-to-event durations */
+  char name[32];      /* "fft_convolve", "stencil_Q", "slice_solves", "interface",
+                         "extract", "sweep" (sequential schedule) */
+  int launches;       /* launches recorded since profiling was enabled */
+  double total_ms;    /* summed event-to-event durations */
+  long long columns;  /* right-hand-side columns processed, summed over launches */
 } ls_kernel_time;
 
 /* enable = 1: clear and start recording events around every kernel launch of

@@ -179,11 +179,12 @@ class LSSolver:
         _lib.check(self._lib.ls_profile(self._h, 1 if enable else 0), "ls_profile")
 
     def profile_read(self):
-        """{kind: (launches, total_ms)} of the recorded launches."""
+        """{kind: (launches, total_ms, columns)} of the recorded launches; columns
+        is the number of right-hand-side columns they processed in total."""
         out = (_lib.LsKernelTime * 16)()
         cnt = _lib.c_int()
         _lib.check(self._lib.ls_profile_read(self._h, out, 16, ctypes_byref(cnt)), "ls_profile_read")
-        return {out[i].name.decode(): (out[i].launches, out[i].total_ms) for i in range(cnt.value)}
+        return {out[i].name.decode(): (out[i].launches, out[i].total_ms, out[i].columns) for i in range(cnt.value)}
 
     # -- setup tables -------------------------------------------------------
     def stencils(self):

@@ -48,7 +48,8 @@ class LsSetupInfo(ctypes.Structure):
 
 
 class LsKernelTime(ctypes.Structure):
-    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int), ("total_ms", c_double)]
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", c_int), ("total_ms", c_double),
+                ("columns", ctypes.c_longlong)]
 
 
 class LsError(RuntimeError):

@@ -77,12 +77,10 @@ struct ls_handle {
   // tables
   DBuf m, m32, khat, khat32, tw, tw32, alpha, beta, gglob, gaux, kmap;
   DBuf s_lo, s_hi, s_first, s_t, fs_off, fg_off, FS, FG, Hm, Hp, status;
-  // interface maps M_k, P_k, N_k ([nslices][L][L]) and runs of slices with equal t class
+  // interface maps M_k, P_k, N_k ([nslices][L][L])
   DBuf IM, IP, IN;
-  struct Run {
-    int k0, count, tmax, fstride;  // slices [k0, k0+count): line-count class and factor stride
-  };
-  std::vector<Run> runs;
+  // per slice on the host: line count t and forward factor stride
+  std::vector<int> t_host, fstride_host;
   // workspaces
   int cap = 0;  // right-hand sides the workspaces hold
   DBuf fftw64, fftw32, fext, uext, yscr, vin, zout, aout, lam, mu, sscr;
@@ -102,6 +100,7 @@ struct ls_handle {
   bool profiling = false;
   struct Rec {
     int kind;
+    int cols;  // right-hand-side columns the launch processed
     hipEvent_t a, b;
   };
   std::vector<Rec> recs;
@@ -164,9 +163,9 @@ hipEvent_t take_event(ls_handle* h) {
 // Brackets one launch with events on the handle's stream when profiling.
 struct Timed {
   ls_handle* h;
-  int kind;
+  int kind, cols;
   hipEvent_t a = nullptr;
-  Timed(ls_handle* hh, int k) : h(hh), kind(k) {
+  Timed(ls_handle* hh, int k, int c) : h(hh), kind(k), cols(c) {
     if (h->profiling) {
       a = take_event(h);
       (void)hipEventRecord(a, h->st);
@@ -176,7 +175,7 @@ struct Timed {
     if (a) {
       hipEvent_t b = take_event(h);
       (void)hipEventRecord(b, h->st);
-      h->recs.push_back({kind, a, b});
+      h->recs.push_back({kind, cols, a, b});
     }
   }
 };
@@ -267,7 +266,7 @@ ls_status upload(const ls_handle* h, DBuf& dst, const std::vector<X>& src) {
 // ---- the applies, on contiguous batches ------------------------------------
 template <typename T>
 ls_status apply_A(ls_handle* h, const C<T>* x, int nb, C<T>* y) {
-  Timed tm(h, kKFft);
+  Timed tm(h, kKFft, nb);
   LSW_HIP_TRY(launch_convolve<T>(x, Prec<T>::m(h), h->n, nb, Prec<T>::khat(h), Prec<T>::tw(h), (T)1,
                                  (T)(h->omega * h->omega), Prec<T>::fftw(h), y, h->st));
   return LS_OK;
@@ -286,24 +285,26 @@ SliceSolveArgs<T> slice_args(ls_handle* h) {
   return a;
 }
 
-// All slices of [k0, k1) solved at once, run by run (one launch per run of
-// slices with equal line-count class and factor stride), Wmax right-hand
-// sides (waves) per workgroup at most, fewer if the LDS would not fit.
+// All slices of [k0, k1) solved in one launch, Wmax right-hand sides (waves)
+// per workgroup at most, fewer if the LDS would not fit.
 template <typename T>
 ls_status solve_slices(ls_handle* h, SliceSolveArgs<T> a, int k0, int k1, int Wmax) {
-  for (const auto& run : h->runs) {
-    const int b0 = std::max(k0, run.k0), b1 = std::min(k1, run.k0 + run.count);
-    if (b0 >= b1) continue;
-    a.slice0 = b0;
-    a.stage = slice_stage_elems<T>(run.tmax, run.fstride);
-    int W = Wmax;
-    while (W > 1 && slice_lds<T>(run.tmax, a.stage, W) > 163840) W = W == 8 ? 4 : 1;
-    if (slice_lds<T>(run.tmax, a.stage, W) > 163840) {
-      set_error("slice subproblem too large for the LDS of one workgroup");
-      return LS_E_INVALID;
-    }
-    LSW_HIP_TRY(launch_slice_solves<T>(a, b1 - b0, run.tmax, W, (a.nrhs + W - 1) / W, h->st));
+  if (k0 >= k1) return LS_OK;
+  int f16 = 0, f32 = 0;
+  for (int k = k0; k < k1; ++k) {
+    int& f = h->t_host[k] > 16 ? f32 : f16;
+    f = std::max(f, h->fstride_host[k]);
   }
+  const bool big = f32 > 0;
+  a.slice0 = k0;
+  a.stage = std::max(f16 ? slice_stage_elems<T>(16, f16) : 0, big ? slice_stage_elems<T>(32, f32) : 0);
+  int W = Wmax;
+  while (W > 1 && slice_lds<T>(big, a.stage, W) > 163840) W = W == 8 ? 4 : 1;
+  if (slice_lds<T>(big, a.stage, W) > 163840) {
+    set_error("slice subproblem too large for the LDS of one workgroup");
+    return LS_E_INVALID;
+  }
+  LSW_HIP_TRY(launch_slice_solves<T>(a, k1 - k0, big, W, (a.nrhs + W - 1) / W, h->st));
   return LS_OK;
 }
 
@@ -314,11 +315,11 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
   C<T>* f = h->fext.as<C<T>>();
   C<T>* u = h->uext.as<C<T>>();
   {
-    Timed tm(h, kKQ);
+    Timed tm(h, kKQ, nb);
     LSW_HIP_TRY(launch_apply_Q<T>(S, r, nb, f, h->st));
   }
   if (h->opt.sweep_schedule == LS_SWEEP_SEQUENTIAL) {
-    Timed tm(h, kKSweep);
+    Timed tm(h, kKSweep, nb);
     LSW_HIP_TRY(launch_sweep<T>(h->slices(), h->L, h->b, h->FS.as<C<T>>(), h->FG.as<C<T>>(), h->Hm.as<C<T>>(),
                                 h->Hp.as<C<T>>(), f, u, h->yscr.as<C<T>>(), nb, kSweepFull, 0, h->st));
   } else {
@@ -331,7 +332,7 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
     a.yscr = h->sscr.as<C<T>>();
     if (nl > 1) {
       // phase A: boundary lines of T_k f_k for every slice
-      Timed tm(h, kKSlices);
+      Timed tm(h, kKSlices, nb);
       a.src_kind = kSrcGrid;
       a.src = f;
       a.dst_kind = kDstLines;
@@ -345,7 +346,7 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
     }
     if (nl > 1) {
       // interface recurrences: 2(l-2)+2 dependent launches, captured once per batch size
-      Timed tm(h, kKIface);
+      Timed tm(h, kKIface, nb);
       const std::pair<int, int> key(nb, (int)sizeof(T));
       auto it = h->graphs.find(key);
       if (it == h->graphs.end()) {
@@ -376,7 +377,7 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
     }
     {
       // phase C: every slice's field from its coupled right-hand side
-      Timed tm(h, kKSlices);
+      Timed tm(h, kKSlices, nb);
       a.src_kind = kSrcGrid;
       a.src = f;
       a.dst_kind = kDstGrid;
@@ -387,7 +388,7 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
     }
   }
   {
-    Timed tm(h, kKExtract);
+    Timed tm(h, kKExtract, nb);
     LSW_HIP_TRY(launch_extract<T>(h->n, h->b, u, nb, z, h->st));
   }
   return LS_OK;
@@ -868,16 +869,9 @@ ls_status device_setup(ls_handle* h, const double* m_dev) {
     fs_tot += (size_t)L * factor_stride(p.t, p.hi - p.lo + 1);
     fg_tot += (size_t)L * factor_stride(p.t, 0);
   }
-  h->runs.clear();
-  for (int k = 0; k < nl; ++k) {
-    const int cls = t[k] > 16 ? 32 : 16;
-    const int fstride = factor_stride(t[k], hi[k] - lo[k] + 1);
-    auto& R = h->runs;
-    if (!R.empty() && R.back().tmax == cls && R.back().fstride == fstride && R.back().k0 + R.back().count == k)
-      R.back().count += 1;
-    else
-      R.push_back({k, 1, cls, fstride});
-  }
+  h->t_host = t;
+  h->fstride_host.assign(nl, 0);
+  for (int k = 0; k < nl; ++k) h->fstride_host[k] = factor_stride(t[k], hi[k] - lo[k] + 1);
   LSW_ALLOC(h->s_lo, nl * sizeof(int));
   LSW_ALLOC(h->s_hi, nl * sizeof(int));
   LSW_ALLOC(h->s_first, nl * sizeof(int));
@@ -1289,12 +1283,14 @@ ls_status ls_profile_read(ls_handle* h, ls_kernel_time* out, int max, int* count
   }
   int launches[kKNumKinds] = {};
   double ms[kKNumKinds] = {};
+  long long cols[kKNumKinds] = {};
   for (auto& r : h->recs) {
     LSW_HIP_TRY(hipEventSynchronize(r.b));
     float t = 0.f;
     LSW_HIP_TRY(hipEventElapsedTime(&t, r.a, r.b));
     launches[r.kind] += 1;
     ms[r.kind] += t;
+    cols[r.kind] += r.cols;
   }
   int c = 0;
   for (int k = 0; k < kKNumKinds && c < max; ++k) {
@@ -1302,6 +1298,7 @@ ls_status ls_profile_read(ls_handle* h, ls_kernel_time* out, int max, int* count
     std::snprintf(out[c].name, sizeof out[c].name, "%s", kKindNames[k]);
     out[c].launches = launches[k];
     out[c].total_ms = ms[k];
+    out[c].columns = cols[k];
     ++c;
   }
   *count = c;

@@ -75,8 +75,18 @@ constexpr size_t slice_lds_bytes(size_t SB) {
   return (2 * SB + (size_t)W * (4 * kDepth<TP> * TP + 2 * TP)) * sizeof(C<T>);
 }
 
+// Wait for every outstanding global load and store of the wave. Issued once,
+// outside any branch, so that the compiler knows at the loop head that no
+// load is still in flight (a wait it places inside a branch that may be
+// skipped would make it wait again there, on stores as well).
+__device__ __attribute__((always_inline)) inline void wait_vm_all() {
+  __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0), expcnt and lgkmcnt unconstrained
+}
+
 // Chunk staging through registers: load count values (this thread's share)
 // while the previous chunk is in use, store them to LDS when it is done.
+// Loads are unconditional (clamped to element 0, which every caller owns) so
+// no wait ends up inside a branch.
 template <typename T, int NREG>
 struct Stager {
   T re[NREG], im[NREG];
@@ -84,12 +94,13 @@ struct Stager {
 #pragma unroll
     for (int q = 0; q < NREG; ++q) {
       const int e = tid + q * nt;
-      const C<T> v = e < count ? g[e] : mk<T>(0, 0);
+      const C<T> v = g[e < count ? e : 0];
       re[q] = v.x;
       im[q] = v.y;
     }
   }
   __device__ __attribute__((always_inline)) inline void store(C<T>* l, int count, int tid, int nt) {
+    wait_vm_all();
 #pragma unroll
     for (int q = 0; q < NREG; ++q) {
       const int e = tid + q * nt;
@@ -105,7 +116,8 @@ struct Stager {
 // passes the t-vector through the wave's own LDS row (LDS operations of a
 // wave complete in order, so no barrier per step).
 template <typename T, int TP, int W>
-__global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSolveArgs<T> A) {
+__device__ __attribute__((always_inline)) inline void slice_body(const SliceSolveArgs<T>& A, int k, int sl,
+                                                                 int group, int ngroups) {
   constexpr int NT = slice_threads<T, W>();
   constexpr int CB = 4;  // columns per lane loaded and used together
   constexpr int S = TP == 16 ? 4 : 2;
@@ -119,8 +131,7 @@ __global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSo
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const bool computes = wv < W;  // waves beyond W only help staging
   const int a = lane / S, cq = lane % S;
-  const int k = A.slice0 + blockIdx.x;
-  const int rr = blockIdx.y * W + wv;
+  const int rr = group * W + wv;
   const bool rvalid = computes && rr < A.nrhs;
   const int L = A.L, b = A.b;
   const int lo = A.P.lo[k], hi = A.P.hi[k], first = A.P.first[k], t = A.P.t[k];
@@ -140,7 +151,7 @@ __global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSo
   C<T>* rst = wreg;                                      // [2][D][TP] right-hand sides
   C<T>* yst = wreg + 2 * D * TP;                         // [2][D][TP] forward results
   C<T>* yb = wreg + 4 * D * TP;                          // [TP] exchange row
-  C<T>* yg = A.yscr + (((size_t)blockIdx.x * gridDim.y + blockIdx.y) * W + (computes ? wv : 0)) * (size_t)L * TP;
+  C<T>* yg = A.yscr + (((size_t)sl * ngroups + group) * W + (computes ? wv : 0)) * (size_t)L * 32;
   const int tid = threadIdx.x;
   Stager<T, NSTAGE> stg;
   Stager<T, NR> ystg;
@@ -153,21 +164,26 @@ __global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSo
       const int e = lane + q * 64;
       const int jj = e % D, cl = e / D;
       const int j = c * D + jj;
-      C<T> v = mk<T>(0, 0);
-      if (rvalid && cl < tw && j < L) {
-        if (A.src_kind == kSrcGrid) {
-          v = A.src[((size_t)rr * L + lo + cl + b) * L + j];
-        } else if (A.src_kind == kSrcSlice) {
-          v = A.src[((size_t)rr * tw + cl) * L + j];
-        } else if (cl == unit_c) {
-          const int dj = col - j;
-          if (dj >= -1 && dj <= 1) v = hrow[((size_t)k * L + j) * 3 + dj + 1];
-        }
+      bool ok = rvalid && cl < tw && j < L;
+      const C<T>* base = A.src;
+      size_t off;
+      if (A.src_kind == kSrcGrid) {
+        off = ((size_t)rr * L + lo + cl + b) * L + j;
+      } else if (A.src_kind == kSrcSlice) {
+        off = ((size_t)rr * tw + cl) * L + j;
+      } else {
+        const int dj = col - j;
+        ok = ok && cl == unit_c && dj >= -1 && dj <= 1;
+        base = hrow;
+        off = ((size_t)k * L + j) * 3 + dj + 1;
       }
-      rreg[q] = v;
+      // one unconditional load per element (element 0 when masked)
+      const C<T> v = base[ok ? off : 0];
+      rreg[q] = ok ? v : mk<T>(0, 0);
     }
   };
   auto store_rhs = [&](int buf) {
+    wait_vm_all();
 #pragma unroll
     for (int q = 0; q < NR; ++q) {
       const int e = lane + q * 64;
@@ -198,11 +214,12 @@ __global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSo
   for (int c = 0; c < nchunks; ++c) {
     const int buf = c & 1;
     const int j1 = (c + 1) * D;
-    const int cnt1 = c + 1 < nchunks ? (L - j1 < D ? L - j1 : D) * fstride : 0;
-    if (c + 1 < nchunks) {
-      stg.load(fs + (size_t)j1 * fstride, cnt1, tid, NT);
-      if (computes) load_rhs(c + 1);
-    }
+    const bool more = c + 1 < nchunks;
+    const int cnt1 = more ? (L - j1 < D ? L - j1 : D) * fstride : 0;
+    // the prefetch and its LDS store run on every chunk (nothing is copied
+    // after the last): straight-line code keeps the compiler's wait analysis exact
+    stg.load(fs + (more ? (size_t)j1 * fstride : 0), cnt1, tid, NT);
+    if (computes) load_rhs(c + 1);
     const C<T>* F = stage + buf * SB;
     const C<T>* RB = rst + buf * D * TP;
     const int jend = (L - c * D < D) ? L - c * D : D;
@@ -241,16 +258,23 @@ __global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSo
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       if (cq == 0 && arow) {
         yb[a] = acc;
-        yg[(size_t)j * TP + a] = acc;
+        yst[buf * D * TP + jj * TP + a] = acc;
       }
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
       ylast = acc;
     }
-    if (c + 1 < nchunks) {
-      lds_barrier();  // every wave is done with buffer buf ^ 1's previous contents
-      stg.store(stage + (buf ^ 1) * SB, cnt1, tid, NT);
-      if (computes) store_rhs(buf ^ 1);
-      lds_barrier();
+    lds_barrier();  // every wave is done with buffer buf ^ 1's previous contents
+    stg.store(stage + (buf ^ 1) * SB, cnt1, tid, NT);
+    if (computes) store_rhs(buf ^ 1);
+    lds_barrier();
+    // the chunk's results go out after the loads above were waited for, so the
+    // next chunk's wait covers these stores too, one chunk after they issued
+    if (computes) {
+#pragma unroll
+      for (int q = 0; q < NR; ++q) {
+        const int e = lane + q * 64;
+        if (e < jend * TP) yg[(size_t)c * D * TP + e] = yst[buf * D * TP + e];
+      }
     }
   }
   // the forward results in yg are read back below
@@ -271,28 +295,63 @@ __global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSo
     }
   };
   emit(L - 1, ylast);  // x_{L-1} = y_{L-1}; it is also what yb holds
-  const int nbch = (L - 1 + D - 1) / D;  // chunks of j in [c D, c D + D) cover 0..L-2
-  auto load_bwd = [&](int c) {
+  // outputs of a backward chunk wait in the wave's (now unused) right-hand side
+  // buffer and leave together, consecutive j per lane group
+  C<T>* xo = rst;
+  auto flush_bwd = [&](int c, int buf) {
+    if (!rvalid) return;
     const int j0 = c * D;
     const int n = (L - 1 - j0 < D ? L - 1 - j0 : D);
+    if (A.dst_kind == kDstLines) {
+      const size_t ci = unit_src ? (size_t)col : (size_t)rr;
+      if (lane < 2 * D) {
+        const int jj = lane % D;
+        const bool isE = lane < D;
+        C<T>* dl = isE ? A.dstE : A.dstF;
+        const int ar = isE ? t - 1 : naux;
+        if (dl && jj < n) dl[k * A.sk + ci * A.sr + (size_t)(j0 + jj) * A.sj] = xo[buf * D * TP + jj * TP + ar];
+      }
+      return;
+    }
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+      const int e = lane + q * 64;
+      const int jj = e % D, ar = e / D;
+      if (jj < n && ar >= naux && ar < t) {
+        const C<T> x = xo[buf * D * TP + jj * TP + ar];
+        if (A.dst_kind == kDstGrid)
+          A.dst[((size_t)rr * L + first + ar + b) * L + j0 + jj] = x;
+        else
+          A.dst[((size_t)rr * tw + ar - naux) * L + j0 + jj] = x;
+      }
+    }
+  };
+  const int nbch = (L - 1 + D - 1) / D;  // chunks of j in [c D, c D + D) cover 0..L-2
+  // chunk c of the backward pass; on == false copies nothing (the last chunk)
+  auto bwd_count = [&](int c, bool on) {
+    const int j0 = c * D;
+    return on ? (L - 1 - j0 < D ? L - 1 - j0 : D) : 0;
+  };
+  auto load_bwd = [&](int c, bool on) {
+    const int j0 = c * D, n = bwd_count(c, on);
     stg.load(fg + (size_t)j0 * gstride, n * gstride, tid, NT);
     if (computes) ystg.load(yg + (size_t)j0 * TP, n * TP, lane, 64);  // this wave's own rows
   };
-  auto store_bwd = [&](int c, int buf) {
-    const int j0 = c * D;
-    const int n = (L - 1 - j0 < D ? L - 1 - j0 : D);
+  auto store_bwd = [&](int c, int buf, bool on) {
+    const int n = bwd_count(c, on);
     stg.store(stage + buf * SB, n * gstride, tid, NT);
     if (computes) ystg.store(yst + buf * D * TP, n * TP, lane, 64);
   };
   if (nbch > 0) {
-    load_bwd(nbch - 1);
-    store_bwd(nbch - 1, 0);
+    load_bwd(nbch - 1, true);
+    store_bwd(nbch - 1, 0, true);
     lds_barrier();
   }
   for (int ci = 0; ci < nbch; ++ci) {
     const int c = nbch - 1 - ci;
     const int buf = ci & 1;
-    if (ci + 1 < nbch) load_bwd(c - 1);
+    const bool more = ci + 1 < nbch;
+    load_bwd(more ? c - 1 : 0, more);
     const C<T>* G = stage + buf * SB;
     const C<T>* Y = yst + buf * D * TP;
     for (int jj = D - 1; jj >= 0 && computes; --jj) {
@@ -323,16 +382,32 @@ __global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSo
       C<T> x = mk<T>(0, 0);
       if (arow) x = csub<T>(Y[jj * TP + a], acc);
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      if (cq == 0 && arow) yb[a] = x;
+      if (cq == 0 && arow) {
+        yb[a] = x;
+        xo[buf * D * TP + jj * TP + a] = x;
+      }
       __atomic_signal_fence(__ATOMIC_SEQ_CST);
-      emit(j, x);
     }
-    if (ci + 1 < nbch) {
-      lds_barrier();
-      store_bwd(c - 1, buf ^ 1);
-      lds_barrier();
-    }
+    lds_barrier();
+    store_bwd(more ? c - 1 : 0, buf ^ 1, more);
+    lds_barrier();
+    if (computes) flush_bwd(c, buf);
   }
+}
+
+// One launch covers a range of slices: blockIdx.x is the group of W
+// right-hand sides, blockIdx.y the slice, the last slice of the range first
+// (it is the longest: the far PML makes it the only 32-line class), so that it
+// starts before the others rather than after them. BIG: the range holds a
+// 32-line slice.
+template <typename T, int W, bool BIG>
+__global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSolveArgs<T> A) {
+  const int sl = gridDim.y - 1 - blockIdx.y;
+  const int k = A.slice0 + sl;
+  if (BIG && A.P.t[k] > 16)
+    slice_body<T, 32, W>(A, k, sl, blockIdx.x, gridDim.x);
+  else
+    slice_body<T, 16, W>(A, k, sl, blockIdx.x, gridDim.x);
 }
 
 // ---- interface recurrences: y = add - M x for a batch of right-hand sides --
@@ -472,12 +547,18 @@ hipError_t allow_lds(K kernel, size_t bytes) {
                              (int)bytes);
 }
 
-template <typename T, int TP, int W>
+template <typename T, int W>
+size_t lds_for(bool big, size_t stage) {
+  const size_t s16 = slice_lds_bytes<T, 16, W>(stage), s32 = slice_lds_bytes<T, 32, W>(stage);
+  return big && s32 > s16 ? s32 : s16;
+}
+
+template <typename T, int W, bool BIG>
 hipError_t launch_one(const SliceSolveArgs<T>& a, int nslices, int ngroups, hipStream_t st) {
-  const size_t bytes = slice_lds_bytes<T, TP, W>(a.stage);
-  hipError_t e = allow_lds(k_slice_solve<T, TP, W>, bytes);
+  const size_t bytes = lds_for<T, W>(BIG, a.stage);
+  hipError_t e = allow_lds(k_slice_solve<T, W, BIG>, bytes);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_slice_solve<T, TP, W>), dim3(nslices, ngroups), dim3(slice_threads<T, W>()), bytes, st, a);
+  hipLaunchKernelGGL((k_slice_solve<T, W, BIG>), dim3(ngroups, nslices), dim3(slice_threads<T, W>()), bytes, st, a);
   return hipGetLastError();
 }
 
@@ -503,31 +584,29 @@ template size_t slice_stage_elems<double>(int, int);
 template size_t slice_stage_elems<float>(int, int);
 
 template <typename T>
-size_t slice_lds(int tmax, size_t stage, int W) {
-  const bool big = tmax > 16;
+size_t slice_lds(bool big, size_t stage, int W) {
   switch (W) {
-    case 1: return big ? slice_lds_bytes<T, 32, 1>(stage) : slice_lds_bytes<T, 16, 1>(stage);
-    case 4: return big ? slice_lds_bytes<T, 32, 4>(stage) : slice_lds_bytes<T, 16, 4>(stage);
-    case 8: return big ? slice_lds_bytes<T, 32, 8>(stage) : slice_lds_bytes<T, 16, 8>(stage);
+    case 1: return lds_for<T, 1>(big, stage);
+    case 4: return lds_for<T, 4>(big, stage);
+    case 8: return lds_for<T, 8>(big, stage);
     default: return 0;
   }
 }
-template size_t slice_lds<double>(int, size_t, int);
-template size_t slice_lds<float>(int, size_t, int);
+template size_t slice_lds<double>(bool, size_t, int);
+template size_t slice_lds<float>(bool, size_t, int);
 
 template <typename T>
-hipError_t launch_slice_solves(const SliceSolveArgs<T>& a, int nslices, int tmax, int W, int ngroups,
+hipError_t launch_slice_solves(const SliceSolveArgs<T>& a, int nslices, bool big, int W, int ngroups,
                                hipStream_t st) {
-  const bool big = tmax > 16;
   switch (W) {
-    case 1: return big ? launch_one<T, 32, 1>(a, nslices, ngroups, st) : launch_one<T, 16, 1>(a, nslices, ngroups, st);
-    case 4: return big ? launch_one<T, 32, 4>(a, nslices, ngroups, st) : launch_one<T, 16, 4>(a, nslices, ngroups, st);
-    case 8: return big ? launch_one<T, 32, 8>(a, nslices, ngroups, st) : launch_one<T, 16, 8>(a, nslices, ngroups, st);
+    case 1: return big ? launch_one<T, 1, true>(a, nslices, ngroups, st) : launch_one<T, 1, false>(a, nslices, ngroups, st);
+    case 4: return big ? launch_one<T, 4, true>(a, nslices, ngroups, st) : launch_one<T, 4, false>(a, nslices, ngroups, st);
+    case 8: return big ? launch_one<T, 8, true>(a, nslices, ngroups, st) : launch_one<T, 8, false>(a, nslices, ngroups, st);
     default: return hipErrorInvalidValue;
   }
 }
-template hipError_t launch_slice_solves<double>(const SliceSolveArgs<double>&, int, int, int, int, hipStream_t);
-template hipError_t launch_slice_solves<float>(const SliceSolveArgs<float>&, int, int, int, int, hipStream_t);
+template hipError_t launch_slice_solves<double>(const SliceSolveArgs<double>&, int, bool, int, int, hipStream_t);
+template hipError_t launch_slice_solves<float>(const SliceSolveArgs<float>&, int, bool, int, int, hipStream_t);
 
 template <typename T>
 hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,

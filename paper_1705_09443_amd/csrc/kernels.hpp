@@ -81,7 +81,7 @@ struct SliceSolveArgs {
   const C<T>* FG;
   const C<T>* Hm;
   const C<T>* Hp;
-  int slice0;      // slice of blockIdx.x = 0
+  int slice0;      // first slice of the launch
   int nrhs;        // right-hand sides (columns) of this launch
   int src_kind;    // SliceSrc
   const C<T>* src; // [nrhs][L][L] (grid) or [nrhs][lines][L] (slice)
@@ -100,13 +100,15 @@ size_t slice_scratch_elems(int L, int W);
 // LDS stage buffer length for slices with at most tmax lines and factor stride fstride_max.
 template <typename T>
 size_t slice_stage_elems(int tmax, int fstride_max);
-// Dynamic LDS bytes of one workgroup (0 for an unsupported W).
+// Dynamic LDS bytes of one workgroup (0 for an unsupported W); big: the
+// launch holds a slice of more than 16 lines.
 template <typename T>
-size_t slice_lds(int tmax, size_t stage, int W);
-// One workgroup per (slice, group of W right-hand sides), one wave per
-// right-hand side; W in {1, 4, 8}; tmax = largest line count (<= 32).
+size_t slice_lds(bool big, size_t stage, int W);
+// One workgroup per (group of W right-hand sides, slice), one wave per
+// right-hand side; W in {1, 4, 8}; slices of up to 32 lines, more than 16
+// only if big.
 template <typename T>
-hipError_t launch_slice_solves(const SliceSolveArgs<T>& a, int nslices, int tmax, int W, int ngroups,
+hipError_t launch_slice_solves(const SliceSolveArgs<T>& a, int nslices, bool big, int W, int ngroups,
                                hipStream_t st);
 // y_k = add_k - M_k x_{k+xoff} for k = kbeg .. kbeg+kcount-1 (in place allowed, y == add)
 template <typename T>
