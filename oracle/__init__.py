@@ -27,13 +27,13 @@ adjoint   gradient of a receiver misfit with respect to m
 solver    end-to-end driver tying the above together
 """
 from .green import green, central_weight, green_table, wrapped_table
-from .lsop import DenseOperator, brute_force_K, dense_A
+from .lsop import DenseOperator, brute_force_K, brute_force_K_at, dense_A
 from .stencils import (neighbourhood, plane_wave_directions, normalise_phase,
                        alpha_beta, sigma_global, pml_stencil, FrequencySamples)
 from .sparse import SparseSystem, Sweep
 from .gmres import fgmres, GmresResult
 from .adjoint import misfit_gradient
-from .solver import OracleSolver
+from .solver import OracleSolver, DEFAULT_PML_C
 
 __all__ = [
     "green", "central_weight", "green_table", "wrapped_table",
@@ -41,5 +41,5 @@ __all__ = [
     "neighbourhood", "plane_wave_directions", "normalise_phase", "alpha_beta",
     "sigma_global", "pml_stencil", "FrequencySamples",
     "SparseSystem", "Sweep", "fgmres", "GmresResult", "misfit_gradient",
-    "OracleSolver",
+    "OracleSolver", "DEFAULT_PML_C", "brute_force_K_at",
 ]

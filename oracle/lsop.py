@@ -51,6 +51,19 @@ def brute_force_K(table: np.ndarray, n: int, d: int, x: np.ndarray) -> np.ndarra
     return (K @ x.reshape(-1)).reshape((n,) * d)
 
 
+def brute_force_K_at(table: np.ndarray, n: int, d: int, x: np.ndarray, points: np.ndarray) -> np.ndarray:
+    """sum_j k_{i-j} x_j at the output points i (array indices, [npoints, d]) by
+    direct summation over all j: the definition, one output at a time, for
+    checking sampled outputs on grids too large for the full O(N^2) product."""
+    out = np.empty(len(points), dtype=np.complex128)
+    for p, i in enumerate(points):
+        # i - j + (n + 1) runs over [i + 2, i + n + 1] as j runs over n-1..0
+        sl = tuple(slice(i[a] + 2, i[a] + n + 2) for a in range(d))
+        block = table[sl][(slice(None, None, -1),) * d]
+        out[p] = np.sum(block * x)
+    return out
+
+
 def dense_A(table: np.ndarray, n: int, d: int, omega: float, m: np.ndarray) -> np.ndarray:
     """The explicit dense matrix I + omega^2 K M (small n only)."""
     idx = np.indices((n,) * d).reshape(d, -1).T

@@ -140,7 +140,9 @@ class Sweep:
     checking the bookkeeping."""
 
     def __init__(self, system: SparseSystem, w: int, m: np.ndarray, exact: bool = False,
-                 samples: FrequencySamples | None = None):
+                 samples: FrequencySamples | None = None, only: list | None = None):
+        """only: factor just these slices (for checking single slice solves on
+        large grids); sweep() and apply() then refuse to run."""
         s = system
         self.s = s
         d, n, b, L = s.d, s.n, s.b, s.L
@@ -155,13 +157,14 @@ class Sweep:
         self.bounds = bounds
         self.samples = samples if samples is not None else FrequencySamples(np.asarray(m), s.omega, n)
         self.exact = exact
-        self.lu = []
-        self.aux_count = []
+        self.lu = [None] * nl
+        self.aux_count = [0] * nl
         self.aux_gamma = {}
-        for k in range(nl):
+        self.complete = only is None
+        for k in (range(nl) if only is None else only):
             A, naux = self._subproblem(k)
-            self.aux_count.append(naux)
-            self.lu.append(spla.splu(A.tocsc()))
+            self.aux_count[k] = naux
+            self.lu[k] = spla.splu(A.tocsc())
         # couplings H_[k,k-1] and H_[k,k+1]
         self.Hm, self.Hp = [None] * nl, [None] * nl
         for k in range(nl):
@@ -260,6 +263,8 @@ class Sweep:
 
     def sweep(self, f: np.ndarray) -> np.ndarray:
         """Algorithm 2, steps 3-8, on the flat extended grid."""
+        if not self.complete:
+            raise RuntimeError("sweep needs every slice factored")
         u = np.zeros_like(f)
         nl = self.nslices
         for k in range(nl):

@@ -259,6 +259,7 @@ class LSSolve(torch.autograd.Function):
     def backward(ctx, grad_u):
         # For a real loss torch passes the conjugate-Wirtinger cotangent; for
         # J = 1/2 sum |R u - d|^2 it is R^T (R u - d), the residual the adjoint takes.
+        # The handle stays open while the graph lives: backward may run more
+        # than once (retain_graph, gradcheck); it is released with ctx.
         grad_m, _ = ctx.solver.adjoint(grad_u.contiguous().to(torch.complex128), ctx.adjoint_tol)
-        ctx.solver.close()
         return grad_m, None, None, None, None, None, None, None

@@ -56,3 +56,17 @@ def test_incident_rhs_is_minus_omega2_K_m_uI():
     ref = -wl.omega ** 2 * brute_force_K(op.table, n, d, m * uinc)
     got = op.rhs_incident(uinc)
     assert np.linalg.norm(got - ref) <= 1e-13 * np.linalg.norm(ref)
+
+
+def test_sampled_direct_sum_equals_full_direct_sum():
+    """brute_force_K_at (one output at a time, for large grids) agrees with the
+    full O(N^2) definition at random points, in 2D and 3D."""
+    from oracle import green_table, brute_force_K, brute_force_K_at
+    for n, d in [(9, 2), (5, 3)]:
+        t = green_table(d, n, 7.0)
+        rng = np.random.default_rng(0)
+        x = rng.standard_normal((n,) * d) + 1j * rng.standard_normal((n,) * d)
+        full = brute_force_K(t, n, d, x)
+        pts = rng.integers(0, n, size=(8, d))
+        s = brute_force_K_at(t, n, d, x, pts)
+        assert np.abs(s - full[tuple(pts.T)]).max() <= 1e-14 * np.abs(full).max()
