@@ -47,6 +47,10 @@ struct DBuf {
     else p = nullptr;
     return e;
   }
+  void swap(DBuf& o) {
+    std::swap(p, o.p);
+    std::swap(bytes, o.bytes);
+  }
   template <typename X>
   X* as() const { return static_cast<X*>(p); }
 };
@@ -326,7 +330,7 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
     const int nl = h->nslices, L = h->L, R = rhs_group(nb);
     C<T>* lam = h->lam.as<C<T>>();
     C<T>* mu = h->mu.as<C<T>>();
-    const size_t LL = (size_t)L * L, vs = (size_t)nb * L;
+    const size_t MS = iface_map_stride<T>(L), vs = (size_t)nb * L;
     SliceSolveArgs<T> a = slice_args<T>(h);
     a.nrhs = nb;
     a.yscr = h->sscr.as<C<T>>();
@@ -358,10 +362,10 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
         LSW_HIP_TRY(hipStreamBeginCapture(h->cst, hipStreamCaptureModeThreadLocal));
         hipError_t ce = hipSuccess;
         for (int k = 1; k <= nl - 2 && ce == hipSuccess; ++k)
-          ce = launch_iface_step<T>(IM, lam, lam, lam, L, nb, k, 1, LL, vs, -1, h->cst);
-        if (ce == hipSuccess) ce = launch_iface_step<T>(IP, mu, lam, mu, L, nb, 1, nl - 1, LL, vs, -1, h->cst);
+          ce = launch_iface_step<T>(IM, lam, lam, lam, L, nb, k, 1, MS, vs, -1, h->cst);
+        if (ce == hipSuccess) ce = launch_iface_step<T>(IP, mu, lam, mu, L, nb, 1, nl - 1, MS, vs, -1, h->cst);
         for (int k = nl - 2; k >= 1 && ce == hipSuccess; --k)
-          ce = launch_iface_step<T>(IN, mu, mu, mu, L, nb, k, 1, LL, vs, +1, h->cst);
+          ce = launch_iface_step<T>(IN, mu, mu, mu, L, nb, k, 1, MS, vs, +1, h->cst);
         if (ce == hipSuccess)
           ce = launch_couple<T>(h->slices(), L, h->b, h->Hm.as<C<T>>(), h->Hp.as<C<T>>(), lam, mu, nb, f, h->cst);
         const hipError_t ee = hipStreamEndCapture(h->cst, &graph);
@@ -435,7 +439,14 @@ ls_status build_interface(ls_handle* h) {
       if (e != LS_OK) return e;
     }
   }
-  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  // re-lay every map set in the operand order of the interface products
+  for (DBuf* Mp : {&h->IM, &h->IP, &h->IN}) {
+    DBuf z;
+    LSW_ALLOC(z, (size_t)nl * iface_map_stride<T>(L) * cs);
+    LSW_HIP_TRY(launch_swizzle_maps<T>(Mp->as<C<T>>(), z.as<C<T>>(), L, nl, h->st));
+    LSW_HIP_TRY(hipStreamSynchronize(h->st));
+    Mp->swap(z);  // the row-major maps are released with z
+  }
   return LS_OK;
 }
 

@@ -27,6 +27,8 @@
 // only and needs no workgroup barrier per step.
 #include "kernels.hpp"
 
+#include <cstdlib>
+
 namespace lsw {
 
 namespace {
@@ -411,103 +413,186 @@ __global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSo
 }
 
 // ---- interface recurrences: y = add - M x for a batch of right-hand sides --
-// M: [L][L] row-major per slice (stride mstride); add, x, y: [nrhs][L] per slice.
-// blockIdx.z selects the slice k = kbeg + z.
+// The L x L maps are stored in the operand order of the matrix-core product:
+// slice k is [row tile r][contraction block b][lane l][4], 16 x 16 complex
+// values per (r, b), zero-padded to whole tiles, with lane l holding row
+// 16 r + l % 16 and the 4 consecutive columns 16 b + 4 (l / 16) + j. One
+// (r, b) block is then one contiguous 64-lane operand load, and the padding
+// removes every bounds test on M. x, add, y: [nrhs][L] per slice.
+__host__ __device__ inline int iface_tiles(int L) { return (L + 15) / 16; }
+
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_iface_gemv(const C<T>* __restrict__ M, const C<T>* add, const C<T>* x,
-                                                    C<T>* y, int L, int nrhs, int kbeg, size_t mstride,
-                                                    size_t vstride, int xoff) {
-  // nrhs <= 4: one wave per output row, lanes over columns, 8 loads in flight per lane
-  constexpr int U = 8;
-  const int k = kbeg + blockIdx.z;
-  const C<T>* Mk = M + (size_t)k * mstride;
+__global__ void k_swizzle_maps(const C<T>* __restrict__ src, C<T>* __restrict__ dst, int L, size_t total) {
+  const size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= total) return;
+  const int nt = iface_tiles(L);
+  const size_t per = (size_t)nt * nt * 256;
+  const size_t k = e / per, rem = e % per;
+  const int r = (int)(rem / ((size_t)nt * 256)), b = (int)((rem / 256) % nt);
+  const int l = (int)((rem / 4) % 64), j = (int)(rem % 4);
+  const int row = 16 * r + (l & 15), col = 16 * b + 4 * (l >> 4) + j;
+  dst[e] = (row < L && col < L) ? src[(k * L + row) * (size_t)L + col] : mk<T>(0, 0);
+}
+
+// At most 4 right-hand sides: a workgroup per 16-row tile, its NW waves
+// taking every NW-th contraction block; each lane accumulates its row's
+// partial dot products over the block's 4 columns it holds, the four lanes of
+// a row then reduce by shuffles and the waves through LDS.
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void k_iface_gemv(const C<T>* __restrict__ MZ, const C<T>* add, const C<T>* x,
+                                                        C<T>* y, int L, int nrhs, int kbeg, size_t mstride,
+                                                        size_t vstride, int xoff) {
+  constexpr int MAXB = 6;  // blocks of one wave in flight at once
+  __shared__ C<T> red[NW][4][16];
+  const int nt = iface_tiles(L);
+  const int r = blockIdx.x, k = kbeg + blockIdx.z;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g4 = lane >> 4;
+  const C<T>* Mr = MZ + (size_t)k * mstride + (size_t)r * nt * 256 + lane * 4;
   const C<T>* xk = x + (size_t)(k + xoff) * vstride;
-  const C<T>* ak = add + (size_t)k * vstride;
-  C<T>* yk = y + (size_t)k * vstride;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int row = blockIdx.x * (kNT / 64) + wave;
-  if (row >= L) return;
   C<T> acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = mk<T>(0, 0);
-  const C<T>* Mr = Mk + (size_t)row * L;
-  for (int c0 = 0; c0 < L; c0 += 64 * U) {
-    C<T> mv[U];
+  for (int b0 = wave; b0 < nt; b0 += NW * MAXB) {
+    C<T> a[MAXB][4];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int c = c0 + u * 64 + lane;
-      mv[u] = c < L ? Mr[c] : mk<T>(0, 0);
+    for (int i = 0; i < MAXB; ++i) {
+      const int b = min(b0 + i * NW, nt - 1);  // clamped: blocks past the end are loaded, not used
+#pragma unroll
+      for (int j = 0; j < 4; ++j) a[i][j] = Mr[(size_t)b * 256 + j];
     }
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      if (q >= nrhs) break;
+    for (int i = 0; i < MAXB; ++i) {
+      const int b = b0 + i * NW;
+      if (b < nt) {
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int c = c0 + u * 64 + lane;
-        if (c < L) acc[q] = cfma<T>(acc[q], mv[u], xk[(size_t)q * L + c]);
+        for (int q = 0; q < 4; ++q) {
+          if (q < nrhs) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+              const int kk = min(16 * b + 4 * g4 + j, L - 1);  // M is 0 there
+              acc[q] = cfma<T>(acc[q], a[i][j], xk[(size_t)q * L + kk]);
+            }
+          }
+        }
       }
     }
   }
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    for (int m = 32; m > 0; m >>= 1) acc[q] = cadd<T>(acc[q], shfl_xor_c<T>(acc[q], m));
-    if (lane == 0 && q < nrhs) yk[(size_t)q * L + row] = csub<T>(ak[(size_t)q * L + row], acc[q]);
+    acc[q] = cadd<T>(acc[q], shfl_xor_c<T>(acc[q], 16));
+    acc[q] = cadd<T>(acc[q], shfl_xor_c<T>(acc[q], 32));
+    if (g4 == 0) red[wave][q][li] = acc[q];
+  }
+  __syncthreads();
+  const int t = threadIdx.x;
+  if (t < 64) {
+    const int q = t >> 4, row = 16 * r + (t & 15);
+    if (q < nrhs && row < L) {
+      C<T> s = red[0][q][t & 15];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) s = cadd<T>(s, red[w][q][t & 15]);
+      const C<T>* ak = add + (size_t)k * vstride;
+      y[(size_t)k * vstride + (size_t)q * L + row] = csub<T>(ak[(size_t)q * L + row], s);
+    }
   }
 }
 
-// nrhs > 4: tiles of 16 rows x 16 right-hand sides, columns staged by CT with
-// the next chunk's loads in flight while the current one is used.
+// More than 4 right-hand sides: the products on the matrix cores. A
+// workgroup owns a 16-row x 16-column (right-hand sides) output tile and
+// splits the contraction over its NW waves; each complex 16x16x4 block is
+// four real MFMAs (Im M negated for the real accumulator). In the j-th MFMA
+// of a block, lane l supplies column 4 (l / 16) + j of M's row l % 16 and the
+// same contraction index of x's column l % 16: the index is permuted the same
+// way in both operands, which leaves the sum unchanged. A wave keeps PF
+// blocks of loads in flight ahead of its MFMAs. Tiles of one row block share
+// M's rows; they go to workgroups with equal id mod 8, i.e. the same XCD.
 template <typename T>
-__global__ __launch_bounds__(kNT) void k_iface_gemm(const C<T>* __restrict__ M, const C<T>* add, const C<T>* x,
-                                                    C<T>* y, int L, int nrhs, int kbeg, size_t mstride,
-                                                    size_t vstride, int xoff) {
-  constexpr int RT = 16, QT = 16, CT = 64;
-  constexpr int PER = RT * CT / kNT;  // loads per thread per chunk and operand
-  __shared__ C<T> Ms[2][RT][CT + 1];
-  __shared__ C<T> Xs[2][QT][CT + 1];
+struct Mfma;
+template <>
+struct Mfma<float> {
+  typedef float v4 __attribute__((ext_vector_type(4)));
+  static __device__ __attribute__((always_inline)) v4 op(float a, float b, v4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  // output element j of lane l is row out_row(l / 16, j), column l % 16
+  static __device__ __attribute__((always_inline)) int out_row(int g, int j) { return 4 * g + j; }
+};
+template <>
+struct Mfma<double> {
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  static __device__ __attribute__((always_inline)) v4 op(double a, double b, v4 c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __attribute__((always_inline)) int out_row(int g, int j) { return 4 * j + g; }
+};
+
+constexpr int kMfmaWaves = 4;
+template <typename T>
+constexpr int kMfmaPrefetch = sizeof(T) == 4 ? 4 : 2;
+
+template <typename T, int NW = kMfmaWaves, int PF = kMfmaPrefetch<T>>
+__global__ __launch_bounds__(64 * NW) void k_iface_mfma(const C<T>* __restrict__ MZ, const C<T>* add,
+                                                        const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
+                                                        size_t mstride, size_t vstride, int xoff, int qtiles) {
+  using V = typename Mfma<T>::v4;
+  __shared__ C<T> red[NW][16][17];
+  const int nt = iface_tiles(L);
+  const int id = blockIdx.x;
+  const int per = 8 * qtiles;  // workgroups per group of 8 row blocks
+  const int r = (id / per) * 8 + id % 8, q = (id % per) / 8;
+  if (r >= nt) return;  // whole workgroup: the grid is rounded up to 8 row blocks
   const int k = kbeg + blockIdx.z;
-  const C<T>* Mk = M + (size_t)k * mstride;
-  const C<T>* xk = x + (size_t)(k + xoff) * vstride;
-  const C<T>* ak = add + (size_t)k * vstride;
-  C<T>* yk = y + (size_t)k * vstride;
-  const int r0 = blockIdx.x * RT, q0 = blockIdx.y * QT;
-  const int ri = threadIdx.x / QT, qi = threadIdx.x % QT;
-  C<T> mreg[PER], xreg[PER];
-  auto load = [&](int c0) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g4 = lane >> 4;
+  const C<T>* Mr = MZ + (size_t)k * mstride + (size_t)r * nt * 256 + lane * 4;
+  const C<T>* Bc = x + (size_t)(k + xoff) * vstride + (size_t)min(q * 16 + li, nrhs - 1) * L;
+  // this wave's contraction blocks, a whole number of prefetch rounds
+  const int nbw = ((nt + NW - 1) / NW + PF - 1) / PF * PF;
+  const int b0 = wave * nbw;
+  V accR = {0, 0, 0, 0}, accI = {0, 0, 0, 0};
+  C<T> a[PF][4], bv[PF][4];
+  // unconditional loads (clamped block and column indices): M is zero past L,
+  // so x's clamped values there multiply zeros
+  auto load = [&](C<T>* ad, C<T>* bd, int b) {
+    const int bc = min(b, nt - 1);
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      const int idx = threadIdx.x + p * kNT;
-      const int rr = idx / CT, cc = idx % CT;
-      mreg[p] = (r0 + rr < L && c0 + cc < L) ? Mk[(size_t)(r0 + rr) * L + c0 + cc] : mk<T>(0, 0);
-      xreg[p] = (q0 + rr < nrhs && c0 + cc < L) ? xk[(size_t)(q0 + rr) * L + c0 + cc] : mk<T>(0, 0);
-    }
-  };
-  auto store = [&](int buf) {
+    for (int j = 0; j < 4; ++j) ad[j] = Mr[(size_t)bc * 256 + j];
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-      const int idx = threadIdx.x + p * kNT;
-      Ms[buf][idx / CT][idx % CT] = mreg[p];
-      Xs[buf][idx / CT][idx % CT] = xreg[p];
-    }
+    for (int j = 0; j < 4; ++j) bd[j] = Bc[min(16 * bc + 4 * g4 + j, L - 1)];
   };
-  C<T> acc = mk<T>(0, 0);
-  load(0);
-  store(0);
-  __syncthreads();
-  int buf = 0;
-  for (int c0 = 0; c0 < L; c0 += CT) {
-    const bool more = c0 + CT < L;
-    if (more) load(c0 + CT);
-#pragma unroll 8
-    for (int cc = 0; cc < CT; ++cc) acc = cfma<T>(acc, Ms[buf][ri][cc], Xs[buf][qi][cc]);
-    if (more) {
-      store(buf ^ 1);
-      __syncthreads();
-      buf ^= 1;
+#pragma unroll
+  for (int s = 0; s < PF; ++s) load(a[s], bv[s], b0 + s);
+  for (int i = 0; i < nbw; i += PF) {
+#pragma unroll
+    for (int s = 0; s < PF; ++s) {
+      if (b0 + i + s < nt) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          accR = Mfma<T>::op(a[s][j].x, bv[s][j].x, accR);
+          accI = Mfma<T>::op(a[s][j].x, bv[s][j].y, accI);
+          accR = Mfma<T>::op(-a[s][j].y, bv[s][j].y, accR);
+          accI = Mfma<T>::op(a[s][j].y, bv[s][j].x, accI);
+        }
+      }
+      load(a[s], bv[s], b0 + i + s + PF);
     }
   }
-  const int row = r0 + ri, q = q0 + qi;
-  if (row < L && q < nrhs) yk[(size_t)q * L + row] = csub<T>(ak[(size_t)q * L + row], acc);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) red[wave][Mfma<T>::out_row(g4, j)][li] = mk<T>(accR[j], accI[j]);
+  __syncthreads();
+  // one output per thread: column t / 16, row t % 16 (consecutive rows of one
+  // right-hand side are contiguous in y)
+  const int t = threadIdx.x;
+  if (t < 256) {
+    const int oc = t >> 4, orow = t & 15;
+    const int R = r * 16 + orow, Q = q * 16 + oc;
+    if (R < L && Q < nrhs) {
+      C<T> sum = red[0][orow][oc];
+#pragma unroll
+      for (int w = 1; w < NW; ++w) sum = cadd<T>(sum, red[w][orow][oc]);
+      const size_t o = (size_t)k * vstride + (size_t)Q * L + R;
+      y[o] = csub<T>(add[o], sum);
+    }
+  }
 }
 
 // f on the first line of D_k -= Hm_k lambda_{k-1}; on its last line -= Hp_k mu_{k+1}.
@@ -609,15 +694,35 @@ template hipError_t launch_slice_solves<double>(const SliceSolveArgs<double>&, i
 template hipError_t launch_slice_solves<float>(const SliceSolveArgs<float>&, int, bool, int, int, hipStream_t);
 
 template <typename T>
+size_t iface_map_stride(int L) {
+  const size_t nt = iface_tiles(L);
+  return nt * nt * 256;
+}
+template size_t iface_map_stride<double>(int);
+template size_t iface_map_stride<float>(int);
+
+template <typename T>
+hipError_t launch_swizzle_maps(const C<T>* src, C<T>* dst, int L, int nslices, hipStream_t st) {
+  const size_t total = (size_t)nslices * iface_map_stride<T>(L);
+  hipLaunchKernelGGL(k_swizzle_maps<T>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, src, dst, L, total);
+  return hipGetLastError();
+}
+template hipError_t launch_swizzle_maps<double>(const double2*, double2*, int, int, hipStream_t);
+template hipError_t launch_swizzle_maps<float>(const float2*, float2*, int, int, hipStream_t);
+
+template <typename T>
 hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
                              int kcount, size_t mstride, size_t vstride, int xoff, hipStream_t st) {
   if (kcount <= 0) return hipSuccess;
+  const int nt = iface_tiles(L);
   if (nrhs <= 4) {
-    hipLaunchKernelGGL(k_iface_gemv<T>, dim3((L + 3) / 4, 1, kcount), dim3(kNT), 0, st, M, add, x, y, L, nrhs, kbeg,
+    constexpr int NW = 8;
+    hipLaunchKernelGGL((k_iface_gemv<T, NW>), dim3(nt, 1, kcount), dim3(64 * NW), 0, st, M, add, x, y, L, nrhs, kbeg,
                        mstride, vstride, xoff);
   } else {
-    hipLaunchKernelGGL(k_iface_gemm<T>, dim3((L + 15) / 16, (nrhs + 15) / 16, kcount), dim3(kNT), 0, st, M, add, x,
-                       y, L, nrhs, kbeg, mstride, vstride, xoff);
+    const int qtiles = (nrhs + 15) / 16, groups = (nt + 7) / 8;
+    hipLaunchKernelGGL((k_iface_mfma<T>), dim3(groups * 8 * qtiles, 1, kcount), dim3(64 * kMfmaWaves), 0, st, M, add,
+                       x, y, L, nrhs, kbeg, mstride, vstride, xoff, qtiles);
   }
   return hipGetLastError();
 }

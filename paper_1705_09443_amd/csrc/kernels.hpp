@@ -110,7 +110,14 @@ size_t slice_lds(bool big, size_t stage, int W);
 template <typename T>
 hipError_t launch_slice_solves(const SliceSolveArgs<T>& a, int nslices, bool big, int W, int ngroups,
                                hipStream_t st);
-// y_k = add_k - M_k x_{k+xoff} for k = kbeg .. kbeg+kcount-1 (in place allowed, y == add)
+// Interface maps in operand order: complex elements per slice, and the
+// re-layout of row-major [nslices][L][L] maps into that order.
+template <typename T>
+size_t iface_map_stride(int L);
+template <typename T>
+hipError_t launch_swizzle_maps(const C<T>* src, C<T>* dst, int L, int nslices, hipStream_t st);
+// y_k = add_k - M_k x_{k+xoff} for k = kbeg .. kbeg+kcount-1 (in place allowed, y == add);
+// M in operand order (mstride = iface_map_stride(L))
 template <typename T>
 hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
                              int kcount, size_t mstride, size_t vstride, int xoff, hipStream_t st);

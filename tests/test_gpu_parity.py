@@ -170,6 +170,27 @@ def test_preconditioner(case):
         assert rel(z32[j], zr) <= 1e-4
 
 
+@pytest.mark.parametrize("nb", [5, 17, 40])
+def test_preconditioner_batches(case, nb):
+    # batches above 4 columns take the matrix-core interface products (16-column
+    # tiles: 5 and 17 leave ragged tiles, 40 spans three)
+    name, wl, m, ref, g64, g32 = case
+    n = wl.n
+    rng = np.random.default_rng(20 + nb)
+    r = crand(rng, (nb, n, n))
+    say(f"[{name}] apply_precond batch of {nb}, fp64 and fp32")
+    z = g64.apply_precond(to_dev(r)).cpu().numpy()
+    z32 = g32.apply_precond(to_dev(r, torch.complex64)).cpu().numpy()
+    worst64 = worst32 = 0.0
+    for j in range(nb):
+        zr = ref.precondition(r[j])
+        worst64 = max(worst64, rel(z[j], zr))
+        worst32 = max(worst32, rel(z32[j], zr))
+    say(f"[{name}] batch {nb}: worst relative error fp64 {worst64:.2e}, fp32 {worst32:.2e}")
+    assert worst64 <= 1e-12
+    assert worst32 <= 1e-4
+
+
 def test_solve_fp64_parity(case):
     name, wl, m, ref, g64, g32 = case
     uinc = wl.incident() if name == "c0" else workloads.plane_waves(
@@ -235,14 +256,15 @@ def test_graph_replays_agree(case):
     n = wl.n
     b, w = CASES[name][2], CASES[name][3]
     rng = np.random.default_rng(10)
-    r = to_dev(crand(rng, (3, n, n)))
-    say(f"[{name}] graph replays")
-    with LSSolver(torch.as_tensor(m).cuda(), wl.omega, b, w, precision="fp64", schedule="sequential") as seq:
-        zref = seq.apply_precond(r).cpu().numpy()
-    outs = []
-    for it in range(4):
-        outs.append(g64.apply_precond(r).cpu().numpy())
-        g64.apply_A(r)                     # eager work between replays
-        torch.cuda.synchronize()
-    for z in outs:
-        assert rel(z, zref) <= 1e-12
+    for nb in (3, 9):                      # vector-ALU and matrix-core interface products
+        r = to_dev(crand(rng, (nb, n, n)))
+        say(f"[{name}] graph replays, batch of {nb}")
+        with LSSolver(torch.as_tensor(m).cuda(), wl.omega, b, w, precision="fp64", schedule="sequential") as seq:
+            zref = seq.apply_precond(r).cpu().numpy()
+        outs = []
+        for it in range(4):
+            outs.append(g64.apply_precond(r).cpu().numpy())
+            g64.apply_A(r)                     # eager work between replays
+            torch.cuda.synchronize()
+        for z in outs:
+            assert rel(z, zref) <= 1e-12
