@@ -224,8 +224,12 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   LSW_ALLOC(h->fext, (size_t)nrhs * E * cs);
   LSW_ALLOC(h->uext, (size_t)nrhs * E * cs);
   LSW_ALLOC(h->yscr, (size_t)nrhs * h->L * 32 * cs);
-  LSW_ALLOC(h->lam, (size_t)h->nslices * nrhs * h->L * cs);
-  LSW_ALLOC(h->mu, (size_t)h->nslices * nrhs * h->L * cs);
+  // interface vectors: rows padded to whole 16-blocks; the padding stays zero
+  const size_t vbytes = (size_t)h->nslices * nrhs * iface_vec_stride(h->L) * cs;
+  LSW_ALLOC(h->lam, vbytes);
+  LSW_ALLOC(h->mu, vbytes);
+  LSW_HIP_TRY(hipMemsetAsync(h->lam.p, 0, vbytes, h->st));
+  LSW_HIP_TRY(hipMemsetAsync(h->mu.p, 0, vbytes, h->st));
   // slice-solve scratch: groups of up to 8 waves, one per right-hand side
   LSW_ALLOC(h->sscr, (size_t)h->nslices * std::max(4, nrhs + 7) * slice_scratch_elems<double>(h->L, 1) * cs);
   LSW_ALLOC(h->vin, (size_t)nrhs * N * cs);
@@ -330,7 +334,8 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
     const int nl = h->nslices, L = h->L, R = rhs_group(nb);
     C<T>* lam = h->lam.as<C<T>>();
     C<T>* mu = h->mu.as<C<T>>();
-    const size_t MS = iface_map_stride<T>(L), vs = (size_t)nb * L;
+    const int Lp = iface_vec_stride(L);
+    const size_t MS = iface_map_stride<T>(L), vs = (size_t)nb * Lp;
     SliceSolveArgs<T> a = slice_args<T>(h);
     a.nrhs = nb;
     a.yscr = h->sscr.as<C<T>>();
@@ -343,7 +348,7 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
       a.dstE = lam;
       a.dstF = mu;
       a.sk = vs;
-      a.sr = L;
+      a.sr = Lp;
       a.sj = 1;
       ls_status e = solve_slices<T>(h, a, 0, nl, R);
       if (e != LS_OK) return e;

@@ -420,6 +420,23 @@ __global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSo
 // (r, b) block is then one contiguous 64-lane operand load, and the padding
 // removes every bounds test on M. x, add, y: [nrhs][L] per slice.
 __host__ __device__ inline int iface_tiles(int L) { return (L + 15) / 16; }
+// x, add, y rows (one per right-hand side) are padded to whole 16-blocks:
+// [nrhs][Lp] per slice, with zeros in [L, Lp) that nothing writes.
+__host__ __device__ inline int iface_vec_len(int L) { return 16 * iface_tiles(L); }
+
+// 4 consecutive complex values from a 32-byte (float) or 16-byte (double)
+// aligned address, as whole 16-byte loads
+__device__ __attribute__((always_inline)) inline void load4(const float2* p, float2* out) {
+  const float4 u = reinterpret_cast<const float4*>(p)[0], v = reinterpret_cast<const float4*>(p)[1];
+  out[0] = make_float2(u.x, u.y);
+  out[1] = make_float2(u.z, u.w);
+  out[2] = make_float2(v.x, v.y);
+  out[3] = make_float2(v.z, v.w);
+}
+__device__ __attribute__((always_inline)) inline void load4(const double2* p, double2* out) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) out[j] = p[j];
+}
 
 template <typename T>
 __global__ void k_swizzle_maps(const C<T>* __restrict__ src, C<T>* __restrict__ dst, int L, size_t total) {
@@ -447,6 +464,7 @@ __global__ __launch_bounds__(64 * NW) void k_iface_gemv(const C<T>* __restrict__
   const int nt = iface_tiles(L);
   const int r = blockIdx.x, k = kbeg + blockIdx.z;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g4 = lane >> 4;
+  const int Lp = iface_vec_len(L);
   const C<T>* Mr = MZ + (size_t)k * mstride + (size_t)r * nt * 256 + lane * 4;
   const C<T>* xk = x + (size_t)(k + xoff) * vstride;
   C<T> acc[4];
@@ -457,8 +475,7 @@ __global__ __launch_bounds__(64 * NW) void k_iface_gemv(const C<T>* __restrict__
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
       const int b = min(b0 + i * NW, nt - 1);  // clamped: blocks past the end are loaded, not used
-#pragma unroll
-      for (int j = 0; j < 4; ++j) a[i][j] = Mr[(size_t)b * 256 + j];
+      load4(Mr + (size_t)b * 256, a[i]);
     }
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
@@ -467,11 +484,10 @@ __global__ __launch_bounds__(64 * NW) void k_iface_gemv(const C<T>* __restrict__
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           if (q < nrhs) {
+            C<T> xv[4];
+            load4(xk + (size_t)q * Lp + 16 * b + 4 * g4, xv);
 #pragma unroll
-            for (int j = 0; j < 4; ++j) {
-              const int kk = min(16 * b + 4 * g4 + j, L - 1);  // M is 0 there
-              acc[q] = cfma<T>(acc[q], a[i][j], xk[(size_t)q * L + kk]);
-            }
+            for (int j = 0; j < 4; ++j) acc[q] = cfma<T>(acc[q], a[i][j], xv[j]);
           }
         }
       }
@@ -491,8 +507,8 @@ __global__ __launch_bounds__(64 * NW) void k_iface_gemv(const C<T>* __restrict__
       C<T> s = red[0][q][t & 15];
 #pragma unroll
       for (int w = 1; w < NW; ++w) s = cadd<T>(s, red[w][q][t & 15]);
-      const C<T>* ak = add + (size_t)k * vstride;
-      y[(size_t)k * vstride + (size_t)q * L + row] = csub<T>(ak[(size_t)q * L + row], s);
+      const size_t o = (size_t)k * vstride + (size_t)q * Lp + row;
+      y[o] = csub<T>(add[o], s);
     }
   }
 }
@@ -526,7 +542,7 @@ struct Mfma<double> {
   static __device__ __attribute__((always_inline)) int out_row(int g, int j) { return 4 * j + g; }
 };
 
-constexpr int kMfmaWaves = 4;
+constexpr int kMfmaWaves = 8;
 template <typename T>
 constexpr int kMfmaPrefetch = sizeof(T) == 4 ? 4 : 2;
 
@@ -543,28 +559,26 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(const C<T>* __restrict__
   if (r >= nt) return;  // whole workgroup: the grid is rounded up to 8 row blocks
   const int k = kbeg + blockIdx.z;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g4 = lane >> 4;
+  const int Lp = iface_vec_len(L);
   const C<T>* Mr = MZ + (size_t)k * mstride + (size_t)r * nt * 256 + lane * 4;
-  const C<T>* Bc = x + (size_t)(k + xoff) * vstride + (size_t)min(q * 16 + li, nrhs - 1) * L;
-  // this wave's contraction blocks, a whole number of prefetch rounds
-  const int nbw = ((nt + NW - 1) / NW + PF - 1) / PF * PF;
-  const int b0 = wave * nbw;
+  // columns past nrhs read the last one: their outputs are not stored
+  const C<T>* Bc = x + (size_t)(k + xoff) * vstride + (size_t)min(q * 16 + li, nrhs - 1) * Lp + 4 * g4;
+  // this wave's contraction blocks: an even share [b0, b1)
+  const int b0 = wave * nt / NW, b1 = (wave + 1) * nt / NW;
   V accR = {0, 0, 0, 0}, accI = {0, 0, 0, 0};
   C<T> a[PF][4], bv[PF][4];
-  // unconditional loads (clamped block and column indices): M is zero past L,
-  // so x's clamped values there multiply zeros
+  // unconditional whole-vector loads (block index clamped to the tile range)
   auto load = [&](C<T>* ad, C<T>* bd, int b) {
     const int bc = min(b, nt - 1);
-#pragma unroll
-    for (int j = 0; j < 4; ++j) ad[j] = Mr[(size_t)bc * 256 + j];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) bd[j] = Bc[min(16 * bc + 4 * g4 + j, L - 1)];
+    load4(Mr + (size_t)bc * 256, ad);
+    load4(Bc + 16 * bc, bd);
   };
 #pragma unroll
   for (int s = 0; s < PF; ++s) load(a[s], bv[s], b0 + s);
-  for (int i = 0; i < nbw; i += PF) {
+  for (int i = b0; i < b1; i += PF) {
 #pragma unroll
     for (int s = 0; s < PF; ++s) {
-      if (b0 + i + s < nt) {
+      if (i + s < b1) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
           accR = Mfma<T>::op(a[s][j].x, bv[s][j].x, accR);
@@ -573,7 +587,7 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(const C<T>* __restrict__
           accI = Mfma<T>::op(a[s][j].y, bv[s][j].x, accI);
         }
       }
-      load(a[s], bv[s], b0 + i + s + PF);
+      load(a[s], bv[s], i + s + PF);
     }
   }
 #pragma unroll
@@ -589,7 +603,7 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(const C<T>* __restrict__
       C<T> sum = red[0][orow][oc];
 #pragma unroll
       for (int w = 1; w < NW; ++w) sum = cadd<T>(sum, red[w][orow][oc]);
-      const size_t o = (size_t)k * vstride + (size_t)Q * L + R;
+      const size_t o = (size_t)k * vstride + (size_t)Q * Lp + R;
       y[o] = csub<T>(add[o], sum);
     }
   }
@@ -607,7 +621,7 @@ __global__ void k_couple(SliceTables P, int L, int b, const C<T>* __restrict__ H
   const int k = (int)(idx / ((size_t)L * nrhs));
   C<T>* fr = f + (size_t)r * L * L;
   if (k > 0) {
-    const C<T>* lv = lam + ((size_t)(k - 1) * nrhs + r) * L;
+    const C<T>* lv = lam + ((size_t)(k - 1) * nrhs + r) * iface_vec_len(L);
     const C<T>* hm = Hm + ((size_t)k * L + j) * 3;
     C<T> acc = mk<T>(0, 0);
     for (int d = -1; d <= 1; ++d)
@@ -616,7 +630,7 @@ __global__ void k_couple(SliceTables P, int L, int b, const C<T>* __restrict__ H
     *o = csub<T>(*o, acc);
   }
   if (k < P.nslices - 1) {
-    const C<T>* mv = mu + ((size_t)(k + 1) * nrhs + r) * L;
+    const C<T>* mv = mu + ((size_t)(k + 1) * nrhs + r) * iface_vec_len(L);
     const C<T>* hp = Hp + ((size_t)k * L + j) * 3;
     C<T> acc = mk<T>(0, 0);
     for (int d = -1; d <= 1; ++d)
@@ -692,6 +706,8 @@ hipError_t launch_slice_solves(const SliceSolveArgs<T>& a, int nslices, bool big
 }
 template hipError_t launch_slice_solves<double>(const SliceSolveArgs<double>&, int, bool, int, int, hipStream_t);
 template hipError_t launch_slice_solves<float>(const SliceSolveArgs<float>&, int, bool, int, int, hipStream_t);
+
+int iface_vec_stride(int L) { return iface_vec_len(L); }
 
 template <typename T>
 size_t iface_map_stride(int L) {

@@ -114,6 +114,9 @@ hipError_t launch_slice_solves(const SliceSolveArgs<T>& a, int nslices, bool big
 // re-layout of row-major [nslices][L][L] maps into that order.
 template <typename T>
 size_t iface_map_stride(int L);
+// Row length of the interface vectors lambda, mu ([nslices][nrhs][Lp], zero
+// past L): L rounded up to a multiple of 16.
+int iface_vec_stride(int L);
 template <typename T>
 hipError_t launch_swizzle_maps(const C<T>* src, C<T>* dst, int L, int nslices, hipStream_t st);
 // y_k = add_k - M_k x_{k+xoff} for k = kbeg .. kbeg+kcount-1 (in place allowed, y == add);
