@@ -84,10 +84,14 @@ struct ls_handle {
   // interface maps M_k, P_k, N_k ([nslices][L][L])
   DBuf IM, IP, IN;
   // per slice on the host: line count t and forward factor stride
-  std::vector<int> t_host, fstride_host;
+  std::vector<int> t_host, fstride_host, tw_host;
+  // factors in matrix-core operand order (slice_mfma.hip), per-slice offsets,
+  // chunk counts and scratch units; total scratch units over all slices
+  DBuf MW, MG, mw_off, mg_off, mnsd, mys_unit;
+  int mys_units = 0;
   // workspaces
   int cap = 0;  // right-hand sides the workspaces hold
-  DBuf fftw64, fftw32, fext, uext, yscr, vin, zout, aout, lam, mu, sscr;
+  DBuf fftw64, fftw32, fext, uext, yscr, vin, zout, aout, lam, mu, sscr, mscr;
   DBuf V, Z, W, X, G, R, T1, T2;
   DBuf pairs, partials, coefs, outs, terms64, terms32, ptrs_a, ptrs_b;
   // adjoint state
@@ -95,6 +99,9 @@ struct ls_handle {
   DBuf psi;
   // captured interface recurrences, one graph per (batch size, precision)
   hipStream_t cst = nullptr;
+  // second stream for the last slice's solves, and the events that order it
+  hipStream_t st2 = nullptr;
+  hipEvent_t evQ = nullptr, evA = nullptr, evL = nullptr, evC = nullptr;
   std::map<std::pair<int, int>, hipGraphExec_t> graphs;
   void drop_graphs() {
     for (auto& kv : graphs) (void)hipGraphExecDestroy(kv.second);
@@ -112,6 +119,9 @@ struct ls_handle {
   ~ls_handle() {
     drop_graphs();
     if (cst) (void)hipStreamDestroy(cst);
+    if (st2) (void)hipStreamDestroy(st2);
+    for (hipEvent_t e : {evQ, evA, evL, evC})
+      if (e) (void)hipEventDestroy(e);
     for (auto& r : recs) {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
@@ -149,9 +159,9 @@ struct ls_handle {
 
 namespace {
 
-enum KernelKind { kKSweep = 0, kKFft, kKQ, kKExtract, kKFactor, kKSlices, kKIface, kKNumKinds };
-const char* kKindNames[kKNumKinds] = {"sweep", "fft_convolve", "stencil_Q", "extract", "factor",
-                                      "slice_solves", "interface"};
+enum KernelKind { kKSweep = 0, kKFft, kKQ, kKExtract, kKFactor, kKSlices, kKIface, kKSlicesLast, kKNumKinds };
+const char* kKindNames[kKNumKinds] = {"sweep",        "fft_convolve", "stencil_Q", "extract", "factor",
+                                      "slice_solves", "interface",    "slice_solves_last"};
 
 hipEvent_t take_event(ls_handle* h) {
   if (!h->pool.empty()) {
@@ -168,17 +178,18 @@ hipEvent_t take_event(ls_handle* h) {
 struct Timed {
   ls_handle* h;
   int kind, cols;
+  hipStream_t s;
   hipEvent_t a = nullptr;
-  Timed(ls_handle* hh, int k, int c) : h(hh), kind(k), cols(c) {
+  Timed(ls_handle* hh, int k, int c, hipStream_t stream = nullptr) : h(hh), kind(k), cols(c), s(stream ? stream : hh->st) {
     if (h->profiling) {
       a = take_event(h);
-      (void)hipEventRecord(a, h->st);
+      (void)hipEventRecord(a, s);
     }
   }
   ~Timed() {
     if (a) {
       hipEvent_t b = take_event(h);
-      (void)hipEventRecord(b, h->st);
+      (void)hipEventRecord(b, s);
       h->recs.push_back({kind, cols, a, b});
     }
   }
@@ -212,6 +223,15 @@ ls_status check_handle(const ls_handle* h) {
 // Right-hand sides per workgroup of the slice solves.
 int rhs_group(int nrhs) { return nrhs == 1 ? 1 : (nrhs <= 4 ? 4 : 8); }
 
+// Batches above this many columns take the matrix-core slice solves.
+constexpr int kMfmaMinCols = 8;
+
+// Scratch of the matrix-core slice solves for ncols columns: the forward
+// results of every slice, (L+1) x 512 scalars per row tile and 16 columns.
+size_t mfma_scratch_bytes(const ls_handle* h, int ncols, size_t cs) {
+  return (size_t)h->mys_units * ((ncols + 15) / 16) * (size_t)(h->L + 1) * 512 * (cs / 2);
+}
+
 // Workspaces sized for nrhs right-hand sides.
 ls_status ensure_workspace(ls_handle* h, int nrhs) {
   if (nrhs <= h->cap) return LS_OK;
@@ -232,6 +252,8 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   LSW_HIP_TRY(hipMemsetAsync(h->mu.p, 0, vbytes, h->st));
   // slice-solve scratch: groups of up to 8 waves, one per right-hand side
   LSW_ALLOC(h->sscr, (size_t)h->nslices * std::max(4, nrhs + 7) * slice_scratch_elems<double>(h->L, 1) * cs);
+  if (nrhs > kMfmaMinCols)
+    LSW_ALLOC(h->mscr, mfma_scratch_bytes(h, nrhs, cs));
   LSW_ALLOC(h->vin, (size_t)nrhs * N * cs);
   LSW_ALLOC(h->zout, (size_t)nrhs * N * cs);
   LSW_ALLOC(h->aout, (size_t)nrhs * N * cs);
@@ -296,8 +318,42 @@ SliceSolveArgs<T> slice_args(ls_handle* h) {
 // All slices of [k0, k1) solved in one launch, Wmax right-hand sides (waves)
 // per workgroup at most, fewer if the LDS would not fit.
 template <typename T>
-ls_status solve_slices(ls_handle* h, SliceSolveArgs<T> a, int k0, int k1, int Wmax) {
+ls_status solve_slices(ls_handle* h, SliceSolveArgs<T> a, int k0, int k1, int Wmax, hipStream_t st = nullptr) {
   if (k0 >= k1) return LS_OK;
+  if (!st) st = h->st;
+  if (a.nrhs > kMfmaMinCols) {
+    if (!a.mfma_scr) {
+      set_error("internal: no scratch for the matrix-core slice solves");
+      return LS_E_STATE;
+    }
+    SliceMfmaArgs<T> m{};
+    m.P = a.P;
+    m.L = a.L;
+    m.b = a.b;
+    m.MW = h->MW.as<C<T>>();
+    m.MG = h->MG.as<C<T>>();
+    m.mw_off = h->mw_off.as<size_t>();
+    m.mg_off = h->mg_off.as<size_t>();
+    m.nsd = h->mnsd.as<int>();
+    m.ys_unit = h->mys_unit.as<int>();
+    m.Hm = a.Hm;
+    m.Hp = a.Hp;
+    m.slice0 = k0;
+    m.nrhs = a.nrhs;
+    m.src_kind = a.src_kind;
+    m.src = a.src;
+    m.col0 = a.col0;
+    m.dst_kind = a.dst_kind;
+    m.dst = a.dst;
+    m.dstE = a.dstE;
+    m.dstF = a.dstF;
+    m.sk = a.sk;
+    m.sr = a.sr;
+    m.sj = a.sj;
+    m.yscr = a.mfma_scr;
+    LSW_HIP_TRY(launch_slice_mfma<T>(m, k1 - k0, st));
+    return LS_OK;
+  }
   int f16 = 0, f32 = 0;
   for (int k = k0; k < k1; ++k) {
     int& f = h->t_host[k] > 16 ? f32 : f16;
@@ -312,7 +368,7 @@ ls_status solve_slices(ls_handle* h, SliceSolveArgs<T> a, int k0, int k1, int Wm
     set_error("slice subproblem too large for the LDS of one workgroup");
     return LS_E_INVALID;
   }
-  LSW_HIP_TRY(launch_slice_solves<T>(a, k1 - k0, big, W, (a.nrhs + W - 1) / W, h->st));
+  LSW_HIP_TRY(launch_slice_solves<T>(a, k1 - k0, big, W, (a.nrhs + W - 1) / W, st));
   return LS_OK;
 }
 
@@ -339,60 +395,122 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
     SliceSolveArgs<T> a = slice_args<T>(h);
     a.nrhs = nb;
     a.yscr = h->sscr.as<C<T>>();
-    if (nl > 1) {
-      // phase A: boundary lines of T_k f_k for every slice
-      Timed tm(h, kKSlices, nb);
-      a.src_kind = kSrcGrid;
-      a.src = f;
-      a.dst_kind = kDstLines;
-      a.dstE = lam;
-      a.dstF = mu;
-      a.sk = vs;
-      a.sr = Lp;
-      a.sj = 1;
-      ls_status e = solve_slices<T>(h, a, 0, nl, R);
-      if (e != LS_OK) return e;
-    }
-    if (nl > 1) {
-      // interface recurrences: 2(l-2)+2 dependent launches, captured once per batch size
-      Timed tm(h, kKIface, nb);
-      const std::pair<int, int> key(nb, (int)sizeof(T));
+    a.mfma_scr = h->mscr.as<T>();
+    // The last slice (the 32-line class with the far PML, the longest solve)
+    // runs on a second stream: its phase A is first needed by the P term, after
+    // the whole lambda recurrence, and its phase C only needs lambda_{l-2}, so
+    // both overlap the recurrences on the main stream.
+    const bool split = nl > 2;
+    const int kmain = split ? nl - 1 : nl;
+    auto phaseA = [&](int k0, int k1, hipStream_t s) -> ls_status {
+      SliceSolveArgs<T> p = a;
+      p.src_kind = kSrcGrid;
+      p.src = f;
+      p.dst_kind = kDstLines;
+      p.dstE = lam;
+      p.dstF = mu;
+      p.sk = vs;
+      p.sr = Lp;
+      p.sj = 1;
+      return solve_slices<T>(h, p, k0, k1, R, s);
+    };
+    auto phaseC = [&](int k0, int k1, hipStream_t s) -> ls_status {
+      SliceSolveArgs<T> p = a;
+      p.src_kind = kSrcGrid;
+      p.src = f;
+      p.dst_kind = kDstGrid;
+      p.dst = u;
+      p.dstE = p.dstF = nullptr;
+      return solve_slices<T>(h, p, k0, k1, R, s);
+    };
+    // graphs: part 0 the lambda recurrence, part 1 the P term, the mu
+    // recurrence and the coupling of the slices on the main stream. The last
+    // slice's coupling (lambda term only) runs on the second stream after its
+    // own phase A, which reads the line it changes.
+    auto graph = [&](int part, hipGraphExec_t& out) -> ls_status {
+      const std::pair<int, int> key(2 * nb + part, (int)sizeof(T));
       auto it = h->graphs.find(key);
-      if (it == h->graphs.end()) {
-        if (!h->cst) LSW_HIP_TRY(hipStreamCreateWithFlags(&h->cst, hipStreamNonBlocking));
-        const C<T>* IM = h->IM.as<C<T>>();
-        const C<T>* IP = h->IP.as<C<T>>();
-        const C<T>* IN = h->IN.as<C<T>>();
-        hipGraph_t graph = nullptr;
-        LSW_HIP_TRY(hipStreamBeginCapture(h->cst, hipStreamCaptureModeThreadLocal));
-        hipError_t ce = hipSuccess;
+      if (it != h->graphs.end()) {
+        out = it->second;
+        return LS_OK;
+      }
+      const C<T>* IM = h->IM.as<C<T>>();
+      const C<T>* IP = h->IP.as<C<T>>();
+      const C<T>* IN = h->IN.as<C<T>>();
+      const C<T>* Hm = h->Hm.as<C<T>>();
+      const C<T>* Hp = h->Hp.as<C<T>>();
+      hipGraph_t g = nullptr;
+      LSW_HIP_TRY(hipStreamBeginCapture(h->cst, hipStreamCaptureModeThreadLocal));
+      hipError_t ce = hipSuccess;
+      if (part == 0) {
         for (int k = 1; k <= nl - 2 && ce == hipSuccess; ++k)
           ce = launch_iface_step<T>(IM, lam, lam, lam, L, nb, k, 1, MS, vs, -1, h->cst);
-        if (ce == hipSuccess) ce = launch_iface_step<T>(IP, mu, lam, mu, L, nb, 1, nl - 1, MS, vs, -1, h->cst);
+      } else {
+        ce = launch_iface_step<T>(IP, mu, lam, mu, L, nb, 1, nl - 1, MS, vs, -1, h->cst);
         for (int k = nl - 2; k >= 1 && ce == hipSuccess; --k)
           ce = launch_iface_step<T>(IN, mu, mu, mu, L, nb, k, 1, MS, vs, +1, h->cst);
-        if (ce == hipSuccess)
-          ce = launch_couple<T>(h->slices(), L, h->b, h->Hm.as<C<T>>(), h->Hp.as<C<T>>(), lam, mu, nb, f, h->cst);
-        const hipError_t ee = hipStreamEndCapture(h->cst, &graph);
-        LSW_HIP_TRY(ce);
-        LSW_HIP_TRY(ee);
-        hipGraphExec_t exec = nullptr;
-        const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        LSW_HIP_TRY(ie);
-        it = h->graphs.emplace(key, exec).first;
+        if (ce == hipSuccess) ce = launch_couple<T>(h->slices(), L, h->b, Hm, Hp, lam, mu, nb, f, 0, kmain, h->cst);
       }
-      LSW_HIP_TRY(hipGraphLaunch(it->second, h->st));
-    }
-    {
-      // phase C: every slice's field from its coupled right-hand side
+      const hipError_t ee = hipStreamEndCapture(h->cst, &g);
+      LSW_HIP_TRY(ce);
+      LSW_HIP_TRY(ee);
+      const hipError_t ie = hipGraphInstantiate(&out, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      LSW_HIP_TRY(ie);
+      h->graphs.emplace(key, out);
+      return LS_OK;
+    };
+    if (nl > 1) {
+      if (!h->cst) LSW_HIP_TRY(hipStreamCreateWithFlags(&h->cst, hipStreamNonBlocking));
+      hipGraphExec_t g0 = nullptr, g1 = nullptr;
+      ls_status e = nl > 2 ? graph(0, g0) : LS_OK;  // part 0 is empty for two slices
+      if (e == LS_OK) e = graph(1, g1);
+      if (e != LS_OK) return e;
+      if (split) {
+        if (!h->st2) {
+          LSW_HIP_TRY(hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking));
+          for (hipEvent_t* ev : {&h->evQ, &h->evA, &h->evL, &h->evC})
+            LSW_HIP_TRY(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+        }
+        LSW_HIP_TRY(hipEventRecord(h->evQ, h->st));
+        LSW_HIP_TRY(hipStreamWaitEvent(h->st2, h->evQ, 0));
+        {
+          Timed tm(h, kKSlicesLast, nb, h->st2);
+          if ((e = phaseA(kmain, nl, h->st2)) != LS_OK) return e;
+        }
+        LSW_HIP_TRY(hipEventRecord(h->evA, h->st2));
+      }
+      {
+        Timed tm(h, kKSlices, nb);
+        if ((e = phaseA(0, kmain, h->st)) != LS_OK) return e;
+      }
+      {
+        Timed tm(h, kKIface, nb);
+        if (g0) LSW_HIP_TRY(hipGraphLaunch(g0, h->st));
+        if (split) {
+          LSW_HIP_TRY(hipEventRecord(h->evL, h->st));
+          LSW_HIP_TRY(hipStreamWaitEvent(h->st, h->evA, 0));
+        }
+        LSW_HIP_TRY(hipGraphLaunch(g1, h->st));
+      }
+      if (split) {
+        LSW_HIP_TRY(hipStreamWaitEvent(h->st2, h->evL, 0));
+        {
+          Timed tm(h, kKSlicesLast, nb, h->st2);
+          LSW_HIP_TRY(launch_couple<T>(h->slices(), L, h->b, h->Hm.as<C<T>>(), h->Hp.as<C<T>>(), lam, mu, nb, f,
+                                       kmain, nl, h->st2));
+          if ((e = phaseC(kmain, nl, h->st2)) != LS_OK) return e;
+        }
+        LSW_HIP_TRY(hipEventRecord(h->evC, h->st2));
+      }
+      {
+        Timed tm(h, kKSlices, nb);
+        if ((e = phaseC(0, kmain, h->st)) != LS_OK) return e;
+      }
+      if (split) LSW_HIP_TRY(hipStreamWaitEvent(h->st, h->evC, 0));
+    } else {
       Timed tm(h, kKSlices, nb);
-      a.src_kind = kSrcGrid;
-      a.src = f;
-      a.dst_kind = kDstGrid;
-      a.dst = u;
-      a.dstE = a.dstF = nullptr;
-      ls_status e = solve_slices<T>(h, a, 0, nl, R);
+      ls_status e = phaseC(0, nl, h->st);
       if (e != LS_OK) return e;
     }
   }
@@ -400,6 +518,44 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
     Timed tm(h, kKExtract, nb);
     LSW_HIP_TRY(launch_extract<T>(h->n, h->b, u, nb, z, h->st));
   }
+  return LS_OK;
+}
+
+// The slice factors again in the operand order of the matrix-core slice
+// solves, with the per-slice offsets, chunk counts and scratch units.
+template <typename T>
+ls_status build_mfma_factors(ls_handle* h) {
+  const int nl = h->nslices, L = h->L;
+  const size_t cs = sizeof(C<T>);
+  std::vector<size_t> mwo(nl), mgo(nl);
+  std::vector<int> nsd(nl), ysu(nl);
+  size_t w = 0, g = 0;
+  int units = 0;
+  for (int k = 0; k < nl; ++k) {
+    const int t = h->t_host[k], tw = h->tw_host[k];
+    mwo[k] = w;
+    mgo[k] = g;
+    w += (size_t)L * mfma_wrec_elems(t, tw);
+    g += (size_t)L * mfma_grec_elems(t);
+    nsd[k] = mfma_chunks(t, tw);
+    ysu[k] = units;
+    units += mfma_row_tiles(t);
+  }
+  LSW_ALLOC(h->MW, w * cs);
+  LSW_ALLOC(h->MG, g * cs);
+  LSW_ALLOC(h->mw_off, nl * sizeof(size_t));
+  LSW_ALLOC(h->mg_off, nl * sizeof(size_t));
+  LSW_ALLOC(h->mnsd, nl * sizeof(int));
+  LSW_ALLOC(h->mys_unit, nl * sizeof(int));
+  if (upload(h, h->mw_off, mwo) != LS_OK || upload(h, h->mg_off, mgo) != LS_OK || upload(h, h->mnsd, nsd) != LS_OK ||
+      upload(h, h->mys_unit, ysu) != LS_OK)
+    return LS_E_DEVICE;
+  for (int k = 0; k < nl; ++k)
+    LSW_HIP_TRY(launch_mfma_factors<T>(h->slices(), L, k, h->t_host[k], h->tw_host[k], h->FS.as<C<T>>(),
+                                       h->FG.as<C<T>>(), h->MW.as<C<T>>() + mwo[k], h->MG.as<C<T>>() + mgo[k],
+                                       h->st));
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  h->mys_units = units;
   return LS_OK;
 }
 
@@ -415,15 +571,19 @@ ls_status build_interface(ls_handle* h) {
   LSW_ALLOC(h->IM, (size_t)nl * LL * cs);
   LSW_ALLOC(h->IP, (size_t)nl * LL * cs);
   LSW_ALLOC(h->IN, (size_t)nl * LL * cs);
-  constexpr int W = 8;  // columns per workgroup (one wave each)
-  // columns per launch: as many groups as a ~2 GB scratch allows
-  const size_t per_group = (size_t)nl * slice_scratch_elems<double>(L, W) * cs;
-  const int groups = (int)std::max<size_t>(1, std::min<size_t>((L + W - 1) / W, (size_t)2e9 / per_group));
-  const int cols = groups * W;
-  DBuf scr;
-  LSW_ALLOC(scr, per_group * groups);
+  constexpr int W = 8;  // waves per workgroup of the vector-ALU path
+  // columns per launch: whole 16-column tiles of the matrix-core path, as many
+  // as an ~8 GB scratch allows; a short last launch of at most 8 columns takes
+  // the vector-ALU path with its own small scratch
+  const size_t tile_bytes = mfma_scratch_bytes(h, 16, cs);
+  const int tiles = (int)std::max<size_t>(1, std::min<size_t>((L + 15) / 16, (size_t)8e9 / tile_bytes));
+  const int cols = tiles * 16;
+  DBuf mscr, vscr;
+  LSW_ALLOC(mscr, tile_bytes * tiles);
+  LSW_ALLOC(vscr, (size_t)nl * slice_scratch_elems<double>(L, W) * cs);
   SliceSolveArgs<T> a = slice_args<T>(h);
-  a.yscr = scr.as<C<T>>();
+  a.yscr = vscr.as<C<T>>();
+  a.mfma_scr = mscr.as<T>();
   a.dst_kind = kDstLines;
   a.sk = LL;
   a.sr = 1;
@@ -887,7 +1047,11 @@ ls_status device_setup(ls_handle* h, const double* m_dev) {
   }
   h->t_host = t;
   h->fstride_host.assign(nl, 0);
-  for (int k = 0; k < nl; ++k) h->fstride_host[k] = factor_stride(t[k], hi[k] - lo[k] + 1);
+  h->tw_host.assign(nl, 0);
+  for (int k = 0; k < nl; ++k) {
+    h->fstride_host[k] = factor_stride(t[k], hi[k] - lo[k] + 1);
+    h->tw_host[k] = hi[k] - lo[k] + 1;
+  }
   LSW_ALLOC(h->s_lo, nl * sizeof(int));
   LSW_ALLOC(h->s_hi, nl * sizeof(int));
   LSW_ALLOC(h->s_first, nl * sizeof(int));
@@ -919,6 +1083,10 @@ ls_status device_setup(ls_handle* h, const double* m_dev) {
   if (status != 0) {
     set_error("zero pivot in the factorization of slice " + std::to_string(status - 1));
     return LS_E_SINGULAR;
+  }
+  {
+    ls_status e = h->prec == LS_FP64 ? build_mfma_factors<double>(h) : build_mfma_factors<float>(h);
+    if (e != LS_OK) return e;
   }
   if (h->opt.sweep_schedule == LS_SWEEP_INTERFACE) {
     ls_status e = h->prec == LS_FP64 ? build_interface<double>(h) : build_interface<float>(h);
@@ -1205,6 +1373,7 @@ ls_status ls_slice_solve(ls_handle* h, int slice, const void* v, int nrhs, void*
     SliceSolveArgs<T> a = slice_args<T>(h);
     a.nrhs = nrhs;
     a.yscr = h->sscr.as<C<T>>();
+    a.mfma_scr = h->mscr.as<T>();
     a.src_kind = kSrcSlice;
     a.src = static_cast<const C<T>*>(v);
     a.dst_kind = kDstSlice;

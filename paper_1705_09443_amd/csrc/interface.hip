@@ -153,7 +153,8 @@ __device__ __attribute__((always_inline)) inline void slice_body(const SliceSolv
   C<T>* rst = wreg;                                      // [2][D][TP] right-hand sides
   C<T>* yst = wreg + 2 * D * TP;                         // [2][D][TP] forward results
   C<T>* yb = wreg + 4 * D * TP;                          // [TP] exchange row
-  C<T>* yg = A.yscr + (((size_t)sl * ngroups + group) * W + (computes ? wv : 0)) * (size_t)L * 32;
+  // scratch by global slice index: launches over disjoint slice ranges may run concurrently
+  C<T>* yg = A.yscr + (((size_t)k * ngroups + group) * W + (computes ? wv : 0)) * (size_t)L * 32;
   const int tid = threadIdx.x;
   Stager<T, NSTAGE> stg;
   Stager<T, NR> ystg;
@@ -612,13 +613,14 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(const C<T>* __restrict__
 // f on the first line of D_k -= Hm_k lambda_{k-1}; on its last line -= Hp_k mu_{k+1}.
 template <typename T>
 __global__ void k_couple(SliceTables P, int L, int b, const C<T>* __restrict__ Hm, const C<T>* __restrict__ Hp,
-                         const C<T>* __restrict__ lam, const C<T>* __restrict__ mu, int nrhs, C<T>* f) {
+                         const C<T>* __restrict__ lam, const C<T>* __restrict__ mu, int nrhs, C<T>* f, int k0,
+                         int kcount) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t tot = (size_t)P.nslices * nrhs * L;
+  const size_t tot = (size_t)kcount * nrhs * L;
   if (idx >= tot) return;
   const int j = (int)(idx % L);
   const int r = (int)((idx / L) % nrhs);
-  const int k = (int)(idx / ((size_t)L * nrhs));
+  const int k = k0 + (int)(idx / ((size_t)L * nrhs));
   C<T>* fr = f + (size_t)r * L * L;
   if (k > 0) {
     const C<T>* lv = lam + ((size_t)(k - 1) * nrhs + r) * iface_vec_len(L);
@@ -749,15 +751,16 @@ template hipError_t launch_iface_step<float>(const float2*, const float2*, const
 
 template <typename T>
 hipError_t launch_couple(const SliceTables& P, int L, int b, const C<T>* Hm, const C<T>* Hp, const C<T>* lam,
-                         const C<T>* mu, int nrhs, C<T>* f, hipStream_t st) {
-  const size_t tot = (size_t)P.nslices * nrhs * L;
+                         const C<T>* mu, int nrhs, C<T>* f, int k0, int k1, hipStream_t st) {
+  if (k1 <= k0) return hipSuccess;
+  const size_t tot = (size_t)(k1 - k0) * nrhs * L;
   hipLaunchKernelGGL(k_couple<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, P, L, b, Hm, Hp, lam, mu,
-                     nrhs, f);
+                     nrhs, f, k0, k1 - k0);
   return hipGetLastError();
 }
 template hipError_t launch_couple<double>(const SliceTables&, int, int, const double2*, const double2*,
-                                          const double2*, const double2*, int, double2*, hipStream_t);
+                                          const double2*, const double2*, int, double2*, int, int, hipStream_t);
 template hipError_t launch_couple<float>(const SliceTables&, int, int, const float2*, const float2*, const float2*,
-                                         const float2*, int, float2*, hipStream_t);
+                                         const float2*, int, float2*, int, int, hipStream_t);
 
 }  // namespace lsw

@@ -93,6 +93,7 @@ struct SliceSolveArgs {
   size_t sk, sr, sj;
   C<T>* yscr;      // nslices * ngroups * slice_scratch_elems(L, W)
   size_t stage;    // LDS stage buffer length (slice_stage_elems)
+  T* mfma_scr;     // scratch of the matrix-core path (batches of more than 8)
 };
 // Scratch (complex elements) of one workgroup of W waves.
 template <typename T>
@@ -119,15 +120,53 @@ size_t iface_map_stride(int L);
 int iface_vec_stride(int L);
 template <typename T>
 hipError_t launch_swizzle_maps(const C<T>* src, C<T>* dst, int L, int nslices, hipStream_t st);
+// ---- slice solves for batches on the matrix cores (slice_mfma.hip) ----
+// Factors in operand order: per slice k and step j a forward record of
+// mfma_wrec_elems(t, tw) complex values (W_j, then the D_k columns of
+// S_j^{-1}) and a backward record of mfma_grec_elems(t) (G_j).
+int mfma_row_tiles(int t);
+int mfma_chunks(int t, int tw);
+size_t mfma_wrec_elems(int t, int tw);
+size_t mfma_grec_elems(int t);
+template <typename T>
+hipError_t launch_mfma_factors(const SliceTables& P, int L, int k, int t, int tw, const C<T>* FS, const C<T>* FG,
+                               C<T>* MW, C<T>* MG, hipStream_t st);
+template <typename T>
+struct SliceMfmaArgs {
+  SliceTables P;
+  int L, b;
+  const C<T>* MW;
+  const C<T>* MG;
+  const size_t* mw_off;  // per slice, complex elements
+  const size_t* mg_off;
+  const int* nsd;        // per slice: chunks of 4 right-hand-side lines
+  const int* ys_unit;    // per slice: sum of the row tiles of the slices before it
+  const C<T>* Hm;
+  const C<T>* Hp;
+  int slice0, nrhs;
+  int src_kind;
+  const C<T>* src;
+  int col0;
+  int dst_kind;
+  C<T>* dst;
+  C<T>* dstE;
+  C<T>* dstF;
+  size_t sk, sr, sj;
+  T* yscr;               // (sum of row tiles) x ceil(nrhs/16) x (L+1) x 512 scalars
+};
+// Slices [slice0, slice0 + nslices) for a batch, one wave per 16 columns.
+template <typename T>
+hipError_t launch_slice_mfma(const SliceMfmaArgs<T>& a, int nslices, hipStream_t st);
+
 // y_k = add_k - M_k x_{k+xoff} for k = kbeg .. kbeg+kcount-1 (in place allowed, y == add);
 // M in operand order (mstride = iface_map_stride(L))
 template <typename T>
 hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
                              int kcount, size_t mstride, size_t vstride, int xoff, hipStream_t st);
-// f -= J_F Hm_k lambda_{k-1} + J_E Hp_k mu_{k+1} on every slice
+// f -= J_F Hm_k lambda_{k-1} + J_E Hp_k mu_{k+1} on slices [k0, k1)
 template <typename T>
 hipError_t launch_couple(const SliceTables& P, int L, int b, const C<T>* Hm, const C<T>* Hp, const C<T>* lam,
-                         const C<T>* mu, int nrhs, C<T>* f, hipStream_t st);
+                         const C<T>* mu, int nrhs, C<T>* f, int k0, int k1, hipStream_t st);
 
 // ---- Krylov helpers (krylov.hip) ----
 struct DotPair {

@@ -156,6 +156,31 @@ def test_slice_solves(case):
             assert rel(w32[j].reshape(-1), ref_w) <= 1e-4, (k, j)
 
 
+def test_slice_solves_batched(case):
+    # 20 columns take the matrix-core slice solves (two 16-column tiles, the
+    # second ragged), every slice including the first (no auxiliary lines) and
+    # the last (the 32-line class at c0)
+    name, wl, m, ref, g64, g32 = case
+    sw = ref.sweep
+    rng = np.random.default_rng(31)
+    nb = 20
+    for k in range(sw.nslices):
+        lo, hi, naux = g64.slice_bounds(k)
+        lines = hi - lo + 1
+        v = crand(rng, (nb, lines, sw.s.L))
+        w = g64.slice_solve(k, to_dev(v)).cpu().numpy()
+        w32 = g32.slice_solve(k, to_dev(v, torch.complex64)).cpu().numpy()
+        worst64 = worst32 = 0.0
+        for j in range(nb):
+            ref_w = sw.solve_slice(k, v[j].reshape(-1))
+            worst64 = max(worst64, rel(w[j].reshape(-1), ref_w))
+            worst32 = max(worst32, rel(w32[j].reshape(-1), ref_w))
+        if k in (0, sw.nslices - 1):
+            say(f"[{name}] batched slice {k}: t={lines + naux}, worst fp64 {worst64:.2e}, fp32 {worst32:.2e}")
+        assert worst64 <= 1e-12, (k, worst64)
+        assert worst32 <= 1e-4, (k, worst32)
+
+
 def test_preconditioner(case):
     name, wl, m, ref, g64, g32 = case
     n = wl.n
