@@ -21,16 +21,92 @@ namespace lsw {
 
 namespace {
 
-// In-place Stockham FFT (radix 4, a final radix 2 when log2 P is odd) of nseq
-// interleaved sequences: element k of sequence s lives at buf[k * nseq + s].
-// tw[k] = exp(-2 pi i k / P); the inverse uses the conjugate (unnormalised).
-// complex values a thread holds per pass (16: no register spills at 512 threads)
+// In-place Stockham FFT of nseq interleaved sequences in LDS: element k of
+// sequence s lives at buf[k * nseq + s]. Radix-16 passes while 16 divides the
+// remaining length, then one radix-8, -4 or -2 pass; each butterfly's DFT is
+// done in registers. twl (LDS) holds w^k = exp(-2 pi i k / P), k < P; the
+// inverse uses the conjugate (unnormalised).
+// complex values a thread holds per pass (16: one radix-16 butterfly)
 template <typename T>
 constexpr int kVals = 16;
 constexpr int kFftMaxThreads = 512;
 
+// x * (-i) forward, x * (+i) inverse
+template <typename T>
+__device__ __attribute__((always_inline)) inline C<T> rot90(C<T> x, bool inv) {
+  return inv ? mk<T>(-x.y, x.x) : mk<T>(x.y, -x.x);
+}
+template <typename T>
+__device__ __attribute__((always_inline)) inline void dft2(C<T>& a, C<T>& b) {
+  const C<T> t = a;
+  a = cadd<T>(t, b);
+  b = csub<T>(t, b);
+}
+// in-place 4-point DFT of x[0], x[s], x[2s], x[3s]
+template <typename T>
+__device__ __attribute__((always_inline)) inline void dft4(C<T>* x, int s, bool inv) {
+  const C<T> a0 = cadd<T>(x[0], x[2 * s]), a1 = csub<T>(x[0], x[2 * s]);
+  const C<T> a2 = cadd<T>(x[s], x[3 * s]), a3 = rot90<T>(csub<T>(x[s], x[3 * s]), inv);
+  x[0] = cadd<T>(a0, a2);
+  x[2 * s] = csub<T>(a0, a2);
+  x[s] = cadd<T>(a1, a3);
+  x[3 * s] = csub<T>(a1, a3);
+}
+// exp(-+ 2 pi i m / 16), m = 0..15, for the internal twiddles of the
+// radix-8/16 DFTs (cos and sin of m pi / 8 from cos(pi/8), sin(pi/8), 1/sqrt 2)
+template <typename T>
+__device__ __attribute__((always_inline)) inline C<T> w16(int m, bool inv) {
+  constexpr double a = 0.92387953251128675613, b = 0.38268343236508977173, h = 0.70710678118654752440;
+  constexpr double cs[16] = {1, a, h, b, 0, -b, -h, -a, -1, -a, -h, -b, 0, b, h, a};
+  constexpr double sn[16] = {0, b, h, a, 1, a, h, b, 0, -b, -h, -a, -1, -a, -h, -b};
+  return mk<T>((T)cs[m & 15], inv ? (T)sn[m & 15] : (T)-sn[m & 15]);
+}
+// in-place R-point DFT of x[0..R) in natural order (R = 2, 4, 8, 16)
 template <typename T, int R>
-__device__ inline void lds_fft_pass(C<T>* buf, int P, int nseq, int Ns, const C<T>* __restrict__ tw, bool inv) {
+__device__ __attribute__((always_inline)) inline void dft(C<T>* x, bool inv) {
+  if constexpr (R == 2) {
+    dft2<T>(x[0], x[1]);
+  } else if constexpr (R == 4) {
+    dft4<T>(x, 1, inv);
+  } else if constexpr (R == 8) {
+    // n = 2a + b: 4-point DFTs over a, twiddles w8^(b c), 2-point DFTs over b
+    dft4<T>(x, 2, inv);
+    dft4<T>(x + 1, 2, inv);
+#pragma unroll
+    for (int c = 1; c < 4; ++c) x[2 * c + 1] = cmul<T>(x[2 * c + 1], w16<T>(2 * c, inv));
+    C<T> y[8];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      C<T> a = x[2 * c], b = x[2 * c + 1];
+      dft2<T>(a, b);
+      y[c] = a;
+      y[c + 4] = b;
+    }
+#pragma unroll
+    for (int k = 0; k < 8; ++k) x[k] = y[k];
+  } else {
+    // n = 4a + b: 4-point DFTs over a, twiddles w16^(b c), 4-point DFTs over b
+#pragma unroll
+    for (int b = 0; b < 4; ++b) dft4<T>(x + b, 4, inv);
+#pragma unroll
+    for (int b = 1; b < 4; ++b)
+#pragma unroll
+      for (int c = 1; c < 4; ++c) x[4 * c + b] = cmul<T>(x[4 * c + b], w16<T>(b * c, inv));
+#pragma unroll
+    for (int c = 0; c < 4; ++c) dft4<T>(x + 4 * c, 1, inv);
+    // element (c, d) sits at 4 c + d and is output c + 4 d: transpose
+    C<T> y[16];
+#pragma unroll
+    for (int c = 0; c < 4; ++c)
+#pragma unroll
+      for (int d = 0; d < 4; ++d) y[c + 4 * d] = x[4 * c + d];
+#pragma unroll
+    for (int k = 0; k < 16; ++k) x[k] = y[k];
+  }
+}
+
+template <typename T, int R>
+__device__ inline void lds_fft_pass(C<T>* buf, int P, int nseq, int Ns, const C<T>* twl, bool inv) {
   constexpr int NB = kVals<T> / R;  // butterflies per thread
   const int tid = threadIdx.x, nt = blockDim.x;
   const int nbf = P / R;
@@ -56,25 +132,11 @@ __device__ inline void lds_fft_pass(C<T>* buf, int P, int nseq, int Ns, const C<
     C<T>* x = v[q];
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      C<T> w = tw[r * step];
+      C<T> w = twl[r * step];
       if (inv) w.y = -w.y;
       x[r] = cmul<T>(x[r], w);
     }
-    if (R == 4) {
-      const C<T> a0 = cadd<T>(x[0], x[2]), a1 = csub<T>(x[0], x[2]);
-      const C<T> a2 = cadd<T>(x[1], x[3]);
-      const C<T> d = csub<T>(x[1], x[3]);
-      // times -i (forward) or +i (inverse)
-      const C<T> a3 = inv ? mk<T>(-d.y, d.x) : mk<T>(d.y, -d.x);
-      x[0] = cadd<T>(a0, a2);
-      x[2] = csub<T>(a0, a2);
-      x[1] = cadd<T>(a1, a3);
-      x[3] = csub<T>(a1, a3);
-    } else {
-      const C<T> a0 = cadd<T>(x[0], x[1]), a1 = csub<T>(x[0], x[1]);
-      x[0] = a0;
-      x[1] = a1;
-    }
+    dft<T, R>(x, inv);
     const int idxD = (j / Ns) * Ns * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) buf[(idxD + r * Ns) * nseq + s] = x[r];
@@ -82,15 +144,22 @@ __device__ inline void lds_fft_pass(C<T>* buf, int P, int nseq, int Ns, const C<
   __syncthreads();
 }
 
-// In-place Stockham FFT (radix 4, a final radix 2 when log2 P is odd) of nseq
-// interleaved sequences: element k of sequence s lives at buf[k * nseq + s].
-// tw[k] = exp(-2 pi i k / P); the inverse uses the conjugate (unnormalised).
-// Needs blockDim.x >= nseq * P / kVals<T>.
+// In-place FFT of nseq interleaved length-P sequences (P a power of two);
+// twl: the length-P twiddle table in LDS. Needs blockDim.x >= nseq * P / kVals<T>.
 template <typename T>
-__device__ void lds_fft(C<T>* buf, int P, int nseq, const C<T>* __restrict__ tw, bool inv) {
+__device__ void lds_fft(C<T>* buf, int P, int nseq, const C<T>* twl, bool inv) {
   int Ns = 1;
-  for (; P / Ns >= 4; Ns *= 4) lds_fft_pass<T, 4>(buf, P, nseq, Ns, tw, inv);
-  if (Ns < P) lds_fft_pass<T, 2>(buf, P, nseq, Ns, tw, inv);
+  for (; P / Ns >= 16; Ns *= 16) lds_fft_pass<T, 16>(buf, P, nseq, Ns, twl, inv);
+  const int rem = P / Ns;
+  if (rem == 8) lds_fft_pass<T, 8>(buf, P, nseq, Ns, twl, inv);
+  else if (rem == 4) lds_fft_pass<T, 4>(buf, P, nseq, Ns, twl, inv);
+  else if (rem == 2) lds_fft_pass<T, 2>(buf, P, nseq, Ns, twl, inv);
+}
+
+// the twiddle table into LDS (no barrier: the caller's next one covers it)
+template <typename T>
+__device__ inline void load_twiddles(C<T>* twl, const C<T>* __restrict__ tw, int P) {
+  for (int i = threadIdx.x; i < P; i += blockDim.x) twl[i] = tw[i];
 }
 
 // ---- pass 1: rows of (s .* x), zero-padded to P -----------------------------
@@ -99,6 +168,8 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_forward(const C<T>* __re
                               int S, const C<T>* __restrict__ tw, C<T>* __restrict__ X) {
   extern __shared__ unsigned char smem_raw[];
   C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+  C<T>* twl = buf + S * P;
+  load_twiddles<T>(twl, tw, P);
   const int rhs = blockIdx.y;
   const int i0 = blockIdx.x * S;
   const size_t nn = (size_t)n * n;
@@ -114,7 +185,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_forward(const C<T>* __re
     buf[k * S + s] = v;
   }
   __syncthreads();
-  lds_fft<T>(buf, P, S, tw, false);
+  lds_fft<T>(buf, P, S, twl, false);
   const int ntile = P / S;
   C<T>* Xr = X + (size_t)rhs * ntile * n * S;
   for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
@@ -131,6 +202,8 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_col_convolve(C<T>* __restric
                                int S, const C<T>* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+  C<T>* twl = buf + S * P;
+  load_twiddles<T>(twl, tw, P);
   const int tile = blockIdx.x, rhs = blockIdx.y;
   const int ntile = P / S;
   C<T>* Xt = X + ((size_t)rhs * ntile + tile) * n * S;
@@ -139,17 +212,19 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_col_convolve(C<T>* __restric
     buf[idx] = row < n ? Xt[idx] : mk<T>(0, 0);
   }
   __syncthreads();
-  lds_fft<T>(buf, P, S, tw, false);
+  lds_fft<T>(buf, P, S, twl, false);
+  // times khat: k depends on |delta| only, so khat is symmetric and column c
+  // of the quadrant is its row c; consecutive threads walk along it
   const int half = P / 2 + 1;
   for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
-    const int r = idx / S, s = idx % S;
+    const int s = idx / P, r = idx % P;
     const int col = tile * S + s;
     const int kr = r <= P - r ? r : P - r;
     const int kc = col <= P - col ? col : P - col;
-    buf[idx] = cmul<T>(buf[idx], khat[(size_t)kr * half + kc]);
+    buf[r * S + s] = cmul<T>(buf[r * S + s], khat[(size_t)kc * half + kr]);
   }
   __syncthreads();
-  lds_fft<T>(buf, P, S, tw, true);
+  lds_fft<T>(buf, P, S, twl, true);
   for (int idx = threadIdx.x; idx < S * n; idx += blockDim.x) Xt[idx] = buf[idx];
 }
 
@@ -160,6 +235,8 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __re
                               C<T>* __restrict__ y) {
   extern __shared__ unsigned char smem_raw[];
   C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+  C<T>* twl = buf + S * P;
+  load_twiddles<T>(twl, tw, P);
   const int rhs = blockIdx.y;
   const int i0 = blockIdx.x * S;
   const int ntile = P / S;
@@ -171,7 +248,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __re
     buf[(tile * S + kk) * S + s] = row < n ? Xr[((size_t)tile * n + row) * S + kk] : mk<T>(0, 0);
   }
   __syncthreads();
-  lds_fft<T>(buf, P, S, tw, true);
+  lds_fft<T>(buf, P, S, twl, true);
   const size_t nn = (size_t)n * n;
   for (int idx = threadIdx.x; idx < S * n; idx += blockDim.x) {
     const int s = idx / n, k = idx % n;
@@ -199,13 +276,15 @@ __global__ void k_wrap_table(const double2* __restrict__ kq, int n, int P, doubl
 __global__ __launch_bounds__(kFftMaxThreads) void k_fft_rows_full(double2* __restrict__ W, int P, int S, const double2* __restrict__ tw) {
   extern __shared__ unsigned char smem_raw[];
   double2* buf = reinterpret_cast<double2*>(smem_raw);
+  double2* twl = buf + S * P;
+  load_twiddles<double>(twl, tw, P);
   const int r0 = blockIdx.x * S;
   for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
     const int s = idx / P, k = idx % P;
     buf[k * S + s] = W[(size_t)(r0 + s) * P + k];
   }
   __syncthreads();
-  lds_fft<double>(buf, P, S, tw, false);
+  lds_fft<double>(buf, P, S, twl, false);
   for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
     const int s = idx / P, k = idx % P;
     W[(size_t)(r0 + s) * P + k] = buf[k * S + s];
@@ -217,13 +296,15 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_cols_full(double2* __res
                                 double2* __restrict__ khat, float2* __restrict__ khat32) {
   extern __shared__ unsigned char smem_raw[];
   double2* buf = reinterpret_cast<double2*>(smem_raw);
+  double2* twl = buf + S * P;
+  load_twiddles<double>(twl, tw, P);
   const int c0 = blockIdx.x * S;
   for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
     const int r = idx / S, s = idx % S;
     buf[idx] = W[(size_t)r * P + c0 + s];
   }
   __syncthreads();
-  lds_fft<double>(buf, P, S, tw, false);
+  lds_fft<double>(buf, P, S, twl, false);
   const int half = P / 2 + 1;
   for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
     const int r = idx / S, s = idx % S;
@@ -237,7 +318,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_cols_full(double2* __res
 
 template <typename T>
 int seq_per_block(int P) {
-  int S = 131072 / (P * (int)sizeof(C<T>));
+  int S = (163840 - P * (int)sizeof(C<T>)) / (P * (int)sizeof(C<T>));
   if (S > 8) S = 8;
   if (S * P > kVals<T> * kFftMaxThreads) S = kVals<T> * kFftMaxThreads / P;
   if (S > P) S = P;
@@ -276,7 +357,7 @@ hipError_t launch_convolve(const C<T>* x, const T* m, int n, int nrhs, const C<T
   const int P = fft_len(n);
   const int S = seq_per_block<T>(P);
   const int nt = threads_for<T>(S, P);
-  const size_t lds = (size_t)S * P * sizeof(C<T>);
+  const size_t lds = (size_t)(S + 1) * P * sizeof(C<T>);
   hipError_t e;
   if ((e = allow_lds(k_row_forward<T>, lds)) != hipSuccess) return e;
   if ((e = allow_lds(k_col_convolve<T>, lds)) != hipSuccess) return e;
@@ -299,7 +380,7 @@ hipError_t launch_green_spectrum(const double2* kq, int n, const double2* tw, do
   const int P = fft_len(n);
   const int S = seq_per_block<double>(P);
   const int nt = threads_for<double>(S, P);
-  const size_t lds = (size_t)S * P * sizeof(double2);
+  const size_t lds = (size_t)(S + 1) * P * sizeof(double2);
   hipError_t e;
   if ((e = allow_lds(k_fft_rows_full, lds)) != hipSuccess) return e;
   if ((e = allow_lds(k_fft_cols_full, lds)) != hipSuccess) return e;

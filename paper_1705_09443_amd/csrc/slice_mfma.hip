@@ -304,10 +304,11 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
   }
 }
 
+// steps of loads in flight (one wave per SIMD leaves the whole register file)
 template <typename T>
-constexpr int pf16 = sizeof(T) == 4 ? 4 : 2;
+constexpr int pf16 = sizeof(T) == 4 ? 8 : 4;
 template <typename T>
-constexpr int pf32 = sizeof(T) == 4 ? 2 : 1;
+constexpr int pf32 = sizeof(T) == 4 ? 4 : 2;
 
 // blockIdx.x: group of 4 column tiles (one per wave); blockIdx.y: slice, the
 // last of the range first (the 32-line class, the longest solve).
