@@ -156,10 +156,51 @@ __device__ void lds_fft(C<T>* buf, int P, int nseq, const C<T>* twl, bool inv) {
   else if (rem == 2) lds_fft_pass<T, 2>(buf, P, nseq, Ns, twl, inv);
 }
 
-// the twiddle table into LDS (no barrier: the caller's next one covers it)
+// the twiddle table into LDS (no barrier: the caller's next one covers it);
+// P <= kVals * blockDim.x, all of a thread's loads in flight at once
 template <typename T>
 __device__ inline void load_twiddles(C<T>* twl, const C<T>* __restrict__ tw, int P) {
-  for (int i = threadIdx.x; i < P; i += blockDim.x) twl[i] = tw[i];
+  constexpr int V = kVals<T>;
+  C<T> v[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int i = threadIdx.x + q * blockDim.x;
+    v[q] = tw[i < P ? i : 0];
+  }
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int i = threadIdx.x + q * blockDim.x;
+    if (i < P) twl[i] = v[q];
+  }
+}
+
+// Global <-> LDS copies: every thread moves at most kVals elements; the
+// loops are unrolled with clamped, unconditional loads (values masked after)
+// so that all of a thread's loads are in flight before the first is used.
+
+// S rows of (s .* x) [+ zero padding to P] into buf (k * S + s)
+template <typename T, bool HASM>
+__device__ __attribute__((always_inline)) inline void load_rows(C<T>* buf, const C<T>* __restrict__ xr,
+                                                                const T* __restrict__ m, int n, int P, int S,
+                                                                int i0) {
+  constexpr int V = kVals<T>;
+  const int total = S * P;
+  C<T> v[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    const int sq = idx / P, k = idx % P, row = i0 + sq;
+    const bool ok = idx < total && k < n && row < n;
+    const size_t o = (size_t)(row < n ? row : n - 1) * n + (k < n ? k : n - 1);
+    C<T> w = xr[o];
+    if (HASM) w = cscale<T>(w, m[o]);
+    v[q] = ok ? w : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < total) buf[(idx % P) * S + idx / P] = v[q];
+  }
 }
 
 // ---- pass 1: rows of (s .* x), zero-padded to P -----------------------------
@@ -174,25 +215,21 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_forward(const C<T>* __re
   const int i0 = blockIdx.x * S;
   const size_t nn = (size_t)n * n;
   const C<T>* xr = x + rhs * nn;
-  for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
-    const int s = idx / P, k = idx % P;
-    const int row = i0 + s;
-    C<T> v = mk<T>(0, 0);
-    if (k < n && row < n) {
-      v = xr[(size_t)row * n + k];
-      if (m) v = cscale<T>(v, m[(size_t)row * n + k]);
-    }
-    buf[k * S + s] = v;
-  }
+  if (m)
+    load_rows<T, true>(buf, xr, m, n, P, S, i0);
+  else
+    load_rows<T, false>(buf, xr, m, n, P, S, i0);
   __syncthreads();
   lds_fft<T>(buf, P, S, twl, false);
   const int ntile = P / S;
   C<T>* Xr = X + (size_t)rhs * ntile * n * S;
-  for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
+#pragma unroll
+  for (int q = 0; q < kVals<T>; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
     const int tile = idx / (S * S), within = idx % (S * S);
-    const int s = within / S, kk = within % S;
-    const int row = i0 + s;
-    if (row < n) Xr[((size_t)tile * n + row) * S + kk] = buf[(tile * S + kk) * S + s];
+    const int sq = within / S, kk = within % S;
+    const int row = i0 + sq;
+    if (idx < S * P && row < n) Xr[((size_t)tile * n + row) * S + kk] = buf[(tile * S + kk) * S + sq];
   }
 }
 
@@ -200,32 +237,61 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_forward(const C<T>* __re
 template <typename T>
 __global__ __launch_bounds__(kFftMaxThreads) void k_col_convolve(C<T>* __restrict__ X, const C<T>* __restrict__ khat, int n, int P,
                                int S, const C<T>* __restrict__ tw) {
+  constexpr int V = kVals<T>;
   extern __shared__ unsigned char smem_raw[];
   C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
   C<T>* twl = buf + S * P;
   load_twiddles<T>(twl, tw, P);
   const int tile = blockIdx.x, rhs = blockIdx.y;
   const int ntile = P / S;
+  const int total = S * P, live = S * n;
   C<T>* Xt = X + ((size_t)rhs * ntile + tile) * n * S;
-  for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
-    const int row = idx / S;
-    buf[idx] = row < n ? Xt[idx] : mk<T>(0, 0);
+  {
+    C<T> v[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      const C<T> w = Xt[idx < live ? idx : 0];
+      v[q] = idx < live ? w : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      if (idx < total) buf[idx] = v[q];
+    }
   }
   __syncthreads();
   lds_fft<T>(buf, P, S, twl, false);
   // times khat: k depends on |delta| only, so khat is symmetric and column c
   // of the quadrant is its row c; consecutive threads walk along it
-  const int half = P / 2 + 1;
-  for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
-    const int s = idx / P, r = idx % P;
-    const int col = tile * S + s;
-    const int kr = r <= P - r ? r : P - r;
-    const int kc = col <= P - col ? col : P - col;
-    buf[r * S + s] = cmul<T>(buf[r * S + s], khat[(size_t)kc * half + kr]);
+  {
+    const int half = P / 2 + 1;
+    C<T> kv[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      const int sq = idx / P, r = idx % P;
+      const int col = tile * S + (idx < total ? sq : 0);
+      const int kr = r <= P - r ? r : P - r;
+      const int kc = col <= P - col ? col : P - col;
+      kv[q] = khat[(size_t)kc * half + kr];
+    }
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      if (idx < total) {
+        const int sq = idx / P, r = idx % P;
+        buf[r * S + sq] = cmul<T>(buf[r * S + sq], kv[q]);
+      }
+    }
   }
   __syncthreads();
   lds_fft<T>(buf, P, S, twl, true);
-  for (int idx = threadIdx.x; idx < S * n; idx += blockDim.x) Xt[idx] = buf[idx];
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < live) Xt[idx] = buf[idx];
+  }
 }
 
 // ---- pass 3: inverse rows and epilogue y = a x + coef * conv --------------
@@ -233,6 +299,7 @@ template <typename T>
 __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __restrict__ X, const C<T>* __restrict__ x, int n, int P,
                               int S, const C<T>* __restrict__ tw, T a, T coef,
                               C<T>* __restrict__ y) {
+  constexpr int V = kVals<T>;
   extern __shared__ unsigned char smem_raw[];
   C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
   C<T>* twl = buf + S * P;
@@ -240,24 +307,49 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __re
   const int rhs = blockIdx.y;
   const int i0 = blockIdx.x * S;
   const int ntile = P / S;
+  const int total = S * P;
   const C<T>* Xr = X + (size_t)rhs * ntile * n * S;
-  for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
-    const int tile = idx / (S * S), within = idx % (S * S);
-    const int s = within / S, kk = within % S;
-    const int row = i0 + s;
-    buf[(tile * S + kk) * S + s] = row < n ? Xr[((size_t)tile * n + row) * S + kk] : mk<T>(0, 0);
+  {
+    C<T> v[V];
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      const int tl = idx / (S * S), within = idx % (S * S);
+      const int sq = within / S, kk = within % S;
+      const int row = i0 + sq;
+      const bool ok = idx < total && row < n;
+      const C<T> w = Xr[ok ? ((size_t)tl * n + row) * S + kk : 0];
+      v[q] = ok ? w : mk<T>(0, 0);
+    }
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      if (idx < total) {
+        const int tl = idx / (S * S), within = idx % (S * S);
+        buf[(tl * S + within % S) * S + within / S] = v[q];
+      }
+    }
   }
   __syncthreads();
   lds_fft<T>(buf, P, S, twl, true);
   const size_t nn = (size_t)n * n;
-  for (int idx = threadIdx.x; idx < S * n; idx += blockDim.x) {
-    const int s = idx / n, k = idx % n;
-    const int row = i0 + s;
-    if (row >= n) continue;
-    const size_t o = rhs * nn + (size_t)row * n + k;
-    C<T> v = cscale<T>(buf[k * S + s], coef);
-    if (a != T(0)) v = cadd<T>(v, cscale<T>(x[o], a));
-    y[o] = v;
+  const int live = S * n;
+  C<T> xv[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    const int sq = idx / n, k = idx % n, row = i0 + sq;
+    const bool ok = idx < live && row < n;
+    xv[q] = a != T(0) ? x[ok ? rhs * nn + (size_t)row * n + k : 0] : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    const int sq = idx / n, k = idx % n, row = i0 + sq;
+    if (idx < live && row < n) {
+      const size_t o = rhs * nn + (size_t)row * n + k;
+      y[o] = cadd<T>(cscale<T>(buf[k * S + sq], coef), cscale<T>(xv[q], a));
+    }
   }
 }
 
