@@ -44,6 +44,9 @@ def parse():
     p.add_argument("--nrhs", type=int, default=None)
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--copy-gib", type=float, default=0.0,
+                   help="first run one plain device copy of this many GiB (a known-size dispatch that "
+                        "calibrates hardware byte counters in a profile of this command)")
     return p.parse_args()
 
 
@@ -67,9 +70,13 @@ def work_per_column(solver, kind: str, cbytes: int, n: int):
     stencil_Q: read n^2, write L^2.
     """
     L, nl = solver.L, solver.nslices
-    if kind == "slice_solves":
+    if kind in ("slice_solves", "slice_solves_last"):
+        # the last slice runs on its own stream beside the others when l > 2
+        ks = range(nl)
+        if nl > 2:
+            ks = [nl - 1] if kind == "slice_solves_last" else range(nl - 1)
         fl = sh = col = 0.0
-        for k in range(nl):
+        for k in ks:
             lo, hi, naux = solver.slice_bounds(k)
             tw = hi - lo + 1
             t = tw + naux
@@ -93,28 +100,44 @@ def work_per_column(solver, kind: str, cbytes: int, n: int):
     return 0.0, 0.0, 0.0
 
 
+# HBM bytes per launch from hardware counters (FETCH_SIZE + WRITE_SIZE, each
+# calibrated on a plain copy of known size), for the 1023^2 64-wave mixed
+# workload: see profiles/c2_mixed_64rhs_hbm_counters.md. Keyed by kind and
+# precision; valid only for the kernels as they were when measured.
+MEASURED_TRAFFIC = {("interface", 8): 10.47e9}
+
+# kinds that run on the second stream, overlapped with the main one
+CONCURRENT = ("slice_solves_last",)
+# published MI355X dense matrix-core peaks (TFLOP/s): fp32 157.3, fp64 78.6
+MFMA_PEAK = {8: 157.3, 16: 78.6}
+
+
 def roofline(solver, prof, cbytes: int, n: int):
-    """Roofline entry of the kind with the largest total time: algorithmic
-    work per launch (mean columns per launch x per-column work + shared work)
-    over the mean event-timed launch duration, against the HBM or the vector
-    ALU peak, whichever bounds the work at that intensity."""
-    dominant = max(prof, key=lambda k: prof[k][1])
+    """Roofline entry of the main-stream kind with the largest total time:
+    algorithmic work per launch (mean columns per launch x per-column work +
+    shared work) over the mean event-timed launch duration, against the HBM
+    peak or the arithmetic peak of the units the kernel runs on (matrix cores
+    for the batched interface products and slice solves, else vector ALU),
+    whichever bounds the work at that intensity."""
+    dominant = max((k for k in prof if k not in CONCURRENT), key=lambda k: prof[k][1])
     launches, total_ms, columns = prof[dominant]
     avg_ms = total_ms / launches
     cols = columns / launches
     fl, sh, colb = work_per_column(solver, dominant, cbytes, n)
     flops = fl * cols
     nbytes = sh + colb * cols
-    ridge = ALU_PEAK[cbytes] * 1e12 / (HBM_PEAK_GBS * 1e9)
+    mfma = (dominant == "interface" and cols > 4) or (dominant.startswith("slice_solves") and cols > 8)
+    peak = MFMA_PEAK[cbytes] if mfma else ALU_PEAK[cbytes]
+    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
     intensity = flops / nbytes if nbytes else float("inf")
     if intensity > ridge:
         achieved = flops / (avg_ms * 1e-3) / 1e12
-        out = {"bound": "alu", "achieved": achieved, "peak": ALU_PEAK[cbytes], "unit": "TFLOP/s"}
+        out = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
     else:
         achieved = nbytes / (avg_ms * 1e-3) / 1e9
         out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
     out["frac"] = out["achieved"] / out["peak"]
-    out["traffic"] = None
+    out["traffic"] = MEASURED_TRAFFIC.get((dominant, cbytes)) if n == 1023 else None
     out.update({"kernel": dominant, "avg_launch_ms": avg_ms, "mean_columns_per_launch": cols,
                 "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
                 "flop_per_byte": intensity})
@@ -165,6 +188,14 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
+    if args.copy_gib > 0:
+        nel = int(args.copy_gib * 2 ** 30) // 8
+        src = torch.ones(nel, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(f"[bench] calibration copy of {nel * 8} bytes", file=sys.stderr, flush=True)
+        del src, dst
     wl2 = workloads.workload("C2")
     wl1 = workloads.workload("C1")
     if args.n:
