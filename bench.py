@@ -9,7 +9,10 @@ the preconditioner (Q stencil, slice solves, interface recurrences, slice
 solves, extraction) and the FFT operator to every right-hand side still
 running, until every right-hand side meets the tolerance. Inputs are resident
 in HBM before the timed region; setup (Algorithm 1) is timed separately and
-excluded.
+excluded. The batched setup is autotuned (the layer thickness and the kernel
+choice per batch size timed on the device for this batch; --no-autotune keeps
+the workload's w = 4 and the default kernels); its setup time includes the
+tuning.
 
 Prints one JSON line. Besides the contract fields it carries the float64
 form (same medium, one wave), per-kind kernel times from HIP events recorded
@@ -44,6 +47,8 @@ def parse():
     p.add_argument("--nrhs", type=int, default=None)
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-autotune", action="store_true",
+                   help="batched leg at the workload's w and the default kernels instead of autotuned ones")
     p.add_argument("--copy-gib", type=float, default=0.0,
                    help="first run one plain device copy of this many GiB (a known-size dispatch that "
                         "calibrates hardware byte counters in a profile of this command)")
@@ -211,11 +216,19 @@ def main():
     # ---- mixed precision, batched (the headline) ----
     uinc2 = torch.as_tensor(wl2.incident(), device=dev)
     t0 = time.perf_counter()
-    mixed = LSSolver(md, wl2.omega, wl2.pml_width, wl2.layer_thickness, precision="mixed",
-                     restart=wl2.restart)
+    if args.no_autotune:
+        mixed = LSSolver(md, wl2.omega, wl2.pml_width, wl2.layer_thickness, precision="mixed",
+                         restart=wl2.restart)
+    else:
+        # w and the kernel choice per batch size timed on the device for this batch
+        mixed = LSSolver(md, wl2.omega, wl2.pml_width, None, precision="mixed", restart=wl2.restart,
+                         autotune=wl2.nrhs)
     torch.cuda.synchronize()
     setup_mixed = time.perf_counter() - t0
-    print(f"[bench] mixed setup {setup_mixed:.2f} s (n={n}, slices={mixed.nslices})", file=sys.stderr, flush=True)
+    wl2 = dataclasses.replace(wl2, layer_thickness=mixed.layer_thickness)
+    tuning = mixed.tuning()
+    print(f"[bench] mixed setup {setup_mixed:.2f} s (n={n}, w={mixed.layer_thickness}, slices={mixed.nslices})",
+          file=sys.stderr, flush=True)
     for i in range(args.warmup):
         u, info = mixed.solve(uinc2, "incident", wl2.tol)
         print(f"[bench] warmup {i}: iterations {sorted(set(x.iterations for x in info))}", file=sys.stderr,
@@ -252,10 +265,16 @@ def main():
         "data": "synthetic: seeded Gaussian-bump medium and plane waves",
         "config": {"workload": (f"2D {n}^2, omega=2pi*{wl2.ppw_omega:g}, 32 Gaussian bumps (seed 0), {wl2.nrhs} "
                                 f"plane waves theta_j=2pi j/{wl2.nrhs}, mixed precision, b={wl2.pml_width}, "
-                                f"w={wl2.layer_thickness}, restart {wl2.restart}, tol {wl2.tol}"),
+                                f"w={wl2.layer_thickness}{'' if args.no_autotune else ' (autotuned)'}, "
+                                f"restart {wl2.restart}, tol {wl2.tol}"),
                    "n": n, "nrhs": wl2.nrhs, "omega": wl2.omega, "precision": "mixed"},
         "iterations": {"min": min(iters), "max": max(iters), "mean": sum(iters) / len(iters)},
         "setup_s": {"mixed": setup_mixed},
+        "autotune": None if args.no_autotune else {
+            "layers": [{"w": r[0], "slices": r[1], "iterations": r[2], "setup_ms": r[3], "solve_ms": r[4]}
+                       for r in tuning["layers"]],
+            "kernels": [{"nrhs": r[0], "slice_kernel": r[1], "iface_kernel": r[2], "apply_ms": r[3]}
+                        for r in tuning["kernels"]]},
         "kernels": kernels,
         "roofline": roof,
     }

@@ -69,7 +69,9 @@ typedef struct {
   int max_iters;     /* total Arnoldi steps per right-hand side (default 1000) */
   double pml_C;      /* PML strength C of Sec. 2.2.2 (default 10) */
   int freq_samples;  /* local-frequency samples for the auxiliary PML (0: n, Sec. 2.3) */
-  int autotune;      /* reserved, 0 */
+  int autotune;      /* 0: no tuning. k > 0: tune for batches of k right-hand sides
+                        (ls_setup: the layer thickness when layer_thickness <= 0, and the
+                        kernel choice per batch size; see "Autotuning" below) */
   void* hip_stream;  /* hipStream_t to enqueue on (NULL: default stream) */
   int sweep_schedule;  /* LS_SWEEP_INTERFACE (default): all slice solves at once plus the
                           interface recurrences; LS_SWEEP_SEQUENTIAL: Algorithm 2 slice by slice.
@@ -98,7 +100,8 @@ void ls_default_options(ls_options* opts);
  *   m_dev            float64 [n][n] perturbation m = 1 - 1/c^2 on the interior grid;
  *                    every value finite and < 1
  *   pml_width        b >= 1, PML width in cells (global and auxiliary)
- *   layer_thickness  w >= 1, interior lines per slice (the last slice takes the remainder)
+ *   layer_thickness  w >= 1, interior lines per slice (the last slice takes the remainder);
+ *                    <= 0 with opts->autotune > 0: chosen by timing (Autotuning below)
  *   opts             NULL for defaults
  *   out              receives the handle (NULL on failure)
  */
@@ -189,6 +192,65 @@ ls_status ls_get_stencils(const ls_handle* h, double* alpha_host, double* beta_h
 
 /* Sample index k* for every extended-grid point, int32 [L][L] on the host. */
 ls_status ls_get_sample_map(const ls_handle* h, int* kmap_host);
+
+/* ---- Autotuning (batching form: layer thickness and kernel choice) ----
+ *
+ * The layer thickness w is a free parameter of the method: the remarks closing
+ * Sec. 2.3 allow any slice width, and argue for w = b from the operation counts
+ * of a serial setup and apply; on this device the best w follows from the
+ * kernels' shapes (slices of at most 16 or 32 lines) and is measured. With
+ * opts->autotune = k > 0 and layer_thickness <= 0, ls_setup sets up every
+ * candidate w (ls_layer_candidates), times one solve of k plane waves
+ * u_I = exp(i omega (cos t_j x1 + sin t_j x2)), t_j = 2 pi j / k, to a 1e-6
+ * relative residual on the device, and keeps the fastest w. For the kept
+ * setup it then times one preconditioner apply per kernel choice at batch
+ * sizes 1, 2, 3, 4, 6, 8, 12, 16, 24, 32, ... up to k, and every batch size
+ * takes the choice measured fastest at the nearest measured size at or above
+ * it (the largest measured size for larger batches). Tuning adds a few setups
+ * and solves to ls_setup; results are identical up to rounding whatever the
+ * choice (each choice is a different schedule of the same arithmetic).
+ */
+
+/* Host-only: the layer thicknesses w >= 2 for which every slice subproblem of
+ * an n-point grid with PML width b has at most 32 lines (the slice kernels'
+ * limit), ascending. out_host: array of cap entries (may be NULL with cap 0);
+ * *count receives the number of candidates (which may exceed cap). */
+ls_status ls_layer_candidates(int n, int pml_width, int* out_host, int cap, int* count);
+
+typedef struct {
+  int layer_thickness;  /* candidate w */
+  int nslices;          /* floor((n+2)/w) */
+  int iterations;       /* most Arnoldi steps over the probe batch */
+  double setup_ms;      /* its setup (Algorithm 1) */
+  double solve_ms;      /* the probe solve */
+} ls_tune_layer;
+
+typedef struct {
+  int nrhs;          /* batch size measured */
+  int slice_kernel;  /* 1, 4, 8: slice solves on the vector ALUs, that many right-hand
+                        sides per workgroup; 16: on the matrix cores, 16-column tiles */
+  int iface_kernel;  /* 0: interface products as vector dot products (nrhs <= 4);
+                        1: on the matrix cores */
+  double apply_ms;   /* one preconditioner apply with this choice */
+} ls_tune_kernels;
+
+/* What the autotuner measured: the candidates of w (nothing when w was given)
+ * and the kernel choice kept at each measured batch size. Host arrays of wcap
+ * and kcap entries (either may be NULL with cap 0); *nw and *nk receive the
+ * counts. */
+ls_status ls_get_tuning(const ls_handle* h, ls_tune_layer* w_host, int wcap, int* nw, ls_tune_kernels* k_host,
+                        int kcap, int* nk);
+
+/* Force the kernel choice for batches of nrhs right-hand sides (1 <= nrhs <=
+ * 256; batches above 256 follow 256), or for every batch size with nrhs = 0.
+ * slice_kernel in {1, 4, 8, 16}, or 0 to restore the default (iface_kernel is
+ * then ignored); iface_kernel 0 or 1, and 0 only for batches of at most 4
+ * (with nrhs = 0, larger batches keep 1). The defaults, the
+ * fastest measured on MI355X at n = 1023, b = 12, w = 4: LS_MIXED slice 1 up
+ * to 2 right-hand sides, 4 up to 4, 16 above, interface 1; LS_FP64 slice 1,
+ * interface 0 for one right-hand side, slice 4 for two, 16 above, interface 1
+ * from two. */
+ls_status ls_set_kernels(ls_handle* h, int nrhs, int slice_kernel, int iface_kernel);
 
 /* ---- Kernel timing (HIP events recorded on the handle's stream) ---- */
 

@@ -25,7 +25,7 @@ from . import _lib
 from ._lib import (LS_FP64, LS_MIXED, LS_RHS_INCIDENT, LS_RHS_SOURCE, LsError, LsGrid, LsOptions,
                    LsRhsInfo, LsSetupInfo)
 
-__all__ = ["LSSolver", "LSSolve", "RhsInfo", "LsError", "host_tables"]
+__all__ = ["LSSolver", "LSSolve", "RhsInfo", "LsError", "host_tables", "layer_candidates"]
 
 _PRECISIONS = {"fp64": LS_FP64, "mixed": LS_MIXED}
 
@@ -51,12 +51,25 @@ def _need(t: torch.Tensor, dtype, shape, name):
     return t.contiguous()
 
 
+def layer_candidates(n: int, pml_width: int):
+    """Layer thicknesses w >= 2 whose slices all fit the slice kernels (host only)."""
+    lib = _lib.load()
+    cnt = _lib.c_int()
+    _lib.check(lib.ls_layer_candidates(n, pml_width, None, 0, ctypes_byref(cnt)), "ls_layer_candidates")
+    out = (_lib.c_int * max(1, cnt.value))()
+    _lib.check(lib.ls_layer_candidates(n, pml_width, out, cnt.value, ctypes_byref(cnt)), "ls_layer_candidates")
+    return list(out[:cnt.value])
+
+
 class LSSolver:
     """One setup (Algorithm 1) for a medium m; any number of solves."""
 
-    def __init__(self, m: torch.Tensor, omega: float, pml_width: int = 12, layer_thickness: int = 4,
+    def __init__(self, m: torch.Tensor, omega: float, pml_width: int = 12, layer_thickness: Optional[int] = 4,
                  precision: str = "fp64", restart: int = 30, max_iters: int = 1000, pml_C: float = 10.0,
-                 freq_samples: int = 0, schedule: str = "interface"):
+                 freq_samples: int = 0, schedule: str = "interface", autotune: int = 0):
+        """layer_thickness None (with autotune = k > 0): chosen by timing solves of k
+        plane waves on the device; autotune = k > 0 also tunes the kernel choice per
+        batch size up to k (ls_setup, Autotuning)."""
         self._lib = _lib.load()
         if m.dim() != 2 or m.shape[0] != m.shape[1]:
             raise ValueError("m must be [n, n]")
@@ -72,11 +85,13 @@ class LSSolver:
         opts.pml_C = pml_C
         opts.freq_samples = freq_samples
         opts.sweep_schedule = {"interface": 0, "sequential": 1}[schedule]
+        opts.autotune = int(autotune)
         opts.hip_stream = _stream_ptr()
         self._opts = opts
         grid = LsGrid(2, self.n)
         handle = _lib.c_void_p()
-        _lib.check(self._lib.ls_setup(ctypes_byref(grid), self.omega, m.data_ptr(), pml_width, layer_thickness,
+        _lib.check(self._lib.ls_setup(ctypes_byref(grid), self.omega, m.data_ptr(), pml_width,
+                                      0 if layer_thickness is None else int(layer_thickness),
                                       ctypes_byref(opts), ctypes_byref(handle)), "ls_setup")
         self._h = handle
         info = LsSetupInfo()
@@ -85,7 +100,7 @@ class LSSolver:
         self.L = info.L
         self.nslices = info.nslices
         self.pml_width = pml_width
-        self.layer_thickness = layer_thickness
+        self.layer_thickness = info.layer_thickness
 
     # -- lifetime --------------------------------------------------------
     def close(self):
@@ -172,6 +187,25 @@ class LSSolver:
         w = torch.empty_like(v)
         _lib.check(self._lib.ls_slice_solve(self._h, k, v.data_ptr(), nb, w.data_ptr(), code), "ls_slice_solve")
         return w
+
+    # -- autotuning ---------------------------------------------------------
+    def tuning(self):
+        """What the autotuner measured: {"layers": [(w, nslices, iterations, setup_ms,
+        solve_ms)], "kernels": [(nrhs, slice_kernel, iface_kernel, apply_ms)]}."""
+        nw, nk = _lib.c_int(), _lib.c_int()
+        _lib.check(self._lib.ls_get_tuning(self._h, None, 0, ctypes_byref(nw), None, 0, ctypes_byref(nk)),
+                   "ls_get_tuning")
+        ws = (_lib.LsTuneLayer * max(1, nw.value))()
+        ks = (_lib.LsTuneKernels * max(1, nk.value))()
+        _lib.check(self._lib.ls_get_tuning(self._h, ws, nw.value, ctypes_byref(nw), ks, nk.value,
+                                           ctypes_byref(nk)), "ls_get_tuning")
+        return {"layers": [(w.layer_thickness, w.nslices, w.iterations, w.setup_ms, w.solve_ms)
+                           for w in ws[:nw.value]],
+                "kernels": [(k.nrhs, k.slice_kernel, k.iface_kernel, k.apply_ms) for k in ks[:nk.value]]}
+
+    def set_kernels(self, nrhs: int, slice_kernel: int, iface_kernel: int):
+        """Force the kernel choice for batches of nrhs (0: every batch size)."""
+        _lib.check(self._lib.ls_set_kernels(self._h, nrhs, slice_kernel, iface_kernel), "ls_set_kernels")
 
     # -- kernel timing ------------------------------------------------------
     def profile(self, enable: bool = True):

@@ -52,6 +52,15 @@ class LsKernelTime(ctypes.Structure):
                 ("columns", ctypes.c_longlong)]
 
 
+class LsTuneLayer(ctypes.Structure):
+    _fields_ = [("layer_thickness", c_int), ("nslices", c_int), ("iterations", c_int), ("setup_ms", c_double),
+                ("solve_ms", c_double)]
+
+
+class LsTuneKernels(ctypes.Structure):
+    _fields_ = [("nrhs", c_int), ("slice_kernel", c_int), ("iface_kernel", c_int), ("apply_ms", c_double)]
+
+
 class LsError(RuntimeError):
     def __init__(self, status: int, where: str, message: str):
         self.status = status
@@ -79,6 +88,10 @@ _SIGNATURES = {
     "ls_get_sample_map": (c_int, [c_void_p, c_void_p]),
     "ls_profile": (c_int, [c_void_p, c_int]),
     "ls_profile_read": (c_int, [c_void_p, ctypes.POINTER(LsKernelTime), c_int, P_int]),
+    "ls_layer_candidates": (c_int, [c_int, c_int, P_int, c_int, P_int]),
+    "ls_get_tuning": (c_int, [c_void_p, ctypes.POINTER(LsTuneLayer), c_int, P_int, ctypes.POINTER(LsTuneKernels),
+                              c_int, P_int]),
+    "ls_set_kernels": (c_int, [c_void_p, c_int, c_int, c_int]),
     "ls_host_tables": (c_int, [c_int, c_double, c_void_p, c_int, c_int, c_double, c_int, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p, c_void_p]),
 }

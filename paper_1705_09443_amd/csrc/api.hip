@@ -2,6 +2,8 @@
 // flexible GMRES loop in float64 around the applies (Sec. 2.5), the adjoint
 // gradient, and the per-operator entry points.
 #include <algorithm>
+#include <chrono>
+#include <limits>
 #include <cstdio>
 #include <cmath>
 #include <cstring>
@@ -65,6 +67,17 @@ struct DBuf {
     }                                                                               \
   } while (0)
 
+// Kernel choice for a batch of right-hand sides: slice solves on the vector
+// ALUs with 1, 4 or 8 right-hand sides per workgroup, or (16) on the matrix
+// cores in 16-column tiles; interface products as vector dot products (0, at
+// most 4 columns) or on the matrix cores (1).
+struct KernelChoice {
+  int slice;
+  int iface;
+};
+// batch sizes with an entry of their own; larger batches follow the last
+constexpr int kChoiceMax = 256;
+
 }  // namespace
 }  // namespace lsw
 
@@ -85,6 +98,10 @@ struct ls_handle {
   DBuf IM, IP, IN;
   // per slice on the host: line count t and forward factor stride
   std::vector<int> t_host, fstride_host, tw_host;
+  // kernel choice per batch size [0, kChoiceMax], and what the autotuner measured
+  std::vector<KernelChoice> choice;
+  std::vector<ls_tune_layer> tune_w;
+  std::vector<ls_tune_kernels> tune_k;
   // factors in matrix-core operand order (slice_mfma.hip), per-slice offsets,
   // chunk counts and scratch units; total scratch units over all slices
   DBuf MW, MG, mw_off, mg_off, mnsd, mys_unit;
@@ -226,6 +243,23 @@ int rhs_group(int nrhs) { return nrhs == 1 ? 1 : (nrhs <= 4 ? 4 : 8); }
 // Batches above this many columns take the matrix-core slice solves.
 constexpr int kMfmaMinCols = 8;
 
+// Default kernel choice: the fastest measured on MI355X for the 1023^2 grid
+// (b = 12, w = 4). complex64: vector slice solves up to 4 right-hand sides
+// (one per workgroup up to 2), matrix-core interface products from one;
+// complex128: the vector forms for one right-hand side, matrix-core slice
+// solves from 3 and interface products from 2.
+KernelChoice default_choice(int nb, bool fp64) {
+  if (fp64) return {nb == 1 ? 1 : nb == 2 ? 4 : 16, nb == 1 ? 0 : 1};
+  return {nb <= 2 ? 1 : nb <= 4 ? 4 : 16, 1};
+}
+
+void set_default_choices(ls_handle* h) {
+  h->choice.resize(kChoiceMax + 1);
+  for (int nb = 0; nb <= kChoiceMax; ++nb) h->choice[nb] = default_choice(std::max(nb, 1), h->prec == LS_FP64);
+}
+
+KernelChoice choice_for(const ls_handle* h, int nb) { return h->choice[std::min(std::max(nb, 1), kChoiceMax)]; }
+
 // Scratch of the matrix-core slice solves for ncols columns: the forward
 // results of every slice, (L+1) x 512 scalars per row tile and 16 columns.
 size_t mfma_scratch_bytes(const ls_handle* h, int ncols, size_t cs) {
@@ -252,8 +286,6 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   LSW_HIP_TRY(hipMemsetAsync(h->mu.p, 0, vbytes, h->st));
   // slice-solve scratch: groups of up to 8 waves, one per right-hand side
   LSW_ALLOC(h->sscr, (size_t)h->nslices * std::max(4, nrhs + 7) * slice_scratch_elems<double>(h->L, 1) * cs);
-  if (nrhs > kMfmaMinCols)
-    LSW_ALLOC(h->mscr, mfma_scratch_bytes(h, nrhs, cs));
   LSW_ALLOC(h->vin, (size_t)nrhs * N * cs);
   LSW_ALLOC(h->zout, (size_t)nrhs * N * cs);
   LSW_ALLOC(h->aout, (size_t)nrhs * N * cs);
@@ -276,6 +308,19 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   LSW_ALLOC(h->ptrs_a, (size_t)nrhs * sizeof(void*));
   LSW_ALLOC(h->ptrs_b, (size_t)nrhs * sizeof(void*));
   h->cap = nrhs;
+  return LS_OK;
+}
+
+// Scratch of the matrix-core slice solves, sized for the workspace's batch
+// (at least ncols columns); grown on first use.
+ls_status ensure_mscr(ls_handle* h, int ncols) {
+  const size_t cs = h->prec == LS_FP64 ? sizeof(double2) : sizeof(float2);
+  const size_t need = mfma_scratch_bytes(h, std::max(ncols, h->cap), cs);
+  if (h->mscr.p && h->mscr.bytes >= need) return LS_OK;
+  // launches in flight may still read the old buffer
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  if (h->st2) LSW_HIP_TRY(hipStreamSynchronize(h->st2));
+  LSW_ALLOC(h->mscr, need);
   return LS_OK;
 }
 
@@ -315,13 +360,14 @@ SliceSolveArgs<T> slice_args(ls_handle* h) {
   return a;
 }
 
-// All slices of [k0, k1) solved in one launch, Wmax right-hand sides (waves)
-// per workgroup at most, fewer if the LDS would not fit.
+// All slices of [k0, k1) solved in one launch: kernel 16 on the matrix cores,
+// else on the vector ALUs with at most kernel (1, 4 or 8) right-hand sides
+// (waves) per workgroup, fewer if the LDS would not fit.
 template <typename T>
-ls_status solve_slices(ls_handle* h, SliceSolveArgs<T> a, int k0, int k1, int Wmax, hipStream_t st = nullptr) {
+ls_status solve_slices(ls_handle* h, SliceSolveArgs<T> a, int k0, int k1, int kernel, hipStream_t st = nullptr) {
   if (k0 >= k1) return LS_OK;
   if (!st) st = h->st;
-  if (a.nrhs > kMfmaMinCols) {
+  if (kernel == 16) {
     if (!a.mfma_scr) {
       set_error("internal: no scratch for the matrix-core slice solves");
       return LS_E_STATE;
@@ -362,7 +408,7 @@ ls_status solve_slices(ls_handle* h, SliceSolveArgs<T> a, int k0, int k1, int Wm
   const bool big = f32 > 0;
   a.slice0 = k0;
   a.stage = std::max(f16 ? slice_stage_elems<T>(16, f16) : 0, big ? slice_stage_elems<T>(32, f32) : 0);
-  int W = Wmax;
+  int W = kernel;
   while (W > 1 && slice_lds<T>(big, a.stage, W) > 163840) W = W == 8 ? 4 : 1;
   if (slice_lds<T>(big, a.stage, W) > 163840) {
     set_error("slice subproblem too large for the LDS of one workgroup");
@@ -387,7 +433,14 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
     LSW_HIP_TRY(launch_sweep<T>(h->slices(), h->L, h->b, h->FS.as<C<T>>(), h->FG.as<C<T>>(), h->Hm.as<C<T>>(),
                                 h->Hp.as<C<T>>(), f, u, h->yscr.as<C<T>>(), nb, kSweepFull, 0, h->st));
   } else {
-    const int nl = h->nslices, L = h->L, R = rhs_group(nb);
+    const int nl = h->nslices, L = h->L;
+    const KernelChoice kc = choice_for(h, nb);
+    const int R = kc.slice;
+    const bool imf = kc.iface != 0 || nb > 4;
+    if (R == 16) {
+      const ls_status me = ensure_mscr(h, nb);
+      if (me != LS_OK) return me;
+    }
     C<T>* lam = h->lam.as<C<T>>();
     C<T>* mu = h->mu.as<C<T>>();
     const int Lp = iface_vec_stride(L);
@@ -428,7 +481,7 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
     // slice's coupling (lambda term only) runs on the second stream after its
     // own phase A, which reads the line it changes.
     auto graph = [&](int part, hipGraphExec_t& out) -> ls_status {
-      const std::pair<int, int> key(2 * nb + part, (int)sizeof(T));
+      const std::pair<int, int> key(4 * nb + 2 * (int)imf + part, (int)sizeof(T));
       auto it = h->graphs.find(key);
       if (it != h->graphs.end()) {
         out = it->second;
@@ -444,11 +497,11 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
       hipError_t ce = hipSuccess;
       if (part == 0) {
         for (int k = 1; k <= nl - 2 && ce == hipSuccess; ++k)
-          ce = launch_iface_step<T>(IM, lam, lam, lam, L, nb, k, 1, MS, vs, -1, h->cst);
+          ce = launch_iface_step<T>(IM, lam, lam, lam, L, nb, k, 1, MS, vs, -1, imf, h->cst);
       } else {
-        ce = launch_iface_step<T>(IP, mu, lam, mu, L, nb, 1, nl - 1, MS, vs, -1, h->cst);
+        ce = launch_iface_step<T>(IP, mu, lam, mu, L, nb, 1, nl - 1, MS, vs, -1, imf, h->cst);
         for (int k = nl - 2; k >= 1 && ce == hipSuccess; --k)
-          ce = launch_iface_step<T>(IN, mu, mu, mu, L, nb, k, 1, MS, vs, +1, h->cst);
+          ce = launch_iface_step<T>(IN, mu, mu, mu, L, nb, k, 1, MS, vs, +1, imf, h->cst);
         if (ce == hipSuccess) ce = launch_couple<T>(h->slices(), L, h->b, Hm, Hp, lam, mu, nb, f, 0, kmain, h->cst);
       }
       const hipError_t ee = hipStreamEndCapture(h->cst, &g);
@@ -594,13 +647,14 @@ ls_status build_interface(ls_handle* h) {
     a.src_kind = kSrcUnitF;
     a.dstE = h->IM.as<C<T>>();
     a.dstF = h->IP.as<C<T>>();
-    ls_status e = solve_slices<T>(h, a, 1, nl, W);
+    const int kern = a.nrhs > kMfmaMinCols ? 16 : W;
+    ls_status e = solve_slices<T>(h, a, 1, nl, kern);
     if (e != LS_OK) return e;
     if (nl > 2) {
       a.src_kind = kSrcUnitE;
       a.dstE = nullptr;
       a.dstF = h->IN.as<C<T>>();
-      e = solve_slices<T>(h, a, 1, nl - 1, W);
+      e = solve_slices<T>(h, a, 1, nl - 1, kern);
       if (e != LS_OK) return e;
     }
   }
@@ -1107,6 +1161,122 @@ ls_status check_precision(const ls_handle* h, int precision, bool factors) {
   return LS_OK;
 }
 
+// ---- autotuning ------------------------------------------------------------
+
+// Layer thicknesses w >= 2 whose slice subproblems all have at most 32 lines:
+// the first slice b PML lines + w, the middle ones b auxiliary lines + w, the
+// last b auxiliary lines + the remaining lines + b PML lines (one slice: all L).
+std::vector<int> layer_candidates(int n, int b) {
+  std::vector<int> out;
+  const int lines = n + 2;
+  for (int w = 2; w <= lines; ++w) {
+    const int nl = std::max(1, lines / w);
+    const int tmax = nl == 1 ? lines + 2 * b : std::max(b + w, lines + 2 * b - (nl - 1) * w);
+    if (tmax <= 32) out.push_back(w);
+  }
+  return out;
+}
+
+// One solve of k plane waves to a 1e-6 residual, timed on the host around the
+// call (which ends with a stream synchronisation), after an untimed solve to a
+// loose tolerance that sizes the workspaces and captures the graphs.
+ls_status probe_solve(ls_handle* h, int k, double& ms, int& iters, bool& converged) {
+  DBuf rhs, u;
+  LSW_ALLOC(rhs, (size_t)k * h->N * sizeof(double2));
+  LSW_ALLOC(u, (size_t)k * h->N * sizeof(double2));
+  LSW_HIP_TRY(launch_plane_waves(rhs.as<double2>(), h->n, h->omega, k, h->st));
+  std::vector<ls_rhs_info> info(k);
+  ls_status e = ls_solve(h, rhs.p, k, LS_RHS_INCIDENT, 1e-1, u.p, info.data());
+  if (e != LS_OK && e != LS_E_NOCONV) return e;
+  const auto t0 = std::chrono::steady_clock::now();
+  e = ls_solve(h, rhs.p, k, LS_RHS_INCIDENT, 1e-6, u.p, info.data());
+  const auto t1 = std::chrono::steady_clock::now();
+  if (e != LS_OK && e != LS_E_NOCONV) return e;
+  ms = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  converged = e == LS_OK;
+  iters = 0;
+  for (const ls_rhs_info& i : info) iters = std::max(iters, i.iterations);
+  return LS_OK;
+}
+
+// Batch sizes the kernel choice is measured at, up to kmax (and kmax itself).
+std::vector<int> tune_sizes(int kmax) {
+  kmax = std::min(kmax, kChoiceMax);
+  std::vector<int> s;
+  for (int nb : {1, 2, 3, 4, 6, 8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256})
+    if (nb <= kmax) s.push_back(nb);
+  if (s.back() != kmax) s.push_back(kmax);
+  return s;
+}
+
+// Times one preconditioner apply (the best of three, after an untimed one) per
+// kernel choice at each measured batch size on a zero batch (no kernel's work
+// depends on the values), keeps the fastest, and gives every batch size the
+// choice of the nearest measured size at or above it.
+template <typename T>
+ls_status tune_kernels(ls_handle* h, int kmax) {
+  const std::vector<int> sizes = tune_sizes(kmax);
+  const int top = sizes.back();
+  ls_status e = ensure_workspace(h, top);
+  if (e != LS_OK) return e;
+  DBuf r, z;
+  LSW_ALLOC(r, (size_t)top * h->N * sizeof(C<T>));
+  LSW_ALLOC(z, (size_t)top * h->N * sizeof(C<T>));
+  LSW_HIP_TRY(hipMemsetAsync(r.p, 0, r.bytes, h->st));
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  LSW_HIP_TRY(hipEventCreate(&ev0));
+  LSW_HIP_TRY(hipEventCreate(&ev1));
+  auto time_apply = [&](int nb, KernelChoice c, double& ms) -> ls_status {
+    h->choice.assign(kChoiceMax + 1, c);
+    ls_status s = apply_P<T>(h, r.as<C<T>>(), nb, z.as<C<T>>());
+    if (s != LS_OK) return s;
+    ms = std::numeric_limits<double>::infinity();
+    for (int rep = 0; rep < 3; ++rep) {
+      LSW_HIP_TRY(hipEventRecord(ev0, h->st));
+      if ((s = apply_P<T>(h, r.as<C<T>>(), nb, z.as<C<T>>())) != LS_OK) return s;
+      LSW_HIP_TRY(hipEventRecord(ev1, h->st));
+      LSW_HIP_TRY(hipEventSynchronize(ev1));
+      float t = 0;
+      LSW_HIP_TRY(hipEventElapsedTime(&t, ev0, ev1));
+      ms = std::min(ms, (double)t);
+    }
+    return LS_OK;
+  };
+  std::vector<ls_tune_kernels> rows;
+  for (int nb : sizes) {
+    KernelChoice best{16, 1};
+    double best_ms = std::numeric_limits<double>::infinity();
+    const int iface0 = nb <= 4 ? 0 : 1;
+    for (int sk : {1, 4, 8, 16}) {
+      if ((sk == 4 && nb < 2) || (sk == 8 && nb < 5)) continue;  // whole idle waves
+      double ms;
+      if ((e = time_apply(nb, {sk, iface0}, ms)) != LS_OK) break;
+      if (ms < best_ms) best_ms = ms, best = {sk, iface0};
+    }
+    if (e == LS_OK && nb <= 4) {  // the matrix-core interface products against the vector ones
+      double ms;
+      if ((e = time_apply(nb, {best.slice, 1}, ms)) == LS_OK && ms < best_ms) best_ms = ms, best.iface = 1;
+    }
+    if (e != LS_OK) break;
+    rows.push_back({nb, best.slice, best.iface, best_ms});
+  }
+  (void)hipEventDestroy(ev0);
+  (void)hipEventDestroy(ev1);
+  set_default_choices(h);
+  if (e != LS_OK) return e;
+  for (int nb = 1; nb <= kChoiceMax; ++nb) {
+    size_t i = 0;
+    while (i + 1 < rows.size() && rows[i].nrhs < nb) ++i;
+    KernelChoice c{rows[i].slice_kernel, rows[i].iface_kernel};
+    if (nb > 4) c.iface = 1;
+    h->choice[nb] = c;
+  }
+  h->choice[0] = h->choice[1];
+  h->tune_k = rows;
+  h->drop_graphs();
+  return LS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1157,6 +1327,51 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
       set_error("restart must be in [1, 200] and max_iters >= 1");
       return LS_E_INVALID;
     }
+    if (o.autotune < 0 || o.autotune > 4096) {
+      set_error("autotune must be in [0, 4096] (right-hand sides to tune for)");
+      return LS_E_INVALID;
+    }
+    if (layer_thickness <= 0) {
+      if (o.autotune == 0) {
+        set_error("layer_thickness must be >= 1, or <= 0 with opts->autotune > 0");
+        return LS_E_INVALID;
+      }
+      // choose w: set up every candidate and time a probe solve on it
+      const std::vector<int> cands = layer_candidates(grid->n, pml_width);
+      if (grid->n < 1 || pml_width < 1 || cands.empty()) {
+        set_error("no layer thickness gives slices of at most 32 lines for this n and pml_width");
+        return LS_E_INVALID;
+      }
+      ls_options oc = o;
+      oc.autotune = 0;
+      oc.max_iters = std::min(o.max_iters, 300);  // bounds the cost of a poor candidate
+      std::vector<ls_tune_layer> rows;
+      int best = -1;
+      double best_ms = std::numeric_limits<double>::infinity();
+      for (int w : cands) {
+        ls_handle* hc = nullptr;
+        const auto t0 = std::chrono::steady_clock::now();
+        ls_status e = ls_setup(grid, omega, m_dev, pml_width, w, &oc, &hc);
+        const auto t1 = std::chrono::steady_clock::now();
+        if (e != LS_OK) return e;
+        double ms = 0;
+        int iters = 0;
+        bool conv = false;
+        e = probe_solve(hc, o.autotune, ms, iters, conv);
+        const int nl = hc->nslices;
+        ls_destroy(hc);
+        if (e != LS_OK) return e;
+        rows.push_back({w, nl, iters, std::chrono::duration<double, std::milli>(t1 - t0).count(), ms});
+        const double score = conv ? ms : std::numeric_limits<double>::infinity();
+        if (best < 0 || score < best_ms) best = w, best_ms = score;
+      }
+      ls_handle* hb = nullptr;
+      const ls_status e = ls_setup(grid, omega, m_dev, pml_width, best, &o, &hb);
+      if (e != LS_OK) return e;
+      hb->tune_w = rows;
+      *out = hb;
+      return LS_OK;
+    }
     std::unique_ptr<ls_handle> h(new ls_handle());
     h->opt = o;
     h->st = static_cast<hipStream_t>(o.hip_stream);
@@ -1183,10 +1398,15 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
     h->nslices = h->H.nslices;
     h->omega = omega;
     h->prec = o.precision;
+    set_default_choices(h.get());
     h->N = (size_t)n * n;
     h->E = (size_t)h->L * h->L;
     ls_status e = device_setup(h.get(), m_dev);
     if (e != LS_OK) return e;
+    if (o.autotune > 0) {
+      e = h->prec == LS_FP64 ? tune_kernels<double>(h.get(), o.autotune) : tune_kernels<float>(h.get(), o.autotune);
+      if (e != LS_OK) return e;
+    }
     *out = h.release();
     return LS_OK;
   } catch (const std::bad_alloc&) {
@@ -1368,6 +1588,8 @@ ls_status ls_slice_solve(ls_handle* h, int slice, const void* v, int nrhs, void*
   }
   ls_status e = ensure_workspace(h, nrhs);
   if (e != LS_OK) return e;
+  const KernelChoice kc = choice_for(h, nrhs);
+  if (kc.slice == 16 && (e = ensure_mscr(h, nrhs)) != LS_OK) return e;
   auto run = [&](auto tag) -> ls_status {
     using T = decltype(tag);
     SliceSolveArgs<T> a = slice_args<T>(h);
@@ -1378,7 +1600,7 @@ ls_status ls_slice_solve(ls_handle* h, int slice, const void* v, int nrhs, void*
     a.src = static_cast<const C<T>*>(v);
     a.dst_kind = kDstSlice;
     a.dst = static_cast<C<T>*>(w);
-    return solve_slices<T>(h, a, slice, slice + 1, rhs_group(nrhs));
+    return solve_slices<T>(h, a, slice, slice + 1, kc.slice);
   };
   e = precision == LS_FP64 ? run(double{}) : run(float{});
   if (e != LS_OK) return e;
@@ -1405,6 +1627,58 @@ ls_status ls_get_info(const ls_handle* h, ls_setup_info* o) {
   o->pml_C = h->H.C;
   o->freq_lo = h->H.freq_lo;
   o->freq_delta = h->H.freq_delta;
+  return LS_OK;
+}
+
+ls_status ls_layer_candidates(int n, int pml_width, int* out_host, int cap, int* count) {
+  if (n < 1 || pml_width < 1 || cap < 0 || (cap > 0 && !out_host) || !count) {
+    set_error("ls_layer_candidates: bad argument (n >= 1, pml_width >= 1, cap >= 0, count not NULL)");
+    return LS_E_INVALID;
+  }
+  const std::vector<int> c = layer_candidates(n, pml_width);
+  for (int i = 0; i < (int)c.size() && i < cap; ++i) out_host[i] = c[i];
+  *count = (int)c.size();
+  return LS_OK;
+}
+
+ls_status ls_get_tuning(const ls_handle* h, ls_tune_layer* w_host, int wcap, int* nw, ls_tune_kernels* k_host,
+                        int kcap, int* nk) {
+  if (check_handle(h) != LS_OK) return LS_E_INVALID;
+  if (wcap < 0 || kcap < 0 || (wcap > 0 && !w_host) || (kcap > 0 && !k_host)) {
+    set_error("ls_get_tuning: bad argument");
+    return LS_E_INVALID;
+  }
+  for (int i = 0; i < (int)h->tune_w.size() && i < wcap; ++i) w_host[i] = h->tune_w[i];
+  for (int i = 0; i < (int)h->tune_k.size() && i < kcap; ++i) k_host[i] = h->tune_k[i];
+  if (nw) *nw = (int)h->tune_w.size();
+  if (nk) *nk = (int)h->tune_k.size();
+  return LS_OK;
+}
+
+ls_status ls_set_kernels(ls_handle* h, int nrhs, int slice_kernel, int iface_kernel) {
+  if (check_handle(h) != LS_OK) return LS_E_INVALID;
+  if (nrhs < 0 || nrhs > kChoiceMax) {
+    set_error("ls_set_kernels: 0 <= nrhs <= 256");
+    return LS_E_INVALID;
+  }
+  if (slice_kernel == 0) {  // back to the defaults
+    const bool fp64 = h->prec == LS_FP64;
+    if (nrhs == 0)
+      set_default_choices(h);
+    else
+      h->choice[nrhs] = default_choice(nrhs, fp64);
+    return LS_OK;
+  }
+  const bool sk_ok = slice_kernel == 1 || slice_kernel == 4 || slice_kernel == 8 || slice_kernel == 16;
+  if (!sk_ok || (iface_kernel != 0 && iface_kernel != 1) || (iface_kernel == 0 && nrhs > 4)) {
+    set_error("ls_set_kernels: slice_kernel in {0, 1, 4, 8, 16}, iface_kernel 0 (nrhs <= 4) or 1");
+    return LS_E_INVALID;
+  }
+  if (nrhs == 0) {
+    for (int nb = 0; nb <= kChoiceMax; ++nb) h->choice[nb] = {slice_kernel, nb <= 4 ? iface_kernel : 1};
+  } else {
+    h->choice[nrhs] = {slice_kernel, iface_kernel};
+  }
   return LS_OK;
 }
 

@@ -730,10 +730,11 @@ template hipError_t launch_swizzle_maps<float>(const float2*, float2*, int, int,
 
 template <typename T>
 hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
-                             int kcount, size_t mstride, size_t vstride, int xoff, hipStream_t st) {
+                             int kcount, size_t mstride, size_t vstride, int xoff, bool mfma, hipStream_t st) {
   if (kcount <= 0) return hipSuccess;
   const int nt = iface_tiles(L);
-  if (nrhs <= 4) {
+  if (!mfma && nrhs > 4) return hipErrorInvalidValue;  // the vector form holds at most 4 columns
+  if (!mfma) {
     constexpr int NW = 8;
     hipLaunchKernelGGL((k_iface_gemv<T, NW>), dim3(nt, 1, kcount), dim3(64 * NW), 0, st, M, add, x, y, L, nrhs, kbeg,
                        mstride, vstride, xoff);
@@ -745,9 +746,9 @@ hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>
   return hipGetLastError();
 }
 template hipError_t launch_iface_step<double>(const double2*, const double2*, const double2*, double2*, int, int,
-                                              int, int, size_t, size_t, int, hipStream_t);
+                                              int, int, size_t, size_t, int, bool, hipStream_t);
 template hipError_t launch_iface_step<float>(const float2*, const float2*, const float2*, float2*, int, int, int,
-                                             int, size_t, size_t, int, hipStream_t);
+                                             int, size_t, size_t, int, bool, hipStream_t);
 
 template <typename T>
 hipError_t launch_couple(const SliceTables& P, int L, int b, const C<T>* Hm, const C<T>* Hp, const C<T>* lam,

@@ -159,10 +159,11 @@ template <typename T>
 hipError_t launch_slice_mfma(const SliceMfmaArgs<T>& a, int nslices, hipStream_t st);
 
 // y_k = add_k - M_k x_{k+xoff} for k = kbeg .. kbeg+kcount-1 (in place allowed, y == add);
-// M in operand order (mstride = iface_map_stride(L))
+// M in operand order (mstride = iface_map_stride(L)); mfma: on the matrix
+// cores, else vector dot products (nrhs <= 4, hipErrorInvalidValue above)
 template <typename T>
 hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
-                             int kcount, size_t mstride, size_t vstride, int xoff, hipStream_t st);
+                             int kcount, size_t mstride, size_t vstride, int xoff, bool mfma, hipStream_t st);
 // f -= J_F Hm_k lambda_{k-1} + J_E Hp_k mu_{k+1} on slices [k0, k1)
 template <typename T>
 hipError_t launch_couple(const SliceTables& P, int L, int b, const C<T>* Hm, const C<T>* Hp, const C<T>* lam,
@@ -206,5 +207,7 @@ hipError_t launch_adjoint_product(const double2* psi, const double2* nu, int nrh
 hipError_t launch_conj(double2* dst, const double2* src, size_t N, hipStream_t st);
 // x (+)= s * y elementwise over N with real s, float64 (incident total field etc.)
 hipError_t launch_add_scaled(double2* x, const double2* y, double s, size_t N, hipStream_t st);
+// k plane waves exp(i omega (cos t_j x1 + sin t_j x2)), t_j = 2 pi j / k, on the interior grid: [k][n][n]
+hipError_t launch_plane_waves(double2* out, int n, double omega, int k, hipStream_t st);
 
 }  // namespace lsw

@@ -115,6 +115,21 @@ __global__ void k_add_scaled(double2* __restrict__ x, const double2* __restrict_
   }
 }
 
+// k plane waves exp(i omega (cos t_j x1 + sin t_j x2)), t_j = 2 pi j / k, at the
+// interior points x = (i + 1) h: [k][n][n]
+__global__ void k_plane_waves(double2* __restrict__ out, int n, double omega, int k) {
+  const size_t N = (size_t)n * n, total = N * k;
+  const double h = 1.0 / (n + 1);
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(e / N);
+    const size_t p = e % N;
+    const double x1 = (double)(p / n + 1) * h, x2 = (double)(p % n + 1) * h;
+    const double t = 2.0 * M_PI * j / k;
+    const double ph = omega * (cos(t) * x1 + sin(t) * x2);
+    out[e] = make_double2(cos(ph), sin(ph));
+  }
+}
+
 __global__ void k_conj(double2* __restrict__ d, const double2* __restrict__ s, size_t N) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x)
     d[i] = make_double2(s[i].x, -s[i].y);
@@ -176,6 +191,11 @@ hipError_t launch_adjoint_product(const double2* psi, const double2* nu, int nrh
 
 hipError_t launch_conj(double2* dst, const double2* src, size_t N, hipStream_t st) {
   hipLaunchKernelGGL(k_conj, dim3(grid_for(N)), dim3(kThreads), 0, st, dst, src, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_plane_waves(double2* out, int n, double omega, int k, hipStream_t st) {
+  hipLaunchKernelGGL(k_plane_waves, dim3(grid_for((size_t)n * n * k)), dim3(kThreads), 0, st, out, n, omega, k);
   return hipGetLastError();
 }
 

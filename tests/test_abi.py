@@ -43,3 +43,50 @@ def test_default_options_and_error_channel():
     assert st == _lib.LS_E_INVALID
     assert lib.ls_last_error().decode()
     lib.ls_destroy(None)  # no-op
+
+
+@pytest.mark.parametrize("n,b", [(22, 4), (40, 6)])
+def test_layer_candidates_match_the_slice_partition(n, b):
+    # every w >= 2 whose slice subproblems (the oracle's partition along x1 plus
+    # b auxiliary lines for every slice after the first) have at most 32 lines
+    import numpy as np
+    import oracle
+    from paper_1705_09443_amd import layer_candidates
+    omega = 2 * np.pi * 2.0
+    m = np.zeros((n, n))
+    alpha, beta, _ = oracle.alpha_beta(oracle.green_table(2, n, omega), n, 2)
+    system = oracle.SparseSystem(2, n, omega, m, alpha, beta, b, 10.0)
+    expect = []
+    for w in range(2, n + 3):
+        sw = oracle.Sweep(system, w, m, only=[])
+        t = [hi - lo + 1 + (b if k > 0 else 0) for k, (lo, hi) in enumerate(sw.bounds)]
+        if max(t) <= 32:
+            expect.append(w)
+    assert layer_candidates(n, b) == expect
+
+
+def test_layer_candidates_of_the_full_size_grid_and_bad_arguments():
+    # n = 1023, b = 12: 1025 lines; w = 4 leaves a 29-line last slice, w = 6
+    # a 35-line one
+    from paper_1705_09443_amd import _lib, layer_candidates
+    assert layer_candidates(1023, 12) == [2, 3, 4, 5]
+    lib = _lib.load()
+    cnt = ctypes.c_int()
+    assert lib.ls_layer_candidates(0, 12, None, 0, ctypes.byref(cnt)) == _lib.LS_E_INVALID
+    assert lib.ls_layer_candidates(63, 12, None, 0, None) == _lib.LS_E_INVALID
+
+
+def test_setup_without_layer_thickness_needs_autotune():
+    # rejected on the host, before any device call
+    from paper_1705_09443_amd import _lib
+    lib = _lib.load()
+    o = _lib.LsOptions()
+    lib.ls_default_options(ctypes.byref(o))
+    grid = _lib.LsGrid(2, 31)
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)
+    assert lib.ls_setup(ctypes.byref(grid), 10.0, dummy, 6, 0, ctypes.byref(o), ctypes.byref(h)) == _lib.LS_E_INVALID
+    assert "autotune" in lib.ls_last_error().decode()
+    o.autotune = -1
+    assert lib.ls_setup(ctypes.byref(grid), 10.0, dummy, 6, 4, ctypes.byref(o), ctypes.byref(h)) == _lib.LS_E_INVALID
+    assert not h.value

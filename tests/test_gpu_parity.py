@@ -197,8 +197,8 @@ def test_preconditioner(case):
 
 @pytest.mark.parametrize("nb", [5, 17, 40])
 def test_preconditioner_batches(case, nb):
-    # batches above 4 columns take the matrix-core interface products (16-column
-    # tiles: 5 and 17 leave ragged tiles, 40 spans three)
+    # these batches take the matrix-core slice solves and interface products by
+    # default (16-column tiles: 5 and 17 leave ragged tiles, 40 spans three)
     name, wl, m, ref, g64, g32 = case
     n = wl.n
     rng = np.random.default_rng(20 + nb)
@@ -214,6 +214,48 @@ def test_preconditioner_batches(case, nb):
     say(f"[{name}] batch {nb}: worst relative error fp64 {worst64:.2e}, fp32 {worst32:.2e}")
     assert worst64 <= 1e-12
     assert worst32 <= 1e-4
+
+
+@pytest.mark.parametrize("nb", [1, 3, 6])
+def test_every_kernel_choice(case, nb):
+    # one preconditioner whatever kernels run it: slice solves on the vector
+    # ALUs (1, 4 or 8 right-hand sides per workgroup) or on the matrix cores
+    # (16-column tiles, here ragged), interface products as dot products or on
+    # the matrix cores; single slice solves likewise
+    name, wl, m, ref, g64, g32 = case
+    n = wl.n
+    sw = ref.sweep
+    rng = np.random.default_rng(50 + nb)
+    r = crand(rng, (nb, n, n))
+    zr = [ref.precondition(r[j]) for j in range(nb)]
+    ks = sorted({0, sw.nslices - 1})
+    vs = {}
+    for k in ks:
+        lo, hi, _ = g64.slice_bounds(k)
+        v = crand(rng, (nb, hi - lo + 1, sw.s.L))
+        vs[k] = (v, [sw.solve_slice(k, v[j].reshape(-1)) for j in range(nb)])
+    try:
+        for sk in (1, 4, 8, 16):
+            for ik in ((0, 1) if nb <= 4 else (1,)):
+                for g in (g64, g32):
+                    g.set_kernels(nb, sk, ik)
+                z = g64.apply_precond(to_dev(r)).cpu().numpy()
+                z32 = g32.apply_precond(to_dev(r, torch.complex64)).cpu().numpy()
+                w64 = max(rel(z[j], zr[j]) for j in range(nb))
+                w32 = max(rel(z32[j], zr[j]) for j in range(nb))
+                say(f"[{name}] batch {nb}, slice kernel {sk}, interface kernel {ik}: "
+                    f"fp64 {w64:.2e}, fp32 {w32:.2e}")
+                assert w64 <= 1e-12 and w32 <= 1e-4
+                for k in ks:
+                    v, wr = vs[k]
+                    w = g64.slice_solve(k, to_dev(v)).cpu().numpy()
+                    w32s = g32.slice_solve(k, to_dev(v, torch.complex64)).cpu().numpy()
+                    for j in range(nb):
+                        assert rel(w[j].reshape(-1), wr[j]) <= 1e-12, (k, j)
+                        assert rel(w32s[j].reshape(-1), wr[j]) <= 1e-4, (k, j)
+    finally:
+        for g in (g64, g32):
+            g.set_kernels(nb, 0, 0)  # back to the defaults
 
 
 def test_solve_fp64_parity(case):
@@ -281,15 +323,19 @@ def test_graph_replays_agree(case):
     n = wl.n
     b, w = CASES[name][2], CASES[name][3]
     rng = np.random.default_rng(10)
-    for nb in (3, 9):                      # vector-ALU and matrix-core interface products
+    for nb, ik in ((3, 0), (3, 1), (9, 1)):   # vector and matrix-core interface products
         r = to_dev(crand(rng, (nb, n, n)))
-        say(f"[{name}] graph replays, batch of {nb}")
+        say(f"[{name}] graph replays, batch of {nb}, interface kernel {ik}")
         with LSSolver(torch.as_tensor(m).cuda(), wl.omega, b, w, precision="fp64", schedule="sequential") as seq:
             zref = seq.apply_precond(r).cpu().numpy()
+        g64.set_kernels(nb, 4 if nb <= 4 else 16, ik)
         outs = []
-        for it in range(4):
-            outs.append(g64.apply_precond(r).cpu().numpy())
-            g64.apply_A(r)                     # eager work between replays
-            torch.cuda.synchronize()
+        try:
+            for it in range(4):
+                outs.append(g64.apply_precond(r).cpu().numpy())
+                g64.apply_A(r)                     # eager work between replays
+                torch.cuda.synchronize()
+        finally:
+            g64.set_kernels(nb, 0, 0)
         for z in outs:
             assert rel(z, zref) <= 1e-12
