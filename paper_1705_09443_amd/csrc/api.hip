@@ -424,9 +424,12 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
   const StencilTables S = h->stencils();
   C<T>* f = h->fext.as<C<T>>();
   C<T>* u = h->uext.as<C<T>>();
+  // the interface schedule keeps f and u interleaved ([L][L][nb]); the
+  // sequential sweep takes them right-hand side by right-hand side
+  const bool il = h->opt.sweep_schedule != LS_SWEEP_SEQUENTIAL;
   {
     Timed tm(h, kKQ, nb);
-    LSW_HIP_TRY(launch_apply_Q<T>(S, r, nb, f, h->st));
+    LSW_HIP_TRY(launch_apply_Q<T>(S, r, nb, f, il, h->st));
   }
   if (h->opt.sweep_schedule == LS_SWEEP_SEQUENTIAL) {
     Timed tm(h, kKSweep, nb);
@@ -569,7 +572,7 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
   }
   {
     Timed tm(h, kKExtract, nb);
-    LSW_HIP_TRY(launch_extract<T>(h->n, h->b, u, nb, z, h->st));
+    LSW_HIP_TRY(launch_extract<T>(h->n, h->b, u, nb, z, il, h->st));
   }
   return LS_OK;
 }
@@ -1543,9 +1546,11 @@ ls_status ls_apply_Q(ls_handle* h, const void* r, int nrhs, void* f, int precisi
   }
   const StencilTables S = h->stencils();
   if (precision == LS_FP64)
-    LSW_HIP_TRY(launch_apply_Q<double>(S, static_cast<const double2*>(r), nrhs, static_cast<double2*>(f), h->st));
+    LSW_HIP_TRY(launch_apply_Q<double>(S, static_cast<const double2*>(r), nrhs, static_cast<double2*>(f), false,
+                                       h->st));
   else
-    LSW_HIP_TRY(launch_apply_Q<float>(S, static_cast<const float2*>(r), nrhs, static_cast<float2*>(f), h->st));
+    LSW_HIP_TRY(launch_apply_Q<float>(S, static_cast<const float2*>(r), nrhs, static_cast<float2*>(f), false,
+                                      h->st));
   LSW_HIP_TRY(hipStreamSynchronize(h->st));
   return LS_OK;
 }

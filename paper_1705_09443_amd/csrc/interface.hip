@@ -171,7 +171,7 @@ __device__ __attribute__((always_inline)) inline void slice_body(const SliceSolv
       const C<T>* base = A.src;
       size_t off;
       if (A.src_kind == kSrcGrid) {
-        off = ((size_t)rr * L + lo + cl + b) * L + j;
+        off = ((size_t)(lo + cl + b) * L + j) * A.nrhs + rr;
       } else if (A.src_kind == kSrcSlice) {
         off = ((size_t)rr * tw + cl) * L + j;
       } else {
@@ -288,7 +288,7 @@ __device__ __attribute__((always_inline)) inline void slice_body(const SliceSolv
   auto emit = [&](int j, C<T> x) {
     if (!rvalid || !arow || cq != 0) return;
     if (A.dst_kind == kDstGrid) {
-      if (a >= naux) A.dst[((size_t)rr * L + first + a + b) * L + j] = x;
+      if (a >= naux) A.dst[((size_t)(first + a + b) * L + j) * A.nrhs + rr] = x;
     } else if (A.dst_kind == kDstSlice) {
       if (a >= naux) A.dst[((size_t)rr * tw + a - naux) * L + j] = x;
     } else {
@@ -323,7 +323,7 @@ __device__ __attribute__((always_inline)) inline void slice_body(const SliceSolv
       if (jj < n && ar >= naux && ar < t) {
         const C<T> x = xo[buf * D * TP + jj * TP + ar];
         if (A.dst_kind == kDstGrid)
-          A.dst[((size_t)rr * L + first + ar + b) * L + j0 + jj] = x;
+          A.dst[((size_t)(first + ar + b) * L + j0 + jj) * A.nrhs + rr] = x;
         else
           A.dst[((size_t)rr * tw + ar - naux) * L + j0 + jj] = x;
       }
@@ -611,6 +611,8 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(const C<T>* __restrict__
 }
 
 // f on the first line of D_k -= Hm_k lambda_{k-1}; on its last line -= Hp_k mu_{k+1}.
+// f interleaved [L][L][nrhs]; one thread per (slice, j, right-hand side), the
+// right-hand side fastest.
 template <typename T>
 __global__ void k_couple(SliceTables P, int L, int b, const C<T>* __restrict__ Hm, const C<T>* __restrict__ Hp,
                          const C<T>* __restrict__ lam, const C<T>* __restrict__ mu, int nrhs, C<T>* f, int k0,
@@ -618,17 +620,16 @@ __global__ void k_couple(SliceTables P, int L, int b, const C<T>* __restrict__ H
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   const size_t tot = (size_t)kcount * nrhs * L;
   if (idx >= tot) return;
-  const int j = (int)(idx % L);
-  const int r = (int)((idx / L) % nrhs);
+  const int r = (int)(idx % nrhs);
+  const int j = (int)((idx / nrhs) % L);
   const int k = k0 + (int)(idx / ((size_t)L * nrhs));
-  C<T>* fr = f + (size_t)r * L * L;
   if (k > 0) {
     const C<T>* lv = lam + ((size_t)(k - 1) * nrhs + r) * iface_vec_len(L);
     const C<T>* hm = Hm + ((size_t)k * L + j) * 3;
     C<T> acc = mk<T>(0, 0);
     for (int d = -1; d <= 1; ++d)
       if (j + d >= 0 && j + d < L) acc = cfma<T>(acc, hm[d + 1], lv[j + d]);
-    C<T>* o = fr + (size_t)(P.lo[k] + b) * L + j;
+    C<T>* o = f + ((size_t)(P.lo[k] + b) * L + j) * nrhs + r;
     *o = csub<T>(*o, acc);
   }
   if (k < P.nslices - 1) {
@@ -637,7 +638,7 @@ __global__ void k_couple(SliceTables P, int L, int b, const C<T>* __restrict__ H
     C<T> acc = mk<T>(0, 0);
     for (int d = -1; d <= 1; ++d)
       if (j + d >= 0 && j + d < L) acc = cfma<T>(acc, hp[d + 1], mv[j + d]);
-    C<T>* o = fr + (size_t)(P.hi[k] + b) * L + j;
+    C<T>* o = f + ((size_t)(P.hi[k] + b) * L + j) * nrhs + r;
     *o = csub<T>(*o, acc);
   }
 }

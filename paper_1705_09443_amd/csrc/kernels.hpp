@@ -49,12 +49,17 @@ struct SliceTables {
   int nslices;
 };
 
+// Extended-grid fields come in two layouts: [nrhs][L][L] (right-hand side
+// slowest: the C ABI's, and the sequential sweep's) and the interleaved
+// [L][L][nrhs] of the interface schedule, where a 16-column tile of the
+// matrix-core slice solves reads one 128-byte run per grid point.
 template <typename T>
-hipError_t launch_apply_Q(const StencilTables& S, const C<T>* r, int nrhs, C<T>* f, hipStream_t st);
+hipError_t launch_apply_Q(const StencilTables& S, const C<T>* r, int nrhs, C<T>* f, bool interleaved,
+                          hipStream_t st);
 template <typename T>
 hipError_t launch_apply_H(const StencilTables& S, const C<T>* u, int nrhs, C<T>* y, hipStream_t st);
 template <typename T>
-hipError_t launch_extract(int n, int b, const C<T>* uext, int nrhs, C<T>* z, hipStream_t st);
+hipError_t launch_extract(int n, int b, const C<T>* uext, int nrhs, C<T>* z, bool interleaved, hipStream_t st);
 // Assemble and factor every slice subproblem (one workgroup per slice);
 // writes FS, FG, the coupling rows Hm, Hp ([nslices][L][3]) and status
 // (nonzero: a zero pivot was met).
@@ -71,6 +76,7 @@ hipError_t launch_sweep(const SliceTables& P, int L, int b, const C<T>* FS, cons
                         int nrhs, int mode, int slice, hipStream_t st);
 
 // ---- interface form of the sweep (interface.hip) ----
+// kSrcGrid / kDstGrid: the interleaved extended grid [L][L][nrhs]
 enum SliceSrc { kSrcGrid = 0, kSrcSlice = 1, kSrcUnitF = 2, kSrcUnitE = 3 };
 enum SliceDst { kDstGrid = 0, kDstSlice = 1, kDstLines = 2 };
 template <typename T>

@@ -121,8 +121,12 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
     const int lc = line < tw ? line : tw - 1;
     rok[cc] = valid && line < tw;
     rp[cc] = UNIT ? hrow + (size_t)k * L * 3
-                  : A.src + (A.src_kind == kSrcGrid ? ((size_t)nc * L + lo + lc + b) * L : ((size_t)nc * tw + lc) * L);
+                  : A.src + (A.src_kind == kSrcGrid ? (size_t)(lo + lc + b) * L * A.nrhs + nc
+                                                    : ((size_t)nc * tw + lc) * L);
   }
+  // step stride along j of the right-hand sides: the interleaved grid holds
+  // nrhs values per point
+  const size_t rjs = A.src_kind == kSrcGrid ? (size_t)A.nrhs : 1;
   auto rhs = [&](int cc, int j) -> C<T> {
     if (UNIT) {
       // the unit source column col has 3 coefficients on one line, rows col-1..col+1
@@ -131,7 +135,7 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
       const C<T> v = rp[cc][(size_t)j * 3 + (dj < -1 ? 0 : dj > 1 ? 2 : dj + 1)];
       return ok ? v : mk<T>(0, 0);
     }
-    const C<T> v = rp[cc][j];
+    const C<T> v = rp[cc][(size_t)j * rjs];
     return rok[cc] ? v : mk<T>(0, 0);
   };
 
@@ -144,6 +148,7 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
     const bool lines = A.dst_kind == kDstLines;
     const size_t ci = UNIT ? (size_t)(A.col0 + n) : (size_t)n;
     if (lines) ds = A.sj;
+    if (A.dst_kind == kDstGrid) ds = A.nrhs;
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
@@ -153,7 +158,7 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
         C<T>* p1 = nullptr;
         if (valid && a < t) {
           if (A.dst_kind == kDstGrid) {
-            if (a >= naux) p0 = A.dst + ((size_t)n * L + first + a + b) * L;
+            if (a >= naux) p0 = A.dst + (size_t)(first + a + b) * L * A.nrhs + n;
           } else if (A.dst_kind == kDstSlice) {
             if (a >= naux) p0 = A.dst + ((size_t)n * tw + a - naux) * L;
           } else {

@@ -110,6 +110,70 @@ __global__ void k_apply_H(StencilTables S, const C<T>* __restrict__ u, int nrhs,
   y[idx] = acc;
 }
 
+// Q into the interleaved layout f[e1][e2][nrhs] (right-hand side fastest). A
+// workgroup takes one extended row, 64 columns and 16 right-hand sides: the
+// stencil reads run along the columns of each right-hand side's plane, the
+// results cross LDS and leave with the right-hand side fastest.
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_Q_il(StencilTables S, const C<T>* __restrict__ r, int nrhs,
+                                                    C<T>* __restrict__ f) {
+  __shared__ C<T> tile[64][17];
+  const int L = S.L, n = S.n, b = S.b;
+  const int c0 = blockIdx.x * 64, e1 = blockIdx.y, q0 = blockIdx.z * 16;
+  const int i1 = e1 - b;
+  const int t = threadIdx.x, c = t & 63, sub = t >> 6;
+  const int i2 = c0 + c - b;
+  const bool type1 = i1 >= 0 && i1 <= n + 1 && c0 + c < L && i2 >= 0 && i2 <= n + 1;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int rr = q0 + sub + 4 * s;
+    C<T> acc = mk<T>(0, 0);
+    if (type1 && rr < nrhs) {
+      const C<T>* rp = r + (size_t)rr * n * n;
+      for (int o = 0; o < 9; ++o) {
+        const int j1 = i1 + o / 3 - 1, j2 = i2 + o % 3 - 1;
+        if (j1 < 1 || j1 > n || j2 < 1 || j2 > n) continue;
+        const double2 al = S.alpha[o];
+        acc = cfma<T>(acc, mk<T>((T)al.x, (T)-al.y), rp[(size_t)(j1 - 1) * n + (j2 - 1)]);
+      }
+    }
+    tile[c][sub + 4 * s] = acc;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int idx = t + 256 * s;
+    const int rr = idx & 15, cc = idx >> 4;
+    const int e2 = c0 + cc, q = q0 + rr;
+    if (e2 < L && q < nrhs) f[((size_t)e1 * L + e2) * nrhs + q] = tile[cc][rr];
+  }
+}
+
+// z[nrhs][n][n] = the interior of the interleaved u[e1][e2][nrhs], through LDS
+// as in k_apply_Q_il.
+template <typename T>
+__global__ __launch_bounds__(256) void k_extract_il(int n, int b, const C<T>* __restrict__ uext, int nrhs,
+                                                    C<T>* __restrict__ z) {
+  __shared__ C<T> tile[16][65];
+  const int L = n + 2 + 2 * b;
+  const int c0 = blockIdx.x * 64, a1 = blockIdx.y, q0 = blockIdx.z * 16;
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int idx = t + 256 * s;
+    const int rr = idx & 15, cc = idx >> 4;
+    const int a2 = c0 + cc, q = q0 + rr;
+    if (a2 < n && q < nrhs) tile[rr][cc] = uext[((size_t)(a1 + 1 + b) * L + a2 + 1 + b) * nrhs + q];
+  }
+  __syncthreads();
+  const int c = t & 63, sub = t >> 6;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int rr = sub + 4 * s, q = q0 + rr;
+    if (c0 + c < n && q < nrhs) z[((size_t)q * n + a1) * n + c0 + c] = tile[rr][c];
+  }
+}
+
 template <typename T>
 __global__ void k_extract(int n, int b, const C<T>* __restrict__ uext, int nrhs, C<T>* __restrict__ z) {
   const size_t nn = (size_t)n * n;
@@ -405,7 +469,12 @@ inline unsigned blocks_for(size_t total, int nt) { return (unsigned)((total + nt
 }  // namespace
 
 template <typename T>
-hipError_t launch_apply_Q(const StencilTables& S, const C<T>* r, int nrhs, C<T>* f, hipStream_t st) {
+hipError_t launch_apply_Q(const StencilTables& S, const C<T>* r, int nrhs, C<T>* f, bool interleaved,
+                          hipStream_t st) {
+  if (interleaved) {
+    hipLaunchKernelGGL(k_apply_Q_il<T>, dim3((S.L + 63) / 64, S.L, (nrhs + 15) / 16), dim3(256), 0, st, S, r, nrhs, f);
+    return hipGetLastError();
+  }
   const size_t tot = (size_t)S.L * S.L * nrhs;
   hipLaunchKernelGGL(k_apply_Q<T>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, S, r, nrhs, f);
   return hipGetLastError();
@@ -419,7 +488,11 @@ hipError_t launch_apply_H(const StencilTables& S, const C<T>* u, int nrhs, C<T>*
 }
 
 template <typename T>
-hipError_t launch_extract(int n, int b, const C<T>* uext, int nrhs, C<T>* z, hipStream_t st) {
+hipError_t launch_extract(int n, int b, const C<T>* uext, int nrhs, C<T>* z, bool interleaved, hipStream_t st) {
+  if (interleaved) {
+    hipLaunchKernelGGL(k_extract_il<T>, dim3((n + 63) / 64, n, (nrhs + 15) / 16), dim3(256), 0, st, n, b, uext, nrhs, z);
+    return hipGetLastError();
+  }
   const size_t tot = (size_t)n * n * nrhs;
   hipLaunchKernelGGL(k_extract<T>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, n, b, uext, nrhs, z);
   return hipGetLastError();
@@ -442,9 +515,9 @@ hipError_t launch_sweep(const SliceTables& P, int L, int b, const C<T>* FS, cons
 }
 
 #define LSW_INST(T)                                                                                  \
-  template hipError_t launch_apply_Q<T>(const StencilTables&, const C<T>*, int, C<T>*, hipStream_t); \
+  template hipError_t launch_apply_Q<T>(const StencilTables&, const C<T>*, int, C<T>*, bool, hipStream_t); \
   template hipError_t launch_apply_H<T>(const StencilTables&, const C<T>*, int, C<T>*, hipStream_t); \
-  template hipError_t launch_extract<T>(int, int, const C<T>*, int, C<T>*, hipStream_t);             \
+  template hipError_t launch_extract<T>(int, int, const C<T>*, int, C<T>*, bool, hipStream_t);       \
   template hipError_t launch_factor_slices<T>(const StencilTables&, const SliceTables&, C<T>*,       \
                                               C<T>*, C<T>*, C<T>*, int*, hipStream_t);               \
   template hipError_t launch_sweep<T>(const SliceTables&, int, int, const C<T>*, const C<T>*,        \
