@@ -245,7 +245,7 @@ ls_status ls_get_tuning(const ls_handle* h, ls_tune_layer* w_host, int wcap, int
  * 256; batches above 256 follow 256), or for every batch size with nrhs = 0.
  * slice_kernel in {1, 4, 8, 16}, or 0 to restore the default (iface_kernel is
  * then ignored); iface_kernel 0 or 1, and 0 only for batches of at most 4
- * (with nrhs = 0, larger batches keep 1). The defaults, the
+ * (with nrhs = 0, larger batches take 1 instead). The defaults, the
  * fastest measured on MI355X at n = 1023, b = 12, w = 4: LS_MIXED slice 1 up
  * to 2 right-hand sides, 4 up to 4, 16 above, interface 1; LS_FP64 slice 1,
  * interface 0 for one right-hand side, slice 4 for two, 16 above, interface 1

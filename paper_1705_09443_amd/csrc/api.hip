@@ -465,7 +465,7 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
       p.dst_kind = kDstLines;
       p.dstE = lam;
       p.dstF = mu;
-      p.sk = vs;
+      p.sk = vs;  // lines into lambda / mu: [slice][nb][Lp]
       p.sr = Lp;
       p.sj = 1;
       return solve_slices<T>(h, p, k0, k1, R, s);
@@ -1256,9 +1256,11 @@ ls_status tune_kernels(ls_handle* h, int kmax) {
       if ((e = time_apply(nb, {sk, iface0}, ms)) != LS_OK) break;
       if (ms < best_ms) best_ms = ms, best = {sk, iface0};
     }
-    if (e == LS_OK && nb <= 4) {  // the matrix-core interface products against the vector ones
+    // the other interface kernels with that slice kernel
+    for (int ik : {0, 1}) {
+      if (e != LS_OK || ik == iface0 || (ik == 0 && nb > 4)) continue;
       double ms;
-      if ((e = time_apply(nb, {best.slice, 1}, ms)) == LS_OK && ms < best_ms) best_ms = ms, best.iface = 1;
+      if ((e = time_apply(nb, {best.slice, ik}, ms)) == LS_OK && ms < best_ms) best_ms = ms, best.iface = ik;
     }
     if (e != LS_OK) break;
     rows.push_back({nb, best.slice, best.iface, best_ms});
@@ -1271,7 +1273,7 @@ ls_status tune_kernels(ls_handle* h, int kmax) {
     size_t i = 0;
     while (i + 1 < rows.size() && rows[i].nrhs < nb) ++i;
     KernelChoice c{rows[i].slice_kernel, rows[i].iface_kernel};
-    if (nb > 4) c.iface = 1;
+    if (nb > 4 && c.iface == 0) c.iface = 1;
     h->choice[nb] = c;
   }
   h->choice[0] = h->choice[1];
@@ -1675,12 +1677,13 @@ ls_status ls_set_kernels(ls_handle* h, int nrhs, int slice_kernel, int iface_ker
     return LS_OK;
   }
   const bool sk_ok = slice_kernel == 1 || slice_kernel == 4 || slice_kernel == 8 || slice_kernel == 16;
-  if (!sk_ok || (iface_kernel != 0 && iface_kernel != 1) || (iface_kernel == 0 && nrhs > 4)) {
+  if (!sk_ok || iface_kernel < 0 || iface_kernel > 1 || (iface_kernel == 0 && nrhs > 4)) {
     set_error("ls_set_kernels: slice_kernel in {0, 1, 4, 8, 16}, iface_kernel 0 (nrhs <= 4) or 1");
     return LS_E_INVALID;
   }
   if (nrhs == 0) {
-    for (int nb = 0; nb <= kChoiceMax; ++nb) h->choice[nb] = {slice_kernel, nb <= 4 ? iface_kernel : 1};
+    for (int nb = 0; nb <= kChoiceMax; ++nb)
+      h->choice[nb] = {slice_kernel, nb > 4 && iface_kernel == 0 ? 1 : iface_kernel};
   } else {
     h->choice[nrhs] = {slice_kernel, iface_kernel};
   }

@@ -419,10 +419,11 @@ __global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSo
 // values per (r, b), zero-padded to whole tiles, with lane l holding row
 // 16 r + l % 16 and the 4 consecutive columns 16 b + 4 (l / 16) + j. One
 // (r, b) block is then one contiguous 64-lane operand load, and the padding
-// removes every bounds test on M. x, add, y: [nrhs][L] per slice.
+// removes every bounds test on M. x, add, y: [nrhs][Lp] per slice.
 __host__ __device__ inline int iface_tiles(int L) { return (L + 15) / 16; }
 // x, add, y rows (one per right-hand side) are padded to whole 16-blocks:
-// [nrhs][Lp] per slice, with zeros in [L, Lp) that nothing writes.
+// [nrhs][Lp] per slice, with zeros in [L, Lp) that nothing writes. (The
+// transposed layout, right-hand side fastest, measured slower in the chain.)
 __host__ __device__ inline int iface_vec_len(int L) { return 16 * iface_tiles(L); }
 
 // 4 consecutive complex values from a 32-byte (float) or 16-byte (double)
@@ -514,15 +515,17 @@ __global__ __launch_bounds__(64 * NW) void k_iface_gemv(const C<T>* __restrict__
   }
 }
 
-// More than 4 right-hand sides: the products on the matrix cores. A
-// workgroup owns a 16-row x 16-column (right-hand sides) output tile and
-// splits the contraction over its NW waves; each complex 16x16x4 block is
-// four real MFMAs (Im M negated for the real accumulator). In the j-th MFMA
-// of a block, lane l supplies column 4 (l / 16) + j of M's row l % 16 and the
-// same contraction index of x's column l % 16: the index is permuted the same
-// way in both operands, which leaves the sum unchanged. A wave keeps PF
-// blocks of loads in flight ahead of its MFMAs. Tiles of one row block share
-// M's rows; they go to workgroups with equal id mod 8, i.e. the same XCD.
+// The products on the matrix cores. A workgroup owns a 16-row x 16-column
+// (right-hand sides) output tile and splits the contraction over its NW
+// waves. Each complex 16x16x4 block is three real MFMAs (Karatsuba's form:
+// with M = A + iB and x = c + id, P1 = A (c + d), P2 = (A + B) d and
+// P3 = (B - A) c give Re = P1 - P2 and Im = P1 + P3), the sums and differences
+// formed on the vector ALUs. In the j-th MFMA of a block, lane l supplies
+// column 4 (l / 16) + j of M's row l % 16 and the same contraction index of
+// x's column l % 16: the index is permuted the same way in both operands,
+// which leaves the sum unchanged. A wave keeps PF blocks of loads in flight
+// ahead of its MFMAs. Tiles of one row block share M's rows; they go to
+// workgroups with equal id mod 8, i.e. the same XCD.
 template <typename T>
 struct Mfma;
 template <>
@@ -547,6 +550,7 @@ constexpr int kMfmaWaves = 8;
 template <typename T>
 constexpr int kMfmaPrefetch = sizeof(T) == 4 ? 4 : 2;
 
+
 template <typename T, int NW = kMfmaWaves, int PF = kMfmaPrefetch<T>>
 __global__ __launch_bounds__(64 * NW) void k_iface_mfma(const C<T>* __restrict__ MZ, const C<T>* add,
                                                         const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
@@ -566,7 +570,7 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(const C<T>* __restrict__
   const C<T>* Bc = x + (size_t)(k + xoff) * vstride + (size_t)min(q * 16 + li, nrhs - 1) * Lp + 4 * g4;
   // this wave's contraction blocks: an even share [b0, b1)
   const int b0 = wave * nt / NW, b1 = (wave + 1) * nt / NW;
-  V accR = {0, 0, 0, 0}, accI = {0, 0, 0, 0};
+  V p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
   C<T> a[PF][4], bv[PF][4];
   // unconditional whole-vector loads (block index clamped to the tile range)
   auto load = [&](C<T>* ad, C<T>* bd, int b) {
@@ -582,17 +586,17 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(const C<T>* __restrict__
       if (i + s < b1) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          accR = Mfma<T>::op(a[s][j].x, bv[s][j].x, accR);
-          accI = Mfma<T>::op(a[s][j].x, bv[s][j].y, accI);
-          accR = Mfma<T>::op(-a[s][j].y, bv[s][j].y, accR);
-          accI = Mfma<T>::op(a[s][j].y, bv[s][j].x, accI);
+          const T A = a[s][j].x, B = a[s][j].y, c = bv[s][j].x, d = bv[s][j].y;
+          p1 = Mfma<T>::op(A, c + d, p1);
+          p2 = Mfma<T>::op(A + B, d, p2);
+          p3 = Mfma<T>::op(B - A, c, p3);
         }
       }
       load(a[s], bv[s], i + s + PF);
     }
   }
 #pragma unroll
-  for (int j = 0; j < 4; ++j) red[wave][Mfma<T>::out_row(g4, j)][li] = mk<T>(accR[j], accI[j]);
+  for (int j = 0; j < 4; ++j) red[wave][Mfma<T>::out_row(g4, j)][li] = mk<T>(p1[j] - p2[j], p1[j] + p3[j]);
   __syncthreads();
   // one output per thread: column t / 16, row t % 16 (consecutive rows of one
   // right-hand side are contiguous in y)
@@ -750,6 +754,8 @@ template hipError_t launch_iface_step<double>(const double2*, const double2*, co
                                               int, int, size_t, size_t, int, bool, hipStream_t);
 template hipError_t launch_iface_step<float>(const float2*, const float2*, const float2*, float2*, int, int, int,
                                              int, size_t, size_t, int, bool, hipStream_t);
+
+
 
 template <typename T>
 hipError_t launch_couple(const SliceTables& P, int L, int b, const C<T>* Hm, const C<T>* Hp, const C<T>* lam,

@@ -165,8 +165,10 @@ template <typename T>
 hipError_t launch_slice_mfma(const SliceMfmaArgs<T>& a, int nslices, hipStream_t st);
 
 // y_k = add_k - M_k x_{k+xoff} for k = kbeg .. kbeg+kcount-1 (in place allowed, y == add);
-// M in operand order (mstride = iface_map_stride(L)); mfma: on the matrix
-// cores, else vector dot products (nrhs <= 4, hipErrorInvalidValue above)
+// M in operand order (mstride = iface_map_stride(L)); x, add, y [nrhs][Lp]
+// per slice (vstride apart). mfma: on the matrix cores, one workgroup per
+// 16 x 16 output tile; else vector dot products (nrhs <= 4,
+// hipErrorInvalidValue above).
 template <typename T>
 hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
                              int kcount, size_t mstride, size_t vstride, int xoff, bool mfma, hipStream_t st);

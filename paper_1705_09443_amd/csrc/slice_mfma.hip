@@ -92,6 +92,18 @@ __device__ __attribute__((always_inline)) inline void ld4(const C<T>* p, C<T>* o
 // sides are columns of J_F Hm_k or J_E Hp_k (setup of the interface maps).
 // Source and destination addresses are fixed per lane up front, so a step is
 // straight-line code: loads, MFMAs, selects and (masked) stores.
+// One complex 16x16x4 block a * x accumulated in Karatsuba's form: with
+// a = A + iB and x = c + id, q1 += A (c + d), q2 += (A + B) d, q3 += (B - A) c,
+// so that Re = q1 - q2 and Im = q1 + q3 (three real MFMAs instead of four).
+// s = c + d is passed in, shared by the blocks that use the same x.
+template <typename T>
+__device__ __attribute__((always_inline)) inline void cmac(C<T> a, T c, T d, T s, typename MF<T>::v4& q1,
+                                                           typename MF<T>::v4& q2, typename MF<T>::v4& q3) {
+  q1 = MF<T>::op(a.x, s, q1);
+  q2 = MF<T>::op(a.x + a.y, d, q2);
+  q3 = MF<T>::op(a.y - a.x, c, q3);
+}
+
 template <typename T, int RT, int NSD, int PF, bool UNIT>
 __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaArgs<T>& A, int k, int q, int nq) {
   using V = typename MF<T>::v4;
@@ -207,42 +219,36 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
       for (int s = 0; s < PF; ++s) {
         const int j = j0 + s;
         if (j < L) {
-          V aR[RT], aI[RT];
+          // complex products in Karatsuba's form (three real MFMAs, see cmac)
+          V q1[RT], q2[RT], q3[RT];
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
-            aR[r] = aI[r] = V{0, 0, 0, 0};
+            q1[r] = q2[r] = q3[r] = V{0, 0, 0, 0};
 #pragma unroll
             for (int cc = 0; cc < NSD; ++cc) {
               const C<T> a = sv[s][r][cc], x = rv[s][cc];
-              aR[r] = MF<T>::op(a.x, x.x, aR[r]);
-              aI[r] = MF<T>::op(a.x, x.y, aI[r]);
-              aR[r] = MF<T>::op(a.y, -x.y, aR[r]);
-              aI[r] = MF<T>::op(a.y, x.x, aI[r]);
+              cmac<T>(a, x.x, x.y, x.x + x.y, q1[r], q2[r], q3[r]);
             }
           }
 #pragma unroll
           for (int kt = 0; kt < RT; ++kt) {
-            V nI = -pI[kt];
+            const V ps = pR[kt] + pI[kt];
 #pragma unroll
             for (int r = 0; r < RT; ++r)
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const C<T> w = wv[s][r * RT + kt][i];  // stored as -W
-                aR[r] = MF<T>::op(w.x, pR[kt][i], aR[r]);
-                aI[r] = MF<T>::op(w.x, pI[kt][i], aI[r]);
-                aR[r] = MF<T>::op(w.y, nI[i], aR[r]);
-                aI[r] = MF<T>::op(w.y, pR[kt][i], aI[r]);
-              }
+              for (int i = 0; i < 4; ++i)  // stored as -W
+                cmac<T>(wv[s][r * RT + kt][i], pR[kt][i], pI[kt][i], ps[i], q1[r], q2[r], q3[r]);
           }
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
-            pR[r] = aR[r];
-            pI[r] = aI[r];
+            V aR = q1[r] - q2[r], aI = q1[r] + q3[r];
+            pR[r] = aR;
+            pI[r] = aI;
             T* yp = ys + ((size_t)j * RT + r) * 512 + lane * 8;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              yp[i] = aR[r][i];
-              yp[4 + i] = aI[r][i];
+              yp[i] = aR[i];
+              yp[4 + i] = aI[i];
             }
           }
         }
@@ -276,30 +282,27 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
       for (int s = 0; s < PB; ++s) {
         const int j = j0 - s;
         if (j >= 0) {
-          V aR[RT], aI[RT];
+          // start from Y_j: Re = q1 - q2 = Re Y, Im = q1 + q3 = Im Y
+          V q1[RT], q2[RT], q3[RT];
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
-            aR[r] = V{yv[s][r][0], yv[s][r][1], yv[s][r][2], yv[s][r][3]};
-            aI[r] = V{yv[s][r][4], yv[s][r][5], yv[s][r][6], yv[s][r][7]};
+            q1[r] = V{0, 0, 0, 0};
+            q2[r] = -V{yv[s][r][0], yv[s][r][1], yv[s][r][2], yv[s][r][3]};
+            q3[r] = V{yv[s][r][4], yv[s][r][5], yv[s][r][6], yv[s][r][7]};
           }
 #pragma unroll
           for (int kt = 0; kt < RT; ++kt) {
-            V nI = -pI[kt];
+            const V ps = pR[kt] + pI[kt];
 #pragma unroll
             for (int r = 0; r < RT; ++r)
 #pragma unroll
-              for (int i = 0; i < 4; ++i) {
-                const C<T> w = gv[s][r * RT + kt][i];  // stored as -G
-                aR[r] = MF<T>::op(w.x, pR[kt][i], aR[r]);
-                aI[r] = MF<T>::op(w.x, pI[kt][i], aI[r]);
-                aR[r] = MF<T>::op(w.y, nI[i], aR[r]);
-                aI[r] = MF<T>::op(w.y, pR[kt][i], aI[r]);
-              }
+              for (int i = 0; i < 4; ++i)  // stored as -G
+                cmac<T>(gv[s][r * RT + kt][i], pR[kt][i], pI[kt][i], ps[i], q1[r], q2[r], q3[r]);
           }
 #pragma unroll
           for (int r = 0; r < RT; ++r) {
-            pR[r] = aR[r];
-            pI[r] = aI[r];
+            pR[r] = q1[r] - q2[r];
+            pI[r] = q1[r] + q3[r];
           }
           emit(j, pR, pI);
         }
