@@ -479,8 +479,9 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
       p.dstE = p.dstF = nullptr;
       return solve_slices<T>(h, p, k0, k1, R, s);
     };
-    // graphs: part 0 the lambda recurrence, part 1 the P term, the mu
-    // recurrence and the coupling of the slices on the main stream. The last
+    // graphs: part 0 the lambda recurrence (with the P terms of slices 1 ..
+    // l-2), part 1 the last P term, the mu recurrence and the coupling of the
+    // slices on the main stream. The last
     // slice's coupling (lambda term only) runs on the second stream after its
     // own phase A, which reads the line it changes.
     auto graph = [&](int part, hipGraphExec_t& out) -> ls_status {
@@ -499,10 +500,14 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
       LSW_HIP_TRY(hipStreamBeginCapture(h->cst, hipStreamCaptureModeThreadLocal));
       hipError_t ce = hipSuccess;
       if (part == 0) {
+        // lambda_k = lambda_k - M_k lambda_{k-1}, and in the same launch the P
+        // term of slice k, mu_k -= P_k lambda_{k-1}, which reads the same vector
         for (int k = 1; k <= nl - 2 && ce == hipSuccess; ++k)
-          ce = launch_iface_step<T>(IM, lam, lam, lam, L, nb, k, 1, MS, vs, -1, imf, h->cst);
+          ce = launch_iface_step<T>(IM, lam, lam, lam, L, nb, k, 1, MS, vs, -1, imf, h->cst, IP, mu, mu);
       } else {
-        ce = launch_iface_step<T>(IP, mu, lam, mu, L, nb, 1, nl - 1, MS, vs, -1, imf, h->cst);
+        // the P term of the last slice (all of them when there are two slices)
+        const int kp = nl > 2 ? nl - 1 : 1;
+        ce = launch_iface_step<T>(IP, mu, lam, mu, L, nb, kp, nl - kp, MS, vs, -1, imf, h->cst);
         for (int k = nl - 2; k >= 1 && ce == hipSuccess; --k)
           ce = launch_iface_step<T>(IN, mu, mu, mu, L, nb, k, 1, MS, vs, +1, imf, h->cst);
         if (ce == hipSuccess) ce = launch_couple<T>(h->slices(), L, h->b, Hm, Hp, lam, mu, nb, f, 0, kmain, h->cst);

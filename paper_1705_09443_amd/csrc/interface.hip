@@ -458,13 +458,18 @@ __global__ void k_swizzle_maps(const C<T>* __restrict__ src, C<T>* __restrict__ 
 // partial dot products over the block's 4 columns it holds, the four lanes of
 // a row then reduce by shuffles and the waves through LDS.
 template <typename T, int NW>
-__global__ __launch_bounds__(64 * NW) void k_iface_gemv(const C<T>* __restrict__ MZ, const C<T>* add, const C<T>* x,
-                                                        C<T>* y, int L, int nrhs, int kbeg, size_t mstride,
-                                                        size_t vstride, int xoff) {
+__global__ __launch_bounds__(64 * NW) void k_iface_gemv(IfaceProd<T> pa, IfaceProd<T> pb, const C<T>* x, int L,
+                                                        int nrhs, int kbeg, size_t mstride, size_t vstride,
+                                                        int xoff) {
   constexpr int MAXB = 6;  // blocks of one wave in flight at once
   __shared__ C<T> red[NW][4][16];
   const int nt = iface_tiles(L);
-  const int r = blockIdx.x, k = kbeg + blockIdx.z;
+  const bool two = pb.M != nullptr;
+  const IfaceProd<T> pr = two && blockIdx.z ? pb : pa;
+  const C<T>* MZ = pr.M;
+  const C<T>* add = pr.add;
+  C<T>* y = pr.y;
+  const int r = blockIdx.x, k = kbeg + (two ? 0 : (int)blockIdx.z);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g4 = lane >> 4;
   const int Lp = iface_vec_len(L);
   const C<T>* Mr = MZ + (size_t)k * mstride + (size_t)r * nt * 256 + lane * 4;
@@ -552,17 +557,22 @@ constexpr int kMfmaPrefetch = sizeof(T) == 4 ? 4 : 2;
 
 
 template <typename T, int NW = kMfmaWaves, int PF = kMfmaPrefetch<T>>
-__global__ __launch_bounds__(64 * NW) void k_iface_mfma(const C<T>* __restrict__ MZ, const C<T>* add,
-                                                        const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
-                                                        size_t mstride, size_t vstride, int xoff, int qtiles) {
+__global__ __launch_bounds__(64 * NW) void k_iface_mfma(IfaceProd<T> pa, IfaceProd<T> pb, const C<T>* x, int L,
+                                                        int nrhs, int kbeg, size_t mstride, size_t vstride, int xoff,
+                                                        int qtiles) {
   using V = typename Mfma<T>::v4;
   __shared__ C<T> red[NW][16][17];
   const int nt = iface_tiles(L);
+  const bool two = pb.M != nullptr;
+  const IfaceProd<T> pr = two && blockIdx.z ? pb : pa;
+  const C<T>* MZ = pr.M;
+  const C<T>* add = pr.add;
+  C<T>* y = pr.y;
   const int id = blockIdx.x;
   const int per = 8 * qtiles;  // workgroups per group of 8 row blocks
   const int r = (id / per) * 8 + id % 8, q = (id % per) / 8;
   if (r >= nt) return;  // whole workgroup: the grid is rounded up to 8 row blocks
-  const int k = kbeg + blockIdx.z;
+  const int k = kbeg + (two ? 0 : (int)blockIdx.z);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g4 = lane >> 4;
   const int Lp = iface_vec_len(L);
   const C<T>* Mr = MZ + (size_t)k * mstride + (size_t)r * nt * 256 + lane * 4;
@@ -735,25 +745,31 @@ template hipError_t launch_swizzle_maps<float>(const float2*, float2*, int, int,
 
 template <typename T>
 hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
-                             int kcount, size_t mstride, size_t vstride, int xoff, bool mfma, hipStream_t st) {
+                             int kcount, size_t mstride, size_t vstride, int xoff, bool mfma, hipStream_t st,
+                             const C<T>* M2, const C<T>* add2, C<T>* y2) {
   if (kcount <= 0) return hipSuccess;
   const int nt = iface_tiles(L);
   if (!mfma && nrhs > 4) return hipErrorInvalidValue;  // the vector form holds at most 4 columns
+  if (M2 && kcount != 1) return hipErrorInvalidValue;  // a second product only beside a single one
+  const IfaceProd<T> p0{M, add, y}, p1{M2, add2, y2};
+  const int nz = M2 ? 2 : kcount;
   if (!mfma) {
     constexpr int NW = 8;
-    hipLaunchKernelGGL((k_iface_gemv<T, NW>), dim3(nt, 1, kcount), dim3(64 * NW), 0, st, M, add, x, y, L, nrhs, kbeg,
+    hipLaunchKernelGGL((k_iface_gemv<T, NW>), dim3(nt, 1, nz), dim3(64 * NW), 0, st, p0, p1, x, L, nrhs, kbeg,
                        mstride, vstride, xoff);
   } else {
     const int qtiles = (nrhs + 15) / 16, groups = (nt + 7) / 8;
-    hipLaunchKernelGGL((k_iface_mfma<T>), dim3(groups * 8 * qtiles, 1, kcount), dim3(64 * kMfmaWaves), 0, st, M, add,
-                       x, y, L, nrhs, kbeg, mstride, vstride, xoff, qtiles);
+    hipLaunchKernelGGL((k_iface_mfma<T>), dim3(groups * 8 * qtiles, 1, nz), dim3(64 * kMfmaWaves), 0, st, p0, p1, x,
+                       L, nrhs, kbeg, mstride, vstride, xoff, qtiles);
   }
   return hipGetLastError();
 }
 template hipError_t launch_iface_step<double>(const double2*, const double2*, const double2*, double2*, int, int,
-                                              int, int, size_t, size_t, int, bool, hipStream_t);
+                                              int, int, size_t, size_t, int, bool, hipStream_t, const double2*,
+                                              const double2*, double2*);
 template hipError_t launch_iface_step<float>(const float2*, const float2*, const float2*, float2*, int, int, int,
-                                             int, size_t, size_t, int, bool, hipStream_t);
+                                             int, size_t, size_t, int, bool, hipStream_t, const float2*,
+                                             const float2*, float2*);
 
 
 

@@ -169,9 +169,18 @@ hipError_t launch_slice_mfma(const SliceMfmaArgs<T>& a, int nslices, hipStream_t
 // per slice (vstride apart). mfma: on the matrix cores, one workgroup per
 // 16 x 16 output tile; else vector dot products (nrhs <= 4,
 // hipErrorInvalidValue above).
+// With M2 (kcount = 1), the same launch also forms y2_k = add2_k - M2_k x_{k+xoff}
+// from the same x.
+template <typename T>
+struct IfaceProd {
+  const C<T>* M;
+  const C<T>* add;
+  C<T>* y;
+};
 template <typename T>
 hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
-                             int kcount, size_t mstride, size_t vstride, int xoff, bool mfma, hipStream_t st);
+                             int kcount, size_t mstride, size_t vstride, int xoff, bool mfma, hipStream_t st,
+                             const C<T>* M2 = nullptr, const C<T>* add2 = nullptr, C<T>* y2 = nullptr);
 // f -= J_F Hm_k lambda_{k-1} + J_E Hp_k mu_{k+1} on slices [k0, k1)
 template <typename T>
 hipError_t launch_couple(const SliceTables& P, int L, int b, const C<T>* Hm, const C<T>* Hp, const C<T>* lam,
