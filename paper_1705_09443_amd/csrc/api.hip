@@ -110,7 +110,7 @@ struct ls_handle {
   int cap = 0;  // right-hand sides the workspaces hold
   DBuf fftw64, fftw32, fext, uext, yscr, vin, zout, aout, lam, mu, sscr, mscr;
   DBuf V, Z, W, X, G, R, T1, T2;
-  DBuf pairs, partials, coefs, outs, terms64, terms32, ptrs_a, ptrs_b;
+  DBuf pairs, groups, partials, coefs, outs, terms64, terms32, ptrs_a, ptrs_b;
   // adjoint state
   int last_nrhs = 0;
   DBuf psi;
@@ -299,7 +299,9 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   LSW_ALLOC(h->T2, (size_t)nrhs * N * sizeof(double2));
   const size_t maxpairs = (size_t)nrhs * (rs + 2);
   LSW_ALLOC(h->pairs, maxpairs * sizeof(DotPair));
-  LSW_ALLOC(h->partials, maxpairs * kDotBlocks * sizeof(double2));
+  LSW_ALLOC(h->groups, maxpairs * sizeof(DotGroup));
+  // dot-product partials: kDotBlocks per pair, or 256 per norm of an update
+  LSW_ALLOC(h->partials, std::max(maxpairs * kDotBlocks, (size_t)nrhs * 256) * sizeof(double2));
   LSW_ALLOC(h->coefs, (4 * maxpairs + 16) * sizeof(double2));
   LSW_ALLOC(h->outs, (size_t)nrhs * 2 * sizeof(AxpyOut));
   // two Gram-Schmidt passes of up to nrhs * restart terms each
@@ -736,6 +738,7 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
   LSW_HIP_TRY(hipMemsetAsync(Xb, 0, (size_t)nrhs * N * sizeof(double2), st));
 
   std::vector<DotPair> hp;
+  std::vector<DotGroup> hg;
   std::vector<AxpyOut> ho;
   std::vector<AxpyTerm<double>> ht64;
   std::vector<AxpyTerm<T>> htT;
@@ -848,8 +851,6 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       off[p + 1] = (int)hp.size();
     }
     const int np = (int)hp.size();
-    for (int p = 0; p < na; ++p) hp.push_back({Wb + (size_t)act[p] * N, Wb + (size_t)act[p] * N});
-    if (upload(h, h->pairs, hp) != LS_OK) return LS_E_DEVICE;
     const int base1 = 1, base2 = 1 + np, base3 = 1 + 2 * np;
     ho.clear();
     ht64.clear();
@@ -870,13 +871,29 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       ho.push_back(o);
     }
     hc.assign(1, one);
-    if (upload(h, h->coefs, hc) != LS_OK || upload(h, h->outs, ho) != LS_OK || upload(h, h->terms64, ht64) != LS_OK)
+    // the dot products of a right-hand side share its w: groups of up to
+    // kDotGroup basis vectors read it once
+    hg.clear();
+    for (int p = 0; p < na; ++p)
+      for (int i = off[p]; i < off[p + 1]; i += kDotGroup) {
+        DotGroup g{};
+        g.y = Wb + (size_t)act[p] * N;
+        g.count = std::min(kDotGroup, off[p + 1] - i);
+        g.pbase = i;
+        for (int k = 0; k < g.count; ++k) g.x[k] = hp[i + k].x;
+        hg.push_back(g);
+      }
+    if (upload(h, h->coefs, hc) != LS_OK || upload(h, h->outs, ho) != LS_OK ||
+        upload(h, h->terms64, ht64) != LS_OK || upload(h, h->groups, hg) != LS_OK)
       return LS_E_DEVICE;
-    LSW_HIP_TRY(launch_dots(h->pairs.as<DotPair>(), np, N, h->partials.as<double2>(), coefs + base1, st));
+    const int ng = (int)hg.size();
+    double2* part = h->partials.as<double2>();
+    LSW_HIP_TRY(launch_mdots(h->groups.as<DotGroup>(), ng, np, N, part, coefs + base1, st));
     LSW_HIP_TRY(launch_axpys<double>(h->outs.as<AxpyOut>(), na, h->terms64.as<AxpyTerm<double>>(), coefs, N, st));
-    LSW_HIP_TRY(launch_dots(h->pairs.as<DotPair>(), np, N, h->partials.as<double2>(), coefs + base2, st));
-    LSW_HIP_TRY(launch_axpys<double>(h->outs.as<AxpyOut>() + na, na, h->terms64.as<AxpyTerm<double>>(), coefs, N, st));
-    LSW_HIP_TRY(launch_dots(h->pairs.as<DotPair>() + np, na, N, h->partials.as<double2>(), coefs + base3, st));
+    LSW_HIP_TRY(launch_mdots(h->groups.as<DotGroup>(), ng, np, N, part, coefs + base2, st));
+    // the second update also forms ||w||^2
+    LSW_HIP_TRY(launch_axpys_norms(h->outs.as<AxpyOut>() + na, na, h->terms64.as<AxpyTerm<double>>(), coefs, N,
+                                   part, coefs + base3, st));
     hc.resize(base3 + na);
     LSW_HIP_TRY(hipMemcpyAsync(hc.data(), coefs, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
     LSW_HIP_TRY(hipStreamSynchronize(st));

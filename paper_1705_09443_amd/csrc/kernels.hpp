@@ -196,6 +196,20 @@ struct DotPair {
 constexpr int kDotBlocks = 64;
 hipError_t launch_dots(const DotPair* pairs, int npairs, size_t N, double2* partials, double2* out,
                        hipStream_t st);
+// The same dot products grouped by a shared y: group g forms
+// out[pbase_g + k] = sum conj(x_{g,k}) y_g for k < count_g <= kDotGroup, reading
+// y_g once for all of them; every product is summed in the same order as
+// launch_dots would (bitwise the same results). npairs: the number of out
+// entries the groups cover, each once.
+constexpr int kDotGroup = 8;
+struct DotGroup {
+  const double2* y;
+  const double2* x[kDotGroup];
+  int count;
+  int pbase;
+};
+hipError_t launch_mdots(const DotGroup* groups, int ngroups, int npairs, size_t N, double2* partials, double2* out,
+                        hipStream_t st);
 // y_o = beta_o * y_o + sum_t c_t x_t. Terms of output o are [tbeg[o], tbeg[o+1]).
 template <typename TX>
 struct AxpyTerm {
@@ -211,8 +225,13 @@ struct AxpyOut {
   int sqrt_scale;
 };
 template <typename TX>
-hipError_t launch_axpys(const AxpyOut* outs, int nout, const AxpyTerm<TX>* terms,
-                        const double2* coefs, size_t N, hipStream_t st);
+hipError_t launch_axpys(const AxpyOut* outs, int nout, const AxpyTerm<TX>* terms, const double2* coefs,
+                        size_t N, hipStream_t st);
+// launch_axpys that also forms norm2[o] = ||y_o||^2 of every updated output
+// (in the pass that writes it; fixed-order reduction through partials, which
+// needs nout * 256 entries)
+hipError_t launch_axpys_norms(const AxpyOut* outs, int nout, const AxpyTerm<double>* terms, const double2* coefs,
+                              size_t N, double2* partials, double2* norm2, hipStream_t st);
 // dst[p] = cast(src[p]) for npairs contiguous batches of N entries.
 template <typename TD, typename TS>
 hipError_t launch_copy_cast(C<TD>* const* dst, const C<TS>* const* src, int npairs, size_t N,

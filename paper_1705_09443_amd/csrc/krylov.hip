@@ -46,22 +46,77 @@ __global__ __launch_bounds__(kThreads) void k_dot_partials(const DotPair* __rest
   }
 }
 
-__global__ void k_dot_reduce(const double2* __restrict__ partials, int npairs, double2* __restrict__ out) {
+// The dot products of one group (shared y) per blockIdx.y: the same per-pair
+// arithmetic and order as k_dot_partials, with y read once.
+__global__ __launch_bounds__(kThreads) void k_mdot_partials(const DotGroup* __restrict__ groups, size_t N,
+                                                            double2* __restrict__ partials) {
+  const int blk = blockIdx.x;
+  const DotGroup& gr = groups[blockIdx.y];
+  const int cnt = gr.count;
+  const size_t chunk = (N + kDotBlocks - 1) / kDotBlocks;
+  const size_t beg = blk * chunk;
+  const size_t end = beg + chunk < N ? beg + chunk : N;
+  const double2* xs[kDotGroup];
+#pragma unroll
+  for (int k = 0; k < kDotGroup; ++k) xs[k] = gr.x[k < cnt ? k : 0];
+  double2 acc[kDotGroup];
+#pragma unroll
+  for (int k = 0; k < kDotGroup; ++k) acc[k] = make_double2(0.0, 0.0);
+  for (size_t i = beg + threadIdx.x; i < end; i += kThreads) {
+    const double2 c = gr.y[i];
+#pragma unroll
+    for (int k = 0; k < kDotGroup; ++k) {
+      if (k < cnt) {
+        const double2 a = xs[k][i];
+        acc[k].x += a.x * c.x + a.y * c.y;
+        acc[k].y += a.x * c.y - a.y * c.x;
+      }
+    }
+  }
+  __shared__ double2 ws[kDotGroup][kThreads / 64];
+#pragma unroll
+  for (int k = 0; k < kDotGroup; ++k) {
+    if (k < cnt) {
+      const double2 v = wave_sum(acc[k]);
+      if ((threadIdx.x & 63) == 0) ws[k][threadIdx.x >> 6] = v;
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < cnt) {
+    const int k = threadIdx.x;
+    double2 s = ws[k][0];
+    for (int w = 1; w < kThreads / 64; ++w) {
+      s.x += ws[k][w].x;
+      s.y += ws[k][w].y;
+    }
+    partials[(size_t)(gr.pbase + k) * kDotBlocks + blk] = s;
+  }
+}
+
+__global__ void k_dot_reduce(const double2* __restrict__ partials, int npairs, double2* __restrict__ out,
+                             int nparts = kDotBlocks) {
   const int p = blockIdx.x * blockDim.x + threadIdx.x;
   if (p >= npairs) return;
   double2 s = make_double2(0.0, 0.0);
-  for (int b = 0; b < kDotBlocks; ++b) {
-    s.x += partials[(size_t)p * kDotBlocks + b].x;
-    s.y += partials[(size_t)p * kDotBlocks + b].y;
+  for (int b = 0; b < nparts; ++b) {
+    s.x += partials[(size_t)p * nparts + b].x;
+    s.y += partials[(size_t)p * nparts + b].y;
   }
   out[p] = s;
 }
 
+// blocks (and partial sums) per output of the updates that also form norms
+constexpr int kNormBlocks = 256;
+
+// norm_partials (optional): ||y_o||^2 of this block's share of the updated
+// output, at norm_partials[o * gridDim.x + blockIdx.x]
 template <typename TX>
 __global__ __launch_bounds__(kThreads) void k_axpys(const AxpyOut* __restrict__ outs,
                                                     const AxpyTerm<TX>* __restrict__ terms,
-                                                    const double2* __restrict__ coefs, size_t N) {
+                                                    const double2* __restrict__ coefs, size_t N,
+                                                    double2* __restrict__ norm_partials) {
   const AxpyOut o = outs[blockIdx.y];
+  double nrm = 0.0;
   double sc = 1.0;
   if (o.scale_coef >= 0) {
     const double v = coefs[o.scale_coef].x;
@@ -84,6 +139,18 @@ __global__ __launch_bounds__(kThreads) void k_axpys(const AxpyOut* __restrict__ 
     y.x = (y.x + acc.x) * sc;
     y.y = (y.y + acc.y) * sc;
     o.y[i] = y;
+    nrm += y.x * y.x + y.y * y.y;
+  }
+  if (norm_partials) {
+    const double2 v = wave_sum(make_double2(nrm, 0.0));
+    __shared__ double ws[kThreads / 64];
+    if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v.x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double s = ws[0];
+      for (int w = 1; w < kThreads / 64; ++w) s += ws[w];
+      norm_partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = make_double2(s, 0.0);
+    }
   }
 }
 
@@ -148,7 +215,15 @@ hipError_t launch_dots(const DotPair* pairs, int npairs, size_t N, double2* part
                        hipStream_t st) {
   if (npairs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_dot_partials, dim3(kDotBlocks, npairs), dim3(kThreads), 0, st, pairs, N, partials);
-  hipLaunchKernelGGL(k_dot_reduce, dim3((npairs + 127) / 128), dim3(128), 0, st, partials, npairs, out);
+  hipLaunchKernelGGL(k_dot_reduce, dim3((npairs + 127) / 128), dim3(128), 0, st, partials, npairs, out, kDotBlocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_mdots(const DotGroup* groups, int ngroups, int npairs, size_t N, double2* partials, double2* out,
+                        hipStream_t st) {
+  if (ngroups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mdot_partials, dim3(kDotBlocks, ngroups), dim3(kThreads), 0, st, groups, N, partials);
+  hipLaunchKernelGGL(k_dot_reduce, dim3((npairs + 127) / 128), dim3(128), 0, st, partials, npairs, out, kDotBlocks);
   return hipGetLastError();
 }
 
@@ -158,7 +233,16 @@ hipError_t launch_axpys(const AxpyOut* outs, int nout, const AxpyTerm<TX>* terms
   if (nout <= 0) return hipSuccess;
   unsigned g = grid_for(N);
   if (g > 512) g = 512;
-  hipLaunchKernelGGL(k_axpys<TX>, dim3(g, nout), dim3(kThreads), 0, st, outs, terms, coefs, N);
+  hipLaunchKernelGGL(k_axpys<TX>, dim3(g, nout), dim3(kThreads), 0, st, outs, terms, coefs, N, (double2*)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpys_norms(const AxpyOut* outs, int nout, const AxpyTerm<double>* terms, const double2* coefs,
+                              size_t N, double2* partials, double2* norm2, hipStream_t st) {
+  if (nout <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_axpys<double>, dim3(kNormBlocks, nout), dim3(kThreads), 0, st, outs, terms, coefs, N,
+                     partials);
+  hipLaunchKernelGGL(k_dot_reduce, dim3((nout + 127) / 128), dim3(128), 0, st, partials, nout, norm2, kNormBlocks);
   return hipGetLastError();
 }
 template hipError_t launch_axpys<double>(const AxpyOut*, int, const AxpyTerm<double>*, const double2*,
