@@ -57,6 +57,53 @@ struct DBuf {
   X* as() const { return static_cast<X*>(p); }
 };
 
+// Descriptor tables of one phase of an iteration, written into pinned host
+// memory and sent to the device with one asynchronous copy, so that the host
+// never waits for the device to drain just to upload them. The caller
+// rewrites a stage only once the copy and every launch that reads its device
+// copy have completed (after a later synchronisation).
+struct Stage {
+  char* host = nullptr;
+  DBuf dev;
+  size_t cap = 0, used = 0;
+  Stage() = default;
+  Stage(const Stage&) = delete;
+  Stage& operator=(const Stage&) = delete;
+  ~Stage() {
+    if (host) (void)hipHostFree(host);
+  }
+  hipError_t alloc(size_t bytes) {
+    if (bytes <= cap && host) return hipSuccess;
+    if (host) (void)hipHostFree(host);
+    host = nullptr;
+    cap = 0;
+    hipError_t e = hipHostMalloc(reinterpret_cast<void**>(&host), bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return e;
+    e = dev.alloc(bytes);
+    if (e != hipSuccess) return e;
+    cap = bytes;
+    return hipSuccess;
+  }
+  void reset() { used = 0; }
+  // appends the table (256-byte aligned) and returns its device address
+  template <typename X>
+  X* put(const X* data, size_t count) {
+    const size_t off = (used + 255) & ~size_t(255), bytes = count * sizeof(X);
+    if (off + bytes > cap) return nullptr;
+    if (bytes) std::memcpy(host + off, data, bytes);
+    used = off + bytes;
+    return reinterpret_cast<X*>(dev.as<char>() + off);
+  }
+  template <typename X>
+  X* put(const std::vector<X>& v) {
+    return put(v.data(), v.size());
+  }
+  hipError_t flush(hipStream_t st) {
+    if (!used) return hipSuccess;
+    return hipMemcpyAsync(dev.p, host, used, hipMemcpyHostToDevice, st);
+  }
+};
+
 #define LSW_ALLOC(buf, nbytes)                                                      \
   do {                                                                              \
     if ((buf).alloc(nbytes) != hipSuccess) {                                        \
@@ -111,6 +158,8 @@ struct ls_handle {
   DBuf fftw64, fftw32, fext, uext, yscr, vin, zout, aout, lam, mu, sscr, mscr;
   DBuf V, Z, W, X, G, R, T1, T2;
   DBuf pairs, groups, partials, coefs, outs, terms64, terms32, ptrs_a, ptrs_b;
+  // descriptor stages of the Arnoldi step: before and after its readback
+  Stage stage_main, stage_post;
   // adjoint state
   int last_nrhs = 0;
   DBuf psi;
@@ -309,6 +358,18 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   LSW_ALLOC(h->terms32, (2 * maxpairs + 2 * nrhs) * sizeof(AxpyTerm<float>));
   LSW_ALLOC(h->ptrs_a, (size_t)nrhs * sizeof(void*));
   LSW_ALLOC(h->ptrs_b, (size_t)nrhs * sizeof(void*));
+  {
+    // 3 pointer pairs per right-hand side, dot groups and update terms of up
+    // to maxpairs products, 2 outputs per right-hand side, alignment slack
+    const size_t main_bytes = (size_t)nrhs * 6 * sizeof(void*) + maxpairs * (sizeof(DotGroup) + 2 * sizeof(AxpyTerm<double>)) +
+                              (size_t)nrhs * 2 * sizeof(AxpyOut) + sizeof(double2) + 16 * 256;
+    const size_t post_bytes = (size_t)nrhs * (sizeof(AxpyOut) + sizeof(AxpyTerm<double>)) + 4 * 256;
+    if (h->stage_main.alloc(main_bytes) != hipSuccess || h->stage_post.alloc(post_bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      set_error("pinned host allocation for the descriptor stages failed");
+      return LS_E_NOMEM;
+    }
+  }
   h->cap = nrhs;
   return LS_OK;
 }
@@ -813,35 +874,35 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     C<T>* vin = h->vin.as<C<T>>();
     C<T>* zout = h->zout.as<C<T>>();
     C<T>* aout = h->aout.as<C<T>>();
-    // z = P v_j (precision T), kept in Z
+    // Every descriptor of this step up to the readback goes through one
+    // asynchronous copy of the main stage; the host does not wait for the
+    // device until the readback.
+    Stage& sm = h->stage_main;
+    sm.reset();
     pa.clear();
     pb.clear();
     for (int p = 0; p < na; ++p) {
       pa.push_back(vin + (size_t)p * N);
       pb.push_back(Vp(act[p], S[act[p]].j));
     }
-    if (upload(h, h->ptrs_a, pa) != LS_OK || upload(h, h->ptrs_b, pb) != LS_OK) return LS_E_DEVICE;
-    LSW_HIP_TRY((launch_copy_cast<T, double>(h->ptrs_a.as<C<T>*>(), h->ptrs_b.as<const double2*>(), na, N, st)));
-    ls_status e = apply_P<T>(h, vin, na, zout);
-    if (e != LS_OK) return e;
+    C<T>** cin_d = reinterpret_cast<C<T>**>(sm.put(pa));
+    const double2* const* cin_s = reinterpret_cast<const double2* const*>(sm.put(pb));
     pa.clear();
     pb.clear();
     for (int p = 0; p < na; ++p) {
       pa.push_back(Zp(act[p], S[act[p]].j));
       pb.push_back(zout + (size_t)p * N);
     }
-    if (upload(h, h->ptrs_a, pa) != LS_OK || upload(h, h->ptrs_b, pb) != LS_OK) return LS_E_DEVICE;
-    LSW_HIP_TRY((launch_copy_cast<T, T>(h->ptrs_a.as<C<T>*>(), h->ptrs_b.as<const C<T>*>(), na, N, st)));
-    // w = A z (precision T) -> float64 work vector W[r]
-    if ((e = apply_A<T>(h, zout, na, aout)) != LS_OK) return e;
+    C<T>** cz_d = reinterpret_cast<C<T>**>(sm.put(pa));
+    const C<T>* const* cz_s = reinterpret_cast<const C<T>* const*>(sm.put(pb));
     pa.clear();
     pb.clear();
     for (int p = 0; p < na; ++p) {
       pa.push_back(Wb + (size_t)act[p] * N);
       pb.push_back(aout + (size_t)p * N);
     }
-    if (upload(h, h->ptrs_a, pa) != LS_OK || upload(h, h->ptrs_b, pb) != LS_OK) return LS_E_DEVICE;
-    LSW_HIP_TRY((launch_copy_cast<double, T>(h->ptrs_a.as<double2*>(), h->ptrs_b.as<const C<T>*>(), na, N, st)));
+    double2** cw_d = reinterpret_cast<double2**>(sm.put(pa));
+    const C<T>* const* cw_s = reinterpret_cast<const C<T>* const*>(sm.put(pb));
     // classical Gram-Schmidt, twice, then the norm
     hp.clear();
     std::vector<int> off(na + 1, 0);
@@ -870,7 +931,6 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       o.tend += nterm;
       ho.push_back(o);
     }
-    hc.assign(1, one);
     // the dot products of a right-hand side share its w: groups of up to
     // kDotGroup basis vectors read it once
     hg.clear();
@@ -883,17 +943,32 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
         for (int k = 0; k < g.count; ++k) g.x[k] = hp[i + k].x;
         hg.push_back(g);
       }
-    if (upload(h, h->coefs, hc) != LS_OK || upload(h, h->outs, ho) != LS_OK ||
-        upload(h, h->terms64, ht64) != LS_OK || upload(h, h->groups, hg) != LS_OK)
-      return LS_E_DEVICE;
+    const AxpyOut* outs_d = sm.put(ho);
+    const AxpyTerm<double>* terms_d = sm.put(ht64);
+    const DotGroup* groups_d = sm.put(hg);
+    const double2* one_d = sm.put(&one, 1);
+    if (!cin_d || !cin_s || !cz_d || !cz_s || !cw_d || !cw_s || !outs_d || !terms_d || !groups_d || !one_d) {
+      set_error("internal: descriptor stage too small");
+      return LS_E_STATE;
+    }
+    LSW_HIP_TRY(sm.flush(st));
+    // coefs[0] = 1 (the unit coefficient of the normalisation below)
+    LSW_HIP_TRY(hipMemcpyAsync(coefs, one_d, sizeof(double2), hipMemcpyDeviceToDevice, st));
+    // z = P v_j (precision T), kept in Z
+    LSW_HIP_TRY((launch_copy_cast<T, double>(cin_d, cin_s, na, N, st)));
+    ls_status e = apply_P<T>(h, vin, na, zout);
+    if (e != LS_OK) return e;
+    LSW_HIP_TRY((launch_copy_cast<T, T>(cz_d, cz_s, na, N, st)));
+    // w = A z (precision T) -> float64 work vector W[r]
+    if ((e = apply_A<T>(h, zout, na, aout)) != LS_OK) return e;
+    LSW_HIP_TRY((launch_copy_cast<double, T>(cw_d, cw_s, na, N, st)));
     const int ng = (int)hg.size();
     double2* part = h->partials.as<double2>();
-    LSW_HIP_TRY(launch_mdots(h->groups.as<DotGroup>(), ng, np, N, part, coefs + base1, st));
-    LSW_HIP_TRY(launch_axpys<double>(h->outs.as<AxpyOut>(), na, h->terms64.as<AxpyTerm<double>>(), coefs, N, st));
-    LSW_HIP_TRY(launch_mdots(h->groups.as<DotGroup>(), ng, np, N, part, coefs + base2, st));
+    LSW_HIP_TRY(launch_mdots(groups_d, ng, np, N, part, coefs + base1, st));
+    LSW_HIP_TRY(launch_axpys<double>(outs_d, na, terms_d, coefs, N, st));
+    LSW_HIP_TRY(launch_mdots(groups_d, ng, np, N, part, coefs + base2, st));
     // the second update also forms ||w||^2
-    LSW_HIP_TRY(launch_axpys_norms(h->outs.as<AxpyOut>() + na, na, h->terms64.as<AxpyTerm<double>>(), coefs, N,
-                                   part, coefs + base3, st));
+    LSW_HIP_TRY(launch_axpys_norms(outs_d + na, na, terms_d, coefs, N, part, coefs + base3, st));
     hc.resize(base3 + na);
     LSW_HIP_TRY(hipMemcpyAsync(hc.data(), coefs, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
     LSW_HIP_TRY(hipStreamSynchronize(st));
@@ -942,10 +1017,18 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       }
     }
     if (!ho.empty()) {
-      if (upload(h, h->outs, ho) != LS_OK || upload(h, h->terms64, ht64) != LS_OK) return LS_E_DEVICE;
-      LSW_HIP_TRY(launch_axpys<double>(h->outs.as<AxpyOut>(), (int)ho.size(), h->terms64.as<AxpyTerm<double>>(),
-                                       coefs, N, st));
-      LSW_HIP_TRY(hipStreamSynchronize(st));
+      // through the post stage, without waiting: the next step's launches
+      // follow on the same stream
+      Stage& sp = h->stage_post;
+      sp.reset();
+      const AxpyOut* o_d = sp.put(ho);
+      const AxpyTerm<double>* t_d = sp.put(ht64);
+      if (!o_d || !t_d) {
+        set_error("internal: descriptor stage too small");
+        return LS_E_STATE;
+      }
+      LSW_HIP_TRY(sp.flush(st));
+      LSW_HIP_TRY(launch_axpys<double>(o_d, (int)ho.size(), t_d, coefs, N, st));
     }
     if (ending.empty()) continue;
     // cycle end: x += Z y, true residual in float64
