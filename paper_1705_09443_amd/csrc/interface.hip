@@ -759,8 +759,15 @@ hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>
                        mstride, vstride, xoff);
   } else {
     const int qtiles = (nrhs + 15) / 16, groups = (nt + 7) / 8;
-    hipLaunchKernelGGL((k_iface_mfma<T>), dim3(groups * 8 * qtiles, 1, nz), dim3(64 * kMfmaWaves), 0, st, p0, p1, x,
-                       L, nrhs, kbeg, mstride, vstride, xoff, qtiles);
+    const dim3 grid(groups * 8 * qtiles, 1, nz), block(64 * kMfmaWaves);
+    // more than two column tiles put two workgroups on some compute units,
+    // where two blocks of loads in flight per wave measured faster than four
+    if (qtiles > 2)
+      hipLaunchKernelGGL((k_iface_mfma<T, kMfmaWaves, 2>), grid, block, 0, st, p0, p1, x, L, nrhs, kbeg, mstride,
+                         vstride, xoff, qtiles);
+    else
+      hipLaunchKernelGGL((k_iface_mfma<T>), grid, block, 0, st, p0, p1, x, L, nrhs, kbeg, mstride, vstride, xoff,
+                         qtiles);
   }
   return hipGetLastError();
 }
