@@ -31,7 +31,8 @@
  *  - Work is enqueued on opts.hip_stream (NULL: the default stream); every
  *    entry point returns with its work complete (host-synchronised).
  *  - Calls on one handle must not overlap.
- *  - Only dim = 2 is implemented; other values return LS_E_INVALID.
+ *  - ls_setup implements dim = 2 only; other values return LS_E_INVALID. The
+ *    3D operator has a handle of its own (ls_op3, below).
  */
 #ifndef LSWEEP_H
 #define LSWEEP_H
@@ -283,6 +284,41 @@ ls_status ls_profile_read(ls_handle* h, ls_kernel_time* out_host, int max, int* 
 ls_status ls_host_tables(int n, double omega, const double* m_host, int pml_width, int layer_thickness,
                          double pml_C, int freq_samples, double* alpha_host, double* beta_host,
                          double* gamma_host, double* aux_host, int* kmap_host, double* green_host);
+
+/*
+ * The 3D operator (Sec. 1, eq. LS with d = 3; Sec. 2.1, eq. LS_d_c): on the
+ * unit cube with n interior points per axis, h = 1/(n+1),
+ *     k_delta = G(|delta| h) h^3,  G(r) = exp(i omega r) / (4 pi r),
+ * and k_0 the integral of G over the ball of volume h^3 in closed form:
+ *     a = h (3/(4 pi))^(1/3),  k_0 = (exp(i omega a)(1 - i omega a) - 1) / omega^2.
+ * A 3D handle holds the Green's spectrum and the medium and applies A and K
+ * by a zero-padded FFT convolution of length P = fft_len(n) >= 2n per axis;
+ * the sweeping preconditioner is not offered in 3D.
+ *
+ * ls_op3_create: m_dev is float64 [n][n][n] (i3 fastest, finite, < 1
+ *   everywhere), copied. hip_stream: hipStream_t for every later call (NULL:
+ *   default stream). 1 <= n <= 1023. Device memory: the spectrum octant
+ *   (P/2+1)^3 in both precisions, plus, during creation only, P^3 complex128.
+ * ls_op3_apply_A: y = x + omega^2 K (m .* x); ls_op3_apply_K: y = K x.
+ *   x_dev, y_dev: [nrhs][n][n][n] complex (complex128 for LS_FP64, complex64
+ *   for LS_MIXED), caller-owned, must not overlap. The first call with a
+ *   larger nrhs grows the handle's work arrays to
+ *   nrhs (n P^2 + n^2 P) complex128 entries.
+ * Errors: LS_E_INVALID for bad arguments (the handle is left unchanged),
+ *   LS_E_NOMEM when an allocation fails, LS_E_DEVICE when a HIP call fails.
+ */
+typedef struct ls_op3 ls_op3;
+ls_status ls_op3_create(int n, double omega, const double* m_dev, void* hip_stream, ls_op3** out);
+ls_status ls_op3_apply_A(ls_op3* h, const void* x_dev, int nrhs, void* y_dev, int precision);
+ls_status ls_op3_apply_K(ls_op3* h, const void* x_dev, int nrhs, void* y_dev, int precision);
+void ls_op3_destroy(ls_op3* h);
+
+/*
+ * Host-only: the 3D Green's table of ls_op3_create, k_delta for delta in
+ * [0, n+1]^3 (k is even in each axis), written to green_host as
+ * (n+2)^3 complex float64 interleaved, delta3 fastest.
+ */
+ls_status ls_host_green3(int n, double omega, double* green_host);
 
 #ifdef __cplusplus
 }

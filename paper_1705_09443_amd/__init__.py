@@ -25,7 +25,8 @@ from . import _lib
 from ._lib import (LS_FP64, LS_MIXED, LS_RHS_INCIDENT, LS_RHS_SOURCE, LsError, LsGrid, LsOptions,
                    LsRhsInfo, LsSetupInfo)
 
-__all__ = ["LSSolver", "LSSolve", "RhsInfo", "LsError", "host_tables", "layer_candidates"]
+__all__ = ["LSSolver", "LSSolve", "LSOperator3", "RhsInfo", "LsError", "host_tables", "host_green3",
+           "layer_candidates"]
 
 _PRECISIONS = {"fp64": LS_FP64, "mixed": LS_MIXED}
 
@@ -239,6 +240,56 @@ class LSSolver:
         km = np.zeros((self.L, self.L), dtype=np.int32)
         _lib.check(self._lib.ls_get_sample_map(self._h, km.ctypes.data), "ls_get_sample_map")
         return km
+
+
+class LSOperator3:
+    """The 3D operator A = I + omega^2 K M on [n]^3 (Sec. 1 and Sec. 2.1 with
+    d = 3) applied by a zero-padded FFT convolution on the device."""
+
+    def __init__(self, m: torch.Tensor, omega: float):
+        self._lib = _lib.load()
+        if m.dim() != 3 or not (m.shape[0] == m.shape[1] == m.shape[2]):
+            raise ValueError("m must be [n, n, n]")
+        self.n = int(m.shape[0])
+        self.omega = float(omega)
+        m = _need(m, torch.float64, (self.n,) * 3, "m")
+        handle = _lib.c_void_p()
+        _lib.check(self._lib.ls_op3_create(self.n, self.omega, m.data_ptr(), _stream_ptr(), ctypes_byref(handle)),
+                   "ls_op3_create")
+        self._h = handle
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.ls_op3_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _apply(self, fn, name, x, precision):
+        dt, code = (torch.complex128, LS_FP64) if precision == "fp64" else (torch.complex64, LS_MIXED)
+        k = x.shape[0]
+        x = _need(x, dt, (k, self.n, self.n, self.n), name)
+        y = torch.empty_like(x)
+        _lib.check(fn(self._h, x.data_ptr(), k, y.data_ptr(), code), name)
+        return y
+
+    def apply_A(self, x, precision="fp64"):
+        return self._apply(self._lib.ls_op3_apply_A, "ls_op3_apply_A", x, precision)
+
+    def apply_K(self, x, precision="fp64"):
+        return self._apply(self._lib.ls_op3_apply_K, "ls_op3_apply_K", x, precision)
+
+
+def host_green3(n: int, omega: float):
+    """The 3D Green's table octant k_delta, delta in [0, n+1]^3 (host only)."""
+    import numpy as np
+    g = np.zeros((n + 2) ** 3 * 2)
+    _lib.check(_lib.load().ls_host_green3(int(n), float(omega), g.ctypes.data), "ls_host_green3")
+    return g.view(np.complex128).reshape(n + 2, n + 2, n + 2)
 
 
 def ctypes_byref(x):

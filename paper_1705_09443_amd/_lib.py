@@ -94,6 +94,11 @@ _SIGNATURES = {
     "ls_set_kernels": (c_int, [c_void_p, c_int, c_int, c_int]),
     "ls_host_tables": (c_int, [c_int, c_double, c_void_p, c_int, c_int, c_double, c_int, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ls_op3_create": (c_int, [c_int, c_double, c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),
+    "ls_op3_apply_A": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),
+    "ls_op3_apply_K": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),
+    "ls_op3_destroy": (None, [c_void_p]),
+    "ls_host_green3": (c_int, [c_int, c_double, c_void_p]),
 }
 
 _lib = None

@@ -223,6 +223,16 @@ struct ls_handle {
   }
 };
 
+// The 3D operator alone: Green's spectrum octant, medium and work arrays.
+struct ls_op3 {
+  int device = 0;
+  hipStream_t st = nullptr;
+  int n = 0, P = 0;
+  double omega = 0;
+  DBuf m, m32, khat, khat32, tw, tw32, w1, w2;
+  int cap = 0;  // right-hand sides the work arrays hold
+};
+
 namespace {
 
 enum KernelKind { kKSweep = 0, kKFft, kKQ, kKExtract, kKFactor, kKSlices, kKIface, kKSlicesLast, kKNumKinds };
@@ -1876,6 +1886,139 @@ ls_status ls_profile_read(ls_handle* h, ls_kernel_time* out, int max, int* count
   *count = c;
   return LS_OK;
 }
+
+ls_status ls_host_green3(int n, double omega, double* green_host) {
+  try {
+    set_error("");
+    if (n < 1 || n > 1023 || !(omega > 0.0) || !std::isfinite(omega) || !green_host) {
+      set_error("ls_host_green3: 1 <= n <= 1023, omega > 0, green_host not NULL");
+      return LS_E_INVALID;
+    }
+    const std::vector<cd> kq = green3_octant(n, omega);
+    for (size_t i = 0; i < kq.size(); ++i) {
+      green_host[2 * i] = kq[i].real();
+      green_host[2 * i + 1] = kq[i].imag();
+    }
+    return LS_OK;
+  } catch (const std::exception& ex) {
+    set_error(ex.what());
+    return LS_E_NOMEM;
+  }
+}
+
+ls_status ls_op3_create(int n, double omega, const double* m_dev, void* hip_stream, ls_op3** out) {
+  try {
+    set_error("");
+    if (!out) {
+      set_error("out must not be NULL");
+      return LS_E_INVALID;
+    }
+    *out = nullptr;
+    if (n < 1 || n > 1023 || !(omega > 0.0) || !std::isfinite(omega) || !m_dev) {
+      set_error("ls_op3_create: 1 <= n <= 1023, omega > 0, m_dev not NULL");
+      return LS_E_INVALID;
+    }
+    std::unique_ptr<ls_op3> h(new ls_op3());
+    LSW_HIP_TRY(hipGetDevice(&h->device));
+    h->st = static_cast<hipStream_t>(hip_stream);
+    h->n = n;
+    h->P = fft_len(n);
+    h->omega = omega;
+    const int P = h->P;
+    const size_t n3 = (size_t)n * n * n;
+    hipStream_t st = h->st;
+    std::vector<double> mh(n3);
+    LSW_HIP_TRY(hipMemcpy(mh.data(), m_dev, n3 * sizeof(double), hipMemcpyDeviceToHost));
+    for (double v : mh)
+      if (!std::isfinite(v) || v >= 1.0) {
+        set_error("m must be finite and < 1 everywhere");
+        return LS_E_INVALID;
+      }
+    std::vector<float> m32(n3);
+    for (size_t i = 0; i < n3; ++i) m32[i] = (float)mh[i];
+    LSW_ALLOC(h->m, n3 * sizeof(double));
+    LSW_ALLOC(h->m32, n3 * sizeof(float));
+    LSW_HIP_TRY(hipMemcpyAsync(h->m.p, m_dev, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+    LSW_HIP_TRY(hipMemcpyAsync(h->m32.p, m32.data(), n3 * sizeof(float), hipMemcpyHostToDevice, st));
+    std::vector<double2> tw(P);
+    std::vector<float2> tw32(P);
+    for (int k = 0; k < P; ++k) {
+      const double a = -2.0 * M_PI * (double)k / (double)P;
+      tw[k] = make_double2(std::cos(a), std::sin(a));
+      tw32[k] = make_float2((float)tw[k].x, (float)tw[k].y);
+    }
+    LSW_ALLOC(h->tw, P * sizeof(double2));
+    LSW_ALLOC(h->tw32, P * sizeof(float2));
+    LSW_HIP_TRY(hipMemcpyAsync(h->tw.p, tw.data(), P * sizeof(double2), hipMemcpyHostToDevice, st));
+    LSW_HIP_TRY(hipMemcpyAsync(h->tw32.p, tw32.data(), P * sizeof(float2), hipMemcpyHostToDevice, st));
+    {
+      const std::vector<cd> kq = green3_octant(n, omega);
+      std::vector<double2> kq_h(kq.size());
+      for (size_t i = 0; i < kq.size(); ++i) kq_h[i] = make_double2(kq[i].real(), kq[i].imag());
+      DBuf kqd, scratch;
+      LSW_ALLOC(kqd, kq_h.size() * sizeof(double2));
+      LSW_ALLOC(scratch, (size_t)P * P * P * sizeof(double2));
+      const size_t H = P / 2 + 1;
+      LSW_ALLOC(h->khat, H * H * H * sizeof(double2));
+      LSW_ALLOC(h->khat32, H * H * H * sizeof(float2));
+      LSW_HIP_TRY(hipMemcpyAsync(kqd.p, kq_h.data(), kq_h.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+      LSW_HIP_TRY(launch_green_spectrum3(kqd.as<double2>(), n, h->tw.as<double2>(), scratch.as<double2>(),
+                                         h->khat.as<double2>(), h->khat32.as<float2>(), st));
+      LSW_HIP_TRY(hipStreamSynchronize(st));
+    }
+    *out = h.release();
+    return LS_OK;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return LS_E_NOMEM;
+  } catch (const std::exception& ex) {
+    set_error(ex.what());
+    return LS_E_INVALID;
+  }
+}
+
+namespace {
+// y = a x + c K (s .* x) for the 3D operator; s = m (with_m) or 1
+ls_status op3_apply(ls_op3* h, const void* x, int nrhs, void* y, int precision, bool with_m, double a, double c) {
+  if (!h) {
+    set_error("null handle");
+    return LS_E_INVALID;
+  }
+  if (nrhs < 1 || !x || !y || (precision != LS_FP64 && precision != LS_MIXED)) {
+    set_error("ls_op3_apply: nrhs >= 1, non-null arrays, precision LS_FP64 or LS_MIXED");
+    return LS_E_INVALID;
+  }
+  if (nrhs > h->cap) {
+    // sized for complex128 so that either precision fits; a failed growth
+    // may have released the old arrays, so the handle then holds none
+    h->cap = 0;
+    LSW_ALLOC(h->w1, (size_t)nrhs * fft3_w1_elems(h->n) * sizeof(double2));
+    LSW_ALLOC(h->w2, (size_t)nrhs * fft3_w2_elems(h->n) * sizeof(double2));
+    h->cap = nrhs;
+  }
+  if (precision == LS_FP64) {
+    LSW_HIP_TRY(launch_convolve3<double>(static_cast<const double2*>(x), with_m ? h->m.as<double>() : nullptr, h->n,
+                                         nrhs, h->khat.as<double2>(), h->tw.as<double2>(), a, c, h->w1.as<double2>(),
+                                         h->w2.as<double2>(), static_cast<double2*>(y), h->st));
+  } else {
+    LSW_HIP_TRY(launch_convolve3<float>(static_cast<const float2*>(x), with_m ? h->m32.as<float>() : nullptr, h->n,
+                                        nrhs, h->khat32.as<float2>(), h->tw32.as<float2>(), (float)a, (float)c,
+                                        h->w1.as<float2>(), h->w2.as<float2>(), static_cast<float2*>(y), h->st));
+  }
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  return LS_OK;
+}
+}  // namespace
+
+ls_status ls_op3_apply_A(ls_op3* h, const void* x_dev, int nrhs, void* y_dev, int precision) {
+  return op3_apply(h, x_dev, nrhs, y_dev, precision, true, 1.0, h ? h->omega * h->omega : 0.0);
+}
+
+ls_status ls_op3_apply_K(ls_op3* h, const void* x_dev, int nrhs, void* y_dev, int precision) {
+  return op3_apply(h, x_dev, nrhs, y_dev, precision, false, 0.0, 1.0);
+}
+
+void ls_op3_destroy(ls_op3* h) { delete h; }
 
 ls_status ls_host_tables(int n, double omega, const double* m_host, int pml_width, int layer_thickness,
                          double pml_C, int freq_samples, double* alpha, double* beta, double* gamma, double* aux,

@@ -408,6 +408,181 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_cols_full(double2* __res
   }
 }
 
+// ---- 3D convolution: five passes of length-P transforms -------------------
+// Every pass loads S sequences into LDS as buf[t * S + s] (element t of
+// sequence s), transforms them with lds_fft and stores them back. Pass 1 and
+// 5 take S rows (contiguous); passes 2-4 take S consecutive k3 (contiguous in
+// memory) of sequences along axis 2 or 1, so every global access moves S
+// consecutive values.
+//   x  [n][n][n] --1--> w1 [n][n][P] --2--> w2 [n][P][P] --3 (axis 1, khat,
+//   inverse)--> w2 --4 (inverse axis 2)--> w1 --5 (inverse axis 3)--> y
+
+// pass 1: S rows rho = i1 n + i2 of (s .* x), zero-padded to P, transformed
+template <typename T, bool HASM>
+__global__ __launch_bounds__(kFftMaxThreads) void k3_rows_fwd(const C<T>* __restrict__ x, const T* __restrict__ m,
+                                                              int n, int P, int S, const C<T>* __restrict__ tw,
+                                                              C<T>* __restrict__ w1) {
+  constexpr int V = kVals<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+  C<T>* twl = buf + S * P;
+  load_twiddles<T>(twl, tw, P);
+  const int rhs = blockIdx.y, r0 = blockIdx.x * S, rows = n * n;
+  const size_t n3 = (size_t)rows * n;
+  const C<T>* xr = x + rhs * n3;
+  C<T> v[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    const int sq = idx / P, k = idx % P, row = r0 + sq;
+    const bool ok = idx < S * P && k < n && row < rows;
+    const size_t o = (size_t)(row < rows ? row : rows - 1) * n + (k < n ? k : n - 1);
+    C<T> w = xr[o];
+    if (HASM) w = cscale<T>(w, m[o]);
+    v[q] = ok ? w : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < S * P) buf[(idx % P) * S + idx / P] = v[q];
+  }
+  __syncthreads();
+  lds_fft<T>(buf, P, S, twl, false);
+  C<T>* out = w1 + (size_t)rhs * rows * P;
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    const int sq = idx / P, k = idx % P, row = r0 + sq;
+    if (idx < S * P && row < rows) out[(size_t)row * P + k] = buf[k * S + sq];
+  }
+}
+
+// Where element t of sequence s of a workgroup lives: base + rhs * rhs_stride
+// + blockIdx.y * oth + (blockIdx.x * S + s) * sst + t * st.
+struct Seq3 {
+  size_t st, sst, oth, rhs;
+};
+
+// passes 2-4: S sequences of nin inputs (the rest zero); MODE 0 forward, 1
+// forward, times khat, inverse (axis 1), 2 inverse; nout outputs stored
+// through out. blockIdx.x: chunk of S sequences, blockIdx.y: the other index
+// (i1 for axis 2, k2 for axis 1), blockIdx.z: right-hand side.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kFftMaxThreads) void k3_axis(const C<T>* __restrict__ src, C<T>* __restrict__ dst,
+                                                          const C<T>* __restrict__ khat, int P, int S, int nin,
+                                                          int nout, Seq3 si, Seq3 so, const C<T>* __restrict__ tw) {
+  constexpr int V = kVals<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+  C<T>* twl = buf + S * P;
+  load_twiddles<T>(twl, tw, P);
+  const int c0 = blockIdx.x * S, o = blockIdx.y, rhs = blockIdx.z;
+  const C<T>* in = src + rhs * si.rhs + (size_t)o * si.oth + (size_t)c0 * si.sst;
+  C<T> v[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    const int t = idx / S, sq = idx % S;
+    const bool ok = idx < S * P && t < nin;
+    const C<T> w = in[ok ? (size_t)t * si.st + (size_t)sq * si.sst : 0];
+    v[q] = ok ? w : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < S * P) buf[idx] = v[q];
+  }
+  __syncthreads();
+  lds_fft<T>(buf, P, S, twl, MODE == 2);
+  if (MODE == 1) {
+    // times khat(k1 = t, k2 = o, k3 = c0 + sq), the table even in every axis
+    const int H = P / 2 + 1;
+    const int k2 = o <= P - o ? o : P - o;
+#pragma unroll
+    for (int q = 0; q < V; ++q) {
+      const int idx = threadIdx.x + q * blockDim.x;
+      if (idx < S * P) {
+        const int t = idx / S, c = c0 + idx % S;
+        const int k1 = t <= P - t ? t : P - t, k3 = c <= P - c ? c : P - c;
+        buf[idx] = cmul<T>(buf[idx], khat[((size_t)k1 * H + k2) * H + k3]);
+      }
+    }
+    __syncthreads();
+    lds_fft<T>(buf, P, S, twl, true);
+  }
+  C<T>* out = dst + rhs * so.rhs + (size_t)o * so.oth + (size_t)c0 * so.sst;
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    const int t = idx / S, sq = idx % S;
+    if (idx < S * P && t < nout) out[(size_t)t * so.st + (size_t)sq * so.sst] = buf[idx];
+  }
+}
+
+// pass 5: S rows of w1, inverse transform, first n entries, epilogue
+template <typename T>
+__global__ __launch_bounds__(kFftMaxThreads) void k3_rows_inv(const C<T>* __restrict__ w1,
+                                                              const C<T>* __restrict__ x, int n, int P, int S,
+                                                              const C<T>* __restrict__ tw, T a, T coef,
+                                                              C<T>* __restrict__ y) {
+  constexpr int V = kVals<T>;
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+  C<T>* twl = buf + S * P;
+  load_twiddles<T>(twl, tw, P);
+  const int rhs = blockIdx.y, r0 = blockIdx.x * S, rows = n * n;
+  const C<T>* in = w1 + (size_t)rhs * rows * P;
+  C<T> v[V];
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    const int sq = idx / P, k = idx % P, row = r0 + sq;
+    const bool ok = idx < S * P && row < rows;
+    const C<T> w = in[(size_t)(ok ? row : 0) * P + k];
+    v[q] = ok ? w : mk<T>(0, 0);
+  }
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    if (idx < S * P) buf[(idx % P) * S + idx / P] = v[q];
+  }
+  __syncthreads();
+  lds_fft<T>(buf, P, S, twl, true);
+  const size_t n3 = (size_t)rows * n;
+#pragma unroll
+  for (int q = 0; q < V; ++q) {
+    const int idx = threadIdx.x + q * blockDim.x;
+    const int sq = idx / n, k = idx % n, row = r0 + sq;
+    if (idx < S * n && row < rows) {
+      const size_t o = rhs * n3 + (size_t)row * n + k;
+      const C<T> xv = a != T(0) ? x[o] : mk<T>(0, 0);
+      y[o] = cadd<T>(cscale<T>(buf[k * S + sq], coef), cscale<T>(xv, a));
+    }
+  }
+}
+
+// setup: the table octant wrapped to P^3 (zero beyond offset n+1)
+__global__ void k3_wrap_table(const double2* __restrict__ kq, int n, int P, double2* __restrict__ W) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)P * P * P) return;
+  const int q1 = (int)(idx / ((size_t)P * P)), q2 = (int)((idx / P) % P), q3 = (int)(idx % P);
+  const int d1 = q1 <= P / 2 ? q1 : P - q1, d2 = q2 <= P / 2 ? q2 : P - q2, d3 = q3 <= P / 2 ? q3 : P - q3;
+  const int Q = n + 2;
+  W[idx] = (d1 < Q && d2 < Q && d3 < Q) ? kq[((size_t)d1 * Q + d2) * Q + d3] : make_double2(0.0, 0.0);
+}
+
+// setup: the octant of the transformed P^3 array
+__global__ void k3_octant(const double2* __restrict__ W, int P, double2* __restrict__ khat,
+                          float2* __restrict__ khat32) {
+  const int H = P / 2 + 1;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)H * H * H) return;
+  const int a = (int)(idx / ((size_t)H * H)), b = (int)((idx / H) % H), c = (int)(idx % H);
+  const double2 v = W[((size_t)a * P + b) * P + c];
+  khat[idx] = v;
+  khat32[idx] = make_float2((float)v.x, (float)v.y);
+}
+
 template <typename T>
 int seq_per_block(int P) {
   int S = (163840 - P * (int)sizeof(C<T>)) / (P * (int)sizeof(C<T>));
@@ -480,6 +655,96 @@ hipError_t launch_green_spectrum(const double2* kq, int n, const double2* tw, do
   hipLaunchKernelGGL(k_wrap_table, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, kq, n, P, scratch);
   hipLaunchKernelGGL(k_fft_rows_full, dim3(P / S), dim3(nt), lds, st, scratch, P, S, tw);
   hipLaunchKernelGGL(k_fft_cols_full, dim3(P / S), dim3(nt), lds, st, scratch, P, S, tw, khat, khat32);
+  return hipGetLastError();
+}
+
+
+size_t fft3_w1_elems(int n) { return (size_t)n * n * fft_len(n); }
+size_t fft3_w2_elems(int n) {
+  const size_t P = fft_len(n);
+  return (size_t)n * P * P;
+}
+
+namespace {
+// sequences per workgroup of the 3D passes: at most 16, S * P <= kVals * 512
+template <typename T>
+int seq3(int P) {
+  int S = 16;
+  while (S > 1 && (S * P > kVals<T> * kFftMaxThreads || (size_t)(S + 1) * P * sizeof(C<T>) > 163840)) S >>= 1;
+  return S > P ? P : S;
+}
+}  // namespace
+
+template <typename T>
+hipError_t launch_convolve3(const C<T>* x, const T* m, int n, int nrhs, const C<T>* khat, const C<T>* tw, T a,
+                            T c, C<T>* w1, C<T>* w2, C<T>* y, hipStream_t st) {
+  const int P = fft_len(n);
+  const int S = seq3<T>(P);
+  const int nt = threads_for<T>(S, P);
+  const size_t lds = (size_t)(S + 1) * P * sizeof(C<T>);
+  hipError_t e;
+  if ((e = allow_lds(k3_rows_fwd<T, true>, lds)) != hipSuccess) return e;
+  if ((e = allow_lds(k3_rows_fwd<T, false>, lds)) != hipSuccess) return e;
+  if ((e = allow_lds(k3_axis<T, 0>, lds)) != hipSuccess) return e;
+  if ((e = allow_lds(k3_axis<T, 1>, lds)) != hipSuccess) return e;
+  if ((e = allow_lds(k3_axis<T, 2>, lds)) != hipSuccess) return e;
+  if ((e = allow_lds(k3_rows_inv<T>, lds)) != hipSuccess) return e;
+  const int rows = n * n;
+  const size_t PP = (size_t)P * P;
+  const size_t r1 = fft3_w1_elems(n), r2 = fft3_w2_elems(n);
+  const T coef = c / ((T)P * (T)P * (T)P);
+  const dim3 grow((rows + S - 1) / S, nrhs);
+  if (m)
+    hipLaunchKernelGGL((k3_rows_fwd<T, true>), grow, dim3(nt), lds, st, x, m, n, P, S, tw, w1);
+  else
+    hipLaunchKernelGGL((k3_rows_fwd<T, false>), grow, dim3(nt), lds, st, x, m, n, P, S, tw, w1);
+  // sequences: element t at stride st, S consecutive k3 (stride 1) per group
+  const Seq3 a1{(size_t)P, 1, (size_t)n * P, r1};  // w1 along i2, groups by i1
+  const Seq3 a2{(size_t)P, 1, PP, r2};             // w2 along k2, groups by i1
+  const Seq3 a3{PP, 1, (size_t)P, r2};             // w2 along i1, groups by k2
+  // axis 2: w1[i1][i2][k3] (i2 < n) -> w2[i1][k2][k3]
+  hipLaunchKernelGGL((k3_axis<T, 0>), dim3(P / S, n, nrhs), dim3(nt), lds, st, w1, w2, khat, P, S, n, P, a1, a2,
+                     tw);
+  // axis 1 with khat: w2[i1][k2][k3] (i1 < n), in place
+  hipLaunchKernelGGL((k3_axis<T, 1>), dim3(P / S, P, nrhs), dim3(nt), lds, st, w2, w2, khat, P, S, n, n, a3, a3,
+                     tw);
+  // inverse axis 2: w2[i1][k2][k3] -> w1[i1][i2][k3] (i2 < n)
+  hipLaunchKernelGGL((k3_axis<T, 2>), dim3(P / S, n, nrhs), dim3(nt), lds, st, w2, w1, khat, P, S, P, n, a2, a1,
+                     tw);
+  hipLaunchKernelGGL(k3_rows_inv<T>, grow, dim3(nt), lds, st, w1, x, n, P, S, tw, a, coef, y);
+  return hipGetLastError();
+}
+template hipError_t launch_convolve3<double>(const double2*, const double*, int, int, const double2*,
+                                             const double2*, double, double, double2*, double2*, double2*,
+                                             hipStream_t);
+template hipError_t launch_convolve3<float>(const float2*, const float*, int, int, const float2*, const float2*,
+                                            float, float, float2*, float2*, float2*, hipStream_t);
+
+hipError_t launch_green_spectrum3(const double2* kq, int n, const double2* tw, double2* scratch, double2* khat,
+                                  float2* khat32, hipStream_t st) {
+  const int P = fft_len(n);
+  const int S = seq3<double>(P);
+  const int nt = threads_for<double>(S, P);
+  const size_t lds = (size_t)(S + 1) * P * sizeof(double2);
+  hipError_t e;
+  if ((e = allow_lds(k3_axis<double, 0>, lds)) != hipSuccess) return e;
+  const size_t P3 = (size_t)P * P * P, PP = (size_t)P * P;
+  hipLaunchKernelGGL(k3_wrap_table, dim3((unsigned)((P3 + 255) / 256)), dim3(256), 0, st, kq, n, P, scratch);
+  // forward transforms along each axis in place, all P inputs and outputs:
+  // axis 3 (S rows as sequences: stride 1 within, P between rows), axis 2, axis 1
+  // axis 3: the P^2 rows (contiguous sequences, P apart) in groups of S rows
+  const Seq3 r3{1, (size_t)P, (size_t)S * P, 0};
+  hipLaunchKernelGGL((k3_axis<double, 0>), dim3(1, (unsigned)(PP / S), 1), dim3(nt), lds, st, scratch, scratch,
+                     (const double2*)nullptr, P, S, P, P, r3, r3, tw);
+  // axis 2 (groups by k1) and axis 1 (groups by k2), S consecutive k3 each
+  const Seq3 r2{(size_t)P, 1, PP, 0}, r1{PP, 1, (size_t)P, 0};
+  hipLaunchKernelGGL((k3_axis<double, 0>), dim3(P / S, P, 1), dim3(nt), lds, st, scratch, scratch,
+                     (const double2*)nullptr, P, S, P, P, r2, r2, tw);
+  hipLaunchKernelGGL((k3_axis<double, 0>), dim3(P / S, P, 1), dim3(nt), lds, st, scratch, scratch,
+                     (const double2*)nullptr, P, S, P, P, r1, r1, tw);
+  const int H = P / 2 + 1;
+  const size_t H3 = (size_t)H * H * H;
+  hipLaunchKernelGGL(k3_octant, dim3((unsigned)((H3 + 255) / 256)), dim3(256), 0, st, scratch, P, khat, khat32);
   return hipGetLastError();
 }
 

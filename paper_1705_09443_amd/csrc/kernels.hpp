@@ -22,6 +22,18 @@ hipError_t launch_convolve(const C<T>* x, const T* m, int n, int nrhs, const C<T
 hipError_t launch_green_spectrum(const double2* kq, int n, const double2* tw, double2* scratch,
                                  double2* khat, float2* khat32, hipStream_t st);
 
+// ---- 3D: the same convolution on [nrhs][n][n][n], P^3 zero padding ----
+// Work per right-hand side: w1 n^2 P and w2 n P^2 complex values.
+size_t fft3_w1_elems(int n);
+size_t fft3_w2_elems(int n);
+template <typename T>
+hipError_t launch_convolve3(const C<T>* x, const T* m, int n, int nrhs, const C<T>* khat, const C<T>* tw, T a,
+                            T c, C<T>* w1, C<T>* w2, C<T>* y, hipStream_t st);
+// khat (octant (P/2+1)^3, float64 and a float32 copy) from the table octant kq
+// [(n+2)]^3; scratch holds P^3 values.
+hipError_t launch_green_spectrum3(const double2* kq, int n, const double2* tw, double2* scratch, double2* khat,
+                                  float2* khat32, hipStream_t st);
+
 // ---- stencils, slices and sweep (sweep.hip) ----
 struct StencilTables {
   const double2* alpha;  // 9

@@ -336,6 +336,28 @@ void pml_gamma_2d(double kappa, double omega, double h, const double os[2][3], c
 
 }  // namespace
 
+std::vector<cd> green3_octant(int n, double omega) {
+  const int Q = n + 2;
+  const double h = 1.0 / (n + 1);
+  std::vector<cd> kq((size_t)Q * Q * Q);
+  parallel_for(Q, [&](int a) {
+    for (int c = 0; c < Q; ++c)
+      for (int e = 0; e < Q; ++e) {
+        cd val;
+        if (a == 0 && c == 0 && e == 0) {
+          const double rad = h * std::cbrt(3.0 / (4.0 * kPi));
+          const cd eia = std::exp(cd(0.0, omega * rad));
+          val = (eia * cd(1.0, -omega * rad) - 1.0) / (omega * omega);
+        } else {
+          const double r = std::sqrt((double)a * a + (double)c * c + (double)e * e) * h;
+          val = std::exp(cd(0.0, omega * r)) / (4.0 * kPi * r) * (h * h * h);
+        }
+        kq[((size_t)a * Q + c) * Q + e] = val;
+      }
+  });
+  return kq;
+}
+
 std::string build_host_setup(const double* m, int n, double omega, int b, int w, double C,
                              int freq_samples, HostSetup& S) {
   char buf[256];

@@ -42,6 +42,12 @@ void bessel_j1y1_small(double x, double* j1, double* y1);
 // Per-axis stretch class of grid index i (0 interior, 1..b low, b+1..2b high).
 int axis_class(int i, int n, int b);
 
+// 3D Green's table k_delta for delta in [0, n+1]^3, [(n+2)][(n+2)][(n+2)]:
+// G(r) = exp(i omega r) / (4 pi r) times h^3 off the origin (Sec. 1, eq.
+// LS_d), k_0 the integral of G over the ball of volume h^3 (reading G1):
+// (exp(i omega a)(1 - i omega a) - 1) / omega^2, a = h (3 / (4 pi))^(1/3).
+std::vector<cd> green3_octant(int n, double omega);
+
 // Build everything from m on the host. Returns "" on success, else a message.
 std::string build_host_setup(const double* m_host, int n, double omega, int b, int w, double C,
                              int freq_samples, HostSetup& out);

@@ -96,3 +96,32 @@ def test_invalid_inputs_raise():
     bad[3, 3] = np.nan
     with pytest.raises(LsError):
         host_tables(bad, 10.0, 4, 2)
+
+
+@pytest.mark.parametrize("n,ppw", [(1, 0.5), (15, 2.0), (31, 2.0)])
+def test_green3_octant(n, ppw):
+    """The library's 3D table (Sec. 1 Green's function, k_0 over the ball of
+    volume h^3) against the oracle's, 1e-14 of its largest entry and 1e-13
+    relative to the local size of G h^3 away from the centre."""
+    from paper_1705_09443_amd import host_green3
+    omega = 2.0 * math.pi * ppw
+    t = oracle.green_table(3, n, omega)[n + 1:, n + 1:, n + 1:]
+    got = host_green3(n, omega)
+    assert got.shape == (n + 2,) * 3
+    assert np.abs(got - t).max() <= 1e-14 * np.abs(t).max()
+    h = 1.0 / (n + 1)
+    r = np.sqrt(sum(g * g for g in np.meshgrid(*([np.arange(n + 2)] * 3), indexing="ij"))) * h
+    r[0, 0, 0] = 1.0
+    scale = h ** 3 / (4 * math.pi * r)
+    err = np.abs(got - t) / scale
+    err[0, 0, 0] = 0.0
+    assert err.max() < 1e-13
+
+
+def test_green3_rejects_bad_arguments():
+    from paper_1705_09443_amd import _lib
+    lib = _lib.load()
+    buf = np.zeros(2 * 27)
+    for n, om in [(0, 1.0), (1024, 1.0), (1, 0.0), (1, float("nan"))]:
+        assert lib.ls_host_green3(n, om, buf.ctypes.data) == _lib.LS_E_INVALID
+    assert lib.ls_host_green3(1, 1.0, None) == _lib.LS_E_INVALID
