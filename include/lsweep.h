@@ -286,6 +286,22 @@ ls_status ls_host_tables(int n, double omega, const double* m_host, int pml_widt
                          double* gamma_host, double* aux_host, int* kmap_host, double* green_host);
 
 /*
+ * Host-only: the float64 setup tables of the 3D method (Sec. 3.1: the
+ * neighbourhood mu = {-1,0,1}^3, lexicographic with axis 0 slowest, and PML
+ * stencils that annihilate the 26 neighbour directions), m_host [n][n][n]:
+ *   alpha_host, beta_host  27 complex
+ *   gamma_host  (2b+1)^3 x 27 complex, by per-axis class (c1, c2, c3)
+ *   aux_host    b x (2b+1) x (2b+1) x ns x 27 complex, by (depth q, c2, c3,
+ *               sample); entries no auxiliary point uses are zero
+ *   kmap_host   L^3 int, the sample index of every extended point
+ * Classes, samples and slabs as in 2D; a slab may have at most 32 lines.
+ * Any output pointer may be NULL.
+ */
+ls_status ls_host_tables3(int n, double omega, const double* m_host, int pml_width, int layer_thickness,
+                          double pml_C, int freq_samples, double* alpha_host, double* beta_host,
+                          double* gamma_host, double* aux_host, int* kmap_host);
+
+/*
  * The 3D operator (Sec. 1, eq. LS with d = 3; Sec. 2.1, eq. LS_d_c): on the
  * unit cube with n interior points per axis, h = 1/(n+1),
  *     k_delta = G(|delta| h) h^3,  G(r) = exp(i omega r) / (4 pi r),

@@ -26,7 +26,7 @@ from ._lib import (LS_FP64, LS_MIXED, LS_RHS_INCIDENT, LS_RHS_SOURCE, LsError, L
                    LsRhsInfo, LsSetupInfo)
 
 __all__ = ["LSSolver", "LSSolve", "LSOperator3", "RhsInfo", "LsError", "host_tables", "host_green3",
-           "layer_candidates"]
+           "host_tables3", "layer_candidates"]
 
 _PRECISIONS = {"fp64": LS_FP64, "mixed": LS_MIXED}
 
@@ -72,12 +72,13 @@ class LSSolver:
         plane waves on the device; autotune = k > 0 also tunes the kernel choice per
         batch size up to k (ls_setup, Autotuning)."""
         self._lib = _lib.load()
-        if m.dim() != 2 or m.shape[0] != m.shape[1]:
-            raise ValueError("m must be [n, n]")
+        if m.dim() not in (2, 3) or len(set(m.shape)) != 1:
+            raise ValueError("m must be [n, n] or [n, n, n]")
+        self.dim = m.dim()
         self.n = int(m.shape[0])
         self.omega = float(omega)
         self.precision = precision
-        m = _need(m, torch.float64, (self.n, self.n), "m")
+        m = _need(m, torch.float64, (self.n,) * self.dim, "m")
         opts = LsOptions()
         self._lib.ls_default_options(ctypes_byref(opts))
         opts.precision = _PRECISIONS[precision]
@@ -89,7 +90,7 @@ class LSSolver:
         opts.autotune = int(autotune)
         opts.hip_stream = _stream_ptr()
         self._opts = opts
-        grid = LsGrid(2, self.n)
+        grid = LsGrid(self.dim, self.n)
         handle = _lib.c_void_p()
         _lib.check(self._lib.ls_setup(ctypes_byref(grid), self.omega, m.data_ptr(), pml_width,
                                       0 if layer_thickness is None else int(layer_thickness),
@@ -130,7 +131,7 @@ class LSSolver:
         """Scattered fields u for a batch [k][n][n] (complex128) of incident
         waves (kind="incident") or right-hand sides g (kind="source")."""
         k = rhs.shape[0]
-        rhs = _need(rhs, torch.complex128, (k, self.n, self.n), "rhs")
+        rhs = _need(rhs, torch.complex128, (k,) + self.grid_shape, "rhs")
         u = torch.empty_like(rhs)
         infos = (LsRhsInfo * k)()
         st = self._lib.ls_solve(self._h, rhs.data_ptr(), k, LS_RHS_INCIDENT if kind == "incident" else LS_RHS_SOURCE,
@@ -142,8 +143,8 @@ class LSSolver:
     def adjoint(self, resid: torch.Tensor, tol: float = 1e-10):
         """dJ/dm for residuals r_j = R^T (R u_j - d_j) of the last solve."""
         k = resid.shape[0]
-        resid = _need(resid, torch.complex128, (k, self.n, self.n), "resid")
-        grad = torch.empty((self.n, self.n), dtype=torch.float64, device=resid.device)
+        resid = _need(resid, torch.complex128, (k,) + self.grid_shape, "resid")
+        grad = torch.empty(self.grid_shape, dtype=torch.float64, device=resid.device)
         infos = (LsRhsInfo * k)()
         _lib.check(self._lib.ls_adjoint(self._h, resid.data_ptr(), k, float(tol), grad.data_ptr(), infos),
                    "ls_adjoint")
@@ -158,20 +159,28 @@ class LSSolver:
         _lib.check(fn(self._h, x.data_ptr(), k, y.data_ptr(), code), name)
         return y
 
+    @property
+    def grid_shape(self):
+        return (self.n,) * self.dim
+
+    @property
+    def ext_shape(self):
+        return (self.L,) * self.dim
+
     def apply_A(self, x, precision=None):
-        return self._unary(self._lib.ls_apply_A, "ls_apply_A", x, lambda k: (k, self.n, self.n), precision)
+        return self._unary(self._lib.ls_apply_A, "ls_apply_A", x, lambda k: (k,) + self.grid_shape, precision)
 
     def apply_K(self, x, precision=None):
-        return self._unary(self._lib.ls_apply_K, "ls_apply_K", x, lambda k: (k, self.n, self.n), precision)
+        return self._unary(self._lib.ls_apply_K, "ls_apply_K", x, lambda k: (k,) + self.grid_shape, precision)
 
     def apply_Q(self, r, precision=None):
-        return self._unary(self._lib.ls_apply_Q, "ls_apply_Q", r, lambda k: (k, self.L, self.L), precision)
+        return self._unary(self._lib.ls_apply_Q, "ls_apply_Q", r, lambda k: (k,) + self.ext_shape, precision)
 
     def apply_H(self, u, precision=None):
-        return self._unary(self._lib.ls_apply_H, "ls_apply_H", u, lambda k: (k, self.L, self.L), precision)
+        return self._unary(self._lib.ls_apply_H, "ls_apply_H", u, lambda k: (k,) + self.ext_shape, precision)
 
     def apply_precond(self, r, precision=None):
-        return self._unary(self._lib.ls_apply_precond, "ls_apply_precond", r, lambda k: (k, self.n, self.n),
+        return self._unary(self._lib.ls_apply_precond, "ls_apply_precond", r, lambda k: (k,) + self.grid_shape,
                            precision)
 
     def slice_bounds(self, k: int):
@@ -184,7 +193,7 @@ class LSSolver:
         dt, code = self._cdtype(precision)
         lo, hi, _ = self.slice_bounds(k)
         nb = v.shape[0]
-        v = _need(v, dt, (nb, hi - lo + 1, self.L), "v")
+        v = _need(v, dt, (nb, hi - lo + 1) + (self.L,) * (self.dim - 1), "v")
         w = torch.empty_like(v)
         _lib.check(self._lib.ls_slice_solve(self._h, k, v.data_ptr(), nb, w.data_ptr(), code), "ls_slice_solve")
         return w
@@ -224,20 +233,22 @@ class LSSolver:
     # -- setup tables -------------------------------------------------------
     def stencils(self):
         import numpy as np
-        b, ns = self.pml_width, self.info.freq_samples
+        b, ns, d = self.pml_width, self.info.freq_samples, self.dim
         nc = 2 * b + 1
-        a = np.zeros(18)
-        be = np.zeros(18)
-        g = np.zeros(nc * nc * 9 * 2)
-        ax = np.zeros(b * nc * ns * 9 * 2)
+        mu = 3 ** d
+        a = np.zeros(2 * mu)
+        be = np.zeros(2 * mu)
+        g = np.zeros(nc ** d * mu * 2)
+        ax = np.zeros(b * nc ** (d - 1) * ns * mu * 2)
         _lib.check(self._lib.ls_get_stencils(self._h, a.ctypes.data, be.ctypes.data, g.ctypes.data, ax.ctypes.data),
                    "ls_get_stencils")
         c = lambda v: v.view(np.complex128)
-        return c(a), c(be), c(g).reshape(nc, nc, 9), c(ax).reshape(b, nc, ns, 9)
+        return (c(a), c(be), c(g).reshape((nc,) * d + (mu,)),
+                c(ax).reshape((b,) + (nc,) * (d - 1) + (ns, mu)))
 
     def sample_map(self):
         import numpy as np
-        km = np.zeros((self.L, self.L), dtype=np.int32)
+        km = np.zeros(self.ext_shape, dtype=np.int32)
         _lib.check(self._lib.ls_get_sample_map(self._h, km.ctypes.data), "ls_get_sample_map")
         return km
 
@@ -324,6 +335,33 @@ def host_tables(m, omega: float, pml_width: int, layer_thickness: int, pml_C: fl
     c = lambda v: v.view(np.complex128)
     return dict(alpha=c(a), beta=c(be), gamma=c(g).reshape(nc, nc, 9), aux=c(ax).reshape(b, nc, ns, 9),
                 kmap=km, green=c(gr).reshape(n + 2, n + 2))
+
+
+def host_tables3(m, omega: float, pml_width: int, layer_thickness: int, pml_C: float = 10.0,
+                 freq_samples: int = 0):
+    """The library's float64 3D setup tables computed on the host (no GPU):
+    alpha, beta [27], gamma [(2b+1)^3][27], aux [b][(2b+1)^2][ns][27], kmap [L]^3."""
+    import numpy as np
+    lib = _lib.load()
+    m = np.ascontiguousarray(m, dtype=np.float64)
+    n = m.shape[0]
+    b = pml_width
+    nc = 2 * b + 1
+    L = n + 2 + 2 * b
+    ns = freq_samples if freq_samples > 0 else n
+    if m.max() == m.min():
+        ns = 1
+    a = np.zeros(54)
+    be = np.zeros(54)
+    g = np.zeros(nc ** 3 * 54)
+    ax = np.zeros(b * nc * nc * ns * 54)
+    km = np.zeros((L, L, L), dtype=np.int32)
+    _lib.check(lib.ls_host_tables3(n, float(omega), m.ctypes.data, b, layer_thickness, float(pml_C), freq_samples,
+                                   a.ctypes.data, be.ctypes.data, g.ctypes.data, ax.ctypes.data, km.ctypes.data),
+               "ls_host_tables3")
+    c = lambda v: v.view(np.complex128)
+    return dict(alpha=c(a), beta=c(be), gamma=c(g).reshape(nc, nc, nc, 27),
+                aux=c(ax).reshape(b, nc, nc, ns, 27), kmap=km)
 
 
 class LSSolve(torch.autograd.Function):

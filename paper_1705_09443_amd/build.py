@@ -18,7 +18,7 @@ BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblsweep.so")
 INCLUDE = os.path.join(os.path.dirname(HERE), "include")
 
-HIP_SOURCES = ["api.hip", "fft.hip", "sweep.hip", "interface.hip", "slice_mfma.hip", "krylov.hip"]
+HIP_SOURCES = ["api.hip", "fft.hip", "sweep.hip", "interface.hip", "slice_mfma.hip", "krylov.hip", "slab3.hip"]
 HOST_SOURCES = ["setup_host.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

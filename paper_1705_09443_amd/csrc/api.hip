@@ -34,6 +34,18 @@ struct DBuf {
   DBuf() = default;
   DBuf(const DBuf&) = delete;
   DBuf& operator=(const DBuf&) = delete;
+  DBuf(DBuf&& o) noexcept : p(o.p), bytes(o.bytes) {
+    o.p = nullptr;
+    o.bytes = 0;
+  }
+  DBuf& operator=(DBuf&& o) noexcept {
+    if (this != &o) {
+      release();
+      std::swap(p, o.p);
+      std::swap(bytes, o.bytes);
+    }
+    return *this;
+  }
   ~DBuf() { release(); }
   void release() {
     if (p) (void)hipFree(p);
@@ -124,14 +136,29 @@ struct KernelChoice {
 };
 // batch sizes with an entry of their own; larger batches follow the last
 constexpr int kChoiceMax = 256;
+// lines of a 3D slab subproblem at most (its dense blocks have t L rows)
+constexpr int kSlab3MaxLines = 32;
 
 }  // namespace
 }  // namespace lsw
 
 using namespace lsw;
 
+// 3D state of a handle (grid dim 3): host tables, the Green's spectrum
+// octant, the stencil tables, and per slab the factors S_j^{-1}, the
+// apply-time block coefficients and the couplings to the neighbouring slabs.
+struct Sweep3 {
+  HostSetup3 H;
+  std::vector<Slab3> slabs;
+  int maxnb = 0;
+  DBuf alpha, beta, gglob, gaux, kmap, khat, khat32, w1, w2, Y, z;
+  std::vector<DBuf> F, cbc, cm, cp;
+};
+
 struct ls_handle {
   int device = 0;
+  int dim = 2;
+  std::unique_ptr<Sweep3> s3;
   hipStream_t st = nullptr;
   ls_options opt{};
   HostSetup H;
@@ -279,6 +306,7 @@ struct Prec<double> {
   static const double2* tw(const ls_handle* h) { return h->tw.as<double2>(); }
   static const double* m(const ls_handle* h) { return h->m.as<double>(); }
   static double2* fftw(ls_handle* h) { return h->fftw64.as<double2>(); }
+  static const double2* khat3(const ls_handle* h) { return h->s3->khat.as<double2>(); }
 };
 template <>
 struct Prec<float> {
@@ -286,6 +314,7 @@ struct Prec<float> {
   static const float2* tw(const ls_handle* h) { return h->tw32.as<float2>(); }
   static const float* m(const ls_handle* h) { return h->m32.as<float>(); }
   static float2* fftw(ls_handle* h) { return h->fftw32.as<float2>(); }
+  static const float2* khat3(const ls_handle* h) { return h->s3->khat32.as<float2>(); }
 };
 
 ls_status check_handle(const ls_handle* h) {
@@ -332,19 +361,30 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   const size_t N = h->N, E = h->E;
   const int rs = h->opt.restart;
   const size_t cs = h->prec == LS_FP64 ? sizeof(double2) : sizeof(float2);
-  LSW_ALLOC(h->fftw64, fft_work_elems<double>(h->n, nrhs) * sizeof(double2));
-  LSW_ALLOC(h->fftw32, fft_work_elems<float>(h->n, nrhs) * sizeof(float2));
-  LSW_ALLOC(h->fext, (size_t)nrhs * E * cs);
-  LSW_ALLOC(h->uext, (size_t)nrhs * E * cs);
-  LSW_ALLOC(h->yscr, (size_t)nrhs * h->L * 32 * cs);
-  // interface vectors: rows padded to whole 16-blocks; the padding stays zero
-  const size_t vbytes = (size_t)h->nslices * nrhs * iface_vec_stride(h->L) * cs;
-  LSW_ALLOC(h->lam, vbytes);
-  LSW_ALLOC(h->mu, vbytes);
-  LSW_HIP_TRY(hipMemsetAsync(h->lam.p, 0, vbytes, h->st));
-  LSW_HIP_TRY(hipMemsetAsync(h->mu.p, 0, vbytes, h->st));
-  // slice-solve scratch: groups of up to 8 waves, one per right-hand side
-  LSW_ALLOC(h->sscr, (size_t)h->nslices * std::max(4, nrhs + 7) * slice_scratch_elems<double>(h->L, 1) * cs);
+  if (h->dim == 3) {
+    Sweep3& s3 = *h->s3;
+    // FFT work sized for complex128 so that both precisions fit
+    LSW_ALLOC(s3.w1, (size_t)nrhs * fft3_w1_elems(h->n) * sizeof(double2));
+    LSW_ALLOC(s3.w2, (size_t)nrhs * fft3_w2_elems(h->n) * sizeof(double2));
+    LSW_ALLOC(h->fext, (size_t)nrhs * E * cs);
+    LSW_ALLOC(h->uext, (size_t)nrhs * E * cs);
+    LSW_ALLOC(s3.Y, (size_t)nrhs * h->L * s3.maxnb * cs);
+    LSW_ALLOC(s3.z, (size_t)nrhs * s3.maxnb * cs);
+  } else {
+    LSW_ALLOC(h->fftw64, fft_work_elems<double>(h->n, nrhs) * sizeof(double2));
+    LSW_ALLOC(h->fftw32, fft_work_elems<float>(h->n, nrhs) * sizeof(float2));
+    LSW_ALLOC(h->fext, (size_t)nrhs * E * cs);
+    LSW_ALLOC(h->uext, (size_t)nrhs * E * cs);
+    LSW_ALLOC(h->yscr, (size_t)nrhs * h->L * 32 * cs);
+    // interface vectors: rows padded to whole 16-blocks; the padding stays zero
+    const size_t vbytes = (size_t)h->nslices * nrhs * iface_vec_stride(h->L) * cs;
+    LSW_ALLOC(h->lam, vbytes);
+    LSW_ALLOC(h->mu, vbytes);
+    LSW_HIP_TRY(hipMemsetAsync(h->lam.p, 0, vbytes, h->st));
+    LSW_HIP_TRY(hipMemsetAsync(h->mu.p, 0, vbytes, h->st));
+    // slice-solve scratch: groups of up to 8 waves, one per right-hand side
+    LSW_ALLOC(h->sscr, (size_t)h->nslices * std::max(4, nrhs + 7) * slice_scratch_elems<double>(h->L, 1) * cs);
+  }
   LSW_ALLOC(h->vin, (size_t)nrhs * N * cs);
   LSW_ALLOC(h->zout, (size_t)nrhs * N * cs);
   LSW_ALLOC(h->aout, (size_t)nrhs * N * cs);
@@ -415,6 +455,11 @@ ls_status upload(const ls_handle* h, DBuf& dst, const std::vector<X>& src) {
 template <typename T>
 ls_status apply_A(ls_handle* h, const C<T>* x, int nb, C<T>* y) {
   Timed tm(h, kKFft, nb);
+  if (h->dim == 3) {
+    LSW_HIP_TRY(launch_convolve3<T>(x, Prec<T>::m(h), h->n, nb, Prec<T>::khat3(h), Prec<T>::tw(h), (T)1,
+                                    (T)(h->omega * h->omega), h->s3->w1.as<C<T>>(), h->s3->w2.as<C<T>>(), y, h->st));
+    return LS_OK;
+  }
   LSW_HIP_TRY(launch_convolve<T>(x, Prec<T>::m(h), h->n, nb, Prec<T>::khat(h), Prec<T>::tw(h), (T)1,
                                  (T)(h->omega * h->omega), Prec<T>::fftw(h), y, h->st));
   return LS_OK;
@@ -491,9 +536,95 @@ ls_status solve_slices(ls_handle* h, SliceSolveArgs<T> a, int k0, int k1, int ke
   return LS_OK;
 }
 
+Stencil3 stencil3(const ls_handle* h) {
+  const Sweep3& s = *h->s3;
+  Stencil3 S;
+  S.alpha = s.alpha.as<double2>();
+  S.beta = s.beta.as<double2>();
+  S.gglob = s.gglob.as<double2>();
+  S.gaux = s.gaux.as<double2>();
+  S.kmap = s.kmap.as<int>();
+  S.m = h->m.as<double>();
+  S.n = h->n;
+  S.b = h->b;
+  S.L = h->L;
+  S.ns = h->ns;
+  S.omega2 = h->omega * h->omega;
+  return S;
+}
+
+// Solve of slab k's subproblem for nb right-hand sides: factors and work
+// vectors filled in; source, couplings and destination left to the caller.
+template <typename T>
+Slab3Apply<T> slab3_args(ls_handle* h, int k, int nb) {
+  Sweep3& s = *h->s3;
+  Slab3Apply<T> a{};
+  a.p = s.slabs[k];
+  a.L = h->L;
+  a.nrhs = nb;
+  a.F = s.F[k].as<C<T>>();
+  a.cbc = s.cbc[k].as<C<T>>();
+  a.cm = s.cm[k].as<C<T>>();
+  a.cp = s.cp[k].as<C<T>>();
+  a.Y = s.Y.as<C<T>>();
+  a.z = s.z.as<C<T>>();
+  return a;
+}
+
+// z = P r in 3D (Algorithm 2 slab by slab): f = Q r, forward sweep
+// u_k = T_k (f_k - H_[k,k-1] u_{k-1}), backward sweep u_k -= T_k H_[k,k+1] u_{k+1},
+// z = u on I.
+template <typename T>
+ls_status apply_P3(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
+  const Stencil3 S = stencil3(h);
+  Sweep3& s = *h->s3;
+  const int L = h->L, b = h->b, nl = (int)s.slabs.size();
+  const size_t LL = (size_t)L * L, E = LL * L;
+  C<T>* f = h->fext.as<C<T>>();
+  C<T>* u = h->uext.as<C<T>>();
+  {
+    Timed tm(h, kKQ, nb);
+    LSW_HIP_TRY(launch3_apply_Q<T>(S, r, nb, f, h->st));
+  }
+  for (int k = 0; k < nl; ++k) {
+    Timed tm(h, kKSlices, nb);
+    const Slab3& p = s.slabs[k];
+    Slab3Apply<T> a = slab3_args<T>(h, k, nb);
+    a.src = f + (size_t)(p.lo + b) * LL;
+    a.src_rs = E;
+    if (k > 0) {
+      a.cu = u + (size_t)(p.lo - 1 + b) * LL;
+      a.cu_rs = E;
+      a.cmode = 1;
+    }
+    a.dst = u + (size_t)(p.lo + b) * LL;
+    a.dst_rs = E;
+    a.dop = 0;
+    LSW_HIP_TRY(launch3_slab_solve<T>(a, h->st));
+  }
+  for (int k = nl - 2; k >= 0; --k) {
+    Timed tm(h, kKSlices, nb);
+    const Slab3& p = s.slabs[k];
+    Slab3Apply<T> a = slab3_args<T>(h, k, nb);
+    a.cu = u + (size_t)(p.hi + 1 + b) * LL;
+    a.cu_rs = E;
+    a.cmode = 2;
+    a.dst = u + (size_t)(p.lo + b) * LL;
+    a.dst_rs = E;
+    a.dop = 1;
+    LSW_HIP_TRY(launch3_slab_solve<T>(a, h->st));
+  }
+  {
+    Timed tm(h, kKExtract, nb);
+    LSW_HIP_TRY(launch3_extract<T>(u, h->n, b, nb, z, h->st));
+  }
+  return LS_OK;
+}
+
 // z = P r (Algorithm 2), interface schedule or slice by slice.
 template <typename T>
 ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
+  if (h->dim == 3) return apply_P3<T>(h, r, nb, z);
   const StencilTables S = h->stencils();
   C<T>* f = h->fext.as<C<T>>();
   C<T>* u = h->uext.as<C<T>>();
@@ -1397,6 +1528,195 @@ ls_status tune_kernels(ls_handle* h, int kmax) {
   return LS_OK;
 }
 
+// y = a x + c K (s .* x) with s = m (with_m) or 1, on the handle's grid
+template <typename T>
+ls_status convolve_any(ls_handle* h, const C<T>* x, bool with_m, int nb, T a, T c, C<T>* y) {
+  const T* m = with_m ? Prec<T>::m(h) : nullptr;
+  if (h->dim == 3)
+    LSW_HIP_TRY(launch_convolve3<T>(x, m, h->n, nb, Prec<T>::khat3(h), Prec<T>::tw(h), a, c, h->s3->w1.as<C<T>>(),
+                                    h->s3->w2.as<C<T>>(), y, h->st));
+  else
+    LSW_HIP_TRY(launch_convolve<T>(x, m, h->n, nb, Prec<T>::khat(h), Prec<T>::tw(h), a, c, Prec<T>::fftw(h), y,
+                                   h->st));
+  return LS_OK;
+}
+
+// 3D setup on the device: medium, twiddles, Green's spectrum octant,
+// stencil tables, and the factors of every slab (all slabs at once).
+template <typename T>
+ls_status factor3(ls_handle* h) {
+  Sweep3& s = *h->s3;
+  const int L = h->L, nl = (int)s.slabs.size();
+  hipStream_t st = h->st;
+  const Stencil3 S = stencil3(h);
+  std::vector<DBuf> wS(nl), wW(nl), wSp(nl), wXr(nl), wcf(nl), wpiv(nl), wperm(nl);
+  std::vector<Slab3Work> works(nl);
+  s.F.resize(nl);
+  s.cbc.resize(nl);
+  s.cm.resize(nl);
+  s.cp.resize(nl);
+  std::vector<C<T>*> Fp(nl), cbp(nl), cmp(nl, nullptr), cpp(nl, nullptr);
+  for (int k = 0; k < nl; ++k) {
+    const size_t nb = s.slabs[k].nb, nb2 = nb * nb;
+    LSW_ALLOC(wS[k], nb2 * sizeof(double2));
+    LSW_ALLOC(wW[k], nb2 * sizeof(double2));
+    LSW_ALLOC(wSp[k], nb2 * sizeof(double2));
+    LSW_ALLOC(wXr[k], 32 * nb * sizeof(double2));
+    LSW_ALLOC(wcf[k], 27 * nb * sizeof(double2));
+    LSW_ALLOC(wpiv[k], nb * sizeof(int));
+    LSW_ALLOC(wperm[k], nb * sizeof(int));
+    works[k] = {wS[k].as<double2>(), wW[k].as<double2>(), wSp[k].as<double2>(), wXr[k].as<double2>(),
+                wcf[k].as<double2>(), wpiv[k].as<int>(), wperm[k].as<int>()};
+    LSW_ALLOC(s.F[k], (size_t)L * nb2 * sizeof(C<T>));
+    LSW_ALLOC(s.cbc[k], (size_t)L * 2 * nb * 9 * sizeof(C<T>));
+    Fp[k] = s.F[k].as<C<T>>();
+    cbp[k] = s.cbc[k].as<C<T>>();
+    if (k > 0) {
+      LSW_ALLOC(s.cm[k], (size_t)L * L * 9 * sizeof(C<T>));
+      cmp[k] = s.cm[k].as<C<T>>();
+    }
+    if (k < nl - 1) {
+      LSW_ALLOC(s.cp[k], (size_t)L * L * 9 * sizeof(C<T>));
+      cpp[k] = s.cp[k].as<C<T>>();
+    }
+  }
+  DBuf slabs_d, works_d, F_d, cb_d, cm_d, cp_d, status;
+  LSW_ALLOC(slabs_d, nl * sizeof(Slab3));
+  LSW_ALLOC(works_d, nl * sizeof(Slab3Work));
+  LSW_ALLOC(F_d, nl * sizeof(void*));
+  LSW_ALLOC(cb_d, nl * sizeof(void*));
+  LSW_ALLOC(cm_d, nl * sizeof(void*));
+  LSW_ALLOC(cp_d, nl * sizeof(void*));
+  LSW_ALLOC(status, sizeof(int));
+  if (upload(h, slabs_d, s.slabs) != LS_OK || upload(h, works_d, works) != LS_OK || upload(h, F_d, Fp) != LS_OK ||
+      upload(h, cb_d, cbp) != LS_OK || upload(h, cm_d, cmp) != LS_OK || upload(h, cp_d, cpp) != LS_OK)
+    return LS_E_DEVICE;
+  LSW_HIP_TRY(hipMemsetAsync(status.p, 0, sizeof(int), st));
+  LSW_HIP_TRY(launch3_factor<T>(S, slabs_d.as<Slab3>(), works_d.as<Slab3Work>(), nl, s.maxnb,
+                                F_d.as<C<T>* const>(), status.as<int>(), st));
+  LSW_HIP_TRY(launch3_apply_coefs<T>(S, slabs_d.as<Slab3>(), nl, s.maxnb, cb_d.as<C<T>* const>(),
+                                     cm_d.as<C<T>* const>(), cp_d.as<C<T>* const>(), st));
+  int bad = 0;
+  LSW_HIP_TRY(hipMemcpyAsync(&bad, status.p, sizeof(int), hipMemcpyDeviceToHost, st));
+  LSW_HIP_TRY(hipStreamSynchronize(st));
+  if (bad) {
+    set_error("zero pivot in the factorization of slab " + std::to_string(bad - 1));
+    return LS_E_SINGULAR;
+  }
+  return LS_OK;
+}
+
+ls_status device_setup3(ls_handle* h, const double* m_dev, const std::vector<double>& mh) {
+  Sweep3& s = *h->s3;
+  const HostSetup3& H3 = s.H;
+  const int n = h->n, P = h->P;
+  const size_t n3 = (size_t)n * n * n;
+  hipStream_t st = h->st;
+  LSW_ALLOC(h->m, n3 * sizeof(double));
+  LSW_HIP_TRY(hipMemcpyAsync(h->m.p, m_dev, n3 * sizeof(double), hipMemcpyDeviceToDevice, st));
+  std::vector<float> m32(n3);
+  for (size_t i = 0; i < n3; ++i) m32[i] = (float)mh[i];
+  LSW_ALLOC(h->m32, n3 * sizeof(float));
+  LSW_HIP_TRY(hipMemcpyAsync(h->m32.p, m32.data(), n3 * sizeof(float), hipMemcpyHostToDevice, st));
+  std::vector<double2> tw(P);
+  std::vector<float2> tw32(P);
+  for (int k = 0; k < P; ++k) {
+    const double a = -2.0 * M_PI * (double)k / (double)P;
+    tw[k] = make_double2(std::cos(a), std::sin(a));
+    tw32[k] = make_float2((float)tw[k].x, (float)tw[k].y);
+  }
+  LSW_ALLOC(h->tw, P * sizeof(double2));
+  LSW_ALLOC(h->tw32, P * sizeof(float2));
+  LSW_HIP_TRY(hipMemcpyAsync(h->tw.p, tw.data(), P * sizeof(double2), hipMemcpyHostToDevice, st));
+  LSW_HIP_TRY(hipMemcpyAsync(h->tw32.p, tw32.data(), P * sizeof(float2), hipMemcpyHostToDevice, st));
+  auto to_d2 = [](const cd* v, size_t count) {
+    std::vector<double2> o(count);
+    for (size_t i = 0; i < count; ++i) o[i] = make_double2(v[i].real(), v[i].imag());
+    return o;
+  };
+  {
+    DBuf kq, scratch;
+    const std::vector<double2> kq_h = to_d2(H3.kq.data(), H3.kq.size());
+    LSW_ALLOC(kq, kq_h.size() * sizeof(double2));
+    LSW_ALLOC(scratch, (size_t)P * P * P * sizeof(double2));
+    const size_t Hh = P / 2 + 1;
+    LSW_ALLOC(s.khat, Hh * Hh * Hh * sizeof(double2));
+    LSW_ALLOC(s.khat32, Hh * Hh * Hh * sizeof(float2));
+    LSW_HIP_TRY(hipMemcpyAsync(kq.p, kq_h.data(), kq_h.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+    LSW_HIP_TRY(launch_green_spectrum3(kq.as<double2>(), n, h->tw.as<double2>(), scratch.as<double2>(),
+                                       s.khat.as<double2>(), s.khat32.as<float2>(), st));
+    LSW_HIP_TRY(hipStreamSynchronize(st));
+  }
+  const std::vector<double2> al = to_d2(H3.alpha, 27), be = to_d2(H3.beta, 27),
+                             gg = to_d2(H3.gamma_glob.data(), H3.gamma_glob.size()),
+                             ga = to_d2(H3.gamma_aux.data(), H3.gamma_aux.size());
+  LSW_ALLOC(s.alpha, al.size() * sizeof(double2));
+  LSW_ALLOC(s.beta, be.size() * sizeof(double2));
+  LSW_ALLOC(s.gglob, gg.size() * sizeof(double2));
+  LSW_ALLOC(s.gaux, ga.size() * sizeof(double2));
+  LSW_ALLOC(s.kmap, H3.kmap.size() * sizeof(int));
+  if (upload(h, s.alpha, al) != LS_OK || upload(h, s.beta, be) != LS_OK || upload(h, s.gglob, gg) != LS_OK ||
+      upload(h, s.gaux, ga) != LS_OK || upload(h, s.kmap, H3.kmap) != LS_OK)
+    return LS_E_DEVICE;
+  return h->prec == LS_FP64 ? factor3<double>(h) : factor3<float>(h);
+}
+
+// ls_setup for grid dim 3 (options already checked)
+ls_status setup3_handle(const ls_grid* grid, double omega, const double* m_dev, int pml_width, int layer_thickness,
+                        const ls_options& o, ls_handle** out) {
+  const int n = grid->n;
+  if (n < 1 || n > 1023) {
+    set_error("3D: n must be in [1, 1023]");
+    return LS_E_INVALID;
+  }
+  if (layer_thickness < 1) {
+    set_error("3D: layer_thickness must be >= 1 (no autotuning in 3D)");
+    return LS_E_INVALID;
+  }
+  std::unique_ptr<ls_handle> h(new ls_handle());
+  h->dim = 3;
+  h->s3.reset(new Sweep3());
+  h->opt = o;
+  h->st = static_cast<hipStream_t>(o.hip_stream);
+  LSW_HIP_TRY(hipGetDevice(&h->device));
+  const size_t n3 = (size_t)n * n * n;
+  std::vector<double> mh(n3);
+  LSW_HIP_TRY(hipMemcpy(mh.data(), m_dev, n3 * sizeof(double), hipMemcpyDeviceToHost));
+  Sweep3& s = *h->s3;
+  const std::string err = build_host_setup3(mh.data(), n, omega, pml_width, layer_thickness, o.pml_C,
+                                            o.freq_samples, kSlab3MaxLines, s.H);
+  if (!err.empty()) {
+    set_error(err);
+    return LS_E_INVALID;
+  }
+  h->n = n;
+  h->b = pml_width;
+  h->w = layer_thickness;
+  h->L = s.H.L;
+  h->P = fft_len(n);
+  h->ns = s.H.ns;
+  h->nslices = s.H.nslices;
+  h->omega = omega;
+  h->prec = o.precision;
+  h->H.C = o.pml_C;
+  h->H.h = s.H.h;
+  h->H.freq_lo = s.H.freq_lo;
+  h->H.freq_delta = s.H.freq_delta;
+  h->H.slices = s.H.slices;
+  set_default_choices(h.get());
+  h->N = n3;
+  h->E = (size_t)h->L * h->L * h->L;
+  for (const SlicePlan& p : s.H.slices) {
+    const Slab3 sl{p.first, p.lo, p.hi, p.t, p.naux, p.t * h->L};
+    s.slabs.push_back(sl);
+    s.maxnb = std::max(s.maxnb, sl.nb);
+  }
+  const ls_status e = device_setup3(h.get(), m_dev, mh);
+  if (e != LS_OK) return e;
+  *out = h.release();
+  return LS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1428,8 +1748,8 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
       set_error("grid and m_dev must not be NULL");
       return LS_E_INVALID;
     }
-    if (grid->dim != 2) {
-      set_error("only dim = 2 is implemented");
+    if (grid->dim != 2 && grid->dim != 3) {
+      set_error("dim must be 2 or 3");
       return LS_E_INVALID;
     }
     ls_options o;
@@ -1450,6 +1770,13 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
     if (o.autotune < 0 || o.autotune > 4096) {
       set_error("autotune must be in [0, 4096] (right-hand sides to tune for)");
       return LS_E_INVALID;
+    }
+    if (grid->dim == 3) {
+      if (o.autotune != 0) {
+        set_error("3D: autotune is not available");
+        return LS_E_INVALID;
+      }
+      return setup3_handle(grid, omega, m_dev, pml_width, layer_thickness, o, out);
     }
     if (layer_thickness <= 0) {
       if (o.autotune == 0) {
@@ -1555,9 +1882,8 @@ ls_status ls_solve(ls_handle* h, const void* rhs_dev, int nrhs, int rhs_kind, do
     double2* G = h->G.as<double2>();
     if (rhs_kind == LS_RHS_INCIDENT) {
       // g = -omega^2 K (m u_I)
-      LSW_HIP_TRY(launch_convolve<double>(static_cast<const double2*>(rhs_dev), h->m.as<double>(), h->n, nrhs,
-                                          h->khat.as<double2>(), h->tw.as<double2>(), 0.0, -h->omega * h->omega,
-                                          h->fftw64.as<double2>(), G, h->st));
+      e = convolve_any<double>(h, static_cast<const double2*>(rhs_dev), true, nrhs, 0.0, -h->omega * h->omega, G);
+      if (e != LS_OK) return e;
     } else {
       LSW_HIP_TRY(hipMemcpyAsync(G, rhs_dev, (size_t)nrhs * N * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
     }
@@ -1602,8 +1928,8 @@ ls_status ls_adjoint(ls_handle* h, const void* resid_dev, int nrhs, double tol, 
     // b_j = K conj(r_j)
     double2* T1 = h->T1.as<double2>();
     LSW_HIP_TRY(launch_conj(T1, static_cast<const double2*>(resid_dev), (size_t)nrhs * N, h->st));
-    LSW_HIP_TRY(launch_convolve<double>(T1, nullptr, h->n, nrhs, h->khat.as<double2>(), h->tw.as<double2>(), 0.0, 1.0,
-                                        h->fftw64.as<double2>(), h->G.as<double2>(), h->st));
+    ls_status e = convolve_any<double>(h, T1, false, nrhs, 0.0, 1.0, h->G.as<double2>());
+    if (e != LS_OK) return e;
     std::vector<ls_rhs_info> info;
     const ls_status gs = run_gmres(h, nrhs, tol, info);
     if (gs != LS_OK && gs != LS_E_NOCONV) return gs;
@@ -1643,14 +1969,10 @@ ls_status ls_apply_K(ls_handle* h, const void* x, int nrhs, void* y, int precisi
   }
   ls_status e = ensure_workspace(h, nrhs);
   if (e != LS_OK) return e;
-  if (precision == LS_FP64)
-    LSW_HIP_TRY(launch_convolve<double>(static_cast<const double2*>(x), nullptr, h->n, nrhs, h->khat.as<double2>(),
-                                        h->tw.as<double2>(), 0.0, 1.0, h->fftw64.as<double2>(),
-                                        static_cast<double2*>(y), h->st));
-  else
-    LSW_HIP_TRY(launch_convolve<float>(static_cast<const float2*>(x), nullptr, h->n, nrhs, h->khat32.as<float2>(),
-                                       h->tw32.as<float2>(), 0.0f, 1.0f, h->fftw32.as<float2>(),
-                                       static_cast<float2*>(y), h->st));
+  e = precision == LS_FP64
+          ? convolve_any<double>(h, static_cast<const double2*>(x), false, nrhs, 0.0, 1.0, static_cast<double2*>(y))
+          : convolve_any<float>(h, static_cast<const float2*>(x), false, nrhs, 0.0f, 1.0f, static_cast<float2*>(y));
+  if (e != LS_OK) return e;
   LSW_HIP_TRY(hipStreamSynchronize(h->st));
   return LS_OK;
 }
@@ -1660,6 +1982,15 @@ ls_status ls_apply_Q(ls_handle* h, const void* r, int nrhs, void* f, int precisi
   if (nrhs < 1 || !r || !f) {
     set_error("ls_apply_Q: bad argument");
     return LS_E_INVALID;
+  }
+  if (h->dim == 3) {
+    const Stencil3 S3 = stencil3(h);
+    if (precision == LS_FP64)
+      LSW_HIP_TRY(launch3_apply_Q<double>(S3, static_cast<const double2*>(r), nrhs, static_cast<double2*>(f), h->st));
+    else
+      LSW_HIP_TRY(launch3_apply_Q<float>(S3, static_cast<const float2*>(r), nrhs, static_cast<float2*>(f), h->st));
+    LSW_HIP_TRY(hipStreamSynchronize(h->st));
+    return LS_OK;
   }
   const StencilTables S = h->stencils();
   if (precision == LS_FP64)
@@ -1677,6 +2008,15 @@ ls_status ls_apply_H(ls_handle* h, const void* u, int nrhs, void* y, int precisi
   if (nrhs < 1 || !u || !y) {
     set_error("ls_apply_H: bad argument");
     return LS_E_INVALID;
+  }
+  if (h->dim == 3) {
+    const Stencil3 S3 = stencil3(h);
+    if (precision == LS_FP64)
+      LSW_HIP_TRY(launch3_apply_H<double>(S3, static_cast<const double2*>(u), nrhs, static_cast<double2*>(y), h->st));
+    else
+      LSW_HIP_TRY(launch3_apply_H<float>(S3, static_cast<const float2*>(u), nrhs, static_cast<float2*>(y), h->st));
+    LSW_HIP_TRY(hipStreamSynchronize(h->st));
+    return LS_OK;
   }
   const StencilTables S = h->stencils();
   if (precision == LS_FP64)
@@ -1710,6 +2050,24 @@ ls_status ls_slice_solve(ls_handle* h, int slice, const void* v, int nrhs, void*
   }
   ls_status e = ensure_workspace(h, nrhs);
   if (e != LS_OK) return e;
+  if (h->dim == 3) {
+    auto run3 = [&](auto tag) -> ls_status {
+      using T = decltype(tag);
+      const Slab3& p = h->s3->slabs[slice];
+      const size_t rs = (size_t)(p.hi - p.lo + 1) * h->L * h->L;
+      Slab3Apply<T> a = slab3_args<T>(h, slice, nrhs);
+      a.src = static_cast<const C<T>*>(v);
+      a.src_rs = rs;
+      a.dst = static_cast<C<T>*>(w);
+      a.dst_rs = rs;
+      LSW_HIP_TRY(launch3_slab_solve<T>(a, h->st));
+      return LS_OK;
+    };
+    e = precision == LS_FP64 ? run3(double{}) : run3(float{});
+    if (e != LS_OK) return e;
+    LSW_HIP_TRY(hipStreamSynchronize(h->st));
+    return LS_OK;
+  }
   const KernelChoice kc = choice_for(h, nrhs);
   if (kc.slice == 16 && (e = ensure_mscr(h, nrhs)) != LS_OK) return e;
   auto run = [&](auto tag) -> ls_status {
@@ -1736,7 +2094,7 @@ ls_status ls_get_info(const ls_handle* h, ls_setup_info* o) {
     set_error("info must not be NULL");
     return LS_E_INVALID;
   }
-  o->dim = 2;
+  o->dim = h->dim;
   o->n = h->n;
   o->pml_width = h->b;
   o->layer_thickness = h->w;
@@ -1779,6 +2137,10 @@ ls_status ls_get_tuning(const ls_handle* h, ls_tune_layer* w_host, int wcap, int
 
 ls_status ls_set_kernels(ls_handle* h, int nrhs, int slice_kernel, int iface_kernel) {
   if (check_handle(h) != LS_OK) return LS_E_INVALID;
+  if (h->dim == 3) {
+    set_error("ls_set_kernels: the 2D slice and interface kernels only");
+    return LS_E_INVALID;
+  }
   if (nrhs < 0 || nrhs > kChoiceMax) {
     set_error("ls_set_kernels: 0 <= nrhs <= 256");
     return LS_E_INVALID;
@@ -1826,6 +2188,14 @@ ls_status ls_get_stencils(const ls_handle* h, double* alpha, double* beta, doubl
       dst[2 * i + 1] = src[i].imag();
     }
   };
+  if (h->dim == 3) {
+    const HostSetup3& H3 = h->s3->H;
+    if (alpha) put(alpha, H3.alpha, 27);
+    if (beta) put(beta, H3.beta, 27);
+    if (gamma) put(gamma, H3.gamma_glob.data(), H3.gamma_glob.size());
+    if (aux) put(aux, H3.gamma_aux.data(), H3.gamma_aux.size());
+    return LS_OK;
+  }
   if (alpha) put(alpha, h->H.alpha, 9);
   if (beta) put(beta, h->H.beta, 9);
   if (gamma) put(gamma, h->H.gamma_glob.data(), h->H.gamma_glob.size());
@@ -1839,7 +2209,8 @@ ls_status ls_get_sample_map(const ls_handle* h, int* kmap) {
     set_error("kmap must not be NULL");
     return LS_E_INVALID;
   }
-  std::copy(h->H.kmap.begin(), h->H.kmap.end(), kmap);
+  const std::vector<int>& km = h->dim == 3 ? h->s3->H.kmap : h->H.kmap;
+  std::copy(km.begin(), km.end(), kmap);
   return LS_OK;
 }
 
@@ -2047,6 +2418,40 @@ ls_status ls_host_tables(int n, double omega, const double* m_host, int pml_widt
     if (aux) put(aux, Hs.gamma_aux.data(), Hs.gamma_aux.size());
     if (kmap) std::copy(Hs.kmap.begin(), Hs.kmap.end(), kmap);
     if (green) put(green, Hs.kq.data(), Hs.kq.size());
+    return LS_OK;
+  } catch (const std::exception& ex) {
+    set_error(ex.what());
+    return LS_E_NOMEM;
+  }
+}
+
+ls_status ls_host_tables3(int n, double omega, const double* m_host, int pml_width, int layer_thickness,
+                          double pml_C, int freq_samples, double* alpha, double* beta, double* gamma, double* aux,
+                          int* kmap) {
+  try {
+    set_error("");
+    if (!m_host) {
+      set_error("m_host must not be NULL");
+      return LS_E_INVALID;
+    }
+    HostSetup3 Hs;
+    const std::string err = build_host_setup3(m_host, n, omega, pml_width, layer_thickness, pml_C, freq_samples,
+                                              kSlab3MaxLines, Hs);
+    if (!err.empty()) {
+      set_error(err);
+      return LS_E_INVALID;
+    }
+    auto put = [](double* dst, const cd* src, size_t count) {
+      for (size_t i = 0; i < count; ++i) {
+        dst[2 * i] = src[i].real();
+        dst[2 * i + 1] = src[i].imag();
+      }
+    };
+    if (alpha) put(alpha, Hs.alpha, 27);
+    if (beta) put(beta, Hs.beta, 27);
+    if (gamma) put(gamma, Hs.gamma_glob.data(), Hs.gamma_glob.size());
+    if (aux) put(aux, Hs.gamma_aux.data(), Hs.gamma_aux.size());
+    if (kmap) std::copy(Hs.kmap.begin(), Hs.kmap.end(), kmap);
     return LS_OK;
   } catch (const std::exception& ex) {
     set_error(ex.what());

@@ -258,4 +258,68 @@ hipError_t launch_add_scaled(double2* x, const double2* y, double s, size_t N, h
 // k plane waves exp(i omega (cos t_j x1 + sin t_j x2)), t_j = 2 pi j / k, on the interior grid: [k][n][n]
 hipError_t launch_plane_waves(double2* out, int n, double omega, int k, hipStream_t st);
 
+// ---- 3D sparsified system and sweep (slab3.hip) ----
+// Float64 stencil tables of the 3D method on the device.
+struct Stencil3 {
+  const double2* alpha;  // 27
+  const double2* beta;   // 27
+  const double2* gglob;  // [(2b+1)^3][27]
+  const double2* gaux;   // [b][2b+1][2b+1][ns][27]
+  const int* kmap;       // [L]^3
+  const double* m;       // [n]^3
+  int n, b, L, ns;
+  double omega2;
+};
+// A slab: lines [first, hi], D = [lo, hi], t lines, naux = lo - first, nb = t L.
+struct Slab3 {
+  int first, lo, hi, t, naux, nb;
+};
+// Float64 work arrays of a slab's factorization.
+struct Slab3Work {
+  double2* S;   // [nb][nb] block being inverted
+  double2* W;   // [nb][nb] S_{j-1}^{-1} C_{j-1}
+  double2* Sp;  // [nb][nb] S_{j-1}^{-1}
+  double2* Xr;  // [32][nb] pivot rows of a panel
+  double2* cf;  // [3][nb][9] block coefficients A_j, B_j, C_{j-1}
+  int* piv;     // [nb] row interchanges
+  int* perm;    // [nb] column order of the inverse
+};
+// One slab solve: factors, coefficients, work vectors, and where its
+// right-hand side comes from and its D part goes to.
+template <typename T>
+struct Slab3Apply {
+  Slab3 p;
+  int L, nrhs;
+  const C<T>* F;    // [L][nb][nb] S_j^{-1}
+  const C<T>* cbc;  // [L][2][nb][9] B_j, C_j
+  const C<T>* cm;   // [L][L][9] coupling of line lo to lo - 1
+  const C<T>* cp;   // [L][L][9] coupling of line hi to hi + 1
+  C<T>* Y;          // [nrhs][L][nb]
+  C<T>* z;          // [nrhs][nb]
+  const C<T>* src;  // D part of the right-hand side, (rhs, aD, e2, e3) at rhs*src_rs + (aD L + e2) L + e3; may be null
+  size_t src_rs;
+  const C<T>* cu;   // line lo - 1 (cmode 1) or hi + 1 (cmode 2) of the sweep field, rhs stride cu_rs
+  size_t cu_rs;
+  int cmode;        // 0 none, 1: minus coupling on the first line of D, 2: plus coupling on the last line
+  C<T>* dst;        // D part of the result, same layout as src with dst_rs
+  size_t dst_rs;
+  int dop;          // 0 store, 1 subtract
+};
+template <typename T>
+hipError_t launch3_apply_Q(const Stencil3& S, const C<T>* r, int nrhs, C<T>* f, hipStream_t st);
+template <typename T>
+hipError_t launch3_apply_H(const Stencil3& S, const C<T>* u, int nrhs, C<T>* y, hipStream_t st);
+template <typename T>
+hipError_t launch3_extract(const C<T>* u, int n, int b, int nrhs, C<T>* z, hipStream_t st);
+// S_j^{-1} of every block of nslab slabs (device arrays slabs, works;
+// factors: device array of per-slab factor bases); status > 0: zero pivot in slab status-1
+template <typename T>
+hipError_t launch3_factor(const Stencil3& S, const Slab3* slabs, const Slab3Work* works, int nslab, int maxnb,
+                          C<T>* const* factors, int* status, hipStream_t st);
+template <typename T>
+hipError_t launch3_apply_coefs(const Stencil3& S, const Slab3* slabs, int nslab, int maxnb, C<T>* const* cbc,
+                               C<T>* const* cm, C<T>* const* cpl, hipStream_t st);
+template <typename T>
+hipError_t launch3_slab_solve(const Slab3Apply<T>& A, hipStream_t st);
+
 }  // namespace lsw

@@ -334,6 +334,82 @@ void pml_gamma_2d(double kappa, double omega, double h, const double os[2][3], c
   normalise_phase(out, 9);
 }
 
+// Null vector of the rows x (rows - 1) matrix F (row-major): the last column
+// of the Q of its Householder QR.
+void null_vector_hh(const cd* F, int rows, cd* out) {
+  const int cols = rows - 1;
+  std::vector<cd> M(F, F + (size_t)rows * cols);
+  std::vector<cd> vs((size_t)cols * rows);
+  for (int c = 0; c < cols; ++c) {
+    cd* v = &vs[(size_t)c * rows];
+    double xn2 = 0.0;
+    for (int r = c; r < rows; ++r) xn2 += std::norm(M[(size_t)r * cols + c]);
+    const double xn = std::sqrt(xn2);
+    const cd x0 = M[(size_t)c * cols + c];
+    const cd ph = (std::abs(x0) == 0.0) ? cd(1.0) : x0 / std::abs(x0);
+    const cd alpha = -ph * xn;
+    double vn2 = 0.0;
+    for (int r = 0; r < rows; ++r) {
+      v[r] = (r < c) ? cd(0.0) : M[(size_t)r * cols + c] - (r == c ? alpha : cd(0.0));
+      vn2 += std::norm(v[r]);
+    }
+    const double vn = std::sqrt(vn2);
+    for (int r = 0; r < rows; ++r) v[r] = (vn > 0) ? v[r] / vn : cd(0.0);
+    for (int cc = c; cc < cols; ++cc) {
+      cd dot(0.0);
+      for (int r = c; r < rows; ++r) dot += std::conj(v[r]) * M[(size_t)r * cols + cc];
+      for (int r = c; r < rows; ++r) M[(size_t)r * cols + cc] -= 2.0 * v[r] * dot;
+    }
+  }
+  std::vector<cd> e(rows, cd(0.0));
+  e[rows - 1] = 1.0;
+  for (int c = cols - 1; c >= 0; --c) {
+    const cd* v = &vs[(size_t)c * rows];
+    cd dot(0.0);
+    for (int r = 0; r < rows; ++r) dot += std::conj(v[r]) * e[r];
+    for (int r = 0; r < rows; ++r) e[r] -= 2.0 * v[r] * dot;
+  }
+  std::copy(e.begin(), e.end(), out);
+}
+
+// gamma of eq. gamma for one point in 3D (Sec. 3.1): as pml_gamma_2d over
+// the 27-point neighbourhood and the 26 directions v / |v|, v in
+// {-1,0,1}^3 minus 0 (lexicographic, axis 0 slowest).
+void pml_gamma_3d(double kappa, double omega, double h, const double os[3][3], cd* out) {
+  double dirs[26][3];
+  int nd = 0;
+  for (int v = 0; v < 27; ++v) {
+    const int a = v / 9 - 1, c = (v / 3) % 3 - 1, e = v % 3 - 1;
+    if (!a && !c && !e) continue;
+    const double nv = std::sqrt((double)(a * a + c * c + e * e));
+    dirs[nd][0] = a / nv;
+    dirs[nd][1] = c / nv;
+    dirs[nd][2] = e / nv;
+    ++nd;
+  }
+  cd F[27 * 26];
+  const double kr = kappa / omega;
+  for (int r = 0; r < 26; ++r)
+    for (int o = 0; o < 27; ++o) {
+      const int d1 = o / 9 - 1, d2 = (o / 3) % 3 - 1, d3 = o % 3 - 1;
+      const double ph = kappa * h * (dirs[r][0] * d1 + dirs[r][1] * d2 + dirs[r][2] * d3);
+      const double dmp = -kr * (dirs[r][0] * (os[0][d1 + 1] - os[0][1]) + dirs[r][1] * (os[1][d2 + 1] - os[1][1]) +
+                                dirs[r][2] * (os[2][d3 + 1] - os[2][1]));
+      F[o * 26 + r] = std::exp(cd(dmp, ph));
+    }
+  null_vector_hh(F, 27, out);
+  normalise_phase(out, 27);
+}
+
+// Local-frequency sample nearest to omega^2 (1 - m) (Sec. 2.3, reading G9).
+int sample_index(double mp, double w2, double lo, double delta, int ns) {
+  if (ns <= 1) return 0;
+  const double v = w2 * (1.0 - mp);
+  const double t = (v - lo) / delta + 0.5;
+  const double f = std::floor(t);
+  return f < 0 ? 0 : (f > ns - 1 ? ns - 1 : (int)f);
+}
+
 }  // namespace
 
 std::vector<cd> green3_octant(int n, double omega) {
@@ -549,6 +625,189 @@ std::string build_host_setup(const double* m, int n, double omega, int b, int w,
     for (int o = 0; o < 3; ++o) os[1][o] = omega_sigma_global(i2 - 1 + o, n, b, C);
     const double kappa = std::sqrt(lo + ks * delta);
     pml_gamma_2d(kappa, omega, h, os, &S.gamma_aux[(size_t)id * 9]);
+  });
+  return "";
+}
+
+}  // namespace lsw
+
+namespace lsw {
+
+std::string build_host_setup3(const double* m, int n, double omega, int b, int w, double C, int freq_samples,
+                              int max_lines, HostSetup3& S) {
+  char buf[256];
+  if (n < 1) return "n must be >= 1";
+  if (!(omega > 0.0) || !std::isfinite(omega)) return "omega must be finite and > 0";
+  if (b < 1) return "pml_width must be >= 1";
+  if (w < 1) return "layer_thickness must be >= 1";
+  if (!(C >= 0.0) || !std::isfinite(C)) return "pml_C must be finite and >= 0";
+  const double h = 1.0 / (n + 1);
+  if (omega * h / std::sqrt(kPi) > 2.0) return "fewer than ~2 points per wavelength (omega*h/sqrt(pi) > 2)";
+  S.n = n;
+  S.b = b;
+  S.w = w;
+  S.omega = omega;
+  S.h = h;
+  S.C = C;
+  S.L = n + 2 + 2 * b;
+  const int L = S.L;
+  const size_t n3 = (size_t)n * n * n;
+
+  // ---- medium range and local-frequency samples (Sec. 2.3, reading G9) ----
+  double mmax = -INFINITY, mmin = INFINITY;
+  for (size_t i = 0; i < n3; ++i) {
+    if (!std::isfinite(m[i])) return "m has a non-finite value";
+    mmax = std::max(mmax, m[i]);
+    mmin = std::min(mmin, m[i]);
+  }
+  if (!(1.0 - mmax > 0.0)) return "max m must be < 1 (the local frequency must be real)";
+  const double w2 = omega * omega;
+  const double lo = w2 * (1.0 - mmax);
+  const double hi = w2 * (1.0 - mmin);
+  int ns = freq_samples > 0 ? freq_samples : n;
+  if (!(hi > lo)) ns = 1;
+  const double delta = ns > 1 ? (hi - lo) / (ns - 1) : 0.0;
+  S.ns = ns;
+  S.freq_lo = lo;
+  S.freq_delta = delta;
+  S.kmap.assign((size_t)L * L * L, 0);
+  parallel_for(L, [&](int e1) {
+    for (int e2 = 0; e2 < L; ++e2)
+      for (int e3 = 0; e3 < L; ++e3) {
+        const int i1 = e1 - b, i2 = e2 - b, i3 = e3 - b;
+        double mp = 0.0;
+        if (i1 >= 1 && i1 <= n && i2 >= 1 && i2 <= n && i3 >= 1 && i3 <= n)
+          mp = m[((size_t)(i1 - 1) * n + (i2 - 1)) * n + (i3 - 1)];
+        S.kmap[((size_t)e1 * L + e2) * L + e3] = sample_index(mp, w2, lo, delta, ns);
+      }
+  });
+
+  // ---- Green's table (Sec. 1, Sec. 2.1, reading G1) ----
+  S.kq = green3_octant(n, omega);
+  const int Q = n + 2;
+  auto kq = [&](int d1, int d2, int d3) {
+    return S.kq[((size_t)std::abs(d1) * Q + std::abs(d2)) * Q + std::abs(d3)];
+  };
+
+  // ---- alpha: streamed QR of K_{mu,mu^c}^H, then the SVD of R (eq. alpha) ----
+  {
+    const int nt = (int)std::min<unsigned>(worker_count(), 2 * n + 1);
+    std::vector<std::vector<cd>> Rs(nt);
+    std::vector<int> have(nt, 0);
+    parallel_for(nt, [&](int t) {
+      constexpr int kRows = 128;
+      std::vector<cd> block;
+      block.reserve((size_t)kRows * 27);
+      std::vector<cd> R;
+      bool hv = false;
+      int rows = 0;
+      for (int l1 = -n + t; l1 <= n; l1 += nt)
+        for (int l2 = -n; l2 <= n; ++l2)
+          for (int l3 = -n; l3 <= n; ++l3) {
+            if (std::abs(l1) <= 1 && std::abs(l2) <= 1 && std::abs(l3) <= 1) continue;
+            for (int o = 0; o < 27; ++o)
+              block.push_back(std::conj(kq(o / 9 - 1 - l1, (o / 3) % 3 - 1 - l2, o % 3 - 1 - l3)));
+            if (++rows == kRows) {
+              qr_append(R, block.data(), rows, 27, hv);
+              hv = true;
+              rows = 0;
+              block.clear();
+            }
+          }
+      if (rows) {
+        qr_append(R, block.data(), rows, 27, hv);
+        hv = true;
+      }
+      Rs[t] = R;
+      have[t] = hv;
+    });
+    std::vector<cd> R;
+    bool hv = false;
+    for (int t = 0; t < nt; ++t)
+      if (have[t]) {
+        qr_append(R, Rs[t].data(), 27, 27, hv);
+        hv = true;
+      }
+    jacobi_min_right_vector(R, 27, 27, S.alpha, S.alpha_sv);
+    normalise_phase(S.alpha, 27);
+    // beta^* = alpha^* K_{mu,mu}:  beta_l = sum_j conj(k_{j-l}) alpha_j (eq. beta)
+    for (int l = 0; l < 27; ++l) {
+      cd s(0.0);
+      for (int j = 0; j < 27; ++j)
+        s += std::conj(kq(j / 9 - l / 9, (j / 3) % 3 - (l / 3) % 3, j % 3 - l % 3)) * S.alpha[j];
+      S.beta[l] = s;
+    }
+  }
+
+  // ---- global PML stencils by per-axis class (eq. gamma, Sec. 3.1) ----
+  const int NC = 2 * b + 1;
+  S.gamma_glob.assign((size_t)NC * NC * NC * 27, cd(0.0));
+  parallel_for(NC * NC * NC, [&](int id) {
+    const int cls[3] = {id / (NC * NC), (id / NC) % NC, id % NC};
+    if (!cls[0] && !cls[1] && !cls[2]) return;
+    double os[3][3];
+    for (int k = 0; k < 3; ++k) {
+      const int i = class_index(cls[k], n, b);
+      for (int o = 0; o < 3; ++o) os[k][o] = omega_sigma_global(i - 1 + o, n, b, C);
+    }
+    pml_gamma_3d(omega, omega, h, os, &S.gamma_glob[(size_t)id * 27]);
+  });
+
+  // ---- slabs (reading G8) ----
+  const int nl = std::max(1, (n + 2) / w);
+  S.nslices = nl;
+  S.slices.resize(nl);
+  for (int k = 0; k < nl; ++k) {
+    SlicePlan& p = S.slices[k];
+    p.lo = (k == 0) ? -b : k * w;
+    p.hi = (k == nl - 1) ? n + 1 + b : (k + 1) * w - 1;
+    p.first = (k == 0) ? p.lo : p.lo - b;
+    p.t = p.hi - p.first + 1;
+    p.naux = p.lo - p.first;
+    if (p.t > max_lines) {
+      std::snprintf(buf, sizeof buf, "slab %d has %d lines; at most %d are supported (reduce w or b)", k, p.t,
+                    max_lines);
+      return buf;
+    }
+  }
+
+  // ---- auxiliary PML stencils at the sampled local frequencies (Sec. 2.3) ----
+  const size_t naux_keys = (size_t)b * NC * NC * ns;
+  S.gamma_aux.assign(naux_keys * 27, cd(0.0));
+  std::vector<char> used(naux_keys, 0);
+  for (int k = 1; k < nl; ++k) {
+    const SlicePlan& p = S.slices[k];
+    for (int q = 0; q < b; ++q) {
+      const int line = p.lo - 1 - q;
+      for (int e2 = 0; e2 < L; ++e2) {
+        const int c2 = axis_class(e2 - b, n, b);
+        for (int e3 = 0; e3 < L; ++e3) {
+          const int c3 = axis_class(e3 - b, n, b);
+          const int ks = S.kmap[((size_t)(line + b) * L + e2) * L + e3];
+          used[(((size_t)q * NC + c2) * NC + c3) * ns + ks] = 1;
+        }
+      }
+    }
+  }
+  std::vector<size_t> todo;
+  for (size_t i = 0; i < used.size(); ++i)
+    if (used[i]) todo.push_back(i);
+  parallel_for((int)todo.size(), [&](int ii) {
+    const size_t id = todo[ii];
+    const int ks = (int)(id % ns);
+    const int c3 = (int)((id / ns) % NC), c2 = (int)((id / ((size_t)ns * NC)) % NC);
+    const int q = (int)(id / ((size_t)ns * NC * NC));
+    double os[3][3];
+    os[0][0] = omega_sigma_aux(q + 1, b, C);
+    os[0][1] = omega_sigma_aux(q, b, C);
+    os[0][2] = omega_sigma_aux(q - 1, b, C);
+    const int cls[2] = {c2, c3};
+    for (int k = 0; k < 2; ++k) {
+      const int i = class_index(cls[k], n, b);
+      for (int o = 0; o < 3; ++o) os[k + 1][o] = omega_sigma_global(i - 1 + o, n, b, C);
+    }
+    const double kappa = std::sqrt(lo + ks * delta);
+    pml_gamma_3d(kappa, omega, h, os, &S.gamma_aux[id * 27]);
   });
   return "";
 }

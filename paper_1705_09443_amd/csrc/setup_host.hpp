@@ -39,6 +39,22 @@ struct HostSetup {
 void bessel_j0y0(double x, double* j0, double* y0);
 void bessel_j1y1_small(double x, double* j1, double* y1);
 
+// The same setup in 3D (Sec. 3.1): 27-point neighbourhood mu = {-1,0,1}^3 in
+// lexicographic order (axis 0 slowest), PML stencils annihilating the 26
+// neighbour directions, the sample map over the extended cube.
+struct HostSetup3 {
+  int n = 0, b = 0, w = 0, L = 0, nslices = 0, ns = 0;
+  double omega = 0, h = 0, C = 0;
+  double freq_lo = 0, freq_delta = 0;
+  std::vector<cd> kq;          // k_delta for delta in [0, n+1]^3, [(n+2)]^3
+  cd alpha[27], beta[27];
+  double alpha_sv[27];         // singular values of K_{mu,mu^c}, descending
+  std::vector<cd> gamma_glob;  // [(2b+1)^3][27] by per-axis class (c1, c2, c3)
+  std::vector<cd> gamma_aux;   // [b][2b+1][2b+1][ns][27] by (depth q, c2, c3, sample k)
+  std::vector<int> kmap;       // [L]^3 sample index of every extended point
+  std::vector<SlicePlan> slices;
+};
+
 // Per-axis stretch class of grid index i (0 interior, 1..b low, b+1..2b high).
 int axis_class(int i, int n, int b);
 
@@ -48,8 +64,13 @@ int axis_class(int i, int n, int b);
 // (exp(i omega a)(1 - i omega a) - 1) / omega^2, a = h (3 / (4 pi))^(1/3).
 std::vector<cd> green3_octant(int n, double omega);
 
-// Build everything from m on the host. Returns "" on success, else a message.
+// Build everything (2D) from m on the host. Returns "" on success, else a message.
 std::string build_host_setup(const double* m_host, int n, double omega, int b, int w, double C,
                              int freq_samples, HostSetup& out);
+
+// 3D: m is [n][n][n]; slices are slabs of lines i1 with at most
+// max_slab_lines lines each (the slab factorization's block size bound).
+std::string build_host_setup3(const double* m_host, int n, double omega, int b, int w, double C,
+                              int freq_samples, int max_slab_lines, HostSetup3& out);
 
 }  // namespace lsw

@@ -1,0 +1,676 @@
+// The 3D sparsified system and moving-PML sweep (Sec. 3.1; Sec. 2.2 and 2.3
+// with d = 3).
+//
+// Stencils: 27-point neighbourhood mu = {-1,0,1}^3, neighbour index
+// o = 9 (d1+1) + 3 (d2+1) + (d3+1). Rows of H at I^h = [0, n+1]^3 use
+// conj(alpha_o) + omega^2 conj(beta_o) m_{i+o}; PML rows use conj(gamma_i,o)
+// by per-axis class; auxiliary-PML rows of a slab use the gamma of their
+// depth, transverse classes and sampled local frequency.
+//
+// Slabs: the subproblem of slab k lives on t lines [first, hi] (b auxiliary
+// lines, then the lines of D_k) times the L x L transverse points. Ordered by
+// the transverse index e2 it is block tridiagonal,
+//     B_j x_{j-1} + A_j x_j + C_j x_{j+1} = r_j,
+// with blocks of nb = t L unknowns (a, e3), index a L + e3, each block row
+// holding at most 9 entries per row (offsets d1, d3). Block elimination
+//     S_0 = A_0,  S_j = A_j - B_j S_{j-1}^{-1} C_{j-1}
+// is done in float64 for all slabs at once; S_j^{-1} is formed by blocked
+// in-place Gauss-Jordan with partial pivoting (32-column panels) and kept
+// (cast to the working precision) as the factor F_j. A slab solve is
+//     y_j = F_j (r_j - B_j y_{j-1}),  x_{L-1} = y_{L-1},
+//     x_j = y_j - F_j (C_j x_{j+1}),
+// one dense matrix-vector product per block and direction.
+#include "kernels.hpp"
+
+namespace lsw {
+
+namespace {
+
+__device__ inline int class3(int i, int n, int b) {
+  if (i < 0) return i + b + 1;
+  if (i > n + 1) return i - (n + 2) + b + 1;
+  return 0;
+}
+
+__device__ inline double2 dconj(double2 v) { return make_double2(v.x, -v.y); }
+
+// Coefficient of H in the row of grid point (i1, i2, i3) for neighbour o.
+__device__ double2 h3_coef(const Stencil3& S, int i1, int i2, int i3, int o) {
+  const int n = S.n;
+  if (i1 >= 0 && i1 <= n + 1 && i2 >= 0 && i2 <= n + 1 && i3 >= 0 && i3 <= n + 1) {
+    const int j1 = i1 + o / 9 - 1, j2 = i2 + (o / 3) % 3 - 1, j3 = i3 + o % 3 - 1;
+    double mm = 0.0;
+    if (j1 >= 1 && j1 <= n && j2 >= 1 && j2 <= n && j3 >= 1 && j3 <= n)
+      mm = S.m[((size_t)(j1 - 1) * n + (j2 - 1)) * n + (j3 - 1)];
+    const double2 al = S.alpha[o], be = S.beta[o];
+    return make_double2(al.x + S.omega2 * be.x * mm, -al.y - S.omega2 * be.y * mm);
+  }
+  const int NC = 2 * S.b + 1;
+  const int c1 = class3(i1, n, S.b), c2 = class3(i2, n, S.b), c3 = class3(i3, n, S.b);
+  return dconj(S.gglob[(((size_t)c1 * NC + c2) * NC + c3) * 27 + o]);
+}
+
+// Coefficient of the subproblem of slab p in the row of local point
+// (a, e2, e3) for neighbour o; zero where the neighbour lies outside the
+// subproblem (Dirichlet line left of the auxiliary PML, D_{k+1}, or beyond
+// the extended grid).
+__device__ double2 sub3_coef(const Stencil3& S, const Slab3& p, int a, int e2, int e3, int o) {
+  const int L = S.L, b = S.b;
+  const int a2 = a + o / 9 - 1, f2 = e2 + (o / 3) % 3 - 1, f3 = e3 + o % 3 - 1;
+  if (a2 < 0 || a2 >= p.t || f2 < 0 || f2 >= L || f3 < 0 || f3 >= L) return make_double2(0.0, 0.0);
+  const int line = p.first + a;
+  if (a < p.naux) {
+    const int q = p.lo - 1 - line;
+    const int ks = S.kmap[((size_t)(line + b) * L + e2) * L + e3];
+    const int NC = 2 * b + 1;
+    const int c2 = class3(e2 - b, S.n, b), c3 = class3(e3 - b, S.n, b);
+    return dconj(S.gaux[((((size_t)q * NC + c2) * NC + c3) * S.ns + ks) * 27 + o]);
+  }
+  return h3_coef(S, line, e2 - b, e3 - b, o);
+}
+
+__device__ inline double2 zmul(double2 a, double2 b) {
+  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+}
+
+// ---- stencil applies ---------------------------------------------------------
+
+// f = Q r on the extended cube: alpha^* r_{mu_i} on I^h, zero on the PML
+template <typename T>
+__global__ void k3_apply_Q(Stencil3 S, const C<T>* __restrict__ r, int nrhs, C<T>* __restrict__ f) {
+  const int L = S.L, n = S.n, b = S.b;
+  const size_t E = (size_t)L * L * L;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * nrhs) return;
+  const size_t rhs = idx / E, e = idx % E;
+  const int i1 = (int)(e / ((size_t)L * L)) - b, i2 = (int)((e / L) % L) - b, i3 = (int)(e % L) - b;
+  C<T> acc = mk<T>(0, 0);
+  if (i1 >= 0 && i1 <= n + 1 && i2 >= 0 && i2 <= n + 1 && i3 >= 0 && i3 <= n + 1) {
+    const C<T>* rr = r + rhs * (size_t)n * n * n;
+    for (int o = 0; o < 27; ++o) {
+      const int j1 = i1 + o / 9 - 1, j2 = i2 + (o / 3) % 3 - 1, j3 = i3 + o % 3 - 1;
+      if (j1 < 1 || j1 > n || j2 < 1 || j2 > n || j3 < 1 || j3 > n) continue;
+      const double2 al = S.alpha[o];
+      const C<T> c = mk<T>((T)al.x, (T)(-al.y));
+      acc = cadd<T>(acc, cmul<T>(c, rr[((size_t)(j1 - 1) * n + (j2 - 1)) * n + (j3 - 1)]));
+    }
+  }
+  f[idx] = acc;
+}
+
+// y = H u on the extended cube (Dirichlet ring dropped)
+template <typename T>
+__global__ void k3_apply_H(Stencil3 S, const C<T>* __restrict__ u, int nrhs, C<T>* __restrict__ y) {
+  const int L = S.L, b = S.b;
+  const size_t E = (size_t)L * L * L;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= E * nrhs) return;
+  const size_t rhs = idx / E, e = idx % E;
+  const int e1 = (int)(e / ((size_t)L * L)), e2 = (int)((e / L) % L), e3 = (int)(e % L);
+  const C<T>* uu = u + rhs * E;
+  C<T> acc = mk<T>(0, 0);
+  for (int o = 0; o < 27; ++o) {
+    const int f1 = e1 + o / 9 - 1, f2 = e2 + (o / 3) % 3 - 1, f3 = e3 + o % 3 - 1;
+    if (f1 < 0 || f1 >= L || f2 < 0 || f2 >= L || f3 < 0 || f3 >= L) continue;
+    const double2 c = h3_coef(S, e1 - b, e2 - b, e3 - b, o);
+    acc = cadd<T>(acc, cmul<T>(mk<T>((T)c.x, (T)c.y), uu[((size_t)f1 * L + f2) * L + f3]));
+  }
+  y[idx] = acc;
+}
+
+// z = u restricted to the interior grid I
+template <typename T>
+__global__ void k3_extract(const C<T>* __restrict__ u, int n, int b, int nrhs, C<T>* __restrict__ z) {
+  const int L = n + 2 + 2 * b;
+  const size_t N = (size_t)n * n * n;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= N * nrhs) return;
+  const size_t rhs = idx / N, i = idx % N;
+  const int i1 = (int)(i / ((size_t)n * n)) + 1, i2 = (int)((i / n) % n) + 1, i3 = (int)(i % n) + 1;
+  z[idx] = u[rhs * (size_t)L * L * L + ((size_t)(i1 + b) * L + (i2 + b)) * L + (i3 + b)];
+}
+
+// ---- factorization (float64, all slabs of a batch at once; blockIdx.z = slab) ----
+
+// cf[0]: A_j (d2 = 0), cf[1]: B_j (d2 = -1), cf[2]: C_{j-1} (d2 = +1, rows of
+// block j - 1), each [nb][9] by (d1, d3)
+__global__ void k3_coefs(Stencil3 S, const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int j) {
+  const Slab3 p = slabs[blockIdx.z];
+  const Slab3Work w = works[blockIdx.z];
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= p.nb * 9) return;
+  const int r = idx / 9, o9 = idx % 9, a = r / S.L, e3 = r % S.L;
+  const int d1 = o9 / 3 - 1, d3 = o9 % 3 - 1;
+  const size_t s3 = (size_t)p.nb * 9;
+  w.cf[idx] = sub3_coef(S, p, a, j, e3, (d1 + 1) * 9 + 3 + (d3 + 1));
+  const double2 zero = make_double2(0.0, 0.0);
+  w.cf[s3 + idx] = j > 0 ? sub3_coef(S, p, a, j, e3, (d1 + 1) * 9 + 0 + (d3 + 1)) : zero;
+  w.cf[2 * s3 + idx] = j > 0 ? sub3_coef(S, p, a, j - 1, e3, (d1 + 1) * 9 + 6 + (d3 + 1)) : zero;
+}
+
+// W = S_{j-1}^{-1} C_{j-1}: column c = (a, e3) of C_{j-1} has its entries in
+// rows (a - d1, e3 - d3) of block j - 1, coefficient cf[2][row][(d1, d3)]
+__global__ void k3_schur_w(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int L) {
+  const Slab3 p = slabs[blockIdx.z];
+  const Slab3Work w = works[blockIdx.z];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (c >= p.nb || r >= p.nb) return;
+  const int a = c / L, e3 = c % L;
+  const double2* cc = w.cf + 2 * (size_t)p.nb * 9;
+  const double2* sp = w.Sp + (size_t)r * p.nb;
+  double2 acc = make_double2(0.0, 0.0);
+  for (int o9 = 0; o9 < 9; ++o9) {
+    const int a2 = a - (o9 / 3 - 1), f3 = e3 - (o9 % 3 - 1);
+    if (a2 < 0 || a2 >= p.t || f3 < 0 || f3 >= L) continue;
+    const int rr = a2 * L + f3;
+    const double2 v = zmul(sp[rr], cc[(size_t)rr * 9 + o9]);
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  w.W[(size_t)r * p.nb + c] = acc;
+}
+
+// S = A_j - B_j W (j > 0) or A_j; row r = (a, e3) of B_j has its entries in
+// rows (a + d1, e3 + d3) of W
+__global__ void k3_schur_s(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int L, int j) {
+  const Slab3 p = slabs[blockIdx.z];
+  const Slab3Work w = works[blockIdx.z];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (c >= p.nb || r >= p.nb) return;
+  const int a = r / L, e3 = r % L, ca = c / L, c3 = c % L;
+  double2 v = make_double2(0.0, 0.0);
+  const int d1 = ca - a, d3 = c3 - e3;
+  if (d1 >= -1 && d1 <= 1 && d3 >= -1 && d3 <= 1) v = w.cf[(size_t)r * 9 + (d1 + 1) * 3 + (d3 + 1)];
+  if (j > 0) {
+    const double2* cb = w.cf + (size_t)p.nb * 9 + (size_t)r * 9;
+    for (int o9 = 0; o9 < 9; ++o9) {
+      const int a2 = a + o9 / 3 - 1, f3 = e3 + o9 % 3 - 1;
+      if (a2 < 0 || a2 >= p.t || f3 < 0 || f3 >= L) continue;
+      const double2 t = zmul(cb[o9], w.W[(size_t)(a2 * L + f3) * p.nb + c]);
+      v.x -= t.x;
+      v.y -= t.y;
+    }
+  }
+  w.S[(size_t)r * p.nb + c] = v;
+}
+
+// Gauss-Jordan on the panel columns [k0, k0 + kp) of S, pivots k0..k0+kp-1
+// chosen by partial pivoting over the rows not yet used; every row swap is
+// recorded in piv and applied to the other columns by k3_gj_swap.
+constexpr int kGjPanel = 32;
+constexpr int kGjThreads = 512;
+
+__global__ __launch_bounds__(kGjThreads) void k3_gj_panel(const Slab3* __restrict__ slabs,
+                                                          const Slab3Work* __restrict__ works, int k0,
+                                                          int* __restrict__ status) {
+  const Slab3 p = slabs[blockIdx.z];
+  const Slab3Work w = works[blockIdx.z];
+  const int nb = p.nb;
+  if (k0 >= nb) return;
+  const int kp = min(kGjPanel, nb - k0);
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  __shared__ double best_v[kGjThreads / 64];
+  __shared__ int best_r[kGjThreads / 64];
+  __shared__ int prow_s;
+  __shared__ double2 prow[kGjPanel];
+  double2* S = w.S;
+  for (int pp = 0; pp < kp; ++pp) {
+    const int cp = k0 + pp;
+    // 1. pivot: largest modulus in column cp among rows cp..nb-1 (first on ties)
+    double bv = -1.0;
+    int br = nb;
+    for (int r = cp + tid; r < nb; r += kGjThreads) {
+      const double2 v = S[(size_t)r * nb + cp];
+      const double m2 = v.x * v.x + v.y * v.y;
+      if (m2 > bv) {
+        bv = m2;
+        br = r;
+      }
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ov = __shfl_xor(bv, off);
+      const int orr = __shfl_xor(br, off);
+      if (ov > bv || (ov == bv && orr < br)) {
+        bv = ov;
+        br = orr;
+      }
+    }
+    if (lane == 0) {
+      best_v[wid] = bv;
+      best_r[wid] = br;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double v = best_v[0];
+      int rr = best_r[0];
+      for (int q = 1; q < kGjThreads / 64; ++q)
+        if (best_v[q] > v || (best_v[q] == v && best_r[q] < rr)) {
+          v = best_v[q];
+          rr = best_r[q];
+        }
+      if (rr >= nb) rr = cp;
+      prow_s = rr;
+      w.piv[cp] = rr;
+    }
+    __syncthreads();
+    const int pr = prow_s;
+    // 2. swap rows cp and pr in the panel columns
+    if (pr != cp && tid < kp) {
+      const double2 a = S[(size_t)cp * nb + k0 + tid], c = S[(size_t)pr * nb + k0 + tid];
+      S[(size_t)cp * nb + k0 + tid] = c;
+      S[(size_t)pr * nb + k0 + tid] = a;
+    }
+    __syncthreads();
+    // 3. pivot row: scaled by 1/pivot, its own entry replaced by 1/pivot
+    if (tid < kp) {
+      const double2 pv = S[(size_t)cp * nb + cp];
+      const double d = pv.x * pv.x + pv.y * pv.y;
+      double2 inv = make_double2(0.0, 0.0);
+      if (!(d > 0.0) || !(d < INFINITY)) {
+        if (tid == 0) atomicMax(status, (int)blockIdx.z + 1);
+      } else {
+        inv = make_double2(pv.x / d, -pv.y / d);
+      }
+      const double2 v = S[(size_t)cp * nb + k0 + tid];
+      prow[tid] = tid == pp ? inv : zmul(v, inv);
+    }
+    __syncthreads();
+    if (tid < kp) S[(size_t)cp * nb + k0 + tid] = prow[tid];
+    // 4. eliminate column cp from every other row (panel columns only); the
+    //    32 lanes of a row sit in one wave, which reads the row's column-cp
+    //    entry before its lane pp overwrites it
+    {
+      const int c = tid & 31, rg = tid >> 5;
+      if (c < kp) {
+        const double2 pc = prow[c];
+        for (int r = rg; r < nb; r += kGjThreads / 32) {
+          if (r == cp) continue;
+          const double2 f = S[(size_t)r * nb + cp];
+          double2 v = c == pp ? make_double2(0.0, 0.0) : S[(size_t)r * nb + k0 + c];
+          const double2 t = zmul(f, pc);
+          v.x -= t.x;
+          v.y -= t.y;
+          S[(size_t)r * nb + k0 + c] = v;
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// The panel's row swaps applied, in order, to every column outside the
+// panel; the pivot rows of those columns copied to Xr [kp][nb]
+__global__ void k3_gj_swap(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int k0) {
+  const Slab3 p = slabs[blockIdx.z];
+  const Slab3Work w = works[blockIdx.z];
+  const int nb = p.nb;
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k0 >= nb || c >= nb) return;
+  const int kp = min(kGjPanel, nb - k0);
+  if (c >= k0 && c < k0 + kp) return;
+  double2* S = w.S;
+  for (int q = 0; q < kp; ++q) {
+    const int r1 = k0 + q, r2 = w.piv[r1];
+    if (r2 != r1) {
+      const double2 a = S[(size_t)r1 * nb + c], b = S[(size_t)r2 * nb + c];
+      S[(size_t)r1 * nb + c] = b;
+      S[(size_t)r2 * nb + c] = a;
+    }
+  }
+  for (int q = 0; q < kp; ++q) w.Xr[(size_t)q * nb + c] = S[(size_t)(k0 + q) * nb + c];
+}
+
+// S[:, c] += X Xr[:, c] for columns c outside the panel, X = S[:, panel]
+// minus the identity on the pivot rows: 64 x 64 tiles, 256 threads, each
+// thread 4 x 4 entries (rows ty + 16 i, columns tx + 16 q)
+__global__ __launch_bounds__(256) void k3_gj_update(const Slab3* __restrict__ slabs,
+                                                    const Slab3Work* __restrict__ works, int k0) {
+  const Slab3 p = slabs[blockIdx.z];
+  const Slab3Work w = works[blockIdx.z];
+  const int nb = p.nb;
+  const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
+  if (k0 >= nb || r0 >= nb || c0 >= nb) return;
+  const int kp = min(kGjPanel, nb - k0);
+  if (c0 >= k0 && c0 + 64 <= k0 + kp) return;  // the whole tile is panel columns
+  __shared__ double2 Xs[kGjPanel][64];  // X tile, k-major
+  __shared__ double2 Rs[kGjPanel][64];
+  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  double2* S = w.S;
+  for (int idx = tid; idx < 64 * kGjPanel; idx += 256) {
+    const int rr = idx / kGjPanel, q = idx % kGjPanel, r = r0 + rr;
+    double2 v = make_double2(0.0, 0.0);
+    if (r < nb && q < kp) {
+      v = S[(size_t)r * nb + k0 + q];
+      if (r == k0 + q) v.x -= 1.0;
+    }
+    Xs[q][rr] = v;
+  }
+  for (int idx = tid; idx < kGjPanel * 64; idx += 256) {
+    const int q = idx / 64, cc = idx % 64, c = c0 + cc;
+    Rs[q][cc] = (q < kp && c < nb) ? w.Xr[(size_t)q * nb + c] : make_double2(0.0, 0.0);
+  }
+  __syncthreads();
+  double2 acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[i][q] = make_double2(0.0, 0.0);
+  for (int k = 0; k < kp; ++k) {
+    double2 xa[4], rb[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) xa[i] = Xs[k][ty + 16 * i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) rb[q] = Rs[k][tx + 16 * q];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        acc[i][q].x += xa[i].x * rb[q].x - xa[i].y * rb[q].y;
+        acc[i][q].y += xa[i].x * rb[q].y + xa[i].y * rb[q].x;
+      }
+  }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int r = r0 + ty + 16 * i;
+    if (r >= nb) continue;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int c = c0 + tx + 16 * q;
+      if (c >= nb || (c >= k0 && c < k0 + kp)) continue;
+      double2 v = S[(size_t)r * nb + c];
+      v.x += acc[i][q].x;
+      v.y += acc[i][q].y;
+      S[(size_t)r * nb + c] = v;
+    }
+  }
+}
+
+// Column order of the inverse: in-place Gauss-Jordan with row interchanges
+// leaves S^{-1} with its columns permuted; replaying the interchanges in
+// reverse on the index list gives perm, and S^{-1}[:, c] = S[:, perm[c]].
+__global__ void k3_gj_perm(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works) {
+  const Slab3 p = slabs[blockIdx.z];
+  const Slab3Work w = works[blockIdx.z];
+  if (threadIdx.x != 0) return;
+  for (int c = 0; c < p.nb; ++c) w.perm[c] = c;
+  for (int c = p.nb - 1; c >= 0; --c) {
+    const int q = w.piv[c];
+    const int t = w.perm[c];
+    w.perm[c] = w.perm[q];
+    w.perm[q] = t;
+  }
+}
+
+// Sp = S^{-1} (float64, for the next block) and F_j = S^{-1} in the working precision
+template <typename T>
+__global__ void k3_gj_store(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int j,
+                            C<T>* const* __restrict__ factors) {
+  const Slab3 p = slabs[blockIdx.z];
+  const Slab3Work w = works[blockIdx.z];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (c >= p.nb || r >= p.nb) return;
+  const double2 v = w.S[(size_t)r * p.nb + w.perm[c]];
+  w.Sp[(size_t)r * p.nb + c] = v;
+  factors[blockIdx.z][((size_t)j * p.nb + r) * p.nb + c] = mk<T>((T)v.x, (T)v.y);
+}
+
+// Apply-time coefficients of slab z: cbc [L][2][nb][9] (B_j, then C_j, by
+// (d1, d3)), and the couplings to the neighbouring slabs: cm [L][L][9] from
+// the rows of line lo to line lo - 1 (k > 0), cp from the rows of line hi to
+// line hi + 1 (k < l - 1), by (d2, d3).
+template <typename T>
+__global__ void k3_apply_coefs(Stencil3 S, const Slab3* __restrict__ slabs, C<T>* const* __restrict__ cbc,
+                               C<T>* const* __restrict__ cm, C<T>* const* __restrict__ cpl) {
+  const Slab3 p = slabs[blockIdx.z];
+  const int L = S.L, b = S.b;
+  const size_t per = (size_t)p.nb * 9;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx < (size_t)L * 2 * per) {
+    const int j = (int)(idx / (2 * per)), side = (int)((idx / per) % 2);
+    const int r = (int)((idx % per) / 9), o9 = (int)(idx % 9);
+    const int a = r / L, e3 = r % L;
+    const double2 v = sub3_coef(S, p, a, j, e3, (o9 / 3) * 9 + (side ? 6 : 0) + o9 % 3);
+    cbc[blockIdx.z][idx] = mk<T>((T)v.x, (T)v.y);
+  }
+  if (idx < (size_t)L * L * 9) {
+    const int e2 = (int)(idx / ((size_t)L * 9)), e3 = (int)((idx / 9) % L), o9 = (int)(idx % 9);
+    const int d2 = o9 / 3 - 1, d3 = o9 % 3 - 1;
+    const bool in = e2 + d2 >= 0 && e2 + d2 < L && e3 + d3 >= 0 && e3 + d3 < L;
+    if (cm[blockIdx.z]) {
+      const double2 v = in ? h3_coef(S, p.lo, e2 - b, e3 - b, 0 * 9 + o9) : make_double2(0.0, 0.0);
+      cm[blockIdx.z][idx] = mk<T>((T)v.x, (T)v.y);
+    }
+    if (cpl[blockIdx.z]) {
+      const double2 v = in ? h3_coef(S, p.hi, e2 - b, e3 - b, 2 * 9 + o9) : make_double2(0.0, 0.0);
+      cpl[blockIdx.z][idx] = mk<T>((T)v.x, (T)v.y);
+    }
+  }
+}
+
+// ---- slab solves -------------------------------------------------------------
+
+// z_j = r_j - B_j y_{j-1}: r_j from the source lines (D part), minus the
+// coupling to line lo - 1 on the first line of D (mode 1), plus the coupling
+// to line hi + 1 on the last line (mode 2)
+template <typename T>
+__global__ void k3_zf(Slab3Apply<T> A, int j) {
+  const Slab3 p = A.p;
+  const int L = A.L, nb = p.nb;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nb * A.nrhs) return;
+  const int rhs = idx / nb, c = idx % nb, a = c / L, e3 = c % L;
+  C<T> v = mk<T>(0, 0);
+  if (a >= p.naux && A.src) v = A.src[rhs * A.src_rs + ((size_t)(a - p.naux) * L + j) * L + e3];
+  if ((A.cmode == 1 && a == p.naux) || (A.cmode == 2 && a == p.t - 1)) {
+    const C<T>* cf = (A.cmode == 1 ? A.cm : A.cp) + ((size_t)j * L + e3) * 9;
+    const C<T>* cu = A.cu + rhs * A.cu_rs;
+    C<T> s = mk<T>(0, 0);
+    for (int o9 = 0; o9 < 9; ++o9) {
+      const int f2 = j + o9 / 3 - 1, f3 = e3 + o9 % 3 - 1;
+      if (f2 < 0 || f2 >= L || f3 < 0 || f3 >= L) continue;
+      s = cadd<T>(s, cmul<T>(cf[o9], cu[(size_t)f2 * L + f3]));
+    }
+    v = A.cmode == 1 ? csub<T>(v, s) : cadd<T>(v, s);
+  }
+  if (j > 0) {
+    const C<T>* cf = A.cbc + ((size_t)(2 * j) * nb + c) * 9;
+    const C<T>* y = A.Y + ((size_t)rhs * L + (j - 1)) * nb;
+    for (int o9 = 0; o9 < 9; ++o9) {
+      const int a2 = a + o9 / 3 - 1, f3 = e3 + o9 % 3 - 1;
+      if (a2 < 0 || a2 >= p.t || f3 < 0 || f3 >= L) continue;
+      v = csub<T>(v, cmul<T>(cf[o9], y[a2 * L + f3]));
+    }
+  }
+  A.z[(size_t)rhs * nb + c] = v;
+}
+
+// z = C_j x_{j+1}; when j + 1 is the last block, its D part goes to dst
+template <typename T>
+__global__ void k3_zb(Slab3Apply<T> A, int j) {
+  const Slab3 p = A.p;
+  const int L = A.L, nb = p.nb;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= nb * A.nrhs) return;
+  const int rhs = idx / nb, c = idx % nb, a = c / L, e3 = c % L;
+  const C<T>* cf = A.cbc + ((size_t)(2 * j + 1) * nb + c) * 9;
+  const C<T>* x = A.Y + ((size_t)rhs * L + (j + 1)) * nb;
+  C<T> v = mk<T>(0, 0);
+  for (int o9 = 0; o9 < 9; ++o9) {
+    const int a2 = a + o9 / 3 - 1, f3 = e3 + o9 % 3 - 1;
+    if (a2 < 0 || a2 >= p.t || f3 < 0 || f3 >= L) continue;
+    v = cadd<T>(v, cmul<T>(cf[o9], x[a2 * L + f3]));
+  }
+  A.z[(size_t)rhs * nb + c] = v;
+  if (j + 1 == L - 1 && a >= p.naux) {
+    C<T>* d = A.dst + rhs * A.dst_rs + ((size_t)(a - p.naux) * L + (L - 1)) * L + e3;
+    *d = A.dop ? csub<T>(*d, x[c]) : x[c];
+  }
+}
+
+// Y_j = F_j z (sub = 0) or Y_j -= F_j z (sub = 1) for the right-hand sides
+// [r0, r0 + rc); one wave per row, z staged in LDS; with out, the D part of
+// the result also goes to dst
+template <typename T, int KC>
+__global__ __launch_bounds__(256) void k3_gemv(Slab3Apply<T> A, int j, int sub, int out, int r0, int rc) {
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* zl = reinterpret_cast<C<T>*>(smem_raw);
+  const Slab3 p = A.p;
+  const int L = A.L, nb = p.nb;
+  for (int i = threadIdx.x; i < rc * nb; i += blockDim.x) zl[i] = A.z[(size_t)(r0 + i / nb) * nb + i % nb];
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+  const int r = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (r >= nb) return;
+  const C<T>* row = A.F + ((size_t)j * nb + r) * nb;
+  T ax[KC], ay[KC];
+#pragma unroll
+  for (int q = 0; q < KC; ++q) ax[q] = ay[q] = T(0);
+#pragma unroll 4
+  for (int c = lane; c < nb; c += 64) {
+    const C<T> f = row[c];
+#pragma unroll
+    for (int q = 0; q < KC; ++q) {
+      if (q < rc) {
+        const C<T> zv = zl[q * nb + c];
+        ax[q] += f.x * zv.x - f.y * zv.y;
+        ay[q] += f.x * zv.y + f.y * zv.x;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < KC; ++q)
+    for (int off = 32; off > 0; off >>= 1) {
+      ax[q] += __shfl_xor(ax[q], off);
+      ay[q] += __shfl_xor(ay[q], off);
+    }
+  if (lane < rc) {
+    T vx = 0, vy = 0;
+#pragma unroll
+    for (int q = 0; q < KC; ++q)
+      if (q == lane) vx = ax[q], vy = ay[q];
+    const int rhs = r0 + lane;
+    C<T>* y = A.Y + ((size_t)rhs * L + j) * nb + r;
+    C<T> v = mk<T>(vx, vy);
+    if (sub) v = csub<T>(*y, v);
+    *y = v;
+    const int a = r / L, e3 = r % L;
+    if (out && a >= p.naux) {
+      C<T>* d = A.dst + rhs * A.dst_rs + ((size_t)(a - p.naux) * L + j) * L + e3;
+      *d = A.dop ? csub<T>(*d, v) : v;
+    }
+  }
+}
+
+}  // namespace
+
+// ---- launchers -----------------------------------------------------------------
+
+template <typename T>
+hipError_t launch3_apply_Q(const Stencil3& S, const C<T>* r, int nrhs, C<T>* f, hipStream_t st) {
+  const size_t tot = (size_t)S.L * S.L * S.L * nrhs;
+  hipLaunchKernelGGL(k3_apply_Q<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, S, r, nrhs, f);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch3_apply_H(const Stencil3& S, const C<T>* u, int nrhs, C<T>* y, hipStream_t st) {
+  const size_t tot = (size_t)S.L * S.L * S.L * nrhs;
+  hipLaunchKernelGGL(k3_apply_H<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, S, u, nrhs, y);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch3_extract(const C<T>* u, int n, int b, int nrhs, C<T>* z, hipStream_t st) {
+  const size_t tot = (size_t)n * n * n * nrhs;
+  hipLaunchKernelGGL(k3_extract<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, u, n, b, nrhs, z);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch3_factor(const Stencil3& S, const Slab3* slabs, const Slab3Work* works, int nslab, int maxnb,
+                          C<T>* const* factors, int* status, hipStream_t st) {
+  const int L = S.L;
+  for (int j = 0; j < L; ++j) {
+    hipLaunchKernelGGL(k3_coefs, dim3((maxnb * 9 + 255) / 256, 1, nslab), dim3(256), 0, st, S, slabs, works, j);
+    const dim3 gm((maxnb + 255) / 256, maxnb, nslab);
+    if (j > 0) hipLaunchKernelGGL(k3_schur_w, gm, dim3(256), 0, st, slabs, works, L);
+    hipLaunchKernelGGL(k3_schur_s, gm, dim3(256), 0, st, slabs, works, L, j);
+    for (int k0 = 0; k0 < maxnb; k0 += kGjPanel) {
+      hipLaunchKernelGGL(k3_gj_panel, dim3(1, 1, nslab), dim3(kGjThreads), 0, st, slabs, works, k0, status);
+      hipLaunchKernelGGL(k3_gj_swap, dim3((maxnb + 255) / 256, 1, nslab), dim3(256), 0, st, slabs, works, k0);
+      hipLaunchKernelGGL(k3_gj_update, dim3((maxnb + 63) / 64, (maxnb + 63) / 64, nslab), dim3(256), 0, st, slabs,
+                         works, k0);
+    }
+    hipLaunchKernelGGL(k3_gj_perm, dim3(1, 1, nslab), dim3(64), 0, st, slabs, works);
+    hipLaunchKernelGGL(k3_gj_store<T>, gm, dim3(256), 0, st, slabs, works, j, factors);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <typename T>
+hipError_t launch3_apply_coefs(const Stencil3& S, const Slab3* slabs, int nslab, int maxnb, C<T>* const* cbc,
+                               C<T>* const* cm, C<T>* const* cpl, hipStream_t st) {
+  const size_t tot = std::max((size_t)S.L * 2 * maxnb * 9, (size_t)S.L * S.L * 9);
+  hipLaunchKernelGGL(k3_apply_coefs<T>, dim3((unsigned)((tot + 255) / 256), 1, nslab), dim3(256), 0, st, S, slabs,
+                     cbc, cm, cpl);
+  return hipGetLastError();
+}
+
+size_t slab3_gemv_lds(int nb, int rc, size_t cs) { return (size_t)rc * nb * cs; }
+
+template <typename T>
+hipError_t launch3_slab_solve(const Slab3Apply<T>& A, hipStream_t st) {
+  const int nb = A.p.nb, L = A.L;
+  const int zt = (nb * A.nrhs + 255) / 256;
+  // right-hand sides per product: as many as 64 KB of LDS hold, at most 8
+  int kc = (int)std::min<size_t>(8, 65536 / ((size_t)nb * sizeof(C<T>)));
+  if (kc < 1) kc = 1;
+  const dim3 gg((nb + 3) / 4);
+  {
+    const size_t lds = slab3_gemv_lds(nb, std::min(kc, A.nrhs), sizeof(C<T>));
+    if (lds > 163840) return hipErrorInvalidValue;
+    if (lds > 65536) {
+      hipError_t e;
+      if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gemv<T, 1>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+        return e;
+    }
+  }
+  auto gemv = [&](int j, int sub, int out) {
+    for (int r0 = 0; r0 < A.nrhs; r0 += kc) {
+      const int rc = std::min(kc, A.nrhs - r0);
+      const size_t lds = slab3_gemv_lds(nb, rc, sizeof(C<T>));
+      if (rc > 4)
+        hipLaunchKernelGGL((k3_gemv<T, 8>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+      else if (rc > 1)
+        hipLaunchKernelGGL((k3_gemv<T, 4>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+      else
+        hipLaunchKernelGGL((k3_gemv<T, 1>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+    }
+  };
+  for (int j = 0; j < L; ++j) {
+    hipLaunchKernelGGL(k3_zf<T>, dim3(zt), dim3(256), 0, st, A, j);
+    gemv(j, 0, 0);
+  }
+  for (int j = L - 2; j >= 0; --j) {
+    hipLaunchKernelGGL(k3_zb<T>, dim3(zt), dim3(256), 0, st, A, j);
+    gemv(j, 1, 1);
+  }
+  return hipGetLastError();
+}
+
+#define LSW_SLAB3_INST(T)                                                                                         \
+  template hipError_t launch3_apply_Q<T>(const Stencil3&, const C<T>*, int, C<T>*, hipStream_t);                  \
+  template hipError_t launch3_apply_H<T>(const Stencil3&, const C<T>*, int, C<T>*, hipStream_t);                  \
+  template hipError_t launch3_extract<T>(const C<T>*, int, int, int, C<T>*, hipStream_t);                         \
+  template hipError_t launch3_factor<T>(const Stencil3&, const Slab3*, const Slab3Work*, int, int, C<T>* const*, \
+                                        int*, hipStream_t);                                                      \
+  template hipError_t launch3_apply_coefs<T>(const Stencil3&, const Slab3*, int, int, C<T>* const*,               \
+                                             C<T>* const*, C<T>* const*, hipStream_t);                            \
+  template hipError_t launch3_slab_solve<T>(const Slab3Apply<T>&, hipStream_t);
+LSW_SLAB3_INST(double)
+LSW_SLAB3_INST(float)
+
+}  // namespace lsw

@@ -1,0 +1,157 @@
+"""GPU parity of the 3D method (Sec. 3.1 with Sec. 2.2-2.3 and Algorithms 1-2
+in d = 3): stencils through the handle, Q and H, single slab solves, the
+sweeping preconditioner and whole solves, against the oracle (SuperLU slab
+factorizations, scipy FFTs), through the C ABI.
+
+Tolerances as in 2D: float64 applies and slab solves 1e-11 relative (the
+library inverts the dense Schur complements of each slab block, the oracle
+factors the sparse slab; both are backward stable, the slabs are
+well-conditioned); complex64 1e-4; whole solves per the same protocol
+(iteration counts within one, the true residual below the tolerance, and
+float64 solutions equal to 1e-10 at equal iteration counts).
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def to_dev(x, dtype=torch.complex128):
+    return torch.as_tensor(np.ascontiguousarray(x)).to(device="cuda", dtype=dtype)
+
+
+def crand(rng, shape):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+CASES3 = {
+    # name: (n, omega/2pi, b, w); slabs of 6, 6 and 11 lines (nb = 102..187,
+    # a ragged last Gauss-Jordan panel)
+    "small": (9, 1.0, 3, 3),
+    # four slabs, the last of 13 lines (nb = 325)
+    "ragged": (15, 2.0, 4, 4),
+}
+
+
+@pytest.fixture(scope="module", params=list(CASES3))
+def case3(request):
+    from paper_1705_09443_amd import LSSolver
+    n, ppw, b, w = CASES3[request.param]
+    omega = 2 * math.pi * ppw
+    m = workloads.gaussian_bump_medium(n, 3, 5, (0.25, 0.75), (0.05, 0.1), (-0.3, 0.3), seed=n)
+    say(f"[{request.param}] oracle setup 3D n={n} b={b} w={w}")
+    ref = oracle.OracleSolver(3, n, omega, m, b, w)
+    md = torch.as_tensor(m).cuda()
+    say(f"[{request.param}] library setup fp64 and mixed")
+    g64 = LSSolver(md, omega, pml_width=b, layer_thickness=w, precision="fp64", schedule="sequential")
+    g32 = LSSolver(md, omega, pml_width=b, layer_thickness=w, precision="mixed", schedule="sequential")
+    yield request.param, n, omega, m, ref, g64, g32
+    g64.close()
+    g32.close()
+
+
+def test_tables_through_handle(case3):
+    name, n, omega, m, ref, g64, g32 = case3
+    assert g64.dim == 3 and g64.nslices == ref.sweep.nslices
+    al, be, gg, ga = g64.stencils()
+    assert np.abs(al - ref.alpha).max() < 1e-12
+    assert np.abs(be - ref.beta).max() < 1e-12 * np.abs(ref.beta).max()
+    for key, g in ref.system.gamma_by_class.items():
+        assert np.abs(gg[key] - g).max() < 1e-12
+    for (q, c2, c3, ks), g in ref.sweep.aux_gamma.items():
+        assert np.abs(ga[q, c2, c3, ks] - g).max() < 1e-12
+
+
+def test_apply_A_Q_H(case3):
+    name, n, omega, m, ref, g64, g32 = case3
+    rng = np.random.default_rng(11)
+    s = ref.system
+    x = crand(rng, (2, n, n, n))
+    u = crand(rng, (2,) + (s.L,) * 3)
+    say(f"[{name}] apply A, Q, H")
+    yA = g64.apply_A(to_dev(x)).cpu().numpy()
+    f = g64.apply_Q(to_dev(x)).cpu().numpy()
+    y = g64.apply_H(to_dev(u)).cpu().numpy()
+    f32 = g32.apply_Q(to_dev(x, torch.complex64)).cpu().numpy()
+    y32 = g32.apply_H(to_dev(u, torch.complex64)).cpu().numpy()
+    for j in range(2):
+        assert rel(yA[j], ref.op.apply_A(x[j])) <= 1e-12
+        assert rel(f[j].reshape(-1), s.apply_Q(x[j])) <= 1e-12
+        assert rel(y[j].reshape(-1), s.apply_H(u[j].reshape(-1))) <= 1e-12
+        assert rel(f32[j].reshape(-1), s.apply_Q(x[j])) <= 1e-6
+        assert rel(y32[j].reshape(-1), s.apply_H(u[j].reshape(-1))) <= 1e-6
+
+
+def test_slab_solves(case3):
+    name, n, omega, m, ref, g64, g32 = case3
+    sw = ref.sweep
+    L = sw.s.L
+    rng = np.random.default_rng(12)
+    for k in range(sw.nslices):
+        lo, hi, naux = g64.slice_bounds(k)
+        assert (lo, hi) == sw.bounds[k]
+        lines = hi - lo + 1
+        v = crand(rng, (3, lines, L, L))
+        say(f"[{name}] slab_solve k={k} lines={lines} aux={naux}")
+        w = g64.slice_solve(k, to_dev(v)).cpu().numpy()
+        w32 = g32.slice_solve(k, to_dev(v, torch.complex64)).cpu().numpy()
+        for j in range(3):
+            ref_w = sw.solve_slice(k, v[j].reshape(-1))
+            e64, e32 = rel(w[j].reshape(-1), ref_w), rel(w32[j].reshape(-1), ref_w)
+            assert e64 <= 1e-11, (k, j, e64)
+            assert e32 <= 1e-4, (k, j, e32)
+
+
+def test_preconditioner(case3):
+    name, n, omega, m, ref, g64, g32 = case3
+    rng = np.random.default_rng(13)
+    r = crand(rng, (3, n, n, n))
+    say(f"[{name}] apply_precond fp64, fp32")
+    z = g64.apply_precond(to_dev(r)).cpu().numpy()
+    z32 = g32.apply_precond(to_dev(r, torch.complex64)).cpu().numpy()
+    for j in range(3):
+        zr = ref.precondition(r[j])
+        e64, e32 = rel(z[j], zr), rel(z32[j], zr)
+        say(f"[{name}]   rhs {j}: fp64 {e64:.2e} fp32 {e32:.2e}")
+        assert e64 <= 1e-11
+        assert e32 <= 1e-4
+
+
+def test_solves(case3):
+    name, n, omega, m, ref, g64, g32 = case3
+    uinc = workloads.plane_waves(n, 3, omega, workloads.angle_directions(2, 3, full_turn=False))
+    say(f"[{name}] ls_solve fp64 and mixed, 2 rhs")
+    u, info = g64.solve(to_dev(uinc), "incident", 1e-8)
+    u32, info32 = g32.solve(to_dev(uinc), "incident", 1e-8)
+    u, u32 = u.cpu().numpy(), u32.cpu().numpy()
+    for j in range(uinc.shape[0]):
+        g = ref.op.rhs_incident(uinc[j])
+        res = ref.solve_rhs(g, 1e-8)
+        say(f"[{name}]   rhs {j}: iterations lib {info[j].iterations} / {info32[j].iterations}, "
+            f"oracle {res.iterations}")
+        assert abs(info[j].iterations - res.iterations) <= 1
+        assert info[j].converged and info32[j].converged
+        assert rel(ref.op.apply_A(u[j]), g) <= 1.01e-8
+        assert rel(ref.op.apply_A(u32[j]), g) <= 1.01e-8
+        if info[j].iterations == res.iterations:
+            assert rel(u[j], res.x) <= 1e-10
+        assert abs(info32[j].iterations - res.iterations) <= 2

@@ -125,3 +125,23 @@ def test_green3_rejects_bad_arguments():
     for n, om in [(0, 1.0), (1024, 1.0), (1, 0.0), (1, float("nan"))]:
         assert lib.ls_host_green3(n, om, buf.ctypes.data) == _lib.LS_E_INVALID
     assert lib.ls_host_green3(1, 1.0, None) == _lib.LS_E_INVALID
+
+
+@pytest.mark.parametrize("n,ppw,b,w", [(9, 1.0, 3, 3), (15, 2.0, 4, 4)])
+def test_tables3_match_oracle(n, ppw, b, w):
+    """3D setup (Sec. 3.1): alpha, beta to 1e-12 of the oracle's (numpy QR +
+    LAPACK SVD), gamma of every global and used auxiliary class to 1e-12
+    after the phase normalisation (reading G5), the sample map bit-exact."""
+    from paper_1705_09443_amd import host_tables3
+    omega = 2 * math.pi * ppw
+    m = workloads.gaussian_bump_medium(n, 3, 5, (0.25, 0.75), (0.05, 0.1), (-0.3, 0.3), seed=1)
+    got = host_tables3(m, omega, b, w)
+    ref = oracle.OracleSolver(3, n, omega, m, b, w)
+    assert np.abs(got["alpha"] - ref.alpha).max() < 1e-12
+    assert np.abs(got["beta"] - ref.beta).max() < 1e-12 * np.abs(ref.beta).max()
+    for key, g in ref.system.gamma_by_class.items():
+        assert np.abs(got["gamma"][key] - g).max() < 1e-12, key
+    assert len(ref.sweep.aux_gamma) > 0
+    for (q, c2, c3, ks), g in ref.sweep.aux_gamma.items():
+        assert np.abs(got["aux"][q, c2, c3, ks] - g).max() < 1e-12
+    assert np.array_equal(got["kmap"].reshape(-1), FrequencySamples(m, omega, n).index(ref.system.m_ext))
