@@ -586,33 +586,55 @@ ls_status apply_P3(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
     Timed tm(h, kKQ, nb);
     LSW_HIP_TRY(launch3_apply_Q<T>(S, r, nb, f, h->st));
   }
-  for (int k = 0; k < nl; ++k) {
-    Timed tm(h, kKSlices, nb);
-    const Slab3& p = s.slabs[k];
-    Slab3Apply<T> a = slab3_args<T>(h, k, nb);
-    a.src = f + (size_t)(p.lo + b) * LL;
-    a.src_rs = E;
-    if (k > 0) {
-      a.cu = u + (size_t)(p.lo - 1 + b) * LL;
-      a.cu_rs = E;
-      a.cmode = 1;
+  // the sweep (f -> u on handle-owned buffers) as one graph per batch size
+  // and precision: several thousand dependent launches per apply
+  const std::pair<int, int> key(-(nb + 1), (int)sizeof(T));
+  auto it = h->graphs.find(key);
+  hipGraphExec_t ge = nullptr;
+  if (it != h->graphs.end()) {
+    ge = it->second;
+  } else {
+    if (!h->cst) LSW_HIP_TRY(hipStreamCreateWithFlags(&h->cst, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    LSW_HIP_TRY(hipStreamBeginCapture(h->cst, hipStreamCaptureModeThreadLocal));
+    hipError_t ce = hipSuccess;
+    for (int k = 0; k < nl && ce == hipSuccess; ++k) {
+      const Slab3& p = s.slabs[k];
+      Slab3Apply<T> a = slab3_args<T>(h, k, nb);
+      a.src = f + (size_t)(p.lo + b) * LL;
+      a.src_rs = E;
+      if (k > 0) {
+        a.cu = u + (size_t)(p.lo - 1 + b) * LL;
+        a.cu_rs = E;
+        a.cmode = 1;
+      }
+      a.dst = u + (size_t)(p.lo + b) * LL;
+      a.dst_rs = E;
+      a.dop = 0;
+      ce = launch3_slab_solve<T>(a, h->cst);
     }
-    a.dst = u + (size_t)(p.lo + b) * LL;
-    a.dst_rs = E;
-    a.dop = 0;
-    LSW_HIP_TRY(launch3_slab_solve<T>(a, h->st));
+    for (int k = nl - 2; k >= 0 && ce == hipSuccess; --k) {
+      const Slab3& p = s.slabs[k];
+      Slab3Apply<T> a = slab3_args<T>(h, k, nb);
+      a.cu = u + (size_t)(p.hi + 1 + b) * LL;
+      a.cu_rs = E;
+      a.cmode = 2;
+      a.dst = u + (size_t)(p.lo + b) * LL;
+      a.dst_rs = E;
+      a.dop = 1;
+      ce = launch3_slab_solve<T>(a, h->cst);
+    }
+    const hipError_t ee = hipStreamEndCapture(h->cst, &g);
+    LSW_HIP_TRY(ce);
+    LSW_HIP_TRY(ee);
+    const hipError_t ie = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    LSW_HIP_TRY(ie);
+    h->graphs.emplace(key, ge);
   }
-  for (int k = nl - 2; k >= 0; --k) {
+  {
     Timed tm(h, kKSlices, nb);
-    const Slab3& p = s.slabs[k];
-    Slab3Apply<T> a = slab3_args<T>(h, k, nb);
-    a.cu = u + (size_t)(p.hi + 1 + b) * LL;
-    a.cu_rs = E;
-    a.cmode = 2;
-    a.dst = u + (size_t)(p.lo + b) * LL;
-    a.dst_rs = E;
-    a.dop = 1;
-    LSW_HIP_TRY(launch3_slab_solve<T>(a, h->st));
+    LSW_HIP_TRY(hipGraphLaunch(ge, h->st));
   }
   {
     Timed tm(h, kKExtract, nb);

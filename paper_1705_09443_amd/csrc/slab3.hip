@@ -200,68 +200,81 @@ __global__ void k3_schur_s(const Slab3* __restrict__ slabs, const Slab3Work* __r
 constexpr int kGjPanel = 32;
 constexpr int kGjThreads = 512;
 
+// Largest candidate (modulus squared bv at row br) over the workgroup, the
+// first row on ties; every thread gets the row.
+__device__ int gj_pick(double bv, int br, double* best_v, int* best_r, int* pick) {
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off);
+    const int orr = __shfl_xor(br, off);
+    if (ov > bv || (ov == bv && orr < br)) {
+      bv = ov;
+      br = orr;
+    }
+  }
+  if (lane == 0) {
+    best_v[wid] = bv;
+    best_r[wid] = br;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double v = best_v[0];
+    int rr = best_r[0];
+    for (int q = 1; q < kGjThreads / 64; ++q)
+      if (best_v[q] > v || (best_v[q] == v && best_r[q] < rr)) {
+        v = best_v[q];
+        rr = best_r[q];
+      }
+    *pick = rr;
+  }
+  __syncthreads();
+  return *pick;
+}
+
 __global__ __launch_bounds__(kGjThreads) void k3_gj_panel(const Slab3* __restrict__ slabs,
                                                           const Slab3Work* __restrict__ works, int k0,
                                                           int* __restrict__ status) {
+  constexpr int RU = 8;                      // rows in flight per thread
+  constexpr int RG = kGjThreads / kGjPanel;  // row groups
   const Slab3 p = slabs[blockIdx.z];
   const Slab3Work w = works[blockIdx.z];
   const int nb = p.nb;
   if (k0 >= nb) return;
   const int kp = min(kGjPanel, nb - k0);
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = threadIdx.x;
   __shared__ double best_v[kGjThreads / 64];
   __shared__ int best_r[kGjThreads / 64];
-  __shared__ int prow_s;
+  __shared__ int pick_s;
   __shared__ double2 prow[kGjPanel];
   double2* S = w.S;
-  for (int pp = 0; pp < kp; ++pp) {
-    const int cp = k0 + pp;
-    // 1. pivot: largest modulus in column cp among rows cp..nb-1 (first on ties)
+  // pivot of the first panel column: largest modulus among rows k0..nb-1
+  int pr;
+  {
     double bv = -1.0;
     int br = nb;
-    for (int r = cp + tid; r < nb; r += kGjThreads) {
-      const double2 v = S[(size_t)r * nb + cp];
+    for (int r = k0 + tid; r < nb; r += kGjThreads) {
+      const double2 v = S[(size_t)r * nb + k0];
       const double m2 = v.x * v.x + v.y * v.y;
       if (m2 > bv) {
         bv = m2;
         br = r;
       }
     }
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ov = __shfl_xor(bv, off);
-      const int orr = __shfl_xor(br, off);
-      if (ov > bv || (ov == bv && orr < br)) {
-        bv = ov;
-        br = orr;
-      }
-    }
-    if (lane == 0) {
-      best_v[wid] = bv;
-      best_r[wid] = br;
-    }
-    __syncthreads();
-    if (tid == 0) {
-      double v = best_v[0];
-      int rr = best_r[0];
-      for (int q = 1; q < kGjThreads / 64; ++q)
-        if (best_v[q] > v || (best_v[q] == v && best_r[q] < rr)) {
-          v = best_v[q];
-          rr = best_r[q];
-        }
-      if (rr >= nb) rr = cp;
-      prow_s = rr;
-      w.piv[cp] = rr;
-    }
-    __syncthreads();
-    const int pr = prow_s;
-    // 2. swap rows cp and pr in the panel columns
+    pr = gj_pick(bv, br, best_v, best_r, &pick_s);
+  }
+  const int c = tid % kGjPanel, rg = tid / kGjPanel;
+  for (int pp = 0; pp < kp; ++pp) {
+    const int cp = k0 + pp;
+    if (pr >= nb) pr = cp;
+    if (tid == 0) w.piv[cp] = pr;
+    // swap rows cp and pr in the panel columns
     if (pr != cp && tid < kp) {
-      const double2 a = S[(size_t)cp * nb + k0 + tid], c = S[(size_t)pr * nb + k0 + tid];
-      S[(size_t)cp * nb + k0 + tid] = c;
+      const double2 a = S[(size_t)cp * nb + k0 + tid], b = S[(size_t)pr * nb + k0 + tid];
+      S[(size_t)cp * nb + k0 + tid] = b;
       S[(size_t)pr * nb + k0 + tid] = a;
     }
     __syncthreads();
-    // 3. pivot row: scaled by 1/pivot, its own entry replaced by 1/pivot
+    // pivot row: scaled by 1/pivot, its own entry replaced by 1/pivot
     if (tid < kp) {
       const double2 pv = S[(size_t)cp * nb + cp];
       const double d = pv.x * pv.x + pv.y * pv.y;
@@ -276,25 +289,44 @@ __global__ __launch_bounds__(kGjThreads) void k3_gj_panel(const Slab3* __restric
     }
     __syncthreads();
     if (tid < kp) S[(size_t)cp * nb + k0 + tid] = prow[tid];
-    // 4. eliminate column cp from every other row (panel columns only); the
-    //    32 lanes of a row sit in one wave, which reads the row's column-cp
-    //    entry before its lane pp overwrites it
-    {
-      const int c = tid & 31, rg = tid >> 5;
-      if (c < kp) {
-        const double2 pc = prow[c];
-        for (int r = rg; r < nb; r += kGjThreads / 32) {
-          if (r == cp) continue;
-          const double2 f = S[(size_t)r * nb + cp];
-          double2 v = c == pp ? make_double2(0.0, 0.0) : S[(size_t)r * nb + k0 + c];
-          const double2 t = zmul(f, pc);
-          v.x -= t.x;
-          v.y -= t.y;
-          S[(size_t)r * nb + k0 + c] = v;
+    // eliminate column cp from every other row (panel columns); the lanes
+    // of a row share a wave, which loads the row's column-cp entry before its
+    // lane pp overwrites it. Lane pp + 1 tracks the next pivot candidate.
+    double bv = -1.0;
+    int br = nb;
+    if (c < kp) {
+      const double2 pc = prow[c];
+      const bool track = c == pp + 1;
+      for (int rb = rg; rb < nb; rb += RG * RU) {
+        double2 f[RU], v[RU];
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          const int r = rb + RG * u;
+          const bool ok = r < nb && r != cp;
+          f[u] = ok ? S[(size_t)r * nb + cp] : make_double2(0.0, 0.0);
+          v[u] = ok && c != pp ? S[(size_t)r * nb + k0 + c] : make_double2(0.0, 0.0);
+        }
+#pragma unroll
+        for (int u = 0; u < RU; ++u) {
+          const int r = rb + RG * u;
+          if (r >= nb || r == cp) continue;
+          const double2 t = zmul(f[u], pc);
+          const double2 nv = make_double2(v[u].x - t.x, v[u].y - t.y);
+          S[(size_t)r * nb + k0 + c] = nv;
+          if (track && r > cp) {
+            const double m2 = nv.x * nv.x + nv.y * nv.y;
+            if (m2 > bv) {
+              bv = m2;
+              br = r;
+            }
+          }
         }
       }
     }
-    __syncthreads();
+    if (pp + 1 < kp)
+      pr = gj_pick(bv, br, best_v, best_r, &pick_s);
+    else
+      __syncthreads();
   }
 }
 
@@ -473,13 +505,22 @@ __global__ void k3_zf(Slab3Apply<T> A, int j) {
     v = A.cmode == 1 ? csub<T>(v, s) : cadd<T>(v, s);
   }
   if (j > 0) {
+    // all 18 loads issued together: out-of-range neighbours read entry c and
+    // are masked (their coefficients are zero as well)
     const C<T>* cf = A.cbc + ((size_t)(2 * j) * nb + c) * 9;
     const C<T>* y = A.Y + ((size_t)rhs * L + (j - 1)) * nb;
+    C<T> cv[9], yv[9];
+    bool ok[9];
+#pragma unroll
     for (int o9 = 0; o9 < 9; ++o9) {
       const int a2 = a + o9 / 3 - 1, f3 = e3 + o9 % 3 - 1;
-      if (a2 < 0 || a2 >= p.t || f3 < 0 || f3 >= L) continue;
-      v = csub<T>(v, cmul<T>(cf[o9], y[a2 * L + f3]));
+      ok[o9] = a2 >= 0 && a2 < p.t && f3 >= 0 && f3 < L;
+      cv[o9] = cf[o9];
+      yv[o9] = y[ok[o9] ? a2 * L + f3 : c];
     }
+#pragma unroll
+    for (int o9 = 0; o9 < 9; ++o9)
+      if (ok[o9]) v = csub<T>(v, cmul<T>(cv[o9], yv[o9]));
   }
   A.z[(size_t)rhs * nb + c] = v;
 }
@@ -495,11 +536,18 @@ __global__ void k3_zb(Slab3Apply<T> A, int j) {
   const C<T>* cf = A.cbc + ((size_t)(2 * j + 1) * nb + c) * 9;
   const C<T>* x = A.Y + ((size_t)rhs * L + (j + 1)) * nb;
   C<T> v = mk<T>(0, 0);
+  C<T> cv[9], xv[9];
+  bool ok[9];
+#pragma unroll
   for (int o9 = 0; o9 < 9; ++o9) {
     const int a2 = a + o9 / 3 - 1, f3 = e3 + o9 % 3 - 1;
-    if (a2 < 0 || a2 >= p.t || f3 < 0 || f3 >= L) continue;
-    v = cadd<T>(v, cmul<T>(cf[o9], x[a2 * L + f3]));
+    ok[o9] = a2 >= 0 && a2 < p.t && f3 >= 0 && f3 < L;
+    cv[o9] = cf[o9];
+    xv[o9] = x[ok[o9] ? a2 * L + f3 : c];
   }
+#pragma unroll
+  for (int o9 = 0; o9 < 9; ++o9)
+    if (ok[o9]) v = cadd<T>(v, cmul<T>(cv[o9], xv[o9]));
   A.z[(size_t)rhs * nb + c] = v;
   if (j + 1 == L - 1 && a >= p.naux) {
     C<T>* d = A.dst + rhs * A.dst_rs + ((size_t)(a - p.naux) * L + (L - 1)) * L + e3;
@@ -508,47 +556,124 @@ __global__ void k3_zb(Slab3Apply<T> A, int j) {
 }
 
 // Y_j = F_j z (sub = 0) or Y_j -= F_j z (sub = 1) for the right-hand sides
-// [r0, r0 + rc); one wave per row, z staged in LDS; with out, the D part of
-// the result also goes to dst
-template <typename T, int KC>
+// [r0, r0 + rc); z staged in LDS ([rhs][nb]); each wave takes R consecutive
+// rows, its lanes W consecutive columns per load (W = 2: 16-byte loads of two
+// complex64), U loads per row in flight; with out, the D part of the result
+// also goes to dst
+template <int W, typename T>
+struct WVec;
+template <>
+struct WVec<1, float> {
+  using type = float2;
+};
+template <>
+struct WVec<2, float> {
+  using type = float4;
+};
+template <>
+struct WVec<1, double> {
+  using type = double2;
+};
+
+template <typename T, int KC, int W, int R>
 __global__ __launch_bounds__(256) void k3_gemv(Slab3Apply<T> A, int j, int sub, int out, int r0, int rc) {
+  // U vectors per row and lane in flight: one chunk covers a row of up to
+  // 64 U W complex, so the matrix loads are all issued before z is staged
+  constexpr int U = 16;
+  using V = typename WVec<W, T>::type;
   extern __shared__ unsigned char smem_raw[];
   C<T>* zl = reinterpret_cast<C<T>*>(smem_raw);
   const Slab3 p = A.p;
   const int L = A.L, nb = p.nb;
-  for (int i = threadIdx.x; i < rc * nb; i += blockDim.x) zl[i] = A.z[(size_t)(r0 + i / nb) * nb + i % nb];
-  __syncthreads();
   const int lane = threadIdx.x & 63;
-  const int r = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (r >= nb) return;
-  const C<T>* row = A.F + ((size_t)j * nb + r) * nb;
-  T ax[KC], ay[KC];
+  const int rb = (blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * R;
+  const V* rows[R];
 #pragma unroll
-  for (int q = 0; q < KC; ++q) ax[q] = ay[q] = T(0);
-#pragma unroll 4
-  for (int c = lane; c < nb; c += 64) {
-    const C<T> f = row[c];
+  for (int q = 0; q < R; ++q)
+    rows[q] = reinterpret_cast<const V*>(A.F + ((size_t)j * nb + min(rb + q, nb - 1)) * nb);
+  const int nv = nb / W;  // vectors per row (nb is a multiple of W)
+  V f[R][U];
+  auto load_chunk = [&](int v0) {
 #pragma unroll
-    for (int q = 0; q < KC; ++q) {
-      if (q < rc) {
-        const C<T> zv = zl[q * nb + c];
-        ax[q] += f.x * zv.x - f.y * zv.y;
-        ay[q] += f.x * zv.y + f.y * zv.x;
+    for (int u = 0; u < U; ++u) {
+      const int v = v0 + 64 * u;
+#pragma unroll
+      for (int q = 0; q < R; ++q) f[q][u] = rows[q][v < nv ? v : 0];
+    }
+  };
+  // z of right-hand sides r0 .. r0 + rc - 1 is one contiguous run of rc nb
+  // complex (nz vectors): its first ZU vectors per thread are loaded before
+  // the matrix chunk, so that they return first (memory counters complete in
+  // order) and are in LDS while the matrix loads are still in flight; the
+  // barrier orders LDS only
+  constexpr int ZU = 16;
+  const V* zs = reinterpret_cast<const V*>(A.z + (size_t)r0 * nb);
+  V* zd = reinterpret_cast<V*>(zl);
+  const int nz = rc * nb / W;
+  V tz[ZU];
+#pragma unroll
+  for (int u = 0; u < ZU; ++u) {
+    const int i = threadIdx.x + u * blockDim.x;
+    tz[u] = zs[i < nz ? i : 0];
+  }
+  load_chunk(lane);
+#pragma unroll
+  for (int u = 0; u < ZU; ++u) {
+    const int i = threadIdx.x + u * blockDim.x;
+    if (i < nz) zd[i] = tz[u];
+  }
+  for (int i = threadIdx.x + ZU * blockDim.x; i < nz; i += blockDim.x) zd[i] = zs[i];
+  lds_barrier();
+  if (rb >= nb) return;
+  T ax[R][KC], ay[R][KC];
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int k = 0; k < KC; ++k) ax[q][k] = ay[q][k] = T(0);
+  for (int v0 = lane; v0 < nv; v0 += 64 * U) {
+    if (v0 != lane) load_chunk(v0);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int v = v0 + 64 * u;
+      if (v >= nv) break;
+#pragma unroll
+      for (int w = 0; w < W; ++w) {
+        const int c = v * W + w;
+#pragma unroll
+        for (int k = 0; k < KC; ++k) {
+          if (k < rc) {
+            const C<T> zv = zl[k * nb + c];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+              const T fx = w == 0 ? reinterpret_cast<const T*>(&f[q][u])[0] : reinterpret_cast<const T*>(&f[q][u])[2];
+              const T fy = w == 0 ? reinterpret_cast<const T*>(&f[q][u])[1] : reinterpret_cast<const T*>(&f[q][u])[3];
+              ax[q][k] += fx * zv.x - fy * zv.y;
+              ay[q][k] += fx * zv.y + fy * zv.x;
+            }
+          }
+        }
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < KC; ++q)
-    for (int off = 32; off > 0; off >>= 1) {
-      ax[q] += __shfl_xor(ax[q], off);
-      ay[q] += __shfl_xor(ay[q], off);
-    }
-  if (lane < rc) {
-    T vx = 0, vy = 0;
+  for (int q = 0; q < R; ++q)
 #pragma unroll
-    for (int q = 0; q < KC; ++q)
-      if (q == lane) vx = ax[q], vy = ay[q];
-    const int rhs = r0 + lane;
+    for (int k = 0; k < KC; ++k)
+      for (int off = 32; off > 0; off >>= 1) {
+        ax[q][k] += __shfl_xor(ax[q][k], off);
+        ay[q][k] += __shfl_xor(ay[q][k], off);
+      }
+  // lane q * KC + k stores row rb + q, right-hand side r0 + k
+  T vx = 0, vy = 0;
+#pragma unroll
+  for (int q = 0; q < R; ++q)
+#pragma unroll
+    for (int k = 0; k < KC; ++k)
+      if (lane == q * KC + k) vx = ax[q][k], vy = ay[q][k];
+  const int q = lane / KC, k = lane % KC;
+  const int r = rb + q;
+  if (q < R && k < rc && r < nb) {
+    const int rhs = r0 + k;
     C<T>* y = A.Y + ((size_t)rhs * L + j) * nb + r;
     C<T> v = mk<T>(vx, vy);
     if (sub) v = csub<T>(*y, v);
@@ -620,6 +745,16 @@ hipError_t launch3_apply_coefs(const Stencil3& S, const Slab3* slabs, int nslab,
 
 size_t slab3_gemv_lds(int nb, int rc, size_t cs) { return (size_t)rc * nb * cs; }
 
+// complex per load of the wide matrix-vector form (complex64 only)
+template <typename T>
+struct WideW {
+  static constexpr int value = 1;
+};
+template <>
+struct WideW<float> {
+  static constexpr int value = 2;
+};
+
 template <typename T>
 hipError_t launch3_slab_solve(const Slab3Apply<T>& A, hipStream_t st) {
   const int nb = A.p.nb, L = A.L;
@@ -627,13 +762,17 @@ hipError_t launch3_slab_solve(const Slab3Apply<T>& A, hipStream_t st) {
   // right-hand sides per product: as many as 64 KB of LDS hold, at most 8
   int kc = (int)std::min<size_t>(8, 65536 / ((size_t)nb * sizeof(C<T>)));
   if (kc < 1) kc = 1;
-  const dim3 gg((nb + 3) / 4);
+  // complex64 with an even block size: two rows per wave, 16-byte loads;
+  // otherwise one row per wave and one complex per load
+  const bool wide = sizeof(T) == 4 && nb % 2 == 0;
+  const int rpb = wide ? 8 : 4;  // rows per workgroup
+  const dim3 gg((nb + rpb - 1) / rpb);
   {
     const size_t lds = slab3_gemv_lds(nb, std::min(kc, A.nrhs), sizeof(C<T>));
     if (lds > 163840) return hipErrorInvalidValue;
     if (lds > 65536) {
       hipError_t e;
-      if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gemv<T, 1>),
+      if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gemv<T, 1, 1, 1>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
         return e;
     }
@@ -642,12 +781,21 @@ hipError_t launch3_slab_solve(const Slab3Apply<T>& A, hipStream_t st) {
     for (int r0 = 0; r0 < A.nrhs; r0 += kc) {
       const int rc = std::min(kc, A.nrhs - r0);
       const size_t lds = slab3_gemv_lds(nb, rc, sizeof(C<T>));
-      if (rc > 4)
-        hipLaunchKernelGGL((k3_gemv<T, 8>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
-      else if (rc > 1)
-        hipLaunchKernelGGL((k3_gemv<T, 4>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
-      else
-        hipLaunchKernelGGL((k3_gemv<T, 1>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+      if (wide) {
+        if (rc > 4)
+          hipLaunchKernelGGL((k3_gemv<T, 8, WideW<T>::value, 2>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+        else if (rc > 1)
+          hipLaunchKernelGGL((k3_gemv<T, 4, WideW<T>::value, 2>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+        else
+          hipLaunchKernelGGL((k3_gemv<T, 1, WideW<T>::value, 2>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+      } else {
+        if (rc > 4)
+          hipLaunchKernelGGL((k3_gemv<T, 8, 1, 1>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+        else if (rc > 1)
+          hipLaunchKernelGGL((k3_gemv<T, 4, 1, 1>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+        else
+          hipLaunchKernelGGL((k3_gemv<T, 1, 1, 1>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+      }
     }
   };
   for (int j = 0; j < L; ++j) {
