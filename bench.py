@@ -14,6 +14,11 @@ choice per batch size timed on the device for this batch; --no-autotune keeps
 the workload's w = 4 and the default kernels); its setup time includes the
 tuning.
 
+A 3D leg (object "c3") times the 127^3 workload the same way: four incident
+waves, mixed precision, the slab-by-slab sweep captured as one graph; its
+roofline is the sweep's factor bytes per apply over the apply's event-timed
+duration.
+
 Prints one JSON line. Besides the contract fields it carries the float64
 form (same medium, one wave), per-kind kernel times from HIP events recorded
 on the library's stream inside the timed region, the roofline of the
@@ -47,6 +52,8 @@ def parse():
     p.add_argument("--nrhs", type=int, default=None)
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-3d", action="store_true", help="skip the 3D leg (127^3, four waves, mixed)")
+    p.add_argument("--steps-3d", type=int, default=2)
     p.add_argument("--no-autotune", action="store_true",
                    help="batched leg at the workload's w and the default kernels instead of autotuned ones")
     p.add_argument("--copy-gib", type=float, default=0.0,
@@ -146,6 +153,68 @@ def roofline(solver, prof, cbytes: int, n: int):
     out.update({"kernel": dominant, "avg_launch_ms": avg_ms, "mean_columns_per_launch": cols,
                 "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
                 "flop_per_byte": intensity})
+    return out
+
+
+def sweep3_bytes(solver, cbytes: int) -> float:
+    """Factor bytes one 3D preconditioner apply streams: every slab solve reads
+    S_j^{-1} (nb x nb complex) once per block in its forward pass (L blocks)
+    and once more in its backward pass (L - 1 blocks); the sweep solves every
+    slab forward and every slab but the last backward."""
+    L, b, w, n = solver.L, solver.pml_width, solver.layer_thickness, solver.n
+    total = 0.0
+    for k in range(solver.nslices):
+        lo, hi, naux = solver.slice_bounds(k)
+        nb = (hi - lo + 1 + naux) * L
+        per = (2 * L - 1) * nb * nb * cbytes
+        total += per * (2 if k < solver.nslices - 1 else 1)
+    return total
+
+
+def leg_3d(args, dev):
+    """The 3D workload (127^3, 16 bumps, four plane waves, mixed precision,
+    b = 8, w = 4): setup timed apart, then whole solves; the sweep's roofline
+    from its event-timed graph launches."""
+    import torch
+    import workloads
+    from paper_1705_09443_amd import LSSolver
+    wl = workloads.workload("C3")
+    n = wl.n
+    m = torch.as_tensor(wl.medium_array(), device=dev)
+    uinc = torch.as_tensor(wl.incident(), device=dev)
+    t0 = time.perf_counter()
+    s3 = LSSolver(m, wl.omega, wl.pml_width, wl.layer_thickness, precision="mixed", restart=wl.restart,
+                  schedule="sequential")
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    print(f"[bench] 3D setup {setup:.2f} s (n={n}, slabs={s3.nslices})", file=sys.stderr, flush=True)
+    u, info = s3.solve(uinc, "incident", wl.tol)  # warm-up (graph capture)
+    torch.cuda.synchronize()
+    s3.profile(True)
+    t0 = time.perf_counter()
+    for i in range(args.steps_3d):
+        u, info = s3.solve(uinc, "incident", wl.tol)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps_3d
+    s3.profile(False)
+    prof = s3.profile_read()
+    assert all(x.converged and x.rel_residual <= wl.tol for x in info), "a 3D right-hand side did not converge"
+    launches, total_ms, cols = prof["slice_solves"]
+    avg_ms = total_ms / launches
+    nbytes = sweep3_bytes(s3, 8)
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    out = {"value": wl.nrhs * n ** 3 / t, "unit": "unknowns*RHS/s", "ms_per_step": t * 1e3,
+           "steps": args.steps_3d, "setup_s": setup,
+           "iterations": [x.iterations for x in info],
+           "config": {"workload": (f"3D {n}^3, omega=2pi*{wl.ppw_omega:g}, 16 Gaussian bumps (seed 0), "
+                                   f"{wl.nrhs} plane waves, mixed precision, b={wl.pml_width}, "
+                                   f"w={wl.layer_thickness}, restart {wl.restart}, tol {wl.tol}"),
+                      "n": n, "nrhs": wl.nrhs},
+           "kernels": {k: {"launches": v[0], "avg_ms": v[1] / v[0]} for k, v in prof.items()},
+           "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                        "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sweep (slab solves)",
+                        "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": nbytes}}
+    s3.close()
     return out
 
 
@@ -303,6 +372,11 @@ def main():
         out["ratio_vs_fp64"] = value / v64
         f64.close()
         del f64
+
+    # ---- 3D ----
+    if not args.no_3d:
+        out["c3"] = leg_3d(args, dev)
+        print(f"[bench] 3D solve {out['c3']['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
 
     # ---- CPU oracle on a bounded sample ----
     if not args.no_cpu:

@@ -108,6 +108,19 @@ void ls_default_options(ls_options* opts);
  */
 ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int pml_width,
                    int layer_thickness, const ls_options* opts, ls_handle** out);
+/*
+ * dim = 3 (Sec. 3.1): m_dev is [n][n][n] and every grid array of the entry
+ * points below gains the third axis ([n][n][n] interior, [L][L][L] extended,
+ * slice arrays [lines][L][L]); the slices are slabs of planes i1. Each slab
+ * subproblem is block tridiagonal along i2 with blocks of (slab lines) x L
+ * unknowns; setup forms S_j^{-1} of every block by blocked Gauss-Jordan with
+ * partial pivoting in float64 (kept in the handle's precision:
+ * L (t L)^2 complex per slab of t lines) and the sweep is applied slab by
+ * slab (Algorithm 2; sweep_schedule is ignored). The 3D operator is the FFT
+ * convolution of ls_op3_create. Not available in 3D: autotune (must be 0),
+ * layer_thickness <= 0, ls_set_kernels. n <= 1023, slabs of at most 32 lines.
+ * A slab whose block has a zero pivot gives LS_E_SINGULAR.
+ */
 
 /*
  * Solve (I + omega^2 K M) u = g for a batch of right-hand sides with
@@ -142,7 +155,8 @@ void ls_destroy(ls_handle* h);
 /* Message of the last failure on the calling thread ("" if none). */
 const char* ls_last_error(void);
 
-/* ---- Per-operator entry points (parity tests and benchmarks) ---- */
+/* ---- Per-operator entry points (parity tests and benchmarks) ----
+ * Shapes are given for dim = 2; in 3D each grid axis list gains one more n or L. */
 
 /* y = (I + omega^2 K M) x on the interior grid (eq. LS_d_c). x, y: [nrhs][n][n]. */
 ls_status ls_apply_A(ls_handle* h, const void* x_dev, int nrhs, void* y_dev, int precision);
@@ -187,11 +201,12 @@ ls_status ls_get_slice(const ls_handle* h, int slice, int* first_line, int* last
  *                          b+1..2b for i = n+2..n+1+b; entry (0,0) unused
  *   aux_host               b x (2b+1) x freq_samples x 9 complex, auxiliary PML
  *                          stencils by (depth q, class c2, sample k)
- * Any pointer may be NULL. */
+ * Any pointer may be NULL. In 3D the layouts of ls_host_tables3 (27 entries
+ * per stencil, gamma by (c1, c2, c3), aux by (q, c2, c3, sample)). */
 ls_status ls_get_stencils(const ls_handle* h, double* alpha_host, double* beta_host,
                           double* gamma_host, double* aux_host);
 
-/* Sample index k* for every extended-grid point, int32 [L][L] on the host. */
+/* Sample index k* for every extended-grid point, int32 [L][L] ([L][L][L] in 3D) on the host. */
 ls_status ls_get_sample_map(const ls_handle* h, int* kmap_host);
 
 /* ---- Autotuning (batching form: layer thickness and kernel choice) ----
