@@ -108,3 +108,17 @@ def test_sparse_system_discretises_ls_equation():
     ud = np.linalg.solve(dense_A(s.op.table, n, 2, wl.omega, s.m), g.reshape(-1)).reshape(g.shape)
     ut = s.system.restrict(spla.spsolve(s.system.H.tocsc(), s.system.apply_Q(g)))
     assert np.linalg.norm(ut - ud) < 1e-2 * np.linalg.norm(ud)
+
+
+def test_exact_T_sweep_is_block_elimination_3d():
+    # three slabs of the extended cube (Sec. 3.1): with the exact Schur
+    # complements the slab-by-slab sweep is block Gaussian elimination
+    n = 7
+    system, m, omega = small_case(n=n, d=3, b=3)
+    sw = Sweep(system, 3, m, exact=True)
+    assert sw.nslices == 3
+    rng = np.random.default_rng(21)
+    f = rng.standard_normal(system.npts) + 1j * rng.standard_normal(system.npts)
+    ref = spla.spsolve(system.H.tocsc(), f)
+    got = sw.sweep(f)
+    assert np.linalg.norm(got - ref) <= 1e-11 * np.linalg.norm(ref)
