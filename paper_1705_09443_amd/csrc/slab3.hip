@@ -575,107 +575,101 @@ struct WVec<1, double> {
   using type = double2;
 };
 
-template <typename T, int KC, int W, int R>
-__global__ __launch_bounds__(256) void k3_gemv(Slab3Apply<T> A, int j, int sub, int out, int r0, int rc) {
-  // U vectors per row and lane in flight: one chunk covers a row of up to
-  // 64 U W complex, so the matrix loads are all issued before z is staged
-  constexpr int U = 16;
+// kernel geometry: 16 waves per workgroup, kGemvRows rows, each row split
+// into two column halves (one wave each); partial sums meet in LDS
+constexpr int kGemvRows = 8;
+constexpr int kGemvThreads = 1024;
+
+template <typename T, int KC, int W>
+__global__ __launch_bounds__(kGemvThreads) void k3_gemv(Slab3Apply<T> A, int j, int sub, int out, int r0, int rc) {
+  constexpr int RW = kGemvRows, H = kGemvThreads / 64 / RW, U = 8, ZU = 4;
   using V = typename WVec<W, T>::type;
   extern __shared__ unsigned char smem_raw[];
   C<T>* zl = reinterpret_cast<C<T>*>(smem_raw);
+  __shared__ C<T> part[kGemvThreads / 64][KC];
   const Slab3 p = A.p;
   const int L = A.L, nb = p.nb;
-  const int lane = threadIdx.x & 63;
-  const int rb = (blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6)) * R;
-  const V* rows[R];
-#pragma unroll
-  for (int q = 0; q < R; ++q)
-    rows[q] = reinterpret_cast<const V*>(A.F + ((size_t)j * nb + min(rb + q, nb - 1)) * nb);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int rr = wv % RW, hh = wv / RW;
+  const int row = blockIdx.x * RW + rr;
+  const V* rp = reinterpret_cast<const V*>(A.F + ((size_t)j * nb + min(row, nb - 1)) * nb);
   const int nv = nb / W;  // vectors per row (nb is a multiple of W)
-  V f[R][U];
-  auto load_chunk = [&](int v0) {
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int v = v0 + 64 * u;
-#pragma unroll
-      for (int q = 0; q < R; ++q) f[q][u] = rows[q][v < nv ? v : 0];
-    }
-  };
-  // z of right-hand sides r0 .. r0 + rc - 1 is one contiguous run of rc nb
-  // complex (nz vectors): its first ZU vectors per thread are loaded before
-  // the matrix chunk, so that they return first (memory counters complete in
-  // order) and are in LDS while the matrix loads are still in flight; the
-  // barrier orders LDS only
-  constexpr int ZU = 16;
+  const int nvh = (nv + H - 1) / H, vb = min(hh * nvh, nv), ve = min(nv, vb + nvh);
+  // z of right-hand sides r0 .. r0 + rc - 1 (one contiguous run of nz
+  // vectors): the first ZU per thread are requested before the matrix, so
+  // that they return first; the barrier orders LDS only, the matrix loads
+  // stay in flight across it
   const V* zs = reinterpret_cast<const V*>(A.z + (size_t)r0 * nb);
   V* zd = reinterpret_cast<V*>(zl);
   const int nz = rc * nb / W;
   V tz[ZU];
 #pragma unroll
   for (int u = 0; u < ZU; ++u) {
-    const int i = threadIdx.x + u * blockDim.x;
+    const int i = threadIdx.x + u * kGemvThreads;
     tz[u] = zs[i < nz ? i : 0];
   }
-  load_chunk(lane);
+  V f[U];
+#pragma unroll
+  for (int u = 0; u < U; ++u) {
+    const int v = vb + lane + 64 * u;
+    f[u] = rp[v < ve ? v : 0];
+  }
 #pragma unroll
   for (int u = 0; u < ZU; ++u) {
-    const int i = threadIdx.x + u * blockDim.x;
+    const int i = threadIdx.x + u * kGemvThreads;
     if (i < nz) zd[i] = tz[u];
   }
-  for (int i = threadIdx.x + ZU * blockDim.x; i < nz; i += blockDim.x) zd[i] = zs[i];
+  for (int i = threadIdx.x + ZU * kGemvThreads; i < nz; i += kGemvThreads) zd[i] = zs[i];
   lds_barrier();
-  if (rb >= nb) return;
-  T ax[R][KC], ay[R][KC];
+  T ax[KC], ay[KC];
 #pragma unroll
-  for (int q = 0; q < R; ++q)
+  for (int k = 0; k < KC; ++k) ax[k] = ay[k] = T(0);
+  for (int v0 = vb + lane; v0 < ve; v0 += 64 * U) {
+    if (v0 != vb + lane) {
 #pragma unroll
-    for (int k = 0; k < KC; ++k) ax[q][k] = ay[q][k] = T(0);
-  for (int v0 = lane; v0 < nv; v0 += 64 * U) {
-    if (v0 != lane) load_chunk(v0);
+      for (int u = 0; u < U; ++u) {
+        const int v = v0 + 64 * u;
+        f[u] = rp[v < ve ? v : 0];
+      }
+    }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int v = v0 + 64 * u;
-      if (v >= nv) break;
+      if (v >= ve) break;
+      const T* fv = reinterpret_cast<const T*>(&f[u]);
 #pragma unroll
       for (int w = 0; w < W; ++w) {
         const int c = v * W + w;
+        const T fx = fv[2 * w], fy = fv[2 * w + 1];
 #pragma unroll
         for (int k = 0; k < KC; ++k) {
           if (k < rc) {
             const C<T> zv = zl[k * nb + c];
-#pragma unroll
-            for (int q = 0; q < R; ++q) {
-              const T fx = w == 0 ? reinterpret_cast<const T*>(&f[q][u])[0] : reinterpret_cast<const T*>(&f[q][u])[2];
-              const T fy = w == 0 ? reinterpret_cast<const T*>(&f[q][u])[1] : reinterpret_cast<const T*>(&f[q][u])[3];
-              ax[q][k] += fx * zv.x - fy * zv.y;
-              ay[q][k] += fx * zv.y + fy * zv.x;
-            }
+            ax[k] += fx * zv.x - fy * zv.y;
+            ay[k] += fx * zv.y + fy * zv.x;
           }
         }
       }
     }
   }
 #pragma unroll
-  for (int q = 0; q < R; ++q)
+  for (int k = 0; k < KC; ++k)
+    for (int off = 32; off > 0; off >>= 1) {
+      ax[k] += __shfl_xor(ax[k], off);
+      ay[k] += __shfl_xor(ay[k], off);
+    }
+  if (lane == 0) {
 #pragma unroll
-    for (int k = 0; k < KC; ++k)
-      for (int off = 32; off > 0; off >>= 1) {
-        ax[q][k] += __shfl_xor(ax[q][k], off);
-        ay[q][k] += __shfl_xor(ay[q][k], off);
-      }
-  // lane q * KC + k stores row rb + q, right-hand side r0 + k
-  T vx = 0, vy = 0;
-#pragma unroll
-  for (int q = 0; q < R; ++q)
-#pragma unroll
-    for (int k = 0; k < KC; ++k)
-      if (lane == q * KC + k) vx = ax[q][k], vy = ay[q][k];
-  const int q = lane / KC, k = lane % KC;
-  const int r = rb + q;
-  if (q < R && k < rc && r < nb) {
+    for (int k = 0; k < KC; ++k) part[wv][k] = mk<T>(ax[k], ay[k]);
+  }
+  __syncthreads();
+  // thread t < RW KC: row t / KC of the workgroup, right-hand side t % KC
+  const int t = threadIdx.x, q = t / KC, k = t % KC, r = blockIdx.x * RW + q;
+  if (t < RW * KC && k < rc && r < nb) {
+    C<T> v = part[q][k];
+    for (int h = 1; h < H; ++h) v = cadd<T>(v, part[h * RW + q][k]);
     const int rhs = r0 + k;
     C<T>* y = A.Y + ((size_t)rhs * L + j) * nb + r;
-    C<T> v = mk<T>(vx, vy);
     if (sub) v = csub<T>(*y, v);
     *y = v;
     const int a = r / L, e3 = r % L;
@@ -760,19 +754,23 @@ hipError_t launch3_slab_solve(const Slab3Apply<T>& A, hipStream_t st) {
   const int nb = A.p.nb, L = A.L;
   const int zt = (nb * A.nrhs + 255) / 256;
   // right-hand sides per product: as many as 64 KB of LDS hold, at most 8
-  int kc = (int)std::min<size_t>(8, 65536 / ((size_t)nb * sizeof(C<T>)));
+  // right-hand sides per product: as many as 60 KB of LDS hold (the kernel's
+  // static partial sums take the rest of the default 64 KB), at most 8
+  int kc = (int)std::min<size_t>(8, 61440 / ((size_t)nb * sizeof(C<T>)));
   if (kc < 1) kc = 1;
-  // complex64 with an even block size: two rows per wave, 16-byte loads;
-  // otherwise one row per wave and one complex per load
+  // complex64 with an even block size: 16-byte loads of two complex
   const bool wide = sizeof(T) == 4 && nb % 2 == 0;
-  const int rpb = wide ? 8 : 4;  // rows per workgroup
-  const dim3 gg((nb + rpb - 1) / rpb);
+  const dim3 gg((nb + kGemvRows - 1) / kGemvRows);
   {
+    // beyond 60 KB only single right-hand-side products run (kc = 1)
     const size_t lds = slab3_gemv_lds(nb, std::min(kc, A.nrhs), sizeof(C<T>));
-    if (lds > 163840) return hipErrorInvalidValue;
-    if (lds > 65536) {
+    if (lds + 2048 > 163840) return hipErrorInvalidValue;
+    if (lds > 61440) {
       hipError_t e;
-      if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gemv<T, 1, 1, 1>),
+      if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gemv<T, 1, 1>),
+                                   hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
+        return e;
+      if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gemv<T, 1, WideW<T>::value>),
                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds)) != hipSuccess)
         return e;
     }
@@ -783,18 +781,18 @@ hipError_t launch3_slab_solve(const Slab3Apply<T>& A, hipStream_t st) {
       const size_t lds = slab3_gemv_lds(nb, rc, sizeof(C<T>));
       if (wide) {
         if (rc > 4)
-          hipLaunchKernelGGL((k3_gemv<T, 8, WideW<T>::value, 2>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 8, WideW<T>::value>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
         else if (rc > 1)
-          hipLaunchKernelGGL((k3_gemv<T, 4, WideW<T>::value, 2>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 4, WideW<T>::value>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
         else
-          hipLaunchKernelGGL((k3_gemv<T, 1, WideW<T>::value, 2>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 1, WideW<T>::value>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
       } else {
         if (rc > 4)
-          hipLaunchKernelGGL((k3_gemv<T, 8, 1, 1>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 8, 1>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
         else if (rc > 1)
-          hipLaunchKernelGGL((k3_gemv<T, 4, 1, 1>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 4, 1>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
         else
-          hipLaunchKernelGGL((k3_gemv<T, 1, 1, 1>), gg, dim3(256), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 1, 1>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
       }
     }
   };
