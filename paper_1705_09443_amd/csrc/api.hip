@@ -369,7 +369,7 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
     LSW_ALLOC(h->fext, (size_t)nrhs * E * cs);
     LSW_ALLOC(h->uext, (size_t)nrhs * E * cs);
     LSW_ALLOC(s3.Y, (size_t)nrhs * h->L * s3.maxnb * cs);
-    LSW_ALLOC(s3.z, (size_t)nrhs * s3.maxnb * cs);
+    LSW_ALLOC(s3.z, (size_t)2 * nrhs * s3.maxnb * cs);
   } else {
     LSW_ALLOC(h->fftw64, fft_work_elems<double>(h->n, nrhs) * sizeof(double2));
     LSW_ALLOC(h->fftw32, fft_work_elems<float>(h->n, nrhs) * sizeof(float2));
@@ -1571,8 +1571,12 @@ ls_status factor3(ls_handle* h) {
   const int L = h->L, nl = (int)s.slabs.size();
   hipStream_t st = h->st;
   const Stencil3 S = stencil3(h);
-  std::vector<DBuf> wS(nl), wW(nl), wSp(nl), wXr(nl), wcf(nl), wpiv(nl), wperm(nl);
-  std::vector<Slab3Work> works(nl);
+  // two chains per slab (top and bottom), each with its own work arrays
+  const int ne = 2 * nl;
+  std::vector<DBuf> wS(ne), wW(ne), wSp(ne), wXr(ne), wcf(ne), wpiv(ne), wperm(ne);
+  std::vector<Slab3Work> works(ne);
+  std::vector<Slab3> eslabs(ne);
+  std::vector<C<T>*> eF(ne);
   s.F.resize(nl);
   s.cbc.resize(nl);
   s.cm.resize(nl);
@@ -1580,18 +1584,22 @@ ls_status factor3(ls_handle* h) {
   std::vector<C<T>*> Fp(nl), cbp(nl), cmp(nl, nullptr), cpp(nl, nullptr);
   for (int k = 0; k < nl; ++k) {
     const size_t nb = s.slabs[k].nb, nb2 = nb * nb;
-    LSW_ALLOC(wS[k], nb2 * sizeof(double2));
-    LSW_ALLOC(wW[k], nb2 * sizeof(double2));
-    LSW_ALLOC(wSp[k], nb2 * sizeof(double2));
-    LSW_ALLOC(wXr[k], 32 * nb * sizeof(double2));
-    LSW_ALLOC(wcf[k], 27 * nb * sizeof(double2));
-    LSW_ALLOC(wpiv[k], nb * sizeof(int));
-    LSW_ALLOC(wperm[k], nb * sizeof(int));
-    works[k] = {wS[k].as<double2>(), wW[k].as<double2>(), wSp[k].as<double2>(), wXr[k].as<double2>(),
-                wcf[k].as<double2>(), wpiv[k].as<int>(), wperm[k].as<int>()};
+    for (int e = 2 * k; e < 2 * k + 2; ++e) {
+      LSW_ALLOC(wS[e], nb2 * sizeof(double2));
+      LSW_ALLOC(wW[e], nb2 * sizeof(double2));
+      LSW_ALLOC(wSp[e], nb2 * sizeof(double2));
+      LSW_ALLOC(wXr[e], 32 * nb * sizeof(double2));
+      LSW_ALLOC(wcf[e], 27 * nb * sizeof(double2));
+      LSW_ALLOC(wpiv[e], nb * sizeof(int));
+      LSW_ALLOC(wperm[e], nb * sizeof(int));
+      works[e] = {wS[e].as<double2>(), wW[e].as<double2>(), wSp[e].as<double2>(), wXr[e].as<double2>(),
+                  wcf[e].as<double2>(), wpiv[e].as<int>(), wperm[e].as<int>(), e == 2 * k ? +1 : -1};
+      eslabs[e] = s.slabs[k];
+    }
     LSW_ALLOC(s.F[k], (size_t)L * nb2 * sizeof(C<T>));
     LSW_ALLOC(s.cbc[k], (size_t)L * 2 * nb * 9 * sizeof(C<T>));
     Fp[k] = s.F[k].as<C<T>>();
+    eF[2 * k] = eF[2 * k + 1] = Fp[k];
     cbp[k] = s.cbc[k].as<C<T>>();
     if (k > 0) {
       LSW_ALLOC(s.cm[k], (size_t)L * L * 9 * sizeof(C<T>));
@@ -1602,19 +1610,21 @@ ls_status factor3(ls_handle* h) {
       cpp[k] = s.cp[k].as<C<T>>();
     }
   }
-  DBuf slabs_d, works_d, F_d, cb_d, cm_d, cp_d, status;
+  DBuf slabs_d, eslabs_d, works_d, F_d, cb_d, cm_d, cp_d, status;
   LSW_ALLOC(slabs_d, nl * sizeof(Slab3));
-  LSW_ALLOC(works_d, nl * sizeof(Slab3Work));
-  LSW_ALLOC(F_d, nl * sizeof(void*));
+  LSW_ALLOC(eslabs_d, ne * sizeof(Slab3));
+  LSW_ALLOC(works_d, ne * sizeof(Slab3Work));
+  LSW_ALLOC(F_d, ne * sizeof(void*));
   LSW_ALLOC(cb_d, nl * sizeof(void*));
   LSW_ALLOC(cm_d, nl * sizeof(void*));
   LSW_ALLOC(cp_d, nl * sizeof(void*));
   LSW_ALLOC(status, sizeof(int));
-  if (upload(h, slabs_d, s.slabs) != LS_OK || upload(h, works_d, works) != LS_OK || upload(h, F_d, Fp) != LS_OK ||
+  if (upload(h, slabs_d, s.slabs) != LS_OK || upload(h, eslabs_d, eslabs) != LS_OK ||
+      upload(h, works_d, works) != LS_OK || upload(h, F_d, eF) != LS_OK ||
       upload(h, cb_d, cbp) != LS_OK || upload(h, cm_d, cmp) != LS_OK || upload(h, cp_d, cpp) != LS_OK)
     return LS_E_DEVICE;
   LSW_HIP_TRY(hipMemsetAsync(status.p, 0, sizeof(int), st));
-  LSW_HIP_TRY(launch3_factor<T>(S, slabs_d.as<Slab3>(), works_d.as<Slab3Work>(), nl, s.maxnb,
+  LSW_HIP_TRY(launch3_factor<T>(S, eslabs_d.as<Slab3>(), works_d.as<Slab3Work>(), ne, s.maxnb,
                                 F_d.as<C<T>* const>(), status.as<int>(), st));
   LSW_HIP_TRY(launch3_apply_coefs<T>(S, slabs_d.as<Slab3>(), nl, s.maxnb, cb_d.as<C<T>* const>(),
                                      cm_d.as<C<T>* const>(), cp_d.as<C<T>* const>(), st));

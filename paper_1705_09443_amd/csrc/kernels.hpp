@@ -283,6 +283,14 @@ struct Slab3Work {
   double2* cf;  // [3][nb][9] block coefficients A_j, B_j, C_{j-1}
   int* piv;     // [nb] row interchanges
   int* perm;    // [nb] column order of the inverse
+  int dir;      // +1: the slab's top chain (blocks 0 .. m-1), -1: its bottom chain (L-1 .. m+1)
+};
+// The blocks one launch of a slab solve works on (the two chains' current
+// blocks, or the middle block alone) and the coupling terms each takes.
+struct Slab3Step {
+  int nt;
+  int j[2];
+  int terms[2];
 };
 // One slab solve: factors, coefficients, work vectors, and where its
 // right-hand side comes from and its D part goes to.
@@ -295,7 +303,7 @@ struct Slab3Apply {
   const C<T>* cm;   // [L][L][9] coupling of line lo to lo - 1
   const C<T>* cp;   // [L][L][9] coupling of line hi to hi + 1
   C<T>* Y;          // [nrhs][L][nb]
-  C<T>* z;          // [nrhs][nb]
+  C<T>* z;          // [2][nrhs][nb], one per block of a step
   const C<T>* src;  // D part of the right-hand side, (rhs, aD, e2, e3) at rhs*src_rs + (aD L + e2) L + e3; may be null
   size_t src_rs;
   const C<T>* cu;   // line lo - 1 (cmode 1) or hi + 1 (cmode 2) of the sweep field, rhs stride cu_rs
@@ -311,10 +319,13 @@ template <typename T>
 hipError_t launch3_apply_H(const Stencil3& S, const C<T>* u, int nrhs, C<T>* y, hipStream_t st);
 template <typename T>
 hipError_t launch3_extract(const C<T>* u, int n, int b, int nrhs, C<T>* z, hipStream_t st);
-// S_j^{-1} of every block of nslab slabs (device arrays slabs, works;
-// factors: device array of per-slab factor bases); status > 0: zero pivot in slab status-1
+// S_j^{-1} of every block of every slab by two-ended elimination (top and
+// bottom chain per slab toward the middle block L/2). nentries = 2 x slabs:
+// entry 2k is slab k's top chain, 2k+1 its bottom chain (device arrays slabs,
+// works, factors: the slab's descriptor, work and factor base per entry);
+// status > 0: zero pivot in slab status-1
 template <typename T>
-hipError_t launch3_factor(const Stencil3& S, const Slab3* slabs, const Slab3Work* works, int nslab, int maxnb,
+hipError_t launch3_factor(const Stencil3& S, const Slab3* slabs, const Slab3Work* works, int nentries, int maxnb,
                           C<T>* const* factors, int* status, hipStream_t st);
 template <typename T>
 hipError_t launch3_apply_coefs(const Stencil3& S, const Slab3* slabs, int nslab, int maxnb, C<T>* const* cbc,

@@ -130,13 +130,50 @@ __global__ void k3_extract(const C<T>* __restrict__ u, int n, int b, int nrhs, C
   z[idx] = u[rhs * (size_t)L * L * L + ((size_t)(i1 + b) * L + (i2 + b)) * L + (i3 + b)];
 }
 
-// ---- factorization (float64, all slabs of a batch at once; blockIdx.z = slab) ----
+// ---- factorization (float64, two chains per slab, all slabs at once) ----
+//
+// Two-ended block elimination: for the middle block m = L/2 the top chain
+// eliminates blocks 0 .. m-1 downwards (S_j = A_j - B_j S_{j-1}^{-1} C_{j-1}),
+// the bottom chain blocks L-1 .. m+1 upwards (S_j = A_j - C_j S_{j+1}^{-1}
+// B_{j+1}), and the middle block takes both Schur terms. Work entry e is the
+// top (dir = +1) or bottom (dir = -1) chain of a slab; blockIdx.z selects the
+// entry estride z + eoff.
+struct ChainStep {
+  int s;        // chain step: top chains take block s, bottom chains L - 1 - s
+  int m;        // middle block
+  int middle;   // 1: every entry takes the middle block m
+  int estride;  // entry = blockIdx.z * estride + eoff
+  int eoff;
+};
 
-// cf[0]: A_j (d2 = 0), cf[1]: B_j (d2 = -1), cf[2]: C_{j-1} (d2 = +1, rows of
-// block j - 1), each [nb][9] by (d1, d3)
-__global__ void k3_coefs(Stencil3 S, const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int j) {
-  const Slab3 p = slabs[blockIdx.z];
-  const Slab3Work w = works[blockIdx.z];
+__device__ inline int cs_entry(const ChainStep& cs) { return blockIdx.z * cs.estride + cs.eoff; }
+
+// block of the entry at this step; false when its chain is done
+__device__ inline bool cs_block(const ChainStep& cs, int dir, int L, int* j) {
+  if (cs.middle) {
+    *j = cs.m;
+    return true;
+  }
+  if (dir > 0) {
+    *j = cs.s;
+    return cs.s < cs.m;
+  }
+  *j = L - 1 - cs.s;
+  return cs.s < L - 1 - cs.m;
+}
+
+__device__ inline bool cs_has_prev(const ChainStep& cs) { return cs.middle || cs.s > 0; }
+
+// cf[0]: A_j (d2 = 0); cf[1]: the rows of block j at d2 = -dir (coupling to
+// the chain's previous block j - dir); cf[2]: the rows of block j - dir at
+// d2 = +dir (coupling back to j); each [nb][9] by (d1, d3)
+__global__ void k3_coefs(Stencil3 S, const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works,
+                         ChainStep cs) {
+  const int e = cs_entry(cs);
+  const Slab3 p = slabs[e];
+  const Slab3Work w = works[e];
+  int j;
+  if (!cs_block(cs, w.dir, S.L, &j)) return;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= p.nb * 9) return;
   const int r = idx / 9, o9 = idx % 9, a = r / S.L, e3 = r % S.L;
@@ -144,15 +181,20 @@ __global__ void k3_coefs(Stencil3 S, const Slab3* __restrict__ slabs, const Slab
   const size_t s3 = (size_t)p.nb * 9;
   w.cf[idx] = sub3_coef(S, p, a, j, e3, (d1 + 1) * 9 + 3 + (d3 + 1));
   const double2 zero = make_double2(0.0, 0.0);
-  w.cf[s3 + idx] = j > 0 ? sub3_coef(S, p, a, j, e3, (d1 + 1) * 9 + 0 + (d3 + 1)) : zero;
-  w.cf[2 * s3 + idx] = j > 0 ? sub3_coef(S, p, a, j - 1, e3, (d1 + 1) * 9 + 6 + (d3 + 1)) : zero;
+  const bool prev = cs_has_prev(cs);
+  w.cf[s3 + idx] = prev ? sub3_coef(S, p, a, j, e3, (d1 + 1) * 9 + (1 - w.dir) * 3 + (d3 + 1)) : zero;
+  w.cf[2 * s3 + idx] = prev ? sub3_coef(S, p, a, j - w.dir, e3, (d1 + 1) * 9 + (1 + w.dir) * 3 + (d3 + 1)) : zero;
 }
 
-// W = S_{j-1}^{-1} C_{j-1}: column c = (a, e3) of C_{j-1} has its entries in
-// rows (a - d1, e3 - d3) of block j - 1, coefficient cf[2][row][(d1, d3)]
-__global__ void k3_schur_w(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int L) {
-  const Slab3 p = slabs[blockIdx.z];
-  const Slab3Work w = works[blockIdx.z];
+// W = Sp cf2: column c = (a, e3) of the coupling back to j has its entries in
+// rows (a - d1, e3 - d3) of the previous block, coefficient cf[2][row][(d1, d3)]
+__global__ void k3_schur_w(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int L,
+                           ChainStep cs) {
+  const int e = cs_entry(cs);
+  const Slab3 p = slabs[e];
+  const Slab3Work w = works[e];
+  int j;
+  if (!cs_block(cs, w.dir, L, &j) || !cs_has_prev(cs)) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
   if (c >= p.nb || r >= p.nb) return;
   const int a = c / L, e3 = c % L;
@@ -170,18 +212,22 @@ __global__ void k3_schur_w(const Slab3* __restrict__ slabs, const Slab3Work* __r
   w.W[(size_t)r * p.nb + c] = acc;
 }
 
-// S = A_j - B_j W (j > 0) or A_j; row r = (a, e3) of B_j has its entries in
-// rows (a + d1, e3 + d3) of W
-__global__ void k3_schur_s(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int L, int j) {
-  const Slab3 p = slabs[blockIdx.z];
-  const Slab3Work w = works[blockIdx.z];
+// S = A_j - cf1 W (with a previous block) or A_j; row r = (a, e3) of the
+// coupling cf1 has its entries in rows (a + d1, e3 + d3) of W
+__global__ void k3_schur_s(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int L,
+                           ChainStep cs) {
+  const int e = cs_entry(cs);
+  const Slab3 p = slabs[e];
+  const Slab3Work w = works[e];
+  int j;
+  if (!cs_block(cs, w.dir, L, &j)) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
   if (c >= p.nb || r >= p.nb) return;
   const int a = r / L, e3 = r % L, ca = c / L, c3 = c % L;
   double2 v = make_double2(0.0, 0.0);
   const int d1 = ca - a, d3 = c3 - e3;
   if (d1 >= -1 && d1 <= 1 && d3 >= -1 && d3 <= 1) v = w.cf[(size_t)r * 9 + (d1 + 1) * 3 + (d3 + 1)];
-  if (j > 0) {
+  if (cs_has_prev(cs)) {
     const double2* cb = w.cf + (size_t)p.nb * 9 + (size_t)r * 9;
     for (int o9 = 0; o9 < 9; ++o9) {
       const int a2 = a + o9 / 3 - 1, f3 = e3 + o9 % 3 - 1;
@@ -190,6 +236,28 @@ __global__ void k3_schur_s(const Slab3* __restrict__ slabs, const Slab3Work* __r
       v.x -= t.x;
       v.y -= t.y;
     }
+  }
+  w.S[(size_t)r * p.nb + c] = v;
+}
+
+// middle block: S -= cf1 W of the partner entry (the slab's bottom chain,
+// entry e + 1): the second Schur term C_m S_{m+1}^{-1} B_{m+1}
+__global__ void k3_schur_sub(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int L,
+                             ChainStep cs) {
+  const int e = cs_entry(cs);
+  const Slab3 p = slabs[e];
+  const Slab3Work w = works[e], v2 = works[e + 1];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
+  if (c >= p.nb || r >= p.nb) return;
+  const int a = r / L, e3 = r % L;
+  const double2* cb = v2.cf + (size_t)p.nb * 9 + (size_t)r * 9;
+  double2 v = w.S[(size_t)r * p.nb + c];
+  for (int o9 = 0; o9 < 9; ++o9) {
+    const int a2 = a + o9 / 3 - 1, f3 = e3 + o9 % 3 - 1;
+    if (a2 < 0 || a2 >= p.t || f3 < 0 || f3 >= L) continue;
+    const double2 t = zmul(cb[o9], v2.W[(size_t)(a2 * L + f3) * p.nb + c]);
+    v.x -= t.x;
+    v.y -= t.y;
   }
   w.S[(size_t)r * p.nb + c] = v;
 }
@@ -232,12 +300,15 @@ __device__ int gj_pick(double bv, int br, double* best_v, int* best_r, int* pick
 }
 
 __global__ __launch_bounds__(kGjThreads) void k3_gj_panel(const Slab3* __restrict__ slabs,
-                                                          const Slab3Work* __restrict__ works, int k0,
-                                                          int* __restrict__ status) {
+                                                          const Slab3Work* __restrict__ works, int L, ChainStep cs,
+                                                          int k0, int* __restrict__ status) {
   constexpr int RU = 8;                      // rows in flight per thread
   constexpr int RG = kGjThreads / kGjPanel;  // row groups
-  const Slab3 p = slabs[blockIdx.z];
-  const Slab3Work w = works[blockIdx.z];
+  const int e = cs_entry(cs);
+  const Slab3 p = slabs[e];
+  const Slab3Work w = works[e];
+  int jb;
+  if (!cs_block(cs, w.dir, L, &jb)) return;
   const int nb = p.nb;
   if (k0 >= nb) return;
   const int kp = min(kGjPanel, nb - k0);
@@ -280,7 +351,7 @@ __global__ __launch_bounds__(kGjThreads) void k3_gj_panel(const Slab3* __restric
       const double d = pv.x * pv.x + pv.y * pv.y;
       double2 inv = make_double2(0.0, 0.0);
       if (!(d > 0.0) || !(d < INFINITY)) {
-        if (tid == 0) atomicMax(status, (int)blockIdx.z + 1);
+        if (tid == 0) atomicMax(status, e / 2 + 1);
       } else {
         inv = make_double2(pv.x / d, -pv.y / d);
       }
@@ -332,9 +403,13 @@ __global__ __launch_bounds__(kGjThreads) void k3_gj_panel(const Slab3* __restric
 
 // The panel's row swaps applied, in order, to every column outside the
 // panel; the pivot rows of those columns copied to Xr [kp][nb]
-__global__ void k3_gj_swap(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int k0) {
-  const Slab3 p = slabs[blockIdx.z];
-  const Slab3Work w = works[blockIdx.z];
+__global__ void k3_gj_swap(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int L, ChainStep cs,
+                           int k0) {
+  const int e = cs_entry(cs);
+  const Slab3 p = slabs[e];
+  const Slab3Work w = works[e];
+  int jb;
+  if (!cs_block(cs, w.dir, L, &jb)) return;
   const int nb = p.nb;
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (k0 >= nb || c >= nb) return;
@@ -356,9 +431,13 @@ __global__ void k3_gj_swap(const Slab3* __restrict__ slabs, const Slab3Work* __r
 // minus the identity on the pivot rows: 64 x 64 tiles, 256 threads, each
 // thread 4 x 4 entries (rows ty + 16 i, columns tx + 16 q)
 __global__ __launch_bounds__(256) void k3_gj_update(const Slab3* __restrict__ slabs,
-                                                    const Slab3Work* __restrict__ works, int k0) {
-  const Slab3 p = slabs[blockIdx.z];
-  const Slab3Work w = works[blockIdx.z];
+                                                    const Slab3Work* __restrict__ works, int L, ChainStep cs,
+                                                    int k0) {
+  const int e = cs_entry(cs);
+  const Slab3 p = slabs[e];
+  const Slab3Work w = works[e];
+  int jb;
+  if (!cs_block(cs, w.dir, L, &jb)) return;
   const int nb = p.nb;
   const int r0 = blockIdx.y * 64, c0 = blockIdx.x * 64;
   if (k0 >= nb || r0 >= nb || c0 >= nb) return;
@@ -420,10 +499,12 @@ __global__ __launch_bounds__(256) void k3_gj_update(const Slab3* __restrict__ sl
 // Column order of the inverse: in-place Gauss-Jordan with row interchanges
 // leaves S^{-1} with its columns permuted; replaying the interchanges in
 // reverse on the index list gives perm, and S^{-1}[:, c] = S[:, perm[c]].
-__global__ void k3_gj_perm(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works) {
-  const Slab3 p = slabs[blockIdx.z];
-  const Slab3Work w = works[blockIdx.z];
-  if (threadIdx.x != 0) return;
+__global__ void k3_gj_perm(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int L, ChainStep cs) {
+  const int e = cs_entry(cs);
+  const Slab3 p = slabs[e];
+  const Slab3Work w = works[e];
+  int jb;
+  if (!cs_block(cs, w.dir, L, &jb) || threadIdx.x != 0) return;
   for (int c = 0; c < p.nb; ++c) w.perm[c] = c;
   for (int c = p.nb - 1; c >= 0; --c) {
     const int q = w.piv[c];
@@ -435,15 +516,18 @@ __global__ void k3_gj_perm(const Slab3* __restrict__ slabs, const Slab3Work* __r
 
 // Sp = S^{-1} (float64, for the next block) and F_j = S^{-1} in the working precision
 template <typename T>
-__global__ void k3_gj_store(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int j,
+__global__ void k3_gj_store(const Slab3* __restrict__ slabs, const Slab3Work* __restrict__ works, int L, ChainStep cs,
                             C<T>* const* __restrict__ factors) {
-  const Slab3 p = slabs[blockIdx.z];
-  const Slab3Work w = works[blockIdx.z];
+  const int e = cs_entry(cs);
+  const Slab3 p = slabs[e];
+  const Slab3Work w = works[e];
+  int j;
+  if (!cs_block(cs, w.dir, L, &j)) return;
   const int c = blockIdx.x * blockDim.x + threadIdx.x, r = blockIdx.y;
   if (c >= p.nb || r >= p.nb) return;
   const double2 v = w.S[(size_t)r * p.nb + w.perm[c]];
   w.Sp[(size_t)r * p.nb + c] = v;
-  factors[blockIdx.z][((size_t)j * p.nb + r) * p.nb + c] = mk<T>((T)v.x, (T)v.y);
+  factors[e][((size_t)j * p.nb + r) * p.nb + c] = mk<T>((T)v.x, (T)v.y);
 }
 
 // Apply-time coefficients of slab z: cbc [L][2][nb][9] (B_j, then C_j, by
@@ -481,15 +565,18 @@ __global__ void k3_apply_coefs(Stencil3 S, const Slab3* __restrict__ slabs, C<T>
 
 // ---- slab solves -------------------------------------------------------------
 
-// z_j = r_j - B_j y_{j-1}: r_j from the source lines (D part), minus the
-// coupling to line lo - 1 on the first line of D (mode 1), plus the coupling
-// to line hi + 1 on the last line (mode 2)
+// z_j = r_j - (B_j y_{j-1}) - (C_j y_{j+1}) for the blocks of one step (the
+// terms each block takes are in st.terms; blockIdx.y = block of the step):
+// r_j from the source lines (D part), minus the coupling to line lo - 1 on the
+// first line of D (cmode 1), plus the coupling to line hi + 1 on the last line
+// (cmode 2)
 template <typename T>
-__global__ void k3_zf(Slab3Apply<T> A, int j) {
+__global__ void k3_zf(Slab3Apply<T> A, Slab3Step st) {
   const Slab3 p = A.p;
-  const int L = A.L, nb = p.nb;
+  const int L = A.L, nb = p.nb, task = blockIdx.y;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nb * A.nrhs) return;
+  if (task >= st.nt || idx >= nb * A.nrhs) return;
+  const int j = st.j[task], terms = st.terms[task];
   const int rhs = idx / nb, c = idx % nb, a = c / L, e3 = c % L;
   C<T> v = mk<T>(0, 0);
   if (a >= p.naux && A.src) v = A.src[rhs * A.src_rs + ((size_t)(a - p.naux) * L + j) * L + e3];
@@ -504,11 +591,12 @@ __global__ void k3_zf(Slab3Apply<T> A, int j) {
     }
     v = A.cmode == 1 ? csub<T>(v, s) : cadd<T>(v, s);
   }
-  if (j > 0) {
+  for (int side = 0; side < 2; ++side) {
+    if (!(terms & (1 << side))) continue;
     // all 18 loads issued together: out-of-range neighbours read entry c and
     // are masked (their coefficients are zero as well)
-    const C<T>* cf = A.cbc + ((size_t)(2 * j) * nb + c) * 9;
-    const C<T>* y = A.Y + ((size_t)rhs * L + (j - 1)) * nb;
+    const C<T>* cf = A.cbc + ((size_t)(2 * j + side) * nb + c) * 9;
+    const C<T>* y = A.Y + ((size_t)rhs * L + (side ? j + 1 : j - 1)) * nb;
     C<T> cv[9], yv[9];
     bool ok[9];
 #pragma unroll
@@ -522,19 +610,21 @@ __global__ void k3_zf(Slab3Apply<T> A, int j) {
     for (int o9 = 0; o9 < 9; ++o9)
       if (ok[o9]) v = csub<T>(v, cmul<T>(cv[o9], yv[o9]));
   }
-  A.z[(size_t)rhs * nb + c] = v;
+  A.z[((size_t)task * A.nrhs + rhs) * nb + c] = v;
 }
 
-// z = C_j x_{j+1}; when j + 1 is the last block, its D part goes to dst
+// z = B_j x_{j-1} (st.terms 0) or C_j x_{j+1} (st.terms 1) for the blocks of
+// one step of the outward pass
 template <typename T>
-__global__ void k3_zb(Slab3Apply<T> A, int j) {
+__global__ void k3_zb(Slab3Apply<T> A, Slab3Step st) {
   const Slab3 p = A.p;
-  const int L = A.L, nb = p.nb;
+  const int L = A.L, nb = p.nb, task = blockIdx.y;
   const int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= nb * A.nrhs) return;
+  if (task >= st.nt || idx >= nb * A.nrhs) return;
+  const int j = st.j[task], side = st.terms[task];
   const int rhs = idx / nb, c = idx % nb, a = c / L, e3 = c % L;
-  const C<T>* cf = A.cbc + ((size_t)(2 * j + 1) * nb + c) * 9;
-  const C<T>* x = A.Y + ((size_t)rhs * L + (j + 1)) * nb;
+  const C<T>* cf = A.cbc + ((size_t)(2 * j + side) * nb + c) * 9;
+  const C<T>* x = A.Y + ((size_t)rhs * L + (side ? j + 1 : j - 1)) * nb;
   C<T> v = mk<T>(0, 0);
   C<T> cv[9], xv[9];
   bool ok[9];
@@ -548,11 +638,7 @@ __global__ void k3_zb(Slab3Apply<T> A, int j) {
 #pragma unroll
   for (int o9 = 0; o9 < 9; ++o9)
     if (ok[o9]) v = cadd<T>(v, cmul<T>(cv[o9], xv[o9]));
-  A.z[(size_t)rhs * nb + c] = v;
-  if (j + 1 == L - 1 && a >= p.naux) {
-    C<T>* d = A.dst + rhs * A.dst_rs + ((size_t)(a - p.naux) * L + (L - 1)) * L + e3;
-    *d = A.dop ? csub<T>(*d, x[c]) : x[c];
-  }
+  A.z[((size_t)task * A.nrhs + rhs) * nb + c] = v;
 }
 
 // Y_j = F_j z (sub = 0) or Y_j -= F_j z (sub = 1) for the right-hand sides
@@ -581,14 +667,17 @@ constexpr int kGemvRows = 8;
 constexpr int kGemvThreads = 1024;
 
 template <typename T, int KC, int W>
-__global__ __launch_bounds__(kGemvThreads) void k3_gemv(Slab3Apply<T> A, int j, int sub, int out, int r0, int rc) {
+__global__ __launch_bounds__(kGemvThreads) void k3_gemv(Slab3Apply<T> A, Slab3Step stp, int sub, int out, int r0,
+                                                        int rc) {
   constexpr int RW = kGemvRows, H = kGemvThreads / 64 / RW, U = 8, ZU = 4;
   using V = typename WVec<W, T>::type;
   extern __shared__ unsigned char smem_raw[];
   C<T>* zl = reinterpret_cast<C<T>*>(smem_raw);
   __shared__ C<T> part[kGemvThreads / 64][KC];
   const Slab3 p = A.p;
-  const int L = A.L, nb = p.nb;
+  const int L = A.L, nb = p.nb, task = blockIdx.y;
+  if (task >= stp.nt) return;
+  const int j = stp.j[task];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int rr = wv % RW, hh = wv / RW;
   const int row = blockIdx.x * RW + rr;
@@ -599,7 +688,7 @@ __global__ __launch_bounds__(kGemvThreads) void k3_gemv(Slab3Apply<T> A, int j, 
   // vectors): the first ZU per thread are requested before the matrix, so
   // that they return first; the barrier orders LDS only, the matrix loads
   // stay in flight across it
-  const V* zs = reinterpret_cast<const V*>(A.z + (size_t)r0 * nb);
+  const V* zs = reinterpret_cast<const V*>(A.z + ((size_t)task * A.nrhs + r0) * nb);
   V* zd = reinterpret_cast<V*>(zl);
   const int nz = rc * nb / W;
   V tz[ZU];
@@ -706,26 +795,41 @@ hipError_t launch3_extract(const C<T>* u, int n, int b, int nrhs, C<T>* z, hipSt
 }
 
 template <typename T>
-hipError_t launch3_factor(const Stencil3& S, const Slab3* slabs, const Slab3Work* works, int nslab, int maxnb,
+hipError_t launch3_factor(const Stencil3& S, const Slab3* slabs, const Slab3Work* works, int nentries, int maxnb,
                           C<T>* const* factors, int* status, hipStream_t st) {
-  const int L = S.L;
-  for (int j = 0; j < L; ++j) {
-    hipLaunchKernelGGL(k3_coefs, dim3((maxnb * 9 + 255) / 256, 1, nslab), dim3(256), 0, st, S, slabs, works, j);
-    const dim3 gm((maxnb + 255) / 256, maxnb, nslab);
-    if (j > 0) hipLaunchKernelGGL(k3_schur_w, gm, dim3(256), 0, st, slabs, works, L);
-    hipLaunchKernelGGL(k3_schur_s, gm, dim3(256), 0, st, slabs, works, L, j);
+  const int L = S.L, m = L / 2, steps = std::max(m, L - 1 - m);
+  const dim3 gm((maxnb + 255) / 256, maxnb);
+  // one block of every entry named by cs: Schur complement (unless skip_s),
+  // then its inverse
+  auto invert = [&](ChainStep cs, int ne) {
     for (int k0 = 0; k0 < maxnb; k0 += kGjPanel) {
-      hipLaunchKernelGGL(k3_gj_panel, dim3(1, 1, nslab), dim3(kGjThreads), 0, st, slabs, works, k0, status);
-      hipLaunchKernelGGL(k3_gj_swap, dim3((maxnb + 255) / 256, 1, nslab), dim3(256), 0, st, slabs, works, k0);
-      hipLaunchKernelGGL(k3_gj_update, dim3((maxnb + 63) / 64, (maxnb + 63) / 64, nslab), dim3(256), 0, st, slabs,
-                         works, k0);
+      hipLaunchKernelGGL(k3_gj_panel, dim3(1, 1, ne), dim3(kGjThreads), 0, st, slabs, works, L, cs, k0, status);
+      hipLaunchKernelGGL(k3_gj_swap, dim3((maxnb + 255) / 256, 1, ne), dim3(256), 0, st, slabs, works, L, cs, k0);
+      hipLaunchKernelGGL(k3_gj_update, dim3((maxnb + 63) / 64, (maxnb + 63) / 64, ne), dim3(256), 0, st, slabs,
+                         works, L, cs, k0);
     }
-    hipLaunchKernelGGL(k3_gj_perm, dim3(1, 1, nslab), dim3(64), 0, st, slabs, works);
-    hipLaunchKernelGGL(k3_gj_store<T>, gm, dim3(256), 0, st, slabs, works, j, factors);
+    hipLaunchKernelGGL(k3_gj_perm, dim3(1, 1, ne), dim3(64), 0, st, slabs, works, L, cs);
+    hipLaunchKernelGGL(k3_gj_store<T>, dim3(gm.x, gm.y, ne), dim3(256), 0, st, slabs, works, L, cs, factors);
+  };
+  for (int s = 0; s < steps; ++s) {
+    const ChainStep cs{s, m, 0, 1, 0};
+    hipLaunchKernelGGL(k3_coefs, dim3((maxnb * 9 + 255) / 256, 1, nentries), dim3(256), 0, st, S, slabs, works, cs);
+    hipLaunchKernelGGL(k3_schur_w, dim3(gm.x, gm.y, nentries), dim3(256), 0, st, slabs, works, L, cs);
+    hipLaunchKernelGGL(k3_schur_s, dim3(gm.x, gm.y, nentries), dim3(256), 0, st, slabs, works, L, cs);
+    invert(cs, nentries);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  // the middle block: both chains' couplings (every entry), then on the top
+  // entries S = A_m - B_m W_top - C_m W_bottom and its inverse
+  const ChainStep all{0, m, 1, 1, 0}, top{0, m, 1, 2, 0};
+  const int nslab = nentries / 2;
+  hipLaunchKernelGGL(k3_coefs, dim3((maxnb * 9 + 255) / 256, 1, nentries), dim3(256), 0, st, S, slabs, works, all);
+  hipLaunchKernelGGL(k3_schur_w, dim3(gm.x, gm.y, nentries), dim3(256), 0, st, slabs, works, L, all);
+  hipLaunchKernelGGL(k3_schur_s, dim3(gm.x, gm.y, nslab), dim3(256), 0, st, slabs, works, L, top);
+  hipLaunchKernelGGL(k3_schur_sub, dim3(gm.x, gm.y, nslab), dim3(256), 0, st, slabs, works, L, top);
+  invert(top, nslab);
+  return hipGetLastError();
 }
 
 template <typename T>
@@ -775,34 +879,65 @@ hipError_t launch3_slab_solve(const Slab3Apply<T>& A, hipStream_t st) {
         return e;
     }
   }
-  auto gemv = [&](int j, int sub, int out) {
+  auto gemv = [&](const Slab3Step& sp, int sub, int out) {
+    const dim3 g(gg.x, sp.nt);
     for (int r0 = 0; r0 < A.nrhs; r0 += kc) {
       const int rc = std::min(kc, A.nrhs - r0);
       const size_t lds = slab3_gemv_lds(nb, rc, sizeof(C<T>));
       if (wide) {
         if (rc > 4)
-          hipLaunchKernelGGL((k3_gemv<T, 8, WideW<T>::value>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 8, WideW<T>::value>), g, dim3(kGemvThreads), lds, st, A, sp, sub, out, r0, rc);
         else if (rc > 1)
-          hipLaunchKernelGGL((k3_gemv<T, 4, WideW<T>::value>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 4, WideW<T>::value>), g, dim3(kGemvThreads), lds, st, A, sp, sub, out, r0, rc);
         else
-          hipLaunchKernelGGL((k3_gemv<T, 1, WideW<T>::value>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 1, WideW<T>::value>), g, dim3(kGemvThreads), lds, st, A, sp, sub, out, r0, rc);
       } else {
         if (rc > 4)
-          hipLaunchKernelGGL((k3_gemv<T, 8, 1>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 8, 1>), g, dim3(kGemvThreads), lds, st, A, sp, sub, out, r0, rc);
         else if (rc > 1)
-          hipLaunchKernelGGL((k3_gemv<T, 4, 1>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 4, 1>), g, dim3(kGemvThreads), lds, st, A, sp, sub, out, r0, rc);
         else
-          hipLaunchKernelGGL((k3_gemv<T, 1, 1>), gg, dim3(kGemvThreads), lds, st, A, j, sub, out, r0, rc);
+          hipLaunchKernelGGL((k3_gemv<T, 1, 1>), g, dim3(kGemvThreads), lds, st, A, sp, sub, out, r0, rc);
       }
     }
   };
-  for (int j = 0; j < L; ++j) {
-    hipLaunchKernelGGL(k3_zf<T>, dim3(zt), dim3(256), 0, st, A, j);
-    gemv(j, 0, 0);
+  // two-ended elimination: the top chain takes blocks 0 .. m-1, the bottom
+  // chain L-1 .. m+1, one block of each per launch; then the middle block;
+  // then both chains outwards
+  const int m = L / 2, lt = m, lb = L - 1 - m, steps = std::max(lt, lb);
+  for (int s = 0; s < steps; ++s) {
+    Slab3Step sp{};
+    if (s < lt) {
+      sp.j[sp.nt] = s;
+      sp.terms[sp.nt++] = s > 0 ? 1 : 0;
+    }
+    if (s < lb) {
+      sp.j[sp.nt] = L - 1 - s;
+      sp.terms[sp.nt++] = s > 0 ? 2 : 0;
+    }
+    hipLaunchKernelGGL(k3_zf<T>, dim3(zt, sp.nt), dim3(256), 0, st, A, sp);
+    gemv(sp, 0, 0);
   }
-  for (int j = L - 2; j >= 0; --j) {
-    hipLaunchKernelGGL(k3_zb<T>, dim3(zt), dim3(256), 0, st, A, j);
-    gemv(j, 1, 1);
+  {
+    Slab3Step sp{};
+    sp.nt = 1;
+    sp.j[0] = m;
+    sp.terms[0] = 3;
+    hipLaunchKernelGGL(k3_zf<T>, dim3(zt, 1), dim3(256), 0, st, A, sp);
+    gemv(sp, 0, 1);
+  }
+  for (int s = 0; s < steps; ++s) {
+    Slab3Step sp{};
+    if (s < lt) {
+      sp.j[sp.nt] = m - 1 - s;
+      sp.terms[sp.nt++] = 1;  // C_j x_{j+1}
+    }
+    if (s < lb) {
+      sp.j[sp.nt] = m + 1 + s;
+      sp.terms[sp.nt++] = 0;  // B_j x_{j-1}
+    }
+    hipLaunchKernelGGL(k3_zb<T>, dim3(zt, sp.nt), dim3(256), 0, st, A, sp);
+    gemv(sp, 1, 1);
   }
   return hipGetLastError();
 }
