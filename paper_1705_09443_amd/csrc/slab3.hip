@@ -299,105 +299,150 @@ __device__ int gj_pick(double bv, int br, double* best_v, int* best_r, int* pick
   return *pick;
 }
 
+// Sub-panel width whose nb x width complex128 columns fit in LDS (150 KB).
+__host__ __device__ inline int gj_subpanel(int nb) { return nb <= 2400 ? 4 : (nb <= 4800 ? 2 : 1); }
+constexpr size_t kGjLdsBytes = 150 * 1024;
+
+// The panel is worked through in sub-panels of SW columns, each held in LDS
+// for all nb rows: its pivots are found, swapped and eliminated there (the
+// same in-place Gauss-Jordan steps), it is written back, and its row
+// interchanges and rank-SW transform are applied to the panel's other
+// columns in global memory before the next sub-panel is loaded.
+template <int SW>
 __global__ __launch_bounds__(kGjThreads) void k3_gj_panel(const Slab3* __restrict__ slabs,
                                                           const Slab3Work* __restrict__ works, int L, ChainStep cs,
                                                           int k0, int* __restrict__ status) {
-  constexpr int RU = 8;                      // rows in flight per thread
-  constexpr int RG = kGjThreads / kGjPanel;  // row groups
+  constexpr int RU = 8;  // rows in flight per thread in the global update
   const int e = cs_entry(cs);
   const Slab3 p = slabs[e];
   const Slab3Work w = works[e];
   int jb;
   if (!cs_block(cs, w.dir, L, &jb)) return;
   const int nb = p.nb;
-  if (k0 >= nb) return;
+  if (k0 >= nb || gj_subpanel(nb) != SW) return;
   const int kp = min(kGjPanel, nb - k0);
   const int tid = threadIdx.x;
+  extern __shared__ unsigned char smem_raw[];
+  double2* buf = reinterpret_cast<double2*>(smem_raw);  // [nb][SW]
   __shared__ double best_v[kGjThreads / 64];
   __shared__ int best_r[kGjThreads / 64];
   __shared__ int pick_s;
-  __shared__ double2 prow[kGjPanel];
+  __shared__ double2 prow[SW];
+  __shared__ double2 rk[SW][kGjPanel];
+  __shared__ int spiv[SW];
   double2* S = w.S;
-  // pivot of the first panel column: largest modulus among rows k0..nb-1
-  int pr;
-  {
-    double bv = -1.0;
-    int br = nb;
-    for (int r = k0 + tid; r < nb; r += kGjThreads) {
-      const double2 v = S[(size_t)r * nb + k0];
-      const double m2 = v.x * v.x + v.y * v.y;
-      if (m2 > bv) {
-        bv = m2;
-        br = r;
-      }
-    }
-    pr = gj_pick(bv, br, best_v, best_r, &pick_s);
-  }
-  const int c = tid % kGjPanel, rg = tid / kGjPanel;
-  for (int pp = 0; pp < kp; ++pp) {
-    const int cp = k0 + pp;
-    if (pr >= nb) pr = cp;
-    if (tid == 0) w.piv[cp] = pr;
-    // swap rows cp and pr in the panel columns
-    if (pr != cp && tid < kp) {
-      const double2 a = S[(size_t)cp * nb + k0 + tid], b = S[(size_t)pr * nb + k0 + tid];
-      S[(size_t)cp * nb + k0 + tid] = b;
-      S[(size_t)pr * nb + k0 + tid] = a;
+  for (int c0 = k0; c0 < k0 + kp; c0 += SW) {
+    const int sw = min(SW, k0 + kp - c0);
+    // 1. the sub-panel columns into LDS
+    for (int idx = tid; idx < nb * SW; idx += kGjThreads) {
+      const int r = idx / SW, q = idx % SW;
+      buf[idx] = q < sw ? S[(size_t)r * nb + c0 + q] : make_double2(0.0, 0.0);
     }
     __syncthreads();
-    // pivot row: scaled by 1/pivot, its own entry replaced by 1/pivot
-    if (tid < kp) {
-      const double2 pv = S[(size_t)cp * nb + cp];
-      const double d = pv.x * pv.x + pv.y * pv.y;
-      double2 inv = make_double2(0.0, 0.0);
-      if (!(d > 0.0) || !(d < INFINITY)) {
-        if (tid == 0) atomicMax(status, e / 2 + 1);
-      } else {
-        inv = make_double2(pv.x / d, -pv.y / d);
-      }
-      const double2 v = S[(size_t)cp * nb + k0 + tid];
-      prow[tid] = tid == pp ? inv : zmul(v, inv);
-    }
-    __syncthreads();
-    if (tid < kp) S[(size_t)cp * nb + k0 + tid] = prow[tid];
-    // eliminate column cp from every other row (panel columns); the lanes
-    // of a row share a wave, which loads the row's column-cp entry before its
-    // lane pp overwrites it. Lane pp + 1 tracks the next pivot candidate.
-    double bv = -1.0;
-    int br = nb;
-    if (c < kp) {
-      const double2 pc = prow[c];
-      const bool track = c == pp + 1;
-      for (int rb = rg; rb < nb; rb += RG * RU) {
-        double2 f[RU], v[RU];
-#pragma unroll
-        for (int u = 0; u < RU; ++u) {
-          const int r = rb + RG * u;
-          const bool ok = r < nb && r != cp;
-          f[u] = ok ? S[(size_t)r * nb + cp] : make_double2(0.0, 0.0);
-          v[u] = ok && c != pp ? S[(size_t)r * nb + k0 + c] : make_double2(0.0, 0.0);
+    // 2. its pivots, in LDS
+    for (int pp = 0; pp < sw; ++pp) {
+      const int cp = c0 + pp;
+      double bv = -1.0;
+      int br = nb;
+      for (int r = cp + tid; r < nb; r += kGjThreads) {
+        const double2 v = buf[r * SW + pp];
+        const double m2 = v.x * v.x + v.y * v.y;
+        if (m2 > bv) {
+          bv = m2;
+          br = r;
         }
+      }
+      int pr = gj_pick(bv, br, best_v, best_r, &pick_s);
+      if (pr >= nb) pr = cp;
+      if (tid == 0) {
+        w.piv[cp] = pr;
+        spiv[pp] = pr;
+      }
+      if (pr != cp && tid < SW) {
+        const double2 a = buf[cp * SW + tid], b = buf[pr * SW + tid];
+        buf[cp * SW + tid] = b;
+        buf[pr * SW + tid] = a;
+      }
+      __syncthreads();
+      if (tid < SW) {
+        const double2 pv = buf[cp * SW + pp];
+        const double d = pv.x * pv.x + pv.y * pv.y;
+        double2 inv = make_double2(0.0, 0.0);
+        if (!(d > 0.0) || !(d < INFINITY)) {
+          if (tid == 0) atomicMax(status, e / 2 + 1);
+        } else {
+          inv = make_double2(pv.x / d, -pv.y / d);
+        }
+        prow[tid] = tid == pp ? inv : zmul(buf[cp * SW + tid], inv);
+      }
+      __syncthreads();
+      if (tid < SW) buf[cp * SW + tid] = prow[tid];
+      // eliminate column cp from every other row; the SW entries of a row
+      // share a wave, which reads the row's column-cp entry before lane pp
+      // overwrites it
+      for (int idx = tid; idx < nb * SW; idx += kGjThreads) {
+        const int r = idx / SW, q = idx % SW;
+        if (r == cp) continue;
+        const double2 f = buf[r * SW + pp];
+        double2 v = q == pp ? make_double2(0.0, 0.0) : buf[idx];
+        const double2 t = zmul(f, prow[q]);
+        v.x -= t.x;
+        v.y -= t.y;
+        buf[idx] = v;
+      }
+      __syncthreads();
+    }
+    // 3. back to global memory
+    for (int idx = tid; idx < nb * SW; idx += kGjThreads) {
+      const int r = idx / SW, q = idx % SW;
+      if (q < sw) S[(size_t)r * nb + c0 + q] = buf[idx];
+    }
+    // 4. the other panel columns: interchanges in order, then
+    //    M[:, c] += X M[Ksub, c] with X = the sub-panel minus the identity on
+    //    its pivot rows
+    if (tid < kp && (k0 + tid < c0 || k0 + tid >= c0 + sw)) {
+      const int c = k0 + tid;
+      for (int q = 0; q < sw; ++q) {
+        const int r1 = c0 + q, r2 = spiv[q];
+        if (r2 != r1) {
+          const double2 a = S[(size_t)r1 * nb + c], b = S[(size_t)r2 * nb + c];
+          S[(size_t)r1 * nb + c] = b;
+          S[(size_t)r2 * nb + c] = a;
+        }
+      }
+      for (int q = 0; q < sw; ++q) rk[q][tid] = S[(size_t)(c0 + q) * nb + c];
+    }
+    __syncthreads();
+    {
+      const int c = tid % kGjPanel, rg = tid / kGjPanel;
+      constexpr int RG = kGjThreads / kGjPanel;
+      const bool col = c < kp && (k0 + c < c0 || k0 + c >= c0 + sw);
+      if (col) {
+        for (int rb = rg; rb < nb; rb += RG * RU) {
+          double2 v[RU];
 #pragma unroll
-        for (int u = 0; u < RU; ++u) {
-          const int r = rb + RG * u;
-          if (r >= nb || r == cp) continue;
-          const double2 t = zmul(f[u], pc);
-          const double2 nv = make_double2(v[u].x - t.x, v[u].y - t.y);
-          S[(size_t)r * nb + k0 + c] = nv;
-          if (track && r > cp) {
-            const double m2 = nv.x * nv.x + nv.y * nv.y;
-            if (m2 > bv) {
-              bv = m2;
-              br = r;
+          for (int u = 0; u < RU; ++u) {
+            const int r = rb + RG * u;
+            v[u] = r < nb ? S[(size_t)r * nb + k0 + c] : make_double2(0.0, 0.0);
+          }
+#pragma unroll
+          for (int u = 0; u < RU; ++u) {
+            const int r = rb + RG * u;
+            if (r >= nb) continue;
+            double2 acc = v[u];
+            for (int q = 0; q < sw; ++q) {
+              double2 x = buf[r * SW + q];
+              if (r == c0 + q) x.x -= 1.0;
+              const double2 t = zmul(x, rk[q][c]);
+              acc.x += t.x;
+              acc.y += t.y;
             }
+            S[(size_t)r * nb + k0 + c] = acc;
           }
         }
       }
     }
-    if (pp + 1 < kp)
-      pr = gj_pick(bv, br, best_v, best_r, &pick_s);
-    else
-      __syncthreads();
+    __syncthreads();
   }
 }
 
@@ -727,15 +772,16 @@ __global__ __launch_bounds__(kGemvThreads) void k3_gemv(Slab3Apply<T> A, Slab3St
       if (v >= ve) break;
       const T* fv = reinterpret_cast<const T*>(&f[u]);
 #pragma unroll
-      for (int w = 0; w < W; ++w) {
-        const int c = v * W + w;
-        const T fx = fv[2 * w], fy = fv[2 * w + 1];
+      for (int k = 0; k < KC; ++k) {
+        if (k < rc) {
+          // the W complex of z that meet this vector, one LDS read
+          const V zz = reinterpret_cast<const V*>(zl)[(k * nb) / W + v];
+          const T* zv = reinterpret_cast<const T*>(&zz);
 #pragma unroll
-        for (int k = 0; k < KC; ++k) {
-          if (k < rc) {
-            const C<T> zv = zl[k * nb + c];
-            ax[k] += fx * zv.x - fy * zv.y;
-            ay[k] += fx * zv.y + fy * zv.x;
+          for (int w = 0; w < W; ++w) {
+            const T fx = fv[2 * w], fy = fv[2 * w + 1], zx = zv[2 * w], zy = zv[2 * w + 1];
+            ax[k] += fx * zx - fy * zy;
+            ay[k] += fx * zy + fy * zx;
           }
         }
       }
@@ -799,11 +845,31 @@ hipError_t launch3_factor(const Stencil3& S, const Slab3* slabs, const Slab3Work
                           C<T>* const* factors, int* status, hipStream_t st) {
   const int L = S.L, m = L / 2, steps = std::max(m, L - 1 - m);
   const dim3 gm((maxnb + 255) / 256, maxnb);
+  if (maxnb > 9600) return hipErrorInvalidValue;
+  {
+    hipError_t e;
+    if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gj_panel<4>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGjLdsBytes)) != hipSuccess ||
+        (e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gj_panel<2>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGjLdsBytes)) != hipSuccess ||
+        (e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gj_panel<1>),
+                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGjLdsBytes)) != hipSuccess)
+      return e;
+  }
   // one block of every entry named by cs: Schur complement (unless skip_s),
   // then its inverse
   auto invert = [&](ChainStep cs, int ne) {
     for (int k0 = 0; k0 < maxnb; k0 += kGjPanel) {
-      hipLaunchKernelGGL(k3_gj_panel, dim3(1, 1, ne), dim3(kGjThreads), 0, st, slabs, works, L, cs, k0, status);
+      for (int sw : {4, 2, 1}) {
+        // entries whose block size takes this sub-panel width (the others return at once)
+        const size_t lds = (size_t)std::min(maxnb, sw == 4 ? 2400 : (sw == 2 ? 4800 : 9600)) * sw * sizeof(double2);
+        if (sw == 4)
+          hipLaunchKernelGGL(k3_gj_panel<4>, dim3(1, 1, ne), dim3(kGjThreads), lds, st, slabs, works, L, cs, k0, status);
+        else if (sw == 2 && maxnb > 2400)
+          hipLaunchKernelGGL(k3_gj_panel<2>, dim3(1, 1, ne), dim3(kGjThreads), lds, st, slabs, works, L, cs, k0, status);
+        else if (sw == 1 && maxnb > 4800)
+          hipLaunchKernelGGL(k3_gj_panel<1>, dim3(1, 1, ne), dim3(kGjThreads), lds, st, slabs, works, L, cs, k0, status);
+      }
       hipLaunchKernelGGL(k3_gj_swap, dim3((maxnb + 255) / 256, 1, ne), dim3(256), 0, st, slabs, works, L, cs, k0);
       hipLaunchKernelGGL(k3_gj_update, dim3((maxnb + 63) / 64, (maxnb + 63) / 64, ne), dim3(256), 0, st, slabs,
                          works, L, cs, k0);
