@@ -118,7 +118,8 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
  * L (t L)^2 complex per slab of t lines) and the sweep is applied slab by
  * slab (Algorithm 2; sweep_schedule is ignored). The 3D operator is the FFT
  * convolution of ls_op3_create. Not available in 3D: autotune (must be 0),
- * layer_thickness <= 0, ls_set_kernels. n <= 1023, slabs of at most 32 lines.
+ * layer_thickness <= 0, ls_set_kernels. n <= 1023, slabs of at most 32 lines
+ * and blocks (slab lines x L) of at most 4800 unknowns (LS_E_INVALID otherwise).
  * A slab whose block has a zero pivot gives LS_E_SINGULAR.
  */
 
@@ -309,7 +310,8 @@ ls_status ls_host_tables(int n, double omega, const double* m_host, int pml_widt
  *   aux_host    b x (2b+1) x (2b+1) x ns x 27 complex, by (depth q, c2, c3,
  *               sample); entries no auxiliary point uses are zero
  *   kmap_host   L^3 int, the sample index of every extended point
- * Classes, samples and slabs as in 2D; a slab may have at most 32 lines.
+ * Classes, samples and slabs as in 2D; a slab may have at most 32 lines and
+ * blocks (lines x L) of at most 4800 unknowns.
  * Any output pointer may be NULL.
  */
 ls_status ls_host_tables3(int n, double omega, const double* m_host, int pml_width, int layer_thickness,

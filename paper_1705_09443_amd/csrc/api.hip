@@ -1716,7 +1716,7 @@ ls_status setup3_handle(const ls_grid* grid, double omega, const double* m_dev, 
   LSW_HIP_TRY(hipMemcpy(mh.data(), m_dev, n3 * sizeof(double), hipMemcpyDeviceToHost));
   Sweep3& s = *h->s3;
   const std::string err = build_host_setup3(mh.data(), n, omega, pml_width, layer_thickness, o.pml_C,
-                                            o.freq_samples, kSlab3MaxLines, s.H);
+                                            o.freq_samples, kSlab3MaxLines, kSlab3MaxBlock, s.H);
   if (!err.empty()) {
     set_error(err);
     return LS_E_INVALID;
@@ -1742,6 +1742,11 @@ ls_status setup3_handle(const ls_grid* grid, double omega, const double* m_dev, 
     const Slab3 sl{p.first, p.lo, p.hi, p.t, p.naux, p.t * h->L};
     s.slabs.push_back(sl);
     s.maxnb = std::max(s.maxnb, sl.nb);
+  }
+  if (s.maxnb > kSlab3MaxBlock) {
+    set_error("3D: a slab block has " + std::to_string(s.maxnb) + " unknowns (slab lines x L); at most " +
+              std::to_string(kSlab3MaxBlock) + " are supported (reduce w or b)");
+    return LS_E_INVALID;
   }
   const ls_status e = device_setup3(h.get(), m_dev, mh);
   if (e != LS_OK) return e;
@@ -2468,7 +2473,7 @@ ls_status ls_host_tables3(int n, double omega, const double* m_host, int pml_wid
     }
     HostSetup3 Hs;
     const std::string err = build_host_setup3(m_host, n, omega, pml_width, layer_thickness, pml_C, freq_samples,
-                                              kSlab3MaxLines, Hs);
+                                              kSlab3MaxLines, kSlab3MaxBlock, Hs);
     if (!err.empty()) {
       set_error(err);
       return LS_E_INVALID;

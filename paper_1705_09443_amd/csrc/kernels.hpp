@@ -274,6 +274,9 @@ struct Stencil3 {
 struct Slab3 {
   int first, lo, hi, t, naux, nb;
 };
+// Largest block (slab lines x L) the slab factorization takes: a two-column
+// sub-panel of this many rows fills the LDS of one workgroup.
+constexpr int kSlab3MaxBlock = 4800;
 // Float64 work arrays of a slab's factorization.
 struct Slab3Work {
   double2* S;   // [nb][nb] block being inverted

@@ -634,7 +634,7 @@ std::string build_host_setup(const double* m, int n, double omega, int b, int w,
 namespace lsw {
 
 std::string build_host_setup3(const double* m, int n, double omega, int b, int w, double C, int freq_samples,
-                              int max_lines, HostSetup3& S) {
+                              int max_lines, int max_block, HostSetup3& S) {
   char buf[256];
   if (n < 1) return "n must be >= 1";
   if (!(omega > 0.0) || !std::isfinite(omega)) return "omega must be finite and > 0";
@@ -652,6 +652,30 @@ std::string build_host_setup3(const double* m, int n, double omega, int b, int w
   S.L = n + 2 + 2 * b;
   const int L = S.L;
   const size_t n3 = (size_t)n * n * n;
+
+  // ---- slabs (reading G8), checked before any of the heavy setup ----
+  const int nl = std::max(1, (n + 2) / w);
+  S.nslices = nl;
+  S.slices.resize(nl);
+  for (int k = 0; k < nl; ++k) {
+    SlicePlan& p = S.slices[k];
+    p.lo = (k == 0) ? -b : k * w;
+    p.hi = (k == nl - 1) ? n + 1 + b : (k + 1) * w - 1;
+    p.first = (k == 0) ? p.lo : p.lo - b;
+    p.t = p.hi - p.first + 1;
+    p.naux = p.lo - p.first;
+    if (p.t > max_lines) {
+      std::snprintf(buf, sizeof buf, "slab %d has %d lines; at most %d are supported (reduce w or b)", k, p.t,
+                    max_lines);
+      return buf;
+    }
+    if ((long long)p.t * L > max_block) {
+      std::snprintf(buf, sizeof buf,
+                    "slab %d has blocks of %lld unknowns (lines x L); at most %d are supported (reduce w or b)", k,
+                    (long long)p.t * L, max_block);
+      return buf;
+    }
+  }
 
   // ---- medium range and local-frequency samples (Sec. 2.3, reading G9) ----
   double mmax = -INFINITY, mmin = INFINITY;
@@ -752,24 +776,6 @@ std::string build_host_setup3(const double* m, int n, double omega, int b, int w
     }
     pml_gamma_3d(omega, omega, h, os, &S.gamma_glob[(size_t)id * 27]);
   });
-
-  // ---- slabs (reading G8) ----
-  const int nl = std::max(1, (n + 2) / w);
-  S.nslices = nl;
-  S.slices.resize(nl);
-  for (int k = 0; k < nl; ++k) {
-    SlicePlan& p = S.slices[k];
-    p.lo = (k == 0) ? -b : k * w;
-    p.hi = (k == nl - 1) ? n + 1 + b : (k + 1) * w - 1;
-    p.first = (k == 0) ? p.lo : p.lo - b;
-    p.t = p.hi - p.first + 1;
-    p.naux = p.lo - p.first;
-    if (p.t > max_lines) {
-      std::snprintf(buf, sizeof buf, "slab %d has %d lines; at most %d are supported (reduce w or b)", k, p.t,
-                    max_lines);
-      return buf;
-    }
-  }
 
   // ---- auxiliary PML stencils at the sampled local frequencies (Sec. 2.3) ----
   const size_t naux_keys = (size_t)b * NC * NC * ns;

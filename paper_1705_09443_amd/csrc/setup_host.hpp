@@ -69,8 +69,8 @@ std::string build_host_setup(const double* m_host, int n, double omega, int b, i
                              int freq_samples, HostSetup& out);
 
 // 3D: m is [n][n][n]; slices are slabs of lines i1 with at most
-// max_slab_lines lines each (the slab factorization's block size bound).
+// max_slab_lines lines and blocks (lines x L) of at most max_block unknowns.
 std::string build_host_setup3(const double* m_host, int n, double omega, int b, int w, double C,
-                              int freq_samples, int max_slab_lines, HostSetup3& out);
+                              int freq_samples, int max_slab_lines, int max_block, HostSetup3& out);
 
 }  // namespace lsw

@@ -300,7 +300,7 @@ __device__ int gj_pick(double bv, int br, double* best_v, int* best_r, int* pick
 }
 
 // Sub-panel width whose nb x width complex128 columns fit in LDS (150 KB).
-__host__ __device__ inline int gj_subpanel(int nb) { return nb <= 2400 ? 4 : (nb <= 4800 ? 2 : 1); }
+__host__ __device__ inline int gj_subpanel(int nb) { return nb <= 2400 ? 4 : 2; }
 constexpr size_t kGjLdsBytes = 150 * 1024;
 
 // The panel is worked through in sub-panels of SW columns, each held in LDS
@@ -845,14 +845,12 @@ hipError_t launch3_factor(const Stencil3& S, const Slab3* slabs, const Slab3Work
                           C<T>* const* factors, int* status, hipStream_t st) {
   const int L = S.L, m = L / 2, steps = std::max(m, L - 1 - m);
   const dim3 gm((maxnb + 255) / 256, maxnb);
-  if (maxnb > 9600) return hipErrorInvalidValue;
+  if (maxnb > kSlab3MaxBlock) return hipErrorInvalidValue;
   {
     hipError_t e;
     if ((e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gj_panel<4>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGjLdsBytes)) != hipSuccess ||
         (e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gj_panel<2>),
-                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGjLdsBytes)) != hipSuccess ||
-        (e = hipFuncSetAttribute(reinterpret_cast<const void*>(k3_gj_panel<1>),
                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)kGjLdsBytes)) != hipSuccess)
       return e;
   }
@@ -860,16 +858,12 @@ hipError_t launch3_factor(const Stencil3& S, const Slab3* slabs, const Slab3Work
   // then its inverse
   auto invert = [&](ChainStep cs, int ne) {
     for (int k0 = 0; k0 < maxnb; k0 += kGjPanel) {
-      for (int sw : {4, 2, 1}) {
-        // entries whose block size takes this sub-panel width (the others return at once)
-        const size_t lds = (size_t)std::min(maxnb, sw == 4 ? 2400 : (sw == 2 ? 4800 : 9600)) * sw * sizeof(double2);
-        if (sw == 4)
-          hipLaunchKernelGGL(k3_gj_panel<4>, dim3(1, 1, ne), dim3(kGjThreads), lds, st, slabs, works, L, cs, k0, status);
-        else if (sw == 2 && maxnb > 2400)
-          hipLaunchKernelGGL(k3_gj_panel<2>, dim3(1, 1, ne), dim3(kGjThreads), lds, st, slabs, works, L, cs, k0, status);
-        else if (sw == 1 && maxnb > 4800)
-          hipLaunchKernelGGL(k3_gj_panel<1>, dim3(1, 1, ne), dim3(kGjThreads), lds, st, slabs, works, L, cs, k0, status);
-      }
+      // entries whose block size takes the other sub-panel width return at once
+      hipLaunchKernelGGL(k3_gj_panel<4>, dim3(1, 1, ne), dim3(kGjThreads),
+                         (size_t)std::min(maxnb, 2400) * 4 * sizeof(double2), st, slabs, works, L, cs, k0, status);
+      if (maxnb > 2400)
+        hipLaunchKernelGGL(k3_gj_panel<2>, dim3(1, 1, ne), dim3(kGjThreads), (size_t)maxnb * 2 * sizeof(double2), st,
+                           slabs, works, L, cs, k0, status);
       hipLaunchKernelGGL(k3_gj_swap, dim3((maxnb + 255) / 256, 1, ne), dim3(256), 0, st, slabs, works, L, cs, k0);
       hipLaunchKernelGGL(k3_gj_update, dim3((maxnb + 63) / 64, (maxnb + 63) / 64, ne), dim3(256), 0, st, slabs,
                          works, L, cs, k0);

@@ -49,6 +49,10 @@ CASES3 = {
     "small": (9, 1.0, 3, 3),
     # four slabs, the last of 13 lines (nb = 325)
     "ragged": (15, 2.0, 4, 4),
+    # eight slabs on L = 41: seven of 8 lines (nb = 328) and a last of 13
+    # (nb = 533: 17 Gauss-Jordan panels, the last of 21 columns, and ragged
+    # 64 x 64 update tiles), 8 points per wavelength
+    "mid": (31, 4.0, 4, 4),
 }
 
 

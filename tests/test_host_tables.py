@@ -145,3 +145,23 @@ def test_tables3_match_oracle(n, ppw, b, w):
     for (q, c2, c3, ks), g in ref.sweep.aux_gamma.items():
         assert np.abs(got["aux"][q, c2, c3, ks] - g).max() < 1e-12
     assert np.array_equal(got["kmap"].reshape(-1), FrequencySamples(m, omega, n).index(ref.system.m_ext))
+
+
+def test_tables3_refuse_oversized_slabs_at_once():
+    # slab limits (32 lines, blocks of 4800 unknowns) are checked before the
+    # O(n^3) host setup: these grids would take minutes to tabulate
+    from paper_1705_09443_amd import _lib
+    import time
+    lib = _lib.load()
+    n = 200
+    m = np.zeros((n, n, n))
+    t0 = time.time()
+    # b = 8, w = 8: the last slab has 8 + 18 lines of L = 218 -> 5668 unknowns per block
+    st = lib.ls_host_tables3(n, 2 * math.pi * 8, m.ctypes.data, 8, 8, 10.0, 0, None, None, None, None, None)
+    assert st == _lib.LS_E_INVALID
+    assert b"4800" in lib.ls_last_error()
+    # w = 40: slabs of 48 lines
+    st = lib.ls_host_tables3(n, 2 * math.pi * 8, m.ctypes.data, 8, 40, 10.0, 0, None, None, None, None, None)
+    assert st == _lib.LS_E_INVALID
+    assert b"32" in lib.ls_last_error()
+    assert time.time() - t0 < 5.0
