@@ -159,3 +159,20 @@ def test_solves(case3):
         if info[j].iterations == res.iterations:
             assert rel(u[j], res.x) <= 1e-10
         assert abs(info32[j].iterations - res.iterations) <= 2
+
+
+def test_preconditioner_batch_of_ten(case3):
+    # ten right-hand sides: the products take them as one chunk of eight and
+    # one of two (both right-hand-side widths of the product kernel)
+    name, n, omega, m, ref, g64, g32 = case3
+    rng = np.random.default_rng(14)
+    r = crand(rng, (10, n, n, n))
+    z = g64.apply_precond(to_dev(r)).cpu().numpy()
+    z32 = g32.apply_precond(to_dev(r, torch.complex64)).cpu().numpy()
+    w64 = w32 = 0.0
+    for j in range(10):
+        zr = ref.precondition(r[j])
+        w64, w32 = max(w64, rel(z[j], zr)), max(w32, rel(z32[j], zr))
+    say(f"[{name}] apply_precond, 10 rhs: worst fp64 {w64:.2e}, fp32 {w32:.2e}")
+    assert w64 <= 1e-11
+    assert w32 <= 1e-4
