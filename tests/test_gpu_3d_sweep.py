@@ -53,6 +53,9 @@ CASES3 = {
     # (nb = 533: 17 Gauss-Jordan panels, the last of 21 columns, and ragged
     # 64 x 64 update tiles), 8 points per wavelength
     "mid": (31, 4.0, 4, 4),
+    # even L = 18: the top chain (blocks 0..8) is one block longer than the
+    # bottom chain (17..10), so the last inward step carries one block
+    "even": (10, 1.0, 3, 3),
 }
 
 
@@ -176,3 +179,28 @@ def test_preconditioner_batch_of_ten(case3):
     say(f"[{name}] apply_precond, 10 rhs: worst fp64 {w64:.2e}, fp32 {w32:.2e}")
     assert w64 <= 1e-11
     assert w32 <= 1e-4
+
+
+def test_single_slab_preconditioner_is_exact_solve():
+    """One slab (w >= n + 2) covers the whole extended cube: the sweep is the
+    exact solve of H (Sec. 2.3), checked against a sparse LU of the oracle's H."""
+    import scipy.sparse.linalg as spla
+    from paper_1705_09443_amd import LSSolver
+    n, b = 7, 2
+    omega = 2 * math.pi * 1.0
+    m = workloads.gaussian_bump_medium(n, 3, 4, (0.25, 0.75), (0.05, 0.1), (-0.3, 0.3), seed=7)
+    ref = oracle.OracleSolver(3, n, omega, m, b, n + 2)
+    assert ref.sweep.nslices == 1
+    s = ref.system
+    rng = np.random.default_rng(15)
+    r = crand(rng, (2, n, n, n))
+    g = LSSolver(torch.as_tensor(m).cuda(), omega, pml_width=b, layer_thickness=n + 2, precision="fp64")
+    try:
+        assert g.nslices == 1
+        z = g.apply_precond(to_dev(r)).cpu().numpy()
+    finally:
+        g.close()
+    lu = spla.splu(s.H.tocsc())
+    for j in range(2):
+        exact = s.restrict(lu.solve(s.apply_Q(r[j])))
+        assert rel(z[j], exact) <= 1e-11
