@@ -204,3 +204,37 @@ def test_single_slab_preconditioner_is_exact_solve():
     for j in range(2):
         exact = s.restrict(lu.solve(s.apply_Q(r[j])))
         assert rel(z[j], exact) <= 1e-11
+
+
+def test_source_kind_sample_map_and_refusals(case3):
+    name, n, omega, m, ref, g64, g32 = case3
+    if name != "small":
+        pytest.skip("one case suffices")
+    from paper_1705_09443_amd import LSSolver, LsError, _lib
+    from oracle.stencils import FrequencySamples
+    # the sample map through the handle (bit-exact, reading G9)
+    km = g64.sample_map()
+    assert np.array_equal(km.reshape(-1), FrequencySamples(m, omega, n).index(ref.system.m_ext))
+    # a right-hand side g given directly (source kind)
+    rng = np.random.default_rng(16)
+    gsrc = crand(rng, (1, n, n, n))
+    u, info = g64.solve(to_dev(gsrc), "source", 1e-10)
+    res = ref.solve_rhs(gsrc[0], 1e-10)
+    assert abs(info[0].iterations - res.iterations) <= 1
+    assert rel(ref.op.apply_A(u.cpu().numpy()[0]), gsrc[0]) <= 1.01e-10
+    # zero medium: g = 0, so u = 0 after no iterations
+    z = LSSolver(torch.zeros((n, n, n), dtype=torch.float64, device="cuda"), omega, pml_width=3,
+                 layer_thickness=3)
+    try:
+        uinc = workloads.plane_waves(n, 3, omega, workloads.angle_directions(1, 3, full_turn=False))
+        u0, info0 = z.solve(to_dev(uinc), "incident", 1e-8)
+        assert info0[0].iterations == 0 and torch.count_nonzero(u0).item() == 0
+        with pytest.raises(LsError):
+            z.set_kernels(4, 16, 1)
+    finally:
+        z.close()
+    md = torch.as_tensor(m).cuda()
+    with pytest.raises(LsError):
+        LSSolver(md, omega, pml_width=3, layer_thickness=3, autotune=4)
+    with pytest.raises(LsError):
+        LSSolver(md, omega, pml_width=3, layer_thickness=0)
