@@ -399,8 +399,10 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   const size_t maxpairs = (size_t)nrhs * (rs + 2);
   LSW_ALLOC(h->pairs, maxpairs * sizeof(DotPair));
   LSW_ALLOC(h->groups, maxpairs * sizeof(DotGroup));
-  // dot-product partials: kDotBlocks per pair, or 256 per norm of an update
-  LSW_ALLOC(h->partials, std::max(maxpairs * kDotBlocks, (size_t)nrhs * 256) * sizeof(double2));
+  // dot-product partials: kDotBlocks (grouped) or kAxpyDotBlocks (fused with
+  // an update) per pair, or 256 per norm of an update
+  LSW_ALLOC(h->partials,
+            std::max(maxpairs * std::max(kDotBlocks, kAxpyDotBlocks), (size_t)nrhs * 256) * sizeof(double2));
   LSW_ALLOC(h->coefs, (4 * maxpairs + 16) * sizeof(double2));
   LSW_ALLOC(h->outs, (size_t)nrhs * 2 * sizeof(AxpyOut));
   // two Gram-Schmidt passes of up to nrhs * restart terms each
@@ -1127,9 +1129,17 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     LSW_HIP_TRY((launch_copy_cast<double, T>(cw_d, cw_s, na, N, st)));
     const int ng = (int)hg.size();
     double2* part = h->partials.as<double2>();
+    int maxterms = 0;
+    for (int p = 0; p < na; ++p) maxterms = std::max(maxterms, off[p + 1] - off[p]);
     LSW_HIP_TRY(launch_mdots(groups_d, ng, np, N, part, coefs + base1, st));
-    LSW_HIP_TRY(launch_axpys<double>(outs_d, na, terms_d, coefs, N, st));
-    LSW_HIP_TRY(launch_mdots(groups_d, ng, np, N, part, coefs + base2, st));
+    if (maxterms <= kAxpyDotMaxTerms) {
+      // the first pass's update also forms the second pass's dot products
+      // (first-pass term i is dot product i)
+      LSW_HIP_TRY(launch_axpys_dots(outs_d, na, terms_d, coefs, N, np, part, coefs + base2, st));
+    } else {
+      LSW_HIP_TRY(launch_axpys<double>(outs_d, na, terms_d, coefs, N, st));
+      LSW_HIP_TRY(launch_mdots(groups_d, ng, np, N, part, coefs + base2, st));
+    }
     // the second update also forms ||w||^2
     LSW_HIP_TRY(launch_axpys_norms(outs_d + na, na, terms_d, coefs, N, part, coefs + base3, st));
     hc.resize(base3 + na);

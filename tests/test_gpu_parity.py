@@ -339,3 +339,32 @@ def test_graph_replays_agree(case):
             g64.set_kernels(nb, 0, 0)
         for z in outs:
             assert rel(z, zref) <= 1e-12
+
+
+@pytest.mark.parametrize("b,restart", [(2, 30), (1, 10)])
+def test_solve_long_arnoldi_cycles(b, restart):
+    """Arnoldi cycles longer than eight steps (a thin PML weakens the sweep):
+    the second Gram-Schmidt pass takes its dot products from the first pass's
+    update while a cycle has at most eight basis vectors, from separate grouped
+    products after that; with restart 10 the solve also crosses restarts.
+    Protocol P2 and P1 against the oracle at tol 1e-10."""
+    from paper_1705_09443_amd import LSSolver
+    n, ppw, w = 40, 2.5, 3
+    wl = workloads.workload("C0").scaled(n, ppw_omega=ppw)
+    m = workloads.gaussian_bump_medium(n, 2, 6, (0.2, 0.8), (0.04, 0.1), (-0.4, 0.4), seed=3)
+    uinc = workloads.plane_waves(n, 2, wl.omega, workloads.angle_directions(2, 2))
+    ref = oracle.OracleSolver(2, n, wl.omega, m, b, w, restart=restart)
+    say(f"[long cycles b={b} restart={restart}] ls_solve fp64, 2 rhs, tol 1e-10")
+    with LSSolver(torch.as_tensor(m).cuda(), wl.omega, b, w, precision="fp64", restart=restart) as g:
+        u, info = g.solve(to_dev(uinc), "incident", 1e-10)
+    u = u.cpu().numpy()
+    for j in range(uinc.shape[0]):
+        gj = ref.op.rhs_incident(uinc[j])
+        res = ref.solve_rhs(gj, 1e-10)
+        say(f"  rhs {j}: iterations {info[j].iterations}, oracle {res.iterations}")
+        assert res.iterations > 8
+        assert abs(info[j].iterations - res.iterations) <= 1          # P2
+        assert info[j].converged and info[j].rel_residual <= 1e-10
+        assert rel(ref.op.apply_A(u[j]), gj) <= 1.01e-10
+        if info[j].iterations == res.iterations:                     # P1
+            assert rel(u[j], res.x) <= 1e-10
