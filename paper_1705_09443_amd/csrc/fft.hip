@@ -105,20 +105,28 @@ __device__ __attribute__((always_inline)) inline void dft(C<T>* x, bool inv) {
   }
 }
 
+// log2 of a power of two
+__device__ __attribute__((always_inline)) inline int ilog2(int v) { return __builtin_ctz((unsigned)v); }
+template <int R>
+constexpr int kLog2 = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
+
+// P, nseq and Ns are powers of two: the index arithmetic is shifts and masks
 template <typename T, int R>
 __device__ inline void lds_fft_pass(C<T>* buf, int P, int nseq, int Ns, const C<T>* twl, bool inv) {
   constexpr int NB = kVals<T> / R;  // butterflies per thread
+  constexpr int LR = kLog2<R>;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int nbf = P / R;
-  const int total = nbf * nseq;
+  const int ls = ilog2(nseq), ln = ilog2(Ns), lstep = ilog2(P) - ln - LR;
+  const int nbf = P >> LR;
+  const int total = nbf << ls;
   C<T> v[NB][R];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int bidx = tid + q * nt;
     if (bidx < total) {
-      const int s = bidx % nseq, j = bidx / nseq;
+      const int s = bidx & (nseq - 1), j = bidx >> ls;
 #pragma unroll
-      for (int r = 0; r < R; ++r) v[q][r] = buf[(j + r * nbf) * nseq + s];
+      for (int r = 0; r < R; ++r) v[q][r] = buf[((j + r * nbf) << ls) + s];
     }
   }
   __syncthreads();
@@ -126,9 +134,9 @@ __device__ inline void lds_fft_pass(C<T>* buf, int P, int nseq, int Ns, const C<
   for (int q = 0; q < NB; ++q) {
     const int bidx = tid + q * nt;
     if (bidx >= total) continue;
-    const int s = bidx % nseq, j = bidx / nseq;
-    const int k = j % Ns;
-    const int step = k * (P / (Ns * R));
+    const int s = bidx & (nseq - 1), j = bidx >> ls;
+    const int k = j & (Ns - 1);
+    const int step = k << lstep;  // k P / (Ns R)
     C<T>* x = v[q];
 #pragma unroll
     for (int r = 1; r < R; ++r) {
@@ -137,9 +145,9 @@ __device__ inline void lds_fft_pass(C<T>* buf, int P, int nseq, int Ns, const C<
       x[r] = cmul<T>(x[r], w);
     }
     dft<T, R>(x, inv);
-    const int idxD = (j / Ns) * Ns * R + k;
+    const int idxD = ((j >> ln) << (ln + LR)) + k;  // (j / Ns) Ns R + k
 #pragma unroll
-    for (int r = 0; r < R; ++r) buf[(idxD + r * Ns) * nseq + s] = x[r];
+    for (int r = 0; r < R; ++r) buf[((idxD + r * Ns) << ls) + s] = x[r];
   }
   __syncthreads();
 }
@@ -184,12 +192,12 @@ __device__ __attribute__((always_inline)) inline void load_rows(C<T>* buf, const
                                                                 const T* __restrict__ m, int n, int P, int S,
                                                                 int i0) {
   constexpr int V = kVals<T>;
-  const int total = S * P;
+  const int total = S * P, lP = ilog2(P);
   C<T> v[V];
 #pragma unroll
   for (int q = 0; q < V; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
-    const int sq = idx / P, k = idx % P, row = i0 + sq;
+    const int sq = idx >> lP, k = idx & (P - 1), row = i0 + sq;
     const bool ok = idx < total && k < n && row < n;
     const size_t o = (size_t)(row < n ? row : n - 1) * n + (k < n ? k : n - 1);
     C<T> w = xr[o];
@@ -199,7 +207,7 @@ __device__ __attribute__((always_inline)) inline void load_rows(C<T>* buf, const
 #pragma unroll
   for (int q = 0; q < V; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
-    if (idx < total) buf[(idx % P) * S + idx / P] = v[q];
+    if (idx < total) buf[(idx & (P - 1)) * S + (idx >> lP)] = v[q];
   }
 }
 
@@ -223,11 +231,12 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_forward(const C<T>* __re
   lds_fft<T>(buf, P, S, twl, false);
   const int ntile = P / S;
   C<T>* Xr = X + (size_t)rhs * ntile * n * S;
+  const int lS = ilog2(S);
 #pragma unroll
   for (int q = 0; q < kVals<T>; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
-    const int tile = idx / (S * S), within = idx % (S * S);
-    const int sq = within / S, kk = within % S;
+    const int tile = idx >> (2 * lS), within = idx & (S * S - 1);
+    const int sq = within >> lS, kk = within & (S - 1);
     const int row = i0 + sq;
     if (idx < S * P && row < n) Xr[((size_t)tile * n + row) * S + kk] = buf[(tile * S + kk) * S + sq];
   }
@@ -265,12 +274,12 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_col_convolve(C<T>* __restric
   // times khat: k depends on |delta| only, so khat is symmetric and column c
   // of the quadrant is its row c; consecutive threads walk along it
   {
-    const int half = P / 2 + 1;
+    const int half = P / 2 + 1, lP = ilog2(P);
     C<T> kv[V];
 #pragma unroll
     for (int q = 0; q < V; ++q) {
       const int idx = threadIdx.x + q * blockDim.x;
-      const int sq = idx / P, r = idx % P;
+      const int sq = idx >> lP, r = idx & (P - 1);
       const int col = tile * S + (idx < total ? sq : 0);
       const int kr = r <= P - r ? r : P - r;
       const int kc = col <= P - col ? col : P - col;
@@ -280,7 +289,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_col_convolve(C<T>* __restric
     for (int q = 0; q < V; ++q) {
       const int idx = threadIdx.x + q * blockDim.x;
       if (idx < total) {
-        const int sq = idx / P, r = idx % P;
+        const int sq = idx >> lP, r = idx & (P - 1);
         buf[r * S + sq] = cmul<T>(buf[r * S + sq], kv[q]);
       }
     }
@@ -309,13 +318,14 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __re
   const int ntile = P / S;
   const int total = S * P;
   const C<T>* Xr = X + (size_t)rhs * ntile * n * S;
+  const int lS = ilog2(S);
   {
     C<T> v[V];
 #pragma unroll
     for (int q = 0; q < V; ++q) {
       const int idx = threadIdx.x + q * blockDim.x;
-      const int tl = idx / (S * S), within = idx % (S * S);
-      const int sq = within / S, kk = within % S;
+      const int tl = idx >> (2 * lS), within = idx & (S * S - 1);
+      const int sq = within >> lS, kk = within & (S - 1);
       const int row = i0 + sq;
       const bool ok = idx < total && row < n;
       const C<T> w = Xr[ok ? ((size_t)tl * n + row) * S + kk : 0];
@@ -325,8 +335,8 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __re
     for (int q = 0; q < V; ++q) {
       const int idx = threadIdx.x + q * blockDim.x;
       if (idx < total) {
-        const int tl = idx / (S * S), within = idx % (S * S);
-        buf[(tl * S + within % S) * S + within / S] = v[q];
+        const int tl = idx >> (2 * lS), within = idx & (S * S - 1);
+        buf[(tl * S + (within & (S - 1))) * S + (within >> lS)] = v[q];
       }
     }
   }
@@ -625,6 +635,7 @@ hipError_t launch_convolve(const C<T>* x, const T* m, int n, int nrhs, const C<T
   const int S = seq_per_block<T>(P);
   const int nt = threads_for<T>(S, P);
   const size_t lds = (size_t)(S + 1) * P * sizeof(C<T>);
+  if (S & (S - 1)) return hipErrorInvalidValue;  // the passes index by shifts
   hipError_t e;
   if ((e = allow_lds(k_row_forward<T>, lds)) != hipSuccess) return e;
   if ((e = allow_lds(k_col_convolve<T>, lds)) != hipSuccess) return e;
@@ -648,6 +659,7 @@ hipError_t launch_green_spectrum(const double2* kq, int n, const double2* tw, do
   const int S = seq_per_block<double>(P);
   const int nt = threads_for<double>(S, P);
   const size_t lds = (size_t)(S + 1) * P * sizeof(double2);
+  if (S & (S - 1)) return hipErrorInvalidValue;  // the passes index by shifts
   hipError_t e;
   if ((e = allow_lds(k_fft_rows_full, lds)) != hipSuccess) return e;
   if ((e = allow_lds(k_fft_cols_full, lds)) != hipSuccess) return e;
@@ -682,6 +694,7 @@ hipError_t launch_convolve3(const C<T>* x, const T* m, int n, int nrhs, const C<
   const int S = seq3<T>(P);
   const int nt = threads_for<T>(S, P);
   const size_t lds = (size_t)(S + 1) * P * sizeof(C<T>);
+  if (S & (S - 1)) return hipErrorInvalidValue;  // the passes index by shifts
   hipError_t e;
   if ((e = allow_lds(k3_rows_fwd<T, true>, lds)) != hipSuccess) return e;
   if ((e = allow_lds(k3_rows_fwd<T, false>, lds)) != hipSuccess) return e;
@@ -726,6 +739,7 @@ hipError_t launch_green_spectrum3(const double2* kq, int n, const double2* tw, d
   const int S = seq3<double>(P);
   const int nt = threads_for<double>(S, P);
   const size_t lds = (size_t)(S + 1) * P * sizeof(double2);
+  if (S & (S - 1)) return hipErrorInvalidValue;  // the passes index by shifts
   hipError_t e;
   if ((e = allow_lds(k3_axis<double, 0>, lds)) != hipSuccess) return e;
   const size_t P3 = (size_t)P * P * P, PP = (size_t)P * P;
