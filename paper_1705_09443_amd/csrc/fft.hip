@@ -304,10 +304,11 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_col_convolve(C<T>* __restric
 }
 
 // ---- pass 3: inverse rows and epilogue y = a x + coef * conv --------------
-template <typename T>
+// W64: right-hand side r written, widened, to y64[r] instead of y
+template <typename T, bool W64>
 __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __restrict__ X, const C<T>* __restrict__ x, int n, int P,
                               int S, const C<T>* __restrict__ tw, T a, T coef,
-                              C<T>* __restrict__ y) {
+                              C<T>* __restrict__ y, double2* const* __restrict__ y64) {
   constexpr int V = kVals<T>;
   extern __shared__ unsigned char smem_raw[];
   C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
@@ -357,8 +358,11 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __re
     const int idx = threadIdx.x + q * blockDim.x;
     const int sq = idx / n, k = idx % n, row = i0 + sq;
     if (idx < live && row < n) {
-      const size_t o = rhs * nn + (size_t)row * n + k;
-      y[o] = cadd<T>(cscale<T>(buf[k * S + sq], coef), cscale<T>(xv[q], a));
+      const C<T> v = cadd<T>(cscale<T>(buf[k * S + sq], coef), cscale<T>(xv[q], a));
+      if (W64)
+        y64[rhs][(size_t)row * n + k] = make_double2((double)v.x, (double)v.y);
+      else
+        y[rhs * nn + (size_t)row * n + k] = v;
     }
   }
 }
@@ -630,7 +634,7 @@ template size_t fft_work_elems<float>(int, int);
 
 template <typename T>
 hipError_t launch_convolve(const C<T>* x, const T* m, int n, int nrhs, const C<T>* khat,
-                           const C<T>* tw, T a, T c, C<T>* work, C<T>* y, hipStream_t st) {
+                           const C<T>* tw, T a, T c, C<T>* work, C<T>* y, hipStream_t st, double2* const* y64) {
   const int P = fft_len(n);
   const int S = seq_per_block<T>(P);
   const int nt = threads_for<T>(S, P);
@@ -639,19 +643,24 @@ hipError_t launch_convolve(const C<T>* x, const T* m, int n, int nrhs, const C<T
   hipError_t e;
   if ((e = allow_lds(k_row_forward<T>, lds)) != hipSuccess) return e;
   if ((e = allow_lds(k_col_convolve<T>, lds)) != hipSuccess) return e;
-  if ((e = allow_lds(k_row_inverse<T>, lds)) != hipSuccess) return e;
+  if ((e = allow_lds(k_row_inverse<T, false>, lds)) != hipSuccess) return e;
+  if ((e = allow_lds(k_row_inverse<T, true>, lds)) != hipSuccess) return e;
   const T coef = c / ((T)P * (T)P);
   dim3 grow((n + S - 1) / S, nrhs), gcol(P / S, nrhs);
   hipLaunchKernelGGL(k_row_forward<T>, grow, dim3(nt), lds, st, x, m, n, P, S, tw, work);
   hipLaunchKernelGGL(k_col_convolve<T>, gcol, dim3(nt), lds, st, work, khat, n, P, S, tw);
-  hipLaunchKernelGGL(k_row_inverse<T>, grow, dim3(nt), lds, st, work, x, n, P, S, tw, a, coef, y);
+  if (y64)
+    hipLaunchKernelGGL((k_row_inverse<T, true>), grow, dim3(nt), lds, st, work, x, n, P, S, tw, a, coef, y, y64);
+  else
+    hipLaunchKernelGGL((k_row_inverse<T, false>), grow, dim3(nt), lds, st, work, x, n, P, S, tw, a, coef, y, y64);
   return hipGetLastError();
 }
 template hipError_t launch_convolve<double>(const double2*, const double*, int, int, const double2*,
                                             const double2*, double, double, double2*, double2*,
-                                            hipStream_t);
+                                            hipStream_t, double2* const*);
 template hipError_t launch_convolve<float>(const float2*, const float*, int, int, const float2*,
-                                           const float2*, float, float, float2*, float2*, hipStream_t);
+                                           const float2*, float, float, float2*, float2*, hipStream_t,
+                                           double2* const*);
 
 hipError_t launch_green_spectrum(const double2* kq, int n, const double2* tw, double2* scratch,
                                  double2* khat, float2* khat32, hipStream_t st) {

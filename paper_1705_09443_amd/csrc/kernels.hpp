@@ -15,9 +15,12 @@ inline int fft_len(int n) {
 template <typename T>
 size_t fft_work_elems(int n, int nrhs);
 // y = a x + c * K (s .* x) on [nrhs][n][n]; s = m or 1 (m == nullptr).
+// With y64 (a device array of nrhs pointers to n x n float64 grids), right-hand
+// side r goes to y64[r] instead, formed in T and then widened (y unused).
 template <typename T>
 hipError_t launch_convolve(const C<T>* x, const T* m, int n, int nrhs, const C<T>* khat,
-                           const C<T>* tw, T a, T c, C<T>* work, C<T>* y, hipStream_t st);
+                           const C<T>* tw, T a, T c, C<T>* work, C<T>* y, hipStream_t st,
+                           double2* const* y64 = nullptr);
 // khat (quadrant (P/2+1)^2) from the table quadrant kq [(n+2)][(n+2)].
 hipError_t launch_green_spectrum(const double2* kq, int n, const double2* tw, double2* scratch,
                                  double2* khat, float2* khat32, hipStream_t st);
@@ -65,9 +68,12 @@ struct SliceTables {
 // slowest: the C ABI's, and the sequential sweep's) and the interleaved
 // [L][L][nrhs] of the interface schedule, where a 16-column tile of the
 // matrix-core slice solves reads one 128-byte run per grid point.
+// With r64 (interleaved only: a device array of nrhs pointers to n x n
+// float64 grids), right-hand side q is read from r64[q], narrowed to T on
+// load (r unused).
 template <typename T>
 hipError_t launch_apply_Q(const StencilTables& S, const C<T>* r, int nrhs, C<T>* f, bool interleaved,
-                          hipStream_t st);
+                          hipStream_t st, const double2* const* r64 = nullptr);
 template <typename T>
 hipError_t launch_apply_H(const StencilTables& S, const C<T>* u, int nrhs, C<T>* y, hipStream_t st);
 template <typename T>

@@ -114,9 +114,10 @@ __global__ void k_apply_H(StencilTables S, const C<T>* __restrict__ u, int nrhs,
 // workgroup takes one extended row, 64 columns and 16 right-hand sides: the
 // stencil reads run along the columns of each right-hand side's plane, the
 // results cross LDS and leave with the right-hand side fastest.
-template <typename T>
+// R64: right-hand side q read from r64[q] (float64), narrowed to T on load
+template <typename T, bool R64>
 __global__ __launch_bounds__(256) void k_apply_Q_il(StencilTables S, const C<T>* __restrict__ r, int nrhs,
-                                                    C<T>* __restrict__ f) {
+                                                    C<T>* __restrict__ f, const double2* const* __restrict__ r64) {
   __shared__ C<T> tile[64][17];
   const int L = S.L, n = S.n, b = S.b;
   const int c0 = blockIdx.x * 64, e1 = blockIdx.y, q0 = blockIdx.z * 16;
@@ -129,12 +130,21 @@ __global__ __launch_bounds__(256) void k_apply_Q_il(StencilTables S, const C<T>*
     const int rr = q0 + sub + 4 * s;
     C<T> acc = mk<T>(0, 0);
     if (type1 && rr < nrhs) {
-      const C<T>* rp = r + (size_t)rr * n * n;
+      const C<T>* rp = R64 ? nullptr : r + (size_t)rr * n * n;
+      const double2* rp64 = R64 ? r64[rr] : nullptr;
       for (int o = 0; o < 9; ++o) {
         const int j1 = i1 + o / 3 - 1, j2 = i2 + o % 3 - 1;
         if (j1 < 1 || j1 > n || j2 < 1 || j2 > n) continue;
         const double2 al = S.alpha[o];
-        acc = cfma<T>(acc, mk<T>((T)al.x, (T)-al.y), rp[(size_t)(j1 - 1) * n + (j2 - 1)]);
+        const size_t at = (size_t)(j1 - 1) * n + (j2 - 1);
+        C<T> rv;
+        if (R64) {
+          const double2 d = rp64[at];
+          rv = mk<T>((T)d.x, (T)d.y);
+        } else {
+          rv = rp[at];
+        }
+        acc = cfma<T>(acc, mk<T>((T)al.x, (T)-al.y), rv);
       }
     }
     tile[c][sub + 4 * s] = acc;
@@ -470,11 +480,16 @@ inline unsigned blocks_for(size_t total, int nt) { return (unsigned)((total + nt
 
 template <typename T>
 hipError_t launch_apply_Q(const StencilTables& S, const C<T>* r, int nrhs, C<T>* f, bool interleaved,
-                          hipStream_t st) {
+                          hipStream_t st, const double2* const* r64) {
   if (interleaved) {
-    hipLaunchKernelGGL(k_apply_Q_il<T>, dim3((S.L + 63) / 64, S.L, (nrhs + 15) / 16), dim3(256), 0, st, S, r, nrhs, f);
+    const dim3 g((S.L + 63) / 64, S.L, (nrhs + 15) / 16);
+    if (r64)
+      hipLaunchKernelGGL((k_apply_Q_il<T, true>), g, dim3(256), 0, st, S, r, nrhs, f, r64);
+    else
+      hipLaunchKernelGGL((k_apply_Q_il<T, false>), g, dim3(256), 0, st, S, r, nrhs, f, r64);
     return hipGetLastError();
   }
+  if (r64) return hipErrorInvalidValue;
   const size_t tot = (size_t)S.L * S.L * nrhs;
   hipLaunchKernelGGL(k_apply_Q<T>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, S, r, nrhs, f);
   return hipGetLastError();
@@ -515,7 +530,8 @@ hipError_t launch_sweep(const SliceTables& P, int L, int b, const C<T>* FS, cons
 }
 
 #define LSW_INST(T)                                                                                  \
-  template hipError_t launch_apply_Q<T>(const StencilTables&, const C<T>*, int, C<T>*, bool, hipStream_t); \
+  template hipError_t launch_apply_Q<T>(const StencilTables&, const C<T>*, int, C<T>*, bool, hipStream_t,    \
+                                        const double2* const*);                                               \
   template hipError_t launch_apply_H<T>(const StencilTables&, const C<T>*, int, C<T>*, hipStream_t); \
   template hipError_t launch_extract<T>(int, int, const C<T>*, int, C<T>*, bool, hipStream_t);       \
   template hipError_t launch_factor_slices<T>(const StencilTables&, const SliceTables&, C<T>*,       \
