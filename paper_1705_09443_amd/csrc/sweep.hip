@@ -125,26 +125,38 @@ __global__ __launch_bounds__(256) void k_apply_Q_il(StencilTables S, const C<T>*
   const int t = threadIdx.x, c = t & 63, sub = t >> 6;
   const int i2 = c0 + c - b;
   const bool type1 = i1 >= 0 && i1 <= n + 1 && c0 + c < L && i2 >= 0 && i2 <= n + 1;
+  // the nine taps of a right-hand side are loaded together from clamped
+  // in-range addresses and masked afterwards (taps off the interior, rows of
+  // the PML and right-hand sides past nrhs contribute zero)
+  bool ok[9];
+  size_t at[9];
+#pragma unroll
+  for (int o = 0; o < 9; ++o) {
+    const int j1 = i1 + o / 3 - 1, j2 = i2 + o % 3 - 1;
+    ok[o] = type1 && j1 >= 1 && j1 <= n && j2 >= 1 && j2 <= n;
+    at[o] = (size_t)(min(max(j1, 1), n) - 1) * n + (min(max(j2, 1), n) - 1);
+  }
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
-    const int rr = q0 + sub + 4 * s;
+    const int rr = q0 + sub + 4 * s, rq = min(rr, nrhs - 1);
+    C<T> rv[9];
+    if (R64) {
+      // the grids are device memory: global loads, not flat ones
+      using G64 = const __attribute__((address_space(1))) double;
+      G64* rp64 = (G64*)r64[rq];
+#pragma unroll
+      for (int o = 0; o < 9; ++o) rv[o] = mk<T>((T)rp64[2 * at[o]], (T)rp64[2 * at[o] + 1]);
+    } else {
+      const C<T>* rp = r + (size_t)rq * n * n;
+#pragma unroll
+      for (int o = 0; o < 9; ++o) rv[o] = rp[at[o]];
+    }
     C<T> acc = mk<T>(0, 0);
-    if (type1 && rr < nrhs) {
-      const C<T>* rp = R64 ? nullptr : r + (size_t)rr * n * n;
-      const double2* rp64 = R64 ? r64[rr] : nullptr;
-      for (int o = 0; o < 9; ++o) {
-        const int j1 = i1 + o / 3 - 1, j2 = i2 + o % 3 - 1;
-        if (j1 < 1 || j1 > n || j2 < 1 || j2 > n) continue;
+#pragma unroll
+    for (int o = 0; o < 9; ++o) {
+      if (ok[o] && rr < nrhs) {
         const double2 al = S.alpha[o];
-        const size_t at = (size_t)(j1 - 1) * n + (j2 - 1);
-        C<T> rv;
-        if (R64) {
-          const double2 d = rp64[at];
-          rv = mk<T>((T)d.x, (T)d.y);
-        } else {
-          rv = rp[at];
-        }
-        acc = cfma<T>(acc, mk<T>((T)al.x, (T)-al.y), rv);
+        acc = cfma<T>(acc, mk<T>((T)al.x, (T)-al.y), rv[o]);
       }
     }
     tile[c][sub + 4 * s] = acc;
