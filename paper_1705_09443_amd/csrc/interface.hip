@@ -625,35 +625,76 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(IfaceProd<T> pa, IfacePr
 }
 
 // f on the first line of D_k -= Hm_k lambda_{k-1}; on its last line -= Hp_k mu_{k+1}.
-// f interleaved [L][L][nrhs]; one thread per (slice, j, right-hand side), the
-// right-hand side fastest.
+// f interleaved [L][L][nrhs]. A workgroup takes one slice (blockIdx.y), 64
+// positions j along the line and 16 right-hand sides: the three taps of each
+// vector are read along j, the sums cross LDS and leave with the right-hand
+// side fastest, as f is laid out.
 template <typename T>
-__global__ void k_couple(SliceTables P, int L, int b, const C<T>* __restrict__ Hm, const C<T>* __restrict__ Hp,
-                         const C<T>* __restrict__ lam, const C<T>* __restrict__ mu, int nrhs, C<T>* f, int k0,
-                         int kcount) {
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const size_t tot = (size_t)kcount * nrhs * L;
-  if (idx >= tot) return;
-  const int r = (int)(idx % nrhs);
-  const int j = (int)((idx / nrhs) % L);
-  const int k = k0 + (int)(idx / ((size_t)L * nrhs));
-  if (k > 0) {
-    const C<T>* lv = lam + ((size_t)(k - 1) * nrhs + r) * iface_vec_len(L);
-    const C<T>* hm = Hm + ((size_t)k * L + j) * 3;
-    C<T> acc = mk<T>(0, 0);
-    for (int d = -1; d <= 1; ++d)
-      if (j + d >= 0 && j + d < L) acc = cfma<T>(acc, hm[d + 1], lv[j + d]);
-    C<T>* o = f + ((size_t)(P.lo[k] + b) * L + j) * nrhs + r;
-    *o = csub<T>(*o, acc);
+__global__ __launch_bounds__(256) void k_couple(SliceTables P, int L, int b, const C<T>* __restrict__ Hm,
+                                                const C<T>* __restrict__ Hp, const C<T>* __restrict__ lam,
+                                                const C<T>* __restrict__ mu, int nrhs, C<T>* f, int k0, int kcount) {
+  __shared__ C<T> tm[64][17], tp[64][17];
+  const int k = k0 + (int)blockIdx.y;
+  if ((int)blockIdx.y >= kcount) return;
+  const int j0 = blockIdx.x * 64, q0 = blockIdx.z * 16;
+  const int t = threadIdx.x, c = t & 63, sub = t >> 6, j = j0 + c;
+  const int Lp = iface_vec_len(L);
+  const bool hasm = k > 0, hasp = k < P.nslices - 1;
+  // coefficients of this position (zero off the line: those taps are masked)
+  C<T> cm[3], cp[3];
+  int at[3];
+  bool ok[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int jj = j + d - 1;
+    ok[d] = j < L && jj >= 0 && jj < L;
+    at[d] = min(max(jj, 0), L - 1);
+    const size_t co = ((size_t)k * L + min(j, L - 1)) * 3 + d;
+    cm[d] = hasm ? Hm[co] : mk<T>(0, 0);
+    cp[d] = hasp ? Hp[co] : mk<T>(0, 0);
   }
-  if (k < P.nslices - 1) {
-    const C<T>* mv = mu + ((size_t)(k + 1) * nrhs + r) * iface_vec_len(L);
-    const C<T>* hp = Hp + ((size_t)k * L + j) * 3;
-    C<T> acc = mk<T>(0, 0);
-    for (int d = -1; d <= 1; ++d)
-      if (j + d >= 0 && j + d < L) acc = cfma<T>(acc, hp[d + 1], mv[j + d]);
-    C<T>* o = f + ((size_t)(P.hi[k] + b) * L + j) * nrhs + r;
-    *o = csub<T>(*o, acc);
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int rr = q0 + sub + 4 * s, rq = min(rr, nrhs - 1);
+    C<T> am = mk<T>(0, 0), ap = mk<T>(0, 0);
+    if (hasm) {
+      const C<T>* lv = lam + ((size_t)(k - 1) * nrhs + rq) * Lp;
+      C<T> v[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v[d] = lv[at[d]];
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (ok[d]) am = cfma<T>(am, cm[d], v[d]);
+    }
+    if (hasp) {
+      const C<T>* mv = mu + ((size_t)(k + 1) * nrhs + rq) * Lp;
+      C<T> v[3];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) v[d] = mv[at[d]];
+#pragma unroll
+      for (int d = 0; d < 3; ++d)
+        if (ok[d]) ap = cfma<T>(ap, cp[d], v[d]);
+    }
+    tm[c][sub + 4 * s] = am;
+    tp[c][sub + 4 * s] = ap;
+  }
+  __syncthreads();
+  const int lo = P.lo[k] + b, hi = P.hi[k] + b;
+#pragma unroll
+  for (int s = 0; s < 4; ++s) {
+    const int idx = t + 256 * s;
+    const int rr = idx & 15, cc = idx >> 4;
+    const int e2 = j0 + cc, q = q0 + rr;
+    if (e2 < L && q < nrhs) {
+      if (hasm) {
+        C<T>* o = f + ((size_t)lo * L + e2) * nrhs + q;
+        *o = csub<T>(*o, tm[cc][rr]);
+      }
+      if (hasp) {
+        C<T>* o = f + ((size_t)hi * L + e2) * nrhs + q;
+        *o = csub<T>(*o, tp[cc][rr]);
+      }
+    }
   }
 }
 
@@ -784,9 +825,8 @@ template <typename T>
 hipError_t launch_couple(const SliceTables& P, int L, int b, const C<T>* Hm, const C<T>* Hp, const C<T>* lam,
                          const C<T>* mu, int nrhs, C<T>* f, int k0, int k1, hipStream_t st) {
   if (k1 <= k0) return hipSuccess;
-  const size_t tot = (size_t)(k1 - k0) * nrhs * L;
-  hipLaunchKernelGGL(k_couple<T>, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, st, P, L, b, Hm, Hp, lam, mu,
-                     nrhs, f, k0, k1 - k0);
+  hipLaunchKernelGGL(k_couple<T>, dim3((L + 63) / 64, k1 - k0, (nrhs + 15) / 16), dim3(256), 0, st, P, L, b, Hm, Hp,
+                     lam, mu, nrhs, f, k0, k1 - k0);
   return hipGetLastError();
 }
 template hipError_t launch_couple<double>(const SliceTables&, int, int, const double2*, const double2*,
