@@ -168,14 +168,17 @@ __global__ __launch_bounds__(kThreads) void k_axpys_dots(const AxpyOut* __restri
   double2 c[KT], d[KT];
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
-    const AxpyTerm<double> tm = terms[o.tbeg + (k < cnt ? k : 0)];
-    xs[k] = reinterpret_cast<const double2*>(tm.x);
-    c[k] = coefs[tm.coef];
-    if (tm.negate) {
-      c[k].x = -c[k].x;
-      c[k].y = -c[k].y;
+    xs[k] = nullptr;
+    c[k] = d[k] = make_double2(0.0, 0.0);
+    if (k < cnt) {
+      const AxpyTerm<double> tm = terms[o.tbeg + k];
+      xs[k] = reinterpret_cast<const double2*>(tm.x);
+      c[k] = coefs[tm.coef];
+      if (tm.negate) {
+        c[k].x = -c[k].x;
+        c[k].y = -c[k].y;
+      }
     }
-    d[k] = make_double2(0.0, 0.0);
   }
   for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < N; i += (size_t)gridDim.x * kThreads) {
     double2 xv[KT];
