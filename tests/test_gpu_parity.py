@@ -368,3 +368,40 @@ def test_solve_long_arnoldi_cycles(b, restart):
         assert rel(ref.op.apply_A(u[j]), gj) <= 1.01e-10
         if info[j].iterations == res.iterations:                     # P1
             assert rel(u[j], res.x) <= 1e-10
+
+
+def test_solve_sequential_schedule(case):
+    """Whole solves with the sequential sweep. In 2D the Arnoldi step takes
+    its cast-copy path there: v_j narrowed into a c64 buffer before Q, and A z
+    widened into the float64 work vector after the FFT. Under the interface
+    schedule those casts happen inside the Q stencil and the FFT epilogue.
+    Both schedules must give the oracle's iteration counts (P2) and agree
+    with each other: float64 to 1e-10 at equal counts, mixed within the
+    tolerance."""
+    from paper_1705_09443_amd import LSSolver
+    name, wl, m, ref, g64, g32 = case
+    if name != "c0":
+        pytest.skip("one case suffices")
+    b, w = CASES[name][2], CASES[name][3]
+    uinc = wl.incident()
+    md = torch.as_tensor(m).cuda()
+    say(f"[{name}] ls_solve, sequential schedule, fp64 and mixed")
+    with LSSolver(md, wl.omega, b, w, precision="fp64", schedule="sequential") as s64, \
+            LSSolver(md, wl.omega, b, w, precision="mixed", schedule="sequential") as s32:
+        us, infos = s64.solve(to_dev(uinc), "incident", 1e-8)
+        us32, infos32 = s32.solve(to_dev(uinc), "incident", 1e-8)
+    ui, infoi = g64.solve(to_dev(uinc), "incident", 1e-8)
+    ui32, infoi32 = g32.solve(to_dev(uinc), "incident", 1e-8)
+    us, us32, ui, ui32 = (x.cpu().numpy() for x in (us, us32, ui, ui32))
+    for j in range(uinc.shape[0]):
+        gj = ref.op.rhs_incident(uinc[j])
+        res = ref.solve_rhs(gj, 1e-8)
+        say(f"  rhs {j}: iterations seq {infos[j].iterations} / {infos32[j].iterations}, "
+            f"interface {infoi[j].iterations} / {infoi32[j].iterations}, oracle {res.iterations}")
+        assert abs(infos[j].iterations - res.iterations) <= 1
+        assert abs(infos32[j].iterations - res.iterations) <= 2
+        for u in (us[j], us32[j]):
+            assert rel(ref.op.apply_A(u), gj) <= 1.01e-8
+        if infos[j].iterations == infoi[j].iterations:
+            assert rel(us[j], ui[j]) <= 1e-10
+        assert rel(us32[j], ui32[j]) <= 1e-6
