@@ -455,7 +455,9 @@ ls_status upload(const ls_handle* h, DBuf& dst, const std::vector<X>& src) {
 
 // ---- the applies, on contiguous batches ------------------------------------
 template <typename T>
-ls_status apply_A(ls_handle* h, const C<T>* x, int nb, C<T>* y, double2* const* y64 = nullptr) {
+// y64, xp (2D only): per-right-hand-side output (float64) and input grids
+ls_status apply_A(ls_handle* h, const C<T>* x, int nb, C<T>* y, double2* const* y64 = nullptr,
+                  const C<T>* const* xp = nullptr) {
   Timed tm(h, kKFft, nb);
   if (h->dim == 3) {
     LSW_HIP_TRY(launch_convolve3<T>(x, Prec<T>::m(h), h->n, nb, Prec<T>::khat3(h), Prec<T>::tw(h), (T)1,
@@ -463,7 +465,7 @@ ls_status apply_A(ls_handle* h, const C<T>* x, int nb, C<T>* y, double2* const* 
     return LS_OK;
   }
   LSW_HIP_TRY(launch_convolve<T>(x, Prec<T>::m(h), h->n, nb, Prec<T>::khat(h), Prec<T>::tw(h), (T)1,
-                                 (T)(h->omega * h->omega), Prec<T>::fftw(h), y, h->st, y64));
+                                 (T)(h->omega * h->omega), Prec<T>::fftw(h), y, h->st, y64, xp));
   return LS_OK;
 }
 
@@ -647,9 +649,11 @@ ls_status apply_P3(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
 
 // z = P r (Algorithm 2), interface schedule or slice by slice.
 // r64 (2D interface schedule only): right-hand side q read from the float64
-// grid r64[q] (a device pointer array), narrowed by the Q stencil (r unused)
+// grid r64[q] (a device pointer array), narrowed by the Q stencil (r unused);
+// zp (same condition): right-hand side q of z written to the grid zp[q]
 template <typename T>
-ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* const* r64 = nullptr) {
+ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* const* r64 = nullptr,
+                  C<T>* const* zp = nullptr) {
   if (h->dim == 3) return apply_P3<T>(h, r, nb, z);
   const StencilTables S = h->stencils();
   C<T>* f = h->fext.as<C<T>>();
@@ -807,7 +811,7 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* c
   }
   {
     Timed tm(h, kKExtract, nb);
-    LSW_HIP_TRY(launch_extract<T>(h->n, h->b, u, nb, z, il, h->st));
+    LSW_HIP_TRY(launch_extract<T>(h->n, h->b, u, nb, z, il, h->st, zp));
   }
   return LS_OK;
 }
@@ -1121,17 +1125,18 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     LSW_HIP_TRY(sm.flush(st));
     // coefs[0] = 1 (the unit coefficient of the normalisation below)
     LSW_HIP_TRY(hipMemcpyAsync(coefs, one_d, sizeof(double2), hipMemcpyDeviceToDevice, st));
-    // z = P v_j (precision T), kept in Z; in 2D with the interface schedule
-    // the Q stencil reads v_j in float64 itself
+    // z = P v_j (precision T), kept in Z. In 2D with the interface schedule
+    // the Q stencil reads v_j in float64 itself and the extraction writes z
+    // into its slot of Z, which the operator then reads
     const bool q64 = h->dim == 2 && h->opt.sweep_schedule != LS_SWEEP_SEQUENTIAL;
     if (!q64) LSW_HIP_TRY((launch_copy_cast<T, double>(cin_d, cin_s, na, N, st)));
-    ls_status e = apply_P<T>(h, vin, na, zout, q64 ? cin_s : nullptr);
+    ls_status e = apply_P<T>(h, vin, na, zout, q64 ? cin_s : nullptr, q64 ? cz_d : nullptr);
     if (e != LS_OK) return e;
-    LSW_HIP_TRY((launch_copy_cast<T, T>(cz_d, cz_s, na, N, st)));
+    if (!q64) LSW_HIP_TRY((launch_copy_cast<T, T>(cz_d, cz_s, na, N, st)));
     // w = A z (precision T) -> float64 work vector W[r]; in 2D the
     // convolution's epilogue writes W[r] itself
     if (h->dim == 2) {
-      if ((e = apply_A<T>(h, zout, na, aout, cw_d)) != LS_OK) return e;
+      if ((e = apply_A<T>(h, zout, na, aout, cw_d, q64 ? cz_d : nullptr)) != LS_OK) return e;
     } else {
       if ((e = apply_A<T>(h, zout, na, aout)) != LS_OK) return e;
       LSW_HIP_TRY((launch_copy_cast<double, T>(cw_d, cw_s, na, N, st)));

@@ -182,6 +182,23 @@ __device__ inline void load_twiddles(C<T>* twl, const C<T>* __restrict__ tw, int
   }
 }
 
+// Element i of a complex grid in device memory, read or written through a
+// global-address-space pointer: grids named by pointer tables would otherwise
+// be reached with flat loads and stores.
+template <typename T>
+__device__ __attribute__((always_inline)) inline C<T> gld(const C<T>* p, size_t i) {
+  using G = const __attribute__((address_space(1))) T;
+  const G* q = (const G*)p;
+  return mk<T>(q[2 * i], q[2 * i + 1]);
+}
+template <typename T>
+__device__ __attribute__((always_inline)) inline void gst(C<T>* p, size_t i, C<T> v) {
+  using G = __attribute__((address_space(1))) T;
+  G* q = (G*)p;
+  q[2 * i] = v.x;
+  q[2 * i + 1] = v.y;
+}
+
 // Global <-> LDS copies: every thread moves at most kVals elements; the
 // loops are unrolled with clamped, unconditional loads (values masked after)
 // so that all of a thread's loads are in flight before the first is used.
@@ -200,7 +217,7 @@ __device__ __attribute__((always_inline)) inline void load_rows(C<T>* buf, const
     const int sq = idx >> lP, k = idx & (P - 1), row = i0 + sq;
     const bool ok = idx < total && k < n && row < n;
     const size_t o = (size_t)(row < n ? row : n - 1) * n + (k < n ? k : n - 1);
-    C<T> w = xr[o];
+    C<T> w = gld<T>(xr, o);
     if (HASM) w = cscale<T>(w, m[o]);
     v[q] = ok ? w : mk<T>(0, 0);
   }
@@ -212,9 +229,11 @@ __device__ __attribute__((always_inline)) inline void load_rows(C<T>* buf, const
 }
 
 // ---- pass 1: rows of (s .* x), zero-padded to P -----------------------------
+// xp: right-hand side r read from the grid xp[r] instead of x
 template <typename T>
 __global__ __launch_bounds__(kFftMaxThreads) void k_row_forward(const C<T>* __restrict__ x, const T* __restrict__ m, int n, int P,
-                              int S, const C<T>* __restrict__ tw, C<T>* __restrict__ X) {
+                              int S, const C<T>* __restrict__ tw, C<T>* __restrict__ X,
+                              const C<T>* const* __restrict__ xp) {
   extern __shared__ unsigned char smem_raw[];
   C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
   C<T>* twl = buf + S * P;
@@ -222,7 +241,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_forward(const C<T>* __re
   const int rhs = blockIdx.y;
   const int i0 = blockIdx.x * S;
   const size_t nn = (size_t)n * n;
-  const C<T>* xr = x + rhs * nn;
+  const C<T>* xr = xp ? xp[rhs] : x + rhs * nn;
   if (m)
     load_rows<T, true>(buf, xr, m, n, P, S, i0);
   else
@@ -305,10 +324,12 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_col_convolve(C<T>* __restric
 
 // ---- pass 3: inverse rows and epilogue y = a x + coef * conv --------------
 // W64: right-hand side r written, widened, to y64[r] instead of y
+// xp: right-hand side r of x read from the grid xp[r]
 template <typename T, bool W64>
 __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __restrict__ X, const C<T>* __restrict__ x, int n, int P,
                               int S, const C<T>* __restrict__ tw, T a, T coef,
-                              C<T>* __restrict__ y, double2* const* __restrict__ y64) {
+                              C<T>* __restrict__ y, double2* const* __restrict__ y64,
+                              const C<T>* const* __restrict__ xp) {
   constexpr int V = kVals<T>;
   extern __shared__ unsigned char smem_raw[];
   C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
@@ -345,13 +366,14 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __re
   lds_fft<T>(buf, P, S, twl, true);
   const size_t nn = (size_t)n * n;
   const int live = S * n;
+  const C<T>* xr = xp ? xp[rhs] : x + rhs * nn;
   C<T> xv[V];
 #pragma unroll
   for (int q = 0; q < V; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
     const int sq = idx / n, k = idx % n, row = i0 + sq;
     const bool ok = idx < live && row < n;
-    xv[q] = a != T(0) ? x[ok ? rhs * nn + (size_t)row * n + k : 0] : mk<T>(0, 0);
+    xv[q] = a != T(0) ? gld<T>(xr, ok ? (size_t)row * n + k : 0) : mk<T>(0, 0);
   }
 #pragma unroll
   for (int q = 0; q < V; ++q) {
@@ -360,7 +382,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __re
     if (idx < live && row < n) {
       const C<T> v = cadd<T>(cscale<T>(buf[k * S + sq], coef), cscale<T>(xv[q], a));
       if (W64)
-        y64[rhs][(size_t)row * n + k] = make_double2((double)v.x, (double)v.y);
+        gst<double>(y64[rhs], (size_t)row * n + k, make_double2((double)v.x, (double)v.y));
       else
         y[rhs * nn + (size_t)row * n + k] = v;
     }
@@ -634,7 +656,8 @@ template size_t fft_work_elems<float>(int, int);
 
 template <typename T>
 hipError_t launch_convolve(const C<T>* x, const T* m, int n, int nrhs, const C<T>* khat,
-                           const C<T>* tw, T a, T c, C<T>* work, C<T>* y, hipStream_t st, double2* const* y64) {
+                           const C<T>* tw, T a, T c, C<T>* work, C<T>* y, hipStream_t st, double2* const* y64,
+                           const C<T>* const* xp) {
   const int P = fft_len(n);
   const int S = seq_per_block<T>(P);
   const int nt = threads_for<T>(S, P);
@@ -647,20 +670,20 @@ hipError_t launch_convolve(const C<T>* x, const T* m, int n, int nrhs, const C<T
   if ((e = allow_lds(k_row_inverse<T, true>, lds)) != hipSuccess) return e;
   const T coef = c / ((T)P * (T)P);
   dim3 grow((n + S - 1) / S, nrhs), gcol(P / S, nrhs);
-  hipLaunchKernelGGL(k_row_forward<T>, grow, dim3(nt), lds, st, x, m, n, P, S, tw, work);
+  hipLaunchKernelGGL(k_row_forward<T>, grow, dim3(nt), lds, st, x, m, n, P, S, tw, work, xp);
   hipLaunchKernelGGL(k_col_convolve<T>, gcol, dim3(nt), lds, st, work, khat, n, P, S, tw);
   if (y64)
-    hipLaunchKernelGGL((k_row_inverse<T, true>), grow, dim3(nt), lds, st, work, x, n, P, S, tw, a, coef, y, y64);
+    hipLaunchKernelGGL((k_row_inverse<T, true>), grow, dim3(nt), lds, st, work, x, n, P, S, tw, a, coef, y, y64, xp);
   else
-    hipLaunchKernelGGL((k_row_inverse<T, false>), grow, dim3(nt), lds, st, work, x, n, P, S, tw, a, coef, y, y64);
+    hipLaunchKernelGGL((k_row_inverse<T, false>), grow, dim3(nt), lds, st, work, x, n, P, S, tw, a, coef, y, y64, xp);
   return hipGetLastError();
 }
 template hipError_t launch_convolve<double>(const double2*, const double*, int, int, const double2*,
                                             const double2*, double, double, double2*, double2*,
-                                            hipStream_t, double2* const*);
+                                            hipStream_t, double2* const*, const double2* const*);
 template hipError_t launch_convolve<float>(const float2*, const float*, int, int, const float2*,
                                            const float2*, float, float, float2*, float2*, hipStream_t,
-                                           double2* const*);
+                                           double2* const*, const float2* const*);
 
 hipError_t launch_green_spectrum(const double2* kq, int n, const double2* tw, double2* scratch,
                                  double2* khat, float2* khat32, hipStream_t st) {

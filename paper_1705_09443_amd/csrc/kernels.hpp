@@ -16,11 +16,13 @@ template <typename T>
 size_t fft_work_elems(int n, int nrhs);
 // y = a x + c * K (s .* x) on [nrhs][n][n]; s = m or 1 (m == nullptr).
 // With y64 (a device array of nrhs pointers to n x n float64 grids), right-hand
-// side r goes to y64[r] instead, formed in T and then widened (y unused).
+// side r goes to y64[r] instead, formed in T and then widened (y unused). With
+// xp (nrhs pointers to n x n grids), right-hand side r is read from xp[r]
+// instead of x.
 template <typename T>
 hipError_t launch_convolve(const C<T>* x, const T* m, int n, int nrhs, const C<T>* khat,
                            const C<T>* tw, T a, T c, C<T>* work, C<T>* y, hipStream_t st,
-                           double2* const* y64 = nullptr);
+                           double2* const* y64 = nullptr, const C<T>* const* xp = nullptr);
 // khat (quadrant (P/2+1)^2) from the table quadrant kq [(n+2)][(n+2)].
 hipError_t launch_green_spectrum(const double2* kq, int n, const double2* tw, double2* scratch,
                                  double2* khat, float2* khat32, hipStream_t st);
@@ -77,7 +79,10 @@ hipError_t launch_apply_Q(const StencilTables& S, const C<T>* r, int nrhs, C<T>*
 template <typename T>
 hipError_t launch_apply_H(const StencilTables& S, const C<T>* u, int nrhs, C<T>* y, hipStream_t st);
 template <typename T>
-hipError_t launch_extract(int n, int b, const C<T>* uext, int nrhs, C<T>* z, bool interleaved, hipStream_t st);
+// With zp (interleaved only: a device array of nrhs pointers to n x n grids),
+// right-hand side q is written to zp[q] instead of z.
+hipError_t launch_extract(int n, int b, const C<T>* uext, int nrhs, C<T>* z, bool interleaved, hipStream_t st,
+                          C<T>* const* zp = nullptr);
 // Assemble and factor every slice subproblem (one workgroup per slice);
 // writes FS, FG, the coupling rows Hm, Hp ([nslices][L][3]) and status
 // (nonzero: a zero pivot was met).

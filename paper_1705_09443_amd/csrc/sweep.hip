@@ -173,9 +173,10 @@ __global__ __launch_bounds__(256) void k_apply_Q_il(StencilTables S, const C<T>*
 
 // z[nrhs][n][n] = the interior of the interleaved u[e1][e2][nrhs], through LDS
 // as in k_apply_Q_il.
+// zp: right-hand side q written to the grid zp[q] instead of z
 template <typename T>
 __global__ __launch_bounds__(256) void k_extract_il(int n, int b, const C<T>* __restrict__ uext, int nrhs,
-                                                    C<T>* __restrict__ z) {
+                                                    C<T>* __restrict__ z, C<T>* const* __restrict__ zp) {
   __shared__ C<T> tile[16][65];
   const int L = n + 2 + 2 * b;
   const int c0 = blockIdx.x * 64, a1 = blockIdx.y, q0 = blockIdx.z * 16;
@@ -192,7 +193,18 @@ __global__ __launch_bounds__(256) void k_extract_il(int n, int b, const C<T>* __
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int rr = sub + 4 * s, q = q0 + rr;
-    if (c0 + c < n && q < nrhs) z[((size_t)q * n + a1) * n + c0 + c] = tile[rr][c];
+    if (c0 + c < n && q < nrhs) {
+      const size_t at = (size_t)a1 * n + c0 + c;
+      if (zp) {
+        // the grids are device memory: global stores, not flat ones
+        using G = __attribute__((address_space(1))) T;
+        G* zq = (G*)zp[q];
+        zq[2 * at] = tile[rr][c].x;
+        zq[2 * at + 1] = tile[rr][c].y;
+      } else {
+        z[(size_t)q * n * n + at] = tile[rr][c];
+      }
+    }
   }
 }
 
@@ -515,11 +527,14 @@ hipError_t launch_apply_H(const StencilTables& S, const C<T>* u, int nrhs, C<T>*
 }
 
 template <typename T>
-hipError_t launch_extract(int n, int b, const C<T>* uext, int nrhs, C<T>* z, bool interleaved, hipStream_t st) {
+hipError_t launch_extract(int n, int b, const C<T>* uext, int nrhs, C<T>* z, bool interleaved, hipStream_t st,
+                          C<T>* const* zp) {
   if (interleaved) {
-    hipLaunchKernelGGL(k_extract_il<T>, dim3((n + 63) / 64, n, (nrhs + 15) / 16), dim3(256), 0, st, n, b, uext, nrhs, z);
+    hipLaunchKernelGGL(k_extract_il<T>, dim3((n + 63) / 64, n, (nrhs + 15) / 16), dim3(256), 0, st, n, b, uext, nrhs, z,
+                       zp);
     return hipGetLastError();
   }
+  if (zp) return hipErrorInvalidValue;
   const size_t tot = (size_t)n * n * nrhs;
   hipLaunchKernelGGL(k_extract<T>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, n, b, uext, nrhs, z);
   return hipGetLastError();
@@ -545,7 +560,8 @@ hipError_t launch_sweep(const SliceTables& P, int L, int b, const C<T>* FS, cons
   template hipError_t launch_apply_Q<T>(const StencilTables&, const C<T>*, int, C<T>*, bool, hipStream_t,    \
                                         const double2* const*);                                               \
   template hipError_t launch_apply_H<T>(const StencilTables&, const C<T>*, int, C<T>*, hipStream_t); \
-  template hipError_t launch_extract<T>(int, int, const C<T>*, int, C<T>*, bool, hipStream_t);       \
+  template hipError_t launch_extract<T>(int, int, const C<T>*, int, C<T>*, bool, hipStream_t,        \
+                                        C<T>* const*);                                               \
   template hipError_t launch_factor_slices<T>(const StencilTables&, const SliceTables&, C<T>*,       \
                                               C<T>*, C<T>*, C<T>*, int*, hipStream_t);               \
   template hipError_t launch_sweep<T>(const SliceTables&, int, int, const C<T>*, const C<T>*,        \
