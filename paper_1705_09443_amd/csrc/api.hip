@@ -460,6 +460,10 @@ ls_status apply_A(ls_handle* h, const C<T>* x, int nb, C<T>* y, double2* const* 
                   const C<T>* const* xp = nullptr) {
   Timed tm(h, kKFft, nb);
   if (h->dim == 3) {
+    if (y64 || xp) {
+      set_error("internal: per-right-hand-side grids in a 3D operator apply");
+      return LS_E_STATE;
+    }
     LSW_HIP_TRY(launch_convolve3<T>(x, Prec<T>::m(h), h->n, nb, Prec<T>::khat3(h), Prec<T>::tw(h), (T)1,
                                     (T)(h->omega * h->omega), h->s3->w1.as<C<T>>(), h->s3->w2.as<C<T>>(), y, h->st));
     return LS_OK;
@@ -1243,7 +1247,8 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     DBuf& tb = std::is_same<T, double>::value ? h->terms64 : h->terms32;
     if (upload(h, tb, htT) != LS_OK) return LS_E_DEVICE;
     LSW_HIP_TRY(launch_axpys<T>(h->outs.as<AxpyOut>(), (int)ho.size(), tb.as<AxpyTerm<T>>(), coefs, N, st));
-    // pack x of the ending set, A x in float64, r = g - A x
+    // A x of the ending set in float64 (2D: read from X in place; 3D: packed
+    // into T1 first), r = g - A x
     const int ne = (int)ending.size();
     double2* T1 = h->T1.as<double2>();
     double2* T2 = h->T2.as<double2>();
@@ -1254,8 +1259,14 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       pb.push_back(Xb + (size_t)ending[p] * N);
     }
     if (upload(h, h->ptrs_a, pa) != LS_OK || upload(h, h->ptrs_b, pb) != LS_OK) return LS_E_DEVICE;
-    LSW_HIP_TRY((launch_copy_cast<double, double>(h->ptrs_a.as<double2*>(), h->ptrs_b.as<const double2*>(), ne, N, st)));
-    if ((e = apply_A<double>(h, T1, ne, T2)) != LS_OK) return e;
+    if (h->dim == 2) {
+      // the operator reads each x from its slot of X
+      if ((e = apply_A<double>(h, T1, ne, T2, nullptr, h->ptrs_b.as<const double2*>())) != LS_OK) return e;
+    } else {
+      LSW_HIP_TRY(
+          (launch_copy_cast<double, double>(h->ptrs_a.as<double2*>(), h->ptrs_b.as<const double2*>(), ne, N, st)));
+      if ((e = apply_A<double>(h, T1, ne, T2)) != LS_OK) return e;
+    }
     ho.clear();
     ht64.clear();
     for (int p = 0; p < ne; ++p) {
