@@ -54,6 +54,9 @@ def parse():
     p.add_argument("--no-cpu", action="store_true")
     p.add_argument("--no-3d", action="store_true", help="skip the 3D leg (127^3, four waves, mixed)")
     p.add_argument("--steps-3d", type=int, default=2)
+    p.add_argument("--no-adjoint", action="store_true",
+                   help="skip the adjoint leg (511^2, 32 waves, mixed: forward solve plus adjoint solve)")
+    p.add_argument("--steps-adjoint", type=int, default=3)
     p.add_argument("--no-autotune", action="store_true",
                    help="batched leg at the workload's w and the default kernels instead of autotuned ones")
     p.add_argument("--copy-gib", type=float, default=0.0,
@@ -218,6 +221,55 @@ def leg_3d(args, dev):
     return out
 
 
+def leg_adjoint(args, dev):
+    """The adjoint workload (511^2, 16 bumps, 32 plane waves, mixed precision):
+    one step is one gradient of the receiver misfit, that is the forward
+    solve (ls_solve) and the adjoint solve with the gradient product
+    (ls_adjoint), both to 1e-10. The receiver residual comes from the
+    warm-up's field against data from a second medium (bump seed 1), formed
+    before the timed region; the timed region holds only the two C-ABI calls
+    per step."""
+    import torch
+    import workloads
+    from paper_1705_09443_amd import LSSolver
+    wl = workloads.workload("C4")
+    n, tol = wl.n, 1e-10
+    uinc = torch.as_tensor(wl.incident(), device=dev)
+    rec = torch.as_tensor(workloads.circle_receivers(n, 0.4), device=dev)
+    with LSSolver(torch.as_tensor(wl.medium_array(seed=1), device=dev), wl.omega, wl.pml_width,
+                  wl.layer_thickness, precision="mixed") as sd:
+        ud, _ = sd.solve(uinc, "incident", tol)
+        data = ud[:, rec].clone()
+        del ud
+    t0 = time.perf_counter()
+    s = LSSolver(torch.as_tensor(wl.medium_array(), device=dev), wl.omega, wl.pml_width, wl.layer_thickness,
+                 precision="mixed")
+    torch.cuda.synchronize()
+    setup = time.perf_counter() - t0
+    u, info = s.solve(uinc, "incident", tol)  # warm-up: graphs, and the residual
+    r = torch.zeros_like(u)
+    r[:, rec] = u[:, rec] - data
+    g, ginfo = s.adjoint(r, tol)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps_adjoint):
+        u, info = s.solve(uinc, "incident", tol)
+        g, ginfo = s.adjoint(r, tol)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps_adjoint
+    assert all(x.converged for x in info) and all(x.converged for x in ginfo), "an adjoint-leg solve did not converge"
+    assert bool(torch.isfinite(g).all()), "non-finite gradient"
+    s.close()
+    return {"value": wl.nrhs * n * n / t, "unit": "unknowns*RHS/s (forward + adjoint solve per RHS)",
+            "ms_per_step": t * 1e3, "steps": args.steps_adjoint, "setup_s": setup,
+            "iterations": {"forward": [x.iterations for x in info], "adjoint": [x.iterations for x in ginfo]},
+            "config": {"workload": (f"2D {n}^2, omega=2pi*{wl.ppw_omega:g}, 16 Gaussian bumps (seed 0), "
+                                    f"{wl.nrhs} plane waves, receivers on the circle r=0.4, data from bump "
+                                    f"seed 1, mixed precision, b={wl.pml_width}, w={wl.layer_thickness}, "
+                                    f"restart {wl.restart}, tol {tol}: one gradient = ls_solve + ls_adjoint"),
+                       "n": n, "nrhs": wl.nrhs}}
+
+
 def cpu_baseline(wl, m, uinc):
     """The float64 oracle on the machine's host cores: its setup (not timed into
     the value, like the GPU's), then one full FGMRES solve of the first
@@ -377,6 +429,11 @@ def main():
     if not args.no_3d:
         out["c3"] = leg_3d(args, dev)
         print(f"[bench] 3D solve {out['c3']['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
+
+    # ---- adjoint (gradient) ----
+    if not args.no_adjoint:
+        out["c4_adjoint"] = leg_adjoint(args, dev)
+        print(f"[bench] adjoint gradient {out['c4_adjoint']['ms_per_step']:.1f} ms", file=sys.stderr, flush=True)
 
     # ---- CPU oracle on a bounded sample ----
     if not args.no_cpu:

@@ -1,0 +1,76 @@
+"""The adjoint workload at full size: 511^2 interior points, omega = 2 pi 32,
+16 Gaussian bumps, 32 plane waves, mixed precision (complex64 applies inside
+float64 FGMRES), PML b = 12, layers w = 4.
+
+Misfit J(m) = 1/2 sum_j |R u_j(m) - d_j|^2 over receivers on the circle of
+radius 0.4, data d from the field of a second medium (bump seed 1). The
+gradient comes from ls_solve then ls_adjoint (eq. LS_d_c and its adjoint).
+
+The oracle cannot run 64 solves at this size in a test, so the check is a
+property that holds at any size. Along two seeded directions dm, the central
+difference (J(m + eps dm) - J(m - eps dm)) / (2 eps), each J from GPU solves
+to 1e-10, matches <dJ/dm, dm> to 1e-4. With eps = 1e-4 and max|dm| = 1, the
+difference's truncation error is O(eps^2) and the solves contribute about
+tol / eps = 1e-6 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import workloads
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-10
+EPS = 1e-4
+
+
+def say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _misfit(s, uinc, rec, data):
+    u, info = s.solve(uinc, "incident", TOL)
+    assert all(i.converged and i.rel_residual <= TOL for i in info)
+    r = torch.zeros_like(u)
+    r[:, rec] = u[:, rec] - data
+    return 0.5 * float((r.abs() ** 2).sum()), r, info
+
+
+def test_c4_gradient_central_differences():
+    from paper_1705_09443_amd import LSSolver
+    wl = workloads.workload("C4")
+    n, omega, b, w = wl.n, wl.omega, wl.pml_width, wl.layer_thickness
+    dev = torch.device("cuda:0")
+    m = wl.medium_array()
+    uinc = torch.as_tensor(wl.incident(), device=dev)
+    rec = torch.as_tensor(workloads.circle_receivers(n, 0.4), device=dev)
+    say(f"[c4] data from the second medium, n={n}, {wl.nrhs} waves")
+    with LSSolver(torch.as_tensor(wl.medium_array(seed=1), device=dev), omega, b, w, precision="mixed") as sd:
+        ud, info = sd.solve(uinc, "incident", TOL)
+        assert all(i.converged for i in info)
+        data = ud[:, rec].clone()
+    say("[c4] misfit and gradient")
+    with LSSolver(torch.as_tensor(m, device=dev), omega, b, w, precision="mixed") as s:
+        J0, r, info = _misfit(s, uinc, rec, data)
+        g, ginfo = s.adjoint(r, TOL)
+    assert all(i.converged and i.rel_residual <= TOL for i in ginfo)
+    g = g.cpu().numpy()
+    say(f"[c4] J = {J0:.6e}; forward iterations {min(i.iterations for i in info)}.."
+        f"{max(i.iterations for i in info)}, adjoint {min(i.iterations for i in ginfo)}.."
+        f"{max(i.iterations for i in ginfo)}")
+    assert np.isfinite(g).all() and np.abs(g).max() > 0
+    for k, dm in enumerate(workloads.fd_directions(n, 2, 2, seed=7)):
+        js = []
+        for sign in (1.0, -1.0):
+            with LSSolver(torch.as_tensor(m + sign * EPS * dm, device=dev), omega, b, w, precision="mixed") as sp:
+                js.append(_misfit(sp, uinc, rec, data)[0])
+        fd = (js[0] - js[1]) / (2 * EPS)
+        an = float(np.sum(g * dm))
+        rel = abs(fd - an) / abs(an)
+        say(f"[c4] direction {k}: central difference {fd:.10e}, adjoint {an:.10e}, relative {rel:.2e}")
+        assert rel <= 1e-4
