@@ -96,7 +96,10 @@ void ls_default_options(ls_options* opts);
  * (eq. gamma) for the global PML and for the auxiliary PML at the sampled
  * local frequencies, slices the extended grid along i1 into floor((n+2)/w)
  * slices, and factors every moving-PML slice subproblem (eq. Hwv_approx).
- *   grid             dim and n
+ *   grid             dim and n; in 2D 1 <= n <= 2047 (the zero-padded FFT
+ *                    length P = 2^k >= 2(n+1) is at most 4096: one complex128
+ *                    sequence of length P and its twiddles fill the LDS of a
+ *                    compute unit), LS_E_INVALID otherwise
  *   omega            angular frequency, > 0
  *   m_dev            float64 [n][n] perturbation m = 1 - 1/c^2 on the interior grid;
  *                    every value finite and < 1

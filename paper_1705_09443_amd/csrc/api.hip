@@ -1896,8 +1896,10 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
     h->st = static_cast<hipStream_t>(o.hip_stream);
     LSW_HIP_TRY(hipGetDevice(&h->device));
     const int n = grid->n;
-    if (n < 1 || n > 16383) {
-      set_error("n must be in [1, 16383]");
+    // the FFT passes hold S >= 1 complex128 sequences of length P plus the
+    // twiddles in LDS: (S + 1) P 16 bytes <= 160 KB, so P <= 4096
+    if (n < 1 || fft_len(n) > 4096) {
+      set_error("n must be in [1, 2047] in 2D (FFT length at most 4096)");
       return LS_E_INVALID;
     }
     std::vector<double> mh((size_t)n * n);
