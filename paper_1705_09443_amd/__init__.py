@@ -26,7 +26,7 @@ from ._lib import (LS_FP64, LS_MIXED, LS_RHS_INCIDENT, LS_RHS_SOURCE, LsError, L
                    LsRhsInfo, LsSetupInfo)
 
 __all__ = ["LSSolver", "LSSolve", "LSOperator3", "RhsInfo", "LsError", "host_tables", "host_green3",
-           "host_tables3", "layer_candidates"]
+           "host_tables3", "layer_candidates", "stencil_cache"]
 
 _PRECISIONS = {"fp64": LS_FP64, "mixed": LS_MIXED}
 
@@ -335,6 +335,17 @@ def host_tables(m, omega: float, pml_width: int, layer_thickness: int, pml_C: fl
     c = lambda v: v.view(np.complex128)
     return dict(alpha=c(a), beta=c(be), gamma=c(g).reshape(nc, nc, 9), aux=c(ax).reshape(b, nc, ns, 9),
                 kmap=km, green=c(gr).reshape(n + 2, n + 2))
+
+
+def stencil_cache(clear: bool = False):
+    """(hits, misses) of the 2D stencil cache since the last clear; clear=True
+    empties it afterwards."""
+    import ctypes
+    lib = _lib.load()
+    hits, misses = ctypes.c_longlong(0), ctypes.c_longlong(0)
+    _lib.check(lib.ls_stencil_cache(1 if clear else 0, ctypes.byref(hits), ctypes.byref(misses)),
+               "ls_stencil_cache")
+    return hits.value, misses.value
 
 
 def host_tables3(m, omega: float, pml_width: int, layer_thickness: int, pml_C: float = 10.0,

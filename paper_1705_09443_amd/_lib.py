@@ -94,6 +94,7 @@ _SIGNATURES = {
     "ls_set_kernels": (c_int, [c_void_p, c_int, c_int, c_int]),
     "ls_host_tables": (c_int, [c_int, c_double, c_void_p, c_int, c_int, c_double, c_int, c_void_p, c_void_p,
                                c_void_p, c_void_p, c_void_p, c_void_p]),
+    "ls_stencil_cache": (c_int, [c_int, ctypes.POINTER(ctypes.c_longlong), ctypes.POINTER(ctypes.c_longlong)]),
     "ls_host_tables3": (c_int, [c_int, c_double, c_void_p, c_int, c_int, c_double, c_int, c_void_p, c_void_p,
                                 c_void_p, c_void_p, c_void_p]),
     "ls_op3_create": (c_int, [c_int, c_double, c_void_p, c_void_p, ctypes.POINTER(c_void_p)]),

@@ -2465,6 +2465,11 @@ ls_status ls_op3_apply_K(ls_op3* h, const void* x_dev, int nrhs, void* y_dev, in
 
 void ls_op3_destroy(ls_op3* h) { delete h; }
 
+ls_status ls_stencil_cache(int clear, long long* hits, long long* misses) {
+  lsw::stencil_cache(clear != 0, hits, misses);
+  return LS_OK;
+}
+
 ls_status ls_host_tables(int n, double omega, const double* m_host, int pml_width, int layer_thickness,
                          double pml_C, int freq_samples, double* alpha, double* beta, double* gamma, double* aux,
                          int* kmap, double* green) {

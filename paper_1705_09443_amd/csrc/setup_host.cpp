@@ -8,6 +8,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <deque>
+#include <memory>
+#include <mutex>
 #include <thread>
 
 namespace lsw {
@@ -434,6 +437,55 @@ std::vector<cd> green3_octant(int n, double omega) {
   return kq;
 }
 
+namespace {
+
+// The velocity-independent 2D tables of one (n, omega, b, C), keys compared
+// exactly. Entries are immutable once inserted; the most recent is first.
+struct StencilEntry {
+  int n, b;
+  double omega, C;
+  std::vector<cd> kq, gamma_glob;
+  cd alpha[9], beta[9];
+  double alpha_sv[9];
+};
+std::mutex g_stencil_mu;
+std::deque<std::shared_ptr<const StencilEntry>> g_stencils;
+long long g_stencil_hits = 0, g_stencil_misses = 0;
+
+std::shared_ptr<const StencilEntry> stencil_find(int n, double omega, int b, double C) {
+  std::lock_guard<std::mutex> lk(g_stencil_mu);
+  for (size_t i = 0; i < g_stencils.size(); ++i) {
+    const auto& e = g_stencils[i];
+    if (e->n == n && e->b == b && e->omega == omega && e->C == C) {
+      auto hit = e;
+      g_stencils.erase(g_stencils.begin() + (long)i);
+      g_stencils.push_front(hit);
+      ++g_stencil_hits;
+      return hit;
+    }
+  }
+  ++g_stencil_misses;
+  return nullptr;
+}
+
+void stencil_insert(std::shared_ptr<const StencilEntry> e) {
+  std::lock_guard<std::mutex> lk(g_stencil_mu);
+  g_stencils.push_front(std::move(e));
+  while ((int)g_stencils.size() > kStencilCacheEntries) g_stencils.pop_back();
+}
+
+}  // namespace
+
+void stencil_cache(bool clear, long long* hits, long long* misses) {
+  std::lock_guard<std::mutex> lk(g_stencil_mu);
+  if (hits) *hits = g_stencil_hits;
+  if (misses) *misses = g_stencil_misses;
+  if (clear) {
+    g_stencils.clear();
+    g_stencil_hits = g_stencil_misses = 0;
+  }
+}
+
 std::string build_host_setup(const double* m, int n, double omega, int b, int w, double C,
                              int freq_samples, HostSetup& S) {
   char buf[256];
@@ -488,95 +540,116 @@ std::string build_host_setup(const double* m, int n, double omega, int b, int w,
       S.kmap[(size_t)e1 * L + e2] = k;
     }
 
-  // ---- Green's table k_delta, delta in [0, n+1]^2 (Sec. 1, Sec. 2.1, G1) ----
-  const int Q = n + 2;
-  S.kq.assign((size_t)Q * Q, cd(0.0));
-  parallel_for(Q, [&](int a) {
-    for (int c = 0; c <= a; ++c) {
-      cd val;
-      if (a == 0 && c == 0) {
-        const double rad = h / std::sqrt(kPi);
-        double j1, y1;
-        bessel_j1y1_small(omega * rad, &j1, &y1);
-        // k0 = (i pi a / (2 omega)) H1(omega a) - 1/omega^2
-        val = cd(0.0, kPi * rad / (2.0 * omega)) * cd(j1, y1) - cd(1.0 / (omega * omega), 0.0);
-      } else {
-        const double r = std::sqrt((double)a * a + (double)c * c) * h;
-        double j0, y0;
-        bessel_j0y0(omega * r, &j0, &y0);
-        // G = (i/4) H0(omega r) = (i/4)(J0 + i Y0), times h^2
-        val = cd(-0.25 * y0, 0.25 * j0) * (h * h);
+  // ---- the velocity-independent tables: from the cache, or computed ----
+  const int NC = 2 * b + 1;
+  if (auto ce = stencil_find(n, omega, b, C)) {
+    S.kq = ce->kq;
+    S.gamma_glob = ce->gamma_glob;
+    std::copy(ce->alpha, ce->alpha + 9, S.alpha);
+    std::copy(ce->beta, ce->beta + 9, S.beta);
+    std::copy(ce->alpha_sv, ce->alpha_sv + 9, S.alpha_sv);
+  } else {
+    // ---- Green's table k_delta, delta in [0, n+1]^2 (Sec. 1, Sec. 2.1, G1) ----
+    const int Q = n + 2;
+    S.kq.assign((size_t)Q * Q, cd(0.0));
+    parallel_for(Q, [&](int a) {
+      for (int c = 0; c <= a; ++c) {
+        cd val;
+        if (a == 0 && c == 0) {
+          const double rad = h / std::sqrt(kPi);
+          double j1, y1;
+          bessel_j1y1_small(omega * rad, &j1, &y1);
+          // k0 = (i pi a / (2 omega)) H1(omega a) - 1/omega^2
+          val = cd(0.0, kPi * rad / (2.0 * omega)) * cd(j1, y1) - cd(1.0 / (omega * omega), 0.0);
+        } else {
+          const double r = std::sqrt((double)a * a + (double)c * c) * h;
+          double j0, y0;
+          bessel_j0y0(omega * r, &j0, &y0);
+          // G = (i/4) H0(omega r) = (i/4)(J0 + i Y0), times h^2
+          val = cd(-0.25 * y0, 0.25 * j0) * (h * h);
+        }
+        S.kq[(size_t)a * Q + c] = val;
+        S.kq[(size_t)c * Q + a] = val;
       }
-      S.kq[(size_t)a * Q + c] = val;
-      S.kq[(size_t)c * Q + a] = val;
-    }
-  });
-  auto kq = [&](int d1, int d2) { return S.kq[(size_t)std::abs(d1) * Q + std::abs(d2)]; };
+    });
+    auto kq = [&](int d1, int d2) { return S.kq[(size_t)std::abs(d1) * Q + std::abs(d2)]; };
 
-  // ---- alpha: streamed QR of K_{mu,mu^c}^H, then the SVD of R (eq. alpha) ----
-  {
-    const int nt = (int)std::min<unsigned>(worker_count(), 2 * n + 1);
-    std::vector<std::vector<cd>> Rs(nt);
-    std::vector<int> have(nt, 0);
-    parallel_for(nt, [&](int t) {
-      std::vector<cd> block;
-      block.reserve(64 * 9);
+    // ---- alpha: streamed QR of K_{mu,mu^c}^H, then the SVD of R (eq. alpha) ----
+    {
+      const int nt = (int)std::min<unsigned>(worker_count(), 2 * n + 1);
+      std::vector<std::vector<cd>> Rs(nt);
+      std::vector<int> have(nt, 0);
+      parallel_for(nt, [&](int t) {
+        std::vector<cd> block;
+        block.reserve(64 * 9);
+        std::vector<cd> R;
+        bool hv = false;
+        int rows = 0;
+        for (int l1 = -n + t; l1 <= n; l1 += nt)
+          for (int l2 = -n; l2 <= n; ++l2) {
+            if (std::abs(l1) <= 1 && std::abs(l2) <= 1) continue;
+            for (int o = 0; o < 9; ++o) {
+              const int j1 = o / 3 - 1, j2 = o % 3 - 1;
+              block.push_back(std::conj(kq(j1 - l1, j2 - l2)));
+            }
+            if (++rows == 64) {
+              qr_append(R, block.data(), rows, 9, hv);
+              hv = true;
+              rows = 0;
+              block.clear();
+            }
+          }
+        if (rows) {
+          qr_append(R, block.data(), rows, 9, hv);
+          hv = true;
+        }
+        Rs[t] = R;
+        have[t] = hv;
+      });
       std::vector<cd> R;
       bool hv = false;
-      int rows = 0;
-      for (int l1 = -n + t; l1 <= n; l1 += nt)
-        for (int l2 = -n; l2 <= n; ++l2) {
-          if (std::abs(l1) <= 1 && std::abs(l2) <= 1) continue;
-          for (int o = 0; o < 9; ++o) {
-            const int j1 = o / 3 - 1, j2 = o % 3 - 1;
-            block.push_back(std::conj(kq(j1 - l1, j2 - l2)));
-          }
-          if (++rows == 64) {
-            qr_append(R, block.data(), rows, 9, hv);
-            hv = true;
-            rows = 0;
-            block.clear();
-          }
+      for (int t = 0; t < nt; ++t)
+        if (have[t]) {
+          qr_append(R, Rs[t].data(), 9, 9, hv);
+          hv = true;
         }
-      if (rows) {
-        qr_append(R, block.data(), rows, 9, hv);
-        hv = true;
+      jacobi_min_right_vector(R, 9, 9, S.alpha, S.alpha_sv);
+      normalise_phase(S.alpha, 9);
+      // beta^* = alpha^* K_{mu,mu}:  beta_l = sum_j conj(k_{j-l}) alpha_j (eq. beta)
+      for (int l = 0; l < 9; ++l) {
+        cd s(0.0);
+        for (int j = 0; j < 9; ++j)
+          s += std::conj(kq(j / 3 - l / 3, j % 3 - l % 3)) * S.alpha[j];
+        S.beta[l] = s;
       }
-      Rs[t] = R;
-      have[t] = hv;
-    });
-    std::vector<cd> R;
-    bool hv = false;
-    for (int t = 0; t < nt; ++t)
-      if (have[t]) {
-        qr_append(R, Rs[t].data(), 9, 9, hv);
-        hv = true;
-      }
-    jacobi_min_right_vector(R, 9, 9, S.alpha, S.alpha_sv);
-    normalise_phase(S.alpha, 9);
-    // beta^* = alpha^* K_{mu,mu}:  beta_l = sum_j conj(k_{j-l}) alpha_j (eq. beta)
-    for (int l = 0; l < 9; ++l) {
-      cd s(0.0);
-      for (int j = 0; j < 9; ++j)
-        s += std::conj(kq(j / 3 - l / 3, j % 3 - l % 3)) * S.alpha[j];
-      S.beta[l] = s;
     }
-  }
 
-  // ---- global PML stencils by per-axis class (eq. gamma) ----
-  const int NC = 2 * b + 1;
-  S.gamma_glob.assign((size_t)NC * NC * 9, cd(0.0));
-  for (int c1 = 0; c1 < NC; ++c1)
-    for (int c2 = 0; c2 < NC; ++c2) {
-      if (c1 == 0 && c2 == 0) continue;
-      double os[2][3];
-      const int cls[2] = {c1, c2};
-      for (int k = 0; k < 2; ++k) {
-        const int i = class_index(cls[k], n, b);
-        for (int o = 0; o < 3; ++o) os[k][o] = omega_sigma_global(i - 1 + o, n, b, C);
+    // ---- global PML stencils by per-axis class (eq. gamma) ----
+    S.gamma_glob.assign((size_t)NC * NC * 9, cd(0.0));
+    for (int c1 = 0; c1 < NC; ++c1)
+      for (int c2 = 0; c2 < NC; ++c2) {
+        if (c1 == 0 && c2 == 0) continue;
+        double os[2][3];
+        const int cls[2] = {c1, c2};
+        for (int k = 0; k < 2; ++k) {
+          const int i = class_index(cls[k], n, b);
+          for (int o = 0; o < 3; ++o) os[k][o] = omega_sigma_global(i - 1 + o, n, b, C);
+        }
+        pml_gamma_2d(omega, omega, h, os, &S.gamma_glob[((size_t)c1 * NC + c2) * 9]);
       }
-      pml_gamma_2d(omega, omega, h, os, &S.gamma_glob[((size_t)c1 * NC + c2) * 9]);
-    }
+
+    auto e = std::make_shared<StencilEntry>();
+    e->n = n;
+    e->b = b;
+    e->omega = omega;
+    e->C = C;
+    e->kq = S.kq;
+    e->gamma_glob = S.gamma_glob;
+    std::copy(S.alpha, S.alpha + 9, e->alpha);
+    std::copy(S.beta, S.beta + 9, e->beta);
+    std::copy(S.alpha_sv, S.alpha_sv + 9, e->alpha_sv);
+    stencil_insert(std::move(e));
+  }
 
   // ---- slices (reading G8) ----
   const int nl = std::max(1, (n + 2) / w);

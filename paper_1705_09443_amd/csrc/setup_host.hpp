@@ -65,8 +65,14 @@ int axis_class(int i, int n, int b);
 std::vector<cd> green3_octant(int n, double omega);
 
 // Build everything (2D) from m on the host. Returns "" on success, else a message.
+// The tables that do not depend on m or w (the Green table, alpha, beta and
+// the global PML stencils: functions of n, omega, b and C) are kept in a
+// process-wide cache of the last kStencilCacheEntries keys and reused.
 std::string build_host_setup(const double* m_host, int n, double omega, int b, int w, double C,
                              int freq_samples, HostSetup& out);
+constexpr int kStencilCacheEntries = 4;
+// Counters of that cache since the last clear; clear = true empties it.
+void stencil_cache(bool clear, long long* hits, long long* misses);
 
 // 3D: m is [n][n][n]; slices are slabs of lines i1 with at most
 // max_slab_lines lines and blocks (lines x L) of at most max_block unknowns.

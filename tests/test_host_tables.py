@@ -165,3 +165,41 @@ def test_tables3_refuse_oversized_slabs_at_once():
     assert st == _lib.LS_E_INVALID
     assert b"32" in lib.ls_last_error()
     assert time.time() - t0 < 5.0
+
+
+def test_stencil_cache_reuses_velocity_independent_tables():
+    """The 2D stencil cache: a second setup with the same (n, omega, b, C)
+    and another medium and layer thickness reuses the Green table, alpha,
+    beta and the global PML stencils. It returns bitwise what a fresh
+    computation gives. A change of any key computes them anew, and the
+    medium-dependent tables (aux stencils, sample map) always follow m."""
+    import numpy as np
+    import workloads
+    from paper_1705_09443_amd import host_tables, stencil_cache
+    n, omega, b = 40, 2 * np.pi * 2.5, 6
+    m1 = workloads.gaussian_bump_medium(n, 2, 6, (0.2, 0.8), (0.04, 0.1), (-0.4, 0.4), seed=3)
+    m2 = workloads.gaussian_bump_medium(n, 2, 6, (0.2, 0.8), (0.04, 0.1), (-0.4, 0.4), seed=4)
+    stencil_cache(clear=True)
+    fresh = host_tables(m1, omega, b, 3)                  # computes and caches
+    assert stencil_cache() == (0, 1)
+    again = host_tables(m2, omega, b, 4)                  # same key: a hit
+    assert stencil_cache() == (1, 1)
+    for k in ("alpha", "beta", "gamma", "green"):
+        assert np.array_equal(again[k], fresh[k]), k
+    # the medium-dependent tables follow m2, not m1
+    stencil_cache(clear=True)
+    ref2 = host_tables(m2, omega, b, 4)
+    assert np.array_equal(again["aux"], ref2["aux"]) and np.array_equal(again["kmap"], ref2["kmap"])
+    assert not np.array_equal(again["aux"], fresh["aux"])
+    # every key component misses: omega, b, C, n
+    stencil_cache(clear=True)
+    host_tables(m1, omega, b, 3)
+    host_tables(m1, omega * (1 + 1e-12), b, 3)
+    host_tables(m1, omega, b - 1, 3)
+    host_tables(m1, omega, b, 3, pml_C=9.0)
+    host_tables(m1[:-1, :-1], omega, b, 3)
+    assert stencil_cache() == (0, 5)
+    # at most four entries are kept: the first key has been evicted
+    host_tables(m1, omega, b, 3)
+    assert stencil_cache() == (0, 6)
+    stencil_cache(clear=True)
