@@ -305,16 +305,17 @@ ls_status ls_host_tables(int n, double omega, const double* m_host, int pml_widt
                          double* gamma_host, double* aux_host, int* kmap_host, double* green_host);
 
 /*
- * The stencil cache (2D). The setup tables that depend neither on m nor on
- * the layer thickness are kept for the last four (n, omega, pml_width,
- * pml_C), compared exactly, and reused by ls_setup and ls_host_tables:
+ * The stencil cache. The setup tables that depend neither on m nor on the
+ * layer thickness are kept for the last four (dim, n, omega, pml_width,
+ * pml_C), compared exactly, and reused by ls_setup, ls_host_tables and
+ * ls_host_tables3:
  * the Green's table (Sec. 2.1), alpha, beta (eqs. alpha, beta) and the
  * global PML stencils (eq. gamma). The stencils are fixed by the discretization
  * and the frequency alone, so repeated setups skip them. Examples are the
  * autotuner's candidates, or an inversion that changes m.
  *   clear   nonzero: empty the cache and reset the counters (after reading)
  *   hits, misses   may be NULL; lookups since the last clear
- * Thread-safe. 3D setups are not cached.
+ * Thread-safe.
  */
 ls_status ls_stencil_cache(int clear, long long* hits, long long* misses);
 

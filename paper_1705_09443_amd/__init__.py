@@ -338,8 +338,8 @@ def host_tables(m, omega: float, pml_width: int, layer_thickness: int, pml_C: fl
 
 
 def stencil_cache(clear: bool = False):
-    """(hits, misses) of the 2D stencil cache since the last clear; clear=True
-    empties it afterwards."""
+    """(hits, misses) of the stencil cache (the m-independent setup tables,
+    2D and 3D) since the last clear; clear=True empties it afterwards."""
     import ctypes
     lib = _lib.load()
     hits, misses = ctypes.c_longlong(0), ctypes.c_longlong(0)

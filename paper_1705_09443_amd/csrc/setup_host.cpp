@@ -439,24 +439,23 @@ std::vector<cd> green3_octant(int n, double omega) {
 
 namespace {
 
-// The velocity-independent 2D tables of one (n, omega, b, C), keys compared
+// The velocity-independent tables of one (d, n, omega, b, C), keys compared
 // exactly. Entries are immutable once inserted; the most recent is first.
 struct StencilEntry {
-  int n, b;
+  int d, n, b;
   double omega, C;
-  std::vector<cd> kq, gamma_glob;
-  cd alpha[9], beta[9];
-  double alpha_sv[9];
+  std::vector<cd> kq, gamma_glob, alpha, beta;  // alpha, beta: 3^d entries
+  std::vector<double> alpha_sv;
 };
 std::mutex g_stencil_mu;
 std::deque<std::shared_ptr<const StencilEntry>> g_stencils;
 long long g_stencil_hits = 0, g_stencil_misses = 0;
 
-std::shared_ptr<const StencilEntry> stencil_find(int n, double omega, int b, double C) {
+std::shared_ptr<const StencilEntry> stencil_find(int d, int n, double omega, int b, double C) {
   std::lock_guard<std::mutex> lk(g_stencil_mu);
   for (size_t i = 0; i < g_stencils.size(); ++i) {
     const auto& e = g_stencils[i];
-    if (e->n == n && e->b == b && e->omega == omega && e->C == C) {
+    if (e->d == d && e->n == n && e->b == b && e->omega == omega && e->C == C) {
       auto hit = e;
       g_stencils.erase(g_stencils.begin() + (long)i);
       g_stencils.push_front(hit);
@@ -472,6 +471,23 @@ void stencil_insert(std::shared_ptr<const StencilEntry> e) {
   std::lock_guard<std::mutex> lk(g_stencil_mu);
   g_stencils.push_front(std::move(e));
   while ((int)g_stencils.size() > kStencilCacheEntries) g_stencils.pop_back();
+}
+
+std::shared_ptr<const StencilEntry> make_entry(int d, int n, double omega, int b, double C,
+                                               const std::vector<cd>& kq, const std::vector<cd>& gamma_glob,
+                                               const cd* alpha, const cd* beta, const double* sv, int nmu) {
+  auto e = std::make_shared<StencilEntry>();
+  e->d = d;
+  e->n = n;
+  e->b = b;
+  e->omega = omega;
+  e->C = C;
+  e->kq = kq;
+  e->gamma_glob = gamma_glob;
+  e->alpha.assign(alpha, alpha + nmu);
+  e->beta.assign(beta, beta + nmu);
+  e->alpha_sv.assign(sv, sv + nmu);
+  return e;
 }
 
 }  // namespace
@@ -542,12 +558,12 @@ std::string build_host_setup(const double* m, int n, double omega, int b, int w,
 
   // ---- the velocity-independent tables: from the cache, or computed ----
   const int NC = 2 * b + 1;
-  if (auto ce = stencil_find(n, omega, b, C)) {
+  if (auto ce = stencil_find(2, n, omega, b, C)) {
     S.kq = ce->kq;
     S.gamma_glob = ce->gamma_glob;
-    std::copy(ce->alpha, ce->alpha + 9, S.alpha);
-    std::copy(ce->beta, ce->beta + 9, S.beta);
-    std::copy(ce->alpha_sv, ce->alpha_sv + 9, S.alpha_sv);
+    std::copy(ce->alpha.begin(), ce->alpha.end(), S.alpha);
+    std::copy(ce->beta.begin(), ce->beta.end(), S.beta);
+    std::copy(ce->alpha_sv.begin(), ce->alpha_sv.end(), S.alpha_sv);
   } else {
     // ---- Green's table k_delta, delta in [0, n+1]^2 (Sec. 1, Sec. 2.1, G1) ----
     const int Q = n + 2;
@@ -638,17 +654,7 @@ std::string build_host_setup(const double* m, int n, double omega, int b, int w,
         pml_gamma_2d(omega, omega, h, os, &S.gamma_glob[((size_t)c1 * NC + c2) * 9]);
       }
 
-    auto e = std::make_shared<StencilEntry>();
-    e->n = n;
-    e->b = b;
-    e->omega = omega;
-    e->C = C;
-    e->kq = S.kq;
-    e->gamma_glob = S.gamma_glob;
-    std::copy(S.alpha, S.alpha + 9, e->alpha);
-    std::copy(S.beta, S.beta + 9, e->beta);
-    std::copy(S.alpha_sv, S.alpha_sv + 9, e->alpha_sv);
-    stencil_insert(std::move(e));
+    stencil_insert(make_entry(2, n, omega, b, C, S.kq, S.gamma_glob, S.alpha, S.beta, S.alpha_sv, 9));
   }
 
   // ---- slices (reading G8) ----
@@ -779,76 +785,86 @@ std::string build_host_setup3(const double* m, int n, double omega, int b, int w
       }
   });
 
-  // ---- Green's table (Sec. 1, Sec. 2.1, reading G1) ----
-  S.kq = green3_octant(n, omega);
-  const int Q = n + 2;
-  auto kq = [&](int d1, int d2, int d3) {
-    return S.kq[((size_t)std::abs(d1) * Q + std::abs(d2)) * Q + std::abs(d3)];
-  };
+  // ---- the velocity-independent tables: from the cache, or computed ----
+  const int NC = 2 * b + 1;
+  if (auto ce = stencil_find(3, n, omega, b, C)) {
+    S.kq = ce->kq;
+    S.gamma_glob = ce->gamma_glob;
+    std::copy(ce->alpha.begin(), ce->alpha.end(), S.alpha);
+    std::copy(ce->beta.begin(), ce->beta.end(), S.beta);
+    std::copy(ce->alpha_sv.begin(), ce->alpha_sv.end(), S.alpha_sv);
+  } else {
+    // ---- Green's table (Sec. 1, Sec. 2.1, reading G1) ----
+    S.kq = green3_octant(n, omega);
+    const int Q = n + 2;
+    auto kq = [&](int d1, int d2, int d3) {
+      return S.kq[((size_t)std::abs(d1) * Q + std::abs(d2)) * Q + std::abs(d3)];
+    };
 
-  // ---- alpha: streamed QR of K_{mu,mu^c}^H, then the SVD of R (eq. alpha) ----
-  {
-    const int nt = (int)std::min<unsigned>(worker_count(), 2 * n + 1);
-    std::vector<std::vector<cd>> Rs(nt);
-    std::vector<int> have(nt, 0);
-    parallel_for(nt, [&](int t) {
-      constexpr int kRows = 128;
-      std::vector<cd> block;
-      block.reserve((size_t)kRows * 27);
+    // ---- alpha: streamed QR of K_{mu,mu^c}^H, then the SVD of R (eq. alpha) ----
+    {
+      const int nt = (int)std::min<unsigned>(worker_count(), 2 * n + 1);
+      std::vector<std::vector<cd>> Rs(nt);
+      std::vector<int> have(nt, 0);
+      parallel_for(nt, [&](int t) {
+        constexpr int kRows = 128;
+        std::vector<cd> block;
+        block.reserve((size_t)kRows * 27);
+        std::vector<cd> R;
+        bool hv = false;
+        int rows = 0;
+        for (int l1 = -n + t; l1 <= n; l1 += nt)
+          for (int l2 = -n; l2 <= n; ++l2)
+            for (int l3 = -n; l3 <= n; ++l3) {
+              if (std::abs(l1) <= 1 && std::abs(l2) <= 1 && std::abs(l3) <= 1) continue;
+              for (int o = 0; o < 27; ++o)
+                block.push_back(std::conj(kq(o / 9 - 1 - l1, (o / 3) % 3 - 1 - l2, o % 3 - 1 - l3)));
+              if (++rows == kRows) {
+                qr_append(R, block.data(), rows, 27, hv);
+                hv = true;
+                rows = 0;
+                block.clear();
+              }
+            }
+        if (rows) {
+          qr_append(R, block.data(), rows, 27, hv);
+          hv = true;
+        }
+        Rs[t] = R;
+        have[t] = hv;
+      });
       std::vector<cd> R;
       bool hv = false;
-      int rows = 0;
-      for (int l1 = -n + t; l1 <= n; l1 += nt)
-        for (int l2 = -n; l2 <= n; ++l2)
-          for (int l3 = -n; l3 <= n; ++l3) {
-            if (std::abs(l1) <= 1 && std::abs(l2) <= 1 && std::abs(l3) <= 1) continue;
-            for (int o = 0; o < 27; ++o)
-              block.push_back(std::conj(kq(o / 9 - 1 - l1, (o / 3) % 3 - 1 - l2, o % 3 - 1 - l3)));
-            if (++rows == kRows) {
-              qr_append(R, block.data(), rows, 27, hv);
-              hv = true;
-              rows = 0;
-              block.clear();
-            }
-          }
-      if (rows) {
-        qr_append(R, block.data(), rows, 27, hv);
-        hv = true;
+      for (int t = 0; t < nt; ++t)
+        if (have[t]) {
+          qr_append(R, Rs[t].data(), 27, 27, hv);
+          hv = true;
+        }
+      jacobi_min_right_vector(R, 27, 27, S.alpha, S.alpha_sv);
+      normalise_phase(S.alpha, 27);
+      // beta^* = alpha^* K_{mu,mu}:  beta_l = sum_j conj(k_{j-l}) alpha_j (eq. beta)
+      for (int l = 0; l < 27; ++l) {
+        cd s(0.0);
+        for (int j = 0; j < 27; ++j)
+          s += std::conj(kq(j / 9 - l / 9, (j / 3) % 3 - (l / 3) % 3, j % 3 - l % 3)) * S.alpha[j];
+        S.beta[l] = s;
       }
-      Rs[t] = R;
-      have[t] = hv;
-    });
-    std::vector<cd> R;
-    bool hv = false;
-    for (int t = 0; t < nt; ++t)
-      if (have[t]) {
-        qr_append(R, Rs[t].data(), 27, 27, hv);
-        hv = true;
-      }
-    jacobi_min_right_vector(R, 27, 27, S.alpha, S.alpha_sv);
-    normalise_phase(S.alpha, 27);
-    // beta^* = alpha^* K_{mu,mu}:  beta_l = sum_j conj(k_{j-l}) alpha_j (eq. beta)
-    for (int l = 0; l < 27; ++l) {
-      cd s(0.0);
-      for (int j = 0; j < 27; ++j)
-        s += std::conj(kq(j / 9 - l / 9, (j / 3) % 3 - (l / 3) % 3, j % 3 - l % 3)) * S.alpha[j];
-      S.beta[l] = s;
     }
-  }
 
-  // ---- global PML stencils by per-axis class (eq. gamma, Sec. 3.1) ----
-  const int NC = 2 * b + 1;
-  S.gamma_glob.assign((size_t)NC * NC * NC * 27, cd(0.0));
-  parallel_for(NC * NC * NC, [&](int id) {
-    const int cls[3] = {id / (NC * NC), (id / NC) % NC, id % NC};
-    if (!cls[0] && !cls[1] && !cls[2]) return;
-    double os[3][3];
-    for (int k = 0; k < 3; ++k) {
-      const int i = class_index(cls[k], n, b);
-      for (int o = 0; o < 3; ++o) os[k][o] = omega_sigma_global(i - 1 + o, n, b, C);
-    }
-    pml_gamma_3d(omega, omega, h, os, &S.gamma_glob[(size_t)id * 27]);
-  });
+    // ---- global PML stencils by per-axis class (eq. gamma, Sec. 3.1) ----
+    S.gamma_glob.assign((size_t)NC * NC * NC * 27, cd(0.0));
+    parallel_for(NC * NC * NC, [&](int id) {
+      const int cls[3] = {id / (NC * NC), (id / NC) % NC, id % NC};
+      if (!cls[0] && !cls[1] && !cls[2]) return;
+      double os[3][3];
+      for (int k = 0; k < 3; ++k) {
+        const int i = class_index(cls[k], n, b);
+        for (int o = 0; o < 3; ++o) os[k][o] = omega_sigma_global(i - 1 + o, n, b, C);
+      }
+      pml_gamma_3d(omega, omega, h, os, &S.gamma_glob[(size_t)id * 27]);
+    });
+    stencil_insert(make_entry(3, n, omega, b, C, S.kq, S.gamma_glob, S.alpha, S.beta, S.alpha_sv, 27));
+  }
 
   // ---- auxiliary PML stencils at the sampled local frequencies (Sec. 2.3) ----
   const size_t naux_keys = (size_t)b * NC * NC * ns;

@@ -67,7 +67,8 @@ std::vector<cd> green3_octant(int n, double omega);
 // Build everything (2D) from m on the host. Returns "" on success, else a message.
 // The tables that do not depend on m or w (the Green table, alpha, beta and
 // the global PML stencils: functions of n, omega, b and C) are kept in a
-// process-wide cache of the last kStencilCacheEntries keys and reused.
+// process-wide cache of the last kStencilCacheEntries keys (shared with the
+// 3D setup, keyed by dimension too) and reused.
 std::string build_host_setup(const double* m_host, int n, double omega, int b, int w, double C,
                              int freq_samples, HostSetup& out);
 constexpr int kStencilCacheEntries = 4;

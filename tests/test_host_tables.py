@@ -203,3 +203,24 @@ def test_stencil_cache_reuses_velocity_independent_tables():
     host_tables(m1, omega, b, 3)
     assert stencil_cache() == (0, 6)
     stencil_cache(clear=True)
+
+
+def test_stencil_cache_3d():
+    """The same cache in 3D: a second 3D setup with another medium and layer
+    thickness reuses the m-independent tables bitwise, and a 2D setup of the
+    same n, omega, b and C does not match a 3D entry."""
+    import numpy as np
+    import workloads
+    from paper_1705_09443_amd import host_tables, host_tables3, stencil_cache
+    n, omega, b = 9, 2 * np.pi * 1.0, 3
+    m1 = workloads.gaussian_bump_medium(n, 3, 5, (0.25, 0.75), (0.05, 0.1), (-0.3, 0.3), seed=1)
+    m2 = workloads.gaussian_bump_medium(n, 3, 5, (0.25, 0.75), (0.05, 0.1), (-0.3, 0.3), seed=2)
+    stencil_cache(clear=True)
+    fresh = host_tables3(m1, omega, b, 3)
+    again = host_tables3(m2, omega, b, 4)
+    assert stencil_cache() == (1, 1)
+    for k in ("alpha", "beta", "gamma"):
+        assert np.array_equal(again[k], fresh[k]), k
+    host_tables(m1[0], omega, b, 3)                        # 2D, same n, omega, b, C
+    assert stencil_cache() == (1, 2)
+    stencil_cache(clear=True)
