@@ -119,7 +119,7 @@ def work_per_column(solver, kind: str, cbytes: int, n: int):
 # calibrated on a plain copy of known size), for the 1023^2 64-wave mixed
 # workload: see profiles/c2_mixed_64rhs_hbm_counters.md. Keyed by kind and
 # precision; valid only for the kernels as they were when measured.
-MEASURED_TRAFFIC = {("interface", 8): 9.46e9}
+MEASURED_TRAFFIC = {("interface", 8): 9.45e9}
 
 # kinds that run on the second stream, overlapped with the main one
 CONCURRENT = ("slice_solves_last",)

@@ -802,9 +802,10 @@ hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>
     const int qtiles = (nrhs + 15) / 16, groups = (nt + 7) / 8;
     const dim3 grid(groups * 8 * qtiles, 1, nz), block(64 * kMfmaWaves);
     // more than two column tiles put two workgroups on some compute units,
-    // where two blocks of loads in flight per wave measured faster than four
+    // where three blocks of loads in flight per wave measured fastest (9.2
+    // against 9.4 ms per C2 interface graph with two, slower with four)
     if (qtiles > 2)
-      hipLaunchKernelGGL((k_iface_mfma<T, kMfmaWaves, 2>), grid, block, 0, st, p0, p1, x, L, nrhs, kbeg, mstride,
+      hipLaunchKernelGGL((k_iface_mfma<T, kMfmaWaves, 3>), grid, block, 0, st, p0, p1, x, L, nrhs, kbeg, mstride,
                          vstride, xoff, qtiles);
     else
       hipLaunchKernelGGL((k_iface_mfma<T>), grid, block, 0, st, p0, p1, x, L, nrhs, kbeg, mstride, vstride, xoff,
