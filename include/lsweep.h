@@ -31,8 +31,11 @@
  *  - Work is enqueued on opts.hip_stream (NULL: the default stream); every
  *    entry point returns with its work complete (host-synchronised).
  *  - Calls on one handle must not overlap.
- *  - ls_setup implements dim = 2 only; other values return LS_E_INVALID. The
- *    3D operator has a handle of its own (ls_op3, below).
+ *  - ls_setup takes dim = 2 (Sec. 2) or dim = 3 (Sec. 3.1); other values
+ *    return LS_E_INVALID. In 3D every grid array gains a third axis
+ *    ([n][n][n] interior, [L][L][L] extended) and the whole solver, the
+ *    sweeping preconditioner included, works on it (see ls_setup). The 3D
+ *    operator alone also has a handle of its own (ls_op3, below).
  */
 #ifndef LSWEEP_H
 #define LSWEEP_H
@@ -58,7 +61,7 @@ typedef enum { LS_FP64 = 0, LS_MIXED = 1 } ls_precision;
 typedef enum { LS_RHS_SOURCE = 0, LS_RHS_INCIDENT = 1 } ls_rhs_kind;
 
 typedef struct {
-  int dim;  /* 2 */
+  int dim;  /* 2 (unit square) or 3 (unit cube) */
   int n;    /* interior points per axis, h = 1/(n+1) */
 } ls_grid;
 
@@ -130,9 +133,10 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
  * Solve (I + omega^2 K M) u = g for a batch of right-hand sides with
  * right-preconditioned restarted GMRES (flexible form), stopping each
  * right-hand side when its true relative residual is <= tol (Sec. 2.5).
- *   rhs_dev    complex128 [nrhs][n][n]: g itself (LS_RHS_SOURCE) or the incident
- *              wave u_I on the interior grid (LS_RHS_INCIDENT, g = -omega^2 K (m u_I))
- *   u_dev      complex128 [nrhs][n][n] output, the scattered field
+ *   rhs_dev    complex128 [nrhs][n][n] ([nrhs][n][n][n] in 3D): g itself
+ *              (LS_RHS_SOURCE) or the incident wave u_I on the interior grid
+ *              (LS_RHS_INCIDENT, g = -omega^2 K (m u_I))
+ *   u_dev      complex128, same shape, output: the scattered field
  *   info_host  host array of nrhs entries (may be NULL)
  * A zero right-hand side gives u = 0 after 0 iterations. Returns LS_E_NOCONV
  * if any right-hand side hit max_iters (u and info are still written).
@@ -143,12 +147,19 @@ ls_status ls_solve(ls_handle* h, const void* rhs_dev, int nrhs, int rhs_kind, do
 
 /*
  * Gradient of J = sum_j 1/2 |R u_j - d_j|^2 with respect to the grid vector m,
- * for the fields of the last ls_solve (same nrhs):
+ * for the fields of the last ls_solve (same nrhs). Derived from eq. LS_d_c
+ * (the paper states no adjoint): with psi = u + u_I the discrete equation reads
+ * A(m) psi = u_I, A = I + omega^2 K M, so d psi = -A^{-1} omega^2 K diag(dm) psi;
+ * K is complex symmetric (k depends on |delta| only), hence the adjoint solve
+ * A^H lambda = r becomes A (K conj lambda) = K conj(r), a solve with the same
+ * A and the same preconditioner:
  *   dJ/dm = -omega^2 Re sum_j psi_j * nu_j,   A nu_j = K conj(r_j),
  * psi_j = u_j + u_I,j (incident kind) or u_j (source kind), r_j = R^T (R u_j - d_j).
- *   resid_dev  complex128 [nrhs][n][n], the residuals r_j on the grid
- *   grad_dev   float64 [n][n] output
+ *   resid_dev  complex128 [nrhs][n][n] ([nrhs][n][n][n] in 3D), the residuals r_j
+ *   grad_dev   float64 [n][n] ([n][n][n] in 3D) output
  *   info_host  host array of nrhs entries for the adjoint solves (may be NULL)
+ * Returns LS_E_STATE unless the handle's last ls_solve had the same nrhs, and
+ * LS_E_NOCONV (gradient still written) if an adjoint solve hit max_iters.
  */
 ls_status ls_adjoint(ls_handle* h, const void* resid_dev, int nrhs, double tol, double* grad_dev,
                      ls_rhs_info* info_host);
@@ -343,8 +354,9 @@ ls_status ls_host_tables3(int n, double omega, const double* m_host, int pml_wid
  * and k_0 the integral of G over the ball of volume h^3 in closed form:
  *     a = h (3/(4 pi))^(1/3),  k_0 = (exp(i omega a)(1 - i omega a) - 1) / omega^2.
  * A 3D handle holds the Green's spectrum and the medium and applies A and K
- * by a zero-padded FFT convolution of length P = fft_len(n) >= 2n per axis;
- * the sweeping preconditioner is not offered in 3D.
+ * by a zero-padded FFT convolution of length P = fft_len(n) >= 2n per axis.
+ * It is the operator alone, for callers that need A or K without a setup;
+ * the preconditioned 3D solve is ls_setup with grid->dim = 3.
  *
  * ls_op3_create: m_dev is float64 [n][n][n] (i3 fastest, finite, < 1
  *   everywhere), copied. hip_stream: hipStream_t for every later call (NULL:

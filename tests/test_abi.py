@@ -90,3 +90,28 @@ def test_setup_without_layer_thickness_needs_autotune():
     o.autotune = -1
     assert lib.ls_setup(ctypes.byref(grid), 10.0, dummy, 6, 4, ctypes.byref(o), ctypes.byref(h)) == _lib.LS_E_INVALID
     assert not h.value
+
+
+def test_three_dimensional_grid_passes_the_host_checks():
+    # dim = 3 is accepted (Sec. 3.1); these refusals come from the 3D setup's
+    # own host checks, before any device call, and name the 3D limits
+    from paper_1705_09443_amd import _lib
+    lib = _lib.load()
+    o = _lib.LsOptions()
+    lib.ls_default_options(ctypes.byref(o))
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)
+    grid = _lib.LsGrid(3, 2000)
+    assert lib.ls_setup(ctypes.byref(grid), 10.0, dummy, 4, 4, ctypes.byref(o), ctypes.byref(h)) == _lib.LS_E_INVALID
+    assert "3D: n must be in [1, 1023]" in lib.ls_last_error().decode()
+    grid = _lib.LsGrid(3, 15)
+    assert lib.ls_setup(ctypes.byref(grid), 10.0, dummy, 4, 0, ctypes.byref(o), ctypes.byref(h)) == _lib.LS_E_INVALID
+    assert "3D: layer_thickness" in lib.ls_last_error().decode()
+    o.autotune = 4
+    assert lib.ls_setup(ctypes.byref(grid), 10.0, dummy, 4, 4, ctypes.byref(o), ctypes.byref(h)) == _lib.LS_E_INVALID
+    assert "3D: autotune" in lib.ls_last_error().decode()
+    grid = _lib.LsGrid(4, 15)
+    o.autotune = 0
+    assert lib.ls_setup(ctypes.byref(grid), 10.0, dummy, 4, 4, ctypes.byref(o), ctypes.byref(h)) == _lib.LS_E_INVALID
+    assert "dim must be 2 or 3" in lib.ls_last_error().decode()
+    assert not h.value
