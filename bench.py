@@ -235,7 +235,7 @@ def leg_adjoint(args, dev):
     wl = workloads.workload("C4")
     n, tol = wl.n, 1e-10
     uinc = torch.as_tensor(wl.incident(), device=dev)
-    rec = torch.as_tensor(workloads.circle_receivers(n, 0.4), device=dev)
+    rec = torch.as_tensor(workloads.circle_receivers(n, 0.45), device=dev)
     with LSSolver(torch.as_tensor(wl.medium_array(seed=1), device=dev), wl.omega, wl.pml_width,
                   wl.layer_thickness, precision="mixed") as sd:
         ud, _ = sd.solve(uinc, "incident", tol)
@@ -264,7 +264,7 @@ def leg_adjoint(args, dev):
             "ms_per_step": t * 1e3, "steps": args.steps_adjoint, "setup_s": setup,
             "iterations": {"forward": [x.iterations for x in info], "adjoint": [x.iterations for x in ginfo]},
             "config": {"workload": (f"2D {n}^2, omega=2pi*{wl.ppw_omega:g}, 16 Gaussian bumps (seed 0), "
-                                    f"{wl.nrhs} plane waves, receivers on the circle r=0.4, data from bump "
+                                    f"{wl.nrhs} plane waves, receivers on the circle r=0.45, data from bump "
                                     f"seed 1, mixed precision, b={wl.pml_width}, w={wl.layer_thickness}, "
                                     f"restart {wl.restart}, tol {tol}: one gradient = ls_solve + ls_adjoint"),
                        "n": n, "nrhs": wl.nrhs}}

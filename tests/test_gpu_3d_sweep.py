@@ -6,9 +6,10 @@ factorizations, scipy FFTs), through the C ABI.
 Tolerances as in 2D: float64 applies and slab solves 1e-11 relative (the
 library inverts the dense Schur complements of each slab block, the oracle
 factors the sparse slab; both are backward stable, the slabs are
-well-conditioned); complex64 1e-4; whole solves per the same protocol
-(iteration counts within one, the true residual below the tolerance, and
-float64 solutions equal to 1e-10 at equal iteration counts).
+well-conditioned); complex64 slab solves and preconditioner 1e-5 (P5);
+whole solves per the same protocol (iteration counts within one in both
+precisions, the true residual below the tolerance, and float64 solutions
+equal to 1e-10 with both sides stopped after the oracle's count, P1).
 """
 import math
 import sys
@@ -41,6 +42,9 @@ def to_dev(x, dtype=torch.complex128):
 
 def crand(rng, shape):
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+FP32_BOUND = 1e-5   # P5
 
 
 CASES3 = {
@@ -124,8 +128,10 @@ def test_slab_solves(case3):
         for j in range(3):
             ref_w = sw.solve_slice(k, v[j].reshape(-1))
             e64, e32 = rel(w[j].reshape(-1), ref_w), rel(w32[j].reshape(-1), ref_w)
+            if j == 0:
+                say(f"[{name}]   slab {k}: fp64 {e64:.2e} fp32 {e32:.2e}")
             assert e64 <= 1e-11, (k, j, e64)
-            assert e32 <= 1e-4, (k, j, e32)
+            assert e32 <= FP32_BOUND, (k, j, e32)
 
 
 def test_preconditioner(case3):
@@ -140,7 +146,7 @@ def test_preconditioner(case3):
         e64, e32 = rel(z[j], zr), rel(z32[j], zr)
         say(f"[{name}]   rhs {j}: fp64 {e64:.2e} fp32 {e32:.2e}")
         assert e64 <= 1e-11
-        assert e32 <= 1e-4
+        assert e32 <= FP32_BOUND
 
 
 def test_solves(case3):
@@ -159,9 +165,20 @@ def test_solves(case3):
         assert info[j].converged and info32[j].converged
         assert rel(ref.op.apply_A(u[j]), g) <= 1.01e-8
         assert rel(ref.op.apply_A(u32[j]), g) <= 1.01e-8
-        if info[j].iterations == res.iterations:
-            assert rel(u[j], res.x) <= 1e-10
-        assert abs(info32[j].iterations - res.iterations) <= 2
+        assert abs(info32[j].iterations - res.iterations) <= 1
+        # P1: both stopped after the oracle's count k (a handle with
+        # max_iters = k and an unreachable tolerance)
+        from paper_1705_09443_amd import LSSolver
+        k = res.iterations
+        b, w = CASES3[name][2], CASES3[name][3]
+        with LSSolver(torch.as_tensor(m).cuda(), omega, pml_width=b, layer_thickness=w, precision="fp64",
+                      schedule="sequential", max_iters=k) as gk:
+            uk, ik = gk.solve(to_dev(uinc[j][None]), "incident", 1e-300, allow_noconv=True)
+        assert ik[0].iterations == k
+        xk = ref.solve_rhs(g, 1e-300, max_iters=k).x
+        e = rel(uk.cpu().numpy()[0], xk)
+        say(f"[{name}]   rhs {j}: P1 after {k} steps {e:.2e}")
+        assert e <= 1e-10
 
 
 def test_preconditioner_batch_of_ten(case3):
@@ -178,7 +195,7 @@ def test_preconditioner_batch_of_ten(case3):
         w64, w32 = max(w64, rel(z[j], zr)), max(w32, rel(z32[j], zr))
     say(f"[{name}] apply_precond, 10 rhs: worst fp64 {w64:.2e}, fp32 {w32:.2e}")
     assert w64 <= 1e-11
-    assert w32 <= 1e-4
+    assert w32 <= FP32_BOUND
 
 
 def test_single_slab_preconditioner_is_exact_solve():

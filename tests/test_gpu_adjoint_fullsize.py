@@ -2,16 +2,19 @@
 16 Gaussian bumps, 32 plane waves, mixed precision (complex64 applies inside
 float64 FGMRES), PML b = 12, layers w = 4.
 
-Misfit J(m) = 1/2 sum_j |R u_j(m) - d_j|^2 over receivers on the circle of
-radius 0.4, data d from the field of a second medium (bump seed 1). The
-gradient comes from ls_solve then ls_adjoint (eq. LS_d_c and its adjoint).
+Misfit J(m) = 1/2 sum_j |R u_j(m) - d_j|^2 over the grid points within h/2 of
+the circle of radius 0.45 about the centre, data d from the field of a second
+medium (bump seed 1). The gradient comes from ls_solve then ls_adjoint
+(eq. LS_d_c and its adjoint).
 
-The oracle cannot run 64 solves at this size in a test, so the check is a
-property that holds at any size. Along two seeded directions dm, the central
-difference (J(m + eps dm) - J(m - eps dm)) / (2 eps), each J from GPU solves
-to 1e-10, matches <dJ/dm, dm> to 1e-4. With eps = 1e-4 and max|dm| = 1, the
-difference's truncation error is O(eps^2) and the solves contribute about
-tol / eps = 1e-6 relative.
+The oracle cannot run these solves at this size in a test, so the check is a
+property that holds at any size, as the workload states it: along 8 seeded
+directions dm (N(0,1) per point, scaled to max-norm 1, seed 2) the central
+difference (J(m + eps dm) - J(m - eps dm)) / (2 eps) with eps = 1e-6 matches
+<dJ/dm, dm> to 1e-5 relative. The difference's truncation error is O(eps^2);
+every J comes from solves to a 1e-12 relative residual (the float64 outer
+loop reaches it with the complex64 preconditioner), so the solves add about
+1e-12 / eps = 1e-6 relative.
 """
 import sys
 
@@ -24,8 +27,10 @@ torch = pytest.importorskip("torch")
 
 pytestmark = pytest.mark.gpu
 
-TOL = 1e-10
-EPS = 1e-4
+TOL = 1e-12
+EPS = 1e-6
+RADIUS = 0.45
+DIRECTIONS = 8
 
 
 def say(msg):
@@ -41,6 +46,7 @@ def _misfit(s, uinc, rec, data):
     return 0.5 * float((r.abs() ** 2).sum()), r, info
 
 
+@pytest.mark.timeout(900)
 def test_c4_gradient_central_differences():
     from paper_1705_09443_amd import LSSolver
     wl = workloads.workload("C4")
@@ -48,7 +54,7 @@ def test_c4_gradient_central_differences():
     dev = torch.device("cuda:0")
     m = wl.medium_array()
     uinc = torch.as_tensor(wl.incident(), device=dev)
-    rec = torch.as_tensor(workloads.circle_receivers(n, 0.4), device=dev)
+    rec = torch.as_tensor(workloads.circle_receivers(n, RADIUS), device=dev)
     say(f"[c4] data from the second medium, n={n}, {wl.nrhs} waves")
     with LSSolver(torch.as_tensor(wl.medium_array(seed=1), device=dev), omega, b, w, precision="mixed") as sd:
         ud, info = sd.solve(uinc, "incident", TOL)
@@ -64,7 +70,8 @@ def test_c4_gradient_central_differences():
         f"{max(i.iterations for i in info)}, adjoint {min(i.iterations for i in ginfo)}.."
         f"{max(i.iterations for i in ginfo)}")
     assert np.isfinite(g).all() and np.abs(g).max() > 0
-    for k, dm in enumerate(workloads.fd_directions(n, 2, 2, seed=7)):
+    worst = 0.0
+    for k, dm in enumerate(workloads.fd_directions(n, 2, DIRECTIONS, seed=2)):
         js = []
         for sign in (1.0, -1.0):
             with LSSolver(torch.as_tensor(m + sign * EPS * dm, device=dev), omega, b, w, precision="mixed") as sp:
@@ -72,5 +79,7 @@ def test_c4_gradient_central_differences():
         fd = (js[0] - js[1]) / (2 * EPS)
         an = float(np.sum(g * dm))
         rel = abs(fd - an) / abs(an)
+        worst = max(worst, rel)
         say(f"[c4] direction {k}: central difference {fd:.10e}, adjoint {an:.10e}, relative {rel:.2e}")
-        assert rel <= 1e-4
+        assert rel <= 1e-5
+    say(f"[c4] worst relative difference over {DIRECTIONS} directions: {worst:.2e}")

@@ -3,11 +3,14 @@ the C ABI, on the same seeded inputs.
 
 Tolerances: float64 paths 1e-12..1e-13 relative (round-off of O(10)-term
 stencils, LU solves and length-P FFTs; the library's own stencil tables
-agree with the oracle's to 1e-12, which bounds the stencil applies); complex64 paths 1e-5 (a few float32
-ulps amplified by the slice solves' conditioning); whole solves per the
-protocol: same iteration count (+-1) and, stopped at the oracle's count,
-1e-10 relative in float64 (P1); the mixed path within 1e-6 of the oracle's
-tight solution (P3).
+agree with the oracle's to 1e-12, which bounds the stencil applies); the
+complex64 slice solves and preconditioner 1e-5 (P5: a few float32 ulps
+amplified by the slice solves' conditioning); whole solves per the protocol:
+iteration counts within one of the oracle's at the same tolerance (P2, both
+precisions), and, with both sides stopped after the oracle's count k (a
+handle with max_iters = k and an unreachable tolerance, so neither stops
+early), 1e-10 relative in float64 (P1); the mixed path within 1e-6 of the
+oracle's tight solution (P3).
 """
 import math
 import sys
@@ -40,6 +43,28 @@ def to_dev(x, dtype=torch.complex128):
 
 def crand(rng, shape):
     return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+FP32_BOUND = 1e-5   # P5
+
+
+def forced_iterations(m, omega, b, w, precision, rhs, kind, k, restart=30, schedule="interface"):
+    """The library's iterate after exactly k Arnoldi steps for one right-hand
+    side: max_iters = k and a tolerance no step meets (LS_E_NOCONV, which still
+    writes the iterate)."""
+    from paper_1705_09443_amd import LSSolver
+    with LSSolver(torch.as_tensor(m).cuda(), omega, b, w, precision=precision, max_iters=k,
+                  restart=restart, schedule=schedule) as s:
+        u, info = s.solve(to_dev(rhs[None]), kind, 1e-300, allow_noconv=True)
+    assert info[0].iterations == k, (info[0].iterations, k)
+    return u.cpu().numpy()[0]
+
+
+def oracle_iterations(ref, g, k):
+    """The oracle's iterate after exactly k Arnoldi steps."""
+    res = ref.solve_rhs(g, 1e-300, max_iters=k)
+    assert res.iterations == k
+    return res.x
 
 
 CASES = {
@@ -87,7 +112,7 @@ def test_sequential_schedule_matches(case):
         zr = ref.precondition(r[j])
         assert rel(zs[j], zr) <= 1e-12
         assert rel(zi[j], zs[j]) <= 1e-12
-        assert rel(zs32[j], zr) <= 1e-4
+        assert rel(zs32[j], zr) <= FP32_BOUND
 
 
 def test_apply_A_and_K(case):
@@ -153,7 +178,7 @@ def test_slice_solves(case):
         for j in range(2):
             ref_w = sw.solve_slice(k, v[j].reshape(-1))
             assert rel(w[j].reshape(-1), ref_w) <= 1e-12, (k, j)
-            assert rel(w32[j].reshape(-1), ref_w) <= 1e-4, (k, j)
+            assert rel(w32[j].reshape(-1), ref_w) <= FP32_BOUND, (k, j)
 
 
 def test_slice_solves_batched(case):
@@ -178,7 +203,7 @@ def test_slice_solves_batched(case):
         if k in (0, sw.nslices - 1):
             say(f"[{name}] batched slice {k}: t={lines + naux}, worst fp64 {worst64:.2e}, fp32 {worst32:.2e}")
         assert worst64 <= 1e-12, (k, worst64)
-        assert worst32 <= 1e-4, (k, worst32)
+        assert worst32 <= FP32_BOUND, (k, worst32)
 
 
 def test_preconditioner(case):
@@ -192,7 +217,7 @@ def test_preconditioner(case):
     for j in range(3):
         zr = ref.precondition(r[j])
         assert rel(z[j], zr) <= 1e-12
-        assert rel(z32[j], zr) <= 1e-4
+        assert rel(z32[j], zr) <= FP32_BOUND
 
 
 @pytest.mark.parametrize("nb", [5, 17, 40])
@@ -213,7 +238,7 @@ def test_preconditioner_batches(case, nb):
         worst32 = max(worst32, rel(z32[j], zr))
     say(f"[{name}] batch {nb}: worst relative error fp64 {worst64:.2e}, fp32 {worst32:.2e}")
     assert worst64 <= 1e-12
-    assert worst32 <= 1e-4
+    assert worst32 <= FP32_BOUND
 
 
 @pytest.mark.parametrize("nb", [1, 3, 6])
@@ -245,14 +270,14 @@ def test_every_kernel_choice(case, nb):
                 w32 = max(rel(z32[j], zr[j]) for j in range(nb))
                 say(f"[{name}] batch {nb}, slice kernel {sk}, interface kernel {ik}: "
                     f"fp64 {w64:.2e}, fp32 {w32:.2e}")
-                assert w64 <= 1e-12 and w32 <= 1e-4
+                assert w64 <= 1e-12 and w32 <= FP32_BOUND
                 for k in ks:
                     v, wr = vs[k]
                     w = g64.slice_solve(k, to_dev(v)).cpu().numpy()
                     w32s = g32.slice_solve(k, to_dev(v, torch.complex64)).cpu().numpy()
                     for j in range(nb):
                         assert rel(w[j].reshape(-1), wr[j]) <= 1e-12, (k, j)
-                        assert rel(w32s[j].reshape(-1), wr[j]) <= 1e-4, (k, j)
+                        assert rel(w32s[j].reshape(-1), wr[j]) <= FP32_BOUND, (k, j)
     finally:
         for g in (g64, g32):
             g.set_kernels(nb, 0, 0)  # back to the defaults
@@ -265,15 +290,19 @@ def test_solve_fp64_parity(case):
     say(f"[{name}] ls_solve fp64, {uinc.shape[0]} rhs")
     u, info = g64.solve(to_dev(uinc), "incident", 1e-6)
     u = u.cpu().numpy()
+    b, w = CASES[name][2], CASES[name][3]
     for j in range(uinc.shape[0]):
-        res = ref.solve_rhs(ref.op.rhs_incident(uinc[j]), 1e-6)
+        g = ref.op.rhs_incident(uinc[j])
+        res = ref.solve_rhs(g, 1e-6)
         assert abs(info[j].iterations - res.iterations) <= 1          # P2
         assert info[j].converged and info[j].rel_residual <= 1e-6
         # true residual with the oracle's own operator
-        g = ref.op.rhs_incident(uinc[j])
         assert rel(ref.op.apply_A(u[j]), g) <= 1.01e-6
-        if info[j].iterations == res.iterations:                     # P1
-            assert rel(u[j], res.x) <= 1e-10
+        k = res.iterations                                           # P1 at the oracle's count
+        uk = forced_iterations(m, wl.omega, b, w, "fp64", uinc[j], "incident", k)
+        err = rel(uk, oracle_iterations(ref, g, k))
+        say(f"  rhs {j}: iterations {info[j].iterations} (oracle {k}); P1 after {k} steps {err:.2e}")
+        assert err <= 1e-10
 
 
 def test_solve_mixed_accuracy(case):
@@ -289,15 +318,24 @@ def test_solve_mixed_accuracy(case):
         coarse = ref.solve_rhs(g, 1e-6)
         assert info[j].converged and info[j].rel_residual <= 1e-6
         assert rel(ref.op.apply_A(u[j]), g) <= 1.01e-6
-        assert rel(u[j], tight) <= 1e-5                              # P3, stated at tol 1e-6
-        assert abs(info[j].iterations - coarse.iterations) <= 2
+        # P3 at tol 1e-6: any two tol-1e-6 solutions differ by up to about
+        # cond(A) * 1e-6, so the bound is 1e-6 or, where the oracle's own
+        # float64 tol-1e-6 solution is further than that from the tight one,
+        # three times that distance (both printed); the tight check follows
+        e_mixed, e_ref = rel(u[j], tight), rel(coarse.x, tight)
+        say(f"  rhs {j}: mixed iterations {info[j].iterations} (oracle {coarse.iterations}); "
+            f"P3 at tol 1e-6: mixed {e_mixed:.2e}, oracle float64 {e_ref:.2e}")
+        assert e_mixed <= max(1e-6, 3 * e_ref)
+        assert abs(info[j].iterations - coarse.iterations) <= 1      # P2
     # the float64 outer loop reaches far below float32 round-off
     u2, info2 = g32.solve(to_dev(uinc), "incident", 1e-10)
     u2 = u2.cpu().numpy()
     for j in range(uinc.shape[0]):
         g = ref.op.rhs_incident(uinc[j])
         assert info2[j].rel_residual <= 1e-10
-        assert rel(u2[j], ref.solve_rhs(g, 1e-12).x) <= 1e-6            # P3
+        e = rel(u2[j], ref.solve_rhs(g, 1e-12).x)
+        say(f"  rhs {j}: P3 at tol 1e-10: {e:.2e}")
+        assert e <= 1e-6                                                 # P3
 
 
 def test_zero_rhs_and_source_kind(case):
@@ -366,8 +404,11 @@ def test_solve_long_arnoldi_cycles(b, restart):
         assert abs(info[j].iterations - res.iterations) <= 1          # P2
         assert info[j].converged and info[j].rel_residual <= 1e-10
         assert rel(ref.op.apply_A(u[j]), gj) <= 1.01e-10
-        if info[j].iterations == res.iterations:                     # P1
-            assert rel(u[j], res.x) <= 1e-10
+        k = res.iterations                                           # P1, across restarts
+        uk = forced_iterations(m, wl.omega, b, w, "fp64", uinc[j], "incident", k, restart=restart)
+        err = rel(uk, oracle_iterations(ref, gj, k))
+        say(f"  rhs {j}: P1 after {k} steps {err:.2e}")
+        assert err <= 1e-10
 
 
 def test_solve_sequential_schedule(case):
@@ -399,9 +440,14 @@ def test_solve_sequential_schedule(case):
         say(f"  rhs {j}: iterations seq {infos[j].iterations} / {infos32[j].iterations}, "
             f"interface {infoi[j].iterations} / {infoi32[j].iterations}, oracle {res.iterations}")
         assert abs(infos[j].iterations - res.iterations) <= 1
-        assert abs(infos32[j].iterations - res.iterations) <= 2
+        assert abs(infos32[j].iterations - res.iterations) <= 1
         for u in (us[j], us32[j]):
             assert rel(ref.op.apply_A(u), gj) <= 1.01e-8
-        if infos[j].iterations == infoi[j].iterations:
-            assert rel(us[j], ui[j]) <= 1e-10
+        # P1 for both schedules at the oracle's count
+        k = res.iterations
+        xk = oracle_iterations(ref, gj, k)
+        for sched in ("sequential", "interface"):
+            e = rel(forced_iterations(m, wl.omega, b, w, "fp64", uinc[j], "incident", k, schedule=sched), xk)
+            say(f"  rhs {j}: P1 {sched} after {k} steps {e:.2e}")
+            assert e <= 1e-10
         assert rel(us32[j], ui32[j]) <= 1e-6
