@@ -21,9 +21,12 @@ duration.
 
 Prints one JSON line. Besides the contract fields it carries the float64
 form (same medium, one wave), per-kind kernel times from HIP events recorded
-on the library's stream inside the timed region, the roofline of the
-dominant kind, and the CPU oracle timed on a bounded sample of the same
-workload (one of the 64 right-hand sides, solved in full).
+on the library's stream inside the timed region, rooflines by the method's
+algorithmic bytes (the sweep apply as "roofline"; the FFT convolution and the
+Q stencil under "roofline_parts", with the interface form's dense map
+products as an overhead figure), the CPU oracle timed on a bounded sample of
+the same workload (one of the 64 right-hand sides, solved in full), and the
+errors of the GPU results on that wave against the oracle.
 """
 from __future__ import annotations
 
@@ -38,8 +41,6 @@ sys.path.insert(0, ROOT)
 
 METRIC = "unknowns*RHS solved/s to 1e-6 residual, mixed+batched vs plain FP64 on 1 GPU"
 HBM_PEAK_GBS = 8000.0
-# published MI355X vector peaks (TFLOP/s): fp32 157.3, fp64 78.6
-ALU_PEAK = {8: 157.3, 16: 78.6}
 
 
 def parse():
@@ -52,6 +53,8 @@ def parse():
     p.add_argument("--nrhs", type=int, default=None)
     p.add_argument("--no-fp64", action="store_true")
     p.add_argument("--no-cpu", action="store_true")
+    p.add_argument("--no-accuracy", action="store_true",
+                   help="skip the oracle's tol-1e-12 solve that the errors of the mixed results are measured against")
     p.add_argument("--no-3d", action="store_true", help="skip the 3D leg (127^3, four waves, mixed)")
     p.add_argument("--steps-3d", type=int, default=2)
     p.add_argument("--no-adjoint", action="store_true",
@@ -65,97 +68,122 @@ def parse():
     return p.parse_args()
 
 
-def fstride(t: int, tw: int) -> int:
-    return (t * t + t * tw + 1) & ~1
+def fft_len(n: int) -> int:
+    P = 1
+    while P < 2 * (n + 1):
+        P <<= 1
+    return P
 
 
-def work_per_column(solver, kind: str, cbytes: int, n: int):
-    """(flops, shared_bytes, column_bytes) of one launch of a kind, per
-    right-hand-side column: flops and the bytes every column moves, plus the
-    bytes the launch reads once whatever its batch (factors, maps, spectrum).
-
-    slice_solves: forward y_j = S_j^-1 r_j - W_j y_{j-1} (t^2 + t tw complex
-      multiply-adds per transverse step) and backward x_j = y_j - G_j x_{j+1}
-      (t^2), all slices; reads the factors once; per column reads the slice
-      right-hand sides, writes and reads back the forward results and writes
-      the solution.
-    interface: 3l-5 dense L x L products (lambda chain, P term, mu chain).
-    fft_convolve: read x and m, three passes over the n x P row transforms
-      (written and read), write y; the (P/2+1)^2 spectrum once.
-    stencil_Q: read n^2, write L^2.
-    """
+def sweep_method_bytes(solver, cbytes: int):
+    """Algorithmic bytes of one preconditioner sweep (Algorithm 2) by the
+    method's count: the 2l-1 slice solves (every slice forward, every slice but
+    the last backward) each read their factors once, 2 L t^2 complex values
+    for a t-line subproblem, shared by the whole batch; per right-hand-side
+    column each solve reads its slice right-hand side and writes its field,
+    (2 w_k + 2 t) L complex values (w_k lines of D_k). Returns (shared bytes,
+    bytes per column)."""
     L, nl = solver.L, solver.nslices
-    if kind in ("slice_solves", "slice_solves_last"):
-        # the last slice runs on its own stream beside the others when l > 2
-        ks = range(nl)
-        if nl > 2:
-            ks = [nl - 1] if kind == "slice_solves_last" else range(nl - 1)
-        fl = sh = col = 0.0
-        for k in ks:
-            lo, hi, naux = solver.slice_bounds(k)
-            tw = hi - lo + 1
-            t = tw + naux
-            fl += 8.0 * L * (2 * t * t + t * tw)
-            sh += cbytes * L * (fstride(t, tw) + fstride(t, 0))
-            col += cbytes * L * (2 * tw + 2 * t)
-        return fl, sh, col
-    if kind == "interface":
-        steps = max(0, 3 * nl - 5)
-        return 8.0 * steps * L * L, float(cbytes * steps * L * L), float(cbytes * 3 * nl * L)
-    if kind == "fft_convolve":
-        P = 1
-        while P < 2 * (n + 1):
-            P <<= 1
-        col = 2 * n * n * cbytes + n * n * 4 + 4 * n * P * cbytes + n * n * cbytes
-        return 10.0 * P * P * (2 * P.bit_length() - 2), float((P // 2 + 1) ** 2 * cbytes), float(col)
-    if kind == "stencil_Q":
-        return 8.0 * 9 * n * n, 0.0, float(cbytes * (n * n + L * L))
-    if kind == "extract":
-        return 0.0, 0.0, float(cbytes * 2 * n * n)
-    return 0.0, 0.0, 0.0
+    shared = col = 0.0
+    for k in range(nl):
+        lo, hi, naux = solver.slice_bounds(k)
+        tw = hi - lo + 1
+        t = tw + naux
+        solves = 2 if k < nl - 1 else 1
+        shared += solves * 2.0 * L * t * t * cbytes
+        col += solves * (2.0 * tw + 2.0 * t) * L * cbytes
+    return shared, col
+
+
+def fft_method_bytes(n: int, cbytes: int):
+    """One zero-padded FFT convolution: read x and m, write y ((2s + s/2) N with
+    a float32 m), and the three passes over the n x P row transforms of the
+    pruned two-dimensional FFT (4 n P s); the (P/2+1)^2 spectrum once per
+    launch. Returns (shared, per column)."""
+    P = fft_len(n)
+    N = n * n
+    return float((P // 2 + 1) ** 2 * cbytes), float((2 * cbytes + cbytes / 2) * N + 4 * n * P * cbytes)
+
+
+def stencil_method_bytes(n: int, L: int, cbytes: int):
+    """Q: read the interior field, write the extended one (s N + s N_ext) per column."""
+    return 0.0, float(cbytes * (n * n + L * L))
+
+
+def interface_map_flops(solver):
+    """The interface form's own work, beyond the method's count: 3l - 5 dense
+    L x L complex products per column and apply (the lambda chain, the fused P
+    terms and the mu chain), 8 flop per complex multiply-add, and the maps'
+    bytes once per apply."""
+    L, nl = solver.L, solver.nslices
+    steps = max(0, 3 * nl - 5)
+    return 8.0 * steps * L * L, float(steps * L * L)
 
 
 # HBM bytes per launch from hardware counters (FETCH_SIZE + WRITE_SIZE, each
-# calibrated on a plain copy of known size), for the 1023^2 64-wave mixed
-# workload: see profiles/c2_mixed_64rhs_hbm_counters.md. Keyed by kind and
-# precision; valid only for the kernels as they were when measured.
-MEASURED_TRAFFIC = {("interface", 8): 9.45e9}
+# calibrated on a plain copy of known size) for the 1023^2 64-wave mixed
+# workload, keyed by part; valid only for the kernels as they were when
+# measured (profiles/c2_mixed_64rhs_hbm_counters.md).
+MEASURED_TRAFFIC = {}
 
-# kinds that run on the second stream, overlapped with the main one
-CONCURRENT = ("slice_solves_last",)
 # published MI355X dense matrix-core peaks (TFLOP/s): fp32 157.3, fp64 78.6
 MFMA_PEAK = {8: 157.3, 16: 78.6}
 
 
-def roofline(solver, prof, cbytes: int, n: int):
-    """Roofline entry of the main-stream kind with the largest total time:
-    algorithmic work per launch (mean columns per launch x per-column work +
-    shared work) over the mean event-timed launch duration, against the HBM
-    peak or the arithmetic peak of the units the kernel runs on (matrix cores
-    for the batched interface products and slice solves, else vector ALU),
-    whichever bounds the work at that intensity."""
-    dominant = max((k for k in prof if k not in CONCURRENT), key=lambda k: prof[k][1])
-    launches, total_ms, columns = prof[dominant]
-    avg_ms = total_ms / launches
-    cols = columns / launches
-    fl, sh, colb = work_per_column(solver, dominant, cbytes, n)
-    flops = fl * cols
-    nbytes = sh + colb * cols
-    mfma = (dominant == "interface" and cols > 4) or (dominant.startswith("slice_solves") and cols > 8)
-    peak = MFMA_PEAK[cbytes] if mfma else ALU_PEAK[cbytes]
-    ridge = peak * 1e12 / (HBM_PEAK_GBS * 1e9)
-    intensity = flops / nbytes if nbytes else float("inf")
-    if intensity > ridge:
-        achieved = flops / (avg_ms * 1e-3) / 1e12
-        out = {"bound": "mfma" if mfma else "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s"}
-    else:
-        achieved = nbytes / (avg_ms * 1e-3) / 1e9
-        out = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    out["frac"] = out["achieved"] / out["peak"]
-    out["traffic"] = MEASURED_TRAFFIC.get((dominant, cbytes)) if n == 1023 else None
-    out.update({"kernel": dominant, "avg_launch_ms": avg_ms, "mean_columns_per_launch": cols,
-                "algorithmic_flops_per_launch": flops, "algorithmic_bytes_per_launch": nbytes,
-                "flop_per_byte": intensity})
+def hbm_roofline(label, formula, shared, per_col, cols, avg_ms, traffic=None):
+    nbytes = shared + per_col * cols
+    achieved = nbytes / (avg_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": label, "avg_launch_ms": avg_ms,
+            "mean_columns_per_launch": cols, "algorithmic_bytes_per_launch": nbytes, "formula": formula}
+
+
+def rooflines(solver, prof, cbytes: int, n: int):
+    """The sweep apply (the dominant part of the step), the FFT convolution and
+    the Q stencil against the HBM peak, each from the method's algorithmic
+    bytes (sweep_method_bytes, fft_method_bytes, stencil_method_bytes) over the
+    mean event-timed duration of one launch; plus the interface form's dense
+    map products as an overhead figure against the matrix-core peak.
+
+    A sweep "launch" is one preconditioner apply on the main stream: its two
+    slice-solve phases and its interface graph (recurrences and coupling);
+    the last slice's solves run on the second stream, overlapped."""
+    L = solver.L
+    out = {}
+    it = prof.get("interface")
+    ss = prof.get("slice_solves")
+    if it and ss:
+        applies = it[0]
+        cols = it[2] / applies
+        avg = (it[1] + ss[1]) / applies
+        sh, pc = sweep_method_bytes(solver, cbytes)
+        out["sweep"] = hbm_roofline(
+            "sweep apply (Algorithm 2: slice solves, phases A and C, plus the interface graph)",
+            "sum over the 2l-1 slice solves of 2 L t^2 s (factors) + columns x (2 w_k + 2 t) L s",
+            sh, pc, cols, avg, MEASURED_TRAFFIC.get(("sweep", cbytes)) if n == 1023 else None)
+        fl, mb = interface_map_flops(solver)
+        t_if = it[1] / applies
+        out["interface_dense_maps"] = {
+            "note": "work of the interface form beyond the method's count (not a roofline of the method)",
+            "flops_per_apply": fl * cols, "map_bytes_per_apply": mb * cbytes, "avg_ms": t_if,
+            "achieved_tflops": fl * cols / (t_if * 1e-3) / 1e12, "mfma_peak_tflops": MFMA_PEAK[cbytes],
+            "frac_of_mfma_peak": fl * cols / (t_if * 1e-3) / 1e12 / MFMA_PEAK[cbytes]}
+    f = prof.get("fft_convolve")
+    if f:
+        sh, pc = fft_method_bytes(n, cbytes)
+        out["fft_convolve"] = hbm_roofline(
+            "FFT convolution (row forward, column convolve, row inverse)",
+            "(P/2+1)^2 s + columns x ((2s + s/2) N + 4 n P s)", sh, pc, f[2] / f[0], f[1] / f[0],
+            MEASURED_TRAFFIC.get(("fft_convolve", cbytes)) if n == 1023 else None)
+    q = prof.get("stencil_Q")
+    if q:
+        sh, pc = stencil_method_bytes(n, L, cbytes)
+        out["stencil_Q"] = hbm_roofline(
+            "Q stencil", "columns x (s N + s N_ext)", sh, pc, q[2] / q[0], q[1] / q[0],
+            MEASURED_TRAFFIC.get(("stencil_Q", cbytes)) if n == 1023 else None)
+        # the mixed Arnoldi step hands Q the float64 basis vector: 16-byte reads
+        out["stencil_Q"]["frac_at_io_width"] = (
+            (q[2] / q[0]) * (16.0 * n * n + cbytes * L * L) / (q[1] / q[0] * 1e-3) / 1e9 / HBM_PEAK_GBS)
     return out
 
 
@@ -216,7 +244,11 @@ def leg_3d(args, dev):
            "kernels": {k: {"launches": v[0], "avg_ms": v[1] / v[0]} for k, v in prof.items()},
            "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "sweep (slab solves)",
-                        "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": nbytes}}
+                        "avg_launch_ms": avg_ms, "algorithmic_bytes_per_launch": nbytes,
+                        "note": ("bytes of this build's slab factors (dense block inverses, every block "
+                                 "streamed once per pass), not the method's count: the paper factors each "
+                                 "slab by nested dissection, whose apply streams far fewer bytes; the figure "
+                                 "rates the streaming of the factors this build keeps")}}
     s3.close()
     return out
 
@@ -270,10 +302,18 @@ def leg_adjoint(args, dev):
                        "n": n, "nrhs": wl.nrhs}}
 
 
-def cpu_baseline(wl, m, uinc):
+def cpu_baseline(wl, m, uinc, mixed0, fp64, accuracy: bool):
     """The float64 oracle on the machine's host cores: its setup (not timed into
     the value, like the GPU's), then one full FGMRES solve of the first
-    incident wave of the batch at the full grid."""
+    incident wave of the batch (theta = 0) at the full grid, timed.
+
+    The same leg states the error of the GPU results against the oracle on
+    that wave: the float64 GPU solve against the oracle's solve at the same
+    tolerance (their iteration counts beside it: at equal counts this is the
+    P1 comparison), and the mixed batched GPU solve against the oracle's
+    tol-1e-12 solution (P3; the oracle's own tol-1e-6 solution's distance to
+    it beside it, the spread any tol-1e-6 solve has)."""
+    import numpy as np
     cores = len(os.sched_getaffinity(0))
     os.environ.setdefault("OMP_NUM_THREADS", str(cores))
     try:
@@ -289,7 +329,7 @@ def cpu_baseline(wl, m, uinc):
     res = s.solve_incident(uinc[:1], tol=wl.tol)[0]
     t_solve = time.perf_counter() - t0
     iters = res.iterations
-    return {
+    base = {
         "value": wl.n ** 2 / t_solve,
         "unit": "unknowns*RHS/s",
         "cores": cores,
@@ -299,6 +339,19 @@ def cpu_baseline(wl, m, uinc):
                    f"{t_solve:.1f} s, {iters} iterations; oracle setup {t_setup:.1f} s excluded like the GPU "
                    f"setup; SuperLU single-threaded, FFT and BLAS on {cores} threads"),
     }
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    err = {"wave": "theta=0", "oracle_iterations_tol_1e-6": iters}
+    if fp64 is not None:
+        err["fp64_1rhs_vs_oracle_same_tol"] = {"rel_l2": rel(fp64[0], res.x), "gpu_iterations": fp64[1],
+                                               "oracle_iterations": iters}
+    if accuracy:
+        g = s.op.rhs_incident(uinc[0])
+        tight = s.solve_rhs(g, 1e-12)
+        err["mixed_64rhs_vs_oracle_tol_1e-12"] = {"rel_l2": rel(mixed0[0], tight.x), "gpu_iterations": mixed0[1],
+                                                  "oracle_tol_1e-6_vs_tol_1e-12": rel(res.x, tight.x)}
+        if fp64 is not None:
+            err["fp64_1rhs_vs_oracle_tol_1e-12"] = rel(fp64[0], tight.x)
+    return base, err
 
 
 def main():
@@ -367,7 +420,8 @@ def main():
     iters = [x.iterations for x in info]
     assert all(x.converged and x.rel_residual <= wl2.tol for x in info), "a right-hand side did not converge"
     value = wl2.nrhs * N / t_mixed
-    roof = roofline(mixed, prof, 8, n)
+    roofs = rooflines(mixed, prof, 8, n)
+    roof = roofs.get("sweep")
     kernels = {k: {"launches": v[0], "avg_ms": v[1] / v[0], "columns_per_launch": v[2] / v[0],
                    "share_of_step": v[1] / (t_mixed * 1e3 * args.steps)} for k, v in prof.items()}
 
@@ -398,11 +452,14 @@ def main():
                         for r in tuning["kernels"]]},
         "kernels": kernels,
         "roofline": roof,
+        "roofline_parts": {k: v for k, v in roofs.items() if k != "sweep"},
     }
+    u_mixed0 = u[0].cpu().numpy()
     mixed.close()
     del mixed
 
     # ---- plain float64, one wave ----
+    u_f64 = None
     if not args.no_fp64:
         uinc1 = torch.as_tensor(wl1.incident(), device=dev)
         t0 = time.perf_counter()
@@ -421,6 +478,7 @@ def main():
         v64 = wl1.nrhs * N / t_f64
         out["fp64"] = {"value": v64, "ms_per_step": t_f64 * 1e3, "iterations": info1[0].iterations,
                        "rel_residual": info1[0].rel_residual, "setup_s": setup_f64, "nrhs": wl1.nrhs}
+        u_f64 = (u1[0].cpu().numpy(), info1[0].iterations)
         out["ratio_vs_fp64"] = value / v64
         f64.close()
         del f64
@@ -438,7 +496,8 @@ def main():
     # ---- CPU oracle on a bounded sample ----
     if not args.no_cpu:
         print("[bench] cpu oracle sample", file=sys.stderr, flush=True)
-        out["cpu_baseline"] = cpu_baseline(wl2, m, wl2.incident())
+        out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(
+            wl2, m, wl2.incident(), (u_mixed0, info[0].iterations), u_f64, not args.no_accuracy)
     print(json.dumps(out), flush=True)
 
 
