@@ -176,6 +176,24 @@ const char* ls_last_error(void);
 /* y = (I + omega^2 K M) x on the interior grid (eq. LS_d_c). x, y: [nrhs][n][n]. */
 ls_status ls_apply_A(ls_handle* h, const void* x_dev, int nrhs, void* y_dev, int precision);
 
+/*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * y = (I + omega^2 K M) x as ls_apply_A on a 2D handle, with the FFT work
+ * array (nrhs x P x n complex values, P = fft length) taken from a static
+ * array of 64 MiB in the library's device memory, one per GPU, held until
+ * the process ends. The call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine); the caller passes x and y as for ls_apply_A.
+ *   Limit: nrhs x P x n x (16 B for LS_FP64, 8 B for LS_MIXED) <= 64 MiB, so
+ *   at n = 1023 (P = 2048) at most 2 right-hand sides in complex128 and 4 in
+ *   complex64; larger batches return LS_E_INVALID with the limit in the
+ *   message. 3D handles return LS_E_INVALID.
+ *   Every call on one GPU shares that GPU's array: calls that overlap on one
+ *   GPU (other threads, other handles, other streams) race and must not be
+ *   made. The array's contents need no clearing between calls.
+ */
+ls_status ls_apply_A_noalloc(ls_handle* h, const void* x_dev, int nrhs, void* y_dev, int precision);
+
 /* y = K x (the convolution with k alone). x, y: [nrhs][n][n]. */
 ls_status ls_apply_K(ls_handle* h, const void* x_dev, int nrhs, void* y_dev, int precision);
 

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -1789,6 +1790,45 @@ ls_status setup3_handle(const ls_grid* grid, double omega, const double* m_dev, 
   return LS_OK;
 }
 
+// ---- scratch of the allocation-free operator apply ---------------------------
+// The FFT work array of ls_apply_A_noalloc (the n x P row transforms of every
+// right-hand side) lives in this code object's own device memory, one copy
+// per GPU, held until the process ends. On the host the name `scratch` is
+// only a stand-in for the symbol: host code uses the device address that
+// hipGetSymbolAddress returns, resolved once per device with that device
+// current, and never passes the name itself to a kernel.
+constexpr size_t kNoAllocScratchBytes = size_t(64) << 20;
+constexpr int kMaxDevices = 64;
+__device__ __align__(256) static unsigned char scratch[kNoAllocScratchBytes];
+
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array; the lookup runs once per
+// device (at the first ls_setup on it, or at the first allocation-free call).
+ls_status scratch_for_device(int device, void** out) {
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (device < 0 || device >= kMaxDevices) {
+    set_error("device index out of range for the static scratch table");
+    return LS_E_DEVICE;
+  }
+  if (!g_scratch_ptr[device]) {
+    int cur = -1;
+    LSW_HIP_TRY(hipGetDevice(&cur));
+    if (cur != device) LSW_HIP_TRY(hipSetDevice(device));
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (cur != device) LSW_HIP_TRY(hipSetDevice(cur));
+    if (e != hipSuccess || !p) {
+      set_error(std::string("hipGetSymbolAddress of the static scratch array failed: ") + hipGetErrorString(e));
+      return LS_E_DEVICE;
+    }
+    g_scratch_ptr[device] = p;
+  }
+  *out = g_scratch_ptr[device];
+  return LS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1924,6 +1964,11 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
     h->E = (size_t)h->L * h->L;
     ls_status e = device_setup(h.get(), m_dev);
     if (e != LS_OK) return e;
+    {
+      // the allocation-free apply's scratch address on this device
+      void* ws = nullptr;
+      if ((e = scratch_for_device(h->device, &ws)) != LS_OK) return e;
+    }
     if (o.autotune > 0) {
       e = h->prec == LS_FP64 ? tune_kernels<double>(h.get(), o.autotune) : tune_kernels<float>(h.get(), o.autotune);
       if (e != LS_OK) return e;
@@ -2033,6 +2078,50 @@ ls_status ls_apply_A(ls_handle* h, const void* x, int nrhs, void* y, int precisi
   if (e != LS_OK) return e;
   LSW_HIP_TRY(hipStreamSynchronize(h->st));
   return LS_OK;
+}
+
+ls_status ls_apply_A_noalloc(ls_handle* h, const void* x, int nrhs, void* y, int precision) {
+  try {
+    if (check_handle(h) != LS_OK || check_precision(h, precision, false) != LS_OK) return LS_E_INVALID;
+    if (h->dim != 2) {
+      set_error("ls_apply_A_noalloc: 2D handles only");
+      return LS_E_INVALID;
+    }
+    if (nrhs < 1 || !x || !y) {
+      set_error("ls_apply_A_noalloc: bad argument");
+      return LS_E_INVALID;
+    }
+    const size_t cs = precision == LS_FP64 ? sizeof(double2) : sizeof(float2);
+    const size_t per_rhs = fft_work_elems<double>(h->n, 1) * cs;
+    if ((size_t)nrhs * per_rhs > kNoAllocScratchBytes) {
+      set_error("ls_apply_A_noalloc: " + std::to_string(nrhs) + " right-hand sides need " +
+                std::to_string((size_t)nrhs * per_rhs) + " bytes of FFT work; the static scratch holds " +
+                std::to_string(kNoAllocScratchBytes) + " bytes, so at most " +
+                std::to_string(kNoAllocScratchBytes / per_rhs) + " at n = " + std::to_string(h->n) +
+                " in this precision (use ls_apply_A, which allocates)");
+      return LS_E_INVALID;
+    }
+    void* ws = nullptr;
+    ls_status e = scratch_for_device(h->device, &ws);
+    if (e != LS_OK) return e;
+    // every value of the work array that the column and inverse passes read is
+    // written first by the forward row pass, so nothing needs clearing
+    if (precision == LS_FP64) {
+      LSW_HIP_TRY(launch_convolve<double>(static_cast<const double2*>(x), Prec<double>::m(h), h->n, nrhs,
+                                          Prec<double>::khat(h), Prec<double>::tw(h), 1.0, h->omega * h->omega,
+                                          static_cast<double2*>(ws), static_cast<double2*>(y), h->st));
+    } else {
+      LSW_HIP_TRY(launch_convolve<float>(static_cast<const float2*>(x), Prec<float>::m(h), h->n, nrhs,
+                                         Prec<float>::khat(h), Prec<float>::tw(h), 1.0f,
+                                         (float)(h->omega * h->omega), static_cast<float2*>(ws),
+                                         static_cast<float2*>(y), h->st));
+    }
+    LSW_HIP_TRY(hipStreamSynchronize(h->st));
+    return LS_OK;
+  } catch (const std::exception& ex) {
+    set_error(ex.what());
+    return LS_E_INVALID;
+  }
 }
 
 ls_status ls_apply_K(ls_handle* h, const void* x, int nrhs, void* y, int precision) {
