@@ -22,7 +22,7 @@ DEFAULT_PML_C = 10.0
 class OracleSolver:
     def __init__(self, d: int, n: int, omega: float, m: np.ndarray, pml_width: int = 12,
                  layer_thickness: int = 4, pml_C: float = DEFAULT_PML_C, restart: int = 30,
-                 exact_sweep: bool = False, workers: int = 1, stencils=None):
+                 exact_sweep: bool = False, workers: int = 1, stencils=None, fronts: int = 1):
         self.d, self.n, self.omega = d, n, float(omega)
         self.m = np.asarray(m, dtype=np.float64)
         self.restart = restart
@@ -33,7 +33,7 @@ class OracleSolver:
             alpha, beta, sv = stencils
         self.alpha, self.beta, self.alpha_sv = alpha, beta, sv
         self.system = SparseSystem(d, n, omega, self.m, alpha, beta, pml_width, pml_C)
-        self.sweep = Sweep(self.system, layer_thickness, self.m, exact=exact_sweep)
+        self.sweep = Sweep(self.system, layer_thickness, self.m, exact=exact_sweep, fronts=fronts)
 
     def precondition(self, r: np.ndarray) -> np.ndarray:
         return self.sweep.apply(r)

@@ -21,7 +21,7 @@ import scipy.sparse as sp
 import scipy.sparse.linalg as spla
 
 from .stencils import (neighbourhood, plane_wave_directions, pml_stencil,
-                       sigma_global, sigma_aux, FrequencySamples)
+                       sigma_global, sigma_aux, sigma_aux_right, FrequencySamples)
 
 
 def axis_class(i: np.ndarray, n: int, b: int) -> np.ndarray:
@@ -126,44 +126,86 @@ class SparseSystem:
         return self.H @ u
 
 
+def slice_partition(n: int, b: int, w: int, fronts: int = 1):
+    """Slices of the extended grid along x1, in grid order, as (lo, hi) line
+    ranges, and the order in which they are eliminated.
+
+    One front (Algorithms 1 and 2; reading G8): l = floor((n+2)/w) slices
+    (at least 1), D_1 = [-b, w-1], D_k = [(k-1)w, kw-1], the last slice
+    D_l = [(l-1)w, n+1+b] absorbs the remainder; eliminated left to right.
+
+    Two fronts (the first remark after Algorithm 2, Sec. 2.4; reading G18):
+    p = floor((n+1)/(2w)) slices of w lines from each end, the outermost of
+    each front also holding the b PML lines of its side, and one middle slice
+    of the remaining n+2-2pw lines (1..2w); the left front is eliminated left
+    to right, the right front right to left, the middle slice last. With
+    p = 0 the single slice is the whole extended grid."""
+    if fronts == 1:
+        nl = max(1, (n + 2) // w)
+        bounds = []
+        for k in range(nl):
+            lo = -b if k == 0 else k * w
+            hi = n + 1 + b if k == nl - 1 else (k + 1) * w - 1
+            bounds.append((lo, hi))
+        return bounds, list(range(nl))
+    if fronts != 2:
+        raise ValueError("fronts must be 1 or 2")
+    p = (n + 1) // (2 * w)
+    if p == 0:
+        return [(-b, n + 1 + b)], [0]
+    left = [(-b if k == 0 else k * w, (k + 1) * w - 1) for k in range(p)]
+    right = [(n + 2 - (k + 1) * w, n + 1 + b if k == 0 else n + 1 - k * w) for k in range(p)]
+    bounds = left + [(p * w, n + 1 - p * w)] + right[::-1]
+    order = list(range(p)) + [2 * p - k for k in range(p)] + [p]
+    return bounds, order
+
+
 class Sweep:
     """Moving-PML sweeping preconditioner (Sec. 2.3; Algorithms 1 and 2).
 
-    Slices along x1 (reading G8): l = floor((n+2)/w) (at least 1);
-    D_1 = [-b, w-1], D_k = [(k-1)w, kw-1] for 1 < k < l, D_l = [(l-1)w, n+1+b];
-    with l = 1 the single slice is the whole extended grid. For k > 1 the
-    auxiliary PML is the b lines [s_k - b, s_k - 1] left of D_k, stretched in
-    x1 by the auxiliary profile and in the other axes by the global one, with
-    stencils built from the sampled local frequency at each point (Sec. 2.3;
-    G9, G10). ``exact=True`` replaces every subproblem by the leading block
-    H_{[1:k,1:k]} (the exact Schur-complement inverse T_k of Sec. 2.3), for
-    checking the bookkeeping."""
+    The extended grid is cut into slices along x1 (slice_partition) and the
+    slices are eliminated in an order: the sparse system H, block tridiagonal
+    in the slices, is factored block by block, with the exact Schur-complement
+    inverse of each slice replaced by the approximation T~ of eq. Hwv_approx:
+    the D part of the solution of a subproblem on D plus b auxiliary PML lines
+    on each side whose neighbouring slice was eliminated before it (left of
+    D_k for the one-front sweep; right of D_k for the right front of the
+    two-front sweep; both sides for its middle slice), zero right-hand side on
+    the auxiliary lines. Auxiliary lines are stretched in x1 by the moved
+    profile and in the other axes by the global one, with stencils built from
+    the sampled local frequency at each point (Sec. 2.3; G9, G10). The apply
+    is the block forward and backward substitution of that factorization
+    (sweep()). ``exact=True`` replaces every subproblem by H on the slice and
+    every slice connected to it through slices eliminated earlier (its exact
+    Schur-complement inverse), for checking the bookkeeping."""
 
     def __init__(self, system: SparseSystem, w: int, m: np.ndarray, exact: bool = False,
-                 samples: FrequencySamples | None = None, only: list | None = None):
+                 samples: FrequencySamples | None = None, only: list | None = None, fronts: int = 1):
         """only: factor just these slices (for checking single slice solves on
         large grids); sweep() and apply() then refuse to run."""
         s = system
         self.s = s
         d, n, b, L = s.d, s.n, s.b, s.L
         self.T = L ** (d - 1)
-        nl = max(1, (n + 2) // w)
+        self.fronts = fronts
+        self.bounds, self.order = slice_partition(n, b, w, fronts)
+        nl = len(self.bounds)
         self.nslices = nl
-        bounds = []
-        for k in range(nl):
-            lo = -b if k == 0 else k * w
-            hi = n + 1 + b if k == nl - 1 else (k + 1) * w - 1
-            bounds.append((lo, hi))
-        self.bounds = bounds
+        self.pos = [0] * nl
+        for i, k in enumerate(self.order):
+            self.pos[k] = i
         self.samples = samples if samples is not None else FrequencySamples(np.asarray(m), s.omega, n)
         self.exact = exact
         self.lu = [None] * nl
-        self.aux_count = [0] * nl
-        self.aux_gamma = {}
+        self.aux_count = [0] * nl          # auxiliary unknowns left of D_k
+        self.aux_count_right = [0] * nl    # auxiliary unknowns right of D_k
+        self.aux_gamma = {}                # left auxiliary stencils by (q, classes, sample)
+        self.aux_gamma_right = {}          # right auxiliary stencils by (q, classes, sample)
         self.complete = only is None
         for k in (range(nl) if only is None else only):
-            A, naux = self._subproblem(k)
+            A, naux, nauxr = self._subproblem(k)
             self.aux_count[k] = naux
+            self.aux_count_right[k] = nauxr
             self.lu[k] = spla.splu(A.tocsc())
         # couplings H_[k,k-1] and H_[k,k+1]
         self.Hm, self.Hp = [None] * nl, [None] * nl
@@ -179,60 +221,94 @@ class Sweep:
         b = self.s.b
         return np.arange((lo + b) * self.T, (hi + b + 1) * self.T)
 
+    def earlier(self, k: int):
+        """Neighbouring slices eliminated before slice k."""
+        return [j for j in (k - 1, k + 1) if 0 <= j < self.nslices and self.pos[j] < self.pos[k]]
+
+    def later(self, k: int):
+        """Neighbouring slices eliminated after slice k."""
+        return [j for j in (k - 1, k + 1) if 0 <= j < self.nslices and self.pos[j] > self.pos[k]]
+
+    def subproblem_lines(self, k: int):
+        """(first, last) grid lines of slice k's subproblem."""
+        lo, hi = self.bounds[k]
+        first, last = lo, hi
+        if self.exact:
+            j = k - 1
+            while j >= 0 and self.pos[j] < self.pos[k]:
+                first = self.bounds[j][0]
+                j -= 1
+            j = k + 1
+            while j < self.nslices and self.pos[j] < self.pos[k]:
+                last = self.bounds[j][1]
+                j += 1
+        else:
+            if k - 1 in self.earlier(k):
+                first = lo - self.s.b
+            if k + 1 in self.earlier(k):
+                last = hi + self.s.b
+        return first, last
+
     def _subproblem(self, k: int):
         s = self.s
         b, T = s.b, self.T
         lo, hi = self.bounds[k]
-        if self.exact:
-            first = -b
-        else:
-            first = lo if k == 0 else lo - b
+        first, last = self.subproblem_lines(k)
         base = (first + b) * T
-        nloc = (hi - first + 1) * T
+        nloc = (last - first + 1) * T
         naux = (lo - first) * T
-        # rows of D_k (and, for the exact variant, of D_1..D_{k-1}) come from H
-        Hsub = s.H[base + naux:base + nloc][:, base:base + nloc].tocoo() if not self.exact \
-            else s.H[base:base + nloc][:, base:base + nloc].tocoo()
+        nauxr = (last - hi) * T
         if self.exact:
-            return Hsub, naux
+            return s.H[base:base + nloc][:, base:base + nloc].tocoo(), naux, nauxr
+        # rows of D_k come from H, restricted to the subproblem's lines
+        Hsub = s.H[(lo + b) * T:(hi + b + 1) * T][:, base:base + nloc].tocoo()
         rows = [Hsub.row + naux]
         cols = [Hsub.col]
         vals = [Hsub.data]
         if naux:
-            r, c, v = self._aux_rows(k, lo, first)
+            r, c, v = self._aux_rows(k, first, last, "left")
+            rows.append(r)
+            cols.append(c)
+            vals.append(v)
+        if nauxr:
+            r, c, v = self._aux_rows(k, first, last, "right")
             rows.append(r)
             cols.append(c)
             vals.append(v)
         A = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                           shape=(nloc, nloc))
-        return A, naux
+        return A, naux, nauxr
 
-    def _aux_rows(self, k, lo, first):
-        """gamma rows of the auxiliary PML left of D_k (eq. Hwv_approx, top block)."""
+    def _aux_rows(self, k, first, last, side):
+        """gamma rows of the auxiliary PML of slice k on one side (eq.
+        Hwv_approx, the auxiliary block), in the subproblem's numbering."""
         s = self.s
         d, n, b, L, T = s.d, s.n, s.b, s.L, self.T
+        lo, hi = self.bounds[k]
         mu = s.mu
         tshape = (L,) * (d - 1)
         tgi = np.indices(tshape).reshape(d - 1, -1).T - b if d > 1 else np.zeros((1, 0), int)
         tcls = axis_class(tgi, n, b)
+        lines = range(first, lo) if side == "left" else range(hi + 1, last + 1)
+        table = self.aux_gamma if side == "left" else self.aux_gamma_right
         rows, cols, vals = [], [], []
-        for a in range(lo - first):            # local aux line a, grid line first + a
-            line = first + a
-            q = lo - 1 - line                  # depth into the auxiliary PML
+        for line in lines:
+            a = line - first                   # local line
+            q = lo - 1 - line if side == "left" else line - hi - 1   # depth into the auxiliary PML
             pts = (line + b) * T + np.arange(T)
             kstar = self.samples.index(s.m_ext[pts])
             gam = np.empty((T, len(mu)), dtype=np.complex128)
             for t in range(T):
                 key = (q,) + tuple(tcls[t]) + (int(kstar[t]),)
-                g = self.aux_gamma.get(key)
+                g = table.get(key)
                 if g is None:
-                    g = self._aux_gamma(q, tcls[t], int(kstar[t]), lo)
-                    self.aux_gamma[key] = g
+                    g = self._aux_gamma(q, tcls[t], int(kstar[t]), lo, hi, side)
+                    table[key] = g
                 gam[t] = g
             for o, off in enumerate(mu):
                 nl_ = a + off[0]
-                if nl_ < 0:
-                    continue                   # Dirichlet line left of the auxiliary PML
+                if nl_ < 0 or nl_ > last - first:
+                    continue                   # the Dirichlet line beyond the auxiliary PML
                 nt = tgi + off[1:]
                 ok = np.all((nt >= -b) & (nt <= n + 1 + b), axis=1)
                 tflat = np.ravel_multi_index(tuple((nt[ok] + b).T), tshape) if d > 1 else np.zeros(ok.sum(), int)
@@ -242,12 +318,16 @@ class Sweep:
                 vals.append(np.conj(gam[t_ok, o]))
         return np.concatenate(rows), np.concatenate(cols), np.concatenate(vals)
 
-    def _aux_gamma(self, q, tcls, kstar, lo):
+    def _aux_gamma(self, q, tcls, kstar, lo, hi, side):
         s = self.s
         n, b, C, w = s.n, s.b, s.C, s.omega
-        line = lo - 1 - q
         sig = np.zeros((s.d, 3))
-        sig[0] = sigma_aux(np.array([line - 1, line, line + 1]), lo, b, C, w)
+        if side == "left":
+            line = lo - 1 - q
+            sig[0] = sigma_aux(np.array([line - 1, line, line + 1]), lo, b, C, w)
+        else:
+            line = hi + 1 + q
+            sig[0] = sigma_aux_right(np.array([line - 1, line, line + 1]), hi, b, C, w)
         for k, c in enumerate(tcls):
             i = class_index(int(c), n, b)
             sig[k + 1] = sigma_global(np.array([i - 1, i, i + 1]), n, b, C, w)
@@ -255,27 +335,35 @@ class Sweep:
         return pml_stencil(kappa, s.h, sig, s.dirs)
 
     def solve_slice(self, k: int, v: np.ndarray) -> np.ndarray:
-        """T~_k v: pad v with zeros on the auxiliary part, solve, restrict to D_k."""
-        naux = self.aux_count[k]
-        rhs = np.zeros(naux + len(v), dtype=np.complex128)
-        rhs[naux:] = v
-        return self.lu[k].solve(rhs)[naux:]
+        """T~_k v: pad v with zeros on the auxiliary lines, solve, restrict to D_k."""
+        naux, nauxr = self.aux_count[k], self.aux_count_right[k]
+        rhs = np.zeros(naux + len(v) + nauxr, dtype=np.complex128)
+        rhs[naux:naux + len(v)] = v
+        return self.lu[k].solve(rhs)[naux:naux + len(v)]
+
+    def coupling(self, k: int, j: int):
+        """H_[k,j] for a neighbouring slice j."""
+        return self.Hm[k] if j == k - 1 else self.Hp[k]
 
     def sweep(self, f: np.ndarray) -> np.ndarray:
-        """Algorithm 2, steps 3-8, on the flat extended grid."""
+        """Algorithm 2, steps 3-8, as the block substitutions of the
+        factorization above, on the flat extended grid: forward, slices in
+        elimination order, u_k = T~_k (f_k - sum of H_[k,j] u_j over the
+        neighbours j eliminated earlier); backward, in reverse order,
+        u_k -= T~_k (sum of H_[k,j] u_j over the neighbours eliminated later)."""
         if not self.complete:
             raise RuntimeError("sweep needs every slice factored")
         u = np.zeros_like(f)
-        nl = self.nslices
-        for k in range(nl):
-            pk = self.points(k)
-            rhs = f[pk].copy()
-            if k > 0:
-                rhs -= self.Hm[k] @ u[self.points(k - 1)]
-            u[pk] = self.solve_slice(k, rhs)
-        for k in range(nl - 2, -1, -1):
-            pk = self.points(k)
-            u[pk] -= self.solve_slice(k, self.Hp[k] @ u[self.points(k + 1)])
+        for k in self.order:
+            rhs = f[self.points(k)].copy()
+            for j in self.earlier(k):
+                rhs -= self.coupling(k, j) @ u[self.points(j)]
+            u[self.points(k)] = self.solve_slice(k, rhs)
+        for k in reversed(self.order):
+            later = self.later(k)
+            if later:
+                corr = sum(self.coupling(k, j) @ u[self.points(j)] for j in later)
+                u[self.points(k)] -= self.solve_slice(k, corr)
         return u
 
     def apply(self, r: np.ndarray) -> np.ndarray:

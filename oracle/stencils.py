@@ -101,6 +101,16 @@ def sigma_aux(line, first_line: int, b: int, C: float, omega: float):
     return np.where(q > 0, -(C / omega) * (q / b) ** 2, 0.0)
 
 
+def sigma_aux_right(line, last_line: int, b: int, C: float, omega: float):
+    """Auxiliary x1 stretch right of a slice ending at ``last_line`` (the
+    two-front sweep's bottom front and middle slice, remark 1 closing Sec. 2.4):
+    the mirror image of sigma_aux, zero up to last_line+1 and
+    +(C/omega)(q/b)^2 at last_line+1+q, q = 0..b (q = b is the Dirichlet line)."""
+    line = np.asarray(line, dtype=np.float64)
+    q = line - (last_line + 1.0)
+    return np.where(q > 0, (C / omega) * (q / b) ** 2, 0.0)
+
+
 def pml_stencil(kappa: float, h: float, sig: np.ndarray, dirs: np.ndarray) -> np.ndarray:
     """gamma for one point (eq. gamma).
 

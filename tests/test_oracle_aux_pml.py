@@ -190,7 +190,8 @@ def test_assembled_aux_rows_follow_depth_and_local_wavenumber(d):
     kappas_seen = set()
     for k in range(1, sw.nslices):
         lo = sw.bounds[k][0]
-        A, naux = sw._subproblem(k)
+        A, naux, nauxr = sw._subproblem(k)
+        assert nauxr == 0
         A = A.tocsr()
         assert naux == b * T
         moved = lambda x, edge=(lo - 1) * h: sigma_moved(x, edge, h, b, C, omega)
