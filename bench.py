@@ -62,6 +62,9 @@ def parse():
     p.add_argument("--steps-adjoint", type=int, default=3)
     p.add_argument("--no-autotune", action="store_true",
                    help="batched leg at the workload's w and the default kernels instead of autotuned ones")
+    p.add_argument("--fronts", type=int, default=2, choices=(1, 2),
+                   help="sweeping fronts of the 2D legs: 2 (default) from both ends toward a middle slice, "
+                        "as the paper's 2D experiments; 1 the single front of Algorithms 1-2")
     p.add_argument("--copy-gib", type=float, default=0.0,
                    help="first run one plain device copy of this many GiB (a known-size dispatch that "
                         "calibrates hardware byte counters in a profile of this command)")
@@ -302,7 +305,7 @@ def leg_adjoint(args, dev):
                        "n": n, "nrhs": wl.nrhs}}
 
 
-def cpu_baseline(wl, m, uinc, mixed0, fp64, accuracy: bool):
+def cpu_baseline(wl, m, uinc, mixed0, fp64, accuracy: bool, fronts: int = 1):
     """The float64 oracle on the machine's host cores: its setup (not timed into
     the value, like the GPU's), then one full FGMRES solve of the first
     incident wave of the batch (theta = 0) at the full grid, timed.
@@ -323,7 +326,8 @@ def cpu_baseline(wl, m, uinc, mixed0, fp64, accuracy: bool):
         pass
     import oracle
     t0 = time.perf_counter()
-    s = oracle.OracleSolver(2, wl.n, wl.omega, m, wl.pml_width, wl.layer_thickness, workers=cores)
+    s = oracle.OracleSolver(2, wl.n, wl.omega, m, wl.pml_width, wl.layer_thickness, workers=cores,
+                            fronts=fronts)
     t_setup = time.perf_counter() - t0
     t0 = time.perf_counter()
     res = s.solve_incident(uinc[:1], tol=wl.tol)[0]
@@ -392,11 +396,11 @@ def main():
     t0 = time.perf_counter()
     if args.no_autotune:
         mixed = LSSolver(md, wl2.omega, wl2.pml_width, wl2.layer_thickness, precision="mixed",
-                         restart=wl2.restart)
+                         restart=wl2.restart, fronts=args.fronts)
     else:
         # w and the kernel choice per batch size timed on the device for this batch
         mixed = LSSolver(md, wl2.omega, wl2.pml_width, None, precision="mixed", restart=wl2.restart,
-                         autotune=wl2.nrhs)
+                         autotune=wl2.nrhs, fronts=args.fronts)
     torch.cuda.synchronize()
     setup_mixed = time.perf_counter() - t0
     wl2 = dataclasses.replace(wl2, layer_thickness=mixed.layer_thickness)
@@ -441,6 +445,7 @@ def main():
         "config": {"workload": (f"2D {n}^2, omega=2pi*{wl2.ppw_omega:g}, 32 Gaussian bumps (seed 0), {wl2.nrhs} "
                                 f"plane waves theta_j=2pi j/{wl2.nrhs}, mixed precision, b={wl2.pml_width}, "
                                 f"w={wl2.layer_thickness}{'' if args.no_autotune else ' (autotuned)'}, "
+                                f"{args.fronts} sweeping front{'s' if args.fronts > 1 else ''}, "
                                 f"restart {wl2.restart}, tol {wl2.tol}"),
                    "n": n, "nrhs": wl2.nrhs, "omega": wl2.omega, "precision": "mixed"},
         "iterations": {"min": min(iters), "max": max(iters), "mean": sum(iters) / len(iters)},
@@ -463,7 +468,8 @@ def main():
     if not args.no_fp64:
         uinc1 = torch.as_tensor(wl1.incident(), device=dev)
         t0 = time.perf_counter()
-        f64 = LSSolver(md, wl1.omega, wl1.pml_width, wl1.layer_thickness, precision="fp64", restart=wl1.restart)
+        f64 = LSSolver(md, wl1.omega, wl1.pml_width, wl1.layer_thickness, precision="fp64", restart=wl1.restart,
+                       fronts=args.fronts)
         torch.cuda.synchronize()
         setup_f64 = time.perf_counter() - t0
         print(f"[bench] fp64 setup {setup_f64:.2f} s", file=sys.stderr, flush=True)
@@ -497,7 +503,7 @@ def main():
     if not args.no_cpu:
         print("[bench] cpu oracle sample", file=sys.stderr, flush=True)
         out["cpu_baseline"], out["error_vs_oracle"] = cpu_baseline(
-            wl2, m, wl2.incident(), (u_mixed0, info[0].iterations), u_f64, not args.no_accuracy)
+            wl2, m, wl2.incident(), (u_mixed0, info[0].iterations), u_f64, not args.no_accuracy, args.fronts)
     print(json.dumps(out), flush=True)
 
 

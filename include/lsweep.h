@@ -80,6 +80,14 @@ typedef struct {
   int sweep_schedule;  /* LS_SWEEP_INTERFACE (default): all slice solves at once plus the
                           interface recurrences; LS_SWEEP_SEQUENTIAL: Algorithm 2 slice by slice.
                           Both compute the same preconditioner up to rounding. */
+  int fronts;          /* 1 (default): one sweeping front along x1 (Algorithms 1-2).
+                          2: two fronts (the first remark after Algorithm 2, Sec. 2.4):
+                          p = floor((n+1)/(2w)) slices of w lines swept from each end toward a
+                          middle slice of the remaining 1..2w lines, which carries auxiliary
+                          PML on both sides and is eliminated last; each front's slices take
+                          their auxiliary PML on the side of the front's earlier slices.
+                          A different preconditioner (iteration counts differ). 2D with the
+                          interface schedule only; LS_E_INVALID otherwise. */
 } ls_options;
 
 typedef enum { LS_SWEEP_INTERFACE = 0, LS_SWEEP_SEQUENTIAL = 1 } ls_sweep_schedule;
@@ -209,21 +217,24 @@ ls_status ls_apply_H(ls_handle* h, const void* u_dev, int nrhs, void* y_dev, int
  * r, z: [nrhs][n][n]. precision must equal the handle's. */
 ls_status ls_apply_precond(ls_handle* h, const void* r_dev, int nrhs, void* z_dev, int precision);
 
-/* w = T~_k v for slice k (0-based): the D_k part of the subproblem solution with
- * right-hand side 0 on the auxiliary PML and v on D_k (eq. Hwv_approx).
- * v, w: [nrhs][lines of D_k][L]. precision must equal the handle's. */
+/* w = T~_k v for slice k (0-based, grid order): the D_k part of the subproblem
+ * solution with right-hand side 0 on the auxiliary PML and v on D_k (eq.
+ * Hwv_approx). v, w: [nrhs][lines of D_k][L], lines in grid order. precision
+ * must equal the handle's. */
 ls_status ls_slice_solve(ls_handle* h, int slice, const void* v_dev, int nrhs, void* w_dev,
                          int precision);
 
 typedef struct {
   int dim, n, pml_width, layer_thickness, L, nslices, freq_samples, precision;
   double omega, h, pml_C, freq_lo, freq_delta;
+  int fronts;  /* ls_options.fronts of the setup */
 } ls_setup_info;
 
 /* Sizes of the setup. */
 ls_status ls_get_info(const ls_handle* h, ls_setup_info* info_host);
 
-/* First and last grid line i1 of slice k, and its number of auxiliary lines. */
+/* First and last grid line i1 of slice k (slices numbered in grid order along
+ * x1, also with two fronts), and its number of auxiliary lines (both sides). */
 ls_status ls_get_slice(const ls_handle* h, int slice, int* first_line, int* last_line, int* aux_lines);
 
 /* Copies of the setup tables, float64 interleaved complex, on the host:
@@ -248,8 +259,10 @@ ls_status ls_get_sample_map(const ls_handle* h, int* kmap_host);
  * Sec. 2.3 allow any slice width, and argue for w = b from the operation counts
  * of a serial setup and apply; on this device the best w follows from the
  * kernels' shapes (slices of at most 16 or 32 lines) and is measured. With
- * opts->autotune = k > 0 and layer_thickness <= 0, ls_setup sets up every
- * candidate w (ls_layer_candidates), times one solve of k plane waves
+ * opts->autotune = k > 0 and layer_thickness <= 0, ls_setup sets up each of
+ * the four thinnest candidates w (ls_layer_candidates for one front; with
+ * two fronts the same rule applied to the two-front slices, the middle slice
+ * included), times one solve of k plane waves
  * u_I = exp(i omega (cos t_j x1 + sin t_j x2)), t_j = 2 pi j / k, to a 1e-6
  * relative residual on the device, and keeps the fastest w. For the kept
  * setup it then times one preconditioner apply per kernel choice at batch
@@ -268,7 +281,7 @@ ls_status ls_layer_candidates(int n, int pml_width, int* out_host, int cap, int*
 
 typedef struct {
   int layer_thickness;  /* candidate w */
-  int nslices;          /* floor((n+2)/w) */
+  int nslices;          /* slices of that setup (one front: floor((n+2)/w)) */
   int iterations;       /* most Arnoldi steps over the probe batch */
   double setup_ms;      /* its setup (Algorithm 1) */
   double solve_ms;      /* the probe solve */

@@ -67,7 +67,7 @@ class LSSolver:
 
     def __init__(self, m: torch.Tensor, omega: float, pml_width: int = 12, layer_thickness: Optional[int] = 4,
                  precision: str = "fp64", restart: int = 30, max_iters: int = 1000, pml_C: float = 10.0,
-                 freq_samples: int = 0, schedule: str = "interface", autotune: int = 0):
+                 freq_samples: int = 0, schedule: str = "interface", autotune: int = 0, fronts: int = 1):
         """layer_thickness None (with autotune = k > 0): chosen by timing solves of k
         plane waves on the device; autotune = k > 0 also tunes the kernel choice per
         batch size up to k (ls_setup, Autotuning)."""
@@ -88,6 +88,7 @@ class LSSolver:
         opts.freq_samples = freq_samples
         opts.sweep_schedule = {"interface": 0, "sequential": 1}[schedule]
         opts.autotune = int(autotune)
+        opts.fronts = int(fronts)
         opts.hip_stream = _stream_ptr()
         self._opts = opts
         grid = LsGrid(self.dim, self.n)

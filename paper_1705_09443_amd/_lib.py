@@ -33,7 +33,7 @@ class LsGrid(ctypes.Structure):
 class LsOptions(ctypes.Structure):
     _fields_ = [("precision", c_int), ("restart", c_int), ("max_iters", c_int), ("pml_C", c_double),
                 ("freq_samples", c_int), ("autotune", c_int), ("hip_stream", c_void_p),
-                ("sweep_schedule", c_int)]
+                ("sweep_schedule", c_int), ("fronts", c_int)]
 
 
 class LsRhsInfo(ctypes.Structure):
@@ -44,7 +44,7 @@ class LsSetupInfo(ctypes.Structure):
     _fields_ = [("dim", c_int), ("n", c_int), ("pml_width", c_int), ("layer_thickness", c_int),
                 ("L", c_int), ("nslices", c_int), ("freq_samples", c_int), ("precision", c_int),
                 ("omega", c_double), ("h", c_double), ("pml_C", c_double), ("freq_lo", c_double),
-                ("freq_delta", c_double)]
+                ("freq_delta", c_double), ("fronts", c_int)]
 
 
 class LsKernelTime(ctypes.Structure):

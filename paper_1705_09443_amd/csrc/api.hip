@@ -168,9 +168,13 @@ struct ls_handle {
   size_t N = 0, E = 0;
   // tables
   DBuf m, m32, khat, khat32, tw, tw32, alpha, beta, gglob, gaux, kmap;
-  DBuf s_lo, s_hi, s_first, s_t, fs_off, fg_off, FS, FG, Hm, Hp, status;
-  // interface maps M_k, P_k, N_k ([nslices][L][L])
-  DBuf IM, IP, IN;
+  DBuf s_lo, s_hi, s_first, s_t, s_naux, s_org, s_dir, s_prev, s_next, s_nlam, fs_off, fg_off, FS, FG, Hm, Hp,
+      status;
+  // interface maps M_k, P_k, N_k ([nslices][L][L]); two fronts: also
+  // Q = E T_mid J_E Hp_mid of the middle slice (one map)
+  DBuf IM, IP, IN, IQ;
+  // grid order -> table index of every slice (the two-front table order differs)
+  std::vector<int> tbl_of_grid;
   // per slice on the host: line count t and forward factor stride
   std::vector<int> t_host, fstride_host, tw_host;
   // kernel choice per batch size [0, kChoiceMax], and what the autotuner measured
@@ -193,6 +197,9 @@ struct ls_handle {
   DBuf psi;
   // captured interface recurrences, one graph per (batch size, precision)
   hipStream_t cst = nullptr;
+  // two fronts: the right front's recurrences run on st3, ordered by these
+  hipStream_t st3 = nullptr;
+  hipEvent_t evPA = nullptr, evR = nullptr, evM = nullptr, evR2 = nullptr;
   // second stream for the last slice's solves, and the events that order it
   hipStream_t st2 = nullptr;
   hipEvent_t evQ = nullptr, evA = nullptr, evL = nullptr, evC = nullptr;
@@ -213,8 +220,9 @@ struct ls_handle {
   ~ls_handle() {
     drop_graphs();
     if (cst) (void)hipStreamDestroy(cst);
+    if (st3) (void)hipStreamDestroy(st3);
     if (st2) (void)hipStreamDestroy(st2);
-    for (hipEvent_t e : {evQ, evA, evL, evC})
+    for (hipEvent_t e : {evQ, evA, evL, evC, evPA, evR, evM, evR2})
       if (e) (void)hipEventDestroy(e);
     for (auto& r : recs) {
       (void)hipEventDestroy(r.a);
@@ -244,6 +252,12 @@ struct ls_handle {
     t.hi = s_hi.as<int>();
     t.first = s_first.as<int>();
     t.t = s_t.as<int>();
+    t.naux = s_naux.as<int>();
+    t.org = s_org.as<int>();
+    t.dir = s_dir.as<int>();
+    t.prev = s_prev.as<int>();
+    t.next = s_next.as<int>();
+    t.next_lam = s_nlam.as<int>();
     t.fs_off = fs_off.as<size_t>();
     t.fg_off = fg_off.as<size_t>();
     t.nslices = nslices;
@@ -691,12 +705,17 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* c
     a.nrhs = nb;
     a.yscr = h->sscr.as<C<T>>();
     a.mfma_scr = h->mscr.as<T>();
-    // The last slice (the 32-line class with the far PML, the longest solve)
-    // runs on a second stream: its phase A is first needed by the P term, after
-    // the whole lambda recurrence, and its phase C only needs lambda_{l-2}, so
-    // both overlap the recurrences on the main stream.
+    // The last slice in table order (one front: the 32-line class with the far
+    // PML, the longest solve; two fronts: the middle slice, the only one with
+    // auxiliary lines on both sides) runs on a second stream: its phase A is
+    // first needed after the whole lambda recurrence (one front: its P term;
+    // two fronts: the middle step), and its phase C only needs the lambda of
+    // its neighbours, so both overlap the recurrences on the main stream.
     const bool split = nl > 2;
     const int kmain = split ? nl - 1 : nl;
+    // two fronts: p slices per front in table order, the middle slice last
+    const bool two = h->H.fronts == 2;
+    const int p = (nl - 1) / 2;
     auto phaseA = [&](int k0, int k1, hipStream_t s) -> ls_status {
       SliceSolveArgs<T> p = a;
       p.src_kind = kSrcGrid;
@@ -723,8 +742,15 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* c
     // slices on the main stream. The last
     // slice's coupling (lambda term only) runs on the second stream after its
     // own phase A, which reads the line it changes.
+    // Two fronts: the recurrences of the two fronts are independent until the
+    // middle slice; they are launched directly (not captured), step by step
+    // alternately on the main stream (left front) and a third stream (right
+    // front), so that both hardware queues hold their front's chain at once.
+    // (A captured graph's launch returns to the host only as its last
+    // launches run, so two graphs on two streams ran one after the other; one
+    // launch holding both fronts' products doubled its duration.)
     auto graph = [&](int part, hipGraphExec_t& out) -> ls_status {
-      const std::pair<int, int> key(4 * nb + 2 * (int)imf + part, (int)sizeof(T));
+      const std::pair<int, int> key((2 * nb + (int)imf) * 8 + part, (int)sizeof(T));
       auto it = h->graphs.find(key);
       if (it != h->graphs.end()) {
         out = it->second;
@@ -743,7 +769,7 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* c
         // term of slice k, mu_k -= P_k lambda_{k-1}, which reads the same vector
         for (int k = 1; k <= nl - 2 && ce == hipSuccess; ++k)
           ce = launch_iface_step<T>(IM, lam, lam, lam, L, nb, k, 1, MS, vs, -1, imf, h->cst, IP, mu, mu);
-      } else {
+      } else if (part == 1) {
         // the P term of the last slice (all of them when there are two slices)
         const int kp = nl > 2 ? nl - 1 : 1;
         ce = launch_iface_step<T>(IP, mu, lam, mu, L, nb, kp, nl - kp, MS, vs, -1, imf, h->cst);
@@ -761,17 +787,21 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* c
       return LS_OK;
     };
     if (nl > 1) {
+      // the executing streams before the capture stream (each takes a
+      // hardware queue when created)
+      if (split && !h->st2) {
+        LSW_HIP_TRY(hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking));
+        for (hipEvent_t* ev : {&h->evQ, &h->evA, &h->evL, &h->evC})
+          LSW_HIP_TRY(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+      }
+      if (two && !h->st3) {
+        LSW_HIP_TRY(hipStreamCreateWithFlags(&h->st3, hipStreamNonBlocking));
+        for (hipEvent_t* ev : {&h->evPA, &h->evR, &h->evM, &h->evR2})
+          LSW_HIP_TRY(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+      }
       if (!h->cst) LSW_HIP_TRY(hipStreamCreateWithFlags(&h->cst, hipStreamNonBlocking));
-      hipGraphExec_t g0 = nullptr, g1 = nullptr;
-      ls_status e = nl > 2 ? graph(0, g0) : LS_OK;  // part 0 is empty for two slices
-      if (e == LS_OK) e = graph(1, g1);
-      if (e != LS_OK) return e;
+      ls_status e = LS_OK;
       if (split) {
-        if (!h->st2) {
-          LSW_HIP_TRY(hipStreamCreateWithFlags(&h->st2, hipStreamNonBlocking));
-          for (hipEvent_t* ev : {&h->evQ, &h->evA, &h->evL, &h->evC})
-            LSW_HIP_TRY(hipEventCreateWithFlags(ev, hipEventDisableTiming));
-        }
         LSW_HIP_TRY(hipEventRecord(h->evQ, h->st));
         LSW_HIP_TRY(hipStreamWaitEvent(h->st2, h->evQ, 0));
         {
@@ -784,7 +814,58 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* c
         Timed tm(h, kKSlices, nb);
         if ((e = phaseA(0, kmain, h->st)) != LS_OK) return e;
       }
-      {
+      if (two) {
+        Timed tm(h, kKIface, nb);
+        const C<T>* IM = h->IM.as<C<T>>();
+        const C<T>* IP = h->IP.as<C<T>>();
+        const C<T>* IN = h->IN.as<C<T>>();
+        const C<T>* Hm = h->Hm.as<C<T>>();
+        const C<T>* Hp = h->Hp.as<C<T>>();
+        const int m = nl - 1;
+        auto V = [&](C<T>* base, int k) { return base + (size_t)k * vs; };
+        // lambda_k -= M_k lambda_{k-1}, mu_k -= P_k lambda_{k-1}: step i of the
+        // left front (slice i) on st, of the right front (slice p + i) on st3
+        LSW_HIP_TRY(hipEventRecord(h->evPA, h->st));
+        LSW_HIP_TRY(hipStreamWaitEvent(h->st3, h->evPA, 0));
+        for (int i = 1; i <= p - 1; ++i)
+          for (const int k : {i, p + i}) {
+            IfaceProd<T> pr[2] = {{IM + (size_t)k * MS, V(lam, k), V(lam, k - 1), V(lam, k)},
+                                  {IP + (size_t)k * MS, V(mu, k), V(lam, k - 1), V(mu, k)}};
+            LSW_HIP_TRY(launch_iface_prods<T>(pr, 2, L, nb, imf, k == i ? h->st : h->st3));
+          }
+        LSW_HIP_TRY(hipEventRecord(h->evR, h->st3));
+        LSW_HIP_TRY(hipStreamWaitEvent(h->st, h->evR, 0));
+        LSW_HIP_TRY(hipEventRecord(h->evL, h->st));  // both lambda recurrences done
+        LSW_HIP_TRY(hipStreamWaitEvent(h->st, h->evA, 0));
+        // the middle slice m: its first (mu) and last (lambda) lines take the
+        // lambda of both fronts' last slices, p - 1 and 2p - 1
+        {
+          IfaceProd<T> a[2] = {{IM + (size_t)m * MS, V(lam, m), V(lam, p - 1), V(lam, m)},
+                               {IP + (size_t)m * MS, V(mu, m), V(lam, p - 1), V(mu, m)}};
+          IfaceProd<T> c[2] = {{h->IQ.as<C<T>>(), V(lam, m), V(lam, 2 * p - 1), V(lam, m)},
+                               {IN + (size_t)m * MS, V(mu, m), V(lam, 2 * p - 1), V(mu, m)}};
+          LSW_HIP_TRY(launch_iface_prods<T>(a, 2, L, nb, imf, h->st));
+          LSW_HIP_TRY(launch_iface_prods<T>(c, 2, L, nb, imf, h->st));
+        }
+        LSW_HIP_TRY(hipEventRecord(h->evM, h->st));
+        LSW_HIP_TRY(hipStreamWaitEvent(h->st3, h->evM, 0));
+        // mu_k -= N_k mu_next outward; next to the middle slice the left front
+        // reads its mu (first line), the right front its lambda (last line)
+        for (int i = p - 1; i >= 1; --i)
+          for (const int k : {i, p + i}) {
+            const C<T>* x = i < p - 1 ? V(mu, k + 1) : (k == i ? V(mu, m) : V(lam, m));
+            IfaceProd<T> pr[1] = {{IN + (size_t)k * MS, V(mu, k), x, V(mu, k)}};
+            LSW_HIP_TRY(launch_iface_prods<T>(pr, 1, L, nb, imf, k == i ? h->st : h->st3));
+          }
+        // each front's couplings on its own stream
+        LSW_HIP_TRY(launch_couple<T>(h->slices(), L, h->b, Hm, Hp, lam, mu, nb, f, p, 2 * p, h->st3));
+        LSW_HIP_TRY(hipEventRecord(h->evR2, h->st3));
+        LSW_HIP_TRY(launch_couple<T>(h->slices(), L, h->b, Hm, Hp, lam, mu, nb, f, 0, p, h->st));
+        LSW_HIP_TRY(hipStreamWaitEvent(h->st, h->evR2, 0));
+      } else {
+        hipGraphExec_t g0 = nullptr, g1 = nullptr;
+        if (nl > 2 && (e = graph(0, g0)) != LS_OK) return e;  // part 0 is empty for two slices
+        if ((e = graph(1, g1)) != LS_OK) return e;
         Timed tm(h, kKIface, nb);
         if (g0) LSW_HIP_TRY(hipGraphLaunch(g0, h->st));
         if (split) {
@@ -794,6 +875,8 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* c
         LSW_HIP_TRY(hipGraphLaunch(g1, h->st));
       }
       if (split) {
+        // the last slice in table order: its coupling (to its neighbours'
+        // lambda, final after evL) and phase C on the second stream
         LSW_HIP_TRY(hipStreamWaitEvent(h->st2, h->evL, 0));
         {
           Timed tm(h, kKSlicesLast, nb, h->st2);
@@ -862,15 +945,24 @@ ls_status build_mfma_factors(ls_handle* h) {
 // Interface maps M_k = E T_k J_F Hm_k, P_k = F T_k J_F Hm_k (k >= 1) and
 // N_k = F T_k J_E Hp_k (1 <= k <= l-2): slice solves whose right-hand sides
 // are the L columns of J_F Hm_k or J_E Hp_k, 32 columns per workgroup.
+// Two fronts (table order: left front, right front, middle slice m = l-1):
+// M_k and P_k for the slices with a predecessor in their front and for the
+// middle slice (whose predecessor is the left front's last slice), N_k for
+// the slices with a successor whose mu is needed (not the outermost ones), and
+// for the middle slice, whose successor is the right front's last slice, also
+// Q_m = E T_m J_E Hp_m: its last line from that neighbour.
 template <typename T>
 ls_status build_interface(ls_handle* h) {
   const int nl = h->nslices, L = h->L;
   if (nl < 2) return LS_OK;
+  const bool two = h->H.fronts == 2;
+  const int p = (nl - 1) / 2;  // two fronts: slices per front
   const size_t cs = sizeof(C<T>);
   const size_t LL = (size_t)L * L;
   LSW_ALLOC(h->IM, (size_t)nl * LL * cs);
   LSW_ALLOC(h->IP, (size_t)nl * LL * cs);
   LSW_ALLOC(h->IN, (size_t)nl * LL * cs);
+  if (two) LSW_ALLOC(h->IQ, LL * cs);
   constexpr int W = 8;  // waves per workgroup of the vector-ALU path
   // columns per launch: whole 16-column tiles of the matrix-core path, as many
   // as an ~8 GB scratch allows; a short last launch of at most 8 columns takes
@@ -895,21 +987,33 @@ ls_status build_interface(ls_handle* h) {
     a.dstE = h->IM.as<C<T>>();
     a.dstF = h->IP.as<C<T>>();
     const int kern = a.nrhs > kMfmaMinCols ? 16 : W;
-    ls_status e = solve_slices<T>(h, a, 1, nl, kern);
+    ls_status e = two ? solve_slices<T>(h, a, 1, p, kern) : solve_slices<T>(h, a, 1, nl, kern);
+    if (e == LS_OK && two) e = solve_slices<T>(h, a, p + 1, nl, kern);
     if (e != LS_OK) return e;
-    if (nl > 2) {
+    if (two || nl > 2) {
       a.src_kind = kSrcUnitE;
       a.dstE = nullptr;
       a.dstF = h->IN.as<C<T>>();
-      e = solve_slices<T>(h, a, 1, nl - 1, kern);
+      e = two ? solve_slices<T>(h, a, 1, p, kern) : solve_slices<T>(h, a, 1, nl - 1, kern);
+      if (e == LS_OK && two) e = solve_slices<T>(h, a, p + 1, 2 * p, kern);
+      if (e == LS_OK && two) {
+        // the middle slice: N_m into its slot of IN, Q_m into IQ
+        SliceSolveArgs<T> am = a;
+        am.sk = 0;
+        am.dstF = h->IN.as<C<T>>() + (size_t)(nl - 1) * LL;
+        am.dstE = h->IQ.as<C<T>>();
+        e = solve_slices<T>(h, am, nl - 1, nl, kern);
+      }
       if (e != LS_OK) return e;
     }
   }
   // re-lay every map set in the operand order of the interface products
-  for (DBuf* Mp : {&h->IM, &h->IP, &h->IN}) {
+  for (DBuf* Mp : {&h->IM, &h->IP, &h->IN, &h->IQ}) {
+    if (!Mp->p) continue;
+    const int count = Mp == &h->IQ ? 1 : nl;
     DBuf z;
-    LSW_ALLOC(z, (size_t)nl * iface_map_stride<T>(L) * cs);
-    LSW_HIP_TRY(launch_swizzle_maps<T>(Mp->as<C<T>>(), z.as<C<T>>(), L, nl, h->st));
+    LSW_ALLOC(z, (size_t)count * iface_map_stride<T>(L) * cs);
+    LSW_HIP_TRY(launch_swizzle_maps<T>(Mp->as<C<T>>(), z.as<C<T>>(), L, count, h->st));
     LSW_HIP_TRY(hipStreamSynchronize(h->st));
     Mp->swap(z);  // the row-major maps are released with z
   }
@@ -1392,15 +1496,23 @@ ls_status device_setup(ls_handle* h, const double* m_dev) {
     return LS_E_DEVICE;
   // slice plan and factor storage
   const int nl = h->nslices;
-  std::vector<int> lo(nl), hi(nl), first(nl), t(nl);
+  std::vector<int> lo(nl), hi(nl), first(nl), t(nl), naux(nl), org(nl), dir(nl), prev(nl), next(nl), nlam(nl);
   std::vector<size_t> fso(nl), fgo(nl);
   size_t fs_tot = 0, fg_tot = 0;
+  h->tbl_of_grid.assign(nl, 0);
   for (int k = 0; k < nl; ++k) {
     const SlicePlan& p = Hs.slices[k];
     lo[k] = p.lo;
     hi[k] = p.hi;
     first[k] = p.first;
     t[k] = p.t;
+    naux[k] = p.naux;
+    org[k] = p.org;
+    dir[k] = p.dir;
+    prev[k] = p.prev;
+    next[k] = p.next;
+    nlam[k] = p.next_lam;
+    h->tbl_of_grid[p.grid] = k;
     fso[k] = fs_tot;
     fgo[k] = fg_tot;
     fs_tot += (size_t)L * factor_stride(p.t, p.hi - p.lo + 1);
@@ -1417,10 +1529,13 @@ ls_status device_setup(ls_handle* h, const double* m_dev) {
   LSW_ALLOC(h->s_hi, nl * sizeof(int));
   LSW_ALLOC(h->s_first, nl * sizeof(int));
   LSW_ALLOC(h->s_t, nl * sizeof(int));
+  for (DBuf* d : {&h->s_naux, &h->s_org, &h->s_dir, &h->s_prev, &h->s_next, &h->s_nlam}) LSW_ALLOC(*d, nl * sizeof(int));
   LSW_ALLOC(h->fs_off, nl * sizeof(size_t));
   LSW_ALLOC(h->fg_off, nl * sizeof(size_t));
   if (upload(h, h->s_lo, lo) != LS_OK || upload(h, h->s_hi, hi) != LS_OK || upload(h, h->s_first, first) != LS_OK ||
-      upload(h, h->s_t, t) != LS_OK || upload(h, h->fs_off, fso) != LS_OK || upload(h, h->fg_off, fgo) != LS_OK)
+      upload(h, h->s_t, t) != LS_OK || upload(h, h->fs_off, fso) != LS_OK || upload(h, h->fg_off, fgo) != LS_OK ||
+      upload(h, h->s_naux, naux) != LS_OK || upload(h, h->s_org, org) != LS_OK || upload(h, h->s_dir, dir) != LS_OK ||
+      upload(h, h->s_prev, prev) != LS_OK || upload(h, h->s_next, next) != LS_OK || upload(h, h->s_nlam, nlam) != LS_OK)
     return LS_E_DEVICE;
   const size_t cs = h->prec == LS_FP64 ? sizeof(double2) : sizeof(float2);
   // padding: the last 16-byte copy of a chunk may read one value past the end
@@ -1442,7 +1557,7 @@ ls_status device_setup(ls_handle* h, const double* m_dev) {
   LSW_HIP_TRY(hipMemcpyAsync(&status, h->status.p, sizeof(int), hipMemcpyDeviceToHost, st));
   LSW_HIP_TRY(hipStreamSynchronize(st));
   if (status != 0) {
-    set_error("zero pivot in the factorization of slice " + std::to_string(status - 1));
+    set_error("zero pivot in the factorization of slice " + std::to_string(Hs.slices[status - 1].grid));
     return LS_E_SINGULAR;
   }
   {
@@ -1473,12 +1588,12 @@ ls_status check_precision(const ls_handle* h, int precision, bool factors) {
 // Layer thicknesses w >= 2 whose slice subproblems all have at most 32 lines:
 // the first slice b PML lines + w, the middle ones b auxiliary lines + w, the
 // last b auxiliary lines + the remaining lines + b PML lines (one slice: all L).
-std::vector<int> layer_candidates(int n, int b) {
+std::vector<int> layer_candidates(int n, int b, int fronts = 1) {
   std::vector<int> out;
   const int lines = n + 2;
   for (int w = 2; w <= lines; ++w) {
-    const int nl = std::max(1, lines / w);
-    const int tmax = nl == 1 ? lines + 2 * b : std::max(b + w, lines + 2 * b - (nl - 1) * w);
+    int tmax = 0;
+    for (const SlicePlan& p : plan_slices(n, b, w, fronts)) tmax = std::max(tmax, p.t);
     if (tmax <= 32) out.push_back(w);
   }
   return out;
@@ -1843,6 +1958,7 @@ void ls_default_options(ls_options* o) {
   o->autotune = 0;
   o->hip_stream = nullptr;
   o->sweep_schedule = LS_SWEEP_INTERFACE;
+  o->fronts = 1;
 }
 
 const char* ls_last_error(void) { return lsw::get_error(); }
@@ -1875,6 +1991,14 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
       set_error("sweep_schedule must be LS_SWEEP_INTERFACE or LS_SWEEP_SEQUENTIAL");
       return LS_E_INVALID;
     }
+    if (o.fronts != 1 && o.fronts != 2) {
+      set_error("fronts must be 1 or 2");
+      return LS_E_INVALID;
+    }
+    if (o.fronts == 2 && (grid->dim != 2 || o.sweep_schedule != LS_SWEEP_INTERFACE)) {
+      set_error("fronts = 2 needs a 2D grid and the interface sweep schedule");
+      return LS_E_INVALID;
+    }
     if (o.restart < 1 || o.restart > 200 || o.max_iters < 1) {
       set_error("restart must be in [1, 200] and max_iters >= 1");
       return LS_E_INVALID;
@@ -1896,11 +2020,14 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
         return LS_E_INVALID;
       }
       // choose w: set up every candidate and time a probe solve on it
-      const std::vector<int> cands = layer_candidates(grid->n, pml_width);
+      std::vector<int> cands = layer_candidates(grid->n, pml_width, o.fronts);
       if (grid->n < 1 || pml_width < 1 || cands.empty()) {
         set_error("no layer thickness gives slices of at most 32 lines for this n and pml_width");
         return LS_E_INVALID;
       }
+      // the four thinnest: thicker layers only lengthen every slice solve
+      // (and push the slices into the 32-line class) for a shorter chain
+      if (cands.size() > 4) cands.resize(4);
       ls_options oc = o;
       oc.autotune = 0;
       oc.max_iters = std::min(o.max_iters, 300);  // bounds the cost of a poor candidate
@@ -1945,7 +2072,7 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
     std::vector<double> mh((size_t)n * n);
     LSW_HIP_TRY(hipMemcpy(mh.data(), m_dev, mh.size() * sizeof(double), hipMemcpyDeviceToHost));
     const std::string err = build_host_setup(mh.data(), n, omega, pml_width, layer_thickness, o.pml_C,
-                                             o.freq_samples, h->H);
+                                             o.freq_samples, h->H, o.fronts);
     if (!err.empty()) {
       set_error(err);
       return LS_E_INVALID;
@@ -2243,7 +2370,8 @@ ls_status ls_slice_solve(ls_handle* h, int slice, const void* v, int nrhs, void*
     a.src = static_cast<const C<T>*>(v);
     a.dst_kind = kDstSlice;
     a.dst = static_cast<C<T>*>(w);
-    return solve_slices<T>(h, a, slice, slice + 1, kc.slice);
+    const int k = h->tbl_of_grid[slice];  // slices are numbered in grid order here
+    return solve_slices<T>(h, a, k, k + 1, kc.slice);
   };
   e = precision == LS_FP64 ? run(double{}) : run(float{});
   if (e != LS_OK) return e;
@@ -2270,6 +2398,7 @@ ls_status ls_get_info(const ls_handle* h, ls_setup_info* o) {
   o->pml_C = h->H.C;
   o->freq_lo = h->H.freq_lo;
   o->freq_delta = h->H.freq_delta;
+  o->fronts = h->dim == 2 ? h->H.fronts : 1;
   return LS_OK;
 }
 
@@ -2336,10 +2465,10 @@ ls_status ls_get_slice(const ls_handle* h, int slice, int* first_line, int* last
     set_error("slice out of range");
     return LS_E_INVALID;
   }
-  const SlicePlan& p = h->H.slices[slice];
+  const SlicePlan& p = h->dim == 2 ? h->H.slices[h->tbl_of_grid[slice]] : h->H.slices[slice];
   if (first_line) *first_line = p.lo;
   if (last_line) *last_line = p.hi;
-  if (aux_lines) *aux_lines = p.naux;
+  if (aux_lines) *aux_lines = p.naux + p.nauxr;
   return LS_OK;
 }
 

@@ -136,9 +136,13 @@ __device__ __attribute__((always_inline)) inline void slice_body(const SliceSolv
   const int rr = group * W + wv;
   const bool rvalid = computes && rr < A.nrhs;
   const int L = A.L, b = A.b;
-  const int lo = A.P.lo[k], hi = A.P.hi[k], first = A.P.first[k], t = A.P.t[k];
-  const int naux = lo - first, tw = hi - lo + 1;
+  const int lo = A.P.lo[k], hi = A.P.hi[k], t = A.P.t[k];
+  const int naux = A.P.naux[k], tw = hi - lo + 1, org = A.P.org[k], dir = A.P.dir[k];
   const int tt = t * t, fstride = factor_stride(t, tw), gstride = factor_stride(t, 0);
+  // grid line (+ b) of local line a, and the row of D_k's local line c in a
+  // slice array (grid order)
+  auto gline = [&](int a) { return org + dir * a + b; };
+  auto srow = [&](int c) { return dir > 0 ? c : tw - 1 - c; };
   const C<T>* fs = A.FS + A.P.fs_off[k];
   const C<T>* fg = A.FG + A.P.fg_off[k];
   const bool unit_src = A.src_kind >= kSrcUnitF;
@@ -171,9 +175,9 @@ __device__ __attribute__((always_inline)) inline void slice_body(const SliceSolv
       const C<T>* base = A.src;
       size_t off;
       if (A.src_kind == kSrcGrid) {
-        off = ((size_t)(lo + cl + b) * L + j) * A.nrhs + rr;
+        off = ((size_t)gline(naux + (cl < tw ? cl : 0)) * L + j) * A.nrhs + rr;
       } else if (A.src_kind == kSrcSlice) {
-        off = ((size_t)rr * tw + cl) * L + j;
+        off = ((size_t)rr * tw + srow(cl < tw ? cl : 0)) * L + j;
       } else {
         const int dj = col - j;
         ok = ok && cl == unit_c && dj >= -1 && dj <= 1;
@@ -285,15 +289,16 @@ __device__ __attribute__((always_inline)) inline void slice_body(const SliceSolv
   __syncthreads();
 
   // ---------------- back substitution ----------------
+  const bool inD = a >= naux && a < naux + tw;
   auto emit = [&](int j, C<T> x) {
     if (!rvalid || !arow || cq != 0) return;
     if (A.dst_kind == kDstGrid) {
-      if (a >= naux) A.dst[((size_t)(first + a + b) * L + j) * A.nrhs + rr] = x;
+      if (inD) A.dst[((size_t)gline(a) * L + j) * A.nrhs + rr] = x;
     } else if (A.dst_kind == kDstSlice) {
-      if (a >= naux) A.dst[((size_t)rr * tw + a - naux) * L + j] = x;
+      if (inD) A.dst[((size_t)rr * tw + srow(a - naux)) * L + j] = x;
     } else {
       const size_t ci = unit_src ? (size_t)col : (size_t)rr;
-      if (a == t - 1 && A.dstE) A.dstE[k * A.sk + ci * A.sr + (size_t)j * A.sj] = x;
+      if (a == naux + tw - 1 && A.dstE) A.dstE[k * A.sk + ci * A.sr + (size_t)j * A.sj] = x;
       if (a == naux && A.dstF) A.dstF[k * A.sk + ci * A.sr + (size_t)j * A.sj] = x;
     }
   };
@@ -311,7 +316,7 @@ __device__ __attribute__((always_inline)) inline void slice_body(const SliceSolv
         const int jj = lane % D;
         const bool isE = lane < D;
         C<T>* dl = isE ? A.dstE : A.dstF;
-        const int ar = isE ? t - 1 : naux;
+        const int ar = isE ? naux + tw - 1 : naux;
         if (dl && jj < n) dl[k * A.sk + ci * A.sr + (size_t)(j0 + jj) * A.sj] = xo[buf * D * TP + jj * TP + ar];
       }
       return;
@@ -320,12 +325,12 @@ __device__ __attribute__((always_inline)) inline void slice_body(const SliceSolv
     for (int q = 0; q < NR; ++q) {
       const int e = lane + q * 64;
       const int jj = e % D, ar = e / D;
-      if (jj < n && ar >= naux && ar < t) {
+      if (jj < n && ar >= naux && ar < naux + tw) {
         const C<T> x = xo[buf * D * TP + jj * TP + ar];
         if (A.dst_kind == kDstGrid)
-          A.dst[((size_t)(first + ar + b) * L + j0 + jj) * A.nrhs + rr] = x;
+          A.dst[((size_t)gline(ar) * L + j0 + jj) * A.nrhs + rr] = x;
         else
-          A.dst[((size_t)rr * tw + ar - naux) * L + j0 + jj] = x;
+          A.dst[((size_t)rr * tw + srow(ar - naux)) * L + j0 + jj] = x;
       }
     }
   };
@@ -458,22 +463,18 @@ __global__ void k_swizzle_maps(const C<T>* __restrict__ src, C<T>* __restrict__ 
 // partial dot products over the block's 4 columns it holds, the four lanes of
 // a row then reduce by shuffles and the waves through LDS.
 template <typename T, int NW>
-__global__ __launch_bounds__(64 * NW) void k_iface_gemv(IfaceProd<T> pa, IfaceProd<T> pb, const C<T>* x, int L,
-                                                        int nrhs, int kbeg, size_t mstride, size_t vstride,
-                                                        int xoff) {
+__global__ __launch_bounds__(64 * NW) void k_iface_gemv(IfaceProds<T> ps, int L, int nrhs) {
   constexpr int MAXB = 6;  // blocks of one wave in flight at once
   __shared__ C<T> red[NW][4][16];
   const int nt = iface_tiles(L);
-  const bool two = pb.M != nullptr;
-  const IfaceProd<T> pr = two && blockIdx.z ? pb : pa;
-  const C<T>* MZ = pr.M;
+  const IfaceProd<T> pr = ps.p[blockIdx.z];
   const C<T>* add = pr.add;
   C<T>* y = pr.y;
-  const int r = blockIdx.x, k = kbeg + (two ? 0 : (int)blockIdx.z);
+  const int r = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g4 = lane >> 4;
   const int Lp = iface_vec_len(L);
-  const C<T>* Mr = MZ + (size_t)k * mstride + (size_t)r * nt * 256 + lane * 4;
-  const C<T>* xk = x + (size_t)(k + xoff) * vstride;
+  const C<T>* Mr = pr.M + (size_t)r * nt * 256 + lane * 4;
+  const C<T>* xk = pr.x;
   C<T> acc[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) acc[q] = mk<T>(0, 0);
@@ -514,7 +515,7 @@ __global__ __launch_bounds__(64 * NW) void k_iface_gemv(IfaceProd<T> pa, IfacePr
       C<T> s = red[0][q][t & 15];
 #pragma unroll
       for (int w = 1; w < NW; ++w) s = cadd<T>(s, red[w][q][t & 15]);
-      const size_t o = (size_t)k * vstride + (size_t)q * Lp + row;
+      const size_t o = (size_t)q * Lp + row;
       y[o] = csub<T>(add[o], s);
     }
   }
@@ -557,27 +558,22 @@ constexpr int kMfmaPrefetch = sizeof(T) == 4 ? 4 : 2;
 
 
 template <typename T, int NW = kMfmaWaves, int PF = kMfmaPrefetch<T>>
-__global__ __launch_bounds__(64 * NW) void k_iface_mfma(IfaceProd<T> pa, IfaceProd<T> pb, const C<T>* x, int L,
-                                                        int nrhs, int kbeg, size_t mstride, size_t vstride, int xoff,
-                                                        int qtiles) {
+__global__ __launch_bounds__(64 * NW) void k_iface_mfma(IfaceProds<T> ps, int L, int nrhs, int qtiles) {
   using V = typename Mfma<T>::v4;
   __shared__ C<T> red[NW][16][17];
   const int nt = iface_tiles(L);
-  const bool two = pb.M != nullptr;
-  const IfaceProd<T> pr = two && blockIdx.z ? pb : pa;
-  const C<T>* MZ = pr.M;
+  const IfaceProd<T> pr = ps.p[blockIdx.z];
   const C<T>* add = pr.add;
   C<T>* y = pr.y;
   const int id = blockIdx.x;
   const int per = 8 * qtiles;  // workgroups per group of 8 row blocks
   const int r = (id / per) * 8 + id % 8, q = (id % per) / 8;
   if (r >= nt) return;  // whole workgroup: the grid is rounded up to 8 row blocks
-  const int k = kbeg + (two ? 0 : (int)blockIdx.z);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g4 = lane >> 4;
   const int Lp = iface_vec_len(L);
-  const C<T>* Mr = MZ + (size_t)k * mstride + (size_t)r * nt * 256 + lane * 4;
+  const C<T>* Mr = pr.M + (size_t)r * nt * 256 + lane * 4;
   // columns past nrhs read the last one: their outputs are not stored
-  const C<T>* Bc = x + (size_t)(k + xoff) * vstride + (size_t)min(q * 16 + li, nrhs - 1) * Lp + 4 * g4;
+  const C<T>* Bc = pr.x + (size_t)min(q * 16 + li, nrhs - 1) * Lp + 4 * g4;
   // this wave's contraction blocks: an even share [b0, b1)
   const int b0 = wave * nt / NW, b1 = (wave + 1) * nt / NW;
   V p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
@@ -618,13 +614,15 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(IfaceProd<T> pa, IfacePr
       C<T> sum = red[0][orow][oc];
 #pragma unroll
       for (int w = 1; w < NW; ++w) sum = cadd<T>(sum, red[w][orow][oc]);
-      const size_t o = (size_t)k * vstride + (size_t)Q * Lp + R;
+      const size_t o = (size_t)Q * Lp + R;
       y[o] = csub<T>(add[o], sum);
     }
   }
 }
 
-// f on the first line of D_k -= Hm_k lambda_{k-1}; on its last line -= Hp_k mu_{k+1}.
+// f on the first local line of D_k -= Hm_k lambda_prev; on its last local line
+// -= Hp_k mu_next (lambda_next where the next slice's last line is the
+// neighbour: the slices next to the two-front middle slice, and that slice).
 // f interleaved [L][L][nrhs]. A workgroup takes one slice (blockIdx.y), 64
 // positions j along the line and 16 right-hand sides: the three taps of each
 // vector are read along j, the sums cross LDS and leave with the right-hand
@@ -639,7 +637,9 @@ __global__ __launch_bounds__(256) void k_couple(SliceTables P, int L, int b, con
   const int j0 = blockIdx.x * 64, q0 = blockIdx.z * 16;
   const int t = threadIdx.x, c = t & 63, sub = t >> 6, j = j0 + c;
   const int Lp = iface_vec_len(L);
-  const bool hasm = k > 0, hasp = k < P.nslices - 1;
+  const int prev = P.prev[k], next = P.next[k];
+  const bool hasm = prev >= 0, hasp = next >= 0;
+  const C<T>* nvec = P.next_lam[k] ? lam : mu;
   // coefficients of this position (zero off the line: those taps are masked)
   C<T> cm[3], cp[3];
   int at[3];
@@ -658,7 +658,7 @@ __global__ __launch_bounds__(256) void k_couple(SliceTables P, int L, int b, con
     const int rr = q0 + sub + 4 * s, rq = min(rr, nrhs - 1);
     C<T> am = mk<T>(0, 0), ap = mk<T>(0, 0);
     if (hasm) {
-      const C<T>* lv = lam + ((size_t)(k - 1) * nrhs + rq) * Lp;
+      const C<T>* lv = lam + ((size_t)prev * nrhs + rq) * Lp;
       C<T> v[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) v[d] = lv[at[d]];
@@ -667,7 +667,7 @@ __global__ __launch_bounds__(256) void k_couple(SliceTables P, int L, int b, con
         if (ok[d]) am = cfma<T>(am, cm[d], v[d]);
     }
     if (hasp) {
-      const C<T>* mv = mu + ((size_t)(k + 1) * nrhs + rq) * Lp;
+      const C<T>* mv = nvec + ((size_t)next * nrhs + rq) * Lp;
       C<T> v[3];
 #pragma unroll
       for (int d = 0; d < 3; ++d) v[d] = mv[at[d]];
@@ -679,7 +679,9 @@ __global__ __launch_bounds__(256) void k_couple(SliceTables P, int L, int b, con
     tp[c][sub + 4 * s] = ap;
   }
   __syncthreads();
-  const int lo = P.lo[k] + b, hi = P.hi[k] + b;
+  // grid rows (+ b) of D_k's first and last local lines
+  const int tw = P.hi[k] - P.lo[k] + 1, naux = P.naux[k];
+  const int lo = P.org[k] + P.dir[k] * naux + b, hi = P.org[k] + P.dir[k] * (naux + tw - 1) + b;
 #pragma unroll
   for (int s = 0; s < 4; ++s) {
     const int idx = t + 256 * s;
@@ -785,33 +787,49 @@ template hipError_t launch_swizzle_maps<double>(const double2*, double2*, int, i
 template hipError_t launch_swizzle_maps<float>(const float2*, float2*, int, int, hipStream_t);
 
 template <typename T>
-hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
-                             int kcount, size_t mstride, size_t vstride, int xoff, bool mfma, hipStream_t st,
-                             const C<T>* M2, const C<T>* add2, C<T>* y2) {
-  if (kcount <= 0) return hipSuccess;
-  const int nt = iface_tiles(L);
+hipError_t launch_iface_prods(const IfaceProd<T>* prods, int nprods, int L, int nrhs, bool mfma, hipStream_t st) {
+  if (nprods <= 0) return hipSuccess;
+  if (nprods > kIfaceMaxProds) return hipErrorInvalidValue;
   if (!mfma && nrhs > 4) return hipErrorInvalidValue;  // the vector form holds at most 4 columns
-  if (M2 && kcount != 1) return hipErrorInvalidValue;  // a second product only beside a single one
-  const IfaceProd<T> p0{M, add, y}, p1{M2, add2, y2};
-  const int nz = M2 ? 2 : kcount;
+  IfaceProds<T> ps{};
+  for (int i = 0; i < nprods; ++i) ps.p[i] = prods[i];
+  const int nt = iface_tiles(L);
   if (!mfma) {
     constexpr int NW = 8;
-    hipLaunchKernelGGL((k_iface_gemv<T, NW>), dim3(nt, 1, nz), dim3(64 * NW), 0, st, p0, p1, x, L, nrhs, kbeg,
-                       mstride, vstride, xoff);
+    hipLaunchKernelGGL((k_iface_gemv<T, NW>), dim3(nt, 1, nprods), dim3(64 * NW), 0, st, ps, L, nrhs);
   } else {
     const int qtiles = (nrhs + 15) / 16, groups = (nt + 7) / 8;
-    const dim3 grid(groups * 8 * qtiles, 1, nz), block(64 * kMfmaWaves);
+    const dim3 grid(groups * 8 * qtiles, 1, nprods), block(64 * kMfmaWaves);
     // more than two column tiles put two workgroups on some compute units,
     // where three blocks of loads in flight per wave measured fastest (9.2
     // against 9.4 ms per C2 interface graph with two, slower with four)
     if (qtiles > 2)
-      hipLaunchKernelGGL((k_iface_mfma<T, kMfmaWaves, 3>), grid, block, 0, st, p0, p1, x, L, nrhs, kbeg, mstride,
-                         vstride, xoff, qtiles);
+      hipLaunchKernelGGL((k_iface_mfma<T, kMfmaWaves, 3>), grid, block, 0, st, ps, L, nrhs, qtiles);
     else
-      hipLaunchKernelGGL((k_iface_mfma<T>), grid, block, 0, st, p0, p1, x, L, nrhs, kbeg, mstride, vstride, xoff,
-                         qtiles);
+      hipLaunchKernelGGL((k_iface_mfma<T>), grid, block, 0, st, ps, L, nrhs, qtiles);
   }
   return hipGetLastError();
+}
+template hipError_t launch_iface_prods<double>(const IfaceProd<double>*, int, int, int, bool, hipStream_t);
+template hipError_t launch_iface_prods<float>(const IfaceProd<float>*, int, int, int, bool, hipStream_t);
+
+template <typename T>
+hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
+                             int kcount, size_t mstride, size_t vstride, int xoff, bool mfma, hipStream_t st,
+                             const C<T>* M2, const C<T>* add2, C<T>* y2) {
+  if (kcount <= 0) return hipSuccess;
+  if (M2 && kcount != 1) return hipErrorInvalidValue;  // a second product only beside a single one
+  if (kcount > kIfaceMaxProds) return hipErrorInvalidValue;
+  IfaceProd<T> ps[kIfaceMaxProds];
+  int np = 0;
+  for (int i = 0; i < kcount; ++i) {
+    const int k = kbeg + i;
+    ps[np++] = {M + (size_t)k * mstride, add + (size_t)k * vstride, x + (size_t)(k + xoff) * vstride,
+                y + (size_t)k * vstride};
+  }
+  if (M2) ps[np++] = {M2 + (size_t)kbeg * mstride, add2 + (size_t)kbeg * vstride, x + (size_t)(kbeg + xoff) * vstride,
+                      y2 + (size_t)kbeg * vstride};
+  return launch_iface_prods<T>(ps, np, L, nrhs, mfma, st);
 }
 template hipError_t launch_iface_step<double>(const double2*, const double2*, const double2*, double2*, int, int,
                                               int, int, size_t, size_t, int, bool, hipStream_t, const double2*,

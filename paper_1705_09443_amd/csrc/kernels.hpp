@@ -56,11 +56,22 @@ struct StencilTables {
 // 16-byte boundary.
 __host__ __device__ inline int factor_stride(int t, int tw) { return (t * t + t * tw + 1) & ~1; }
 
+// Per slice, in table order. A subproblem's t lines are numbered locally in
+// the order of its front, a = 0..t-1 at grid line org + dir a: naux auxiliary
+// lines, the tw = hi - lo + 1 lines of D_k, then t - naux - tw auxiliary lines
+// (the two-front middle slice only). Every slice kernel works in these local
+// coordinates: the stencil offset d1 along local lines is dir d1 in the grid.
 struct SliceTables {
   const int* lo;     // per slice: first grid line of D_k
   const int* hi;     // last grid line of D_k
-  const int* first;  // first line of the subproblem
+  const int* first;  // lowest grid line of the subproblem
   const int* t;      // lines of the subproblem
+  const int* naux;   // auxiliary lines before D_k, locally
+  const int* org;    // grid line of local line 0
+  const int* dir;    // +1 (along x1) or -1
+  const int* prev;   // slice coupled to D_k's first local line (eliminated earlier), -1: none
+  const int* next;   // slice coupled to D_k's last local line, -1: none
+  const int* next_lam;  // 1: that coupling reads the next slice's lambda, 0: its mu
   const size_t* fs_off;  // offset (complex elements) of slice k in FS: L x factor_stride(t, tw)
   const size_t* fg_off;  // offset of slice k in FG: L x factor_stride(t, 0)
   int nslices;
@@ -187,19 +198,30 @@ struct SliceMfmaArgs {
 template <typename T>
 hipError_t launch_slice_mfma(const SliceMfmaArgs<T>& a, int nslices, hipStream_t st);
 
-// y_k = add_k - M_k x_{k+xoff} for k = kbeg .. kbeg+kcount-1 (in place allowed, y == add);
-// M in operand order (mstride = iface_map_stride(L)); x, add, y [nrhs][Lp]
-// per slice (vstride apart). mfma: on the matrix cores, one workgroup per
-// 16 x 16 output tile; else vector dot products (nrhs <= 4,
-// hipErrorInvalidValue above).
-// With M2 (kcount = 1), the same launch also forms y2_k = add2_k - M2_k x_{k+xoff}
-// from the same x.
+// One product of an interface step, y = add - M x, every pointer already at
+// its slice: M one L x L map in operand order, x, add, y [nrhs][Lp] (in place
+// allowed, y == add).
 template <typename T>
 struct IfaceProd {
   const C<T>* M;
   const C<T>* add;
+  const C<T>* x;
   C<T>* y;
 };
+constexpr int kIfaceMaxProds = 4;
+template <typename T>
+struct IfaceProds {
+  IfaceProd<T> p[kIfaceMaxProds];
+};
+// Up to kIfaceMaxProds independent products in one launch (blockIdx.z picks
+// one; none may write what another reads). mfma: on the matrix cores, one
+// workgroup per 16 x 16 output tile; else vector dot products (nrhs <= 4,
+// hipErrorInvalidValue above).
+template <typename T>
+hipError_t launch_iface_prods(const IfaceProd<T>* prods, int nprods, int L, int nrhs, bool mfma, hipStream_t st);
+// y_k = add_k - M_k x_{k+xoff} for k = kbeg .. kbeg+kcount-1, maps mstride
+// apart (iface_map_stride(L)), vectors vstride apart; with M2 (kcount = 1)
+// the same launch also forms y2_k = add2_k - M2_k x_{k+xoff}.
 template <typename T>
 hipError_t launch_iface_step(const C<T>* M, const C<T>* add, const C<T>* x, C<T>* y, int L, int nrhs, int kbeg,
                              int kcount, size_t mstride, size_t vstride, int xoff, bool mfma, hipStream_t st,

@@ -502,8 +502,75 @@ void stencil_cache(bool clear, long long* hits, long long* misses) {
   }
 }
 
+std::vector<SlicePlan> plan_slices(int n, int b, int w, int fronts) {
+  std::vector<SlicePlan> out;
+  const int p = fronts == 2 ? (n + 1) / (2 * w) : 0;
+  if (fronts != 2 || p == 0) {
+    const int nl = fronts == 2 ? 1 : std::max(1, (n + 2) / w);
+    out.resize(nl);
+    for (int k = 0; k < nl; ++k) {
+      SlicePlan& q = out[k];
+      q.lo = (k == 0) ? -b : k * w;
+      q.hi = (k == nl - 1) ? n + 1 + b : (k + 1) * w - 1;
+      q.first = (k == 0) ? q.lo : q.lo - b;
+      q.t = q.hi - q.first + 1;
+      q.naux = q.lo - q.first;
+      q.org = q.first;
+      q.dir = 1;
+      q.prev = k - 1;
+      q.next = k + 1 < nl ? k + 1 : -1;
+      q.grid = k;
+    }
+    return out;
+  }
+  out.resize(2 * p + 1);
+  const int mid = 2 * p;
+  for (int k = 0; k < p; ++k) {  // left front, along x1
+    SlicePlan& q = out[k];
+    q.lo = k == 0 ? -b : k * w;
+    q.hi = (k + 1) * w - 1;
+    q.naux = k == 0 ? 0 : b;
+    q.first = q.lo - q.naux;
+    q.t = q.hi - q.first + 1;
+    q.org = q.first;
+    q.dir = 1;
+    q.prev = k - 1;
+    q.next = k + 1 < p ? k + 1 : mid;
+    q.next_lam = 0;
+    q.grid = k;
+  }
+  for (int j = 0; j < p; ++j) {  // right front, against x1
+    SlicePlan& q = out[p + j];
+    q.lo = n + 2 - (j + 1) * w;
+    q.hi = j == 0 ? n + 1 + b : n + 1 - j * w;
+    q.naux = j == 0 ? 0 : b;
+    q.first = q.lo;
+    q.t = q.hi - q.lo + 1 + q.naux;
+    q.org = q.hi + q.naux;
+    q.dir = -1;
+    q.prev = j == 0 ? -1 : p + j - 1;
+    q.next = j + 1 < p ? p + j + 1 : mid;
+    q.next_lam = j + 1 < p ? 0 : 1;  // next to the middle slice: its last line
+    q.grid = 2 * p - j;
+  }
+  SlicePlan& q = out[mid];  // middle: auxiliary lines on both sides
+  q.lo = p * w;
+  q.hi = n + 1 - p * w;
+  q.naux = b;
+  q.nauxr = b;
+  q.first = q.lo - b;
+  q.t = q.hi - q.lo + 1 + 2 * b;
+  q.org = q.first;
+  q.dir = 1;
+  q.prev = p - 1;       // the left front's last slice (its lambda)
+  q.next = 2 * p - 1;   // the right front's last slice (its lambda)
+  q.next_lam = 1;
+  q.grid = p;
+  return out;
+}
+
 std::string build_host_setup(const double* m, int n, double omega, int b, int w, double C,
-                             int freq_samples, HostSetup& S) {
+                             int freq_samples, HostSetup& S, int fronts) {
   char buf[256];
   if (n < 1) return "n must be >= 1";
   if (!(omega > 0.0) || !std::isfinite(omega)) return "omega must be finite and > 0";
@@ -657,31 +724,38 @@ std::string build_host_setup(const double* m, int n, double omega, int b, int w,
     stencil_insert(make_entry(2, n, omega, b, C, S.kq, S.gamma_glob, S.alpha, S.beta, S.alpha_sv, 9));
   }
 
-  // ---- slices (reading G8) ----
-  const int nl = std::max(1, (n + 2) / w);
+  // ---- slices (readings G8, G18) ----
+  if (fronts != 1 && fronts != 2) return "fronts must be 1 or 2";
+  S.fronts = fronts;
+  S.slices = plan_slices(n, b, w, fronts);
+  const int nl = (int)S.slices.size();
   S.nslices = nl;
-  S.slices.resize(nl);
-  for (int k = 0; k < nl; ++k) {
-    SlicePlan& p = S.slices[k];
-    p.lo = (k == 0) ? -b : k * w;
-    p.hi = (k == nl - 1) ? n + 1 + b : (k + 1) * w - 1;
-    p.first = (k == 0) ? p.lo : p.lo - b;
-    p.t = p.hi - p.first + 1;
-    p.naux = p.lo - p.first;
-    if (p.t > 32) {
-      std::snprintf(buf, sizeof buf, "slice %d has %d lines; at most 32 are supported (reduce w or b)", k, p.t);
+  for (int k = 0; k < nl; ++k)
+    if (S.slices[k].t > 32) {
+      std::snprintf(buf, sizeof buf, "slice %d has %d lines; at most 32 are supported (reduce w or b)",
+                    S.slices[k].grid, S.slices[k].t);
       return buf;
     }
-  }
 
   // ---- auxiliary PML stencils at the sampled local frequencies (Sec. 2.3) ----
-  // Only (depth, class, sample) triples that some auxiliary point uses are built.
+  // Stored for the auxiliary PML before a slice's D_k in its own (local) order;
+  // lines after D_k (the two-front middle slice) take the same stencil with
+  // the x1 offsets mirrored. Only (depth, class, sample) triples that some
+  // auxiliary point uses are built.
   S.gamma_aux.assign((size_t)b * NC * ns * 9, cd(0.0));
   std::vector<char> used((size_t)b * NC * ns, 0);
-  for (int k = 1; k < nl; ++k) {
+  for (int k = 0; k < nl; ++k) {
     const SlicePlan& p = S.slices[k];
-    for (int q = 0; q < b; ++q) {
-      const int line = p.lo - 1 - q;
+    const int tw = p.hi - p.lo + 1;
+    for (int a = 0; a < p.t; ++a) {
+      int q;
+      if (a < p.naux)
+        q = p.naux - 1 - a;
+      else if (a >= p.naux + tw)
+        q = a - p.naux - tw;
+      else
+        continue;
+      const int line = p.org + p.dir * a;
       for (int e2 = 0; e2 < L; ++e2) {
         const int c2 = axis_class(e2 - b, n, b);
         const int ks = S.kmap[(size_t)(line + b) * L + e2];

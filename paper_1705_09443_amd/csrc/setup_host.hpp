@@ -13,16 +13,31 @@ namespace lsw {
 
 using cd = std::complex<double>;
 
+// One slice subproblem. Its t lines are numbered locally a = 0..t-1 in the
+// order of its front: grid line org + dir * a. Local lines [0, naux) are
+// auxiliary PML before D_k, [naux, naux + (hi - lo + 1)) are D_k, the rest
+// (nauxr lines) auxiliary PML after it. The one-front sweep and the left front
+// of the two-front sweep run along x1 (dir = +1, auxiliary lines left of
+// D_k); the right front runs against it (dir = -1: its auxiliary lines, right
+// of D_k in the grid, come first locally); the two-front middle slice has
+// auxiliary lines on both sides.
 struct SlicePlan {
   int lo;     // first grid line i1 of D_k
   int hi;     // last grid line of D_k
-  int first;  // first line of the subproblem (lo - b for k > 0, lo for k = 0)
-  int t;      // lines in the subproblem, hi - first + 1
-  int naux;   // auxiliary lines, lo - first
+  int first;  // lowest grid line of the subproblem
+  int t;      // lines in the subproblem
+  int naux;   // auxiliary lines before D_k (local order)
+  int nauxr = 0;     // auxiliary lines after D_k (local order)
+  int org = 0;       // grid line of local line 0
+  int dir = 1;       // +1 or -1
+  int prev = -1;     // slice (table index) eliminated just before, coupled to D_k's first local line; -1: none
+  int next = -1;     // slice coupled to D_k's last local line, eliminated after; -1: none
+  int next_lam = 0;  // 1: that coupling takes the next slice's last line (lambda), 0 its first line (mu)
+  int grid = 0;      // position of the slice in grid order
 };
 
 struct HostSetup {
-  int n = 0, b = 0, w = 0, L = 0, P = 0, nslices = 0, ns = 0;
+  int n = 0, b = 0, w = 0, L = 0, P = 0, nslices = 0, ns = 0, fronts = 1;
   double omega = 0, h = 0, C = 0;
   double freq_lo = 0, freq_delta = 0;
   std::vector<cd> kq;          // k_delta for delta in [0, n+1]^2, [(n+2)][(n+2)]
@@ -70,7 +85,14 @@ std::vector<cd> green3_octant(int n, double omega);
 // process-wide cache of the last kStencilCacheEntries keys (shared with the
 // 3D setup, keyed by dimension too) and reused.
 std::string build_host_setup(const double* m_host, int n, double omega, int b, int w, double C,
-                             int freq_samples, HostSetup& out);
+                             int freq_samples, HostSetup& out, int fronts = 1);
+// The slices in table order (see SlicePlan). One front (Algorithms 1-2,
+// reading G8): l = floor((n+2)/w) slices along x1, the last taking the
+// remainder. Two fronts (the first remark after Algorithm 2, Sec. 2.4;
+// reading G18): p = floor((n+1)/(2w)) slices of w lines from each end, then
+// the middle slice of the remaining 1..2w lines, eliminated last; table order
+// is the left front outward-in, the right front outward-in, the middle.
+std::vector<SlicePlan> plan_slices(int n, int b, int w, int fronts);
 constexpr int kStencilCacheEntries = 4;
 // Counters of that cache since the last clear; clear = true empties it.
 void stencil_cache(bool clear, long long* hits, long long* misses);

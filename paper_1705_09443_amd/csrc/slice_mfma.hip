@@ -110,8 +110,8 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
   constexpr int WREC = RT * RT * 256 + RT * NSD * 64, GREC = RT * RT * 256;
   const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const int L = A.L, b = A.b;
-  const int lo = A.P.lo[k], hi = A.P.hi[k], first = A.P.first[k], t = A.P.t[k];
-  const int naux = lo - first, tw = hi - lo + 1;
+  const int lo = A.P.lo[k], hi = A.P.hi[k], t = A.P.t[k];
+  const int naux = A.P.naux[k], tw = hi - lo + 1, org = A.P.org[k], dir = A.P.dir[k];
   const int n = q * 16 + li;
   const bool valid = n < A.nrhs;
   const int nc = valid ? n : A.nrhs - 1;  // loads of padding columns read a real one
@@ -132,9 +132,11 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
     const int line = 4 * cc + g;
     const int lc = line < tw ? line : tw - 1;
     rok[cc] = valid && line < tw;
+    // D_k's local line lc: grid line org + dir (naux + lc); in a slice array
+    // (grid order) row lc, or tw - 1 - lc against x1
     rp[cc] = UNIT ? hrow + (size_t)k * L * 3
-                  : A.src + (A.src_kind == kSrcGrid ? (size_t)(lo + lc + b) * L * A.nrhs + nc
-                                                    : ((size_t)nc * tw + lc) * L);
+                  : A.src + (A.src_kind == kSrcGrid ? (size_t)(org + dir * (naux + lc) + b) * L * A.nrhs + nc
+                                                    : ((size_t)nc * tw + (dir > 0 ? lc : tw - 1 - lc)) * L);
   }
   // step stride along j of the right-hand sides: the interleaved grid holds
   // nrhs values per point
@@ -169,12 +171,13 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
         C<T>* p0 = nullptr;
         C<T>* p1 = nullptr;
         if (valid && a < t) {
+          const bool inD = a >= naux && a < naux + tw;
           if (A.dst_kind == kDstGrid) {
-            if (a >= naux) p0 = A.dst + (size_t)(first + a + b) * L * A.nrhs + n;
+            if (inD) p0 = A.dst + (size_t)(org + dir * a + b) * L * A.nrhs + n;
           } else if (A.dst_kind == kDstSlice) {
-            if (a >= naux) p0 = A.dst + ((size_t)n * tw + a - naux) * L;
+            if (inD) p0 = A.dst + ((size_t)n * tw + (dir > 0 ? a - naux : tw - 1 - (a - naux))) * L;
           } else {
-            if (a == t - 1 && A.dstE) p0 = A.dstE + k * A.sk + ci * A.sr;
+            if (a == naux + tw - 1 && A.dstE) p0 = A.dstE + k * A.sk + ci * A.sr;
             if (a == naux && A.dstF) p1 = A.dstF + k * A.sk + ci * A.sr;
           }
         }

@@ -229,11 +229,11 @@ __global__ __launch_bounds__(256) void k_factor(StencilTables S, SliceTables P, 
                                                 C<T>* __restrict__ Hp, int* __restrict__ status) {
   const int k = blockIdx.x;
   const int tid = threadIdx.x, nt = blockDim.x;
-  const int lo = P.lo[k], hi = P.hi[k], first = P.first[k], t = P.t[k];
-  const int naux = lo - first;
+  const int lo = P.lo[k], hi = P.hi[k], t = P.t[k];
+  const int naux = P.naux[k], org = P.org[k], dir = P.dir[k];
   const int L = S.L, b = S.b;
   const int W = 2 * t;
-  const int tw = t - naux;  // lines of D_k
+  const int tw = hi - lo + 1;  // lines of D_k
   const int tt = t * t, fstride = factor_stride(t, tw), gstride = factor_stride(t, 0);
   __shared__ double2 Gp[kTMax * kTMax];
   __shared__ double2 M[kTMax * 2 * kTMax];
@@ -245,17 +245,20 @@ __global__ __launch_bounds__(256) void k_factor(StencilTables S, SliceTables P, 
   C<T>* fg = FG + P.fg_off[k];
   for (int j = 0; j < L; ++j) {
     // 1. the three tridiagonal blocks of block row j
+    // local lines a and offsets d1: grid line org + dir a, grid offset dir d1
     for (int idx = tid; idx < t * 9; idx += nt) {
       const int a = idx / 9, o = idx % 9, d1 = o / 3 - 1, d2 = o % 3 - 1;
-      const int line = first + a, i2 = j - b;
+      const int line = org + dir * a, i2 = j - b;
       double2 c = make_double2(0.0, 0.0);
       if (a + d1 >= 0 && a + d1 < t && j + d2 >= 0 && j + d2 < L) {
-        if (a < naux) {
-          const int q = lo - 1 - line;
+        if (a < naux) {  // auxiliary PML before D_k, depth q from D_k's edge
           const int ks = S.kmap[(size_t)(line + b) * L + j];
-          c = aux_coef(S, q, i2, ks, d1, d2);
+          c = aux_coef(S, naux - 1 - a, i2, ks, d1, d2);
+        } else if (a >= naux + tw) {  // after D_k: the same stencils, mirrored
+          const int ks = S.kmap[(size_t)(line + b) * L + j];
+          c = aux_coef(S, a - naux - tw, i2, ks, -d1, d2);
         } else {
-          c = h_coef(S, line, i2, d1, d2);
+          c = h_coef(S, line, i2, dir * d1, d2);
         }
       }
       double2* dst = d2 < 0 ? Bt : (d2 == 0 ? At : Ct);
@@ -364,13 +367,16 @@ __global__ __launch_bounds__(256) void k_factor(StencilTables S, SliceTables P, 
     }
     lds_barrier();
   }
-  // couplings H_[k,k-1] (first line of D_k) and H_[k,k+1] (last line of D_k)
+  // couplings to the slices before and after in the front's order: Hm from
+  // D_k's first local line one line back, Hp from its last local line one
+  // line on (H_[k,k-1] and H_[k,k+1] of the one-front sweep)
+  const int dfirst = org + dir * naux, dlast = org + dir * (naux + tw - 1);
   for (int idx = tid; idx < 3 * L; idx += nt) {
     const int j = idx / 3, d2 = idx % 3 - 1;
     const bool ok = j + d2 >= 0 && j + d2 < L;
     double2 cm = make_double2(0.0, 0.0), cp = make_double2(0.0, 0.0);
-    if (ok && k > 0) cm = h_coef(S, lo, j - b, -1, d2);
-    if (ok && k < P.nslices - 1) cp = h_coef(S, hi, j - b, +1, d2);
+    if (ok && P.prev[k] >= 0) cm = h_coef(S, dfirst, j - b, -dir, d2);
+    if (ok && P.next[k] >= 0) cp = h_coef(S, dlast, j - b, dir, d2);
     Hm[(size_t)k * L * 3 + idx] = ccast<T, double>(cm);
     Hp[(size_t)k * L * 3 + idx] = ccast<T, double>(cp);
   }

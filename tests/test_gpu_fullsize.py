@@ -1,9 +1,10 @@
 """Parity at the full 2D workload size: 1023^2, omega = 2 pi 64, b = 12, w = 4,
 the seeded 32-bump medium, in the launch configurations the benchmark times
-(one float64 wave; 64 mixed-precision waves in one batch).
+(one float64 wave; 64 mixed-precision waves in one batch), for the two-front
+sweep the benchmark runs and for the single front of Algorithms 1-2.
 
-Against the oracle at this size (its setup factors all 256 slice
-subproblems once for the module):
+Against the oracle at this size with the same number of fronts (its setup
+factors every slice subproblem once per configuration):
 * A x at sampled points by direct summation (eq. LS_d_c), float64 and mixed;
 * single slice solves T~_k v (eq. Hwv_approx) for the first, a middle and
   the last (32-line) slice, float64 <= 1e-10 and complex64 <= 1e-5 (P5);
@@ -53,21 +54,26 @@ def _cores():
     return max(1, min(16, len(os.sched_getaffinity(0))))
 
 
-@pytest.fixture(scope="module")
-def c1():
+@pytest.fixture(scope="module", params=[2, 1], ids=["two_fronts", "one_front"])
+def c1(request):
+    # the benchmark's configuration (two sweeping fronts) first, then the
+    # single front of Algorithms 1-2
+    fronts = request.param
     wl = workloads.workload("C1")
     m = wl.medium_array()
-    say(f"[fullsize] oracle setup n={wl.n} (Green table, stencils, 256 slice factorizations)")
-    ref = oracle.OracleSolver(2, wl.n, wl.omega, m, wl.pml_width, wl.layer_thickness, workers=_cores())
-    return wl, m, ref
+    say(f"[fullsize] oracle setup n={wl.n}, {fronts} front(s) (Green table, stencils, slice factorizations)")
+    ref = oracle.OracleSolver(2, wl.n, wl.omega, m, wl.pml_width, wl.layer_thickness, workers=_cores(),
+                              fronts=fronts)
+    yield wl, m, ref, fronts
+    del ref
 
 
 @pytest.fixture(scope="module")
 def gpu_fp64(c1):
     from paper_1705_09443_amd import LSSolver
-    wl, m, _ = c1
+    wl, m, _, fronts = c1
     s = LSSolver(torch.as_tensor(m, device="cuda:0"), wl.omega, wl.pml_width, wl.layer_thickness,
-                 precision="fp64")
+                 precision="fp64", fronts=fronts)
     yield s
     s.close()
 
@@ -76,9 +82,9 @@ def gpu_fp64(c1):
 def gpu_mixed(c1):
     from paper_1705_09443_amd import LSSolver
     wl2 = workloads.workload("C2")
-    _, m, _ = c1
+    _, m, _, fronts = c1
     s = LSSolver(torch.as_tensor(m, device="cuda:0"), wl2.omega, wl2.pml_width, wl2.layer_thickness,
-                 precision="mixed", restart=wl2.restart)
+                 precision="mixed", restart=wl2.restart, fronts=fronts)
     yield s
     s.close()
 
@@ -86,7 +92,9 @@ def gpu_mixed(c1):
 @pytest.mark.timeout(900)
 @pytest.mark.parametrize("precision,bound", [("fp64", 1e-11), ("mixed", 2e-5)])
 def test_apply_A_sampled(c1, gpu_fp64, precision, bound):
-    wl, m, ref = c1
+    wl, m, ref, fronts = c1
+    if fronts != 2:
+        pytest.skip("the operator does not depend on the sweep: one configuration suffices")
     op = ref.op
     n = wl.n
     rng = np.random.default_rng(5)
@@ -103,14 +111,14 @@ def test_apply_A_sampled(c1, gpu_fp64, precision, bound):
 
 @pytest.mark.parametrize("precision,bound", [("fp64", 1e-10), ("mixed", 1e-5)])
 def test_slice_solves_sampled_slices(c1, gpu_fp64, gpu_mixed, precision, bound):
-    wl, _, ref = c1
+    wl, _, ref, fronts = c1
     sw = ref.sweep
     gpu = gpu_fp64 if precision == "fp64" else gpu_mixed
     assert gpu.nslices == sw.nslices
     rng = np.random.default_rng(11)
     for k in SLICES:
         lo, hi, naux = gpu.slice_bounds(k)
-        assert (lo, hi) == sw.bounds[k] and naux * gpu.L == sw.aux_count[k]
+        assert (lo, hi) == sw.bounds[k] and naux * gpu.L == sw.aux_count[k] + sw.aux_count_right[k]
         v = rng.standard_normal((2, hi - lo + 1, gpu.L)) + 1j * rng.standard_normal((2, hi - lo + 1, gpu.L))
         dt = np.complex128 if precision == "fp64" else np.complex64
         w = gpu.slice_solve(k, torch.as_tensor(v.astype(dt), device="cuda:0"), precision=precision)
@@ -127,19 +135,23 @@ def test_preconditioner_full_size(c1, gpu_fp64, gpu_mixed):
     # the library against the oracle's slice-by-slice sweep, and against the
     # library's own slice-by-slice schedule
     from paper_1705_09443_amd import LSSolver
-    wl, m, ref = c1
+    wl, m, ref, fronts = c1
     n = wl.n
     rng = np.random.default_rng(12)
     r = rng.standard_normal((2, n, n)) + 1j * rng.standard_normal((2, n, n))
     z = gpu_fp64.apply_precond(torch.as_tensor(r, device="cuda:0")).cpu().numpy()
     z32 = gpu_mixed.apply_precond(torch.as_tensor(r.astype(np.complex64), device="cuda:0")).cpu().numpy()
-    with LSSolver(torch.as_tensor(m, device="cuda:0"), wl.omega, wl.pml_width, wl.layer_thickness,
-                  precision="fp64", schedule="sequential") as sq:
-        zs = sq.apply_precond(torch.as_tensor(r, device="cuda:0")).cpu().numpy()
+    zs = None
+    if fronts == 1:   # the slice-by-slice schedule exists for one front
+        with LSSolver(torch.as_tensor(m, device="cuda:0"), wl.omega, wl.pml_width, wl.layer_thickness,
+                      precision="fp64", schedule="sequential") as sq:
+            zs = sq.apply_precond(torch.as_tensor(r, device="cuda:0")).cpu().numpy()
     for j in range(2):
         zr = ref.precondition(r[j])
-        e64, e32, es, eis = rel(z[j], zr), rel(z32[j], zr), rel(zs[j], zr), rel(z[j], zs[j])
-        say(f"[P r 1023^2 col {j}] vs oracle: interface fp64 {e64:.2e}, sequential fp64 {es:.2e}, "
+        e64, e32 = rel(z[j], zr), rel(z32[j], zr)
+        es = rel(zs[j], zr) if zs is not None else 0.0
+        eis = rel(z[j], zs[j]) if zs is not None else 0.0
+        say(f"[P r 1023^2 {fronts} front(s) col {j}] vs oracle: interface fp64 {e64:.2e}, sequential fp64 {es:.2e}, "
             f"interface complex64 {e32:.2e}; interface vs sequential fp64 {eis:.2e}")
         assert e64 <= 1e-10 and es <= 1e-10 and eis <= 1e-10
         assert e32 <= 1e-5
@@ -153,7 +165,7 @@ def _true_residual(op, uinc, u):
 @pytest.mark.timeout(900)
 def test_fp64_solve_c1(c1, gpu_fp64):
     from paper_1705_09443_amd import LSSolver
-    wl, m, ref = c1
+    wl, m, ref, fronts = c1
     uinc = wl.incident()
     u, info = gpu_fp64.solve(torch.as_tensor(uinc, device="cuda:0"), "incident", wl.tol)
     u = u.cpu().numpy()
@@ -161,7 +173,7 @@ def test_fp64_solve_c1(c1, gpu_fp64):
     g = ref.op.rhs_incident(uinc[0])
     ro = ref.solve_rhs(g, wl.tol)
     k = ro.iterations
-    say(f"[C1 fp64] iterations {info[0].iterations} (oracle {k}), library residual "
+    say(f"[C1 fp64, {fronts} front(s)] iterations {info[0].iterations} (oracle {k}), library residual "
         f"{info[0].rel_residual:.2e}, oracle-operator residual {res:.2e}")
     assert info[0].converged and res <= wl.tol * 1.01
     assert abs(k - info[0].iterations) <= 1                                   # P2
@@ -169,7 +181,7 @@ def test_fp64_solve_c1(c1, gpu_fp64):
     # within one cycle, so its solution is its iterate after those k steps
     assert k <= ref.restart and ro.converged
     with LSSolver(torch.as_tensor(m, device="cuda:0"), wl.omega, wl.pml_width, wl.layer_thickness,
-                  precision="fp64", max_iters=k) as sk:
+                  precision="fp64", max_iters=k, fronts=fronts) as sk:
         uk, ik = sk.solve(torch.as_tensor(uinc, device="cuda:0"), "incident", 1e-300, allow_noconv=True)
     assert ik[0].iterations == k
     e = rel(uk.cpu().numpy()[0], ro.x)
@@ -180,13 +192,13 @@ def test_fp64_solve_c1(c1, gpu_fp64):
 @pytest.mark.timeout(1200)
 def test_mixed_batched_solve_c2(c1, gpu_mixed):
     wl2 = workloads.workload("C2")
-    _, m, ref = c1
+    _, m, ref, fronts = c1
     uinc = wl2.incident()
     u, info = gpu_mixed.solve(torch.as_tensor(uinc, device="cuda:0"), "incident", wl2.tol)
     u = u.cpu().numpy()
     res = np.array([_true_residual(ref.op, uinc[j], u[j]) for j in range(uinc.shape[0])])
     its = [i.iterations for i in info]
-    say(f"[C2 mixed] 64 waves, iterations {min(its)}..{max(its)}, oracle-operator residual max {res.max():.2e}")
+    say(f"[C2 mixed, {fronts} front(s)] 64 waves, iterations {min(its)}..{max(its)}, oracle-operator residual max {res.max():.2e}")
     assert all(i.converged for i in info)
     assert res.max() <= wl2.tol * 1.01
     sel = list(C2_WAVES)
