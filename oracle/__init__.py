@@ -25,6 +25,8 @@ sparse    the sparse system H u = f (eq. Huf), slices, moving-PML subproblems
 gmres     right-preconditioned restarted (flexible) GMRES
 adjoint   gradient of a receiver misfit with respect to m
 solver    end-to-end driver tying the above together
+direct    the sparsifying stencils as a direct Helmholtz scheme, QSFEM, and
+          the phase error against the Green's function (Sec. 4)
 """
 from .green import green, central_weight, green_table, wrapped_table
 from .lsop import DenseOperator, brute_force_K, brute_force_K_at, dense_A
