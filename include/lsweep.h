@@ -213,6 +213,29 @@ ls_status ls_apply_Q(ls_handle* h, const void* r_dev, int nrhs, void* f_dev, int
  * u, y: [nrhs][L][L]. */
 ls_status ls_apply_H(ls_handle* h, const void* u_dev, int nrhs, void* y_dev, int precision);
 
+/* ---- The sparsifying stencils as a direct Helmholtz scheme (Sec. 4) ----
+ * On a handle set up with m = 0, H is the scheme's matrix: at every point i
+ * of I^h the row alpha^* u_{mu_i}, the PML rows gamma_i^* u_{mu_i}; the
+ * equation alpha^* u_{mu_i} = beta^* f_{mu_i} discretises
+ * (-Laplacian - omega^2) u = f, and with f = delta_c / h^2 (a point source at
+ * grid point c) its solution approximates the free-space Green's function
+ * about c. (With m != 0 the same calls solve H u = b for that medium.) */
+
+/* b = beta^* f_{mu_i} on I^h = [0, n+1]^2, 0 on the PML (2D handles).
+ * f: [nrhs][n][n] interior, b: [nrhs][L][L] extended. */
+ls_status ls_apply_B(ls_handle* h, const void* f_dev, int nrhs, void* b_dev, int precision);
+
+/* Solve H u = b on the extended grid for a batch (2D handles): right-
+ * preconditioned flexible GMRES in float64, the sweep of Algorithm 2 (its
+ * steps 3-8, in the handle's precision, fronts and schedule) as the
+ * preconditioner, each right-hand side stopped at ||b - H u|| <= tol ||b||.
+ *   rhs_dev, u_dev  complex128 [nrhs][L][L] (u = 0 on the Dirichlet ring)
+ *   info_host       nrhs entries (may be NULL)
+ * LS_E_NOCONV as for ls_solve (u and info still written). The call sizes the
+ * handle's Krylov workspaces for extended-grid vectors; a following ls_solve
+ * keeps the larger buffers. ls_adjoint after it returns LS_E_STATE. */
+ls_status ls_solve_H(ls_handle* h, const void* rhs_dev, int nrhs, double tol, void* u_dev, ls_rhs_info* info_host);
+
 /* z = P r, Algorithm 2: f = Q r, forward and backward sweep, restrict to I.
  * r, z: [nrhs][n][n]. precision must equal the handle's. */
 ls_status ls_apply_precond(ls_handle* h, const void* r_dev, int nrhs, void* z_dev, int precision);

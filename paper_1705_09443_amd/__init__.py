@@ -180,6 +180,22 @@ class LSSolver:
     def apply_H(self, u, precision=None):
         return self._unary(self._lib.ls_apply_H, "ls_apply_H", u, lambda k: (k,) + self.ext_shape, precision)
 
+    def apply_B(self, f, precision=None):
+        """beta^* f_mu on I^h (the direct scheme's right-hand side, Sec. 4)."""
+        return self._unary(self._lib.ls_apply_B, "ls_apply_B", f, lambda k: (k,) + self.ext_shape, precision)
+
+    def solve_H(self, rhs: torch.Tensor, tol: float = 1e-10, allow_noconv: bool = False):
+        """u with H u = rhs on the extended grid [k][L][L] (complex128): the
+        sparse system itself, preconditioned by the sweep (ls_solve_H)."""
+        k = rhs.shape[0]
+        rhs = _need(rhs, torch.complex128, (k,) + self.ext_shape, "rhs")
+        u = torch.empty_like(rhs)
+        infos = (LsRhsInfo * k)()
+        st = self._lib.ls_solve_H(self._h, rhs.data_ptr(), k, float(tol), u.data_ptr(), infos)
+        if not (allow_noconv and st == _lib.LS_E_NOCONV):
+            _lib.check(st, "ls_solve_H")
+        return u, [RhsInfo(i.iterations, i.rel_residual, bool(i.converged)) for i in infos]
+
     def apply_precond(self, r, precision=None):
         return self._unary(self._lib.ls_apply_precond, "ls_apply_precond", r, lambda k: (k,) + self.grid_shape,
                            precision)

@@ -78,6 +78,8 @@ _SIGNATURES = {
     "ls_last_error": (ctypes.c_char_p, []),
     "ls_apply_A": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),
     "ls_apply_A_noalloc": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),
+    "ls_apply_B": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),
+    "ls_solve_H": (c_int, [c_void_p, c_void_p, c_int, c_double, c_void_p, ctypes.POINTER(LsRhsInfo)]),
     "ls_apply_K": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),
     "ls_apply_Q": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),
     "ls_apply_H": (c_int, [c_void_p, c_void_p, c_int, c_void_p, c_int]),

@@ -192,6 +192,10 @@ struct ls_handle {
   DBuf pairs, groups, partials, coefs, outs, terms64, terms32, ptrs_a, ptrs_b;
   // descriptor stages of the Arnoldi step: before and after its readback
   Stage stage_main, stage_post;
+  // the Krylov loop's operator: false, the Lippmann-Schwinger operator A on
+  // the interior grid with P = extract(sweep(Q .)); true, the sparse system H
+  // on the extended grid with the sweep alone (ls_solve_H)
+  bool hmode = false;
   // adjoint state
   int last_nrhs = 0;
   DBuf psi;
@@ -671,6 +675,9 @@ ls_status apply_P3(ls_handle* h, const C<T>* r, int nb, C<T>* z) {
 // grid r64[q] (a device pointer array), narrowed by the Q stencil (r unused);
 // zp (same condition): right-hand side q of z written to the grid zp[q]
 template <typename T>
+ls_status sweep_core(ls_handle* h, int nb, C<T>* f, C<T>* u);
+
+template <typename T>
 ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* const* r64 = nullptr,
                   C<T>* const* zp = nullptr) {
   if (h->dim == 3) return apply_P3<T>(h, r, nb, z);
@@ -684,6 +691,35 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* c
     Timed tm(h, kKQ, nb);
     LSW_HIP_TRY(launch_apply_Q<T>(S, r, nb, f, il, h->st, r64));
   }
+  const ls_status e = sweep_core<T>(h, nb, f, u);
+  if (e != LS_OK) return e;
+  {
+    Timed tm(h, kKExtract, nb);
+    LSW_HIP_TRY(launch_extract<T>(h->n, h->b, u, nb, z, il, h->st, zp));
+  }
+  return LS_OK;
+}
+
+// z = the sweep applied to v (Algorithm 2, steps 3-8), both on the extended
+// grid [nb][L][L]: the preconditioner of the sparse system H itself (the
+// direct Helmholtz scheme's solve); the interface schedule works on the
+// interleaved copies in the handle's buffers.
+template <typename T>
+ls_status apply_sweep_ext(ls_handle* h, const C<T>* v, int nb, C<T>* z) {
+  if (h->opt.sweep_schedule == LS_SWEEP_SEQUENTIAL) return sweep_core<T>(h, nb, const_cast<C<T>*>(v), z);
+  C<T>* f = h->fext.as<C<T>>();
+  C<T>* u = h->uext.as<C<T>>();
+  LSW_HIP_TRY(launch_interleave<T>(v, nb, h->E, f, true, h->st));
+  const ls_status e = sweep_core<T>(h, nb, f, u);
+  if (e != LS_OK) return e;
+  LSW_HIP_TRY(launch_interleave<T>(u, nb, h->E, z, false, h->st));
+  return LS_OK;
+}
+
+// The sweep on the handle's layout: f -> u, [nb][L][L] for the sequential
+// schedule, interleaved [L][L][nb] for the interface schedule.
+template <typename T>
+ls_status sweep_core(ls_handle* h, int nb, C<T>* f, C<T>* u) {
   if (h->opt.sweep_schedule == LS_SWEEP_SEQUENTIAL) {
     Timed tm(h, kKSweep, nb);
     LSW_HIP_TRY(launch_sweep<T>(h->slices(), h->L, h->b, h->FS.as<C<T>>(), h->FG.as<C<T>>(), h->Hm.as<C<T>>(),
@@ -896,10 +932,6 @@ ls_status apply_P(ls_handle* h, const C<T>* r, int nb, C<T>* z, const double2* c
       ls_status e = phaseC(0, nl, h->st);
       if (e != LS_OK) return e;
     }
-  }
-  {
-    Timed tm(h, kKExtract, nb);
-    LSW_HIP_TRY(launch_extract<T>(h->n, h->b, u, nb, z, il, h->st, zp));
   }
   return LS_OK;
 }
@@ -1237,14 +1269,18 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     // z = P v_j (precision T), kept in Z. In 2D with the interface schedule
     // the Q stencil reads v_j in float64 itself and the extraction writes z
     // into its slot of Z, which the operator then reads
-    const bool q64 = h->dim == 2 && h->opt.sweep_schedule != LS_SWEEP_SEQUENTIAL;
+    const bool q64 = h->dim == 2 && !h->hmode && h->opt.sweep_schedule != LS_SWEEP_SEQUENTIAL;
     if (!q64) LSW_HIP_TRY((launch_copy_cast<T, double>(cin_d, cin_s, na, N, st)));
-    ls_status e = apply_P<T>(h, vin, na, zout, q64 ? cin_s : nullptr, q64 ? cz_d : nullptr);
+    ls_status e = h->hmode ? apply_sweep_ext<T>(h, vin, na, zout)
+                           : apply_P<T>(h, vin, na, zout, q64 ? cin_s : nullptr, q64 ? cz_d : nullptr);
     if (e != LS_OK) return e;
     if (!q64) LSW_HIP_TRY((launch_copy_cast<T, T>(cz_d, cz_s, na, N, st)));
     // w = A z (precision T) -> float64 work vector W[r]; in 2D the
     // convolution's epilogue writes W[r] itself
-    if (h->dim == 2) {
+    if (h->hmode) {
+      LSW_HIP_TRY(launch_apply_H<T>(h->stencils(), zout, na, aout, st));
+      LSW_HIP_TRY((launch_copy_cast<double, T>(cw_d, cw_s, na, N, st)));
+    } else if (h->dim == 2) {
       if ((e = apply_A<T>(h, zout, na, aout, cw_d, q64 ? cz_d : nullptr)) != LS_OK) return e;
     } else {
       if ((e = apply_A<T>(h, zout, na, aout)) != LS_OK) return e;
@@ -1364,13 +1400,16 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       pb.push_back(Xb + (size_t)ending[p] * N);
     }
     if (upload(h, h->ptrs_a, pa) != LS_OK || upload(h, h->ptrs_b, pb) != LS_OK) return LS_E_DEVICE;
-    if (h->dim == 2) {
+    if (h->dim == 2 && !h->hmode) {
       // the operator reads each x from its slot of X
       if ((e = apply_A<double>(h, T1, ne, T2, nullptr, h->ptrs_b.as<const double2*>())) != LS_OK) return e;
     } else {
       LSW_HIP_TRY(
           (launch_copy_cast<double, double>(h->ptrs_a.as<double2*>(), h->ptrs_b.as<const double2*>(), ne, N, st)));
-      if ((e = apply_A<double>(h, T1, ne, T2)) != LS_OK) return e;
+      if (h->hmode)
+        LSW_HIP_TRY(launch_apply_H<double>(h->stencils(), T1, ne, T2, st));
+      else if ((e = apply_A<double>(h, T1, ne, T2)) != LS_OK)
+        return e;
     }
     ho.clear();
     ht64.clear();
@@ -2291,6 +2330,67 @@ ls_status ls_apply_Q(ls_handle* h, const void* r, int nrhs, void* f, int precisi
                                       h->st));
   LSW_HIP_TRY(hipStreamSynchronize(h->st));
   return LS_OK;
+}
+
+ls_status ls_apply_B(ls_handle* h, const void* f, int nrhs, void* b, int precision) {
+  if (check_handle(h) != LS_OK || check_precision(h, precision, false) != LS_OK) return LS_E_INVALID;
+  if (h->dim != 2 || nrhs < 1 || !f || !b) {
+    set_error("ls_apply_B: bad argument (2D handle, nrhs >= 1, non-null arrays)");
+    return LS_E_INVALID;
+  }
+  // the Q stencil's kernel with beta in place of alpha
+  StencilTables S = h->stencils();
+  S.alpha = S.beta;
+  if (precision == LS_FP64)
+    LSW_HIP_TRY(launch_apply_Q<double>(S, static_cast<const double2*>(f), nrhs, static_cast<double2*>(b), false, h->st));
+  else
+    LSW_HIP_TRY(launch_apply_Q<float>(S, static_cast<const float2*>(f), nrhs, static_cast<float2*>(b), false, h->st));
+  LSW_HIP_TRY(hipStreamSynchronize(h->st));
+  return LS_OK;
+}
+
+ls_status ls_solve_H(ls_handle* h, const void* rhs_dev, int nrhs, double tol, void* u_dev, ls_rhs_info* info_host) {
+  try {
+    if (check_handle(h) != LS_OK) return LS_E_INVALID;
+    if (h->dim != 2 || nrhs < 1 || !rhs_dev || !u_dev || !(tol > 0.0) || !std::isfinite(tol)) {
+      set_error("ls_solve_H: bad argument (2D handle, nrhs >= 1, non-null arrays, tol > 0)");
+      return LS_E_INVALID;
+    }
+    // the Krylov loop on extended-grid vectors: its workspaces are sized for
+    // E values per right-hand side for this call; afterwards the handle is
+    // back on the interior grid (the larger buffers are kept)
+    struct Restore {
+      ls_handle* h;
+      size_t N;
+      ~Restore() {
+        h->N = N;
+        h->hmode = false;
+        h->cap = 0;
+      }
+    } restore{h, h->N};
+    h->last_nrhs = 0;
+    h->N = h->E;
+    h->cap = 0;
+    ls_status e = ensure_workspace(h, nrhs);
+    if (e != LS_OK) return e;
+    const size_t E = h->E;
+    LSW_HIP_TRY(hipMemcpyAsync(h->G.p, rhs_dev, (size_t)nrhs * E * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
+    h->hmode = true;
+    std::vector<ls_rhs_info> info;
+    const ls_status gs = run_gmres(h, nrhs, tol, info);
+    if (gs != LS_OK && gs != LS_E_NOCONV) return gs;
+    LSW_HIP_TRY(hipMemcpyAsync(u_dev, h->X.p, (size_t)nrhs * E * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
+    LSW_HIP_TRY(hipStreamSynchronize(h->st));
+    if (info_host)
+      for (int r = 0; r < nrhs; ++r) info_host[r] = info[r];
+    return gs;
+  } catch (const std::bad_alloc&) {
+    set_error("host allocation failed");
+    return LS_E_NOMEM;
+  } catch (const std::exception& ex) {
+    set_error(ex.what());
+    return LS_E_INVALID;
+  }
 }
 
 ls_status ls_apply_H(ls_handle* h, const void* u, int nrhs, void* y, int precision) {

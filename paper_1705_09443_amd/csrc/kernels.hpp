@@ -94,6 +94,10 @@ template <typename T>
 // right-hand side q is written to zp[q] instead of z.
 hipError_t launch_extract(int n, int b, const C<T>* uext, int nrhs, C<T>* z, bool interleaved, hipStream_t st,
                           C<T>* const* zp = nullptr);
+// Between the [nb][E] layout of extended-grid batches and the interleaved
+// [E][nb] one (to_il: the former into the latter; else back).
+template <typename T>
+hipError_t launch_interleave(const C<T>* in, int nb, size_t E, C<T>* out, bool to_il, hipStream_t st);
 // Assemble and factor every slice subproblem (one workgroup per slice);
 // writes FS, FG, the coupling rows Hm, Hp ([nslices][L][3]) and status
 // (nonzero: a zero pivot was met).

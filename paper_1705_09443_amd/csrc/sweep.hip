@@ -382,6 +382,38 @@ __global__ __launch_bounds__(256) void k_factor(StencilTables S, SliceTables P, 
   }
 }
 
+// One 64-point x 16-column tile per workgroup through LDS, so that both the
+// point-fastest and the column-fastest sides move in contiguous runs.
+template <typename T>
+__global__ __launch_bounds__(256) void k_interleave(const C<T>* __restrict__ in, int nb, size_t E,
+                                                    C<T>* __restrict__ out, int to_il) {
+  __shared__ C<T> tile[64][17];
+  const size_t p0 = (size_t)blockIdx.x * 64;
+  const int q0 = blockIdx.y * 16;
+  const int t = threadIdx.x;
+  for (int s = 0; s < 4; ++s) {
+    const int idx = t + 256 * s;
+    if (to_il) {  // read [q][p]: 64 consecutive points of a column
+      const int pp = idx & 63, qq = idx >> 6;
+      if (p0 + pp < E && q0 + qq < nb) tile[pp][qq] = in[(size_t)(q0 + qq) * E + p0 + pp];
+    } else {      // read [p][q]: 16 consecutive columns of a point
+      const int qq = idx & 15, pp = idx >> 4;
+      if (p0 + pp < E && q0 + qq < nb) tile[pp][qq] = in[(p0 + pp) * nb + q0 + qq];
+    }
+  }
+  __syncthreads();
+  for (int s = 0; s < 4; ++s) {
+    const int idx = t + 256 * s;
+    if (to_il) {
+      const int qq = idx & 15, pp = idx >> 4;
+      if (p0 + pp < E && q0 + qq < nb) out[(p0 + pp) * nb + q0 + qq] = tile[pp][qq];
+    } else {
+      const int pp = idx & 63, qq = idx >> 6;
+      if (p0 + pp < E && q0 + qq < nb) out[(size_t)(q0 + qq) * E + p0 + pp] = tile[pp][qq];
+    }
+  }
+}
+
 // ---- slice solves and the sweep (one workgroup per right-hand side) -------
 enum SolveKind { kFwd = 0, kBwd = 1, kTest = 2 };
 
@@ -545,6 +577,15 @@ hipError_t launch_extract(int n, int b, const C<T>* uext, int nrhs, C<T>* z, boo
   hipLaunchKernelGGL(k_extract<T>, dim3(blocks_for(tot, 256)), dim3(256), 0, st, n, b, uext, nrhs, z);
   return hipGetLastError();
 }
+
+template <typename T>
+hipError_t launch_interleave(const C<T>* in, int nb, size_t E, C<T>* out, bool to_il, hipStream_t st) {
+  const dim3 grid((unsigned)((E + 63) / 64), (unsigned)((nb + 15) / 16));
+  hipLaunchKernelGGL(k_interleave<T>, grid, dim3(256), 0, st, in, nb, E, out, to_il ? 1 : 0);
+  return hipGetLastError();
+}
+template hipError_t launch_interleave<double>(const double2*, int, size_t, double2*, bool, hipStream_t);
+template hipError_t launch_interleave<float>(const float2*, int, size_t, float2*, bool, hipStream_t);
 
 template <typename T>
 hipError_t launch_factor_slices(const StencilTables& S, const SliceTables& P, C<T>* FS, C<T>* FG,
