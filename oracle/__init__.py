@@ -33,7 +33,7 @@ from .lsop import DenseOperator, brute_force_K, brute_force_K_at, dense_A
 from .stencils import (neighbourhood, plane_wave_directions, normalise_phase,
                        alpha_beta, sigma_global, pml_stencil, FrequencySamples)
 from .sparse import SparseSystem, Sweep
-from .gmres import fgmres, GmresResult
+from .gmres import fgmres, GmresResult, block_fgmres, BlockGmresResult
 from .adjoint import misfit_gradient
 from .solver import OracleSolver, DEFAULT_PML_C
 
@@ -42,6 +42,6 @@ __all__ = [
     "DenseOperator", "brute_force_K", "dense_A",
     "neighbourhood", "plane_wave_directions", "normalise_phase", "alpha_beta",
     "sigma_global", "pml_stencil", "FrequencySamples",
-    "SparseSystem", "Sweep", "fgmres", "GmresResult", "misfit_gradient",
+    "SparseSystem", "Sweep", "fgmres", "GmresResult", "block_fgmres", "BlockGmresResult", "misfit_gradient",
     "OracleSolver", "DEFAULT_PML_C", "brute_force_K_at",
 ]

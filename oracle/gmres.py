@@ -102,3 +102,70 @@ def fgmres(apply_A: Callable, apply_P: Callable, g: np.ndarray, tol: float,
             return GmresResult(x.reshape(shape), iters, True, rel, estimates)
         if iters >= max_iters:
             return GmresResult(x.reshape(shape), iters, False, rel, estimates)
+
+
+@dataclasses.dataclass
+class BlockGmresResult:
+    x: np.ndarray                       # [B][shape]
+    iterations: int                     # block Arnoldi steps over all cycles
+    converged: bool
+    rel_residuals: np.ndarray           # true ||g_c - A x_c|| / ||g_c|| per column
+    estimates: list                     # largest column residual estimate after every step
+
+
+def block_fgmres(apply_A: Callable, apply_P: Callable, G: np.ndarray, tol: float, restart: int = 10,
+                 max_iters: int = 200) -> BlockGmresResult:
+    """Block flexible GMRES with right preconditioning: one shared block
+    Krylov space for all B right-hand sides (a batch of the problem of Sec.
+    2.5; reading G20). Cycle: R = G - A X, R = V_0 S (QR), then per step the
+    block Arnoldi step Z_j = P V_j (each column), W = A Z_j, two passes of
+    block Gram-Schmidt against V_0..V_j (H_ij = V_i^H W), W = V_{j+1} H_{j+1,j}
+    (QR); Y minimises ||E S - Hbar Y||_F column by column (E the first block
+    of the identity) and X = X + [Z_0 .. Z_j] Y at the cycle's end. The cycle
+    ends when every column's residual estimate meets tol ||g_c|| (or after
+    ``restart`` steps); the true residuals decide whether to stop or restart."""
+    B = G.shape[0]
+    shape = G.shape[1:]
+    Gm = G.reshape(B, -1).T.astype(np.complex128)            # N x B
+    gn = np.linalg.norm(Gm, axis=0)
+    X = np.zeros_like(Gm)
+    if not np.any(gn):
+        return BlockGmresResult(X.T.reshape(G.shape), 0, True, np.zeros(B), [])
+    gn = np.where(gn == 0.0, 1.0, gn)
+    cols = lambda f, M: np.stack([f(M[:, c].reshape(shape)).reshape(-1) for c in range(M.shape[1])], axis=1)
+    its = 0
+    estimates = []
+    R = Gm.copy()
+    while True:
+        V0, S = np.linalg.qr(R)
+        V, Z = [V0], []
+        Hbar = np.zeros(((restart + 1) * B, restart * B), dtype=np.complex128)
+        E = np.zeros(((restart + 1) * B, B), dtype=np.complex128)
+        E[:B] = S
+        Y = None
+        for j in range(restart):
+            Zj = cols(apply_P, V[j])
+            Z.append(Zj)
+            W = cols(apply_A, Zj)
+            for _ in range(2):                                   # block Gram-Schmidt, twice
+                for i in range(j + 1):
+                    Hij = V[i].conj().T @ W
+                    Hbar[i * B:(i + 1) * B, j * B:(j + 1) * B] += Hij
+                    W = W - V[i] @ Hij
+            Vn, Rn = np.linalg.qr(W)
+            Hbar[(j + 1) * B:(j + 2) * B, j * B:(j + 1) * B] = Rn
+            V.append(Vn)
+            its += 1
+            k = (j + 1) * B
+            Y = np.linalg.lstsq(Hbar[:k + B, :k], E[:k + B], rcond=None)[0]
+            est = np.linalg.norm(E[:k + B] - Hbar[:k + B, :k] @ Y, axis=0) / gn
+            estimates.append(float(est.max()))
+            if est.max() <= tol or its >= max_iters:
+                break
+        X = X + np.concatenate(Z, axis=1) @ Y
+        R = Gm - cols(apply_A, X)
+        rel = np.linalg.norm(R, axis=0) / gn
+        if rel.max() <= tol:
+            return BlockGmresResult(X.T.reshape(G.shape), its, True, rel, estimates)
+        if its >= max_iters:
+            return BlockGmresResult(X.T.reshape(G.shape), its, False, rel, estimates)

@@ -12,7 +12,7 @@ import numpy as np
 from .lsop import DenseOperator
 from .stencils import alpha_beta
 from .sparse import SparseSystem, Sweep
-from .gmres import fgmres, GmresResult
+from .gmres import fgmres, GmresResult, block_fgmres
 from .adjoint import misfit_gradient
 
 #: PML strength C (reading G2: the paper only says C = Theta(1)).
@@ -40,6 +40,10 @@ class OracleSolver:
 
     def solve_rhs(self, g: np.ndarray, tol: float = 1e-6, max_iters: int = 1000) -> GmresResult:
         return fgmres(self.op.apply_A, self.precondition, g, tol, self.restart, max_iters)
+
+    def solve_block(self, G: np.ndarray, tol: float = 1e-6, restart: int = 10, max_iters: int = 200):
+        """All right-hand sides G [B][n]^d in one shared block Krylov space."""
+        return block_fgmres(self.op.apply_A, self.precondition, G, tol, restart, max_iters)
 
     def solve_incident(self, u_inc: np.ndarray, tol: float = 1e-6, max_iters: int = 1000):
         """Scattered fields for a batch of incident waves [k][n]^d."""
