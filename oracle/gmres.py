@@ -111,37 +111,44 @@ class BlockGmresResult:
     converged: bool
     rel_residuals: np.ndarray           # true ||g_c - A x_c|| / ||g_c|| per column
     estimates: list                     # largest column residual estimate after every step
+    col_iterations: np.ndarray          # block steps taken while column c was in the block
 
 
 def block_fgmres(apply_A: Callable, apply_P: Callable, G: np.ndarray, tol: float, restart: int = 10,
                  max_iters: int = 200) -> BlockGmresResult:
     """Block flexible GMRES with right preconditioning: one shared block
-    Krylov space for all B right-hand sides (a batch of the problem of Sec.
-    2.5; reading G20). Cycle: R = G - A X, R = V_0 S (QR), then per step the
-    block Arnoldi step Z_j = P V_j (each column), W = A Z_j, two passes of
-    block Gram-Schmidt against V_0..V_j (H_ij = V_i^H W), W = V_{j+1} H_{j+1,j}
-    (QR); Y minimises ||E S - Hbar Y||_F column by column (E the first block
-    of the identity) and X = X + [Z_0 .. Z_j] Y at the cycle's end. The cycle
-    ends when every column's residual estimate meets tol ||g_c|| (or after
-    ``restart`` steps); the true residuals decide whether to stop or restart."""
+    Krylov space for a batch of right-hand sides (a batch of the problem of
+    Sec. 2.5; reading G20). The block holds the columns not yet converged
+    (zero right-hand sides never enter it: x = 0). Cycle: R = G - A X over the
+    block's columns, R = V_0 S (QR), then per step the block Arnoldi step
+    Z_j = P V_j (each column), W = A Z_j, two passes of block Gram-Schmidt
+    against V_0..V_j (H_ij = V_i^H W), W = V_{j+1} H_{j+1,j} (QR); Y minimises
+    ||E S - Hbar Y||_F column by column (E the first block of the identity)
+    and X = X + [Z_0 .. Z_j] Y at the cycle's end. The cycle ends when every
+    column's residual estimate meets tol ||g_c|| (or after ``restart`` steps);
+    the true residuals then decide which columns stay in the block for the
+    next cycle."""
     B = G.shape[0]
     shape = G.shape[1:]
     Gm = G.reshape(B, -1).T.astype(np.complex128)            # N x B
     gn = np.linalg.norm(Gm, axis=0)
     X = np.zeros_like(Gm)
-    if not np.any(gn):
-        return BlockGmresResult(X.T.reshape(G.shape), 0, True, np.zeros(B), [])
-    gn = np.where(gn == 0.0, 1.0, gn)
+    rel = np.zeros(B)
+    col_its = np.zeros(B, dtype=int)
+    act = np.nonzero(gn > 0.0)[0]
+    if act.size == 0:
+        return BlockGmresResult(X.T.reshape(G.shape), 0, True, rel, [], col_its)
     cols = lambda f, M: np.stack([f(M[:, c].reshape(shape)).reshape(-1) for c in range(M.shape[1])], axis=1)
     its = 0
     estimates = []
-    R = Gm.copy()
+    R = Gm[:, act].copy()
     while True:
+        b = act.size
         V0, S = np.linalg.qr(R)
         V, Z = [V0], []
-        Hbar = np.zeros(((restart + 1) * B, restart * B), dtype=np.complex128)
-        E = np.zeros(((restart + 1) * B, B), dtype=np.complex128)
-        E[:B] = S
+        Hbar = np.zeros(((restart + 1) * b, restart * b), dtype=np.complex128)
+        E = np.zeros(((restart + 1) * b, b), dtype=np.complex128)
+        E[:b] = S
         Y = None
         for j in range(restart):
             Zj = cols(apply_P, V[j])
@@ -150,22 +157,25 @@ def block_fgmres(apply_A: Callable, apply_P: Callable, G: np.ndarray, tol: float
             for _ in range(2):                                   # block Gram-Schmidt, twice
                 for i in range(j + 1):
                     Hij = V[i].conj().T @ W
-                    Hbar[i * B:(i + 1) * B, j * B:(j + 1) * B] += Hij
+                    Hbar[i * b:(i + 1) * b, j * b:(j + 1) * b] += Hij
                     W = W - V[i] @ Hij
             Vn, Rn = np.linalg.qr(W)
-            Hbar[(j + 1) * B:(j + 2) * B, j * B:(j + 1) * B] = Rn
+            Hbar[(j + 1) * b:(j + 2) * b, j * b:(j + 1) * b] = Rn
             V.append(Vn)
             its += 1
-            k = (j + 1) * B
-            Y = np.linalg.lstsq(Hbar[:k + B, :k], E[:k + B], rcond=None)[0]
-            est = np.linalg.norm(E[:k + B] - Hbar[:k + B, :k] @ Y, axis=0) / gn
+            col_its[act] += 1
+            k = (j + 1) * b
+            Y = np.linalg.lstsq(Hbar[:k + b, :k], E[:k + b], rcond=None)[0]
+            est = np.linalg.norm(E[:k + b] - Hbar[:k + b, :k] @ Y, axis=0) / gn[act]
             estimates.append(float(est.max()))
             if est.max() <= tol or its >= max_iters:
                 break
-        X = X + np.concatenate(Z, axis=1) @ Y
-        R = Gm - cols(apply_A, X)
-        rel = np.linalg.norm(R, axis=0) / gn
+        X[:, act] = X[:, act] + np.concatenate(Z, axis=1) @ Y
+        Ra = Gm[:, act] - cols(apply_A, X[:, act])
+        rel[act] = np.linalg.norm(Ra, axis=0) / gn[act]
         if rel.max() <= tol:
-            return BlockGmresResult(X.T.reshape(G.shape), its, True, rel, estimates)
+            return BlockGmresResult(X.T.reshape(G.shape), its, True, rel, estimates, col_its)
         if its >= max_iters:
-            return BlockGmresResult(X.T.reshape(G.shape), its, False, rel, estimates)
+            return BlockGmresResult(X.T.reshape(G.shape), its, False, rel, estimates, col_its)
+        keep = rel[act] > tol
+        act, R = act[keep], Ra[:, keep]

@@ -5,7 +5,10 @@ a batch of right-hand sides; reading G20).
   number of steps, its iterate equals fgmres's.
 * On a small dense system it reaches the direct solution, every column's true
   residual below the tolerance, and its residual estimates never increase
-  (each step minimises over a larger space).
+  (each step minimises over a larger space). A zero column stays out of the
+  block (x = 0 after no step); columns that converge leave it at a restart.
+* Finite termination: with B columns on a system of order N = B s, s block
+  steps span the whole space, and the residual is zero up to rounding.
 * On the Lippmann-Schwinger problem with the sweeping preconditioner it needs
   no more block steps than the slowest column needs GMRES steps alone (the
   block space contains every column's own Krylov space), here fewer.
@@ -37,12 +40,30 @@ def test_single_column_is_gmres(k):
 def test_dense_system_block_solution():
     A, fA, fP, rng = dense_case(seed=1)
     G = rng.standard_normal((5, 40)) + 1j * rng.standard_normal((5, 40))
-    res = block_fgmres(fA, fP, G, 1e-12, restart=4)
+    G[2] = 0.0
+    res = block_fgmres(fA, fP, G, 1e-12, restart=2)
     assert res.converged and res.rel_residuals.max() <= 1e-12
     X = np.linalg.solve(A, G.T).T
     assert np.linalg.norm(res.x - X) <= 1e-10 * np.linalg.norm(X)
+    assert not np.any(res.x[2]) and res.col_iterations[2] == 0
     est = res.estimates
-    assert all(b <= a * (1 + 1e-12) for a, b in zip(est[:4], est[1:4]))   # within the first cycle
+    assert est[1] <= est[0] * (1 + 1e-12)                                # within the first cycle
+    # several cycles, and some column left the block before the last one
+    assert res.iterations > 2 and res.col_iterations.max() == res.iterations
+    assert res.col_iterations[[0, 1, 3, 4]].min() < res.iterations
+
+
+def test_finite_termination():
+    n, B = 40, 5
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((n, n)) + 1j * rng.standard_normal((n, n))
+    G = rng.standard_normal((B, n)) + 1j * rng.standard_normal((B, n))
+    ident = lambda x: x
+    res = block_fgmres(lambda x: A @ x, ident, G, 1e-300, restart=n // B, max_iters=n // B)
+    assert res.iterations == n // B
+    assert res.rel_residuals.max() <= 1e-9
+    early = block_fgmres(lambda x: A @ x, ident, G, 1e-300, restart=n // B, max_iters=n // B - 1)
+    assert early.rel_residuals.min() > 1e-6
 
 
 def test_block_steps_on_the_lippmann_schwinger_problem():
