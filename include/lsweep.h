@@ -88,6 +88,18 @@ typedef struct {
                           their auxiliary PML on the side of the front's earlier slices.
                           A different preconditioner (iteration counts differ). 2D with the
                           interface schedule only; LS_E_INVALID otherwise. */
+  int block_size;      /* 1 (default): GMRES per right-hand side (every column its own
+                          Krylov space). B in [2, 64]: block flexible GMRES, consecutive groups
+                          of B columns (the last may be smaller) each sharing one block Krylov
+                          space (Cholesky QR twice for the block QR, the Gram products as
+                          matrix-core GEMMs); restart then counts block
+                          steps per cycle and max_iters block steps (ls_rhs_info.iterations: the
+                          block steps taken while the column was in its block). A column leaves
+                          its block at a restart once its true residual meets tol; a zero
+                          right-hand side never enters it. Linearly dependent right-hand sides
+                          in a block fall back to the per-column loop. Needs
+                          block_size * restart <= 2048. Same u to the tolerance, different
+                          iterates and counts. */
 } ls_options;
 
 typedef enum { LS_SWEEP_INTERFACE = 0, LS_SWEEP_SEQUENTIAL = 1 } ls_sweep_schedule;

@@ -67,10 +67,13 @@ class LSSolver:
 
     def __init__(self, m: torch.Tensor, omega: float, pml_width: int = 12, layer_thickness: Optional[int] = 4,
                  precision: str = "fp64", restart: int = 30, max_iters: int = 1000, pml_C: float = 10.0,
-                 freq_samples: int = 0, schedule: str = "interface", autotune: int = 0, fronts: int = 1):
+                 freq_samples: int = 0, schedule: str = "interface", autotune: int = 0, fronts: int = 1,
+                 block_size: int = 1):
         """layer_thickness None (with autotune = k > 0): chosen by timing solves of k
         plane waves on the device; autotune = k > 0 also tunes the kernel choice per
-        batch size up to k (ls_setup, Autotuning)."""
+        batch size up to k (ls_setup, Autotuning). block_size > 1: block flexible
+        GMRES over groups of that many right-hand sides (restart and max_iters then
+        count block steps)."""
         self._lib = _lib.load()
         if m.dim() not in (2, 3) or len(set(m.shape)) != 1:
             raise ValueError("m must be [n, n] or [n, n, n]")
@@ -89,6 +92,7 @@ class LSSolver:
         opts.sweep_schedule = {"interface": 0, "sequential": 1}[schedule]
         opts.autotune = int(autotune)
         opts.fronts = int(fronts)
+        opts.block_size = int(block_size)
         opts.hip_stream = _stream_ptr()
         self._opts = opts
         grid = LsGrid(self.dim, self.n)

@@ -33,7 +33,7 @@ class LsGrid(ctypes.Structure):
 class LsOptions(ctypes.Structure):
     _fields_ = [("precision", c_int), ("restart", c_int), ("max_iters", c_int), ("pml_C", c_double),
                 ("freq_samples", c_int), ("autotune", c_int), ("hip_stream", c_void_p),
-                ("sweep_schedule", c_int), ("fronts", c_int)]
+                ("sweep_schedule", c_int), ("fronts", c_int), ("block_size", c_int)]
 
 
 class LsRhsInfo(ctypes.Structure):

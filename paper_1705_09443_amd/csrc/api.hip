@@ -14,6 +14,8 @@
 #include <type_traits>
 #include <vector>
 
+#include <rocblas/rocblas.h>
+
 #include "../../include/lsweep.h"
 #include "kernels.hpp"
 #include "setup_host.hpp"
@@ -196,6 +198,10 @@ struct ls_handle {
   // the interior grid with P = extract(sweep(Q .)); true, the sparse system H
   // on the extended grid with the sweep alone (ls_solve_H)
   bool hmode = false;
+  // block flexible GMRES (ls_options.block_size > 1): library GEMM handle
+  // on st and the small coefficient matrices of every block
+  rocblas_handle blas = nullptr;
+  DBuf bcoef, gpart;
   // adjoint state
   int last_nrhs = 0;
   DBuf psi;
@@ -223,6 +229,7 @@ struct ls_handle {
   std::vector<hipEvent_t> pool;
   ~ls_handle() {
     drop_graphs();
+    if (blas) (void)rocblas_destroy_handle(blas);
     if (cst) (void)hipStreamDestroy(cst);
     if (st3) (void)hipStreamDestroy(st3);
     if (st2) (void)hipStreamDestroy(st2);
@@ -281,9 +288,22 @@ struct ls_op3 {
 
 namespace {
 
-enum KernelKind { kKSweep = 0, kKFft, kKQ, kKExtract, kKFactor, kKSlices, kKIface, kKSlicesLast, kKNumKinds };
-const char* kKindNames[kKNumKinds] = {"sweep",        "fft_convolve", "stencil_Q", "extract", "factor",
-                                      "slice_solves", "interface",    "slice_solves_last"};
+enum KernelKind {
+  kKSweep = 0,
+  kKFft,
+  kKQ,
+  kKExtract,
+  kKFactor,
+  kKSlices,
+  kKIface,
+  kKSlicesLast,
+  kKGram,
+  kKGramUpd,
+  kKNumKinds
+};
+const char* kKindNames[kKNumKinds] = {"sweep",        "fft_convolve",      "stencil_Q",  "extract",
+                                      "factor",       "slice_solves",      "interface",  "slice_solves_last",
+                                      "block_gram",   "block_update"};
 
 hipEvent_t take_event(ls_handle* h) {
   if (!h->pool.empty()) {
@@ -408,7 +428,8 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   LSW_ALLOC(h->zout, (size_t)nrhs * N * cs);
   LSW_ALLOC(h->aout, (size_t)nrhs * N * cs);
   LSW_ALLOC(h->V, (size_t)nrhs * (rs + 1) * N * sizeof(double2));
-  LSW_ALLOC(h->Z, (size_t)nrhs * rs * N * cs);
+  // the block method keeps its directions in complex128 (X += Z Y is one GEMM)
+  LSW_ALLOC(h->Z, (size_t)nrhs * rs * N * (h->opt.block_size > 1 ? sizeof(double2) : cs));
   LSW_ALLOC(h->W, (size_t)nrhs * N * sizeof(double2));
   LSW_ALLOC(h->X, (size_t)nrhs * N * sizeof(double2));
   LSW_ALLOC(h->G, (size_t)nrhs * N * sizeof(double2));
@@ -1470,7 +1491,573 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
   return LS_OK;
 }
 
+// ---- block flexible GMRES (ls_options.block_size > 1) -------------------------
+// The batch of Sec. 2.5 with one shared block Krylov space per block of
+// right-hand sides (consecutive columns): per step Z_j = P V_j and W = A Z_j
+// for every column (the batched applies of the per-column loop), then two
+// passes of classical block Gram-Schmidt against V_0..V_j and the block QR
+// W = V_{j+1} R by Cholesky QR done twice. The Gram products are GEMMs of
+// (N x (j+1)B)^H (N x B) on the matrix cores (library zgemm); the small
+// Cholesky factorizations, the Householder QR of the block Hessenberg matrix
+// and the least-squares solves run on the host in float64. A column leaves
+// its block at a restart once its true residual meets the tolerance; a zero
+// right-hand side never enters it.
+
+#define LSW_BLAS_TRY(expr)                                                      \
+  do {                                                                          \
+    rocblas_status _b = (expr);                                                 \
+    if (_b != rocblas_status_success) {                                         \
+      set_error(std::string(#expr) + ": " + rocblas_status_to_string(_b));      \
+      return LS_E_DEVICE;                                                       \
+    }                                                                           \
+  } while (0)
+
+using cplx = std::complex<double>;
+
+// G = R^H R for a Hermitian b x b matrix (column-major), R upper triangular.
+// A pivot at or below rel * G_kk (column k lies in the span of the earlier
+// columns to that relative accuracy, or is zero) leaves row k of R zero and
+// makes the result false.
+bool cholesky_upper(const cplx* G, int b, cplx* R, double rel) {
+  bool ok = true;
+  std::fill(R, R + (size_t)b * b, cplx(0.0));
+  for (int k = 0; k < b; ++k) {
+    const double gkk = G[(size_t)k * b + k].real();
+    double d = gkk;
+    for (int i = 0; i < k; ++i) d -= std::norm(R[(size_t)k * b + i]);
+    if (!(gkk > 0.0) || !(d > rel * gkk)) {
+      ok = false;
+      continue;
+    }
+    const double rkk = std::sqrt(d);
+    R[(size_t)k * b + k] = rkk;
+    for (int c = k + 1; c < b; ++c) {
+      cplx acc = G[(size_t)c * b + k];
+      for (int i = 0; i < k; ++i) acc -= std::conj(R[(size_t)k * b + i]) * R[(size_t)c * b + i];
+      R[(size_t)c * b + k] = acc / rkk;
+    }
+  }
+  return ok;
+}
+
+// Ri = R^{-1} for a nonsingular upper triangular b x b R (column-major).
+void upper_inverse(const cplx* R, int b, cplx* Ri) {
+  std::fill(Ri, Ri + (size_t)b * b, cplx(0.0));
+  for (int c = 0; c < b; ++c) {
+    Ri[(size_t)c * b + c] = 1.0 / R[(size_t)c * b + c];
+    for (int i = c - 1; i >= 0; --i) {
+      cplx acc = 0.0;
+      for (int k = i + 1; k <= c; ++k) acc += R[(size_t)k * b + i] * Ri[(size_t)c * b + k];
+      Ri[(size_t)c * b + i] = -acc / R[(size_t)i * b + i];
+    }
+  }
+}
+
+// Host state of one block of right-hand sides.
+struct BlockState {
+  int first = 0;           // first global column of the block
+  std::vector<int> cols;   // global columns in the block this cycle
+  int j = 0;               // block steps in the cycle
+  int iters = 0;           // block steps over all cycles
+  bool in_cycle = false;
+  bool end = false;        // the cycle ends after this step
+  int p0 = 0;              // first position of the block's columns in the step's batch
+  // Householder QR of the block Hessenberg matrix ((rs+1)b x rs b,
+  // column-major, reflectors below the diagonal) and Q^H E ((rs+1)b x b)
+  std::vector<cplx> Hb, E, tau;
+  // host copies of the small matrices; the uploaded ones stay untouched
+  // until the next synchronisation
+  std::vector<cplx> C1, C2, G, R, R1, R2, R1i, R2i, Y;
+  bool qr_ok = true;
+  int b() const { return (int)cols.size(); }
+};
+
+template <typename T>
+ls_status block_gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& info) {
+  const size_t N = h->N;
+  const int rs = h->opt.restart;
+  const int Bsz = std::min(h->opt.block_size, nrhs);
+  const int nblk = (nrhs + Bsz - 1) / Bsz;
+  const int max_iters = h->opt.max_iters;
+  hipStream_t st = h->st;
+  if (!h->blas) {
+    LSW_BLAS_TRY(rocblas_create_handle(&h->blas));
+    LSW_BLAS_TRY(rocblas_set_atomics_mode(h->blas, rocblas_atomics_not_allowed));
+    LSW_BLAS_TRY(rocblas_set_pointer_mode(h->blas, rocblas_pointer_mode_host));
+  }
+  LSW_BLAS_TRY(rocblas_set_stream(h->blas, st));
+  rocblas_handle bl = h->blas;
+  const size_t rsz = (size_t)(2 * rs + 3) * Bsz * Bsz;  // complex entries per block
+  LSW_ALLOC(h->bcoef, (size_t)nblk * rsz * sizeof(double2));
+  // Gram products C = A^H B with A (N x m), B (N x nc): split over N into
+  // nch chunks of Lc rows (one strided-batched GEMM; the last N - nch Lc rows
+  // in one more), then the chunk results summed in a fixed order
+  const int nch = (int)std::max<size_t>(1, std::min<size_t>(256, N / 8192));
+  const int Lc = (int)(N / nch), tail = (int)(N - (size_t)nch * Lc);
+  LSW_ALLOC(h->gpart, (size_t)(nch + 1) * rs * Bsz * Bsz * sizeof(double2));
+  double2* Vb = h->V.as<double2>();
+  double2* Zb = h->Z.as<double2>();
+  double2* Wb = h->W.as<double2>();
+  double2* Xb = h->X.as<double2>();
+  double2* Gb = h->G.as<double2>();
+  double2* Rb = h->R.as<double2>();
+  double2* T1 = h->T1.as<double2>();
+  double2* T2 = h->T2.as<double2>();
+  double2* bc = h->bcoef.as<double2>();
+  auto Vp = [&](const BlockState& B, int k) { return Vb + (size_t)B.first * (rs + 1) * N + (size_t)k * B.b() * N; };
+  auto Zp = [&](const BlockState& B, int k) { return Zb + (size_t)B.first * rs * N + (size_t)k * B.b() * N; };
+  auto region = [&](int blk) { return bc + (size_t)blk * rsz; };
+  auto C1d = [&](int blk) { return region(blk); };
+  auto C2d = [&](int blk) { return region(blk) + (size_t)rs * Bsz * Bsz; };
+  auto Gd = [&](int blk) { return region(blk) + (size_t)2 * rs * Bsz * Bsz; };
+  auto R1id = [&](int blk) { return Gd(blk) + (size_t)Bsz * Bsz; };
+  auto R2id = [&](int blk) { return Gd(blk) + (size_t)2 * Bsz * Bsz; };
+  const cplx one(1.0, 0.0), zero(0.0, 0.0), mone(-1.0, 0.0);
+  auto zc = [](const double2* p) { return reinterpret_cast<const rocblas_double_complex*>(p); };
+  auto zm = [](double2* p) { return reinterpret_cast<rocblas_double_complex*>(p); };
+  auto zs = [](const cplx& c) { return reinterpret_cast<const rocblas_double_complex*>(&c); };
+  const rocblas_operation OC = rocblas_operation_conjugate_transpose, ON = rocblas_operation_none;
+  const int iN = (int)N;
+  double2* gp = h->gpart.as<double2>();
+  auto gram = [&](int m, int nc, const double2* A, const double2* Bm, double2* Cout) -> ls_status {
+    const rocblas_stride sc = (rocblas_stride)m * nc;
+    LSW_BLAS_TRY(rocblas_zgemm_strided_batched(bl, OC, ON, m, nc, Lc, zs(one), zc(A), iN, (rocblas_stride)Lc,
+                                               zc(Bm), iN, (rocblas_stride)Lc, zs(zero), zm(gp), m, sc, nch));
+    if (tail > 0)
+      LSW_BLAS_TRY(rocblas_zgemm(bl, OC, ON, m, nc, tail, zs(one), zc(A + (size_t)nch * Lc), iN,
+                                 zc(Bm + (size_t)nch * Lc), iN, zs(zero), zm(gp + (size_t)nch * sc), m));
+    LSW_HIP_TRY(launch_sum_parts(gp, nch + (tail > 0 ? 1 : 0), (size_t)sc, Cout, st));
+    return LS_OK;
+  };
+
+  // column norms of ncols contiguous columns (fixed-order reductions)
+  std::vector<double> parts;
+  auto colnorms = [&](const double2* x, int ncols, std::vector<double>& out) -> ls_status {
+    double* pd = h->partials.as<double>();
+    LSW_HIP_TRY(launch_colnorm2(x, ncols, N, pd, st));
+    parts.resize((size_t)ncols * kDotBlocks);
+    LSW_HIP_TRY(hipMemcpyAsync(parts.data(), pd, parts.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    LSW_HIP_TRY(hipStreamSynchronize(st));
+    out.assign(ncols, 0.0);
+    for (int c = 0; c < ncols; ++c) {
+      double acc = 0.0;
+      for (int k = 0; k < kDotBlocks; ++k) acc += parts[(size_t)c * kDotBlocks + k];
+      out[c] = std::sqrt(std::max(acc, 0.0));
+    }
+    return LS_OK;
+  };
+  // dst_i = src_i for pointer pairs (float64 copies through the pointer tables)
+  std::vector<void*> pa, pb;
+  auto gather = [&](const std::vector<double2*>& dst, const std::vector<const double2*>& src) -> ls_status {
+    if (dst.empty()) return LS_OK;
+    pa.assign(dst.begin(), dst.end());
+    pb.clear();
+    for (auto p : src) pb.push_back(const_cast<double2*>(p));
+    if (upload(h, h->ptrs_a, pa) != LS_OK || upload(h, h->ptrs_b, pb) != LS_OK) return LS_E_DEVICE;
+    LSW_HIP_TRY((launch_copy_cast<double, double>(h->ptrs_a.as<double2*>(), h->ptrs_b.as<const double2*>(),
+                                                  (int)dst.size(), N, st)));
+    return LS_OK;
+  };
+
+  // Cholesky QR, twice, of the b columns at in[blk] (contiguous) into
+  // out[blk], through tmp[blk]; R into B.R. B.qr_ok false: numerically rank
+  // deficient (R from the first pass, out not written).
+  std::vector<BlockState> S(nblk);
+  auto block_qr = [&](const std::vector<int>& bls, const std::vector<double2*>& in, const std::vector<double2*>& tmp,
+                      const std::vector<double2*>& out) -> ls_status {
+    Timed tm(h, kKGram, 0);
+    ls_status e = LS_OK;
+    for (size_t q = 0; q < bls.size(); ++q) {
+      BlockState& B = S[bls[q]];
+      const int b = B.b();
+      if ((e = gram(b, b, in[q], in[q], Gd(bls[q]))) != LS_OK) return e;
+      B.G.resize((size_t)b * b);
+      LSW_HIP_TRY(hipMemcpyAsync(B.G.data(), Gd(bls[q]), B.G.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+    }
+    LSW_HIP_TRY(hipStreamSynchronize(st));
+    for (size_t q = 0; q < bls.size(); ++q) {
+      BlockState& B = S[bls[q]];
+      const int b = B.b();
+      for (const cplx& g : B.G)
+        if (!std::isfinite(g.real()) || !std::isfinite(g.imag())) {
+          set_error("non-finite value in the block Arnoldi process");
+          return LS_E_NUMERIC;
+        }
+      B.R1.resize((size_t)b * b);
+      B.qr_ok = cholesky_upper(B.G.data(), b, B.R1.data(), 1e-14);
+      if (!B.qr_ok) {
+        B.R = B.R1;
+        continue;
+      }
+      B.R1i.resize((size_t)b * b);
+      upper_inverse(B.R1.data(), b, B.R1i.data());
+      LSW_HIP_TRY(hipMemcpyAsync(R1id(bls[q]), B.R1i.data(), B.R1i.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+      LSW_BLAS_TRY(rocblas_zgemm(bl, ON, ON, iN, b, b, zs(one), zc(in[q]), iN, zc(R1id(bls[q])), b, zs(zero),
+                                 zm(tmp[q]), iN));
+      if ((e = gram(b, b, tmp[q], tmp[q], Gd(bls[q]))) != LS_OK) return e;
+      LSW_HIP_TRY(hipMemcpyAsync(B.G.data(), Gd(bls[q]), B.G.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+    }
+    LSW_HIP_TRY(hipStreamSynchronize(st));
+    for (size_t q = 0; q < bls.size(); ++q) {
+      BlockState& B = S[bls[q]];
+      if (!B.qr_ok) continue;
+      const int b = B.b();
+      B.R2.resize((size_t)b * b);
+      if (!cholesky_upper(B.G.data(), b, B.R2.data(), 1e-14)) {
+        B.qr_ok = false;
+        B.R = B.R1;
+        continue;
+      }
+      B.R2i.resize((size_t)b * b);
+      upper_inverse(B.R2.data(), b, B.R2i.data());
+      LSW_HIP_TRY(hipMemcpyAsync(R2id(bls[q]), B.R2i.data(), B.R2i.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+      LSW_BLAS_TRY(rocblas_zgemm(bl, ON, ON, iN, b, b, zs(one), zc(tmp[q]), iN, zc(R2id(bls[q])), b, zs(zero),
+                                 zm(out[q]), iN));
+      // R = R2 R1
+      B.R.assign((size_t)b * b, 0.0);
+      for (int c = 0; c < b; ++c)
+        for (int i = 0; i <= c; ++i) {
+          cplx acc = 0.0;
+          for (int k = i; k <= c; ++k) acc += B.R2[(size_t)k * b + i] * B.R1[(size_t)c * b + k];
+          B.R[(size_t)c * b + i] = acc;
+        }
+    }
+    return LS_OK;
+  };
+  // a new cycle of block B: E = [S; 0] with the initial block's R = S
+  auto start_cycle = [&](BlockState& B) {
+    const int b = B.b();
+    const size_t ldh = (size_t)(rs + 1) * b;
+    B.j = 0;
+    B.in_cycle = true;
+    B.Hb.assign(ldh * rs * b, 0.0);
+    B.tau.assign((size_t)rs * b, 0.0);
+    B.E.assign(ldh * b, 0.0);
+    for (int c = 0; c < b; ++c)
+      for (int i = 0; i < b; ++i) B.E[(size_t)c * ldh + i] = B.R[(size_t)c * b + i];
+  };
+
+  std::vector<int> col_its(nrhs, 0), cdone(nrhs, 0);
+  std::vector<double> gn, relres(nrhs, 0.0);
+  LSW_HIP_TRY(hipMemsetAsync(Xb, 0, (size_t)nrhs * N * sizeof(double2), st));
+  ls_status e = colnorms(Gb, nrhs, gn);
+  if (e != LS_OK) return e;
+  for (int c = 0; c < nrhs; ++c)
+    if (!std::isfinite(gn[c])) {
+      set_error("right-hand side has a non-finite norm");
+      return LS_E_NUMERIC;
+    }
+  // initial blocks: the nonzero columns of G
+  {
+    std::vector<int> bls;
+    std::vector<double2*> dst, in, tmp, out;
+    std::vector<const double2*> src;
+    int pos = 0;
+    for (int k = 0; k < nblk; ++k) {
+      BlockState& B = S[k];
+      B.first = k * Bsz;
+      for (int c = B.first; c < std::min(nrhs, B.first + Bsz); ++c) {
+        if (gn[c] == 0.0) cdone[c] = 1;
+        else B.cols.push_back(c);
+      }
+      if (B.cols.empty()) continue;
+      bls.push_back(k);
+      in.push_back(T1 + (size_t)pos * N);
+      tmp.push_back(T2 + (size_t)pos * N);
+      out.push_back(Vp(B, 0));
+      for (int c : B.cols) {
+        dst.push_back(T1 + (size_t)pos++ * N);
+        src.push_back(Gb + (size_t)c * N);
+      }
+    }
+    if ((e = gather(dst, src)) != LS_OK) return e;
+    if (!bls.empty() && (e = block_qr(bls, in, tmp, out)) != LS_OK) return e;
+    for (int k : bls)
+      if (!S[k].qr_ok) {
+        // linearly dependent right-hand sides: no block Krylov space of full
+        // width; nothing has been done yet, so solve them column by column
+        return gmres<T>(h, nrhs, tol, info);
+      }
+    for (int k : bls) start_cycle(S[k]);
+  }
+
+  const bool q64 = h->dim == 2 && !h->hmode && h->opt.sweep_schedule != LS_SWEEP_SEQUENTIAL;
+  C<T>* vin = h->vin.as<C<T>>();
+  C<T>* zout = h->zout.as<C<T>>();
+  C<T>* aout = h->aout.as<C<T>>();
+  while (true) {
+    std::vector<int> act;
+    int na = 0;
+    for (int k = 0; k < nblk; ++k)
+      if (S[k].in_cycle) {
+        act.push_back(k);
+        S[k].p0 = na;
+        na += S[k].b();
+      }
+    if (act.empty()) break;
+    // Z_j = P V_j, W = A Z_j for every column of the active blocks
+    std::vector<void*> vptr, wptr;
+    for (int k : act)
+      for (int c = 0; c < S[k].b(); ++c) {
+        vptr.push_back(Vp(S[k], S[k].j) + (size_t)c * N);
+        wptr.push_back(Wb + (size_t)(S[k].p0 + c) * N);
+      }
+    if (upload(h, h->ptrs_a, vptr) != LS_OK || upload(h, h->ptrs_b, wptr) != LS_OK) return LS_E_DEVICE;
+    if (q64) {
+      e = apply_P<T>(h, vin, na, zout, h->ptrs_a.as<const double2*>(), nullptr);
+    } else {
+      for (int k : act)
+        LSW_HIP_TRY((launch_cast_flat<T, double>(vin + (size_t)S[k].p0 * N, Vp(S[k], S[k].j), (size_t)S[k].b() * N, st)));
+      e = h->hmode ? apply_sweep_ext<T>(h, vin, na, zout) : apply_P<T>(h, vin, na, zout);
+    }
+    if (e != LS_OK) return e;
+    for (int k : act)
+      LSW_HIP_TRY((launch_cast_flat<double, T>(Zp(S[k], S[k].j), zout + (size_t)S[k].p0 * N, (size_t)S[k].b() * N, st)));
+    if (h->hmode) {
+      LSW_HIP_TRY(launch_apply_H<T>(h->stencils(), zout, na, aout, st));
+      LSW_HIP_TRY((launch_cast_flat<double, T>(Wb, aout, (size_t)na * N, st)));
+    } else if (h->dim == 2) {
+      if ((e = apply_A<T>(h, zout, na, aout, h->ptrs_b.as<double2* const>())) != LS_OK) return e;
+    } else {
+      if ((e = apply_A<T>(h, zout, na, aout)) != LS_OK) return e;
+      LSW_HIP_TRY((launch_cast_flat<double, T>(Wb, aout, (size_t)na * N, st)));
+    }
+    // two passes of classical block Gram-Schmidt against V_0 .. V_j
+    {
+      for (int k : act) {
+        BlockState& B = S[k];
+        const int b = B.b(), K = (B.j + 1) * b;
+        double2* Wk = Wb + (size_t)B.p0 * N;
+        const double2* V0 = Vp(B, 0);
+        for (double2* Cd : {C1d(k), C2d(k)}) {
+          {
+            Timed tg(h, kKGram, b);
+            if ((e = gram(K, b, V0, Wk, Cd)) != LS_OK) return e;
+          }
+          Timed tu(h, kKGramUpd, b);
+          LSW_BLAS_TRY(rocblas_zgemm(bl, ON, ON, iN, b, K, zs(mone), zc(V0), iN, zc(Cd), K, zs(one), zm(Wk), iN));
+        }
+        B.C1.resize((size_t)K * b);
+        B.C2.resize((size_t)K * b);
+        LSW_HIP_TRY(hipMemcpyAsync(B.C1.data(), C1d(k), B.C1.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+        LSW_HIP_TRY(hipMemcpyAsync(B.C2.data(), C2d(k), B.C2.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
+      }
+    }
+    // W = V_{j+1} R (block_qr's first synchronisation also completes the
+    // coefficient read-backs above)
+    {
+      std::vector<double2*> in, tmp, out;
+      for (int k : act) {
+        in.push_back(Wb + (size_t)S[k].p0 * N);
+        tmp.push_back(T1 + (size_t)S[k].p0 * N);
+        out.push_back(Vp(S[k], S[k].j + 1));
+      }
+      if ((e = block_qr(act, in, tmp, out)) != LS_OK) return e;
+    }
+    // host: the new block column of the block Hessenberg matrix, its
+    // Householder QR and the residual estimates
+    std::vector<int> ending;
+    for (int k : act) {
+      BlockState& B = S[k];
+      const int b = B.b(), j = B.j, K = (j + 1) * b, c0 = j * b;
+      const size_t ldh = (size_t)(rs + 1) * b;
+      cplx* Hb = B.Hb.data();
+      for (int c = 0; c < b; ++c) {
+        cplx* col = Hb + (size_t)(c0 + c) * ldh;
+        for (int i = 0; i < K; ++i) col[i] = B.C1[(size_t)c * K + i] + B.C2[(size_t)c * K + i];
+        for (int i = 0; i < b; ++i) col[K + i] = i <= c ? B.R[(size_t)c * b + i] : cplx(0.0);
+      }
+      // earlier reflectors: reflector r acts on rows r .. r+b
+      for (int r = 0; r < c0; ++r) {
+        const cplx* v = Hb + (size_t)r * ldh + r;  // v[0] = 1 implied
+        const cplx tc = std::conj(B.tau[r]);
+        for (int c = c0; c < c0 + b; ++c) {
+          cplx* y = Hb + (size_t)c * ldh + r;
+          cplx w = y[0];
+          for (int i = 1; i <= b; ++i) w += std::conj(v[i]) * y[i];
+          w *= tc;
+          y[0] -= w;
+          for (int i = 1; i <= b; ++i) y[i] -= v[i] * w;
+        }
+      }
+      // new reflectors for the columns c0 .. c0+b-1 (Householder vectors as
+      // in LAPACK's zlarfg: H^H x = beta e_1, beta real)
+      for (int col = c0; col < c0 + b; ++col) {
+        cplx* x = Hb + (size_t)col * ldh + col;
+        double xn = 0.0;
+        for (int i = 1; i <= b; ++i) xn += std::norm(x[i]);
+        xn = std::sqrt(xn);
+        cplx tau = 0.0;
+        if (xn != 0.0 || x[0].imag() != 0.0) {
+          const double ar = x[0].real(), ai = x[0].imag();
+          const double beta = -std::copysign(std::sqrt(ar * ar + ai * ai + xn * xn), ar);
+          tau = cplx((beta - ar) / beta, -ai / beta);
+          const cplx sc = 1.0 / (x[0] - beta);
+          for (int i = 1; i <= b; ++i) x[i] *= sc;
+          x[0] = beta;
+        }
+        B.tau[col] = tau;
+        const cplx tc = std::conj(tau);
+        auto reflect = [&](cplx* y) {
+          cplx w = y[0];
+          for (int i = 1; i <= b; ++i) w += std::conj(x[i]) * y[i];
+          w *= tc;
+          y[0] -= w;
+          for (int i = 1; i <= b; ++i) y[i] -= x[i] * w;
+        };
+        if (tau != 0.0) {
+          for (int c = col + 1; c < c0 + b; ++c) reflect(Hb + (size_t)c * ldh + col);
+          for (int c = 0; c < b; ++c) reflect(B.E.data() + (size_t)c * ldh + col);
+        }
+      }
+      B.j += 1;
+      B.iters += 1;
+      double est = 0.0;
+      for (int c = 0; c < b; ++c) {
+        col_its[B.cols[c]] += 1;
+        double r2 = 0.0;
+        for (int i = 0; i < b; ++i) r2 += std::norm(B.E[(size_t)c * ldh + K + i]);
+        est = std::max(est, std::sqrt(r2) / gn[B.cols[c]]);
+      }
+      if (!std::isfinite(est)) {
+        set_error("non-finite residual estimate in the block Arnoldi process");
+        return LS_E_NUMERIC;
+      }
+      B.end = est <= tol || B.j == rs || B.iters >= max_iters || !B.qr_ok;
+      if (B.end) ending.push_back(k);
+    }
+    if (ending.empty()) continue;
+    // cycle end: Y = R^{-1} (Q^H E)[0:k], X += [Z_0 .. Z_{j-1}] Y
+    std::vector<int> ecol;  // ending columns, in order
+    {
+      Timed tm(h, kKGramUpd, 0);
+      for (int k : ending) {
+        BlockState& B = S[k];
+        const int b = B.b(), kk = B.j * b;
+        const size_t ldh = (size_t)(rs + 1) * b;
+        B.Y.assign((size_t)kk * b, 0.0);
+        for (int c = 0; c < b; ++c)
+          for (int i = kk - 1; i >= 0; --i) {
+            cplx acc = B.E[(size_t)c * ldh + i];
+            for (int m = i + 1; m < kk; ++m) acc -= B.Hb[(size_t)m * ldh + i] * B.Y[(size_t)c * kk + m];
+            const cplx d = B.Hb[(size_t)i * ldh + i];
+            B.Y[(size_t)c * kk + i] = d == 0.0 ? cplx(0.0) : acc / d;
+          }
+        LSW_HIP_TRY(hipMemcpyAsync(C1d(k), B.Y.data(), B.Y.size() * sizeof(double2), hipMemcpyHostToDevice, st));
+        double2* out = T1 + (size_t)ecol.size() * N;
+        LSW_BLAS_TRY(rocblas_zgemm(bl, ON, ON, iN, b, kk, zs(one), zc(Zp(B, 0)), iN, zc(C1d(k)), kk, zs(zero),
+                                   zm(out), iN));
+        for (int c : B.cols) ecol.push_back(c);
+      }
+    }
+    const int ne = (int)ecol.size();
+    {
+      std::vector<AxpyOut> ho;
+      std::vector<AxpyTerm<double>> ht;
+      for (int q = 0; q < ne; ++q) {
+        ht.push_back({T1 + (size_t)q * N, 0, 0});
+        ho.push_back({Xb + (size_t)ecol[q] * N, q, q + 1, 0, -1, 0});
+      }
+      std::vector<double2> hc(1, make_double2(1.0, 0.0));
+      if (upload(h, h->coefs, hc) != LS_OK || upload(h, h->outs, ho) != LS_OK || upload(h, h->terms64, ht) != LS_OK)
+        return LS_E_DEVICE;
+      LSW_HIP_TRY(launch_axpys<double>(h->outs.as<AxpyOut>(), ne, h->terms64.as<AxpyTerm<double>>(),
+                                       h->coefs.as<double2>(), N, st));
+    }
+    // true residuals R[q] = g - A x of the ending columns (float64)
+    {
+      std::vector<void*> xp;
+      for (int c : ecol) xp.push_back(Xb + (size_t)c * N);
+      if (upload(h, h->ptrs_b, xp) != LS_OK) return LS_E_DEVICE;
+      if (h->dim == 2 && !h->hmode) {
+        if ((e = apply_A<double>(h, T1, ne, T2, nullptr, h->ptrs_b.as<const double2*>())) != LS_OK) return e;
+      } else {
+        std::vector<double2*> dst;
+        std::vector<const double2*> src;
+        for (int q = 0; q < ne; ++q) {
+          dst.push_back(T1 + (size_t)q * N);
+          src.push_back(Xb + (size_t)ecol[q] * N);
+        }
+        if ((e = gather(dst, src)) != LS_OK) return e;
+        if (h->hmode) LSW_HIP_TRY(launch_apply_H<double>(h->stencils(), T1, ne, T2, st));
+        else if ((e = apply_A<double>(h, T1, ne, T2)) != LS_OK) return e;
+      }
+      std::vector<AxpyOut> ho;
+      std::vector<AxpyTerm<double>> ht;
+      for (int q = 0; q < ne; ++q) {
+        ht.push_back({Gb + (size_t)ecol[q] * N, 0, 0});
+        ht.push_back({T2 + (size_t)q * N, 0, 1});
+        ho.push_back({Rb + (size_t)q * N, 2 * q, 2 * q + 2, 1, -1, 0});
+      }
+      if (upload(h, h->outs, ho) != LS_OK || upload(h, h->terms64, ht) != LS_OK) return LS_E_DEVICE;
+      LSW_HIP_TRY(launch_axpys<double>(h->outs.as<AxpyOut>(), ne, h->terms64.as<AxpyTerm<double>>(),
+                                       h->coefs.as<double2>(), N, st));
+    }
+    std::vector<double> rn;
+    if ((e = colnorms(Rb, ne, rn)) != LS_OK) return e;
+    // which columns stay; the blocks that go on restart from their residuals
+    std::vector<int> bls;
+    std::vector<double2*> dst, in, tmp, out;
+    std::vector<const double2*> src;
+    int q = 0, pos = 0;
+    for (int k : ending) {
+      BlockState& B = S[k];
+      std::vector<int> keep;
+      std::vector<int> keep_q;
+      for (int c : B.cols) {
+        if (!std::isfinite(rn[q])) {
+          set_error("non-finite true residual");
+          return LS_E_NUMERIC;
+        }
+        relres[c] = rn[q] / gn[c];
+        if (relres[c] <= tol) cdone[c] = 1;
+        else if (B.iters >= max_iters) cdone[c] = 2;
+        else {
+          keep.push_back(c);
+          keep_q.push_back(q);
+        }
+        ++q;
+      }
+      B.in_cycle = false;
+      B.cols = keep;
+      if (keep.empty()) continue;
+      bls.push_back(k);
+      in.push_back(T1 + (size_t)pos * N);
+      tmp.push_back(T2 + (size_t)pos * N);
+      out.push_back(Vp(B, 0));
+      for (int qq : keep_q) {
+        dst.push_back(T1 + (size_t)pos++ * N);
+        src.push_back(Rb + (size_t)qq * N);
+      }
+    }
+    if ((e = gather(dst, src)) != LS_OK) return e;
+    if (!bls.empty() && (e = block_qr(bls, in, tmp, out)) != LS_OK) return e;
+    for (int k : bls) {
+      if (!S[k].qr_ok) {
+        set_error("the residuals of a block became linearly dependent at a restart");
+        return LS_E_NUMERIC;
+      }
+      start_cycle(S[k]);
+    }
+  }
+  info.resize(nrhs);
+  bool all = true;
+  for (int c = 0; c < nrhs; ++c) {
+    info[c].iterations = col_its[c];
+    info[c].rel_residual = gn[c] == 0.0 ? 0.0 : relres[c];
+    info[c].converged = cdone[c] == 1;
+    all = all && cdone[c] == 1;
+  }
+  if (!all) {
+    set_error("block GMRES reached max_iters before the tolerance for some right-hand side");
+    return LS_E_NOCONV;
+  }
+  return LS_OK;
+}
+
 ls_status run_gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& info) {
+  if (h->opt.block_size > 1 && nrhs > 1)
+    return h->prec == LS_FP64 ? block_gmres<double>(h, nrhs, tol, info) : block_gmres<float>(h, nrhs, tol, info);
   return h->prec == LS_FP64 ? gmres<double>(h, nrhs, tol, info) : gmres<float>(h, nrhs, tol, info);
 }
 
@@ -1998,6 +2585,7 @@ void ls_default_options(ls_options* o) {
   o->hip_stream = nullptr;
   o->sweep_schedule = LS_SWEEP_INTERFACE;
   o->fronts = 1;
+  o->block_size = 1;
 }
 
 const char* ls_last_error(void) { return lsw::get_error(); }
@@ -2036,6 +2624,10 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
     }
     if (o.fronts == 2 && (grid->dim != 2 || o.sweep_schedule != LS_SWEEP_INTERFACE)) {
       set_error("fronts = 2 needs a 2D grid and the interface sweep schedule");
+      return LS_E_INVALID;
+    }
+    if (o.block_size < 1 || o.block_size > 64 || (o.block_size > 1 && o.block_size * o.restart > 2048)) {
+      set_error("block_size must be in [1, 64], with block_size * restart <= 2048 when above 1");
       return LS_E_INVALID;
     }
     if (o.restart < 1 || o.restart > 200 || o.max_iters < 1) {

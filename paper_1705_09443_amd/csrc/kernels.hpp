@@ -303,6 +303,13 @@ hipError_t launch_adjoint_product(const double2* psi, const double2* nu, int nrh
 hipError_t launch_conj(double2* dst, const double2* src, size_t N, hipStream_t st);
 // x (+)= s * y elementwise over N with real s, float64 (incident total field etc.)
 hipError_t launch_add_scaled(double2* x, const double2* y, double s, size_t N, hipStream_t st);
+// dst[i] = src[i] over count values, converting the precision
+template <typename TD, typename TS>
+hipError_t launch_cast_flat(C<TD>* dst, const C<TS>* src, size_t count, hipStream_t st);
+// partials[c][0..kDotBlocks) of ||x_c||^2 for the ncols columns of [ncols][N]
+hipError_t launch_colnorm2(const double2* x, int ncols, size_t N, double* partials, hipStream_t st);
+// out[i] = sum of parts[c][i] over c < nparts, for i < count (fixed order)
+hipError_t launch_sum_parts(const double2* parts, int nparts, size_t count, double2* out, hipStream_t st);
 // k plane waves exp(i omega (cos t_j x1 + sin t_j x2)), t_j = 2 pi j / k, on the interior grid: [k][n][n]
 hipError_t launch_plane_waves(double2* out, int n, double omega, int k, hipStream_t st);
 

@@ -2,6 +2,8 @@
 // with fixed-order reductions (bitwise reproducible, no float atomics),
 // multi-term axpy updates, precision casts and the adjoint's pointwise
 // product.
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace lsw {
@@ -234,6 +236,37 @@ __global__ void k_copy_cast(C<TD>* const* __restrict__ dst, const C<TS>* const* 
     d[i] = ccast<TD, TS>(s[i]);
 }
 
+template <typename TD, typename TS>
+__global__ void k_cast_flat(C<TD>* __restrict__ dst, const C<TS>* __restrict__ src, size_t count) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = ccast<TD, TS>(src[i]);
+}
+
+// partials[c][blk] = the blk-th chunk of ||x_c||^2 for the columns of a
+// [ncols][N] block (fixed chunks and order: reproducible)
+__global__ __launch_bounds__(kThreads) void k_colnorm2(const double2* __restrict__ x, size_t N,
+                                                       double* __restrict__ partials) {
+  const int c = blockIdx.y, blk = blockIdx.x;
+  const double2* xc = x + (size_t)c * N;
+  const size_t chunk = (N + kDotBlocks - 1) / kDotBlocks;
+  const size_t beg = blk * chunk;
+  const size_t end = beg + chunk < N ? beg + chunk : N;
+  double acc = 0.0;
+  for (size_t i = beg + threadIdx.x; i < end; i += kThreads) {
+    const double2 a = xc[i];
+    acc += a.x * a.x + a.y * a.y;
+  }
+  for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+  __shared__ double ws[kThreads / 64];
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = ws[0];
+    for (int w = 1; w < kThreads / 64; ++w) s += ws[w];
+    partials[(size_t)c * kDotBlocks + blk] = s;
+  }
+}
+
 __global__ void k_adjoint_product(const double2* __restrict__ psi, const double2* __restrict__ nu, int nrhs,
                                   size_t N, double omega2, double* __restrict__ grad) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
@@ -345,6 +378,40 @@ template hipError_t launch_copy_cast<double, float>(double2* const*, const float
                                                     hipStream_t);
 template hipError_t launch_copy_cast<float, float>(float2* const*, const float2* const*, int, size_t,
                                                    hipStream_t);
+
+template <typename TD, typename TS>
+hipError_t launch_cast_flat(C<TD>* dst, const C<TS>* src, size_t count, hipStream_t st) {
+  hipLaunchKernelGGL((k_cast_flat<TD, TS>), dim3(2048), dim3(256), 0, st, dst, src, count);
+  return hipGetLastError();
+}
+template hipError_t launch_cast_flat<double, float>(double2*, const float2*, size_t, hipStream_t);
+template hipError_t launch_cast_flat<float, double>(float2*, const double2*, size_t, hipStream_t);
+template hipError_t launch_cast_flat<double, double>(double2*, const double2*, size_t, hipStream_t);
+template hipError_t launch_cast_flat<float, float>(float2*, const float2*, size_t, hipStream_t);
+
+// out[i] = sum over c < nparts of parts[c * count + i] (fixed order)
+__global__ void k_sum_parts(const double2* __restrict__ parts, int nparts, size_t count, double2* __restrict__ out) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    double2 acc = parts[i];
+    for (int c = 1; c < nparts; ++c) {
+      const double2 v = parts[(size_t)c * count + i];
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    out[i] = acc;
+  }
+}
+
+hipError_t launch_sum_parts(const double2* parts, int nparts, size_t count, double2* out, hipStream_t st) {
+  const int blocks = (int)std::min<size_t>((count + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_sum_parts, dim3(std::max(blocks, 1)), dim3(256), 0, st, parts, nparts, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_colnorm2(const double2* x, int ncols, size_t N, double* partials, hipStream_t st) {
+  hipLaunchKernelGGL(k_colnorm2, dim3(kDotBlocks, ncols), dim3(kThreads), 0, st, x, N, partials);
+  return hipGetLastError();
+}
 
 hipError_t launch_adjoint_product(const double2* psi, const double2* nu, int nrhs, size_t N, double omega2,
                                   double* grad, hipStream_t st) {

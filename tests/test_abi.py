@@ -115,3 +115,22 @@ def test_three_dimensional_grid_passes_the_host_checks():
     assert lib.ls_setup(ctypes.byref(grid), 10.0, dummy, 4, 4, ctypes.byref(o), ctypes.byref(h)) == _lib.LS_E_INVALID
     assert "dim must be 2 or 3" in lib.ls_last_error().decode()
     assert not h.value
+
+
+def test_block_size_limits_are_host_checks():
+    # block flexible GMRES: groups of at most 64 columns, and the block
+    # Hessenberg matrix of a cycle at most 2048 columns wide
+    from paper_1705_09443_amd import _lib
+    lib = _lib.load()
+    o = _lib.LsOptions()
+    lib.ls_default_options(ctypes.byref(o))
+    assert o.block_size == 1
+    grid = _lib.LsGrid(2, 31)
+    h = ctypes.c_void_p()
+    dummy = ctypes.c_void_p(16)
+    for bs, rs in ((0, 30), (65, 30), (64, 33)):
+        o.block_size, o.restart = bs, rs
+        assert lib.ls_setup(ctypes.byref(grid), 10.0, dummy, 6, 4, ctypes.byref(o), ctypes.byref(h)) == \
+            _lib.LS_E_INVALID
+        assert "block_size" in lib.ls_last_error().decode()
+    assert not h.value
