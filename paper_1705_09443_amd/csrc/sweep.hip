@@ -110,64 +110,145 @@ __global__ void k_apply_H(StencilTables S, const C<T>* __restrict__ u, int nrhs,
   y[idx] = acc;
 }
 
-// Q into the interleaved layout f[e1][e2][nrhs] (right-hand side fastest). A
-// workgroup takes one extended row, 64 columns and 16 right-hand sides: the
-// stencil reads run along the columns of each right-hand side's plane, the
-// results cross LDS and leave with the right-hand side fastest.
-// R64: right-hand side q read from r64[q] (float64), narrowed to T on load
+// Q into the interleaved layout f[e1][e2][nrhs] (right-hand side fastest).
+// A workgroup owns a strip of 64 columns, kQRows consecutive extended rows
+// and 16 right-hand sides, and slides down the strip in chunks of CH rows: a
+// ring of CH + 2 input rows (66 columns, the strip and its two neighbours,
+// for 16 right-hand sides) sits in LDS, so every input row is fetched once
+// per strip (plus two halo rows per strip). A chunk's CH input rows are
+// loaded at once (CH x 5 loads per thread in flight), then its CH output rows
+// are formed; each crosses LDS and leaves with the right-hand side fastest.
+// R64: right-hand side q read from r64[q] (float64), narrowed to T when it
+// enters the ring.
+constexpr int kQRows = 32;
+constexpr int kQCols = 66;                          // 64 outputs + 2 halo columns
+constexpr int kQLoads = (16 * kQCols + 255) / 256;  // input loads per thread and row
+constexpr int kQRingRows = kQLoads * 256 / kQCols + 1;  // every load slot has a place
+
+// v stored at byte offset off of the buffer rs; an offset past the buffer's
+// size (the hardware's range check) drops the store, with no branch
+template <typename T>
+__device__ inline void store_or_drop(__amdgpu_buffer_rsrc_t rs, int off, C<T> v) {
+  if constexpr (sizeof(C<T>) == 8) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, 0, 0);
+  } else {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), rs, off, 0, 0);
+  }
+}
+
 template <typename T, bool R64>
 __global__ __launch_bounds__(256) void k_apply_Q_il(StencilTables S, const C<T>* __restrict__ r, int nrhs,
                                                     C<T>* __restrict__ f, const double2* const* __restrict__ r64) {
-  __shared__ C<T> tile[64][17];
+  constexpr int CH = sizeof(T) == 4 ? 4 : 2;  // rows per chunk (the LDS ring holds CH + 2)
+  constexpr int RS = CH + 2;
+  __shared__ C<T> ring[RS][kQRingRows][kQCols];
+  __shared__ C<T> tile[2][64][17];
   const int L = S.L, n = S.n, b = S.b;
-  const int c0 = blockIdx.x * 64, e1 = blockIdx.y, q0 = blockIdx.z * 16;
-  const int i1 = e1 - b;
+  const int c0 = blockIdx.x * 64, r0 = blockIdx.y * kQRows, q0 = blockIdx.z * 16;
+  const int r1 = min(r0 + kQRows, L);
   const int t = threadIdx.x, c = t & 63, sub = t >> 6;
-  const int i2 = c0 + c - b;
-  const bool type1 = i1 >= 0 && i1 <= n + 1 && c0 + c < L && i2 >= 0 && i2 <= n + 1;
-  // the nine taps of a right-hand side are loaded together from clamped
-  // in-range addresses and masked afterwards (taps off the interior, rows of
-  // the PML and right-hand sides past nrhs contribute zero)
-  bool ok[9];
-  size_t at[9];
+  // this thread's load slots: right-hand side lq[s], input column
+  // c0 - b - 1 + lc[s]; lv[s] false for slots off the interior columns or
+  // past the 16 right-hand sides (their values are zeroed)
+  int lq[kQLoads], lc[kQLoads], col[kQLoads];
+  bool lv[kQLoads];
+  // the grids of this thread's right-hand sides (global address space:
+  // global loads, not flat ones)
+  using G64 = const __attribute__((address_space(1))) double;
+  using GT = const __attribute__((address_space(1))) T;
+  G64* rp64[kQLoads];
+  GT* rpT[kQLoads];
 #pragma unroll
-  for (int o = 0; o < 9; ++o) {
-    const int j1 = i1 + o / 3 - 1, j2 = i2 + o % 3 - 1;
-    ok[o] = type1 && j1 >= 1 && j1 <= n && j2 >= 1 && j2 <= n;
-    at[o] = (size_t)(min(max(j1, 1), n) - 1) * n + (min(max(j2, 1), n) - 1);
+  for (int s = 0; s < kQLoads; ++s) {
+    const int idx = t + 256 * s;
+    lq[s] = idx / kQCols;
+    lc[s] = idx % kQCols;
+    const int j2 = c0 - b - 1 + lc[s];
+    lv[s] = idx < 16 * kQCols && q0 + lq[s] < nrhs && j2 >= 1 && j2 <= n;
+    col[s] = min(max(j2, 1), n) - 1;
+    const int q = min(q0 + lq[s], nrhs - 1);
+    if constexpr (R64) rp64[s] = (G64*)r64[q];
+    else rpT[s] = (GT*)(r + (size_t)q * n * n);  // scalar view of the complex grid
   }
+  // raw values of input rows, in the input's precision
+  using RT = typename std::conditional<R64, double2, C<T>>::type;
+  auto load_row = [&](int j1, RT(&rg)[kQLoads]) {
+    const size_t base = (size_t)(min(max(j1, 1), n) - 1) * n;
 #pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int rr = q0 + sub + 4 * s, rq = min(rr, nrhs - 1);
-    C<T> rv[9];
-    if (R64) {
-      // the grids are device memory: global loads, not flat ones
-      using G64 = const __attribute__((address_space(1))) double;
-      G64* rp64 = (G64*)r64[rq];
-#pragma unroll
-      for (int o = 0; o < 9; ++o) rv[o] = mk<T>((T)rp64[2 * at[o]], (T)rp64[2 * at[o] + 1]);
-    } else {
-      const C<T>* rp = r + (size_t)rq * n * n;
-#pragma unroll
-      for (int o = 0; o < 9; ++o) rv[o] = rp[at[o]];
+    for (int s = 0; s < kQLoads; ++s) {
+      const size_t at = base + col[s];
+      if constexpr (R64) rg[s] = make_double2(rp64[s][2 * at], rp64[s][2 * at + 1]);
+      else rg[s] = mk<T>(rpT[s][2 * at], rpT[s][2 * at + 1]);
     }
-    C<T> acc = mk<T>(0, 0);
+  };
+  // ring slot of input row j1 (rows from r0 - b - 1 on)
+  auto slot = [&](int j1) { return (j1 - (r0 - b - 1)) % RS; };
+  auto store_row = [&](int j1, const RT(&rg)[kQLoads]) {
+    const int sl = slot(j1);
+    const bool rowok = j1 >= 1 && j1 <= n;
 #pragma unroll
-    for (int o = 0; o < 9; ++o) {
-      if (ok[o] && rr < nrhs) {
-        const double2 al = S.alpha[o];
-        acc = cfma<T>(acc, mk<T>((T)al.x, (T)-al.y), rv[o]);
+    for (int s = 0; s < kQLoads; ++s) {
+      // zero off the interior by a factor, not a branch
+      const T msk = (rowok && lv[s]) ? T(1) : T(0);
+      ring[sl][lq[s]][lc[s]] = mk<T>((T)rg[s].x * msk, (T)rg[s].y * msk);
+    }
+  };
+  C<T> al[9];
+#pragma unroll
+  for (int o = 0; o < 9; ++o) al[o] = mk<T>((T)S.alpha[o].x, (T)-S.alpha[o].y);
+  const int i2 = c0 + c - b;
+  const bool colok = c0 + c < L && i2 >= 0 && i2 <= n + 1;
+  {
+    RT rg[2][kQLoads];
+    load_row(r0 - b - 1, rg[0]);
+    load_row(r0 - b, rg[1]);
+    store_row(r0 - b - 1, rg[0]);
+    store_row(r0 - b, rg[1]);
+  }
+  for (int e0 = r0; e0 < r1; e0 += CH) {
+    // input rows e0 - b + 1 .. e0 - b + CH (clamped rows past the strip's end
+    // are loaded and dropped)
+    {
+      RT rg[CH][kQLoads];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) load_row(e0 - b + 1 + k, rg[k]);
+#pragma unroll
+      for (int k = 0; k < CH; ++k) store_row(e0 - b + 1 + k, rg[k]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < CH; ++k) {
+      const int e1 = e0 + k, i1 = e1 - b;
+      const bool ok = colok && i1 >= 0 && i1 <= n + 1;
+      const int s0 = slot(i1 - 1), s1 = slot(i1), s2 = slot(i1 + 1);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int rr = sub + 4 * s;
+        C<T> acc = mk<T>(0, 0);
+#pragma unroll
+        for (int o = 0; o < 9; ++o) {
+          const int sl = o < 3 ? s0 : (o < 6 ? s1 : s2);
+          acc = cfma<T>(acc, al[o], ring[sl][rr][c + o % 3]);
+        }
+        tile[k & 1][c][rr] = ok ? acc : mk<T>(0, 0);
+      }
+      __syncthreads();
+      // output row e1 through a buffer of that row: columns past L and right-
+      // hand sides past nrhs are dropped by the range check, and a row past
+      // the strip's end has an empty buffer
+      const __amdgpu_buffer_rsrc_t rs = __builtin_amdgcn_make_buffer_rsrc(
+          f + (size_t)min(e1, L - 1) * L * nrhs, 0, e1 < r1 ? (int)(L * nrhs * sizeof(C<T>)) : 0, 0x00020000);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int idx = t + 256 * s;
+        const int rr = idx & 15, cc = idx >> 4;
+        const int e2 = c0 + cc, q = q0 + rr;
+        const int off = (e2 < L && q < nrhs) ? (e2 * nrhs + q) * (int)sizeof(C<T>) : -1;
+        store_or_drop<T>(rs, off, tile[k & 1][cc][rr]);
       }
     }
-    tile[c][sub + 4 * s] = acc;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int s = 0; s < 4; ++s) {
-    const int idx = t + 256 * s;
-    const int rr = idx & 15, cc = idx >> 4;
-    const int e2 = c0 + cc, q = q0 + rr;
-    if (e2 < L && q < nrhs) f[((size_t)e1 * L + e2) * nrhs + q] = tile[cc][rr];
   }
 }
 
@@ -544,7 +625,7 @@ template <typename T>
 hipError_t launch_apply_Q(const StencilTables& S, const C<T>* r, int nrhs, C<T>* f, bool interleaved,
                           hipStream_t st, const double2* const* r64) {
   if (interleaved) {
-    const dim3 g((S.L + 63) / 64, S.L, (nrhs + 15) / 16);
+    const dim3 g((S.L + 63) / 64, (S.L + kQRows - 1) / kQRows, (nrhs + 15) / 16);
     if (r64)
       hipLaunchKernelGGL((k_apply_Q_il<T, true>), g, dim3(256), 0, st, S, r, nrhs, f, r64);
     else
