@@ -9,10 +9,11 @@ the preconditioner (Q stencil, slice solves, interface recurrences, slice
 solves, extraction) and the FFT operator to every right-hand side still
 running, until every right-hand side meets the tolerance. Inputs are resident
 in HBM before the timed region; setup (Algorithm 1) is timed separately and
-excluded. The batched setup is autotuned (the layer thickness and the kernel
-choice per batch size timed on the device for this batch; --no-autotune keeps
-the workload's w = 4 and the default kernels); its setup time includes the
-tuning.
+excluded. The batched leg runs at the workload's w = 4 with the default
+kernel choice per batch size (the autotuner's choice for this batch on
+MI355X, where w = 4 and w = 5 come within 2 % of each other); --autotune
+times the candidates on the device instead, and its setup time then
+includes the tuning.
 
 A 3D leg (object "c3") times the 127^3 workload the same way: four incident
 waves, mixed precision, the slab-by-slab sweep captured as one graph; its
@@ -66,8 +67,9 @@ def parse():
     p.add_argument("--block-size", type=int, default=64,
                    help="block flexible GMRES leg: columns per block (0: skip the leg)")
     p.add_argument("--steps-block", type=int, default=2)
-    p.add_argument("--no-autotune", action="store_true",
-                   help="batched leg at the workload's w and the default kernels instead of autotuned ones")
+    p.add_argument("--autotune", action="store_true",
+                   help="batched leg autotuned (w and the kernel choice timed on the device) instead of the "
+                        "workload's w = 4 and the default kernels")
     p.add_argument("--fronts", type=int, default=2, choices=(1, 2),
                    help="sweeping fronts of the 2D legs: 2 (default) from both ends toward a middle slice, "
                         "as the paper's 2D experiments; 1 the single front of Algorithms 1-2")
@@ -131,9 +133,17 @@ def interface_map_flops(solver):
 
 # HBM bytes per launch from hardware counters (FETCH_SIZE + WRITE_SIZE, each
 # calibrated on a plain copy of known size) for the 1023^2 64-wave mixed
-# workload, keyed by part; valid only for the kernels as they were when
-# measured (profiles/c2_mixed_64rhs_hbm_counters.md).
-MEASURED_TRAFFIC = {}
+# workload at w = 4 with two fronts and the default kernel choice, keyed by
+# (part, complex bytes, w, fronts); valid only for the kernels as they were
+# when measured (profiles/c2_mixed_64rhs_hbm_counters.md). Per launch at the
+# run's mean columns per launch: sweep 56.3 (one apply: every slice-solve,
+# interface-product and coupling kernel), FFT 45.8 (complex64 launches),
+# Q 56.3.
+MEASURED_TRAFFIC = {
+    ("sweep", 8, 4, 2): 2.2801e10,
+    ("fft_convolve", 8, 4, 2): 7.4507e9,
+    ("stencil_Q", 8, 4, 2): 1.8365e9,
+}
 
 # published MI355X dense matrix-core peaks (TFLOP/s): fp32 157.3, fp64 78.6
 MFMA_PEAK = {8: 157.3, 16: 78.6}
@@ -147,7 +157,7 @@ def hbm_roofline(label, formula, shared, per_col, cols, avg_ms, traffic=None):
             "mean_columns_per_launch": cols, "algorithmic_bytes_per_launch": nbytes, "formula": formula}
 
 
-def rooflines(solver, prof, cbytes: int, n: int):
+def rooflines(solver, prof, cbytes: int, n: int, fronts: int = 1):
     """The sweep apply (the dominant part of the step), the FFT convolution and
     the Q stencil against the HBM peak, each from the method's algorithmic
     bytes (sweep_method_bytes, fft_method_bytes, stencil_method_bytes) over the
@@ -159,6 +169,12 @@ def rooflines(solver, prof, cbytes: int, n: int):
     the last slice's solves run on the second stream, overlapped."""
     L = solver.L
     out = {}
+
+    def traffic(part):
+        if n != 1023:
+            return None
+        return MEASURED_TRAFFIC.get((part, cbytes, solver.layer_thickness, fronts))
+
     it = prof.get("interface")
     ss = prof.get("slice_solves")
     if it and ss:
@@ -169,7 +185,7 @@ def rooflines(solver, prof, cbytes: int, n: int):
         out["sweep"] = hbm_roofline(
             "sweep apply (Algorithm 2: slice solves, phases A and C, plus the interface graph)",
             "sum over the 2l-1 slice solves of 2 L t^2 s (factors) + columns x (2 w_k + 2 t) L s",
-            sh, pc, cols, avg, MEASURED_TRAFFIC.get(("sweep", cbytes)) if n == 1023 else None)
+            sh, pc, cols, avg, traffic("sweep"))
         fl, mb = interface_map_flops(solver)
         t_if = it[1] / applies
         out["interface_dense_maps"] = {
@@ -183,13 +199,13 @@ def rooflines(solver, prof, cbytes: int, n: int):
         out["fft_convolve"] = hbm_roofline(
             "FFT convolution (row forward, column convolve, row inverse)",
             "(P/2+1)^2 s + columns x ((2s + s/2) N + 4 n P s)", sh, pc, f[2] / f[0], f[1] / f[0],
-            MEASURED_TRAFFIC.get(("fft_convolve", cbytes)) if n == 1023 else None)
+            traffic("fft_convolve"))
     q = prof.get("stencil_Q")
     if q:
         sh, pc = stencil_method_bytes(n, L, cbytes)
         out["stencil_Q"] = hbm_roofline(
             "Q stencil", "columns x (s N + s N_ext)", sh, pc, q[2] / q[0], q[1] / q[0],
-            MEASURED_TRAFFIC.get(("stencil_Q", cbytes)) if n == 1023 else None)
+            traffic("stencil_Q"))
         # the mixed Arnoldi step hands Q the float64 basis vector: 16-byte reads
         out["stencil_Q"]["frac_at_io_width"] = (
             (q[2] / q[0]) * (16.0 * n * n + cbytes * L * L) / (q[1] / q[0] * 1e-3) / 1e9 / HBM_PEAK_GBS)
@@ -511,7 +527,7 @@ def main():
     # ---- mixed precision, batched (the headline) ----
     uinc2 = torch.as_tensor(wl2.incident(), device=dev)
     t0 = time.perf_counter()
-    if args.no_autotune:
+    if not args.autotune:
         mixed = LSSolver(md, wl2.omega, wl2.pml_width, wl2.layer_thickness, precision="mixed",
                          restart=wl2.restart, fronts=args.fronts)
     else:
@@ -541,7 +557,7 @@ def main():
     iters = [x.iterations for x in info]
     assert all(x.converged and x.rel_residual <= wl2.tol for x in info), "a right-hand side did not converge"
     value = wl2.nrhs * N / t_mixed
-    roofs = rooflines(mixed, prof, 8, n)
+    roofs = rooflines(mixed, prof, 8, n, args.fronts)
     roof = roofs.get("sweep")
     kernels = {k: {"launches": v[0], "avg_ms": v[1] / v[0], "columns_per_launch": v[2] / v[0],
                    "share_of_step": v[1] / (t_mixed * 1e3 * args.steps)} for k, v in prof.items()}
@@ -561,13 +577,13 @@ def main():
         "data": "synthetic: seeded Gaussian-bump medium and plane waves",
         "config": {"workload": (f"2D {n}^2, omega=2pi*{wl2.ppw_omega:g}, 32 Gaussian bumps (seed 0), {wl2.nrhs} "
                                 f"plane waves theta_j=2pi j/{wl2.nrhs}, mixed precision, b={wl2.pml_width}, "
-                                f"w={wl2.layer_thickness}{'' if args.no_autotune else ' (autotuned)'}, "
+                                f"w={wl2.layer_thickness}{' (autotuned)' if args.autotune else ''}, "
                                 f"{args.fronts} sweeping front{'s' if args.fronts > 1 else ''}, "
                                 f"restart {wl2.restart}, tol {wl2.tol}"),
                    "n": n, "nrhs": wl2.nrhs, "omega": wl2.omega, "precision": "mixed"},
         "iterations": {"min": min(iters), "max": max(iters), "mean": sum(iters) / len(iters)},
         "setup_s": {"mixed": setup_mixed},
-        "autotune": None if args.no_autotune else {
+        "autotune": None if not args.autotune else {
             "layers": [{"w": r[0], "slices": r[1], "iterations": r[2], "setup_ms": r[3], "solve_ms": r[4]}
                        for r in tuning["layers"]],
             "kernels": [{"nrhs": r[0], "slice_kernel": r[1], "iface_kernel": r[2], "apply_ms": r[3]}
