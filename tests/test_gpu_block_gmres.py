@@ -199,3 +199,31 @@ def test_three_dimensional_blocks():
         assert info[c].converged and abs(info[c].iterations - k) <= 1
         assert rel(ref.op.apply_A(u[c]), g[c]) <= 1.01e-8
     assert e1 <= 1e-10
+
+
+def test_ragged_groups_and_the_adjoint(lsp):
+    # 6 columns in groups of 4 and 2; the adjoint solve through the block
+    # loop gives the per-column loop's gradient (both solves to 1e-12)
+    from paper_1705_09443_amd import LSSolver
+    fronts, m, omega, ref, uinc, G, tight = lsp
+    if fronts == 2:
+        pytest.skip("the grouping does not depend on the sweep")
+    md = torch.as_tensor(m).cuda()
+    with LSSolver(md, omega, B, W, precision="fp64", block_size=4, restart=10) as s:
+        u, info = s.solve(to_dev(uinc), "incident", 1e-6)
+        u = u.cpu().numpy()
+        for cols in ([0, 1, 2, 3], [4, 5]):
+            res = ref.solve_block(G[cols], 1e-6, restart=10)
+            for i, c in enumerate(cols):
+                assert info[c].converged and abs(info[c].iterations - res.col_iterations[i]) <= 1
+                assert rel(ref.op.apply_A(u[c]), G[c]) <= 1.01e-6
+        ub, _ = s.solve(to_dev(uinc), "incident", 1e-12)
+        rng = np.random.default_rng(9)
+        r = to_dev(rng.standard_normal((NRHS, N2, N2)) + 1j * rng.standard_normal((NRHS, N2, N2)))
+        gb, gi = s.adjoint(r, 1e-12)
+    with LSSolver(md, omega, B, W, precision="fp64") as s1:
+        s1.solve(to_dev(uinc), "incident", 1e-12)
+        g1, _ = s1.adjoint(r, 1e-12)
+    e = float(torch.linalg.norm(gb - g1) / torch.linalg.norm(g1))
+    say(f"[block 4 of 6 columns] steps {[i.iterations for i in info]}; adjoint gradient vs per-column: {e:.2e}")
+    assert all(i.converged for i in gi) and e <= 1e-9
