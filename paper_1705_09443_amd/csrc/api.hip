@@ -193,7 +193,7 @@ struct ls_handle {
   DBuf V, Z, W, X, G, R, T1, T2;
   DBuf pairs, groups, partials, coefs, outs, terms64, terms32, ptrs_a, ptrs_b;
   // descriptor stages of the Arnoldi step: before and after its readback
-  Stage stage_main, stage_post;
+  Stage stage_main;
   // the Krylov loop's operator: false, the Lippmann-Schwinger operator A on
   // the interior grid with P = extract(sweep(Q .)); true, the sparse system H
   // on the extended grid with the sweep alone (ls_solve_H)
@@ -453,10 +453,12 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   {
     // 3 pointer pairs per right-hand side, dot groups and update terms of up
     // to maxpairs products, 2 outputs per right-hand side, alignment slack
+    // (+ one unit term per right-hand side in the second pass, and the
+    // per-right-hand-side offsets of its products)
     const size_t main_bytes = (size_t)nrhs * 6 * sizeof(void*) + maxpairs * (sizeof(DotGroup) + 2 * sizeof(AxpyTerm<double>)) +
-                              (size_t)nrhs * 2 * sizeof(AxpyOut) + sizeof(double2) + 16 * 256;
-    const size_t post_bytes = (size_t)nrhs * (sizeof(AxpyOut) + sizeof(AxpyTerm<double>)) + 4 * 256;
-    if (h->stage_main.alloc(main_bytes) != hipSuccess || h->stage_post.alloc(post_bytes) != hipSuccess) {
+                              (size_t)nrhs * (2 * sizeof(AxpyOut) + sizeof(AxpyTerm<double>)) +
+                              (size_t)(nrhs + 1) * sizeof(int) + sizeof(double2) + 16 * 256;
+    if (h->stage_main.alloc(main_bytes) != hipSuccess) {
       (void)hipGetLastError();
       set_error("pinned host allocation for the descriptor stages failed");
       return LS_E_NOMEM;
@@ -1244,8 +1246,11 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       for (int k = 0; k <= S[r].j; ++k) hp.push_back({Vp(r, k), Wb + (size_t)r * N});
       off[p + 1] = (int)hp.size();
     }
+    // coefficients: the first pass's products (base1), the second pass's
+    // (base2), h^2 = ||w_2||^2 per right-hand side (base3) and the first
+    // pass's ||w_1||^2 (base4)
     const int np = (int)hp.size();
-    const int base1 = 1, base2 = 1 + np, base3 = 1 + 2 * np;
+    const int base1 = 1, base2 = 1 + np, base3 = 1 + 2 * np, base4 = 1 + 2 * np + na;
     ho.clear();
     ht64.clear();
     for (int p = 0; p < na; ++p) {
@@ -1255,13 +1260,17 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       o.tend = (int)ht64.size();
       ho.push_back(o);
     }
-    // second-pass terms use the base2 coefficients
-    const int nterm = (int)ht64.size();
-    for (int i = 0; i < nterm; ++i) ht64.push_back({ht64[i].x, ht64[i].coef + np, 1});
+    // the second pass writes the next basis vector itself:
+    // v_{j+1} = (w_1 - V c_2) / h with h^2 = ||w_1||^2 - |c_2|^2 (V
+    // orthonormal and c_2 = V^H w_1; c_2 is the small reorthogonalisation
+    // correction, so the difference does not cancel), the unit term w_1 with
+    // coefs[0] = 1. It replaces a separate normalisation pass.
     for (int p = 0; p < na; ++p) {
-      AxpyOut o = ho[p];
-      o.tbeg += nterm;
-      o.tend += nterm;
+      const int r = act[p];
+      AxpyOut o{Vp(r, S[r].j + 1), (int)ht64.size(), 0, 1, base3 + p, 1};
+      ht64.push_back({Wb + (size_t)r * N, 0, 0});
+      for (int k = 0; k <= S[r].j; ++k) ht64.push_back({Vp(r, k), base2 + off[p] + k, 1});
+      o.tend = (int)ht64.size();
       ho.push_back(o);
     }
     // the dot products of a right-hand side share its w: groups of up to
@@ -1280,7 +1289,9 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     const AxpyTerm<double>* terms_d = sm.put(ht64);
     const DotGroup* groups_d = sm.put(hg);
     const double2* one_d = sm.put(&one, 1);
-    if (!cin_d || !cin_s || !cz_d || !cz_s || !cw_d || !cw_s || !outs_d || !terms_d || !groups_d || !one_d) {
+    const int* off_d = sm.put(off);
+    if (!cin_d || !cin_s || !cz_d || !cz_s || !cw_d || !cw_s || !outs_d || !terms_d || !groups_d || !one_d ||
+        !off_d) {
       set_error("internal: descriptor stage too small");
       return LS_E_STATE;
     }
@@ -1314,20 +1325,18 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     LSW_HIP_TRY(launch_mdots(groups_d, ng, np, N, part, coefs + base1, st));
     if (maxterms <= kAxpyDotMaxTerms) {
       // the first pass's update also forms the second pass's dot products
-      // (first-pass term i is dot product i)
-      LSW_HIP_TRY(launch_axpys_dots(outs_d, na, terms_d, coefs, N, np, part, coefs + base2, st));
+      // (first-pass term i is dot product i) and ||w_1||^2
+      LSW_HIP_TRY(launch_axpys_dots(outs_d, na, terms_d, coefs, N, np, part, coefs + base2, st, coefs + base4));
     } else {
-      LSW_HIP_TRY(launch_axpys<double>(outs_d, na, terms_d, coefs, N, st));
+      LSW_HIP_TRY(launch_axpys_norms(outs_d, na, terms_d, coefs, N, part, coefs + base4, st));
       LSW_HIP_TRY(launch_mdots(groups_d, ng, np, N, part, coefs + base2, st));
     }
-    // the second update also forms ||w||^2
-    LSW_HIP_TRY(launch_axpys_norms(outs_d + na, na, terms_d, coefs, N, part, coefs + base3, st));
+    // h^2, then the second update straight into v_{j+1}
+    LSW_HIP_TRY(launch_pythag(coefs + base4, coefs + base2, off_d, na, coefs + base3, st));
+    LSW_HIP_TRY(launch_axpys<double>(outs_d + na, na, terms_d, coefs, N, st));
     hc.resize(base3 + na);
     LSW_HIP_TRY(hipMemcpyAsync(hc.data(), coefs, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
     LSW_HIP_TRY(hipStreamSynchronize(st));
-    // next basis vectors v_{j+1} = w / ||w|| (scale read on the device)
-    ho.clear();
-    ht64.clear();
     std::vector<int> ending;
     for (int p = 0; p < na; ++p) {
       const int r = act[p];
@@ -1362,26 +1371,9 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       s.iters += 1;
       s.j += 1;
       const bool conv = std::abs(s.s[j + 1]) <= tol * s.beta0;
-      if (conv || s.j == rs || s.iters >= max_iters || hn == 0.0) {
-        ending.push_back(r);
-      } else {
-        ht64.push_back({Wb + (size_t)r * N, 0, 0});
-        ho.push_back({Vp(r, s.j), (int)ht64.size() - 1, (int)ht64.size(), 1, base3 + p, 1});
-      }
-    }
-    if (!ho.empty()) {
-      // through the post stage, without waiting: the next step's launches
-      // follow on the same stream
-      Stage& sp = h->stage_post;
-      sp.reset();
-      const AxpyOut* o_d = sp.put(ho);
-      const AxpyTerm<double>* t_d = sp.put(ht64);
-      if (!o_d || !t_d) {
-        set_error("internal: descriptor stage too small");
-        return LS_E_STATE;
-      }
-      LSW_HIP_TRY(sp.flush(st));
-      LSW_HIP_TRY(launch_axpys<double>(o_d, (int)ho.size(), t_d, coefs, N, st));
+      // v_{j+1} is already in V; a right-hand side that ends its cycle here
+      // (or breaks down: h = 0) does not read it
+      if (conv || s.j == rs || s.iters >= max_iters || hn == 0.0) ending.push_back(r);
     }
     if (ending.empty()) continue;
     // cycle end: x += Z y, true residual in float64

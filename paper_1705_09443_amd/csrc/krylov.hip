@@ -159,15 +159,19 @@ __global__ __launch_bounds__(kThreads) void k_axpys(const AxpyOut* __restrict__ 
 // k_axpys for outputs without scale, each of at most KT terms, that also
 // sums conj(x_t) y_o over the updated y_o for every term: the term vectors
 // stay in registers between the update and the products
+// norm_partials (optional): ||y_o||^2 of this block's share of the updated
+// output as well, at norm_partials[o * gridDim.x + blockIdx.x]
 template <int KT>
 __global__ __launch_bounds__(kThreads) void k_axpys_dots(const AxpyOut* __restrict__ outs,
                                                          const AxpyTerm<double>* __restrict__ terms,
                                                          const double2* __restrict__ coefs, size_t N,
-                                                         double2* __restrict__ partials) {
+                                                         double2* __restrict__ partials,
+                                                         double2* __restrict__ norm_partials) {
   const AxpyOut o = outs[blockIdx.y];
   const int cnt = o.tend - o.tbeg;
   const double2* xs[KT];
   double2 c[KT], d[KT];
+  double nrm = 0.0;
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     xs[k] = nullptr;
@@ -199,6 +203,7 @@ __global__ __launch_bounds__(kThreads) void k_axpys_dots(const AxpyOut* __restri
     y.x = y.x + acc.x;
     y.y = y.y + acc.y;
     o.y[i] = y;
+    nrm += y.x * y.x + y.y * y.y;
 #pragma unroll
     for (int k = 0; k < KT; ++k) {
       if (k < cnt) {
@@ -207,7 +212,11 @@ __global__ __launch_bounds__(kThreads) void k_axpys_dots(const AxpyOut* __restri
       }
     }
   }
-  __shared__ double2 ws[KT][kThreads / 64];
+  __shared__ double2 ws[KT + 1][kThreads / 64];
+  if (norm_partials) {
+    const double2 v = wave_sum(make_double2(nrm, 0.0));
+    if ((threadIdx.x & 63) == 0) ws[KT][threadIdx.x >> 6] = v;
+  }
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     if (k < cnt) {
@@ -225,6 +234,23 @@ __global__ __launch_bounds__(kThreads) void k_axpys_dots(const AxpyOut* __restri
     }
     partials[(size_t)(o.tbeg + k) * gridDim.x + blockIdx.x] = s;
   }
+  if (norm_partials && threadIdx.x == 0) {
+    double s = ws[KT][0].x;
+    for (int w = 1; w < kThreads / 64; ++w) s += ws[KT][w].x;
+    norm_partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = make_double2(s, 0.0);
+  }
+}
+
+// h2[p] = norm2[p] - sum over k in [off[p], off[p+1]) of |c[k]|^2: the squared
+// norm of w - V c for an orthonormal V whose products with w are c (in a fixed
+// order, one thread per output)
+__global__ void k_pythag(const double2* __restrict__ norm2, const double2* __restrict__ c,
+                         const int* __restrict__ off, int nout, double2* __restrict__ h2) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= nout) return;
+  double s = norm2[p].x;
+  for (int k = off[p]; k < off[p + 1]; ++k) s -= c[k].x * c[k].x + c[k].y * c[k].y;
+  h2[p] = make_double2(s, 0.0);
 }
 
 template <typename TD, typename TS>
@@ -350,11 +376,22 @@ hipError_t launch_axpys_norms(const AxpyOut* outs, int nout, const AxpyTerm<doub
   return hipGetLastError();
 }
 hipError_t launch_axpys_dots(const AxpyOut* outs, int nout, const AxpyTerm<double>* terms, const double2* coefs,
-                             size_t N, int ndots, double2* partials, double2* dots, hipStream_t st) {
+                             size_t N, int ndots, double2* partials, double2* dots, hipStream_t st,
+                             double2* norm2) {
   if (nout <= 0) return hipSuccess;
+  // the norm partials follow the ndots products' partials
+  double2* np = norm2 ? partials + (size_t)ndots * kAxpyDotBlocks : nullptr;
   hipLaunchKernelGGL(k_axpys_dots<kAxpyDotMaxTerms>, dim3(kAxpyDotBlocks, nout), dim3(kThreads), 0, st, outs, terms,
-                     coefs, N, partials);
+                     coefs, N, partials, np);
   hipLaunchKernelGGL(k_dot_reduce, dim3((ndots + 127) / 128), dim3(128), 0, st, partials, ndots, dots, kAxpyDotBlocks);
+  if (norm2)
+    hipLaunchKernelGGL(k_dot_reduce, dim3((nout + 127) / 128), dim3(128), 0, st, np, nout, norm2, kAxpyDotBlocks);
+  return hipGetLastError();
+}
+hipError_t launch_pythag(const double2* norm2, const double2* c, const int* off, int nout, double2* h2,
+                         hipStream_t st) {
+  if (nout <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pythag, dim3((nout + 127) / 128), dim3(128), 0, st, norm2, c, off, nout, h2);
   return hipGetLastError();
 }
 template hipError_t launch_axpys<double>(const AxpyOut*, int, const AxpyTerm<double>*, const double2*,
