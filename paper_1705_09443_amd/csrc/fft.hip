@@ -111,8 +111,9 @@ template <int R>
 constexpr int kLog2 = R == 2 ? 1 : R == 4 ? 2 : R == 8 ? 3 : 4;
 
 // P, nseq and Ns are powers of two: the index arithmetic is shifts and masks
-template <typename T, int R>
-__device__ inline void lds_fft_pass(C<T>* buf, int P, int nseq, int Ns, const C<T>* twl, bool inv) {
+template <typename T, int R, bool inv>
+__device__ __attribute__((always_inline)) inline void lds_fft_pass(C<T>* buf, int P, int nseq, int Ns,
+                                                                   const C<T>* twl) {
   constexpr int NB = kVals<T> / R;  // butterflies per thread
   constexpr int LR = kLog2<R>;
   const int tid = threadIdx.x, nt = blockDim.x;
@@ -154,14 +155,14 @@ __device__ inline void lds_fft_pass(C<T>* buf, int P, int nseq, int Ns, const C<
 
 // In-place FFT of nseq interleaved length-P sequences (P a power of two);
 // twl: the length-P twiddle table in LDS. Needs blockDim.x >= nseq * P / kVals<T>.
-template <typename T>
-__device__ void lds_fft(C<T>* buf, int P, int nseq, const C<T>* twl, bool inv) {
+template <typename T, bool inv>
+__device__ __attribute__((always_inline)) inline void lds_fft(C<T>* buf, int P, int nseq, const C<T>* twl) {
   int Ns = 1;
-  for (; P / Ns >= 16; Ns *= 16) lds_fft_pass<T, 16>(buf, P, nseq, Ns, twl, inv);
+  for (; P / Ns >= 16; Ns *= 16) lds_fft_pass<T, 16, inv>(buf, P, nseq, Ns, twl);
   const int rem = P / Ns;
-  if (rem == 8) lds_fft_pass<T, 8>(buf, P, nseq, Ns, twl, inv);
-  else if (rem == 4) lds_fft_pass<T, 4>(buf, P, nseq, Ns, twl, inv);
-  else if (rem == 2) lds_fft_pass<T, 2>(buf, P, nseq, Ns, twl, inv);
+  if (rem == 8) lds_fft_pass<T, 8, inv>(buf, P, nseq, Ns, twl);
+  else if (rem == 4) lds_fft_pass<T, 4, inv>(buf, P, nseq, Ns, twl);
+  else if (rem == 2) lds_fft_pass<T, 2, inv>(buf, P, nseq, Ns, twl);
 }
 
 // the twiddle table into LDS (no barrier: the caller's next one covers it);
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_forward(const C<T>* __re
   else
     load_rows<T, false>(buf, xr, m, n, P, S, i0);
   __syncthreads();
-  lds_fft<T>(buf, P, S, twl, false);
+  lds_fft<T, false>(buf, P, S, twl);
   const int ntile = P / S;
   C<T>* Xr = X + (size_t)rhs * ntile * n * S;
   const int lS = ilog2(S);
@@ -289,7 +290,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_col_convolve(C<T>* __restric
     }
   }
   __syncthreads();
-  lds_fft<T>(buf, P, S, twl, false);
+  lds_fft<T, false>(buf, P, S, twl);
   // times khat: k depends on |delta| only, so khat is symmetric and column c
   // of the quadrant is its row c; consecutive threads walk along it
   {
@@ -314,7 +315,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_col_convolve(C<T>* __restric
     }
   }
   __syncthreads();
-  lds_fft<T>(buf, P, S, twl, true);
+  lds_fft<T, true>(buf, P, S, twl);
 #pragma unroll
   for (int q = 0; q < V; ++q) {
     const int idx = threadIdx.x + q * blockDim.x;
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __re
     }
   }
   __syncthreads();
-  lds_fft<T>(buf, P, S, twl, true);
+  lds_fft<T, true>(buf, P, S, twl);
   const size_t nn = (size_t)n * n;
   const int live = S * n;
   const C<T>* xr = xp ? xp[rhs] : x + rhs * nn;
@@ -389,6 +390,290 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __re
   }
 }
 
+// ---- transforms of a compile-time length ------------------------------------
+// For P = 128 ... 4096 the passes are instantiated per length: the plan, the
+// LDS offsets and the lane maps are constants, so the only index arithmetic
+// left is a base address per butterfly. A thread owns butterfly j of
+// sequence s in every pass (bidx = tid + q NT, s = bidx mod S, j = bidx / S),
+// which gives two register-resident steps:
+//  * the first pass (radix 16, stride P/16) takes its inputs straight from
+//    device memory; with zero padding beyond n < P/2 its upper eight inputs
+//    are zero and its first 4-point stage is halved;
+//  * in the last pass (stride P/R) a thread's NB = 16/R butterflies are
+//    j0 + q P/16, so it holds elements j0 + r' P/16, r' < 16: exactly the
+//    inputs of the inverse transform's first pass. The column pass multiplies
+//    them by the spectrum in registers and goes on without an LDS exchange.
+// The twiddles of the pass with stride NS and radix R sit contiguously in
+// LDS at NS - 1 + k (R - 1) + r - 1 (w^(r k P / (NS R)), k < NS, 1 <= r < R):
+// P - 1 values for the whole plan.
+
+constexpr int ct_radix(int P, int NS) { return P / NS >= 16 ? 16 : P / NS; }
+constexpr int ct_log2(int v) { return v <= 1 ? 0 : 1 + ct_log2(v / 2); }
+constexpr bool ct_length(int P) { return P >= 128 && P <= 4096; }
+
+// the twiddles of every pass into LDS (the caller's next barrier covers them)
+template <typename T, int P, int S>
+__device__ __attribute__((always_inline)) inline void ct_twiddles(C<T>* twl, const C<T>* __restrict__ tw) {
+  constexpr int NT = S * P / 16;
+  constexpr int R2 = ct_radix(P, 16), R3 = P > 256 ? ct_radix(P, 256) : 2;
+  for (int e = threadIdx.x; e < P - 1; e += NT) {
+    int m = 0;  // entries of the first pass (stride 1) are never read
+    if (e >= 15 && e < 16 * R2 - 1) {
+      const int l = e - 15, k = l / (R2 - 1), r = l - k * (R2 - 1) + 1;
+      m = r * k * (P / (16 * R2));
+    }
+    if constexpr (P > 256) {
+      if (e >= 255) {
+        const int l = e - 255, k = l / (R3 - 1), r = l - k * (R3 - 1) + 1;
+        m = r * k * (P / (256 * R3));
+      }
+    }
+    twl[e] = tw[m];
+  }
+}
+
+// 16-point DFT (natural order) whose inputs 8..15 are zero: the first
+// 4-point stage of the 4 x 4 decomposition has two inputs per transform
+template <typename T, bool INV>
+__device__ __attribute__((always_inline)) inline void dft16_low(C<T>* x) {
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const C<T> a0 = x[b], a1 = x[b + 4], ra = rot90<T>(a1, INV);
+    x[b] = cadd<T>(a0, a1);
+    x[b + 8] = csub<T>(a0, a1);
+    x[b + 4] = cadd<T>(a0, ra);
+    x[b + 12] = csub<T>(a0, ra);
+  }
+#pragma unroll
+  for (int b = 1; b < 4; ++b)
+#pragma unroll
+    for (int c = 1; c < 4; ++c) x[4 * c + b] = cmul<T>(x[4 * c + b], w16<T>(b * c, INV));
+#pragma unroll
+  for (int c = 0; c < 4; ++c) dft4<T>(x + 4 * c, 1, INV);
+  C<T> y[16];
+#pragma unroll
+  for (int c = 0; c < 4; ++c)
+#pragma unroll
+    for (int d = 0; d < 4; ++d) y[c + 4 * d] = x[4 * c + d];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[k] = y[k];
+}
+
+// inputs of the pass of stride NS from LDS: butterfly (s, j) reads element
+// j + r P/R of sequence s at (j + r P/R) S + s = bidx + r (P/R) S
+template <typename T, int P, int S, int NS>
+__device__ __attribute__((always_inline)) inline void ct_read(const C<T>* buf, C<T> (&v)[16]) {
+  constexpr int R = ct_radix(P, NS), NB = 16 / R, NT = S * P / 16;
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int r = 0; r < R; ++r) v[q * R + r] = buf[threadIdx.x + q * NT + r * (P / R) * S];
+}
+
+// twiddles and R-point DFTs of the pass of stride NS
+template <typename T, int P, int S, int NS, bool INV>
+__device__ __attribute__((always_inline)) inline void ct_bfly(const C<T>* twl, C<T> (&v)[16]) {
+  constexpr int R = ct_radix(P, NS), NB = 16 / R, NT = S * P / 16, LS = ct_log2(S);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    if constexpr (NS > 1) {
+      const int k = ((threadIdx.x + q * NT) >> LS) & (NS - 1);
+      const C<T>* w = twl + (NS - 1) + k * (R - 1);
+#pragma unroll
+      for (int r = 1; r < R; ++r) v[q * R + r] = INV ? cmulc<T>(v[q * R + r], w[r - 1]) : cmul<T>(v[q * R + r], w[r - 1]);
+    }
+    dft<T, R>(&v[q * R], INV);
+  }
+}
+
+// outputs of the pass of stride NS to LDS: element (j / NS) NS R + k + r NS
+template <typename T, int P, int S, int NS>
+__device__ __attribute__((always_inline)) inline void ct_write(C<T>* buf, const C<T> (&v)[16]) {
+  constexpr int R = ct_radix(P, NS), NB = 16 / R, NT = S * P / 16, LS = ct_log2(S);
+  constexpr int LN = ct_log2(NS), LR = ct_log2(R);
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int bidx = threadIdx.x + q * NT, s = bidx & (S - 1), j = bidx >> LS;
+    const int base = ((((j >> LN) << (LN + LR)) + (j & (NS - 1))) << LS) + s;
+#pragma unroll
+    for (int r = 0; r < R; ++r) buf[base + r * NS * S] = v[q * R + r];
+  }
+}
+
+// the passes after the first, from the LDS written by the first pass: every
+// pass but the last writes LDS back; the last leaves its outputs in v
+template <typename T, int P, int S, bool INV, int NS = 16>
+__device__ __attribute__((always_inline)) inline void ct_rest(C<T>* buf, const C<T>* twl, C<T> (&v)[16]) {
+  __syncthreads();
+  ct_read<T, P, S, NS>(buf, v);
+  ct_bfly<T, P, S, NS, INV>(twl, v);
+  if constexpr (NS * ct_radix(P, NS) < P) {
+    __syncthreads();
+    ct_write<T, P, S, NS>(buf, v);
+    ct_rest<T, P, S, INV, NS * 16>(buf, twl, v);
+  }
+}
+
+// stride of the last pass and its radix
+template <int P>
+constexpr int ct_last_ns() { return P > 256 ? 256 : 16; }
+template <int P>
+constexpr int ct_last_radix() { return ct_radix(P, ct_last_ns<P>()); }
+
+// last-pass registers (butterfly q, output r) -> first-pass registers of the
+// next transform (element j0 + r' P/16 at r' = q + r NB)
+template <typename T, int P>
+__device__ __attribute__((always_inline)) inline void ct_regroup(C<T> (&v)[16]) {
+  constexpr int R = ct_last_radix<P>(), NB = 16 / R;
+  C<T> u[16];
+#pragma unroll
+  for (int q = 0; q < NB; ++q)
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[q + r * NB] = v[q * R + r];
+#pragma unroll
+  for (int i = 0; i < 16; ++i) v[i] = u[i];
+}
+
+// pass 1, rows: S rows of (s .* x) zero-padded to P, transformed, written as
+// the tiles [P/S][n][S]
+template <typename T, int P, int S, bool HASM>
+__global__ __launch_bounds__(S * P / 16) void k_row_forward_ct(const C<T>* __restrict__ x, const T* __restrict__ m,
+                                                              int n, const C<T>* __restrict__ tw,
+                                                              C<T>* __restrict__ X, const C<T>* const* __restrict__ xp) {
+  constexpr int LS = ct_log2(S), RL = ct_last_radix<P>(), NBL = 16 / RL;
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+  C<T>* twl = buf + S * P;
+  ct_twiddles<T, P, S>(twl, tw);
+  const int rhs = blockIdx.y, i0 = blockIdx.x * S;
+  const int s = threadIdx.x & (S - 1), j0 = threadIdx.x >> LS, row = i0 + s;
+  const size_t nn = (size_t)n * n;
+  const C<T>* xr = xp ? xp[rhs] : x + rhs * nn;
+  C<T> v[16];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int c = j0 + r * (P / 16);
+    const bool ok = row < n && c < n;
+    const size_t o = ok ? (size_t)row * n + c : 0;
+    C<T> w = gld<T>(xr, o);
+    if (HASM) w = cscale<T>(w, m[o]);
+    v[r] = ok ? w : mk<T>(0, 0);
+  }
+  dft16_low<T, false>(v);
+  ct_write<T, P, S, 1>(buf, v);
+  ct_rest<T, P, S, false>(buf, twl, v);
+  // the last pass's outputs: frequency f = j0 + q P/16 + r P/RL of row i0 + s
+  if (row < n) {
+    C<T>* Xr = X + (size_t)rhs * (P / S) * n * S;
+#pragma unroll
+    for (int q = 0; q < NBL; ++q)
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int f = j0 + q * (P / 16) + r * (P / RL);
+        Xr[((size_t)(f >> LS) * n + row) * S + (f & (S - 1))] = v[q * RL + r];
+      }
+  }
+}
+
+// pass 2, one tile of S columns (blockIdx.y) of right-hand side blockIdx.x:
+// column FFT of the n live rows, times the spectrum, inverse column FFT, the
+// n live rows written back in place
+template <typename T, int P, int S>
+__global__ __launch_bounds__(S * P / 16) void k_col_convolve_ct(C<T>* __restrict__ X, const C<T>* __restrict__ khat,
+                                                               int n, const C<T>* __restrict__ tw) {
+  constexpr int LS = ct_log2(S), RL = ct_last_radix<P>(), NBL = 16 / RL;
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+  C<T>* twl = buf + S * P;
+  ct_twiddles<T, P, S>(twl, tw);
+  const int rhs = blockIdx.x, tile = blockIdx.y;
+  const int s = threadIdx.x & (S - 1), j0 = threadIdx.x >> LS;
+  C<T>* Xt = X + ((size_t)rhs * (P / S) + tile) * n * S;
+  const int live = n * S;
+  C<T> v[16];
+#pragma unroll
+  for (int r = 0; r < 8; ++r) {
+    const int idx = threadIdx.x + r * (P / 16) * S;  // row j0 + r P/16, column s
+    const C<T> w = Xt[idx < live ? idx : 0];
+    v[r] = idx < live ? w : mk<T>(0, 0);
+  }
+  dft16_low<T, false>(v);
+  ct_write<T, P, S, 1>(buf, v);
+  ct_rest<T, P, S, false>(buf, twl, v);
+  ct_regroup<T, P>(v);
+  // times khat: row frequency f = j0 + r P/16; the spectrum is even in both
+  // indices, and its stored quadrant is symmetric (column c is row c)
+  {
+    constexpr int half = P / 2 + 1;
+    const int c = tile * S + s, kc = c <= P - c ? c : P - c;
+    const C<T>* kr = khat + (size_t)kc * half;
+    C<T> kv[16];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) kv[r] = r < 8 ? kr[j0 + r * (P / 16)] : kr[P - j0 - r * (P / 16)];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) v[r] = cmul<T>(v[r], kv[r]);
+  }
+  dft<T, 16>(v, true);
+  __syncthreads();  // every read of the forward transform's last pass is done
+  ct_write<T, P, S, 1>(buf, v);
+  ct_rest<T, P, S, true>(buf, twl, v);
+  // rows j0 + q P/16 + r P/RL; only r < RL/2 can be below n < P/2
+#pragma unroll
+  for (int q = 0; q < NBL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL / 2; ++r) {
+      const int idx = threadIdx.x + (q * (P / 16) + r * (P / RL)) * S;
+      if (idx < live) Xt[idx] = v[q * RL + r];
+    }
+}
+
+// pass 3: S rows gathered from the tiles, inverse FFT, first n entries,
+// epilogue a x + coef (.) to y (or, widened, to y64[rhs])
+template <typename T, int P, int S, bool W64>
+__global__ __launch_bounds__(S * P / 16) void k_row_inverse_ct(const C<T>* __restrict__ X, const C<T>* __restrict__ x,
+                                                              int n, const C<T>* __restrict__ tw, T a, T coef,
+                                                              C<T>* __restrict__ y, double2* const* __restrict__ y64,
+                                                              const C<T>* const* __restrict__ xp) {
+  constexpr int LS = ct_log2(S), RL = ct_last_radix<P>(), NBL = 16 / RL;
+  extern __shared__ unsigned char smem_raw[];
+  C<T>* buf = reinterpret_cast<C<T>*>(smem_raw);
+  C<T>* twl = buf + S * P;
+  ct_twiddles<T, P, S>(twl, tw);
+  const int rhs = blockIdx.y, i0 = blockIdx.x * S;
+  const int s = threadIdx.x & (S - 1), j0 = threadIdx.x >> LS, row = i0 + s;
+  const bool live = row < n;
+  const C<T>* Xr = X + (size_t)rhs * (P / S) * n * S;
+  C<T> v[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int f = j0 + r * (P / 16);
+    const C<T> w = Xr[live ? ((size_t)(f >> LS) * n + row) * S + (f & (S - 1)) : 0];
+    v[r] = live ? w : mk<T>(0, 0);
+  }
+  dft<T, 16>(v, true);
+  ct_write<T, P, S, 1>(buf, v);
+  ct_rest<T, P, S, true>(buf, twl, v);
+  if (!live) return;
+  const size_t nn = (size_t)n * n;
+  const C<T>* xr = xp ? xp[rhs] : x + rhs * nn;
+  // columns j0 + q P/16 + r P/RL; only r < RL/2 can be below n < P/2
+#pragma unroll
+  for (int q = 0; q < NBL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL / 2; ++r) {
+      const int c = j0 + q * (P / 16) + r * (P / RL);
+      if (c < n) {
+        const size_t o = (size_t)row * n + c;
+        C<T> w = cscale<T>(v[q * RL + r], coef);
+        if (a != T(0)) w = cadd<T>(w, cscale<T>(gld<T>(xr, o), a));
+        if (W64)
+          gst<double>(y64[rhs], o, make_double2((double)w.x, (double)w.y));
+        else
+          y[rhs * nn + o] = w;
+      }
+    }
+}
+
 // ---- setup: khat = FFT2 of the wrapped table, quadrant kept ---------------
 __global__ void k_wrap_table(const double2* __restrict__ kq, int n, int P, double2* __restrict__ W) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -412,7 +697,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_rows_full(double2* __res
     buf[k * S + s] = W[(size_t)(r0 + s) * P + k];
   }
   __syncthreads();
-  lds_fft<double>(buf, P, S, twl, false);
+  lds_fft<double, false>(buf, P, S, twl);
   for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
     const int s = idx / P, k = idx % P;
     W[(size_t)(r0 + s) * P + k] = buf[k * S + s];
@@ -432,7 +717,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_fft_cols_full(double2* __res
     buf[idx] = W[(size_t)r * P + c0 + s];
   }
   __syncthreads();
-  lds_fft<double>(buf, P, S, twl, false);
+  lds_fft<double, false>(buf, P, S, twl);
   const int half = P / 2 + 1;
   for (int idx = threadIdx.x; idx < S * P; idx += blockDim.x) {
     const int r = idx / S, s = idx % S;
@@ -483,7 +768,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k3_rows_fwd(const C<T>* __rest
     if (idx < S * P) buf[(idx % P) * S + idx / P] = v[q];
   }
   __syncthreads();
-  lds_fft<T>(buf, P, S, twl, false);
+  lds_fft<T, false>(buf, P, S, twl);
   C<T>* out = w1 + (size_t)rhs * rows * P;
 #pragma unroll
   for (int q = 0; q < V; ++q) {
@@ -529,7 +814,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k3_axis(const C<T>* __restrict
     if (idx < S * P) buf[idx] = v[q];
   }
   __syncthreads();
-  lds_fft<T>(buf, P, S, twl, MODE == 2);
+  lds_fft<T, (MODE == 2)>(buf, P, S, twl);
   if (MODE == 1) {
     // times khat(k1 = t, k2 = o, k3 = c0 + sq), the table even in every axis
     const int H = P / 2 + 1;
@@ -544,7 +829,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k3_axis(const C<T>* __restrict
       }
     }
     __syncthreads();
-    lds_fft<T>(buf, P, S, twl, true);
+    lds_fft<T, true>(buf, P, S, twl);
   }
   C<T>* out = dst + rhs * so.rhs + (size_t)o * so.oth + (size_t)c0 * so.sst;
 #pragma unroll
@@ -583,7 +868,7 @@ __global__ __launch_bounds__(kFftMaxThreads) void k3_rows_inv(const C<T>* __rest
     if (idx < S * P) buf[(idx % P) * S + idx / P] = v[q];
   }
   __syncthreads();
-  lds_fft<T>(buf, P, S, twl, true);
+  lds_fft<T, true>(buf, P, S, twl);
   const size_t n3 = (size_t)rows * n;
 #pragma unroll
   for (int q = 0; q < V; ++q) {
@@ -620,7 +905,7 @@ __global__ void k3_octant(const double2* __restrict__ W, int P, double2* __restr
 }
 
 template <typename T>
-int seq_per_block(int P) {
+constexpr int seq_per_block(int P) {
   int S = (163840 - P * (int)sizeof(C<T>)) / (P * (int)sizeof(C<T>));
   if (S > 8) S = 8;
   if (S * P > kVals<T> * kFftMaxThreads) S = kVals<T> * kFftMaxThreads / P;
@@ -654,11 +939,51 @@ size_t fft_work_elems(int n, int nrhs) {
 template size_t fft_work_elems<double>(int, int);
 template size_t fft_work_elems<float>(int, int);
 
+template <typename T, int P>
+hipError_t launch_convolve_ct(const C<T>* x, const T* m, int n, int nrhs, const C<T>* khat, const C<T>* tw, T a,
+                              T coef, C<T>* work, C<T>* y, hipStream_t st, double2* const* y64,
+                              const C<T>* const* xp) {
+  constexpr int S = seq_per_block<T>(P), NT = S * P / 16;
+  static_assert((S & (S - 1)) == 0 && NT >= 64 && NT <= kFftMaxThreads, "compile-time plan");
+  const size_t lds = (size_t)(S + 1) * P * sizeof(C<T>);
+  hipError_t e;
+  if ((e = allow_lds(k_row_forward_ct<T, P, S, true>, lds)) != hipSuccess) return e;
+  if ((e = allow_lds(k_row_forward_ct<T, P, S, false>, lds)) != hipSuccess) return e;
+  if ((e = allow_lds(k_col_convolve_ct<T, P, S>, lds)) != hipSuccess) return e;
+  if ((e = allow_lds(k_row_inverse_ct<T, P, S, false>, lds)) != hipSuccess) return e;
+  if ((e = allow_lds(k_row_inverse_ct<T, P, S, true>, lds)) != hipSuccess) return e;
+  // the column pass takes right-hand sides fastest: consecutive workgroups
+  // read the same spectrum columns
+  const dim3 grow((n + S - 1) / S, nrhs), gcol(nrhs, P / S);
+  if (m)
+    hipLaunchKernelGGL((k_row_forward_ct<T, P, S, true>), grow, dim3(NT), lds, st, x, m, n, tw, work, xp);
+  else
+    hipLaunchKernelGGL((k_row_forward_ct<T, P, S, false>), grow, dim3(NT), lds, st, x, m, n, tw, work, xp);
+  hipLaunchKernelGGL((k_col_convolve_ct<T, P, S>), gcol, dim3(NT), lds, st, work, khat, n, tw);
+  if (y64)
+    hipLaunchKernelGGL((k_row_inverse_ct<T, P, S, true>), grow, dim3(NT), lds, st, work, x, n, tw, a, coef, y, y64,
+                       xp);
+  else
+    hipLaunchKernelGGL((k_row_inverse_ct<T, P, S, false>), grow, dim3(NT), lds, st, work, x, n, tw, a, coef, y, y64,
+                       xp);
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_convolve(const C<T>* x, const T* m, int n, int nrhs, const C<T>* khat,
                            const C<T>* tw, T a, T c, C<T>* work, C<T>* y, hipStream_t st, double2* const* y64,
                            const C<T>* const* xp) {
   const int P = fft_len(n);
+  const T coef_ct = c / ((T)P * (T)P);
+  switch (P) {
+    case 128: return launch_convolve_ct<T, 128>(x, m, n, nrhs, khat, tw, a, coef_ct, work, y, st, y64, xp);
+    case 256: return launch_convolve_ct<T, 256>(x, m, n, nrhs, khat, tw, a, coef_ct, work, y, st, y64, xp);
+    case 512: return launch_convolve_ct<T, 512>(x, m, n, nrhs, khat, tw, a, coef_ct, work, y, st, y64, xp);
+    case 1024: return launch_convolve_ct<T, 1024>(x, m, n, nrhs, khat, tw, a, coef_ct, work, y, st, y64, xp);
+    case 2048: return launch_convolve_ct<T, 2048>(x, m, n, nrhs, khat, tw, a, coef_ct, work, y, st, y64, xp);
+    case 4096: return launch_convolve_ct<T, 4096>(x, m, n, nrhs, khat, tw, a, coef_ct, work, y, st, y64, xp);
+    default: break;  // shorter lengths: the runtime-length passes below
+  }
   const int S = seq_per_block<T>(P);
   const int nt = threads_for<T>(S, P);
   const size_t lds = (size_t)(S + 1) * P * sizeof(C<T>);
