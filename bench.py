@@ -135,15 +135,20 @@ def interface_map_flops(solver):
 # calibrated on a plain copy of known size) for the 1023^2 64-wave mixed
 # workload at w = 4 with two fronts and the default kernel table (the tuned
 # run keeps w = 4 and may pick other kernels at some batch sizes), keyed by
-# (part, complex bytes, w, fronts); valid only for the kernels as they were
-# when measured (profiles/c2_mixed_64rhs_hbm_counters.md). Per launch at the
-# run's mean columns per launch: sweep 56.3 (one apply: every slice-solve,
-# interface-product and coupling kernel), FFT 45.8 (complex64 launches),
-# Q 56.3.
+# (part, complex bytes of the part's launches, w, fronts); valid only for the
+# kernels as they were when measured (profiles/c2_mixed_64rhs_hbm_counters.md).
+# Per launch at the run's mean columns per launch: sweep 56.3 (one apply:
+# every slice-solve, interface-product and coupling kernel), FFT 56.3
+# (complex64 launches) and 32 (the complex128 launches of the true
+# residuals), Q 56.3.
+# Each entry: (bytes per launch, mean columns per launch of the counter run);
+# a run with another mean is charged the shared bytes of the method's count
+# plus the measured per-column remainder times its own mean.
 MEASURED_TRAFFIC = {
-    ("sweep", 8, 4, 2): 2.2801e10,
-    ("fft_convolve", 8, 4, 2): 7.4507e9,
-    ("stencil_Q", 8, 4, 2): 1.8365e9,
+    ("sweep", 8, 4, 2): (2.2801e10, 56.29),
+    ("fft_convolve", 8, 4, 2): (5.8571e9, 56.29),
+    ("fft_convolve_c128", 16, 4, 2): (6.1987e9, 32.0),
+    ("stencil_Q", 8, 4, 2): (1.8365e9, 56.29),
 }
 
 # published MI355X dense matrix-core peaks (TFLOP/s): fp32 157.3, fp64 78.6
@@ -171,10 +176,13 @@ def rooflines(solver, prof, cbytes: int, n: int, fronts: int = 1):
     L = solver.L
     out = {}
 
-    def traffic(part):
+    def traffic(part, shared, cols, cb=cbytes):
         if n != 1023:
             return None
-        return MEASURED_TRAFFIC.get((part, cbytes, solver.layer_thickness, fronts))
+        t = MEASURED_TRAFFIC.get((part, cb, solver.layer_thickness, fronts))
+        if t is None:
+            return None
+        return shared + (t[0] - shared) * cols / t[1]
 
     it = prof.get("interface")
     ss = prof.get("slice_solves")
@@ -186,7 +194,7 @@ def rooflines(solver, prof, cbytes: int, n: int, fronts: int = 1):
         out["sweep"] = hbm_roofline(
             "sweep apply (Algorithm 2: slice solves, phases A and C, plus the interface graph)",
             "sum over the 2l-1 slice solves of 2 L t^2 s (factors) + columns x (2 w_k + 2 t) L s",
-            sh, pc, cols, avg, traffic("sweep"))
+            sh, pc, cols, avg, traffic("sweep", sh, cols))
         fl, mb = interface_map_flops(solver)
         t_if = it[1] / applies
         out["interface_dense_maps"] = {
@@ -194,19 +202,22 @@ def rooflines(solver, prof, cbytes: int, n: int, fronts: int = 1):
             "flops_per_apply": fl * cols, "map_bytes_per_apply": mb * cbytes, "avg_ms": t_if,
             "achieved_tflops": fl * cols / (t_if * 1e-3) / 1e12, "mfma_peak_tflops": MFMA_PEAK[cbytes],
             "frac_of_mfma_peak": fl * cols / (t_if * 1e-3) / 1e12 / MFMA_PEAK[cbytes]}
-    f = prof.get("fft_convolve")
-    if f:
-        sh, pc = fft_method_bytes(n, cbytes)
-        out["fft_convolve"] = hbm_roofline(
-            "FFT convolution (row forward, column convolve, row inverse)",
-            "(P/2+1)^2 s + columns x ((2s + s/2) N + 4 n P s)", sh, pc, f[2] / f[0], f[1] / f[0],
-            traffic("fft_convolve"))
+    # operator applies in each precision: complex64 (the Arnoldi steps of the
+    # mixed path) and complex128 (true residuals, the float64 path)
+    for part, cb in (("fft_convolve", 8), ("fft_convolve_c128", 16)):
+        f = prof.get(part)
+        if f and f[0]:
+            sh, pc = fft_method_bytes(n, cb)
+            out[part] = hbm_roofline(
+                f"FFT convolution, complex{8 * cb} launches (row forward, column convolve, row inverse)",
+                "(P/2+1)^2 s + columns x ((2s + s/2) N + 4 n P s)", sh, pc, f[2] / f[0], f[1] / f[0],
+                traffic(part, sh, f[2] / f[0], cb))
     q = prof.get("stencil_Q")
     if q:
         sh, pc = stencil_method_bytes(n, L, cbytes)
         out["stencil_Q"] = hbm_roofline(
             "Q stencil", "columns x (s N + s N_ext)", sh, pc, q[2] / q[0], q[1] / q[0],
-            traffic("stencil_Q"))
+            traffic("stencil_Q", sh, q[2] / q[0]))
         # the mixed Arnoldi step hands Q the float64 basis vector: 16-byte reads
         out["stencil_Q"]["frac_at_io_width"] = (
             (q[2] / q[0]) * (16.0 * n * n + cbytes * L * L) / (q[1] / q[0] * 1e-3) / 1e9 / HBM_PEAK_GBS)

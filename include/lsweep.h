@@ -200,11 +200,12 @@ ls_status ls_apply_A(ls_handle* h, const void* x_dev, int nrhs, void* y_dev, int
  * For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the same
  * y = (I + omega^2 K M) x as ls_apply_A on a 2D handle, with the FFT work
- * array (nrhs x P x n complex values, P = fft length) taken from a static
+ * array (nrhs x P x n8 complex values, P = fft length, n8 = n rounded up to
+ * a multiple of 8) taken from a static
  * array of 64 MiB in the library's device memory, one per GPU, held until
  * the process ends. The call allocates nothing (no hipMalloc, hipFree or
  * allocating library routine); the caller passes x and y as for ls_apply_A.
- *   Limit: nrhs x P x n x (16 B for LS_FP64, 8 B for LS_MIXED) <= 64 MiB, so
+ *   Limit: nrhs x P x n8 x (16 B for LS_FP64, 8 B for LS_MIXED) <= 64 MiB, so
  *   at n = 1023 (P = 2048) at most 2 right-hand sides in complex128 and 4 in
  *   complex64; larger batches return LS_E_INVALID with the limit in the
  *   message. 3D handles return LS_E_INVALID.
@@ -352,8 +353,11 @@ ls_status ls_set_kernels(ls_handle* h, int nrhs, int slice_kernel, int iface_ker
 /* ---- Kernel timing (HIP events recorded on the handle's stream) ---- */
 
 typedef struct {
-  char name[32];      /* "fft_convolve", "stencil_Q", "slice_solves", "interface",
-                         "extract", "sweep" (sequential schedule) */
+  char name[32];      /* "fft_convolve" (complex64 operator applies),
+                         "fft_convolve_c128" (complex128 ones), "stencil_Q",
+                         "slice_solves", "slice_solves_last", "interface",
+                         "extract", "factor", "block_gram", "block_update",
+                         "sweep" (sequential schedule) */
   int launches;       /* launches recorded since profiling was enabled */
   double total_ms;    /* summed event-to-event durations */
   long long columns;  /* right-hand-side columns processed, summed over launches */

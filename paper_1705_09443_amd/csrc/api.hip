@@ -299,11 +299,12 @@ enum KernelKind {
   kKSlicesLast,
   kKGram,
   kKGramUpd,
+  kKFft64,
   kKNumKinds
 };
 const char* kKindNames[kKNumKinds] = {"sweep",        "fft_convolve",      "stencil_Q",  "extract",
                                       "factor",       "slice_solves",      "interface",  "slice_solves_last",
-                                      "block_gram",   "block_update"};
+                                      "block_gram",   "block_update",      "fft_convolve_c128"};
 
 hipEvent_t take_event(ls_handle* h) {
   if (!h->pool.empty()) {
@@ -500,7 +501,7 @@ template <typename T>
 // y64, xp (2D only): per-right-hand-side output (float64) and input grids
 ls_status apply_A(ls_handle* h, const C<T>* x, int nb, C<T>* y, double2* const* y64 = nullptr,
                   const C<T>* const* xp = nullptr) {
-  Timed tm(h, kKFft, nb);
+  Timed tm(h, sizeof(T) == sizeof(float) ? kKFft : kKFft64, nb);
   if (h->dim == 3) {
     if (y64 || xp) {
       set_error("internal: per-right-hand-side grids in a 3D operator apply");

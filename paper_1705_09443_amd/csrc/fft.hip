@@ -409,7 +409,10 @@ __global__ __launch_bounds__(kFftMaxThreads) void k_row_inverse(const C<T>* __re
 
 constexpr int ct_radix(int P, int NS) { return P / NS >= 16 ? 16 : P / NS; }
 constexpr int ct_log2(int v) { return v <= 1 ? 0 : 1 + ct_log2(v / 2); }
-constexpr bool ct_length(int P) { return P >= 128 && P <= 4096; }
+// rows per tile of the row transforms [P/S][ct_rows(n)][S]: n rounded up to
+// a multiple of 8, so that every S x S block (S <= 8) starts a cache line
+// (with n odd, half the tiles would otherwise straddle two lines per block)
+__host__ __device__ constexpr int ct_rows(int n) { return (n + 7) & ~7; }
 
 // the twiddles of every pass into LDS (the caller's next barrier covers them)
 template <typename T, int P, int S>
@@ -564,13 +567,14 @@ __global__ __launch_bounds__(S * P / 16) void k_row_forward_ct(const C<T>* __res
   ct_rest<T, P, S, false>(buf, twl, v);
   // the last pass's outputs: frequency f = j0 + q P/16 + r P/RL of row i0 + s
   if (row < n) {
-    C<T>* Xr = X + (size_t)rhs * (P / S) * n * S;
+    const int np = ct_rows(n);
+    C<T>* Xr = X + (size_t)rhs * (P / S) * np * S;
 #pragma unroll
     for (int q = 0; q < NBL; ++q)
 #pragma unroll
       for (int r = 0; r < RL; ++r) {
         const int f = j0 + q * (P / 16) + r * (P / RL);
-        Xr[((size_t)(f >> LS) * n + row) * S + (f & (S - 1))] = v[q * RL + r];
+        Xr[((size_t)(f >> LS) * np + row) * S + (f & (S - 1))] = v[q * RL + r];
       }
   }
 }
@@ -588,8 +592,20 @@ __global__ __launch_bounds__(S * P / 16) void k_col_convolve_ct(C<T>* __restrict
   ct_twiddles<T, P, S>(twl, tw);
   const int rhs = blockIdx.x, tile = blockIdx.y;
   const int s = threadIdx.x & (S - 1), j0 = threadIdx.x >> LS;
-  C<T>* Xt = X + ((size_t)rhs * (P / S) + tile) * n * S;
+  C<T>* Xt = X + ((size_t)rhs * (P / S) + tile) * ct_rows(n) * S;
   const int live = n * S;
+  // the spectrum values this thread multiplies by, loaded before the forward
+  // transform so that their latency hides behind it: row frequency
+  // f = j0 + r P/16; the spectrum is even in both indices, and its stored
+  // quadrant is symmetric (column c is row c)
+  C<T> kv[16];
+  {
+    constexpr int half = P / 2 + 1;
+    const int c = tile * S + s, kc = c <= P - c ? c : P - c;
+    const C<T>* kr = khat + (size_t)kc * half;
+#pragma unroll
+    for (int r = 0; r < 16; ++r) kv[r] = r < 8 ? kr[j0 + r * (P / 16)] : kr[P - j0 - r * (P / 16)];
+  }
   C<T> v[16];
 #pragma unroll
   for (int r = 0; r < 8; ++r) {
@@ -601,18 +617,8 @@ __global__ __launch_bounds__(S * P / 16) void k_col_convolve_ct(C<T>* __restrict
   ct_write<T, P, S, 1>(buf, v);
   ct_rest<T, P, S, false>(buf, twl, v);
   ct_regroup<T, P>(v);
-  // times khat: row frequency f = j0 + r P/16; the spectrum is even in both
-  // indices, and its stored quadrant is symmetric (column c is row c)
-  {
-    constexpr int half = P / 2 + 1;
-    const int c = tile * S + s, kc = c <= P - c ? c : P - c;
-    const C<T>* kr = khat + (size_t)kc * half;
-    C<T> kv[16];
 #pragma unroll
-    for (int r = 0; r < 16; ++r) kv[r] = r < 8 ? kr[j0 + r * (P / 16)] : kr[P - j0 - r * (P / 16)];
-#pragma unroll
-    for (int r = 0; r < 16; ++r) v[r] = cmul<T>(v[r], kv[r]);
-  }
+  for (int r = 0; r < 16; ++r) v[r] = cmul<T>(v[r], kv[r]);
   dft<T, 16>(v, true);
   __syncthreads();  // every read of the forward transform's last pass is done
   ct_write<T, P, S, 1>(buf, v);
@@ -642,21 +648,33 @@ __global__ __launch_bounds__(S * P / 16) void k_row_inverse_ct(const C<T>* __res
   const int rhs = blockIdx.y, i0 = blockIdx.x * S;
   const int s = threadIdx.x & (S - 1), j0 = threadIdx.x >> LS, row = i0 + s;
   const bool live = row < n;
-  const C<T>* Xr = X + (size_t)rhs * (P / S) * n * S;
+  const int np = ct_rows(n);
+  const C<T>* Xr = X + (size_t)rhs * (P / S) * np * S;
   C<T> v[16];
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int f = j0 + r * (P / 16);
-    const C<T> w = Xr[live ? ((size_t)(f >> LS) * n + row) * S + (f & (S - 1)) : 0];
+    const C<T> w = Xr[live ? ((size_t)(f >> LS) * np + row) * S + (f & (S - 1)) : 0];
     v[r] = live ? w : mk<T>(0, 0);
   }
+  // x at this thread's outputs, loaded before the transform: columns
+  // j0 + q P/16 + r P/RL; only r < RL/2 can be below n < P/2
+  const size_t nn = (size_t)n * n;
+  const C<T>* xr = xp ? xp[rhs] : x + rhs * nn;
+  C<T> xv[NBL][RL / 2];
+#pragma unroll
+  for (int q = 0; q < NBL; ++q)
+#pragma unroll
+    for (int r = 0; r < RL / 2; ++r) {
+      const int c = j0 + q * (P / 16) + r * (P / RL);
+      const bool ok = live && c < n && a != T(0);
+      const C<T> w = gld<T>(xr, ok ? (size_t)row * n + c : 0);
+      xv[q][r] = ok ? w : mk<T>(0, 0);
+    }
   dft<T, 16>(v, true);
   ct_write<T, P, S, 1>(buf, v);
   ct_rest<T, P, S, true>(buf, twl, v);
   if (!live) return;
-  const size_t nn = (size_t)n * n;
-  const C<T>* xr = xp ? xp[rhs] : x + rhs * nn;
-  // columns j0 + q P/16 + r P/RL; only r < RL/2 can be below n < P/2
 #pragma unroll
   for (int q = 0; q < NBL; ++q)
 #pragma unroll
@@ -665,7 +683,7 @@ __global__ __launch_bounds__(S * P / 16) void k_row_inverse_ct(const C<T>* __res
       if (c < n) {
         const size_t o = (size_t)row * n + c;
         C<T> w = cscale<T>(v[q * RL + r], coef);
-        if (a != T(0)) w = cadd<T>(w, cscale<T>(gld<T>(xr, o), a));
+        if (a != T(0)) w = cadd<T>(w, cscale<T>(xv[q][r], a));
         if (W64)
           gst<double>(y64[rhs], o, make_double2((double)w.x, (double)w.y));
         else
@@ -934,7 +952,7 @@ hipError_t allow_lds(K kernel, size_t bytes) {
 template <typename T>
 size_t fft_work_elems(int n, int nrhs) {
   const int P = fft_len(n);
-  return (size_t)nrhs * P * n;
+  return (size_t)nrhs * P * ct_rows(n);
 }
 template size_t fft_work_elems<double>(int, int);
 template size_t fft_work_elems<float>(int, int);

@@ -584,23 +584,31 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(IfaceProds<T> ps, int L,
     load4(Mr + (size_t)bc * 256, ad);
     load4(Bc + 16 * bc, bd);
   };
+  auto block = [&](const C<T>* ad, const C<T>* bd) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const T A = ad[j].x, B = ad[j].y, c = bd[j].x, d = bd[j].y;
+      p1 = Mfma<T>::op(A, c + d, p1);
+      p2 = Mfma<T>::op(A + B, d, p2);
+      p3 = Mfma<T>::op(B - A, c, p3);
+    }
+  };
+  // whole groups of PF blocks with no branch inside, then the remaining
+  // blocks, already loaded by the last group (a branch per block measured
+  // 9 % slower per chain step: 15.8 against 14.4 us at L = 1047, 64 columns)
+  const int full = (b1 - b0) / PF * PF;
 #pragma unroll
   for (int s = 0; s < PF; ++s) load(a[s], bv[s], b0 + s);
-  for (int i = b0; i < b1; i += PF) {
+  for (int i = b0; i < b0 + full; i += PF) {
 #pragma unroll
     for (int s = 0; s < PF; ++s) {
-      if (i + s < b1) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const T A = a[s][j].x, B = a[s][j].y, c = bv[s][j].x, d = bv[s][j].y;
-          p1 = Mfma<T>::op(A, c + d, p1);
-          p2 = Mfma<T>::op(A + B, d, p2);
-          p3 = Mfma<T>::op(B - A, c, p3);
-        }
-      }
+      block(a[s], bv[s]);
       load(a[s], bv[s], i + s + PF);
     }
   }
+#pragma unroll
+  for (int s = 0; s < PF - 1; ++s)
+    if (b0 + full + s < b1) block(a[s], bv[s]);
 #pragma unroll
   for (int j = 0; j < 4; ++j) red[wave][Mfma<T>::out_row(g4, j)][li] = mk<T>(p1[j] - p2[j], p1[j] + p3[j]);
   __syncthreads();

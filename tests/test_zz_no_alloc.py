@@ -53,7 +53,7 @@ def test_noalloc_refuses_batches_beyond_the_scratch():
     with LSSolver(torch.as_tensor(m).cuda(), omega, 12, 4, precision="mixed") as s:
         x = torch.zeros((5, n, n), dtype=torch.complex64, device="cuda")
         y = torch.empty_like(x)
-        # 2048 x 1023 x 8 B = 16.0 MiB per right-hand side: 4 fit in 64 MiB, 5 do not
+        # 2048 x 1024 x 8 B = 16.0 MiB per right-hand side (rows padded to 1024): 4 fit in 64 MiB, 5 do not
         st = lib.ls_apply_A_noalloc(s._h, x.data_ptr(), 5, y.data_ptr(), _lib.LS_MIXED)
         assert st == _lib.LS_E_INVALID
         msg = lib.ls_last_error().decode()
