@@ -72,6 +72,19 @@ __device__ inline void lds_barrier() {
 void set_error(const std::string& msg);
 const char* get_error();
 
+// v stored at byte offset off of the buffer rs; an offset past the buffer's
+// size (the hardware's range check) drops the store, with no branch
+template <typename T>
+__device__ inline void store_or_drop(__amdgpu_buffer_rsrc_t rs, int off, C<T> v) {
+  if constexpr (sizeof(C<T>) == 8) {
+    typedef unsigned u2 __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, 0, 0);
+  } else {
+    typedef unsigned u4 __attribute__((ext_vector_type(4)));
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), rs, off, 0, 0);
+  }
+}
+
 }  // namespace lsw
 
 #define LSW_HIP_TRY(expr)                                                          \

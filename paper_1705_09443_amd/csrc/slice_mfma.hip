@@ -153,46 +153,72 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
     return rok[cc] ? v : mk<T>(0, 0);
   };
 
-  // outputs: per row held by this lane, its destination line (null if none) and
-  // the step stride; lines mode may send one row to both E and F
-  C<T>* dp[RT][4];
-  C<T>* dq[RT][4];
-  size_t ds = 1;
+  // outputs: per row held by this lane, the byte offsets of its destination
+  // in the E (or only) and F buffers (lines mode may send one row to both)
+  // and their step strides. A row with no destination has an offset past the
+  // buffers' size and stride 0: the range-checked store drops it, so the
+  // steps store with no branch.
+  constexpr int kNone = -16;  // 0xfffffff0 as the hardware's unsigned offset
+  const int cs = (int)sizeof(C<T>);
+  int op[RT][4], oq[RT][4], sp[RT][4], sq[RT][4];
+  const C<T>* bp = A.dst;
+  const C<T>* bq = A.dst;
   {
     const bool lines = A.dst_kind == kDstLines;
     const size_t ci = UNIT ? (size_t)(A.col0 + n) : (size_t)n;
-    if (lines) ds = A.sj;
-    if (A.dst_kind == kDstGrid) ds = A.nrhs;
+    // grid mode: offsets from the lowest grid line of D_k
+    const int lmin = org + b + (dir > 0 ? naux : dir * (naux + tw - 1));
+    if (A.dst_kind == kDstGrid) bp = A.dst + (size_t)lmin * L * A.nrhs;
+    if (lines) {
+      if (A.dstE) bp = A.dstE + k * A.sk;
+      if (A.dstF) bq = A.dstF + k * A.sk;
+    }
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const int a = r * 16 + MF<T>::rowof(g, i);
-        C<T>* p0 = nullptr;
-        C<T>* p1 = nullptr;
+        int o0 = kNone, o1 = kNone, s0 = 0, s1 = 0;
         if (valid && a < t) {
           const bool inD = a >= naux && a < naux + tw;
           if (A.dst_kind == kDstGrid) {
-            if (inD) p0 = A.dst + (size_t)(org + dir * a + b) * L * A.nrhs + n;
+            if (inD) {
+              o0 = (((org + dir * a + b) - lmin) * L * A.nrhs + n) * cs;
+              s0 = A.nrhs * cs;
+            }
           } else if (A.dst_kind == kDstSlice) {
-            if (inD) p0 = A.dst + ((size_t)n * tw + (dir > 0 ? a - naux : tw - 1 - (a - naux))) * L;
+            if (inD) {
+              o0 = ((n * tw + (dir > 0 ? a - naux : tw - 1 - (a - naux))) * L) * cs;
+              s0 = cs;
+            }
           } else {
-            if (a == naux + tw - 1 && A.dstE) p0 = A.dstE + k * A.sk + ci * A.sr;
-            if (a == naux && A.dstF) p1 = A.dstF + k * A.sk + ci * A.sr;
+            if (a == naux + tw - 1 && A.dstE) {
+              o0 = (int)(ci * A.sr) * cs;
+              s0 = (int)A.sj * cs;
+            }
+            if (a == naux && A.dstF) {
+              o1 = (int)(ci * A.sr) * cs;
+              s1 = (int)A.sj * cs;
+            }
           }
         }
-        dp[r][i] = p0;
-        dq[r][i] = p1;
+        op[r][i] = o0;
+        oq[r][i] = o1;
+        sp[r][i] = s0;
+        sq[r][i] = s1;
       }
   }
+  const __amdgpu_buffer_rsrc_t rsp = __builtin_amdgcn_make_buffer_rsrc(const_cast<C<T>*>(bp), 0, 0x7fffffff, 0x00020000);
+  const __amdgpu_buffer_rsrc_t rsq = __builtin_amdgcn_make_buffer_rsrc(const_cast<C<T>*>(bq), 0, 0x7fffffff, 0x00020000);
+  const bool twoq = A.dst_kind == kDstLines && A.dstF;
   auto emit = [&](int j, const V* xR, const V* xI) {
 #pragma unroll
     for (int r = 0; r < RT; ++r)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
         const C<T> x = mk<T>(xR[r][i], xI[r][i]);
-        if (dp[r][i]) dp[r][i][(size_t)j * ds] = x;
-        if (dq[r][i]) dq[r][i][(size_t)j * ds] = x;
+        store_or_drop<T>(rsp, op[r][i] + j * sp[r][i], x);
+        if (twoq) store_or_drop<T>(rsq, oq[r][i] + j * sq[r][i], x);
       }
   };
 
@@ -278,40 +304,47 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
         for (int i = 0; i < 8; ++i) yv[s][r][i] = yp[i];
       }
     };
+    // X_j = Y_j - G_j X_{j+1} from ring slot s
+    auto step = [&](int s, int j) {
+      // start from Y_j: Re = q1 - q2 = Re Y, Im = q1 + q3 = Im Y
+      V q1[RT], q2[RT], q3[RT];
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        q1[r] = V{0, 0, 0, 0};
+        q2[r] = -V{yv[s][r][0], yv[s][r][1], yv[s][r][2], yv[s][r][3]};
+        q3[r] = V{yv[s][r][4], yv[s][r][5], yv[s][r][6], yv[s][r][7]};
+      }
+#pragma unroll
+      for (int kt = 0; kt < RT; ++kt) {
+        const V ps = pR[kt] + pI[kt];
+#pragma unroll
+        for (int r = 0; r < RT; ++r)
+#pragma unroll
+          for (int i = 0; i < 4; ++i)  // stored as -G
+            cmac<T>(gv[s][r * RT + kt][i], pR[kt][i], pI[kt][i], ps[i], q1[r], q2[r], q3[r]);
+      }
+#pragma unroll
+      for (int r = 0; r < RT; ++r) {
+        pR[r] = q1[r] - q2[r];
+        pI[r] = q1[r] + q3[r];
+      }
+      emit(j, pR, pI);
+    };
+    // steps L-2 .. 0: whole groups of PB with no branch inside, then the
+    // remaining steps, already loaded by the last group
+    const int full = (L - 1) / PB * PB;
 #pragma unroll
     for (int s = 0; s < PB; ++s) load(s, L - 2 - s);
-    for (int j0 = L - 2; j0 >= 0; j0 -= PB) {
+    for (int j0 = L - 2; j0 > L - 2 - full; j0 -= PB) {
 #pragma unroll
       for (int s = 0; s < PB; ++s) {
-        const int j = j0 - s;
-        if (j >= 0) {
-          // start from Y_j: Re = q1 - q2 = Re Y, Im = q1 + q3 = Im Y
-          V q1[RT], q2[RT], q3[RT];
-#pragma unroll
-          for (int r = 0; r < RT; ++r) {
-            q1[r] = V{0, 0, 0, 0};
-            q2[r] = -V{yv[s][r][0], yv[s][r][1], yv[s][r][2], yv[s][r][3]};
-            q3[r] = V{yv[s][r][4], yv[s][r][5], yv[s][r][6], yv[s][r][7]};
-          }
-#pragma unroll
-          for (int kt = 0; kt < RT; ++kt) {
-            const V ps = pR[kt] + pI[kt];
-#pragma unroll
-            for (int r = 0; r < RT; ++r)
-#pragma unroll
-              for (int i = 0; i < 4; ++i)  // stored as -G
-                cmac<T>(gv[s][r * RT + kt][i], pR[kt][i], pI[kt][i], ps[i], q1[r], q2[r], q3[r]);
-          }
-#pragma unroll
-          for (int r = 0; r < RT; ++r) {
-            pR[r] = q1[r] - q2[r];
-            pI[r] = q1[r] + q3[r];
-          }
-          emit(j, pR, pI);
-        }
-        load(s, j - PB);
+        step(s, j0 - s);
+        load(s, j0 - s - PB);
       }
     }
+#pragma unroll
+    for (int s = 0; s < PB - 1; ++s)
+      if (L - 2 - full - s >= 0) step(s, L - 2 - full - s);
   }
 }
 
@@ -373,6 +406,9 @@ template hipError_t launch_mfma_factors<float>(const SliceTables&, int, int, int
 template <typename T>
 hipError_t launch_slice_mfma(const SliceMfmaArgs<T>& a, int nslices, hipStream_t st) {
   const int nq = (a.nrhs + 15) / 16;
+  // the output stores address a slice's lines (at most 32, plus the column
+  // and step terms) with 32-bit byte offsets
+  if ((size_t)34 * a.L * a.nrhs * sizeof(C<T>) >= ((size_t)1 << 31) - 4096) return hipErrorInvalidValue;
   if (a.src_kind >= kSrcUnitF)
     hipLaunchKernelGGL((k_slice_mfma<T, true>), dim3((nq + 3) / 4, nslices), dim3(256), 0, st, a);
   else

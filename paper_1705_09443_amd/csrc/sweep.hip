@@ -125,19 +125,6 @@ constexpr int kQCols = 66;                          // 64 outputs + 2 halo colum
 constexpr int kQLoads = (16 * kQCols + 255) / 256;  // input loads per thread and row
 constexpr int kQRingRows = kQLoads * 256 / kQCols + 1;  // every load slot has a place
 
-// v stored at byte offset off of the buffer rs; an offset past the buffer's
-// size (the hardware's range check) drops the store, with no branch
-template <typename T>
-__device__ inline void store_or_drop(__amdgpu_buffer_rsrc_t rs, int off, C<T> v) {
-  if constexpr (sizeof(C<T>) == 8) {
-    typedef unsigned u2 __attribute__((ext_vector_type(2)));
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u2, v), rs, off, 0, 0);
-  } else {
-    typedef unsigned u4 __attribute__((ext_vector_type(4)));
-    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), rs, off, 0, 0);
-  }
-}
-
 template <typename T, bool R64>
 __global__ __launch_bounds__(256) void k_apply_Q_il(StencilTables S, const C<T>* __restrict__ r, int nrhs,
                                                     C<T>* __restrict__ f, const double2* const* __restrict__ r64) {
