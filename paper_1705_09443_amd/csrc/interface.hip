@@ -420,29 +420,56 @@ __global__ __launch_bounds__((slice_threads<T, W>())) void k_slice_solve(SliceSo
 
 // ---- interface recurrences: y = add - M x for a batch of right-hand sides --
 // The L x L maps are stored in the operand order of the matrix-core product:
-// slice k is [row tile r][contraction block b][lane l][4], 16 x 16 complex
-// values per (r, b), zero-padded to whole tiles, with lane l holding row
-// 16 r + l % 16 and the 4 consecutive columns 16 b + 4 (l / 16) + j. One
-// (r, b) block is then one contiguous 64-lane operand load, and the padding
-// removes every bounds test on M. x, add, y: [nrhs][Lp] per slice.
+// slice k is [row tile r][contraction block b], 16 x 16 complex values per
+// (r, b), zero-padded to whole tiles. Lane l of a block holds row
+// 16 r + l % 16 and the 4 columns 16 b + iface_k(l / 16, j), j = 0..3, in
+// 16-byte chunks (2 complex64 or 1 complex128), chunk c of every lane side by
+// side: each 16-byte load of the wave reads one contiguous kilobyte. The
+// contraction index within a block is permuted so that a lane's chunk c
+// holds consecutive indices, and the four lane groups' chunks c are
+// consecutive: the same loads of x then read contiguous runs of each column.
+// The padding removes every bounds test on M. x, add, y: [nrhs][Lp] per slice.
+template <typename T>
+__host__ __device__ constexpr int iface_ch() { return 16 / (int)sizeof(C<T>); }
+// contraction index (within a 16-block) of lane group g4's j-th value
+template <typename T>
+__host__ __device__ constexpr int iface_k(int g4, int j) {
+  return (j / iface_ch<T>()) * 4 * iface_ch<T>() + g4 * iface_ch<T>() + j % iface_ch<T>();
+}
+// position of lane l's j-th value within its 256-value block
+template <typename T>
+__host__ __device__ constexpr int iface_pos(int l, int j) {
+  return ((j / iface_ch<T>()) * 64 + l) * iface_ch<T>() + j % iface_ch<T>();
+}
 __host__ __device__ inline int iface_tiles(int L) { return (L + 15) / 16; }
 // x, add, y rows (one per right-hand side) are padded to whole 16-blocks:
 // [nrhs][Lp] per slice, with zeros in [L, Lp) that nothing writes. (The
 // transposed layout, right-hand side fastest, measured slower in the chain.)
 __host__ __device__ inline int iface_vec_len(int L) { return 16 * iface_tiles(L); }
 
-// 4 consecutive complex values from a 32-byte (float) or 16-byte (double)
-// aligned address, as whole 16-byte loads
-__device__ __attribute__((always_inline)) inline void load4(const float2* p, float2* out) {
-  const float4 u = reinterpret_cast<const float4*>(p)[0], v = reinterpret_cast<const float4*>(p)[1];
+// lane's 4 values of one map block (laid out by iface_pos), whole 16-byte loads
+__device__ __attribute__((always_inline)) inline void load_m4(const float2* blk, int lane, float2* out) {
+  const float4 u = reinterpret_cast<const float4*>(blk)[lane], v = reinterpret_cast<const float4*>(blk)[64 + lane];
   out[0] = make_float2(u.x, u.y);
   out[1] = make_float2(u.z, u.w);
   out[2] = make_float2(v.x, v.y);
   out[3] = make_float2(v.z, v.w);
 }
-__device__ __attribute__((always_inline)) inline void load4(const double2* p, double2* out) {
+__device__ __attribute__((always_inline)) inline void load_m4(const double2* blk, int lane, double2* out) {
 #pragma unroll
-  for (int j = 0; j < 4; ++j) out[j] = p[j];
+  for (int j = 0; j < 4; ++j) out[j] = blk[j * 64 + lane];
+}
+// lane group g4's 4 values of one 16-block of a column of x (indices iface_k)
+__device__ __attribute__((always_inline)) inline void load_x4(const float2* col, int g4, float2* out) {
+  const float4 u = reinterpret_cast<const float4*>(col)[g4], v = reinterpret_cast<const float4*>(col)[4 + g4];
+  out[0] = make_float2(u.x, u.y);
+  out[1] = make_float2(u.z, u.w);
+  out[2] = make_float2(v.x, v.y);
+  out[3] = make_float2(v.z, v.w);
+}
+__device__ __attribute__((always_inline)) inline void load_x4(const double2* col, int g4, double2* out) {
+#pragma unroll
+  for (int j = 0; j < 4; ++j) out[j] = col[4 * j + g4];
 }
 
 template <typename T>
@@ -453,8 +480,10 @@ __global__ void k_swizzle_maps(const C<T>* __restrict__ src, C<T>* __restrict__ 
   const size_t per = (size_t)nt * nt * 256;
   const size_t k = e / per, rem = e % per;
   const int r = (int)(rem / ((size_t)nt * 256)), b = (int)((rem / 256) % nt);
-  const int l = (int)((rem / 4) % 64), j = (int)(rem % 4);
-  const int row = 16 * r + (l & 15), col = 16 * b + 4 * (l >> 4) + j;
+  constexpr int ch = iface_ch<T>();
+  const int in = (int)(rem % 256);
+  const int l = (in / ch) % 64, j = in / (64 * ch) * ch + in % ch;  // iface_pos<T>(l, j) == in
+  const int row = 16 * r + (l & 15), col = 16 * b + iface_k<T>(l >> 4, j);
   dst[e] = (row < L && col < L) ? src[(k * L + row) * (size_t)L + col] : mk<T>(0, 0);
 }
 
@@ -473,7 +502,7 @@ __global__ __launch_bounds__(64 * NW) void k_iface_gemv(IfaceProds<T> ps, int L,
   const int r = blockIdx.x;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g4 = lane >> 4;
   const int Lp = iface_vec_len(L);
-  const C<T>* Mr = pr.M + (size_t)r * nt * 256 + lane * 4;
+  const C<T>* Mr = pr.M + (size_t)r * nt * 256;
   const C<T>* xk = pr.x;
   C<T> acc[4];
 #pragma unroll
@@ -483,7 +512,7 @@ __global__ __launch_bounds__(64 * NW) void k_iface_gemv(IfaceProds<T> ps, int L,
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
       const int b = min(b0 + i * NW, nt - 1);  // clamped: blocks past the end are loaded, not used
-      load4(Mr + (size_t)b * 256, a[i]);
+      load_m4(Mr + (size_t)b * 256, lane, a[i]);
     }
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
@@ -493,7 +522,7 @@ __global__ __launch_bounds__(64 * NW) void k_iface_gemv(IfaceProds<T> ps, int L,
         for (int q = 0; q < 4; ++q) {
           if (q < nrhs) {
             C<T> xv[4];
-            load4(xk + (size_t)q * Lp + 16 * b + 4 * g4, xv);
+            load_x4(xk + (size_t)q * Lp + 16 * b, g4, xv);
 #pragma unroll
             for (int j = 0; j < 4; ++j) acc[q] = cfma<T>(acc[q], a[i][j], xv[j]);
           }
@@ -527,7 +556,7 @@ __global__ __launch_bounds__(64 * NW) void k_iface_gemv(IfaceProds<T> ps, int L,
 // with M = A + iB and x = c + id, P1 = A (c + d), P2 = (A + B) d and
 // P3 = (B - A) c give Re = P1 - P2 and Im = P1 + P3), the sums and differences
 // formed on the vector ALUs. In the j-th MFMA of a block, lane l supplies
-// column 4 (l / 16) + j of M's row l % 16 and the same contraction index of
+// column iface_k(l / 16, j) of M's row l % 16 and the same contraction index of
 // x's column l % 16: the index is permuted the same way in both operands,
 // which leaves the sum unchanged. A wave keeps PF blocks of loads in flight
 // ahead of its MFMAs. Tiles of one row block share M's rows; they go to
@@ -571,9 +600,9 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(IfaceProds<T> ps, int L,
   if (r >= nt) return;  // whole workgroup: the grid is rounded up to 8 row blocks
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, li = lane & 15, g4 = lane >> 4;
   const int Lp = iface_vec_len(L);
-  const C<T>* Mr = pr.M + (size_t)r * nt * 256 + lane * 4;
+  const C<T>* Mr = pr.M + (size_t)r * nt * 256;
   // columns past nrhs read the last one: their outputs are not stored
-  const C<T>* Bc = pr.x + (size_t)min(q * 16 + li, nrhs - 1) * Lp + 4 * g4;
+  const C<T>* Bc = pr.x + (size_t)min(q * 16 + li, nrhs - 1) * Lp;
   // this wave's contraction blocks: an even share [b0, b1)
   const int b0 = wave * nt / NW, b1 = (wave + 1) * nt / NW;
   V p1 = {0, 0, 0, 0}, p2 = {0, 0, 0, 0}, p3 = {0, 0, 0, 0};
@@ -581,8 +610,8 @@ __global__ __launch_bounds__(64 * NW) void k_iface_mfma(IfaceProds<T> ps, int L,
   // unconditional whole-vector loads (block index clamped to the tile range)
   auto load = [&](C<T>* ad, C<T>* bd, int b) {
     const int bc = min(b, nt - 1);
-    load4(Mr + (size_t)bc * 256, ad);
-    load4(Bc + 16 * bc, bd);
+    load_m4(Mr + (size_t)bc * 256, lane, ad);
+    load_x4(Bc + 16 * bc, g4, bd);
   };
   auto block = [&](const C<T>* ad, const C<T>* bd) {
 #pragma unroll

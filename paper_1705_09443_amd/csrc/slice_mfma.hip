@@ -117,8 +117,14 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
   const int nc = valid ? n : A.nrhs - 1;  // loads of padding columns read a real one
   const C<T>* mw = A.MW + A.mw_off[k];
   const C<T>* mg = A.MG + A.mg_off[k];
-  // forward results Y_j, lane-major as the MFMA leaves them
+  // forward results Y_j as the MFMA leaves them: per row tile and step, a
+  // lane's 8 values (Re, then Im) in 16-byte chunks, chunk c of every lane
+  // side by side, so that each 16-byte access of the wave covers one
+  // contiguous kilobyte (whole cache lines) and not every other 16 bytes
+  // of two kilobytes
   T* ys = A.yscr + ((size_t)A.ys_unit[k] * nq + (size_t)q * RT) * (size_t)(L + 1) * 512;
+  constexpr int ychw = 16 / (int)sizeof(T);  // values per chunk
+  auto ych = [&](int i) { return ((i / ychw) * 64 + lane) * ychw; };
 
   // right-hand sides: chunk cc of this lane holds line 4 cc + g of column nc
   const C<T>* rp[NSD];
@@ -273,11 +279,11 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
             V aR = q1[r] - q2[r], aI = q1[r] + q3[r];
             pR[r] = aR;
             pI[r] = aI;
-            T* yp = ys + ((size_t)j * RT + r) * 512 + lane * 8;
+            T* yp = ys + ((size_t)j * RT + r) * 512;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-              yp[i] = aR[i];
-              yp[4 + i] = aI[i];
+              yp[ych(i) + i % ychw] = aR[i];
+              yp[ych(4 + i) + i % ychw] = aI[i];
             }
           }
         }
@@ -299,9 +305,9 @@ __device__ __attribute__((always_inline)) inline void mfma_body(const SliceMfmaA
       for (int blk = 0; blk < RT * RT; ++blk) ld4<T>(rec + blk * 256 + lane * 4, gv[s][blk]);
 #pragma unroll
       for (int r = 0; r < RT; ++r) {
-        const T* yp = ys + ((size_t)jc * RT + r) * 512 + lane * 8;
+        const T* yp = ys + ((size_t)jc * RT + r) * 512;
 #pragma unroll
-        for (int i = 0; i < 8; ++i) yv[s][r][i] = yp[i];
+        for (int i = 0; i < 8; ++i) yv[s][r][i] = yp[ych(i) + i % ychw];
       }
     };
     // X_j = Y_j - G_j X_{j+1} from ring slot s
