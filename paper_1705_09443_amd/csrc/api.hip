@@ -440,13 +440,12 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   const size_t maxpairs = (size_t)nrhs * (rs + 2);
   LSW_ALLOC(h->pairs, maxpairs * sizeof(DotPair));
   LSW_ALLOC(h->groups, maxpairs * sizeof(DotGroup));
-  // dot-product partials: kDotBlocks (grouped) or kAxpyDotBlocks (fused with
-  // an update) per pair, or 256 per norm of an update
-  LSW_ALLOC(h->partials,
-            std::max(maxpairs * std::max(kDotBlocks, kAxpyDotBlocks), (size_t)nrhs * 256) * sizeof(double2));
+  // dot-product partials: kDotBlocks per pair, or 256 per norm of an update
+  LSW_ALLOC(h->partials, std::max(maxpairs * (size_t)kDotBlocks, (size_t)nrhs * 256) * sizeof(double2));
   LSW_ALLOC(h->coefs, (4 * maxpairs + 16) * sizeof(double2));
   LSW_ALLOC(h->outs, (size_t)nrhs * 2 * sizeof(AxpyOut));
-  // two Gram-Schmidt passes of up to nrhs * restart terms each
+  // the terms of one step's update and normalisation, and of the solution
+  // and residual updates at a cycle's end
   LSW_ALLOC(h->terms64, (2 * maxpairs + 2 * nrhs) * sizeof(AxpyTerm<double>));
   LSW_ALLOC(h->terms32, (2 * maxpairs + 2 * nrhs) * sizeof(AxpyTerm<float>));
   LSW_ALLOC(h->ptrs_a, (size_t)nrhs * sizeof(void*));
@@ -1239,7 +1238,10 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     }
     double2** cw_d = reinterpret_cast<double2**>(sm.put(pa));
     const C<T>* const* cw_s = reinterpret_cast<const C<T>* const*>(sm.put(pb));
-    // classical Gram-Schmidt, twice, then the norm
+    // classical Gram-Schmidt, one pass, then the exact norm: c = V^H w,
+    // w_1 = w - V c with ||w_1||^2 formed by the same pass, v_{j+1} = w_1 / ||w_1||.
+    // The norm is summed from w_1 itself: h^2 = ||w||^2 - |c|^2 would cancel
+    // here, where w lies close to the span of V.
     hp.clear();
     std::vector<int> off(na + 1, 0);
     for (int p = 0; p < na; ++p) {
@@ -1247,11 +1249,9 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       for (int k = 0; k <= S[r].j; ++k) hp.push_back({Vp(r, k), Wb + (size_t)r * N});
       off[p + 1] = (int)hp.size();
     }
-    // coefficients: the first pass's products (base1), the second pass's
-    // (base2), h^2 = ||w_2||^2 per right-hand side (base3) and the first
-    // pass's ||w_1||^2 (base4)
+    // coefficients: the products c (base1), then ||w_1||^2 per right-hand side (base3)
     const int np = (int)hp.size();
-    const int base1 = 1, base2 = 1 + np, base3 = 1 + 2 * np, base4 = 1 + 2 * np + na;
+    const int base1 = 1, base3 = 1 + np;
     ho.clear();
     ht64.clear();
     for (int p = 0; p < na; ++p) {
@@ -1261,16 +1261,11 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       o.tend = (int)ht64.size();
       ho.push_back(o);
     }
-    // the second pass writes the next basis vector itself:
-    // v_{j+1} = (w_1 - V c_2) / h with h^2 = ||w_1||^2 - |c_2|^2 (V
-    // orthonormal and c_2 = V^H w_1; c_2 is the small reorthogonalisation
-    // correction, so the difference does not cancel), the unit term w_1 with
-    // coefs[0] = 1. It replaces a separate normalisation pass.
+    // v_{j+1} = w_1 / ||w_1||: the unit term w_1 (coefs[0] = 1), scaled
     for (int p = 0; p < na; ++p) {
       const int r = act[p];
       AxpyOut o{Vp(r, S[r].j + 1), (int)ht64.size(), 0, 1, base3 + p, 1};
       ht64.push_back({Wb + (size_t)r * N, 0, 0});
-      for (int k = 0; k <= S[r].j; ++k) ht64.push_back({Vp(r, k), base2 + off[p] + k, 1});
       o.tend = (int)ht64.size();
       ho.push_back(o);
     }
@@ -1290,9 +1285,7 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     const AxpyTerm<double>* terms_d = sm.put(ht64);
     const DotGroup* groups_d = sm.put(hg);
     const double2* one_d = sm.put(&one, 1);
-    const int* off_d = sm.put(off);
-    if (!cin_d || !cin_s || !cz_d || !cz_s || !cw_d || !cw_s || !outs_d || !terms_d || !groups_d || !one_d ||
-        !off_d) {
+    if (!cin_d || !cin_s || !cz_d || !cz_s || !cw_d || !cw_s || !outs_d || !terms_d || !groups_d || !one_d) {
       set_error("internal: descriptor stage too small");
       return LS_E_STATE;
     }
@@ -1319,21 +1312,9 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       if ((e = apply_A<T>(h, zout, na, aout)) != LS_OK) return e;
       LSW_HIP_TRY((launch_copy_cast<double, T>(cw_d, cw_s, na, N, st)));
     }
-    const int ng = (int)hg.size();
     double2* part = h->partials.as<double2>();
-    int maxterms = 0;
-    for (int p = 0; p < na; ++p) maxterms = std::max(maxterms, off[p + 1] - off[p]);
-    LSW_HIP_TRY(launch_mdots(groups_d, ng, np, N, part, coefs + base1, st));
-    if (maxterms <= kAxpyDotMaxTerms) {
-      // the first pass's update also forms the second pass's dot products
-      // (first-pass term i is dot product i) and ||w_1||^2
-      LSW_HIP_TRY(launch_axpys_dots(outs_d, na, terms_d, coefs, N, np, part, coefs + base2, st, coefs + base4));
-    } else {
-      LSW_HIP_TRY(launch_axpys_norms(outs_d, na, terms_d, coefs, N, part, coefs + base4, st));
-      LSW_HIP_TRY(launch_mdots(groups_d, ng, np, N, part, coefs + base2, st));
-    }
-    // h^2, then the second update straight into v_{j+1}
-    LSW_HIP_TRY(launch_pythag(coefs + base4, coefs + base2, off_d, na, coefs + base3, st));
+    LSW_HIP_TRY(launch_mdots(groups_d, (int)hg.size(), np, N, part, coefs + base1, st));
+    LSW_HIP_TRY(launch_axpys_norms(outs_d, na, terms_d, coefs, N, part, coefs + base3, st));
     LSW_HIP_TRY(launch_axpys<double>(outs_d + na, na, terms_d, coefs, N, st));
     hc.resize(base3 + na);
     LSW_HIP_TRY(hipMemcpyAsync(hc.data(), coefs, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
@@ -1345,8 +1326,8 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       const int j = s.j;
       std::complex<double>* col = &s.Hm[(size_t)j * (rs + 1)];
       for (int k = 0; k <= j; ++k) {
-        const double2 a = hc[base1 + off[p] + k], c2 = hc[base2 + off[p] + k];
-        col[k] = std::complex<double>(a.x + c2.x, a.y + c2.y);
+        const double2 a = hc[base1 + off[p] + k];
+        col[k] = std::complex<double>(a.x, a.y);
       }
       const double w2 = hc[base3 + p].x;
       const double hn = std::sqrt(std::max(w2, 0.0));

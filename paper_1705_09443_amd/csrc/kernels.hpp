@@ -281,25 +281,6 @@ hipError_t launch_axpys(const AxpyOut* outs, int nout, const AxpyTerm<TX>* terms
 // needs nout * 256 entries)
 hipError_t launch_axpys_norms(const AxpyOut* outs, int nout, const AxpyTerm<double>* terms, const double2* coefs,
                               size_t N, double2* partials, double2* norm2, hipStream_t st);
-// launch_axpys (no scale: every scale_coef < 0) that also forms, over the
-// updated outputs, dots[t] = sum conj(x_t) y_o for every term t of every
-// output o (the dot products of the next Gram-Schmidt pass, read from the
-// vectors the update already holds): fixed-order reduction through
-// kAxpyDotBlocks partials per term, so partials needs ndots * kAxpyDotBlocks
-// entries; ndots = the number of terms. Every output has at most
-// kAxpyDotMaxTerms terms (the caller checks). With norm2, also norm2[o] =
-// ||y_o||^2 of every updated output (its partials after the products', so
-// partials then needs (ndots + nout) * kAxpyDotBlocks entries).
-constexpr int kAxpyDotBlocks = 256;
-constexpr int kAxpyDotMaxTerms = 8;
-hipError_t launch_axpys_dots(const AxpyOut* outs, int nout, const AxpyTerm<double>* terms, const double2* coefs,
-                             size_t N, int ndots, double2* partials, double2* dots, hipStream_t st,
-                             double2* norm2 = nullptr);
-// h2[p] = norm2[p] - sum over k in [off[p], off[p+1]) of |c[k]|^2 (off: device
-// array of nout + 1 offsets): ||w - V c||^2 from ||w||^2 when V is
-// orthonormal and c = V^H w
-hipError_t launch_pythag(const double2* norm2, const double2* c, const int* off, int nout, double2* h2,
-                         hipStream_t st);
 // dst[p] = cast(src[p]) for npairs contiguous batches of N entries.
 template <typename TD, typename TS>
 hipError_t launch_copy_cast(C<TD>* const* dst, const C<TS>* const* src, int npairs, size_t N,

@@ -156,103 +156,6 @@ __global__ __launch_bounds__(kThreads) void k_axpys(const AxpyOut* __restrict__ 
   }
 }
 
-// k_axpys for outputs without scale, each of at most KT terms, that also
-// sums conj(x_t) y_o over the updated y_o for every term: the term vectors
-// stay in registers between the update and the products
-// norm_partials (optional): ||y_o||^2 of this block's share of the updated
-// output as well, at norm_partials[o * gridDim.x + blockIdx.x]
-template <int KT>
-__global__ __launch_bounds__(kThreads) void k_axpys_dots(const AxpyOut* __restrict__ outs,
-                                                         const AxpyTerm<double>* __restrict__ terms,
-                                                         const double2* __restrict__ coefs, size_t N,
-                                                         double2* __restrict__ partials,
-                                                         double2* __restrict__ norm_partials) {
-  const AxpyOut o = outs[blockIdx.y];
-  const int cnt = o.tend - o.tbeg;
-  const double2* xs[KT];
-  double2 c[KT], d[KT];
-  double nrm = 0.0;
-#pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    xs[k] = nullptr;
-    c[k] = d[k] = make_double2(0.0, 0.0);
-    if (k < cnt) {
-      const AxpyTerm<double> tm = terms[o.tbeg + k];
-      xs[k] = reinterpret_cast<const double2*>(tm.x);
-      c[k] = coefs[tm.coef];
-      if (tm.negate) {
-        c[k].x = -c[k].x;
-        c[k].y = -c[k].y;
-      }
-    }
-  }
-  for (size_t i = (size_t)blockIdx.x * kThreads + threadIdx.x; i < N; i += (size_t)gridDim.x * kThreads) {
-    double2 xv[KT];
-#pragma unroll
-    for (int k = 0; k < KT; ++k)
-      if (k < cnt) xv[k] = xs[k][i];
-    double2 acc = make_double2(0.0, 0.0);
-#pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      if (k < cnt) {
-        acc.x += c[k].x * xv[k].x - c[k].y * xv[k].y;
-        acc.y += c[k].x * xv[k].y + c[k].y * xv[k].x;
-      }
-    }
-    double2 y = o.zero_first ? make_double2(0.0, 0.0) : o.y[i];
-    y.x = y.x + acc.x;
-    y.y = y.y + acc.y;
-    o.y[i] = y;
-    nrm += y.x * y.x + y.y * y.y;
-#pragma unroll
-    for (int k = 0; k < KT; ++k) {
-      if (k < cnt) {
-        d[k].x += xv[k].x * y.x + xv[k].y * y.y;
-        d[k].y += xv[k].x * y.y - xv[k].y * y.x;
-      }
-    }
-  }
-  __shared__ double2 ws[KT + 1][kThreads / 64];
-  if (norm_partials) {
-    const double2 v = wave_sum(make_double2(nrm, 0.0));
-    if ((threadIdx.x & 63) == 0) ws[KT][threadIdx.x >> 6] = v;
-  }
-#pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    if (k < cnt) {
-      const double2 v = wave_sum(d[k]);
-      if ((threadIdx.x & 63) == 0) ws[k][threadIdx.x >> 6] = v;
-    }
-  }
-  __syncthreads();
-  if (threadIdx.x < cnt) {
-    const int k = threadIdx.x;
-    double2 s = ws[k][0];
-    for (int w = 1; w < kThreads / 64; ++w) {
-      s.x += ws[k][w].x;
-      s.y += ws[k][w].y;
-    }
-    partials[(size_t)(o.tbeg + k) * gridDim.x + blockIdx.x] = s;
-  }
-  if (norm_partials && threadIdx.x == 0) {
-    double s = ws[KT][0].x;
-    for (int w = 1; w < kThreads / 64; ++w) s += ws[KT][w].x;
-    norm_partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = make_double2(s, 0.0);
-  }
-}
-
-// h2[p] = norm2[p] - sum over k in [off[p], off[p+1]) of |c[k]|^2: the squared
-// norm of w - V c for an orthonormal V whose products with w are c (in a fixed
-// order, one thread per output)
-__global__ void k_pythag(const double2* __restrict__ norm2, const double2* __restrict__ c,
-                         const int* __restrict__ off, int nout, double2* __restrict__ h2) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nout) return;
-  double s = norm2[p].x;
-  for (int k = off[p]; k < off[p + 1]; ++k) s -= c[k].x * c[k].x + c[k].y * c[k].y;
-  h2[p] = make_double2(s, 0.0);
-}
-
 template <typename TD, typename TS>
 __global__ void k_copy_cast(C<TD>* const* __restrict__ dst, const C<TS>* const* __restrict__ src, size_t N) {
   const int p = blockIdx.y;
@@ -373,25 +276,6 @@ hipError_t launch_axpys_norms(const AxpyOut* outs, int nout, const AxpyTerm<doub
   hipLaunchKernelGGL(k_axpys<double>, dim3(kNormBlocks, nout), dim3(kThreads), 0, st, outs, terms, coefs, N,
                      partials);
   hipLaunchKernelGGL(k_dot_reduce, dim3((nout + 127) / 128), dim3(128), 0, st, partials, nout, norm2, kNormBlocks);
-  return hipGetLastError();
-}
-hipError_t launch_axpys_dots(const AxpyOut* outs, int nout, const AxpyTerm<double>* terms, const double2* coefs,
-                             size_t N, int ndots, double2* partials, double2* dots, hipStream_t st,
-                             double2* norm2) {
-  if (nout <= 0) return hipSuccess;
-  // the norm partials follow the ndots products' partials
-  double2* np = norm2 ? partials + (size_t)ndots * kAxpyDotBlocks : nullptr;
-  hipLaunchKernelGGL(k_axpys_dots<kAxpyDotMaxTerms>, dim3(kAxpyDotBlocks, nout), dim3(kThreads), 0, st, outs, terms,
-                     coefs, N, partials, np);
-  hipLaunchKernelGGL(k_dot_reduce, dim3((ndots + 127) / 128), dim3(128), 0, st, partials, ndots, dots, kAxpyDotBlocks);
-  if (norm2)
-    hipLaunchKernelGGL(k_dot_reduce, dim3((nout + 127) / 128), dim3(128), 0, st, np, nout, norm2, kAxpyDotBlocks);
-  return hipGetLastError();
-}
-hipError_t launch_pythag(const double2* norm2, const double2* c, const int* off, int nout, double2* h2,
-                         hipStream_t st) {
-  if (nout <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_pythag, dim3((nout + 127) / 128), dim3(128), 0, st, norm2, c, off, nout, h2);
   return hipGetLastError();
 }
 template hipError_t launch_axpys<double>(const AxpyOut*, int, const AxpyTerm<double>*, const double2*,
