@@ -453,8 +453,8 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   {
     // 3 pointer pairs per right-hand side, dot groups and update terms of up
     // to maxpairs products, 2 outputs per right-hand side, alignment slack
-    // (+ one unit term per right-hand side in the second pass, and the
-    // per-right-hand-side offsets of its products)
+    // (+ one unit term per right-hand side in the normalisation; the
+    // remaining terms are spare)
     const size_t main_bytes = (size_t)nrhs * 6 * sizeof(void*) + maxpairs * (sizeof(DotGroup) + 2 * sizeof(AxpyTerm<double>)) +
                               (size_t)nrhs * (2 * sizeof(AxpyOut) + sizeof(AxpyTerm<double>)) +
                               (size_t)(nrhs + 1) * sizeof(int) + sizeof(double2) + 16 * 256;
