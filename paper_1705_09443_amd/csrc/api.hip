@@ -2742,13 +2742,12 @@ ls_status ls_solve(ls_handle* h, const void* rhs_dev, int nrhs, int rhs_kind, do
     h->last_nrhs = 0;
     const ls_status gs = run_gmres(h, nrhs, tol, info);
     if (gs != LS_OK && gs != LS_E_NOCONV) return gs;
-    LSW_HIP_TRY(hipMemcpyAsync(u_dev, h->X.p, (size_t)nrhs * N * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
-    // total field psi = u + u_I (incident) or u (source), kept for ls_adjoint
+    // u, and the total field psi = u + u_I (incident) or u (source) kept for
+    // ls_adjoint, in one pass over the solution
     LSW_ALLOC(h->psi, (size_t)nrhs * N * sizeof(double2));
-    LSW_HIP_TRY(hipMemcpyAsync(h->psi.p, h->X.p, (size_t)nrhs * N * sizeof(double2), hipMemcpyDeviceToDevice, h->st));
-    if (rhs_kind == LS_RHS_INCIDENT)
-      LSW_HIP_TRY(launch_add_scaled(h->psi.as<double2>(), static_cast<const double2*>(rhs_dev), 1.0, (size_t)nrhs * N,
-                                    h->st));
+    LSW_HIP_TRY(launch_solution_out(static_cast<double2*>(u_dev), h->psi.as<double2>(), h->X.as<double2>(),
+                                    rhs_kind == LS_RHS_INCIDENT ? static_cast<const double2*>(rhs_dev) : nullptr,
+                                    (size_t)nrhs * N, h->st));
     LSW_HIP_TRY(hipStreamSynchronize(h->st));
     h->last_nrhs = nrhs;
     if (info_host)

@@ -290,8 +290,10 @@ hipError_t launch_adjoint_product(const double2* psi, const double2* nu, int nrh
                                   double omega2, double* grad, hipStream_t st);
 // dst = conj(src) over N entries (float64)
 hipError_t launch_conj(double2* dst, const double2* src, size_t N, hipStream_t st);
-// x (+)= s * y elementwise over N with real s, float64 (incident total field etc.)
-hipError_t launch_add_scaled(double2* x, const double2* y, double s, size_t N, hipStream_t st);
+// u = x and psi = x + y (y null: psi = x) elementwise over N, float64: a
+// solve's output and the total field kept for the adjoint, in one pass
+hipError_t launch_solution_out(double2* u, double2* psi, const double2* x, const double2* y, size_t N,
+                               hipStream_t st);
 // dst[i] = src[i] over count values, converting the precision
 template <typename TD, typename TS>
 hipError_t launch_cast_flat(C<TD>* dst, const C<TS>* src, size_t count, hipStream_t st);

@@ -208,10 +208,15 @@ __global__ void k_adjoint_product(const double2* __restrict__ psi, const double2
   }
 }
 
-__global__ void k_add_scaled(double2* __restrict__ x, const double2* __restrict__ y, double s, size_t N) {
+// u = x and psi = x + y (y may be null: psi = x), one pass over x and y;
+// each element of y is read before u is written, so u may be y itself
+__global__ void k_solution_out(double2* u, double2* __restrict__ psi, const double2* __restrict__ x,
+                               const double2* y, size_t N) {
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (size_t)gridDim.x * blockDim.x) {
-    x[i].x += s * y[i].x;
-    x[i].y += s * y[i].y;
+    const double2 v = x[i];
+    const double2 w = y ? y[i] : make_double2(0.0, 0.0);
+    u[i] = v;
+    psi[i] = make_double2(v.x + w.x, v.y + w.y);
   }
 }
 
@@ -350,8 +355,9 @@ hipError_t launch_plane_waves(double2* out, int n, double omega, int k, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_add_scaled(double2* x, const double2* y, double s, size_t N, hipStream_t st) {
-  hipLaunchKernelGGL(k_add_scaled, dim3(grid_for(N)), dim3(kThreads), 0, st, x, y, s, N);
+hipError_t launch_solution_out(double2* u, double2* psi, const double2* x, const double2* y, size_t N,
+                               hipStream_t st) {
+  hipLaunchKernelGGL(k_solution_out, dim3(grid_for(N)), dim3(kThreads), 0, st, u, psi, x, y, N);
   return hipGetLastError();
 }
 
