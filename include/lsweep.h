@@ -156,7 +156,8 @@ ls_status ls_setup(const ls_grid* grid, double omega, const double* m_dev, int p
  *   rhs_dev    complex128 [nrhs][n][n] ([nrhs][n][n][n] in 3D): g itself
  *              (LS_RHS_SOURCE) or the incident wave u_I on the interior grid
  *              (LS_RHS_INCIDENT, g = -omega^2 K (m u_I))
- *   u_dev      complex128, same shape, output: the scattered field
+ *   u_dev      complex128, same shape, output: the scattered field; may be
+ *              rhs_dev itself (each input value is read before u is written)
  *   info_host  host array of nrhs entries (may be NULL)
  * A zero right-hand side gives u = 0 after 0 iterations. Returns LS_E_NOCONV
  * if any right-hand side hit max_iters (u and info are still written).
