@@ -382,10 +382,11 @@ def test_graph_replays_agree(case):
 @pytest.mark.parametrize("b,restart", [(2, 30), (1, 10)])
 def test_solve_long_arnoldi_cycles(b, restart):
     """Arnoldi cycles longer than eight steps (a thin PML weakens the sweep):
-    the second Gram-Schmidt pass takes its dot products from the first pass's
-    update while a cycle has at most eight basis vectors, from separate grouped
-    products after that; with restart 10 the solve also crosses restarts.
-    Protocol P2 and P1 against the oracle at tol 1e-10."""
+    the grouped dot products of the Gram-Schmidt pass then span more than one
+    group of eight basis vectors, and the single classical pass must keep the
+    basis orthogonal enough over many steps; with restart 10 the solve also
+    crosses restarts. Protocol P2 and P1 against the oracle (modified
+    Gram-Schmidt) at tol 1e-10."""
     from paper_1705_09443_amd import LSSolver
     n, ppw, w = 40, 2.5, 3
     wl = workloads.workload("C0").scaled(n, ppw_omega=ppw)
