@@ -1085,6 +1085,9 @@ struct RhsState {
   std::vector<std::complex<double>> Hm;  // (restart+1) x restart, column-major
   std::vector<double> cs;
   std::vector<std::complex<double>> sn, s;
+  // norms of the basis vectors of the cycle as stored (u_0 = r / ||r|| has
+  // norm 1; u_{k+1} = w - sum_i c_i u_i is kept unnormalised)
+  std::vector<double> bn;
 };
 
 void givens(std::complex<double> f, std::complex<double> g, double& c, std::complex<double>& s,
@@ -1130,6 +1133,7 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     s.cs.assign(rs, 0.0);
     s.sn.assign(rs, 0.0);
     s.s.assign(rs + 1, 0.0);
+    s.bn.assign(rs + 1, 1.0);
   }
   LSW_HIP_TRY(hipMemsetAsync(Xb, 0, (size_t)nrhs * N * sizeof(double2), st));
 
@@ -1238,34 +1242,36 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     }
     double2** cw_d = reinterpret_cast<double2**>(sm.put(pa));
     const C<T>* const* cw_s = reinterpret_cast<const C<T>* const*>(sm.put(pb));
-    // classical Gram-Schmidt, one pass, then the exact norm: c = V^H w,
-    // w_1 = w - V c with ||w_1||^2 formed by the same pass, v_{j+1} = w_1 / ||w_1||.
-    // The norm is summed from w_1 itself: h^2 = ||w||^2 - |c|^2 would cancel
-    // here, where w lies close to the span of V.
+    // classical Gram-Schmidt, one pass, with the exact norm of its result.
+    // The basis vectors of a cycle are orthogonal but not normalised: u_0 =
+    // r / ||r||, then u_{j+1} = w - sum_k (u_k^H w / b_k^2) u_k with
+    // b_k = ||u_k||, written straight into its slot with b_{j+1}^2 summed by the
+    // same pass (no normalisation pass). With q_k = u_k / b_k and
+    // z_j = P u_j, A z_j = sum_k (u_k^H w / b_k) q_k + b_{j+1} q_{j+1}: that is the
+    // Hessenberg column, and x = Z y as with a normalised basis. The norm is
+    // summed exactly: ||w||^2 - |c|^2 would cancel, w lying close to span(V).
     hp.clear();
     std::vector<int> off(na + 1, 0);
+    std::vector<double> kscale;
     for (int p = 0; p < na; ++p) {
       const int r = act[p];
-      for (int k = 0; k <= S[r].j; ++k) hp.push_back({Vp(r, k), Wb + (size_t)r * N});
+      for (int k = 0; k <= S[r].j; ++k) {
+        hp.push_back({Vp(r, k), Wb + (size_t)r * N});
+        kscale.push_back(1.0 / (S[r].bn[k] * S[r].bn[k]));
+      }
       off[p + 1] = (int)hp.size();
     }
-    // coefficients: the products c (base1), then ||w_1||^2 per right-hand side (base3)
+    // coefficients: the products u_k^H w (base1), the update's u_k^H w / b_k^2
+    // (base2), then b_{j+1}^2 per right-hand side (base3)
     const int np = (int)hp.size();
-    const int base1 = 1, base3 = 1 + np;
+    const int base1 = 1, base2 = 1 + np, base3 = 1 + 2 * np;
     ho.clear();
     ht64.clear();
     for (int p = 0; p < na; ++p) {
       const int r = act[p];
-      AxpyOut o{Wb + (size_t)r * N, (int)ht64.size(), 0, 0, -1, 0};
-      for (int k = 0; k <= S[r].j; ++k) ht64.push_back({Vp(r, k), base1 + off[p] + k, 1});
-      o.tend = (int)ht64.size();
-      ho.push_back(o);
-    }
-    // v_{j+1} = w_1 / ||w_1||: the unit term w_1 (coefs[0] = 1), scaled
-    for (int p = 0; p < na; ++p) {
-      const int r = act[p];
-      AxpyOut o{Vp(r, S[r].j + 1), (int)ht64.size(), 0, 1, base3 + p, 1};
-      ht64.push_back({Wb + (size_t)r * N, 0, 0});
+      AxpyOut o{Vp(r, S[r].j + 1), (int)ht64.size(), 0, 1, -1, 0};
+      ht64.push_back({Wb + (size_t)r * N, 0, 0});  // the unit term w (coefs[0] = 1)
+      for (int k = 0; k <= S[r].j; ++k) ht64.push_back({Vp(r, k), base2 + off[p] + k, 1});
       o.tend = (int)ht64.size();
       ho.push_back(o);
     }
@@ -1285,7 +1291,9 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     const AxpyTerm<double>* terms_d = sm.put(ht64);
     const DotGroup* groups_d = sm.put(hg);
     const double2* one_d = sm.put(&one, 1);
-    if (!cin_d || !cin_s || !cz_d || !cz_s || !cw_d || !cw_s || !outs_d || !terms_d || !groups_d || !one_d) {
+    const double* kscale_d = sm.put(kscale);
+    if (!cin_d || !cin_s || !cz_d || !cz_s || !cw_d || !cw_s || !outs_d || !terms_d || !groups_d || !one_d ||
+        !kscale_d) {
       set_error("internal: descriptor stage too small");
       return LS_E_STATE;
     }
@@ -1314,8 +1322,8 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
     }
     double2* part = h->partials.as<double2>();
     LSW_HIP_TRY(launch_mdots(groups_d, (int)hg.size(), np, N, part, coefs + base1, st));
+    LSW_HIP_TRY(launch_scale_coefs(coefs + base1, kscale_d, coefs + base2, np, st));
     LSW_HIP_TRY(launch_axpys_norms(outs_d, na, terms_d, coefs, N, part, coefs + base3, st));
-    LSW_HIP_TRY(launch_axpys<double>(outs_d + na, na, terms_d, coefs, N, st));
     hc.resize(base3 + na);
     LSW_HIP_TRY(hipMemcpyAsync(hc.data(), coefs, hc.size() * sizeof(double2), hipMemcpyDeviceToHost, st));
     LSW_HIP_TRY(hipStreamSynchronize(st));
@@ -1327,7 +1335,7 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
       std::complex<double>* col = &s.Hm[(size_t)j * (rs + 1)];
       for (int k = 0; k <= j; ++k) {
         const double2 a = hc[base1 + off[p] + k];
-        col[k] = std::complex<double>(a.x, a.y);
+        col[k] = std::complex<double>(a.x, a.y) / s.bn[k];
       }
       const double w2 = hc[base3 + p].x;
       const double hn = std::sqrt(std::max(w2, 0.0));
@@ -1336,6 +1344,7 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
         return LS_E_NUMERIC;
       }
       col[j + 1] = hn;
+      s.bn[j + 1] = hn;
       for (int k = 0; k < j; ++k) {
         const std::complex<double> a = col[k], c = col[k + 1];
         col[k] = s.cs[k] * a + s.sn[k] * c;
@@ -1443,6 +1452,7 @@ ls_status gmres(ls_handle* h, int nrhs, double tol, std::vector<ls_rhs_info>& in
         s.j = 0;
         std::fill(s.s.begin(), s.s.end(), 0.0);
         s.s[0] = rn[p];
+        s.bn.assign(s.bn.size(), 1.0);
         ys.push_back({Vp(r, 0), Rb + (size_t)r * N});
         sc.push_back(rn[p]);
       }

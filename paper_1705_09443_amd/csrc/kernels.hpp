@@ -290,6 +290,8 @@ hipError_t launch_adjoint_product(const double2* psi, const double2* nu, int nrh
                                   double omega2, double* grad, hipStream_t st);
 // dst = conj(src) over N entries (float64)
 hipError_t launch_conj(double2* dst, const double2* src, size_t N, hipStream_t st);
+// out[t] = in[t] * s[t], t < n (complex coefficients, real factors)
+hipError_t launch_scale_coefs(const double2* in, const double* s, double2* out, int n, hipStream_t st);
 // u = x and psi = x + y (y null: psi = x) elementwise over N, float64: a
 // solve's output and the total field kept for the adjoint, in one pass
 hipError_t launch_solution_out(double2* u, double2* psi, const double2* x, const double2* y, size_t N,

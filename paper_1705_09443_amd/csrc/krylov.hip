@@ -208,6 +208,13 @@ __global__ void k_adjoint_product(const double2* __restrict__ psi, const double2
   }
 }
 
+// out[t] = in[t] * s[t] for n complex coefficients and real factors
+__global__ void k_scale_coefs(const double2* __restrict__ in, const double* __restrict__ s, double2* __restrict__ out,
+                              int n) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) out[t] = make_double2(in[t].x * s[t], in[t].y * s[t]);
+}
+
 // u = x and psi = x + y (y may be null: psi = x), one pass over x and y;
 // each element of y is read before u is written, so u may be y itself
 __global__ void k_solution_out(double2* u, double2* __restrict__ psi, const double2* __restrict__ x,
@@ -355,6 +362,11 @@ hipError_t launch_plane_waves(double2* out, int n, double omega, int k, hipStrea
   return hipGetLastError();
 }
 
+hipError_t launch_scale_coefs(const double2* in, const double* s, double2* out, int n, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_scale_coefs, dim3((n + 127) / 128), dim3(128), 0, st, in, s, out, n);
+  return hipGetLastError();
+}
 hipError_t launch_solution_out(double2* u, double2* psi, const double2* x, const double2* y, size_t N,
                                hipStream_t st) {
   hipLaunchKernelGGL(k_solution_out, dim3(grid_for(N)), dim3(kThreads), 0, st, u, psi, x, y, N);
