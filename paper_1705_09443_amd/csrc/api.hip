@@ -451,11 +451,12 @@ ls_status ensure_workspace(ls_handle* h, int nrhs) {
   LSW_ALLOC(h->ptrs_a, (size_t)nrhs * sizeof(void*));
   LSW_ALLOC(h->ptrs_b, (size_t)nrhs * sizeof(void*));
   {
-    // 3 pointer pairs per right-hand side, dot groups and update terms of up
-    // to maxpairs products, 2 outputs per right-hand side, alignment slack
-    // (+ one unit term per right-hand side in the normalisation; the
-    // remaining terms are spare)
-    const size_t main_bytes = (size_t)nrhs * 6 * sizeof(void*) + maxpairs * (sizeof(DotGroup) + 2 * sizeof(AxpyTerm<double>)) +
+    // 3 pointer pairs per right-hand side, dot groups, update terms and
+    // coefficient factors of up to maxpairs products, outputs and one unit
+    // term per right-hand side, alignment slack (terms and outputs with room
+    // to spare)
+    const size_t main_bytes = (size_t)nrhs * 6 * sizeof(void*) +
+                              maxpairs * (sizeof(DotGroup) + 2 * sizeof(AxpyTerm<double>) + sizeof(double)) +
                               (size_t)nrhs * (2 * sizeof(AxpyOut) + sizeof(AxpyTerm<double>)) +
                               (size_t)(nrhs + 1) * sizeof(int) + sizeof(double2) + 16 * 256;
     if (h->stage_main.alloc(main_bytes) != hipSuccess) {
